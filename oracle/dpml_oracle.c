@@ -1,0 +1,316 @@
+/*
+ * dpml_oracle.c -- plain FP64 CPU oracle for the reflectionless discrete PML
+ * of A. Chern, "A Reflectionless Discrete Perfectly Matched Layer"
+ * (J. Comput. Phys.; arXiv 1804.01390).
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is the slow, obviously correct
+ * reference that the GPU library is checked against.  Only the test suite,
+ * the smoke check and the benchmark's CPU-baseline leg load it.  It shares
+ * no code, header, table or helper with the GPU library.
+ *
+ * What it computes (paper notation, grid spacing h, per-axis shift tau_a):
+ *
+ *   Eq. (DiscretePML a):
+ *     U_tt = c^2 * sum_a (tau_a^-1 U - 2U + tau_a U)/h^2
+ *            + sum_a (1/h) ( sigma_a * tau_a Psi_a - (tau_a^-1 sigma_a)(tau_a^-1 Phi_a) )
+ *   Eq. (DiscretePML b):
+ *     Phi_a,t = -1/2 ( (tau_a^-1 sigma_a)(tau_a^-1 Phi_a) + sigma_a Phi_a )
+ *               - (tau_a U - tau_a^-1 U)/(2h)
+ *   Eq. (DiscretePML c):
+ *     Psi_a,t = -1/2 ( (tau_a^-1 sigma_a) Psi_a + sigma_a (tau_a Psi_a) )
+ *               - (tau_a U - tau_a^-1 U)/(2h)
+ *
+ * The equations are evaluated at EVERY cell of the grid (the paper states
+ * them on all of Z^d; the restriction of Phi/Psi to the layer in Sec. 1.1.2
+ * is an economy, not part of the definition).  The truncation is periodic
+ * (Sec. 1.1.3, the runs of Figs. 2 and 3).  The coefficient c^2 multiplies the
+ * Laplacian only; it must equal 1 wherever a damping term acts (the paper
+ * uses unit wave speed).
+ *
+ * Time discretisation (the paper's runs use RK4 with an unstated step; this
+ * oracle follows the leapfrog reading): U by the explicit central
+ * second difference, Phi and Psi by a forward step, and every right-hand
+ * side of one step evaluated from time-level-n data only:
+ *
+ *   U^{n+1}   = 2 U^n - U^{n-1} + dt^2 * A(U^n, Phi^n, Psi^n)
+ *   Phi^{n+1} = Phi^n + dt * B(U^n, Phi^n)
+ *   Psi^{n+1} = Psi^n + dt * C(U^n, Psi^n)
+ *
+ * With that placement the Fourier-domain derivation of Sec. 3.3 carries over
+ * with -omega^2 -> (z - 2 + 1/z)/dt^2 in Eq. (UEquationFourier) and
+ * -i omega -> (z - 1)/dt in Eqs. (PhiEquationFourier), (PsiEquationFourier),
+ * z the one-step amplification factor; the discrete plane waves of Thm. 1
+ * then continue into the layer exactly, with decay factor rho(s, k, omega')
+ * and omega' = i (z - 1)/dt.
+ *
+ * Start (zero or given initial velocity, Phi = Psi = 0):
+ *   U^{-1} = U^0 - dt V^0 + dt^2/2 * A(U^0, 0, 0)
+ *
+ * Point sources (not in the paper): after step n (U^n -> U^{n+1}),
+ *   U^{n+1}[s] += dt^2 * w_s[n] / h^d,  and receivers record U^{n+1}[r].
+ *
+ * Arrays are row-major with axis 0 (x) fastest: cell (x, y, z) sits at
+ * x + N0*(y + N1*z).  Unused axes have extent 1.
+ *
+ * Build: gcc -O2 -ffp-contract=off -fopenmp -shared -fPIC (no fast-math).
+ */
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+typedef struct {
+    int32_t ndim;            /* 1, 2 or 3 */
+    int32_t pad_;
+    int64_t N[3];            /* cells per axis, axis 0 fastest; unused axes 1 */
+    double h;                /* grid spacing */
+    double dt;               /* time step */
+    const double *c2;        /* NULL: c^2 = 1; else one value per cell */
+    const double *sigma[3];  /* sigma_a(i_a), N[a] values each; NULL = all 0 */
+} orc_grid;
+
+static int64_t orc_wrap(int64_t i, int64_t n)
+{
+    if (i < 0) return i + n;
+    if (i >= n) return i - n;
+    return i;
+}
+
+static double orc_sigma(const orc_grid *g, int a, int64_t i)
+{
+    return g->sigma[a] ? g->sigma[a][i] : 0.0;
+}
+
+/* Decompose a flat cell index into per-axis indices. */
+static void orc_coords(const orc_grid *g, int64_t c, int64_t ii[3])
+{
+    ii[0] = c % g->N[0];
+    ii[1] = (c / g->N[0]) % g->N[1];
+    ii[2] = c / (g->N[0] * g->N[1]);
+}
+
+static int64_t orc_stride(const orc_grid *g, int a)
+{
+    if (a == 0) return 1;
+    if (a == 1) return g->N[0];
+    return g->N[0] * g->N[1];
+}
+
+/* Flat index of the cell one step along axis a (dir = +1 or -1), periodic. */
+static int64_t orc_shift(const orc_grid *g, int64_t c, const int64_t ii[3], int a, int dir)
+{
+    int64_t j = orc_wrap(ii[a] + dir, g->N[a]);
+    return c + (j - ii[a]) * orc_stride(g, a);
+}
+
+static int64_t orc_ncells(const orc_grid *g)
+{
+    return g->N[0] * g->N[1] * g->N[2];
+}
+
+/* Right-hand side of Eq. (DiscretePML a) at cell c. Phi/Psi may be NULL
+ * (treated as zero, used at the start). */
+static double orc_rhs_u(const orc_grid *g, const double *U,
+                        double *const Phi[3], double *const Psi[3], int64_t c)
+{
+    int64_t ii[3];
+    double lap = 0.0, damp = 0.0;
+    orc_coords(g, c, ii);
+    for (int a = 0; a < g->ndim; ++a) {
+        int64_t cp = orc_shift(g, c, ii, a, +1);
+        int64_t cm = orc_shift(g, c, ii, a, -1);
+        int64_t im = orc_wrap(ii[a] - 1, g->N[a]);
+        lap += (U[cm] - 2.0 * U[c] + U[cp]) / (g->h * g->h);
+        if (Phi && Psi) {
+            double s_here = orc_sigma(g, a, ii[a]);   /* sigma_a        */
+            double s_left = orc_sigma(g, a, im);      /* tau^-1 sigma_a */
+            damp += (s_here * Psi[a][cp] - s_left * Phi[a][cm]) / g->h;
+        }
+    }
+    return (g->c2 ? g->c2[c] : 1.0) * lap + damp;
+}
+
+/* Right-hand side of Eq. (DiscretePML b) for Phi_a at cell c. */
+static double orc_rhs_phi(const orc_grid *g, const double *U, const double *Phi_a,
+                          int a, int64_t c)
+{
+    int64_t ii[3];
+    orc_coords(g, c, ii);
+    int64_t cp = orc_shift(g, c, ii, a, +1);
+    int64_t cm = orc_shift(g, c, ii, a, -1);
+    int64_t im = orc_wrap(ii[a] - 1, g->N[a]);
+    double s_here = orc_sigma(g, a, ii[a]);
+    double s_left = orc_sigma(g, a, im);
+    return -0.5 * (s_left * Phi_a[cm] + s_here * Phi_a[c])
+           - (U[cp] - U[cm]) / (2.0 * g->h);
+}
+
+/* Right-hand side of Eq. (DiscretePML c) for Psi_a at cell c. */
+static double orc_rhs_psi(const orc_grid *g, const double *U, const double *Psi_a,
+                          int a, int64_t c)
+{
+    int64_t ii[3];
+    orc_coords(g, c, ii);
+    int64_t cp = orc_shift(g, c, ii, a, +1);
+    int64_t cm = orc_shift(g, c, ii, a, -1);
+    int64_t im = orc_wrap(ii[a] - 1, g->N[a]);
+    double s_here = orc_sigma(g, a, ii[a]);
+    double s_left = orc_sigma(g, a, im);
+    return -0.5 * (s_left * Psi_a[c] + s_here * Psi_a[cp])
+           - (U[cp] - U[cm]) / (2.0 * g->h);
+}
+
+/* Evaluate A(U, Phi, Psi) of Eq. (DiscretePML a) on the whole grid. */
+void orc_rhs_u_all(const orc_grid *g, const double *U,
+                   double *const Phi[3], double *const Psi[3], double *out)
+{
+    int64_t n = orc_ncells(g);
+    #pragma omp parallel for schedule(static)
+    for (int64_t c = 0; c < n; ++c)
+        out[c] = orc_rhs_u(g, U, Phi, Psi, c);
+}
+
+/* Start: U^{-1} = U^0 - dt V^0 + dt^2/2 A(U^0, 0, 0).  V0 may be NULL. */
+void orc_start(const orc_grid *g, const double *U0, const double *V0, double *Um1)
+{
+    int64_t n = orc_ncells(g);
+    double dt = g->dt;
+    #pragma omp parallel for schedule(static)
+    for (int64_t c = 0; c < n; ++c) {
+        double a = orc_rhs_u(g, U0, NULL, NULL, c);
+        double v = V0 ? V0[c] : 0.0;
+        Um1[c] = U0[c] - dt * v + 0.5 * dt * dt * a;
+    }
+}
+
+/* One step of the scheme from time-n data only.
+ * Inputs: Un, Unm1, Phi[a], Psi[a] (time n).  Outputs: Unp1, PhiN[a], PsiN[a]
+ * (time n+1); outputs must not alias inputs. */
+void orc_step(const orc_grid *g, const double *Un, const double *Unm1,
+              double *const Phi[3], double *const Psi[3],
+              double *Unp1, double *const PhiN[3], double *const PsiN[3])
+{
+    int64_t n = orc_ncells(g);
+    double dt = g->dt;
+    #pragma omp parallel for schedule(static)
+    for (int64_t c = 0; c < n; ++c) {
+        double a = orc_rhs_u(g, Un, Phi, Psi, c);
+        Unp1[c] = 2.0 * Un[c] - Unm1[c] + dt * dt * a;
+        for (int ax = 0; ax < g->ndim; ++ax) {
+            PhiN[ax][c] = Phi[ax][c] + dt * orc_rhs_phi(g, Un, Phi[ax], ax, c);
+            PsiN[ax][c] = Psi[ax][c] + dt * orc_rhs_psi(g, Un, Psi[ax], ax, c);
+        }
+    }
+}
+
+/* Add the point-source term of step `n` to U^{n+1} and record receivers.
+ * wavelets: [ns][nt] row-major; traces: [nr][nt] row-major. */
+static void orc_sources_receivers(const orc_grid *g, double *Unp1, int64_t n,
+                                  int64_t ns, const int64_t *src, const double *wav,
+                                  int64_t nr, const int64_t *rec, double *traces,
+                                  int64_t nt)
+{
+    double hd = 1.0;
+    for (int a = 0; a < g->ndim; ++a) hd *= g->h;
+    if (n < nt) {
+        for (int64_t s = 0; s < ns; ++s)
+            Unp1[src[s]] += g->dt * g->dt * wav[s * nt + n] / hd;
+        for (int64_t r = 0; r < nr; ++r)
+            traces[r * nt + n] = Unp1[rec[r]];
+    }
+}
+
+/* Run `nsteps` steps in place.  On entry U = U^{n0}, Uprev = U^{n0-1},
+ * Phi/Psi at n0; on return they hold time n0+nsteps.  Step n0+k uses wavelet
+ * sample n0+k and writes trace column n0+k (when n0+k < nt).
+ * The run works on private copies, so the caller's arrays are only read at
+ * entry and written at exit.  Returns 0, or -1 if out of memory. */
+int orc_run(const orc_grid *g, double *U, double *Uprev,
+            double *const Phi[3], double *const Psi[3],
+            int64_t n0, int64_t nsteps,
+            int64_t ns, const int64_t *src, const double *wav,
+            int64_t nr, const int64_t *rec, double *traces, int64_t nt)
+{
+    int64_t n = orc_ncells(g);
+    size_t bytes = (size_t)n * sizeof(double);
+    /* private buffers: u[0..2] for U, f[a][0..1] for Phi_a, p[a][0..1] for Psi_a */
+    double *u[3] = {0, 0, 0};
+    double *f[3][2] = {{0, 0}, {0, 0}, {0, 0}};
+    double *p[3][2] = {{0, 0}, {0, 0}, {0, 0}};
+    int ok = 1;
+    for (int k = 0; k < 3; ++k) ok &= (u[k] = malloc(bytes)) != NULL;
+    for (int a = 0; a < g->ndim; ++a)
+        for (int k = 0; k < 2; ++k) {
+            ok &= (f[a][k] = malloc(bytes)) != NULL;
+            ok &= (p[a][k] = malloc(bytes)) != NULL;
+        }
+    if (ok) {
+        memcpy(u[0], U, bytes);      /* U^n     */
+        memcpy(u[1], Uprev, bytes);  /* U^{n-1} */
+        for (int a = 0; a < g->ndim; ++a) {
+            memcpy(f[a][0], Phi[a], bytes);
+            memcpy(p[a][0], Psi[a], bytes);
+        }
+        int inow = 0, iold = 1, inew = 2, cur = 0;
+        for (int64_t k = 0; k < nsteps; ++k) {
+            double *phi_now[3] = {0, 0, 0}, *psi_now[3] = {0, 0, 0};
+            double *phi_new[3] = {0, 0, 0}, *psi_new[3] = {0, 0, 0};
+            for (int a = 0; a < g->ndim; ++a) {
+                phi_now[a] = f[a][cur]; phi_new[a] = f[a][1 - cur];
+                psi_now[a] = p[a][cur]; psi_new[a] = p[a][1 - cur];
+            }
+            orc_step(g, u[inow], u[iold], phi_now, psi_now, u[inew], phi_new, psi_new);
+            orc_sources_receivers(g, u[inew], n0 + k, ns, src, wav, nr, rec, traces, nt);
+            int t = iold; iold = inow; inow = inew; inew = t;
+            cur = 1 - cur;
+        }
+        memcpy(U, u[inow], bytes);
+        memcpy(Uprev, u[iold], bytes);
+        for (int a = 0; a < g->ndim; ++a) {
+            memcpy(Phi[a], f[a][cur], bytes);
+            memcpy(Psi[a], p[a][cur], bytes);
+        }
+    }
+    for (int k = 0; k < 3; ++k) free(u[k]);
+    for (int a = 0; a < 3; ++a)
+        for (int k = 0; k < 2; ++k) { free(f[a][k]); free(p[a][k]); }
+    return ok ? 0 : -1;
+}
+
+/* Plain discrete wave equation, Eq. (DiscreteWaveEquation), leapfrog, with no
+ * damping terms at all: the untruncated "free space" reference.
+ * On entry U = U^{n0}, Uprev = U^{n0-1}; on return time n0+nsteps. */
+int orc_wave_run(const orc_grid *g, double *U, double *Uprev, int64_t nsteps)
+{
+    int64_t n = orc_ncells(g);
+    size_t bytes = (size_t)n * sizeof(double);
+    double *u[3] = {malloc(bytes), malloc(bytes), malloc(bytes)};
+    double dt2 = g->dt * g->dt;
+    if (!u[0] || !u[1] || !u[2]) {
+        free(u[0]); free(u[1]); free(u[2]);
+        return -1;
+    }
+    memcpy(u[0], U, bytes);
+    memcpy(u[1], Uprev, bytes);
+    int inow = 0, iold = 1, inew = 2;
+    for (int64_t k = 0; k < nsteps; ++k) {
+        const double *un = u[inow], *uo = u[iold];
+        double *uw = u[inew];
+        #pragma omp parallel for schedule(static)
+        for (int64_t c = 0; c < n; ++c) {
+            int64_t ii[3];
+            double lap = 0.0;
+            orc_coords(g, c, ii);
+            for (int a = 0; a < g->ndim; ++a) {
+                int64_t cp = orc_shift(g, c, ii, a, +1);
+                int64_t cm = orc_shift(g, c, ii, a, -1);
+                lap += (un[cm] - 2.0 * un[c] + un[cp]) / (g->h * g->h);
+            }
+            uw[c] = 2.0 * un[c] - uo[c] + dt2 * (g->c2 ? g->c2[c] : 1.0) * lap;
+        }
+        int t = iold; iold = inow; inow = inew; inew = t;
+    }
+    memcpy(U, u[inow], bytes);
+    memcpy(Uprev, u[iold], bytes);
+    free(u[0]); free(u[1]); free(u[2]);
+    return 0;
+}
