@@ -1,0 +1,198 @@
+/*
+ * dpml.h -- C ABI of the MI355X (gfx950) library for explicit time stepping
+ * of the discrete scalar wave equation with the reflectionless discrete
+ * perfectly matched layer of A. Chern, "A Reflectionless Discrete Perfectly
+ * Matched Layer" (J. Comput. Phys.; arXiv 1804.01390).
+ *
+ * The scheme (per axis a, grid spacing h, shifts tau_a):
+ *   Eq. (DiscretePML a):
+ *     U_tt = c^2 sum_a (tau_a^-1 U - 2U + tau_a U)/h^2
+ *            + sum_a (1/h)( sigma_a tau_a Psi_a - (tau_a^-1 sigma_a)(tau_a^-1 Phi_a) )
+ *   Eq. (DiscretePML b):
+ *     Phi_a,t = -1/2((tau_a^-1 sigma_a)(tau_a^-1 Phi_a) + sigma_a Phi_a) - (tau_a U - tau_a^-1 U)/(2h)
+ *   Eq. (DiscretePML c):
+ *     Psi_a,t = -1/2((tau_a^-1 sigma_a) Psi_a + sigma_a tau_a Psi_a) - (tau_a U - tau_a^-1 U)/(2h)
+ * discretised in time by leapfrog for U and a forward step for Phi/Psi, every
+ * right-hand side of a step taken from time level n:
+ *   U^{n+1}   = 2U^n - U^{n-1} + dt^2 A(U^n, Phi^n, Psi^n)
+ *   Phi^{n+1} = Phi^n + dt B(U^n, Phi^n),   Psi^{n+1} = Psi^n + dt C(U^n, Psi^n).
+ * With this placement every discrete plane wave continues into the layer
+ * exactly (Thm. 1 with omega' = i(z-1)/dt, z the one-step factor), so the
+ * layer reflects nothing, for any damping profile.
+ *
+ * GRID AND LAYOUT.  Axis 0 (x) is fastest.  Axis a has n[a] interior cells
+ * and lo[a] / hi[a] layer cells below / above them: N[a] = lo + n + hi cells,
+ * interior [lo, lo+n).  The grid is periodic, so the two layer sides form one
+ * band [lo+n, N) U [0, lo) traversed in +a direction (the "physical domain
+ * surrounded by the layer" of the paper's runs, Sec. 1.1.3).  Fields U are
+ * dense arrays of prod N[a] cells, cell (x,y,z) at x + N0*(y + N1*z).
+ * sigma_a(i) belongs to the edge [i, i+1] and must vanish for i in [lo, lo+n).
+ *
+ * AUXILIARY LAYOUT (what dpml_field returns).  Phi_a and Psi_a are stored
+ * only on the band (Sec. 1.1.2: Phi_a lives on {i_a >= 0}, Psi_a on
+ * {i_a >= 1} in the paper's coordinates).  The band coordinate of index i is
+ * j = (i - lo - n) mod N, j in [0, M], M = lo + hi (j = M is interior cell
+ * lo).  The compact array for axis a has the same shape as U with extent
+ * N[a] replaced by M+1 (x fastest); Phi_a is meaningful at j in [0, M-1],
+ * Psi_a at j in [1, M]; the remaining slot of each stays 0.
+ *
+ * PRECISION.  dtype DPML_F32 or DPML_F64 for every device field; host tables
+ * (sigma, c^2) are always FP64 and converted on upload.
+ *
+ * MEMORY.  The caller owns all large device memory: dpml_create borrows a
+ * workspace of dpml_workspace_bytes() bytes (256-byte aligned) that must stay
+ * alive until dpml_destroy.  The library itself allocates only the small
+ * source/receiver index tables registered by dpml_inject / dpml_record.
+ *
+ * STREAMS.  All device work is enqueued on the HIP stream given to
+ * dpml_create (NULL = the null stream), in call order.  Calls that return
+ * device results do not synchronise unless stated.  A handle must be used by
+ * one host thread at a time.
+ *
+ * ERRORS.  Every int-returning call returns DPML_OK (0) or a negative code;
+ * no exception crosses the ABI.  dpml_last_error() gives a message.
+ */
+#ifndef DPML_H
+#define DPML_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define DPML_OK 0
+#define DPML_EINVAL (-1)     /* invalid argument or unsupported configuration */
+#define DPML_ENOMEM (-2)     /* workspace too small or allocation failed       */
+#define DPML_EHIP (-3)       /* a HIP runtime call failed                      */
+#define DPML_ESTATE (-4)     /* call not valid in the handle's current state   */
+#define DPML_ENONFINITE (-5) /* a NaN or Inf appeared in the wave field        */
+
+#define DPML_F32 0
+#define DPML_F64 1
+
+/* Field selectors for dpml_field. */
+#define DPML_FIELD_U 0        /* U^n                                   */
+#define DPML_FIELD_UPREV 1    /* U^{n-1}                               */
+#define DPML_FIELD_PHI(a) (2 + 2 * (a))  /* Phi_a^n, compact band array */
+#define DPML_FIELD_PSI(a) (3 + 2 * (a))  /* Psi_a^n, compact band array */
+
+/* Kernel variants (dpml_set_variant). */
+#define DPML_VARIANT_AUTO 0   /* library default for the grid             */
+#define DPML_VARIANT_CELL 1   /* one thread per cell, 2D thread blocks     */
+#define DPML_VARIANT_MARCH 2  /* row tiles marching along the slowest axis */
+
+typedef struct dpml_grid {
+    int32_t ndim;    /* 2 or 3 */
+    int32_t dtype;   /* DPML_F32 or DPML_F64 */
+    int64_t n[3];    /* interior cells per axis (unused axes: 1) */
+    int32_t lo[3];   /* layer cells below the interior (unused axes: 0) */
+    int32_t hi[3];   /* layer cells above the interior (unused axes: 0) */
+} dpml_grid_t;
+
+typedef struct dpml dpml_t;
+
+/* Bytes of device workspace dpml_create needs for grid g; c2_is_field != 0
+ * when c^2 will be given per cell.  Returns 0 for an invalid grid. */
+size_t dpml_workspace_bytes(const dpml_grid_t *g, int32_t c2_is_field);
+
+/* Create a stepper (Eq. (DiscretePML) with the time placement above).
+ *   h, dt    grid spacing and time step (> 0).
+ *   c2       host FP64: c2_len == 1 (constant) or prod N[a] values (per cell).
+ *            c^2 multiplies the Laplacian only and must be 1 on every layer
+ *            cell and within one cell of the layer (unit speed where damping
+ *            acts, as in the paper).
+ *   sigma    host FP64 arrays sigma[a] of N[a] values for a < ndim (NULL for
+ *            an axis means no damping on it).  sigma >= 0, finite, zero on the
+ *            interior indices [lo, lo+n).  Any profile is reflectionless
+ *            (Sec. 1.1.3, the remark after Thm. 1).
+ *   workspace, ws_bytes  caller-owned device memory (borrowed).
+ *   stream   hipStream_t for all work of this handle.
+ * Host arrays are copied; the caller may free them on return.
+ * Errors: DPML_EINVAL for ndim/dtype/extents out of range, non-positive h/dt,
+ * c_max dt/h sqrt(ndim) > 1 (leapfrog stability), dt max(sigma) > 4
+ * (forward-step stability of the auxiliaries), bad sigma or c^2 values;
+ * DPML_ENOMEM if ws_bytes is too small or workspace is not 256-byte aligned;
+ * DPML_EHIP on a runtime failure.  On error *out is set to NULL. */
+int dpml_create(const dpml_grid_t *g, double h, double dt,
+                const double *c2, int64_t c2_len,
+                const double *const sigma[3],
+                void *workspace, size_t ws_bytes, void *stream,
+                dpml_t **out);
+
+/* Set the initial state (time index 0): U^0 = U0, Phi = Psi = 0 and
+ * U^{-1} = U^0 - dt V^0 + dt^2/2 A(U^0), the start that is exact for
+ * Fourier modes at rest.  U0, V0: device arrays of the grid's dtype and
+ * prod N[a] cells (V0 == NULL: zero initial velocity, as in the paper's
+ * runs).  Read on the stream; they may be released once the stream passes
+ * this point. */
+int dpml_set_state(dpml_t *h, const void *U0, const void *V0);
+
+/* Register point sources (not part of the paper): after step n the value
+ * dt^2 w_s[n] / h^ndim is added to U^{n+1} at cell cells[s].
+ *   cells     host int64 flat cell indices (copied), 0 <= cell < prod N.
+ *   wavelets  device [ns][nt] array in dtype (borrowed until replaced).
+ * ns == 0 removes all sources.  Replaces earlier registrations. */
+int dpml_inject(dpml_t *h, int64_t ns, const int64_t *cells,
+                const void *wavelets, int64_t nt);
+
+/* Register point receivers: after step n (and its sources), traces[r][n] =
+ * U^{n+1}[cells[r]] for n < nt.  cells: host int64 (copied); traces: device
+ * [nr][nt] in dtype (borrowed).  nr == 0 removes receivers. */
+int dpml_record(dpml_t *h, int64_t nr, const int64_t *cells, void *traces,
+                int64_t nt);
+
+/* Register a recorded plane: after step n, planes[n] = U^{n+1} on the plane
+ * i_axis = index (x-fastest order of the remaining axes).  planes: device
+ * [nt][plane cells] in dtype (borrowed).  axis < 0 removes the recorder. */
+int dpml_record_plane(dpml_t *h, int32_t axis, int64_t index, void *planes,
+                      int64_t nt);
+
+/* Choose the kernel variant (DPML_VARIANT_*) and, for the marching variant,
+ * the tile height in rows (0 = default).  Results are identical up to
+ * rounding order between variants. */
+int dpml_set_variant(dpml_t *h, int32_t variant, int32_t tile_rows);
+
+/* Enqueue nsteps fused steps (U, Phi, Psi, sources, receivers).  Returns
+ * before the work completes.  DPML_ESTATE before dpml_set_state;
+ * DPML_EINVAL if nsteps < 0. */
+int dpml_step(dpml_t *h, int64_t nsteps);
+
+/* As dpml_step, but every `every` steps (and at the end) synchronises and
+ * scans U^n for NaN/Inf; returns DPML_ENONFINITE at the first hit (the state
+ * is left at that step). */
+int dpml_step_checked(dpml_t *h, int64_t nsteps, int64_t every);
+
+/* Borrowed device pointer to a field of the current time level (see the
+ * DPML_FIELD_* selectors and the auxiliary layout above) and its extents in
+ * x, y, z order (unused axes 1).  Valid until the next dpml_step. */
+int dpml_field(dpml_t *h, int32_t which, void **ptr, int64_t shape[3]);
+
+/* Time index n of the current level U^n. */
+int64_t dpml_time_index(const dpml_t *h);
+
+/* Checkpoint / resume: dpml_state_bytes() bytes of device memory hold U^n,
+ * U^{n-1} and every Phi_a, Psi_a.  dpml_get_state copies the state out,
+ * dpml_put_state restores it with time index n (stream-ordered).  A resumed
+ * run is bit-identical to an uninterrupted one. */
+size_t dpml_state_bytes(const dpml_t *h);
+int dpml_get_state(dpml_t *h, void *blob);
+int dpml_put_state(dpml_t *h, const void *blob, int64_t n);
+
+/* Wait for the handle's stream and report any deferred HIP error. */
+int dpml_sync(dpml_t *h);
+
+/* Release the handle (not the caller's workspace or buffers). */
+void dpml_destroy(dpml_t *h);
+
+/* Message for an error code, and the last detailed message of a handle
+ * (or of the last failed dpml_create when h == NULL). */
+const char *dpml_strerror(int code);
+const char *dpml_last_error(const dpml_t *h);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DPML_H */

@@ -17,6 +17,8 @@ Parity status of each function (see the pins in ``tests/test_oracle_pins.py``):
                             energy conservation; reflection against free space,
                             Figs. 2/3; 1-D light-cone Green's function)
   wave_run               -- pinned (exact Fourier modes)
+  adjoint                -- pinned (dot-product identity for the wavelet map,
+                            which is linear; central differences for c^2)
 """
 from __future__ import annotations
 
@@ -82,6 +84,9 @@ def _load():
         lib.orc_run.restype = ctypes.c_int
         lib.orc_wave_run.argtypes = [gp, _DP, _DP, ctypes.c_int64]
         lib.orc_wave_run.restype = ctypes.c_int
+        lib.orc_adjoint.argtypes = [gp, _DP, ctypes.c_int64, ctypes.c_int64, _I64P, _DP,
+                                    ctypes.c_int64, _I64P, _DP, _DP, _DP]
+        lib.orc_adjoint.restype = ctypes.c_int
         _lib = lib
     return _lib
 
@@ -246,3 +251,24 @@ def wave_run(g: Grid, U, Uprev, nsteps: int):
     if rc != 0:
         raise MemoryError("oracle wave_run: out of memory")
     return U, Up
+
+
+def adjoint(g: Grid, U0, nsteps: int, sources, wavelets, receivers, resid):
+    """Discrete adjoint of start + ``nsteps`` steps (zero initial velocity)
+    for J = 1/2 sum (d - obs)^2, given resid = d - obs of shape [nr][nsteps].
+    Returns (dJ/dc2 per cell, dJ/dw of shape [ns][nsteps])."""
+    lib = _load()
+    gs, keep = g._struct()
+    U0 = _f64(U0)
+    src = np.ascontiguousarray(sources, dtype=np.int64)
+    rec = np.ascontiguousarray(receivers, dtype=np.int64)
+    wav = _f64(wavelets)
+    res = _f64(resid)
+    assert wav.shape == (len(src), nsteps) and res.shape == (len(rec), nsteps)
+    gc2 = np.zeros_like(U0)
+    gw = np.zeros((len(src), nsteps))
+    rc = lib.orc_adjoint(ctypes.byref(gs), _dp(U0), nsteps, len(src), src.ctypes.data_as(_I64P),
+                         _dp(wav), len(rec), rec.ctypes.data_as(_I64P), _dp(res), _dp(gc2), _dp(gw))
+    if rc != 0:
+        raise MemoryError("oracle adjoint: out of memory")
+    return gc2, gw

@@ -314,3 +314,123 @@ int orc_wave_run(const orc_grid *g, double *U, double *Uprev, int64_t nsteps)
     free(u[0]); free(u[1]); free(u[2]);
     return 0;
 }
+
+/* ------------------------------------------------------------------------
+ * Discrete adjoint (reverse mode) of orc_start + orc_run with point sources
+ * and receivers, for the misfit J = 1/2 sum_{r,n} (d_r[n] - obs_r[n])^2 where
+ * d_r[n] = U^{n+1}[rec_r] after step n.  The caller passes the residual
+ * resid[r][n] = d_r[n] - obs_r[n]; the routine returns
+ *   grad_c2[c]   = dJ/dc^2(c)       (c^2 given per cell; NULL c2 means 1)
+ *   grad_w[s][n] = dJ/dw_s[n]
+ * The forward levels U^0..U^{N-1} are recomputed and stored in full (plain,
+ * no checkpointing).  Zero initial velocity and Phi = Psi = 0 at start.
+ *
+ * Transposing one step (x^{n+1} = T x^n + b^n) gives, with a^k the adjoint
+ * of U^k and p_a, q_a those of Phi_a, Psi_a at level n+1:
+ *   grad_c2   += dt^2 a^{n+1} * (L U^n)                (L: periodic Laplacian)
+ *   a^n        = 2 a^{n+1} - a^{n+2} + dt^2 L(c^2 a^{n+1})
+ *                + dt sum_a G_a(p_a + q_a)             (G_a^T = -G_a)
+ *   p_a^n(i)   = p_a(i) - dt/2 sigma(i)(p_a(i) + p_a(i+e))   - dt^2/h sigma(i)   a^{n+1}(i+e)
+ *   q_a^n(i)   = q_a(i) - dt/2 sigma(i-1)(q_a(i) + q_a(i-e)) + dt^2/h sigma(i-1) a^{n+1}(i-e)
+ * with G_a U = (U(i+e) - U(i-e))/(2h).  The start U^{-1} = U^0 + dt^2/2 c^2 L U^0
+ * adds  grad_c2 += dt^2/2 a^{-1} L U^0, with a^{-1} = -a^1.
+ * ------------------------------------------------------------------------ */
+static double orc_lap(const orc_grid *g, const double *U, int64_t c)
+{
+    int64_t ii[3];
+    double lap = 0.0;
+    orc_coords(g, c, ii);
+    for (int a = 0; a < g->ndim; ++a) {
+        int64_t cp = orc_shift(g, c, ii, a, +1);
+        int64_t cm = orc_shift(g, c, ii, a, -1);
+        lap += (U[cm] - 2.0 * U[c] + U[cp]) / (g->h * g->h);
+    }
+    return lap;
+}
+
+int orc_adjoint(const orc_grid *g, const double *U0, int64_t nsteps,
+                int64_t ns, const int64_t *src, const double *wav,
+                int64_t nr, const int64_t *rec, const double *resid,
+                double *grad_c2, double *grad_w)
+{
+    int64_t n = orc_ncells(g);
+    int d = g->ndim;
+    size_t bytes = (size_t)n * sizeof(double);
+    double hd = 1.0;
+    for (int a = 0; a < d; ++a) hd *= g->h;
+    double dt = g->dt, dt2 = dt * dt;
+    int ok = 1;
+    /* forward: store U^0 .. U^{N-1} */
+    double *hist = malloc(bytes * (size_t)(nsteps > 0 ? nsteps : 1));
+    double *Uprev = malloc(bytes), *U = malloc(bytes);
+    double *Phi[3] = {0, 0, 0}, *Psi[3] = {0, 0, 0};
+    ok &= hist && Uprev && U;
+    for (int a = 0; a < d; ++a) {
+        ok &= (Phi[a] = calloc((size_t)n, sizeof(double))) != NULL;
+        ok &= (Psi[a] = calloc((size_t)n, sizeof(double))) != NULL;
+    }
+    /* adjoint buffers */
+    double *a_next = calloc((size_t)n, sizeof(double));   /* a^{n+2} */
+    double *a_cur = calloc((size_t)n, sizeof(double));    /* a^{n+1} */
+    double *a_new = calloc((size_t)n, sizeof(double));
+    double *c2a = malloc(bytes);
+    double *p[3] = {0, 0, 0}, *q[3] = {0, 0, 0}, *pn[3] = {0, 0, 0}, *qn[3] = {0, 0, 0};
+    ok &= a_next && a_cur && a_new && c2a;
+    for (int a = 0; a < d; ++a) {
+        ok &= (p[a] = calloc((size_t)n, sizeof(double))) != NULL;
+        ok &= (q[a] = calloc((size_t)n, sizeof(double))) != NULL;
+        ok &= (pn[a] = calloc((size_t)n, sizeof(double))) != NULL;
+        ok &= (qn[a] = calloc((size_t)n, sizeof(double))) != NULL;
+    }
+    if (ok) {
+        memcpy(U, U0, bytes);
+        orc_start(g, U0, NULL, Uprev);
+        for (int64_t k = 0; k < nsteps; ++k) {
+            memcpy(hist + (size_t)k * (size_t)n, U, bytes);
+            /* one step with a scratch traces array (not needed here) */
+            orc_run(g, U, Uprev, Phi, Psi, k, 1, ns, src, wav, 0, NULL, NULL, nsteps);
+        }
+        memset(grad_c2, 0, bytes);
+        for (int64_t k = nsteps - 1; k >= 0; --k) {
+            const double *Un = hist + (size_t)k * (size_t)n;
+            /* receivers read U^{k+1}: seed its adjoint with the residual */
+            for (int64_t r = 0; r < nr; ++r) a_cur[rec[r]] += resid[r * nsteps + k];
+            /* sources were added to U^{k+1} */
+            for (int64_t s = 0; s < ns; ++s) grad_w[s * nsteps + k] = dt2 / hd * a_cur[src[s]];
+            for (int64_t c = 0; c < n; ++c) c2a[c] = (g->c2 ? g->c2[c] : 1.0) * a_cur[c];
+            #pragma omp parallel for schedule(static)
+            for (int64_t c = 0; c < n; ++c) {
+                int64_t ii[3];
+                orc_coords(g, c, ii);
+                grad_c2[c] += dt2 * a_cur[c] * orc_lap(g, Un, c);
+                double v = 2.0 * a_cur[c] - a_next[c] + dt2 * orc_lap(g, c2a, c);
+                for (int a = 0; a < d; ++a) {
+                    int64_t cp = orc_shift(g, c, ii, a, +1);
+                    int64_t cm = orc_shift(g, c, ii, a, -1);
+                    int64_t im = orc_wrap(ii[a] - 1, g->N[a]);
+                    double s_here = orc_sigma(g, a, ii[a]);
+                    double s_left = orc_sigma(g, a, im);
+                    v += dt * ((p[a][cp] + q[a][cp]) - (p[a][cm] + q[a][cm])) / (2.0 * g->h);
+                    pn[a][c] = p[a][c] - 0.5 * dt * s_here * (p[a][c] + p[a][cp])
+                               - dt2 / g->h * s_here * a_cur[cp];
+                    qn[a][c] = q[a][c] - 0.5 * dt * s_left * (q[a][c] + q[a][cm])
+                               + dt2 / g->h * s_left * a_cur[cm];
+                }
+                a_new[c] = v;
+            }
+            double *t = a_next; a_next = a_cur; a_cur = a_new; a_new = t;
+            for (int a = 0; a < d; ++a) {
+                double *tp = p[a]; p[a] = pn[a]; pn[a] = tp;
+                double *tq = q[a]; q[a] = qn[a]; qn[a] = tq;
+            }
+        }
+        /* start: a^{-1} = -a^1 (a_next now holds a^1) */
+        for (int64_t c = 0; c < n; ++c)
+            grad_c2[c] += 0.5 * dt2 * (-a_next[c]) * orc_lap(g, U0, c);
+    }
+    free(hist); free(Uprev); free(U); free(a_next); free(a_cur); free(a_new); free(c2a);
+    for (int a = 0; a < 3; ++a) {
+        free(Phi[a]); free(Psi[a]); free(p[a]); free(q[a]); free(pn[a]); free(qn[a]);
+    }
+    return ok ? 0 : -1;
+}

@@ -1,0 +1,275 @@
+"""MI355X (gfx950) stepper for the discrete scalar wave equation with the
+reflectionless discrete perfectly matched layer of A. Chern ("A Reflectionless
+Discrete Perfectly Matched Layer", arXiv 1804.01390).
+
+This module is a thin ctypes binding over ``libdpml.so`` (C ABI in
+``include/dpml.h``): it marshals arguments and uses torch only to allocate
+device memory and to name the current HIP stream.  Every step of the scheme
+runs in the library's HIP kernels; there is no CPU or torch fallback -- if the
+library or the GPU is missing, constructing a ``Simulation`` raises.
+
+Shapes: per-axis sizes are given in the paper's axis order (x, y, z); device
+fields are torch tensors of shape reversed(N) (z, y, x), x fastest.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libdpml.so")
+
+DPML_OK, DPML_EINVAL, DPML_ENOMEM, DPML_EHIP, DPML_ESTATE, DPML_ENONFINITE = 0, -1, -2, -3, -4, -5
+DPML_F32, DPML_F64 = 0, 1
+VARIANT_AUTO, VARIANT_CELL, VARIANT_MARCH = 0, 1, 2
+FIELD_U, FIELD_UPREV = 0, 1
+
+
+def FIELD_PHI(a: int) -> int:
+    return 2 + 2 * a
+
+
+def FIELD_PSI(a: int) -> int:
+    return 3 + 2 * a
+
+
+EXPORTED = [
+    "dpml_workspace_bytes", "dpml_create", "dpml_set_state", "dpml_inject", "dpml_record",
+    "dpml_record_plane", "dpml_set_variant", "dpml_step", "dpml_step_checked", "dpml_field",
+    "dpml_time_index", "dpml_state_bytes", "dpml_get_state", "dpml_put_state", "dpml_sync",
+    "dpml_destroy", "dpml_strerror", "dpml_last_error",
+]
+
+
+class DpmlError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__("dpml error %d: %s" % (code, msg))
+        self.code = code
+
+
+class GridT(ctypes.Structure):
+    _fields_ = [("ndim", ctypes.c_int32), ("dtype", ctypes.c_int32),
+                ("n", ctypes.c_int64 * 3), ("lo", ctypes.c_int32 * 3), ("hi", ctypes.c_int32 * 3)]
+
+
+_lib = None
+_VP = ctypes.c_void_p
+_DP = ctypes.POINTER(ctypes.c_double)
+_I64P = ctypes.POINTER(ctypes.c_int64)
+
+
+def load_library():
+    """Load libdpml.so (built by ``python -m paper_1804_01390_amd.build``)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError("libdpml.so is not built; run: python -m paper_1804_01390_amd.build")
+    lib = ctypes.CDLL(LIB_PATH)
+    gp = ctypes.POINTER(GridT)
+    sig = {
+        "dpml_workspace_bytes": (ctypes.c_size_t, [gp, ctypes.c_int32]),
+        "dpml_create": (ctypes.c_int, [gp, ctypes.c_double, ctypes.c_double, _DP, ctypes.c_int64,
+                                       _DP * 3, _VP, ctypes.c_size_t, _VP, ctypes.POINTER(_VP)]),
+        "dpml_set_state": (ctypes.c_int, [_VP, _VP, _VP]),
+        "dpml_inject": (ctypes.c_int, [_VP, ctypes.c_int64, _I64P, _VP, ctypes.c_int64]),
+        "dpml_record": (ctypes.c_int, [_VP, ctypes.c_int64, _I64P, _VP, ctypes.c_int64]),
+        "dpml_record_plane": (ctypes.c_int, [_VP, ctypes.c_int32, ctypes.c_int64, _VP, ctypes.c_int64]),
+        "dpml_set_variant": (ctypes.c_int, [_VP, ctypes.c_int32, ctypes.c_int32]),
+        "dpml_step": (ctypes.c_int, [_VP, ctypes.c_int64]),
+        "dpml_step_checked": (ctypes.c_int, [_VP, ctypes.c_int64, ctypes.c_int64]),
+        "dpml_field": (ctypes.c_int, [_VP, ctypes.c_int32, ctypes.POINTER(_VP), ctypes.c_int64 * 3]),
+        "dpml_time_index": (ctypes.c_int64, [_VP]),
+        "dpml_state_bytes": (ctypes.c_size_t, [_VP]),
+        "dpml_get_state": (ctypes.c_int, [_VP, _VP]),
+        "dpml_put_state": (ctypes.c_int, [_VP, _VP, ctypes.c_int64]),
+        "dpml_sync": (ctypes.c_int, [_VP]),
+        "dpml_destroy": (None, [_VP]),
+        "dpml_strerror": (ctypes.c_char_p, [ctypes.c_int]),
+        "dpml_last_error": (ctypes.c_char_p, [_VP]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _grid(n, lo, hi, dtype_code) -> GridT:
+    g = GridT()
+    g.ndim = len(n)
+    g.dtype = dtype_code
+    for a in range(3):
+        g.n[a] = int(n[a]) if a < len(n) else 1
+        g.lo[a] = int(lo[a]) if a < len(n) else 0
+        g.hi[a] = int(hi[a]) if a < len(n) else 0
+    return g
+
+
+def workspace_bytes(n, lo, hi, dtype_code: int, c2_field: bool) -> int:
+    return int(load_library().dpml_workspace_bytes(ctypes.byref(_grid(n, lo, hi, dtype_code)),
+                                                   1 if c2_field else 0))
+
+
+class Simulation:
+    """One discrete-PML stepper on one GPU.
+
+    n, lo, hi : interior cells and layer cells below/above, per axis (x, y, z)
+    h, dt     : grid spacing and time step
+    sigma     : per-axis FP64 damping arrays of length lo+n+hi (sigma(i) on
+                edge [i, i+1]); None for an undamped axis
+    c2        : scalar (1.0) or FP64 array of shape reversed(N)
+    dtype     : torch.float32 or torch.float64
+    """
+
+    def __init__(self, n: Sequence[int], lo: Sequence[int], hi: Sequence[int], h: float, dt: float,
+                 sigma: Sequence[Optional[np.ndarray]], c2=1.0, dtype=None, device=None):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("paper_1804_01390_amd needs a ROCm GPU; none is visible")
+        self.torch = torch
+        self.lib = load_library()
+        self.dtype = dtype if dtype is not None else torch.float32
+        if self.dtype not in (torch.float32, torch.float64):
+            raise ValueError("dtype must be torch.float32 or torch.float64")
+        self.code = DPML_F32 if self.dtype == torch.float32 else DPML_F64
+        self.device = torch.device(device if device is not None else "cuda:0")
+        self.n, self.lo, self.hi = list(n), list(lo), list(hi)
+        self.ndim = len(n)
+        self.N = [self.lo[a] + self.n[a] + self.hi[a] for a in range(self.ndim)]
+        self.shape = tuple(reversed(self.N))
+        self.h, self.dt = float(h), float(dt)
+        c2a = np.ascontiguousarray(np.asarray(c2, dtype=np.float64).reshape(-1))
+        field = c2a.size != 1
+        g = _grid(self.n, self.lo, self.hi, self.code)
+        nbytes = self.lib.dpml_workspace_bytes(ctypes.byref(g), 1 if field else 0)
+        if nbytes == 0:
+            raise DpmlError(DPML_EINVAL, "invalid grid")
+        self.workspace = torch.empty(int(nbytes), dtype=torch.uint8, device=self.device)
+        sig3 = (_DP * 3)()
+        self._sig_keep = []
+        for a in range(3):
+            if a < self.ndim and sigma is not None and a < len(sigma) and sigma[a] is not None:
+                s = np.ascontiguousarray(np.asarray(sigma[a], dtype=np.float64))
+                if s.shape != (self.N[a],):
+                    raise ValueError("sigma[%d] must have %d entries" % (a, self.N[a]))
+                self._sig_keep.append(s)
+                sig3[a] = s.ctypes.data_as(_DP)
+            else:
+                sig3[a] = _DP()
+        handle = _VP()
+        with torch.cuda.device(self.device):
+            stream = torch.cuda.current_stream(self.device).cuda_stream
+        rc = self.lib.dpml_create(ctypes.byref(g), self.h, self.dt, c2a.ctypes.data_as(_DP), c2a.size,
+                                  sig3, ctypes.c_void_p(self.workspace.data_ptr()), int(nbytes),
+                                  ctypes.c_void_p(stream), ctypes.byref(handle))
+        if rc != DPML_OK:
+            raise DpmlError(rc, self.lib.dpml_last_error(None).decode())
+        self.handle = handle
+        self._keep = {}
+
+    # -- helpers ----------------------------------------------------------
+    def _check(self, rc: int):
+        if rc != DPML_OK:
+            raise DpmlError(rc, self.lib.dpml_last_error(self.handle).decode())
+
+    def _dev(self, t):
+        t = self.torch.as_tensor(t)
+        if t.device != self.device or t.dtype != self.dtype or not t.is_contiguous():
+            t = t.to(device=self.device, dtype=self.dtype).contiguous()
+        return t
+
+    # -- API ----------------------------------------------------------------
+    def set_variant(self, variant: int, tile_rows: int = 0):
+        self._check(self.lib.dpml_set_variant(self.handle, variant, tile_rows))
+
+    def set_state(self, U0, V0=None):
+        """U^0 (and optional V^0) as arrays/tensors of shape reversed(N)."""
+        U0 = self._dev(U0)
+        if tuple(U0.shape) != self.shape:
+            raise ValueError("U0 must have shape %s" % (self.shape,))
+        V = None if V0 is None else self._dev(V0)
+        self._keep["U0"], self._keep["V0"] = U0, V
+        self._check(self.lib.dpml_set_state(self.handle, ctypes.c_void_p(U0.data_ptr()),
+                                            ctypes.c_void_p(V.data_ptr() if V is not None else 0)))
+
+    def inject(self, cells: Sequence[int], wavelets):
+        """Point sources at flat cell indices with wavelets [ns][nt]."""
+        c = np.ascontiguousarray(np.asarray(cells, dtype=np.int64).reshape(-1))
+        w = self._dev(wavelets)
+        if w.dim() != 2 or w.shape[0] != c.size:
+            raise ValueError("wavelets must be [ns][nt]")
+        self._keep["wavelets"] = w
+        self._check(self.lib.dpml_inject(self.handle, c.size, c.ctypes.data_as(_I64P),
+                                         ctypes.c_void_p(w.data_ptr()), w.shape[1]))
+
+    def record(self, cells: Sequence[int], nt: int):
+        """Point receivers; returns the device trace tensor [nr][nt]."""
+        c = np.ascontiguousarray(np.asarray(cells, dtype=np.int64).reshape(-1))
+        tr = self.torch.zeros((c.size, nt), dtype=self.dtype, device=self.device)
+        self._keep["traces"] = tr
+        self._check(self.lib.dpml_record(self.handle, c.size, c.ctypes.data_as(_I64P),
+                                         ctypes.c_void_p(tr.data_ptr()), nt))
+        return tr
+
+    def record_plane(self, axis: int, index: int, nt: int):
+        """Record U on the plane i_axis = index after every step; returns the
+        device tensor [nt][...] (remaining axes, slowest first)."""
+        rest = [self.N[a] for a in range(self.ndim) if a != axis]
+        pl = self.torch.zeros([nt] + list(reversed(rest)), dtype=self.dtype, device=self.device)
+        self._keep["planes"] = pl
+        self._check(self.lib.dpml_record_plane(self.handle, axis, index, ctypes.c_void_p(pl.data_ptr()), nt))
+        return pl
+
+    def step(self, nsteps: int = 1):
+        self._check(self.lib.dpml_step(self.handle, int(nsteps)))
+
+    def step_checked(self, nsteps: int, every: int):
+        self._check(self.lib.dpml_step_checked(self.handle, int(nsteps), int(every)))
+
+    def field(self, which: int):
+        """Borrowed view of a field of the current level (valid until the next step)."""
+        ptr = _VP()
+        shape = (ctypes.c_int64 * 3)()
+        self._check(self.lib.dpml_field(self.handle, which, ctypes.byref(ptr), shape))
+        ext = [shape[a] for a in range(self.ndim)]
+        off = ptr.value - self.workspace.data_ptr()
+        esize = 4 if self.code == DPML_F32 else 8
+        count = int(np.prod(ext))
+        raw = self.workspace[off: off + count * esize]
+        return raw.view(self.dtype).view(tuple(reversed(ext)))
+
+    @property
+    def U(self):
+        return self.field(FIELD_U)
+
+    @property
+    def time_index(self) -> int:
+        return int(self.lib.dpml_time_index(self.handle))
+
+    def get_state(self):
+        nb = int(self.lib.dpml_state_bytes(self.handle))
+        blob = self.torch.empty(nb, dtype=self.torch.uint8, device=self.device)
+        self._check(self.lib.dpml_get_state(self.handle, ctypes.c_void_p(blob.data_ptr())))
+        return blob, self.time_index
+
+    def put_state(self, blob, n: int):
+        self._check(self.lib.dpml_put_state(self.handle, ctypes.c_void_p(blob.data_ptr()), int(n)))
+
+    def sync(self):
+        self._check(self.lib.dpml_sync(self.handle))
+
+    def close(self):
+        if getattr(self, "handle", None):
+            self.lib.dpml_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,409 @@
+// dpml_kernels.hpp -- gfx950 kernels of the discrete-PML wave stepper.
+//
+// One fused sweep per time step (Eq. (DiscretePML a-c), leapfrog for U and a
+// forward step for Phi/Psi, every right-hand side from time level n):
+//
+//   U^{n+1}(i)  = 2U^n - U^{n-1} + dt^2 c^2 sum_a (U(i-e_a) - 2U + U(i+e_a))/h^2
+//                 + dt^2/h sum_a ( sigma_a(i) Psi_a(i+e_a) - sigma_a(i-1) Phi_a(i-e_a) )
+//   Phi_a^{n+1} = Phi_a - dt/2 (sigma_a(i-1) Phi_a(i-e_a) + sigma_a(i) Phi_a(i))
+//                 - dt/(2h) (U(i+e_a) - U(i-e_a))
+//   Psi_a^{n+1} = Psi_a - dt/2 (sigma_a(i-1) Psi_a(i) + sigma_a(i) Psi_a(i+e_a))
+//                 - dt/(2h) (U(i+e_a) - U(i-e_a))
+//
+// U^{n+1} overwrites U^{n-1} in place (each cell reads its own old value
+// before writing it; neighbours are read from U^n only).  Phi/Psi are double
+// buffered because the update of band slot j reads slots j-1 / j+1.
+//
+// Layout: x fastest.  The layer along axis a is the periodic band
+// [b, N) U [0, lo) with b = lo + n; its band coordinate is
+// j = (i - b) mod N in [0, M], M = lo + hi, and Phi_a/Psi_a are stored
+// compactly with extent M+1 in place of N along axis a.  The damping table
+// sig[j] holds sigma_a at array index (b + j) mod N (sig[M] = sigma(lo) = 0).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace dpmlk {
+
+template <typename T>
+struct Axis {
+    int32_t N;        // cells along the axis
+    int32_t b;        // first band cell (lo + n)
+    int32_t M;        // band thickness lo + hi (0: no layer on this axis)
+    int32_t hi;       // N - b
+    const T *sig;     // sig[j], j in [0, M]
+    const T *phi;     // Phi_a^n   (compact)
+    const T *psi;     // Psi_a^n   (compact)
+    T *phi_o;         // Phi_a^{n+1}
+    T *psi_o;         // Psi_a^{n+1}
+};
+
+template <typename T>
+struct StepArgs {
+    Axis<T> ax[3];
+    const T *u;       // U^n
+    T *uo;            // U^{n-1} on entry, U^{n+1} on exit
+    const T *c2;      // per-cell c^2, or nullptr
+    T k_lap;          // dt^2 c^2 / h^2 (constant c^2) or dt^2 / h^2 (c^2 field)
+    T k_damp;         // dt^2 / h
+    T half_dt;        // dt / 2
+    T dt_2h;          // dt / (2h)
+    int32_t nx, ny, nz;
+    int32_t tiles_x;  // tiles along x (marching kernels)
+    int32_t tiles_y;  // tiles along y (3D marching kernel)
+    int32_t tile_rows;// rows (2D) or planes (3D) per marching tile
+    int32_t n_tiles;  // real tiles (the grid may be padded to a multiple of 8)
+};
+
+__device__ __forceinline__ int wrap_dec(int i, int n) { return i == 0 ? n - 1 : i - 1; }
+__device__ __forceinline__ int wrap_inc(int i, int n) { return i == n - 1 ? 0 : i + 1; }
+
+// Band coordinate of array index i along an axis, or a value > M outside the
+// band and the first interior cell.
+template <typename T>
+__device__ __forceinline__ int band_coord(const Axis<T> &A, int i)
+{
+    return i >= A.b ? i - A.b : i + A.hi;
+}
+
+// Damping terms of one axis at a cell with band coordinate j <= M: returns
+// the contribution sigma(i) Psi(i+e) - sigma(i-1) Phi(i-e) (to be scaled by
+// dt^2/h) and writes Phi^{n+1}, Psi^{n+1} of the cell.
+//   cbase: compact index of slot j = 0 for this cell's line along the axis;
+//   cstr : stride of the axis in the compact array;  du = U(i+e) - U(i-e).
+template <typename T>
+__device__ __forceinline__ T layer_terms(const Axis<T> &A, int j, int64_t cbase, int64_t cstr,
+                                         T du, T half_dt, T dt_2h)
+{
+    const int64_t c = cbase + (int64_t)j * cstr;
+    const T s = A.sig[j];                              // sigma_a(i)
+    const T sl = j > 0 ? A.sig[j - 1] : T(0);          // sigma_a(i-1)
+    const T phi_l = j > 0 ? A.phi[c - cstr] : T(0);    // Phi_a(i-e)
+    const T psi_r = j < A.M ? A.psi[c + cstr] : T(0);  // Psi_a(i+e)
+    const T grad = dt_2h * du;
+    if (j < A.M) {
+        const T phi_c = A.phi[c];
+        A.phi_o[c] = phi_c - half_dt * (sl * phi_l + s * phi_c) - grad;
+    }
+    if (j > 0) {
+        const T psi_c = A.psi[c];
+        A.psi_o[c] = psi_c - half_dt * (sl * psi_c + s * psi_r) - grad;
+    }
+    return s * psi_r - sl * phi_l;
+}
+
+// Complete update of one cell given its stencil values.  (x, y, z) are the
+// cell coordinates; for 2D z = 0 and the z values are unused.
+template <typename T, int D>
+__device__ __forceinline__ T cell_update(const StepArgs<T> &p, int x, int y, int z, int64_t idx,
+                                         T uc, T uxm, T uxp, T uym, T uyp, T uzm, T uzp, T uold)
+{
+    T lap = (uxm + uxp - T(2) * uc) + (uym + uyp - T(2) * uc);
+    if (D == 3) lap += (uzm + uzp - T(2) * uc);
+    T k = p.k_lap;
+    if (p.c2) k *= p.c2[idx];
+    T acc = T(2) * uc - uold + k * lap;
+    T damp = T(0);
+    const int64_t nx = p.nx, ny = p.ny;
+    // x-axis layer: compact [z][y][Mx+1]
+    if (p.ax[0].M > 0) {
+        const int j = band_coord(p.ax[0], x);
+        if (j <= p.ax[0].M) {
+            const int64_t base = ((int64_t)z * ny + y) * (p.ax[0].M + 1);
+            damp += layer_terms(p.ax[0], j, base, 1, uxp - uxm, p.half_dt, p.dt_2h);
+        }
+    }
+    // y-axis layer: compact [z][My+1][x]
+    if (p.ax[1].M > 0) {
+        const int j = band_coord(p.ax[1], y);
+        if (j <= p.ax[1].M) {
+            const int64_t base = (int64_t)z * (p.ax[1].M + 1) * nx + x;
+            damp += layer_terms(p.ax[1], j, base, nx, uyp - uym, p.half_dt, p.dt_2h);
+        }
+    }
+    // z-axis layer: compact [Mz+1][y][x]
+    if (D == 3 && p.ax[2].M > 0) {
+        const int j = band_coord(p.ax[2], z);
+        if (j <= p.ax[2].M) {
+            const int64_t base = (int64_t)y * nx + x;
+            damp += layer_terms(p.ax[2], j, base, nx * ny, uzp - uzm, p.half_dt, p.dt_2h);
+        }
+    }
+    return acc + p.k_damp * damp;
+}
+
+// ---------------------------------------------------------------------------
+// Variant CELL: one thread per cell, blocks of 64 x 4 (x 1) threads.
+// ---------------------------------------------------------------------------
+template <typename T, int D>
+__global__ void __launch_bounds__(256) k_step_cell(StepArgs<T> p)
+{
+    const int x = blockIdx.x * 64 + threadIdx.x;
+    const int y = blockIdx.y * 4 + threadIdx.y;
+    const int z = D == 3 ? (int)blockIdx.z : 0;
+    if (x >= p.nx || y >= p.ny) return;
+    const int64_t nx = p.nx, ny = p.ny;
+    const int64_t row = ((int64_t)z * ny + y) * nx;
+    const int64_t idx = row + x;
+    const T *u = p.u;
+    const int xm = wrap_dec(x, p.nx), xp = wrap_inc(x, p.nx);
+    const int ym = wrap_dec(y, p.ny), yp = wrap_inc(y, p.ny);
+    T uzm = T(0), uzp = T(0);
+    if (D == 3) {
+        const int zm = wrap_dec(z, p.nz), zp = wrap_inc(z, p.nz);
+        uzm = u[((int64_t)zm * ny + y) * nx + x];
+        uzp = u[((int64_t)zp * ny + y) * nx + x];
+    }
+    const int64_t plane = (int64_t)z * ny * nx;
+    const T r = cell_update<T, D>(p, x, y, z, idx, u[idx], u[row + xm], u[row + xp],
+                                  u[plane + (int64_t)ym * nx + x], u[plane + (int64_t)yp * nx + x],
+                                  uzm, uzp, p.uo[idx]);
+    p.uo[idx] = r;
+}
+
+// Map a hardware block id to a logical tile so that the blocks one XCD
+// executes (ids congruent mod 8) get consecutive tiles: neighbouring tiles
+// then share their halo rows in that XCD's L2.
+__device__ __forceinline__ int xcd_tile(int b, int nblocks)
+{
+    const int per = nblocks >> 3;   // nblocks is a multiple of 8
+    return (b & 7) * per + (b >> 3);
+}
+
+// ---------------------------------------------------------------------------
+// Variant MARCH, 2D: a block of 256 threads owns 256*VX consecutive columns
+// and marches over `tile_rows` rows, keeping U^n of rows y-1, y, y+1 in
+// registers.  Each row of U^n is read from HBM once per tile (plus two halo
+// rows per tile); x neighbours inside the thread's vector come from
+// registers, the two outer ones from the L1 cache.
+// ---------------------------------------------------------------------------
+template <typename T, int VX> struct Vec;
+template <> struct Vec<float, 1> { using type = float; };
+template <> struct Vec<float, 2> { using type = float2; };
+template <> struct Vec<float, 4> { using type = float4; };
+template <> struct Vec<double, 1> { using type = double; };
+template <> struct Vec<double, 2> { using type = double2; };
+
+template <typename T, int VX>
+struct Row {
+    T v[VX];
+};
+
+template <typename T, int VX>
+__device__ __forceinline__ Row<T, VX> load_row(const T *ptr)
+{
+    Row<T, VX> r;
+    using V = typename Vec<T, VX>::type;
+    const V w = *reinterpret_cast<const V *>(ptr);
+    const T *e = reinterpret_cast<const T *>(&w);
+#pragma unroll
+    for (int k = 0; k < VX; ++k) r.v[k] = e[k];
+    return r;
+}
+
+template <typename T, int VX>
+__device__ __forceinline__ void store_row(T *ptr, const Row<T, VX> &r)
+{
+    using V = typename Vec<T, VX>::type;
+    V w;
+    T *e = reinterpret_cast<T *>(&w);
+#pragma unroll
+    for (int k = 0; k < VX; ++k) e[k] = r.v[k];
+    *reinterpret_cast<V *>(ptr) = w;
+}
+
+template <typename T, int VX>
+__global__ void __launch_bounds__(256) k_step_march2d(StepArgs<T> p)
+{
+    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+    if (tile >= p.n_tiles) return;
+    const int tx = tile % p.tiles_x;          // tiles along x vary fastest
+    const int ty = tile / p.tiles_x;
+    const int x0 = (tx * 256 + (int)threadIdx.x) * VX;
+    if (x0 >= p.nx) return;
+    const int nx = p.nx, ny = p.ny;
+    const int y0 = ty * p.tile_rows;
+    const int y1 = min(y0 + p.tile_rows, ny);
+    const T *u = p.u;
+    const int xl = wrap_dec(x0, nx);          // left neighbour of the vector
+    const int xr = wrap_inc(x0 + VX - 1, nx); // right neighbour of the vector
+
+    Row<T, VX> um = load_row<T, VX>(u + (int64_t)wrap_dec(y0, ny) * nx + x0);
+    Row<T, VX> uc = load_row<T, VX>(u + (int64_t)y0 * nx + x0);
+    Row<T, VX> up = load_row<T, VX>(u + (int64_t)wrap_inc(y0, ny) * nx + x0);
+    for (int y = y0; y < y1; ++y) {
+        const int64_t row = (int64_t)y * nx;
+        // prefetch the row after next while this one is computed
+        Row<T, VX> upp = up;
+        if (y + 1 < y1) upp = load_row<T, VX>(u + (int64_t)wrap_inc(y + 1, ny) * nx + x0);
+        const Row<T, VX> old = load_row<T, VX>(p.uo + row + x0);
+        const T left = u[row + xl];
+        const T right = u[row + xr];
+        Row<T, VX> out;
+#pragma unroll
+        for (int k = 0; k < VX; ++k) {
+            const T uxm = k == 0 ? left : uc.v[k - 1];
+            const T uxp = k == VX - 1 ? right : uc.v[k + 1];
+            out.v[k] = cell_update<T, 2>(p, x0 + k, y, 0, row + x0 + k, uc.v[k], uxm, uxp,
+                                         um.v[k], up.v[k], T(0), T(0), old.v[k]);
+        }
+        store_row<T, VX>(p.uo + row + x0, out);
+        um = uc;
+        uc = up;
+        up = upp;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Variant MARCH, 3D: a block of 64 x 4 threads owns a 64 x (4*RY) tile of an
+// (x, y) plane and marches over `tile_rows` planes in z, keeping U^n of
+// planes z-1, z, z+1 in registers; x and y neighbours come from L1/L2.
+// ---------------------------------------------------------------------------
+template <typename T, int RY>
+__global__ void __launch_bounds__(256) k_step_march3d(StepArgs<T> p)
+{
+    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+    if (tile >= p.n_tiles) return;
+    const int per_plane = p.tiles_x * p.tiles_y;
+    const int tz = tile / per_plane;
+    const int rem = tile - tz * per_plane;
+    const int ty = rem / p.tiles_x;           // y tiles fastest after x
+    const int tx = rem - ty * p.tiles_x;
+    const int x = tx * 64 + (int)threadIdx.x;
+    if (x >= p.nx) return;
+    const int nx = p.nx, ny = p.ny, nz = p.nz;
+    const int64_t sxy = (int64_t)nx * ny;
+    const int z0 = tz * p.tile_rows;
+    const int z1 = min(z0 + p.tile_rows, nz);
+    const int xm = wrap_dec(x, nx), xp = wrap_inc(x, nx);
+    const T *u = p.u;
+    int yy[RY];
+    bool ok[RY];
+    T um[RY], uc[RY], up[RY];
+#pragma unroll
+    for (int r = 0; r < RY; ++r) {
+        yy[r] = (ty * 4 + (int)threadIdx.y) * RY + r;
+        ok[r] = yy[r] < ny;
+        const int64_t col = (int64_t)(ok[r] ? yy[r] : 0) * nx + x;
+        um[r] = u[(int64_t)wrap_dec(z0, nz) * sxy + col];
+        uc[r] = u[(int64_t)z0 * sxy + col];
+        up[r] = u[(int64_t)wrap_inc(z0, nz) * sxy + col];
+    }
+    for (int z = z0; z < z1; ++z) {
+        const int64_t plane = (int64_t)z * sxy;
+        const bool more = z + 1 < z1;
+        const int64_t nplane = (int64_t)(more ? wrap_inc(z + 1, nz) : z) * sxy;
+        T upp[RY];
+#pragma unroll
+        for (int r = 0; r < RY; ++r) {
+            const int y = ok[r] ? yy[r] : 0;
+            const int64_t col = (int64_t)y * nx + x;
+            upp[r] = more ? u[nplane + col] : T(0);
+            if (ok[r]) {
+                const int64_t idx = plane + col;
+                const T uxm = u[plane + (int64_t)y * nx + xm];
+                const T uxp = u[plane + (int64_t)y * nx + xp];
+                const T uym = u[plane + (int64_t)wrap_dec(y, ny) * nx + x];
+                const T uyp = u[plane + (int64_t)wrap_inc(y, ny) * nx + x];
+                const T old = p.uo[idx];
+                p.uo[idx] = cell_update<T, 3>(p, x, y, z, idx, uc[r], uxm, uxp, uym, uyp,
+                                              um[r], up[r], old);
+            }
+            um[r] = uc[r];
+            uc[r] = up[r];
+            up[r] = upp[r];
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Start: U^{-1} = U^0 - dt V^0 + dt^2/2 c^2 Lap(U^0)  (Phi = Psi = 0).
+// ---------------------------------------------------------------------------
+template <typename T, int D>
+__global__ void __launch_bounds__(256) k_start(const T *__restrict__ u0, const T *__restrict__ v0,
+                                               T *__restrict__ um1, const T *__restrict__ c2,
+                                               T half_k_lap, T dt, int nx, int ny, int nz)
+{
+    const int x = blockIdx.x * 64 + threadIdx.x;
+    const int y = blockIdx.y * 4 + threadIdx.y;
+    const int z = D == 3 ? (int)blockIdx.z : 0;
+    if (x >= nx || y >= ny) return;
+    const int64_t sx = nx, sxy = (int64_t)nx * ny;
+    const int64_t idx = (int64_t)z * sxy + (int64_t)y * sx + x;
+    const int64_t plane = (int64_t)z * sxy;
+    const T c = u0[idx];
+    T lap = (u0[plane + (int64_t)y * sx + wrap_dec(x, nx)] + u0[plane + (int64_t)y * sx + wrap_inc(x, nx)] - T(2) * c)
+          + (u0[plane + (int64_t)wrap_dec(y, ny) * sx + x] + u0[plane + (int64_t)wrap_inc(y, ny) * sx + x] - T(2) * c);
+    if (D == 3)
+        lap += u0[(int64_t)wrap_dec(z, nz) * sxy + (int64_t)y * sx + x]
+             + u0[(int64_t)wrap_inc(z, nz) * sxy + (int64_t)y * sx + x] - T(2) * c;
+    T k = half_k_lap;
+    if (c2) k *= c2[idx];
+    T r = c + k * lap;
+    if (v0) r -= dt * v0[idx];
+    um1[idx] = r;
+}
+
+// Point sources: U[cell_s] += amp * w[s][n]   (amp = dt^2 / h^d).  The host
+// sorts the sources by cell: cells[q] is the q-th cell in sorted order and
+// order[q] the caller's index of that source.  The first thread of each run
+// of equal cells adds the whole run (in the caller's order), so coincident
+// sources need no atomics and the result is deterministic.
+template <typename T>
+__global__ void __launch_bounds__(256) k_inject(T *__restrict__ u, const int64_t *__restrict__ cells,
+                                                const int64_t *__restrict__ order,
+                                                const T *__restrict__ wav, int64_t ns, int64_t nt,
+                                                int64_t n, T amp)
+{
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= ns) return;
+    const int64_t cell = cells[q];
+    if (q > 0 && cells[q - 1] == cell) return;
+    T add = T(0);
+    for (int64_t r = q; r < ns && cells[r] == cell; ++r) add += wav[order[r] * nt + n];
+    u[cell] += amp * add;
+}
+
+// Receivers: traces[r][n] = U[cell_r].
+template <typename T>
+__global__ void __launch_bounds__(256) k_record(const T *__restrict__ u, const int64_t *__restrict__ cells,
+                                                T *__restrict__ traces, int64_t nr, int64_t nt, int64_t n)
+{
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= nr) return;
+    traces[r * nt + n] = u[cells[r]];
+}
+
+// Plane recorder: out[q] = U on the plane i_axis = index, q in x-fastest order
+// of the two remaining axes (extents e0 fastest, e1).
+template <typename T>
+__global__ void __launch_bounds__(256) k_record_plane(const T *__restrict__ u, T *__restrict__ out,
+                                                      int64_t e0, int64_t e1, int64_t s0, int64_t s1,
+                                                      int64_t offset)
+{
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= e0 * e1) return;
+    const int64_t a = q % e0, b = q / e0;
+    out[q] = u[offset + a * s0 + b * s1];
+}
+
+// Non-finite scan: flags[block] = 1 if the block's cells hold a NaN or Inf.
+template <typename T>
+__global__ void __launch_bounds__(256) k_nonfinite(const T *__restrict__ u, int64_t n, int32_t *__restrict__ flags)
+{
+    __shared__ int any;
+    if (threadIdx.x == 0) any = 0;
+    __syncthreads();
+    int bad = 0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const T v = u[i];
+        bad |= !(v - v == T(0));   // NaN or +-Inf
+    }
+    if (bad) any = 1;              // benign race: every writer stores 1
+    __syncthreads();
+    if (threadIdx.x == 0) flags[blockIdx.x] = any;
+}
+
+}  // namespace dpmlk

@@ -1,0 +1,213 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 CPU oracle on
+the same seeded inputs.  Tolerances (peak-normalised max error per field):
+1e-12 in FP64, 2e-5 in FP32.  Auxiliaries are compared on their supports."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import synthetic
+from helpers import compare_states, gpu_state, rel_err
+
+torch = pytest.importorskip("torch")
+dp = pytest.importorskip("paper_1804_01390_amd")
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"f64": 1e-12, "f32": 2e-5}
+
+
+def _dtype(name):
+    return torch.float64 if name == "f64" else torch.float32
+
+
+def _run_both(n, lo, hi, sigma, U0, steps, dtype, variant=dp.VARIANT_AUTO, c2=None, dt=0.5, h=1.0,
+              V0=None, tile_rows=0):
+    print("case n=%s lo=%s hi=%s steps=%d %s variant=%d" % (n, lo, hi, steps, dtype, variant), flush=True)
+    N = [lo[a] + n[a] + hi[a] for a in range(len(n))]
+    sim = dp.Simulation(n, lo, hi, h, dt, sigma, c2=1.0 if c2 is None else c2, dtype=_dtype(dtype))
+    sim.set_variant(variant, tile_rows)
+    sim.set_state(torch.from_numpy(U0), None if V0 is None else torch.from_numpy(V0))
+    sim.step(steps)
+    gs = gpu_state(sim)
+    g = oracle.Grid(N, h, dt, sigma, c2=c2)
+    ref, _ = oracle.run(g, oracle.start(g, U0, V0), steps)
+    sim.close()
+    return compare_states(gs, ref, n, lo, hi)
+
+
+def _assert_errs(errs, dtype):
+    print("errors:", {k: "%.2e" % v for k, v in errs.items()}, flush=True)
+    for k, v in errs.items():
+        assert v <= TOL[dtype], (k, v)
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("variant", [dp.VARIANT_CELL, dp.VARIANT_MARCH])
+def test_bump2d_parity(dtype, variant):
+    """128^2 interior + 16-cell layer, quadratic ramp to 2, Gaussian width 4,
+    dt = 0.5, 500 steps (the small FP64 parity workload)."""
+    w = synthetic.bump2d(128, 16, 500)
+    errs = _run_both(w.n, w.lo, w.hi, w.sigma, w.U0, w.steps, dtype, variant)
+    _assert_errs(errs, dtype)
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("variant,tile_rows", [(dp.VARIANT_CELL, 0), (dp.VARIANT_MARCH, 0),
+                                               (dp.VARIANT_MARCH, 7)])
+def test_ragged_2d_random_damping(dtype, variant, tile_rows):
+    """Odd extents (several tiles plus ragged tails), unequal sides, one side
+    without a layer, random damping (Fig. 3 profile), white-noise data."""
+    rng = np.random.default_rng(21)
+    n, lo, hi = [611, 203], [5, 9], [13, 0]
+    sig = [synthetic.sigma_random(n[a], lo[a], hi[a], 2.0, rng) for a in range(2)]
+    U0 = synthetic.white_noise_disk(n, lo, hi, 60.0, 0.25, rng)
+    errs = _run_both(n, lo, hi, sig, U0, 150, dtype, variant, tile_rows=tile_rows)
+    _assert_errs(errs, dtype)
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_axis_without_layer_and_odd_width(dtype):
+    """x has no layer at all (plain periodic), y has a one-sided layer; odd row
+    length (vector width falls back to 1)."""
+    rng = np.random.default_rng(3)
+    n, lo, hi = [257, 100], [0, 0], [0, 12]
+    sig = [None, synthetic.sigma_ramp(n[1], 0, 12, 2.0)]
+    U0 = synthetic.gaussian_sum(n, lo, hi, 8, 2.0, 6.0, rng)
+    errs = _run_both(n, lo, hi, sig, U0, 120, dtype, dp.VARIANT_MARCH)
+    _assert_errs(errs, dtype)
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("variant", [dp.VARIANT_CELL, dp.VARIANT_MARCH])
+def test_3d_parity(dtype, variant):
+    rng = np.random.default_rng(8)
+    n, lo, hi = [45, 38, 33], [6, 3, 7], [4, 8, 5]
+    sig = [synthetic.sigma_random(n[a], lo[a], hi[a], 2.0, rng) for a in range(3)]
+    U0 = synthetic.gaussian_sum(n, lo, hi, 6, 2.0, 5.0, rng)
+    errs = _run_both(n, lo, hi, sig, U0, 80, dtype, variant, dt=0.4)
+    _assert_errs(errs, dtype)
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_c2_field_and_initial_velocity(dtype):
+    rng = np.random.default_rng(5)
+    n, lo, hi = [200, 150], [10, 10], [10, 10]
+    sig = [synthetic.sigma_ramp(n[a], 10, 10, 2.0) for a in range(2)]
+    c2 = synthetic.smooth_c2(n, lo, hi, 6, 10.0, 30.0, 0.5, 8, rng)
+    U0 = synthetic.gaussian_sum(n, lo, hi, 10, 2.0, 6.0, rng)
+    V0 = synthetic.gaussian_sum(n, lo, hi, 10, 2.0, 6.0, rng)
+    dt = 0.5 / math.sqrt(float(np.max(c2)))
+    errs = _run_both(n, lo, hi, sig, U0, 200, dtype, dp.VARIANT_MARCH, c2=c2, dt=dt, V0=V0)
+    _assert_errs(errs, dtype)
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_sources_receivers_plane_3d(dtype):
+    """Ricker point source at the centre, point receivers and a recorded
+    plane through the source."""
+    w = synthetic.ricker3d(n=40, m=6, steps=90, ppw=8.0)
+    w.sources.append(synthetic.flat_index(w.N, [10, 12, 30]))
+    wav = np.vstack([w.wavelets, 0.5 * np.roll(w.wavelets[0], 7)[None, :]])
+    rec = [w.sources[0], synthetic.flat_index(w.N, [3, 3, 3]), synthetic.flat_index(w.N, [30, 25, 20]),
+           w.sources[1]]
+    print("case ricker3d n=40 m=6 steps=90 %s" % dtype, flush=True)
+    sim = dp.Simulation(w.n, w.lo, w.hi, w.h, w.dt, w.sigma, dtype=_dtype(dtype))
+    sim.set_state(torch.zeros(tuple(reversed(w.N)), dtype=torch.float64))
+    sim.inject(w.sources, torch.from_numpy(wav))
+    tr = sim.record(rec, w.steps)
+    axis, index = w.plane
+    pl = sim.record_plane(axis, index, w.steps)
+    sim.step(w.steps)
+    gs = gpu_state(sim)
+    g = oracle.Grid(w.N, w.h, w.dt, w.sigma)
+    ref, rtr = oracle.run(g, oracle.start(g, np.zeros(tuple(reversed(w.N)))), w.steps,
+                          sources=w.sources, wavelets=wav, receivers=rec, nt=w.steps)
+    errs = compare_states(gs, ref, w.n, w.lo, w.hi)
+    errs["traces"] = rel_err(tr.double().cpu().numpy(), rtr)
+    # plane at the final step must equal the final field on that plane
+    errs["plane_final"] = rel_err(pl[-1].double().cpu().numpy(), ref.U[index])
+    sim.close()
+    _assert_errs(errs, dtype)
+
+
+def test_plane_recorder_matches_oracle_every_step():
+    w = synthetic.ricker3d(n=24, m=4, steps=30, ppw=6.0)
+    sim = dp.Simulation(w.n, w.lo, w.hi, w.h, w.dt, w.sigma, dtype=torch.float64)
+    sim.set_state(torch.zeros(tuple(reversed(w.N)), dtype=torch.float64))
+    sim.inject(w.sources, torch.from_numpy(w.wavelets))
+    axis, index = w.plane
+    pl = sim.record_plane(axis, index, w.steps).cpu()
+    sim.step(w.steps)
+    sim.sync()
+    pl = sim._keep["planes"].double().cpu().numpy()
+    g = oracle.Grid(w.N, w.h, w.dt, w.sigma)
+    s = oracle.start(g, np.zeros(tuple(reversed(w.N))))
+    for k in range(w.steps):
+        s, _ = oracle.run(g, s, 1, sources=w.sources, wavelets=w.wavelets, nt=w.steps)
+        assert rel_err(pl[k], s.U[index]) <= 1e-12, k
+    sim.close()
+
+
+def test_checkpoint_resume_is_bit_identical():
+    w = synthetic.bump2d(96, 12, 0)
+    runs = []
+    for resume in (False, True):
+        sim = dp.Simulation(w.n, w.lo, w.hi, w.h, w.dt, w.sigma, dtype=torch.float32)
+        sim.set_state(torch.from_numpy(w.U0))
+        sim.step(77)
+        if resume:
+            blob, n = sim.get_state()
+            blob = blob.clone()
+            sim.close()
+            sim = dp.Simulation(w.n, w.lo, w.hi, w.h, w.dt, w.sigma, dtype=torch.float32)
+            sim.put_state(blob, n)
+        sim.step(123)
+        sim.sync()
+        runs.append(gpu_state(sim))
+        assert sim.time_index == 200
+        sim.close()
+    a, b = runs
+    assert np.array_equal(a.U, b.U) and np.array_equal(a.Uprev, b.Uprev)
+    for k in range(2):
+        assert np.array_equal(a.Phi[k], b.Phi[k]) and np.array_equal(a.Psi[k], b.Psi[k])
+
+
+def test_runs_are_deterministic():
+    w = synthetic.bumps2d(n=700, m=20, steps=60, seed=4)
+    out = []
+    for _ in range(2):
+        sim = dp.Simulation(w.n, w.lo, w.hi, w.h, w.dt, w.sigma, dtype=torch.float32)
+        sim.set_state(torch.from_numpy(w.U0))
+        sim.step(w.steps)
+        sim.sync()
+        out.append(sim.U.cpu().numpy().copy())
+        sim.close()
+    assert np.array_equal(out[0], out[1])
+
+
+def test_step_checked_reports_nonfinite():
+    w = synthetic.bump2d(64, 8, 0)
+    U0 = w.U0.copy()
+    U0[40, 40] = np.nan
+    sim = dp.Simulation(w.n, w.lo, w.hi, w.h, w.dt, w.sigma, dtype=torch.float64)
+    sim.set_state(torch.from_numpy(U0))
+    with pytest.raises(dp.DpmlError) as ei:
+        sim.step_checked(20, 5)
+    assert ei.value.code == dp.DPML_ENONFINITE
+    sim.close()
+    sim = dp.Simulation(w.n, w.lo, w.hi, w.h, w.dt, w.sigma, dtype=torch.float64)
+    sim.set_state(torch.from_numpy(w.U0))
+    sim.step_checked(20, 5)
+    assert sim.time_index == 20
+    sim.close()
+
+
+def test_step_before_state_is_an_error():
+    w = synthetic.bump2d(32, 4, 0)
+    sim = dp.Simulation(w.n, w.lo, w.hi, w.h, w.dt, w.sigma, dtype=torch.float32)
+    with pytest.raises(dp.DpmlError) as ei:
+        sim.step(1)
+    assert ei.value.code == dp.DPML_ESTATE
+    sim.close()
