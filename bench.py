@@ -117,6 +117,30 @@ def traffic_from_profile(workload: str, dtype_name: str):
     return rec.get("bytes_per_launch")
 
 
+def copy_probe(mib: int = 1024, reps: int = 20):
+    """A plain device copy of known size (torch's copy kernel): the achievable
+    read+write bandwidth on this GPU and the reference for scaling the HBM
+    counters of rocprofv3 (FETCH_SIZE / WRITE_SIZE) to bytes."""
+    import torch
+    n = mib * (1 << 20) // 4
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    gbs = 2 * n * 4 / (ms * 1e-3) / 1e9
+    print(json.dumps({"copy_probe_bytes_read": n * 4, "copy_probe_bytes_written": n * 4,
+                      "ms": round(ms, 4), "GB_per_s": round(gbs, 1)}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -127,7 +151,12 @@ def main():
     ap.add_argument("--dtypes", default="f32,f64")
     ap.add_argument("--variant", type=int, default=0)
     ap.add_argument("--tile-rows", type=int, default=0)
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only time a plain 1 GiB device copy and exit")
     args = ap.parse_args()
+    if args.copy_probe:
+        copy_probe()
+        return
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only (the stencil would shard by slabs "
               "with halo exchange; that path is not built); use --gpus 1", file=sys.stderr)

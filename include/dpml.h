@@ -89,6 +89,12 @@ typedef struct dpml_grid {
     int64_t n[3];    /* interior cells per axis (unused axes: 1) */
     int32_t lo[3];   /* layer cells below the interior (unused axes: 0) */
     int32_t hi[3];   /* layer cells above the interior (unused axes: 0) */
+    int64_t batch;   /* independent problems of this grid stepped together
+                        (shots sharing c^2 and sigma); <= 1 means one.  Every
+                        device field is then [batch][member] with the member
+                        layout below; cell indices passed to dpml_inject /
+                        dpml_record address the whole batch
+                        (member * prod N + cell). */
 } dpml_grid_t;
 
 typedef struct dpml dpml_t;
@@ -180,8 +186,86 @@ size_t dpml_state_bytes(const dpml_t *h);
 int dpml_get_state(dpml_t *h, void *blob);
 int dpml_put_state(dpml_t *h, const void *blob, int64_t n);
 
+/* ---- Discrete adjoint (reverse mode of the scheme above) ----------------
+ * For the receiver misfit J = 1/2 sum_{r,n} (traces[r][n] - obs[r][n])^2 the
+ * adjoint of one step is the transposed step, run backwards in time:
+ *   a^n   = 2a^{n+1} - a^{n+2} + dt^2 L(c^2 a^{n+1}) + dt sum_a G_a(p_a + q_a)
+ *   p_a^n = p_a - dt/2 sigma(i)(p_a(i) + p_a(i+e)) - dt^2/h sigma(i) a^{n+1}(i+e)
+ *   q_a^n = q_a - dt/2 sigma(i-1)(q_a(i) + q_a(i-e)) + dt^2/h sigma(i-1) a^{n+1}(i-e)
+ * (a, p, q adjoint to U, Phi, Psi; G_a the central difference, L the
+ * Laplacian), giving dJ/dc^2 = sum_n dt^2 a^{n+1} L U^n (+ the start term)
+ * and dJ/dw_s[n] = dt^2/h^d a^{n+1}(s).  Forward levels are recomputed from
+ * checkpoints taken every ckpt_every steps (sqrt(T) checkpointing). */
+
+/* Bytes of caller-owned device memory the checkpointed forward + adjoint of
+ * nsteps steps needs (checkpoints, one segment of recomputed levels, the
+ * adjoint state).  0 on invalid arguments. */
+size_t dpml_adjoint_workspace_bytes(const dpml_t *h, int64_t nsteps, int64_t ckpt_every);
+
+/* Run nsteps steps from time index 0 (after dpml_set_state) exactly as
+ * dpml_step does (sources, receivers, plane), saving a checkpoint of the
+ * state every ckpt_every steps into adj_ws (borrowed until the next call of
+ * this function).  DPML_ESTATE if the handle is not at time index 0. */
+int dpml_forward_checkpointed(dpml_t *h, int64_t nsteps, int64_t ckpt_every,
+                              void *adj_ws, size_t bytes);
+
+/* Gradients of J after dpml_forward_checkpointed:
+ *   resid    device [nr][nt] in dtype: traces - obs for the registered
+ *            receivers (same layout as the trace buffer);
+ *   grad_c2  device FP64, prod N values, ACCUMULATED (+=) over all batch
+ *            members and steps (FP64 accumulation, deterministic);
+ *   grad_w   device [ns][nt] in dtype for the registered sources (written
+ *            for n < nsteps), or NULL.
+ * Afterwards the handle's fields hold an intermediate level: call
+ * dpml_set_state or dpml_put_state before stepping again.  May be called
+ * again (e.g. with another residual) while the checkpoints are intact. */
+int dpml_adjoint(dpml_t *h, const void *resid, double *grad_c2, void *grad_w);
+
 /* Wait for the handle's stream and report any deferred HIP error. */
 int dpml_sync(dpml_t *h);
+
+/* ---- Many independent 2D problems of different sizes --------------------
+ * Each problem is its own grid (Eq. (DiscretePML) with unit wave speed, the
+ * time placement above and its own h, dt, sigma); one kernel launch per step
+ * advances every problem, walking a flat work list of row tiles over all of
+ * them, and a whole run of steps can be captured into one HIP graph and
+ * replayed by a single launch.  No sources/receivers on this path. */
+typedef struct dpml_multi dpml_multi_t;
+
+/* Workspace bytes for `count` problems (grids[p].ndim must be 2, one dtype
+ * for all, batch <= 1).  0 on invalid grids. */
+size_t dpml_multi_workspace_bytes(int64_t count, const dpml_grid_t *grids);
+
+/* Create.  h[p], dt[p] per problem (dt/h sqrt(2) <= 1, dt max sigma <= 4);
+ * sigmas[3p + a] the host FP64 damping array of axis a (a = 0, 1; entry
+ * 3p + 2 unused), same rules as dpml_create.  Host arrays are copied;
+ * workspace is borrowed (256-byte aligned); all work goes on `stream`.
+ * Errors as dpml_create (message from dpml_multi_last_error(NULL)). */
+int dpml_multi_create(int64_t count, const dpml_grid_t *grids, const double *h,
+                      const double *dt, const double *const *sigmas,
+                      void *workspace, size_t ws_bytes, void *stream,
+                      dpml_multi_t **out);
+
+/* Start every problem at rest: U0[p] is a device array of problem p's
+ * dtype and cells (read on the stream). */
+int dpml_multi_set_state(dpml_multi_t *h, const void *const *U0);
+
+/* Advance all problems nsteps steps.  use_graph != 0 captures the nsteps
+ * launches into one HIP graph (cached for the same nsteps and buffer parity)
+ * and replays it with one launch. */
+int dpml_multi_step(dpml_multi_t *h, int64_t nsteps, int32_t use_graph);
+
+/* Borrowed pointer and extents of a field of problem `prob` (selectors and
+ * layouts as dpml_field). */
+int dpml_multi_field(dpml_multi_t *h, int64_t prob, int32_t which, void **ptr,
+                     int64_t shape[3]);
+
+/* Tiles in the work list of one step (for reporting). */
+int64_t dpml_multi_tiles(const dpml_multi_t *h);
+
+int dpml_multi_sync(dpml_multi_t *h);
+void dpml_multi_destroy(dpml_multi_t *h);
+const char *dpml_multi_last_error(const dpml_multi_t *h);
 
 /* Release the handle (not the caller's workspace or buffers). */
 void dpml_destroy(dpml_t *h);

@@ -14,6 +14,7 @@ fields are torch tensors of shape reversed(N) (z, y, x), x fastest.
 from __future__ import annotations
 
 import ctypes
+import math
 import os
 from typing import Optional, Sequence
 
@@ -41,6 +42,10 @@ EXPORTED = [
     "dpml_record_plane", "dpml_set_variant", "dpml_step", "dpml_step_checked", "dpml_field",
     "dpml_time_index", "dpml_state_bytes", "dpml_get_state", "dpml_put_state", "dpml_sync",
     "dpml_destroy", "dpml_strerror", "dpml_last_error",
+    "dpml_adjoint_workspace_bytes", "dpml_forward_checkpointed", "dpml_adjoint",
+    "dpml_multi_workspace_bytes", "dpml_multi_create", "dpml_multi_set_state", "dpml_multi_step",
+    "dpml_multi_field", "dpml_multi_tiles", "dpml_multi_sync", "dpml_multi_destroy",
+    "dpml_multi_last_error",
 ]
 
 
@@ -52,7 +57,8 @@ class DpmlError(RuntimeError):
 
 class GridT(ctypes.Structure):
     _fields_ = [("ndim", ctypes.c_int32), ("dtype", ctypes.c_int32),
-                ("n", ctypes.c_int64 * 3), ("lo", ctypes.c_int32 * 3), ("hi", ctypes.c_int32 * 3)]
+                ("n", ctypes.c_int64 * 3), ("lo", ctypes.c_int32 * 3), ("hi", ctypes.c_int32 * 3),
+                ("batch", ctypes.c_int64)]
 
 
 _lib = None
@@ -90,6 +96,20 @@ def load_library():
         "dpml_destroy": (None, [_VP]),
         "dpml_strerror": (ctypes.c_char_p, [ctypes.c_int]),
         "dpml_last_error": (ctypes.c_char_p, [_VP]),
+        "dpml_adjoint_workspace_bytes": (ctypes.c_size_t, [_VP, ctypes.c_int64, ctypes.c_int64]),
+        "dpml_forward_checkpointed": (ctypes.c_int, [_VP, ctypes.c_int64, ctypes.c_int64, _VP, ctypes.c_size_t]),
+        "dpml_adjoint": (ctypes.c_int, [_VP, _VP, _VP, _VP]),
+        "dpml_multi_workspace_bytes": (ctypes.c_size_t, [ctypes.c_int64, gp]),
+        "dpml_multi_create": (ctypes.c_int, [ctypes.c_int64, gp, _DP, _DP, ctypes.POINTER(_DP), _VP,
+                                             ctypes.c_size_t, _VP, ctypes.POINTER(_VP)]),
+        "dpml_multi_set_state": (ctypes.c_int, [_VP, ctypes.POINTER(_VP)]),
+        "dpml_multi_step": (ctypes.c_int, [_VP, ctypes.c_int64, ctypes.c_int32]),
+        "dpml_multi_field": (ctypes.c_int, [_VP, ctypes.c_int64, ctypes.c_int32, ctypes.POINTER(_VP),
+                                            ctypes.c_int64 * 3]),
+        "dpml_multi_tiles": (ctypes.c_int64, [_VP]),
+        "dpml_multi_sync": (ctypes.c_int, [_VP]),
+        "dpml_multi_destroy": (None, [_VP]),
+        "dpml_multi_last_error": (ctypes.c_char_p, [_VP]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -99,10 +119,11 @@ def load_library():
     return lib
 
 
-def _grid(n, lo, hi, dtype_code) -> GridT:
+def _grid(n, lo, hi, dtype_code, batch: int = 1) -> GridT:
     g = GridT()
     g.ndim = len(n)
     g.dtype = dtype_code
+    g.batch = int(batch)
     for a in range(3):
         g.n[a] = int(n[a]) if a < len(n) else 1
         g.lo[a] = int(lo[a]) if a < len(n) else 0
@@ -110,8 +131,8 @@ def _grid(n, lo, hi, dtype_code) -> GridT:
     return g
 
 
-def workspace_bytes(n, lo, hi, dtype_code: int, c2_field: bool) -> int:
-    return int(load_library().dpml_workspace_bytes(ctypes.byref(_grid(n, lo, hi, dtype_code)),
+def workspace_bytes(n, lo, hi, dtype_code: int, c2_field: bool, batch: int = 1) -> int:
+    return int(load_library().dpml_workspace_bytes(ctypes.byref(_grid(n, lo, hi, dtype_code, batch)),
                                                    1 if c2_field else 0))
 
 
@@ -124,10 +145,13 @@ class Simulation:
                 edge [i, i+1]); None for an undamped axis
     c2        : scalar (1.0) or FP64 array of shape reversed(N)
     dtype     : torch.float32 or torch.float64
+    batch     : independent problems (shots) sharing c2 and sigma; fields are
+                then [batch, *reversed(N)] and cell indices address the batch
     """
 
     def __init__(self, n: Sequence[int], lo: Sequence[int], hi: Sequence[int], h: float, dt: float,
-                 sigma: Sequence[Optional[np.ndarray]], c2=1.0, dtype=None, device=None):
+                 sigma: Sequence[Optional[np.ndarray]], c2=1.0, dtype=None, device=None,
+                 batch: int = 1):
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("paper_1804_01390_amd needs a ROCm GPU; none is visible")
@@ -141,11 +165,14 @@ class Simulation:
         self.n, self.lo, self.hi = list(n), list(lo), list(hi)
         self.ndim = len(n)
         self.N = [self.lo[a] + self.n[a] + self.hi[a] for a in range(self.ndim)]
-        self.shape = tuple(reversed(self.N))
+        self.batch = int(batch)
+        self.member_shape = tuple(reversed(self.N))
+        self.shape = self.member_shape if self.batch == 1 else (self.batch,) + self.member_shape
+        self.cells = int(np.prod(self.N))
         self.h, self.dt = float(h), float(dt)
         c2a = np.ascontiguousarray(np.asarray(c2, dtype=np.float64).reshape(-1))
         field = c2a.size != 1
-        g = _grid(self.n, self.lo, self.hi, self.code)
+        g = _grid(self.n, self.lo, self.hi, self.code, self.batch)
         nbytes = self.lib.dpml_workspace_bytes(ctypes.byref(g), 1 if field else 0)
         if nbytes == 0:
             raise DpmlError(DPML_EINVAL, "invalid grid")
@@ -239,9 +266,10 @@ class Simulation:
         ext = [shape[a] for a in range(self.ndim)]
         off = ptr.value - self.workspace.data_ptr()
         esize = 4 if self.code == DPML_F32 else 8
-        count = int(np.prod(ext))
+        count = int(np.prod(ext)) * self.batch
         raw = self.workspace[off: off + count * esize]
-        return raw.view(self.dtype).view(tuple(reversed(ext)))
+        view = tuple(reversed(ext)) if self.batch == 1 else (self.batch,) + tuple(reversed(ext))
+        return raw.view(self.dtype).view(view)
 
     @property
     def U(self):
@@ -263,9 +291,136 @@ class Simulation:
     def sync(self):
         self._check(self.lib.dpml_sync(self.handle))
 
+    # -- adjoint --------------------------------------------------------------
+    def forward_checkpointed(self, nsteps: int, ckpt_every: int = 0):
+        """Run nsteps from time 0 saving sqrt(T) checkpoints (or every
+        ``ckpt_every`` steps) for a later ``adjoint`` call."""
+        every = int(ckpt_every) if ckpt_every > 0 else max(1, int(round(math.sqrt(nsteps))))
+        nb = int(self.lib.dpml_adjoint_workspace_bytes(self.handle, int(nsteps), every))
+        if nb == 0:
+            raise DpmlError(DPML_EINVAL, "bad checkpoint arguments")
+        if self._keep.get("adj_ws") is None or self._keep["adj_ws"].numel() < nb:
+            self._keep["adj_ws"] = None
+            self._keep["adj_ws"] = self.torch.empty(nb, dtype=self.torch.uint8, device=self.device)
+        ws = self._keep["adj_ws"]
+        self._check(self.lib.dpml_forward_checkpointed(self.handle, int(nsteps), every,
+                                                       ctypes.c_void_p(ws.data_ptr()), ws.numel()))
+        self.adj_nsteps = int(nsteps)
+
+    def adjoint(self, resid, grad_c2=None, want_wavelets: bool = True):
+        """Gradients for J = 1/2 sum (traces - obs)^2 given resid = traces - obs
+        ([nr][nt], same layout as the trace buffer).  Returns (dJ/dc2 as FP64
+        tensor of one member's shape, dJ/dw [ns][nt] or None)."""
+        res = self._dev(resid) if resid is not None else None
+        if grad_c2 is None:
+            grad_c2 = self.torch.zeros(self.member_shape, dtype=self.torch.float64, device=self.device)
+        gw = None
+        if want_wavelets and "wavelets" in self._keep:
+            gw = self.torch.zeros_like(self._keep["wavelets"])
+        self._check(self.lib.dpml_adjoint(self.handle, ctypes.c_void_p(res.data_ptr() if res is not None else 0),
+                                          ctypes.c_void_p(grad_c2.data_ptr()),
+                                          ctypes.c_void_p(gw.data_ptr() if gw is not None else 0)))
+        self._keep["resid"] = res
+        return grad_c2, gw
+
     def close(self):
         if getattr(self, "handle", None):
             self.lib.dpml_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class MultiSimulation:
+    """Many independent 2D problems of different sizes advanced together by
+    one kernel launch per step (optionally one HIP-graph launch per run).
+
+    problems: sequence of objects with attributes n, lo, hi (2 entries each),
+              h, dt and sigma (two FP64 arrays); unit wave speed.
+    """
+
+    def __init__(self, problems, dtype=None, device=None):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("paper_1804_01390_amd needs a ROCm GPU; none is visible")
+        self.torch = torch
+        self.lib = load_library()
+        self.dtype = dtype if dtype is not None else torch.float32
+        self.code = DPML_F32 if self.dtype == torch.float32 else DPML_F64
+        self.device = torch.device(device if device is not None else "cuda:0")
+        self.count = len(problems)
+        grids = (GridT * self.count)()
+        h = np.ascontiguousarray([float(p.h) for p in problems])
+        dt = np.ascontiguousarray([float(p.dt) for p in problems])
+        sig = (_DP * (3 * self.count))()
+        self._keep_host = []
+        self.shapes = []
+        for i, p in enumerate(problems):
+            grids[i] = _grid(p.n, p.lo, p.hi, self.code)
+            N = [p.lo[a] + p.n[a] + p.hi[a] for a in range(2)]
+            self.shapes.append(tuple(reversed(N)))
+            for a in range(3):
+                if a < 2 and p.sigma[a] is not None:
+                    arr = np.ascontiguousarray(p.sigma[a], dtype=np.float64)
+                    self._keep_host.append(arr)
+                    sig[3 * i + a] = arr.ctypes.data_as(_DP)
+                else:
+                    sig[3 * i + a] = _DP()
+        nbytes = self.lib.dpml_multi_workspace_bytes(self.count, grids)
+        if nbytes == 0:
+            raise DpmlError(DPML_EINVAL, self.lib.dpml_multi_last_error(None).decode())
+        self.workspace = torch.empty(int(nbytes), dtype=torch.uint8, device=self.device)
+        with torch.cuda.device(self.device):
+            stream = torch.cuda.current_stream(self.device).cuda_stream
+        handle = _VP()
+        rc = self.lib.dpml_multi_create(self.count, grids, h.ctypes.data_as(_DP), dt.ctypes.data_as(_DP),
+                                        sig, ctypes.c_void_p(self.workspace.data_ptr()), int(nbytes),
+                                        ctypes.c_void_p(stream), ctypes.byref(handle))
+        if rc != DPML_OK:
+            raise DpmlError(rc, self.lib.dpml_multi_last_error(None).decode())
+        self.handle = handle
+        self.tiles = int(self.lib.dpml_multi_tiles(handle))
+        self.cells = int(sum(int(np.prod(s)) for s in self.shapes))
+        self._keep = []
+
+    def _check(self, rc):
+        if rc != DPML_OK:
+            raise DpmlError(rc, self.lib.dpml_multi_last_error(self.handle).decode())
+
+    def set_state(self, U0s):
+        ts = []
+        for i, u in enumerate(U0s):
+            t = self.torch.as_tensor(u).to(device=self.device, dtype=self.dtype).contiguous()
+            if tuple(t.shape) != self.shapes[i]:
+                raise ValueError("U0[%d] must have shape %s" % (i, self.shapes[i]))
+            ts.append(t)
+        ptrs = (_VP * self.count)(*[t.data_ptr() for t in ts])
+        self._keep = ts
+        self._check(self.lib.dpml_multi_set_state(self.handle, ptrs))
+
+    def step(self, nsteps: int, graph: bool = False):
+        self._check(self.lib.dpml_multi_step(self.handle, int(nsteps), 1 if graph else 0))
+
+    def field(self, prob: int, which: int):
+        ptr = _VP()
+        shape = (ctypes.c_int64 * 3)()
+        self._check(self.lib.dpml_multi_field(self.handle, prob, which, ctypes.byref(ptr), shape))
+        ext = [shape[0], shape[1]]
+        off = ptr.value - self.workspace.data_ptr()
+        esize = 4 if self.code == DPML_F32 else 8
+        count = ext[0] * ext[1]
+        return self.workspace[off: off + count * esize].view(self.dtype).view(ext[1], ext[0])
+
+    def sync(self):
+        self._check(self.lib.dpml_multi_sync(self.handle))
+
+    def close(self):
+        if getattr(self, "handle", None):
+            self.lib.dpml_multi_destroy(self.handle)
             self.handle = None
 
     def __del__(self):

@@ -20,6 +20,8 @@ def hipcc_command(out: str):
             "-fPIC", "-shared",
             # no packed FP32 instructions in generated code
             "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+            # evaluate expressions exactly as written (no FMA contraction)
+            "-ffp-contract=off",
             "-Wall", "-Wno-unused-result",
             "-I", os.path.join(ROOT, "include"),
             "-o", out] + SOURCES

@@ -36,8 +36,9 @@ struct Layout {
     int32_t lo[3] = {0, 0, 0};
     int32_t hi[3] = {0, 0, 0};
     int32_t M[3] = {0, 0, 0};
-    int64_t ncell = 0;
-    int64_t aux_elems[3] = {0, 0, 0};   // elements of one compact aux array
+    int64_t ncell = 0;                  // cells of one problem
+    int64_t batch = 1;                  // independent problems sharing c^2 and sigma
+    int64_t aux_elems[3] = {0, 0, 0};   // elements of one compact aux array (one problem)
     // byte offsets into the workspace
     size_t off_u[2] = {0, 0};
     size_t off_c2 = 0;
@@ -73,16 +74,18 @@ std::string make_layout(const dpml_grid_t *g, bool c2_field, Layout &L)
         }
         L.ncell *= L.N[a];
     }
-    if (L.ncell > ((int64_t)1 << 40)) return "grid too large";
+    L.batch = g->batch > 1 ? g->batch : 1;
+    if (L.batch > 65535) return "batch too large";
+    if (L.ncell * L.batch > ((int64_t)1 << 40)) return "grid too large";
     size_t off = 0;
-    const size_t ubytes = align_up((size_t)L.ncell * L.esize);
+    const size_t ubytes = align_up((size_t)(L.ncell * L.batch) * L.esize);
     L.off_u[0] = off; off += ubytes;
     L.off_u[1] = off; off += ubytes;
-    if (c2_field) { L.off_c2 = off; off += ubytes; }
+    if (c2_field) { L.off_c2 = off; off += align_up((size_t)L.ncell * L.esize); }
     for (int a = 0; a < L.ndim; ++a) {
         if (L.M[a] == 0) continue;
         L.aux_elems[a] = L.ncell / L.N[a] * (L.M[a] + 1);
-        const size_t ab = align_up((size_t)L.aux_elems[a] * L.esize);
+        const size_t ab = align_up((size_t)(L.aux_elems[a] * L.batch) * L.esize);
         for (int k = 0; k < 2; ++k) {
             L.off_phi[a][k] = off; off += ab;
             L.off_psi[a][k] = off; off += ab;
@@ -116,7 +119,14 @@ struct dpml {
     // receivers
     int64_t nr = 0, nt_rec = 0;
     int64_t *d_rec_cells = nullptr;
+    int64_t *d_rec_sorted = nullptr, *d_rec_order = nullptr;
     void *traces = nullptr;
+    bool recording = true;   // off while the adjoint recomputes segments
+    // checkpointed forward / adjoint
+    char *adj_ws = nullptr;
+    size_t adj_bytes = 0;
+    int64_t adj_nsteps = 0, adj_every = 0;
+    bool adj_ready = false;
     // plane recorder
     int plane_axis = -1;
     int64_t plane_index = 0, nt_plane = 0;
@@ -172,29 +182,35 @@ dpmlk::StepArgs<T> make_args(dpml *H)
     p.u = (const T *)H->u_now;
     p.uo = (T *)H->u_old;
     p.c2 = H->c2_field ? (const T *)H->at(L.off_c2) : nullptr;
-    const double kl = H->dt * H->dt / (H->h * H->h);
-    p.k_lap = (T)(H->c2_field ? kl : kl * H->c2_const);
-    p.k_damp = (T)(H->dt * H->dt / H->h);
-    p.half_dt = (T)(0.5 * H->dt);
-    p.dt_2h = (T)(H->dt / (2.0 * H->h));
+    p.c2_const = (T)H->c2_const;
+    p.inv_h2 = (T)(1.0 / (H->h * H->h));
+    p.inv_h = (T)(1.0 / H->h);
+    p.inv_2h = (T)(1.0 / (2.0 * H->h));
+    p.dt = (T)H->dt;
+    p.dt2 = (T)(H->dt * H->dt);
     p.nx = (int32_t)L.N[0];
     p.ny = (int32_t)L.N[1];
     p.nz = (int32_t)L.N[2];
+    p.bstride = L.ncell;
+    for (int a = 0; a < 3; ++a) p.bstride_aux[a] = L.aux_elems[a];
+    p.hist = nullptr;
     return p;
 }
 
 int round8(int v) { return (v + 7) / 8 * 8; }
 
 template <typename T>
-int launch_step(dpml *H)
+int launch_step(dpml *H, T *hist = nullptr)
 {
     const Layout &L = H->L;
     dpmlk::StepArgs<T> p = make_args<T>(H);
+    p.hist = hist;
+    const unsigned B = (unsigned)L.batch;
     int variant = H->variant == DPML_VARIANT_AUTO ? DPML_VARIANT_MARCH : H->variant;
     if (variant == DPML_VARIANT_CELL) {
         dim3 block(64, 4, 1);
         dim3 grid((unsigned)((L.N[0] + 63) / 64), (unsigned)((L.N[1] + 3) / 4),
-                  (unsigned)(L.ndim == 3 ? L.N[2] : 1));
+                  (unsigned)(L.ndim == 3 ? L.N[2] : 1) * B);
         if (L.ndim == 2)
             hipLaunchKernelGGL((dpmlk::k_step_cell<T, 2>), grid, block, 0, H->stream, p);
         else
@@ -207,7 +223,7 @@ int launch_step(dpml *H)
         p.tiles_x = (int)((L.N[0] + 256 * vx - 1) / (256 * vx));
         const int tiles_y = (int)((L.N[1] + p.tile_rows - 1) / p.tile_rows);
         p.n_tiles = p.tiles_x * tiles_y;
-        dim3 grid((unsigned)round8(p.n_tiles)), block(256);
+        dim3 grid((unsigned)round8(p.n_tiles), B), block(256);
         if (vx == 2)
             hipLaunchKernelGGL((dpmlk::k_step_march2d<T, (sizeof(T) == 4 ? 2 : 1)>), grid, block, 0, H->stream, p);
         else
@@ -219,7 +235,7 @@ int launch_step(dpml *H)
         p.tiles_y = (int)((L.N[1] + 4 * RY - 1) / (4 * RY));
         const int tiles_z = (int)((L.N[2] + p.tile_rows - 1) / p.tile_rows);
         p.n_tiles = p.tiles_x * p.tiles_y * tiles_z;
-        dim3 grid((unsigned)round8(p.n_tiles)), block(64, 4);
+        dim3 grid((unsigned)round8(p.n_tiles), B), block(64, 4);
         hipLaunchKernelGGL((dpmlk::k_step_march3d<T, RY>), grid, block, 0, H->stream, p);
     }
     HIP_TRY(H, hipGetLastError());
@@ -240,12 +256,12 @@ int launch_epilogue(dpml *H)
         hipLaunchKernelGGL((dpmlk::k_inject<T>), grid, block, 0, H->stream, unew, H->d_src_cells,
                            H->d_src_order, (const T *)H->wavelets, H->ns, H->nt_src, H->n, amp);
     }
-    if (H->nr > 0 && H->n < H->nt_rec) {
+    if (H->recording && H->nr > 0 && H->n < H->nt_rec) {
         dim3 grid((unsigned)((H->nr + 255) / 256)), block(256);
         hipLaunchKernelGGL((dpmlk::k_record<T>), grid, block, 0, H->stream, (const T *)unew,
                            H->d_rec_cells, (T *)H->traces, H->nr, H->nt_rec, H->n);
     }
-    if (H->plane_axis >= 0 && H->n < H->nt_plane) {
+    if (H->recording && H->plane_axis >= 0 && H->n < H->nt_plane) {
         int a0 = -1, a1 = -1;
         for (int a = 0; a < L.ndim; ++a) {
             if (a == H->plane_axis) continue;
@@ -286,27 +302,29 @@ int set_state_impl(dpml *H, const void *U0, const void *V0)
     H->u_now = H->at(L.off_u[0]);
     H->u_old = H->at(L.off_u[1]);
     H->cur = 0;
-    HIP_TRY(H, hipMemcpyAsync(H->u_now, U0, (size_t)L.ncell * sizeof(T), hipMemcpyDeviceToDevice, H->stream));
+    HIP_TRY(H, hipMemcpyAsync(H->u_now, U0, (size_t)(L.ncell * L.batch) * sizeof(T), hipMemcpyDeviceToDevice, H->stream));
     for (int a = 0; a < L.ndim; ++a) {
         if (L.M[a] == 0) continue;
         for (int k = 0; k < 2; ++k) {
-            HIP_TRY(H, hipMemsetAsync(H->at(L.off_phi[a][k]), 0, (size_t)L.aux_elems[a] * sizeof(T), H->stream));
-            HIP_TRY(H, hipMemsetAsync(H->at(L.off_psi[a][k]), 0, (size_t)L.aux_elems[a] * sizeof(T), H->stream));
+            HIP_TRY(H, hipMemsetAsync(H->at(L.off_phi[a][k]), 0, (size_t)(L.aux_elems[a] * L.batch) * sizeof(T), H->stream));
+            HIP_TRY(H, hipMemsetAsync(H->at(L.off_psi[a][k]), 0, (size_t)(L.aux_elems[a] * L.batch) * sizeof(T), H->stream));
         }
     }
-    const double kl = H->dt * H->dt / (H->h * H->h);
-    const T half_k = (T)(0.5 * (H->c2_field ? kl : kl * H->c2_const));
     const T *c2 = H->c2_field ? (const T *)H->at(L.off_c2) : nullptr;
+    const T inv_h2 = (T)(1.0 / (H->h * H->h));
+    const T half_dt2 = (T)(0.5 * H->dt * H->dt);
     dim3 block(64, 4, 1);
-    dim3 grid((unsigned)((L.N[0] + 63) / 64), (unsigned)((L.N[1] + 3) / 4), (unsigned)(L.ndim == 3 ? L.N[2] : 1));
-    // read U0 from the caller's buffer (the copy may still be in flight on the
-    // same stream, which orders it before this kernel)
+    dim3 grid((unsigned)((L.N[0] + 63) / 64), (unsigned)((L.N[1] + 3) / 4),
+              (unsigned)((L.ndim == 3 ? L.N[2] : 1) * L.batch));
+    // read U0 from the caller's buffer (stream order puts the copy above first)
     if (L.ndim == 2)
         hipLaunchKernelGGL((dpmlk::k_start<T, 2>), grid, block, 0, H->stream, (const T *)U0, (const T *)V0,
-                           (T *)H->u_old, c2, half_k, (T)H->dt, (int)L.N[0], (int)L.N[1], (int)L.N[2]);
+                           (T *)H->u_old, c2, (T)H->c2_const, inv_h2, (T)H->dt, half_dt2,
+                           (int)L.N[0], (int)L.N[1], (int)L.N[2]);
     else
         hipLaunchKernelGGL((dpmlk::k_start<T, 3>), grid, block, 0, H->stream, (const T *)U0, (const T *)V0,
-                           (T *)H->u_old, c2, half_k, (T)H->dt, (int)L.N[0], (int)L.N[1], (int)L.N[2]);
+                           (T *)H->u_old, c2, (T)H->c2_const, inv_h2, (T)H->dt, half_dt2,
+                           (int)L.N[0], (int)L.N[1], (int)L.N[2]);
     HIP_TRY(H, hipGetLastError());
     H->n = 0;
     H->state_set = true;
@@ -356,7 +374,7 @@ int nonfinite_check(dpml *H, bool *bad)
 {
     int32_t *flags = (int32_t *)H->at(H->L.off_flags);
     hipLaunchKernelGGL((dpmlk::k_nonfinite<T>), dim3(kFlagBlocks), dim3(256), 0, H->stream,
-                       (const T *)H->u_now, H->L.ncell, flags);
+                       (const T *)H->u_now, H->L.ncell * H->L.batch, flags);
     HIP_TRY(H, hipGetLastError());
     std::vector<int32_t> host(kFlagBlocks);
     HIP_TRY(H, hipMemcpyAsync(host.data(), flags, kFlagBlocks * sizeof(int32_t), hipMemcpyDeviceToHost, H->stream));
@@ -469,7 +487,7 @@ int dpml_inject(dpml_t *H, int64_t ns, const int64_t *cells, const void *wavelet
     if (!H) return DPML_EINVAL;
     if (ns < 0 || (ns > 0 && (!cells || !wavelets || nt < 1))) return H->fail(DPML_EINVAL, "bad source arguments");
     for (int64_t s = 0; s < ns; ++s)
-        if (cells[s] < 0 || cells[s] >= H->L.ncell) return H->fail(DPML_EINVAL, "source cell out of range");
+        if (cells[s] < 0 || cells[s] >= H->L.ncell * H->L.batch) return H->fail(DPML_EINVAL, "source cell out of range");
     HIP_TRY(H, hipStreamSynchronize(H->stream));
     if (H->d_src_cells) { HIP_TRY(H, hipFree(H->d_src_cells)); H->d_src_cells = nullptr; }
     if (H->d_src_order) { HIP_TRY(H, hipFree(H->d_src_order)); H->d_src_order = nullptr; }
@@ -495,13 +513,23 @@ int dpml_record(dpml_t *H, int64_t nr, const int64_t *cells, void *traces, int64
     if (!H) return DPML_EINVAL;
     if (nr < 0 || (nr > 0 && (!cells || !traces || nt < 1))) return H->fail(DPML_EINVAL, "bad receiver arguments");
     for (int64_t r = 0; r < nr; ++r)
-        if (cells[r] < 0 || cells[r] >= H->L.ncell) return H->fail(DPML_EINVAL, "receiver cell out of range");
+        if (cells[r] < 0 || cells[r] >= H->L.ncell * H->L.batch) return H->fail(DPML_EINVAL, "receiver cell out of range");
     HIP_TRY(H, hipStreamSynchronize(H->stream));
-    if (H->d_rec_cells) { HIP_TRY(H, hipFree(H->d_rec_cells)); H->d_rec_cells = nullptr; }
+    for (int64_t **pp : {&H->d_rec_cells, &H->d_rec_sorted, &H->d_rec_order})
+        if (*pp) { HIP_TRY(H, hipFree(*pp)); *pp = nullptr; }
     H->nr = 0;
     if (nr == 0) return DPML_OK;
+    std::vector<int64_t> order((size_t)nr);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), [&](int64_t a, int64_t b) { return cells[a] < cells[b]; });
+    std::vector<int64_t> sorted((size_t)nr);
+    for (int64_t q = 0; q < nr; ++q) sorted[q] = cells[order[q]];
     HIP_TRY(H, hipMalloc((void **)&H->d_rec_cells, (size_t)nr * sizeof(int64_t)));
+    HIP_TRY(H, hipMalloc((void **)&H->d_rec_sorted, (size_t)nr * sizeof(int64_t)));
+    HIP_TRY(H, hipMalloc((void **)&H->d_rec_order, (size_t)nr * sizeof(int64_t)));
     HIP_TRY(H, hipMemcpy(H->d_rec_cells, cells, (size_t)nr * sizeof(int64_t), hipMemcpyHostToDevice));
+    HIP_TRY(H, hipMemcpy(H->d_rec_sorted, sorted.data(), (size_t)nr * sizeof(int64_t), hipMemcpyHostToDevice));
+    HIP_TRY(H, hipMemcpy(H->d_rec_order, order.data(), (size_t)nr * sizeof(int64_t), hipMemcpyHostToDevice));
     H->nr = nr;
     H->nt_rec = nt;
     H->traces = traces;
@@ -512,7 +540,7 @@ int dpml_record_plane(dpml_t *H, int32_t axis, int64_t index, void *planes, int6
 {
     if (!H) return DPML_EINVAL;
     if (axis < 0) { H->plane_axis = -1; return DPML_OK; }
-    if (axis >= H->L.ndim || index < 0 || index >= H->L.N[axis] || !planes || nt < 1)
+    if (axis >= H->L.ndim || index < 0 || index >= H->L.N[axis] || !planes || nt < 1 || H->L.batch != 1)
         return H->fail(DPML_EINVAL, "bad plane recorder arguments");
     H->plane_axis = axis;
     H->plane_index = index;
@@ -579,8 +607,8 @@ size_t dpml_state_bytes(const dpml_t *H)
 {
     if (!H) return 0;
     const Layout &L = H->L;
-    size_t b = 2 * (size_t)L.ncell * L.esize;
-    for (int a = 0; a < L.ndim; ++a) b += 2 * (size_t)L.aux_elems[a] * L.esize;
+    size_t b = 2 * (size_t)(L.ncell * L.batch) * L.esize;
+    for (int a = 0; a < L.ndim; ++a) b += 2 * (size_t)(L.aux_elems[a] * L.batch) * L.esize;
     return b;
 }
 
@@ -597,12 +625,12 @@ int copy_state(dpml_t *H, char *blob, bool to_blob)
         off += bytes;
         return DPML_OK;
     };
-    const size_t ub = (size_t)L.ncell * L.esize;
+    const size_t ub = (size_t)(L.ncell * L.batch) * L.esize;
     int rc = cp(H->u_now, ub);
     if (!rc) rc = cp(H->u_old, ub);
     for (int a = 0; a < L.ndim && !rc; ++a) {
         if (L.M[a] == 0) continue;
-        const size_t ab = (size_t)L.aux_elems[a] * L.esize;
+        const size_t ab = (size_t)(L.aux_elems[a] * L.batch) * L.esize;
         rc = cp(H->at(L.off_phi[a][H->cur]), ab);
         if (!rc) rc = cp(H->at(L.off_psi[a][H->cur]), ab);
     }
@@ -629,8 +657,8 @@ int dpml_put_state(dpml_t *H, const void *blob, int64_t n)
         for (int a = 0; a < L.ndim; ++a) {
             if (L.M[a] == 0) continue;
             for (int k = 0; k < 2; ++k) {
-                HIP_TRY(H, hipMemsetAsync(H->at(L.off_phi[a][k]), 0, (size_t)L.aux_elems[a] * L.esize, H->stream));
-                HIP_TRY(H, hipMemsetAsync(H->at(L.off_psi[a][k]), 0, (size_t)L.aux_elems[a] * L.esize, H->stream));
+                HIP_TRY(H, hipMemsetAsync(H->at(L.off_phi[a][k]), 0, (size_t)(L.aux_elems[a] * L.batch) * L.esize, H->stream));
+                HIP_TRY(H, hipMemsetAsync(H->at(L.off_psi[a][k]), 0, (size_t)(L.aux_elems[a] * L.batch) * L.esize, H->stream));
             }
         }
     }
@@ -656,6 +684,8 @@ void dpml_destroy(dpml_t *H)
     if (H->d_src_cells) (void)hipFree(H->d_src_cells);
     if (H->d_src_order) (void)hipFree(H->d_src_order);
     if (H->d_rec_cells) (void)hipFree(H->d_rec_cells);
+    if (H->d_rec_sorted) (void)hipFree(H->d_rec_sorted);
+    if (H->d_rec_order) (void)hipFree(H->d_rec_order);
     delete H;
 }
 
@@ -676,5 +706,533 @@ const char *dpml_last_error(const dpml_t *H)
 {
     return H ? H->err.c_str() : g_create_error.c_str();
 }
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Checkpointed forward and discrete adjoint
+// ---------------------------------------------------------------------------
+namespace {
+
+struct AdjLayout {
+    int64_t nck = 0;
+    size_t state = 0, off_ckpt = 0, level = 0, off_hist = 0;
+    size_t off_lam[2] = {0, 0};
+    size_t off_p[3][2] = {{0, 0}, {0, 0}, {0, 0}};
+    size_t off_q[3][2] = {{0, 0}, {0, 0}, {0, 0}};
+    size_t total = 0;
+};
+
+AdjLayout adj_layout(const dpml *H, int64_t nsteps, int64_t every)
+{
+    const Layout &L = H->L;
+    AdjLayout A;
+    A.nck = (nsteps + every - 1) / every;
+    A.state = align_up(dpml_state_bytes(H));
+    A.level = align_up((size_t)(L.ncell * L.batch) * L.esize);
+    size_t off = 0;
+    A.off_ckpt = off; off += (size_t)A.nck * A.state;
+    A.off_hist = off; off += (size_t)every * A.level;
+    for (int k = 0; k < 2; ++k) { A.off_lam[k] = off; off += A.level; }
+    for (int a = 0; a < L.ndim; ++a) {
+        if (L.M[a] == 0) continue;
+        const size_t ab = align_up((size_t)(L.aux_elems[a] * L.batch) * L.esize);
+        for (int k = 0; k < 2; ++k) {
+            A.off_p[a][k] = off; off += ab;
+            A.off_q[a][k] = off; off += ab;
+        }
+    }
+    A.total = off;
+    return A;
+}
+
+template <typename T>
+int forward_ckpt_impl(dpml *H, int64_t nsteps)
+{
+    const AdjLayout A = adj_layout(H, nsteps, H->adj_every);
+    for (int64_t k = 0; k < nsteps; ++k) {
+        if (k % H->adj_every == 0) {
+            int rc = copy_state(H, H->adj_ws + A.off_ckpt + (size_t)(k / H->adj_every) * A.state, true);
+            if (rc) return rc;
+        }
+        int rc = step_impl<T>(H, 1);
+        if (rc) return rc;
+    }
+    return DPML_OK;
+}
+
+template <typename T>
+int adjoint_impl(dpml *H, const void *resid, double *grad, void *grad_w)
+{
+    const Layout &L = H->L;
+    const int64_t nsteps = H->adj_nsteps, every = H->adj_every;
+    const AdjLayout A = adj_layout(H, nsteps, every);
+    char *ws = H->adj_ws;
+    const size_t lb = (size_t)(L.ncell * L.batch) * sizeof(T);
+    for (int k = 0; k < 2; ++k) HIP_TRY(H, hipMemsetAsync(ws + A.off_lam[k], 0, lb, H->stream));
+    for (int a = 0; a < L.ndim; ++a) {
+        if (L.M[a] == 0) continue;
+        const size_t ab = (size_t)(L.aux_elems[a] * L.batch) * sizeof(T);
+        for (int k = 0; k < 2; ++k) {
+            HIP_TRY(H, hipMemsetAsync(ws + A.off_p[a][k], 0, ab, H->stream));
+            HIP_TRY(H, hipMemsetAsync(ws + A.off_q[a][k], 0, ab, H->stream));
+        }
+    }
+    int lcur = 0;     // lam[lcur] = a^{n+1}, lam[1-lcur] = a^{n+2}
+    int acur = 0;     // p/q[acur] = adjoint auxiliaries at level n+1
+    double hd = 1;
+    for (int a = 0; a < L.ndim; ++a) hd *= H->h;
+    const T wamp = (T)(H->dt * H->dt / hd);
+    H->recording = false;
+    dim3 block(64, 4, 1);
+    dim3 grid((unsigned)((L.N[0] + 63) / 64), (unsigned)((L.N[1] + 3) / 4), (unsigned)(L.ndim == 3 ? L.N[2] : 1));
+    for (int64_t seg = A.nck - 1; seg >= 0; --seg) {
+        const int64_t t0 = seg * every, t1 = std::min(t0 + every, nsteps);
+        // restore the checkpoint and recompute U^{t0} .. U^{t1-1} into the history
+        H->state_set = true;
+        H->cur = 0;
+        H->u_now = H->at(L.off_u[0]);
+        H->u_old = H->at(L.off_u[1]);
+        int rc = copy_state(H, ws + A.off_ckpt + (size_t)seg * A.state, false);
+        if (rc) return rc;
+        H->n = t0;
+        HIP_TRY(H, hipMemcpyAsync(ws + A.off_hist, H->u_now, lb, hipMemcpyDeviceToDevice, H->stream));
+        for (int64_t k = t0; k + 1 < t1; ++k) {
+            T *hist = (T *)(ws + A.off_hist + (size_t)(k - t0 + 1) * A.level);
+            rc = launch_step<T>(H, hist);
+            if (rc) return rc;
+            rc = launch_epilogue<T>(H);       // sources only (recording is off)
+            if (rc) return rc;
+            if (H->ns > 0 && H->n < H->nt_src) {   // the history must include the sources too
+                dim3 g2((unsigned)((H->ns + 255) / 256)), b2(256);
+                hipLaunchKernelGGL((dpmlk::k_inject<T>), g2, b2, 0, H->stream, hist, H->d_src_cells,
+                                   H->d_src_order, (const T *)H->wavelets, H->ns, H->nt_src, H->n, wamp);
+            }
+            std::swap(H->u_now, H->u_old);
+            H->cur = 1 - H->cur;
+            H->n += 1;
+        }
+        // reverse sweep over the segment
+        for (int64_t n = t1 - 1; n >= t0; --n) {
+            T *lam = (T *)(ws + A.off_lam[lcur]);
+            T *lam_o = (T *)(ws + A.off_lam[1 - lcur]);
+            if (H->nr > 0 && n < H->nt_rec) {
+                dim3 g2((unsigned)((H->nr + 255) / 256)), b2(256);
+                hipLaunchKernelGGL((dpmlk::k_inject<T>), g2, b2, 0, H->stream, lam, H->d_rec_sorted,
+                                   H->d_rec_order, (const T *)resid, H->nr, H->nt_rec, n, (T)1);
+            }
+            if (H->ns > 0 && n < H->nt_src && grad_w) {
+                dim3 g2((unsigned)((H->ns + 255) / 256)), b2(256);
+                hipLaunchKernelGGL((dpmlk::k_gather_scaled<T>), g2, b2, 0, H->stream, (const T *)lam,
+                                   H->d_src_cells, H->d_src_order, (T *)grad_w, H->ns, H->nt_src, n, wamp);
+            }
+            dpmlk::AdjArgs<T> q{};
+            for (int a = 0; a < 3; ++a) {
+                q.ax[a] = make_axis<T>(H, a, false);
+                if (a < L.ndim && L.M[a] > 0) {
+                    q.ax[a].phi = (const T *)(ws + A.off_p[a][acur]);
+                    q.ax[a].psi = (const T *)(ws + A.off_q[a][acur]);
+                    q.ax[a].phi_o = (T *)(ws + A.off_p[a][1 - acur]);
+                    q.ax[a].psi_o = (T *)(ws + A.off_q[a][1 - acur]);
+                }
+                q.bstride_aux[a] = L.aux_elems[a];
+            }
+            q.lam = lam;
+            q.lam_o = lam_o;
+            q.un = (const T *)(ws + A.off_hist + (size_t)(n - t0) * A.level);
+            q.c2 = H->c2_field ? (const T *)H->at(L.off_c2) : nullptr;
+            q.grad = grad;
+            q.c2_const = (T)H->c2_const;
+            q.inv_h2 = (T)(1.0 / (H->h * H->h));
+            q.inv_2h = (T)(1.0 / (2.0 * H->h));
+            q.dt = (T)H->dt;
+            q.dt2 = (T)(H->dt * H->dt);
+            q.half_dt = (T)(0.5 * H->dt);
+            q.k_damp = (T)(H->dt * H->dt / H->h);
+            q.nx = (int32_t)L.N[0];
+            q.ny = (int32_t)L.N[1];
+            q.nz = (int32_t)L.N[2];
+            q.batch = (int32_t)L.batch;
+            q.bstride = L.ncell;
+            if (L.ndim == 2)
+                hipLaunchKernelGGL((dpmlk::k_adjoint_cell<T, 2>), grid, block, 0, H->stream, q);
+            else
+                hipLaunchKernelGGL((dpmlk::k_adjoint_cell<T, 3>), grid, block, 0, H->stream, q);
+            HIP_TRY(H, hipGetLastError());
+            lcur = 1 - lcur;
+            acur = 1 - acur;
+        }
+    }
+    // start: lam[1 - lcur] holds a^1, the history slot 0 holds U^0
+    const T half_dt2 = (T)(0.5 * H->dt * H->dt);
+    const T inv_h2 = (T)(1.0 / (H->h * H->h));
+    if (L.ndim == 2)
+        hipLaunchKernelGGL((dpmlk::k_adjoint_start<T, 2>), grid, block, 0, H->stream,
+                           (const T *)(ws + A.off_lam[1 - lcur]), (const T *)(ws + A.off_hist), grad, half_dt2,
+                           inv_h2, (int)L.N[0], (int)L.N[1], (int)L.N[2], (int)L.batch, (int64_t)L.ncell);
+    else
+        hipLaunchKernelGGL((dpmlk::k_adjoint_start<T, 3>), grid, block, 0, H->stream,
+                           (const T *)(ws + A.off_lam[1 - lcur]), (const T *)(ws + A.off_hist), grad, half_dt2,
+                           inv_h2, (int)L.N[0], (int)L.N[1], (int)L.N[2], (int)L.batch, (int64_t)L.ncell);
+    HIP_TRY(H, hipGetLastError());
+    H->recording = true;
+    H->state_set = false;     // the fields now hold a recomputed intermediate level
+    return DPML_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t dpml_adjoint_workspace_bytes(const dpml_t *H, int64_t nsteps, int64_t ckpt_every)
+{
+    if (!H || nsteps < 1 || ckpt_every < 1) return 0;
+    return adj_layout(H, nsteps, ckpt_every).total;
+}
+
+int dpml_forward_checkpointed(dpml_t *H, int64_t nsteps, int64_t ckpt_every, void *adj_ws, size_t bytes)
+{
+    if (!H) return DPML_EINVAL;
+    if (nsteps < 1 || ckpt_every < 1 || !adj_ws) return H->fail(DPML_EINVAL, "bad checkpoint arguments");
+    if (!H->state_set || H->n != 0) return H->fail(DPML_ESTATE, "the forward run must start at time index 0");
+    if (bytes < adj_layout(H, nsteps, ckpt_every).total) return H->fail(DPML_ENOMEM, "adjoint workspace too small");
+    if (((uintptr_t)adj_ws) % kAlign != 0) return H->fail(DPML_ENOMEM, "adjoint workspace must be 256-byte aligned");
+    H->adj_ws = (char *)adj_ws;
+    H->adj_bytes = bytes;
+    H->adj_nsteps = nsteps;
+    H->adj_every = ckpt_every;
+    H->adj_ready = false;
+    int rc = H->L.dtype == DPML_F32 ? forward_ckpt_impl<float>(H, nsteps) : forward_ckpt_impl<double>(H, nsteps);
+    if (rc) return rc;
+    H->adj_ready = true;
+    return DPML_OK;
+}
+
+int dpml_adjoint(dpml_t *H, const void *resid, double *grad_c2, void *grad_w)
+{
+    if (!H) return DPML_EINVAL;
+    if (!H->adj_ready) return H->fail(DPML_ESTATE, "no checkpointed forward run to differentiate");
+    if (!grad_c2 || (H->nr > 0 && !resid)) return H->fail(DPML_EINVAL, "bad adjoint arguments");
+    return H->L.dtype == DPML_F32 ? adjoint_impl<float>(H, resid, grad_c2, grad_w)
+                                  : adjoint_impl<double>(H, resid, grad_c2, grad_w);
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Many independent 2D problems of different sizes stepped by one launch per
+// step (a flat tile work list over all problems), optionally captured with
+// the whole step sequence into one HIP graph.
+// ---------------------------------------------------------------------------
+struct dpml_multi {
+    int64_t count = 0;
+    int dtype = 0;
+    size_t esize = 4;
+    std::vector<Layout> L;
+    std::vector<double> h, dt;
+    std::vector<size_t> base;        // workspace offset of each problem's block
+    char *ws = nullptr;
+    hipStream_t stream = nullptr;
+    hipStream_t cap = nullptr;       // private stream used only for graph capture
+    size_t off_desc[2] = {0, 0};     // device StepArgs tables for buffer parity 0 / 1
+    size_t off_tiles = 0;
+    int64_t ntiles = 0;
+    int vx = 1;
+    int tile_rows = 32;
+    int parity = 0;                  // 0: buffers u0/aux0 hold level n
+    int64_t n = 0;
+    bool state_set = false;
+    hipGraphExec_t exec = nullptr;
+    hipGraph_t graph = nullptr;
+    int64_t graph_steps = -1;
+    int graph_parity = -1;
+    std::string err;
+    int fail(int code, const std::string &m) { err = m; return code; }
+};
+
+namespace {
+
+thread_local std::string g_multi_error;
+
+struct MultiLayout {
+    std::vector<Layout> L;
+    std::vector<size_t> base;
+    size_t off_desc[2] = {0, 0}, off_tiles = 0, total = 0;
+    int64_t ntiles = 0;
+    int vx = 1;
+};
+
+constexpr int kMultiTileRows = 32;
+
+std::string multi_layout(int64_t count, const dpml_grid_t *grids, MultiLayout &M)
+{
+    if (count < 1 || count > (1 << 20) || !grids) return "bad problem count";
+    const int dtype = grids[0].dtype;
+    size_t off = 0;
+    bool even = true;
+    M.L.resize((size_t)count);
+    M.base.resize((size_t)count);
+    for (int64_t p = 0; p < count; ++p) {
+        if (grids[p].ndim != 2) return "multi-problem stepping is 2D only";
+        if (grids[p].dtype != dtype) return "all problems must share one dtype";
+        if (grids[p].batch > 1) return "multi-problem grids take no batch";
+        std::string e = make_layout(&grids[p], false, M.L[p]);
+        if (!e.empty()) return "problem " + std::to_string(p) + ": " + e;
+        M.base[p] = off;
+        off += align_up(M.L[p].total);
+        even &= M.L[p].N[0] % 2 == 0;
+    }
+    M.vx = (dtype == DPML_F32 && even) ? 2 : 1;
+    int64_t nt = 0;
+    for (int64_t p = 0; p < count; ++p) {
+        const int64_t tx = (M.L[p].N[0] + 256 * M.vx - 1) / (256 * M.vx);
+        const int64_t ty = (M.L[p].N[1] + kMultiTileRows - 1) / kMultiTileRows;
+        nt += tx * ty;
+    }
+    M.ntiles = nt;
+    const size_t argsz = dtype == DPML_F32 ? sizeof(dpmlk::StepArgs<float>) : sizeof(dpmlk::StepArgs<double>);
+    for (int k = 0; k < 2; ++k) { M.off_desc[k] = off; off += align_up((size_t)count * argsz); }
+    M.off_tiles = off; off += align_up((size_t)nt * sizeof(dpmlk::TileRef));
+    M.total = off;
+    return "";
+}
+
+// A throw-away single-problem view of problem p at buffer parity q, so the
+// single-problem argument builders can be reused.
+dpml problem_view(const dpml_multi *H, int64_t p, int q)
+{
+    dpml v;
+    v.L = H->L[p];
+    v.ws = H->ws + H->base[p];
+    v.h = H->h[p];
+    v.dt = H->dt[p];
+    v.c2_const = 1.0;
+    v.c2_field = false;
+    v.cur = q;
+    v.u_now = v.at(v.L.off_u[q]);
+    v.u_old = v.at(v.L.off_u[1 - q]);
+    return v;
+}
+
+template <typename T>
+int multi_tables(dpml_multi *H, const double *const *sigmas)
+{
+    // damping tables of every problem
+    for (int64_t p = 0; p < H->count; ++p) {
+        dpml v = problem_view(H, p, 0);
+        const double *sg[3] = {sigmas[3 * p], sigmas[3 * p + 1], nullptr};
+        double one = 1.0;
+        int rc = upload_tables<T>(&v, &one, 1, sg);
+        if (rc) return H->fail(rc, v.err);
+    }
+    // argument tables for both parities and the tile list
+    for (int q = 0; q < 2; ++q) {
+        std::vector<dpmlk::StepArgs<T>> args((size_t)H->count);
+        for (int64_t p = 0; p < H->count; ++p) {
+            dpml v = problem_view(H, p, q);
+            args[p] = make_args<T>(&v);
+            args[p].tile_rows = H->tile_rows;
+            args[p].tiles_x = (int)((v.L.N[0] + 256 * H->vx - 1) / (256 * H->vx));
+        }
+        HIP_TRY(nullptr, hipMemcpy(H->ws + H->off_desc[q], args.data(), args.size() * sizeof(args[0]),
+                                   hipMemcpyHostToDevice));
+    }
+    std::vector<dpmlk::TileRef> tiles;
+    tiles.reserve((size_t)H->ntiles);
+    for (int64_t p = 0; p < H->count; ++p) {
+        const int tx = (int)((H->L[p].N[0] + 256 * H->vx - 1) / (256 * H->vx));
+        const int ty = (int)((H->L[p].N[1] + H->tile_rows - 1) / H->tile_rows);
+        for (int y = 0; y < ty; ++y)
+            for (int x = 0; x < tx; ++x) tiles.push_back({(int32_t)p, x, y, 0});
+    }
+    HIP_TRY(nullptr, hipMemcpy(H->ws + H->off_tiles, tiles.data(), tiles.size() * sizeof(tiles[0]),
+                               hipMemcpyHostToDevice));
+    return DPML_OK;
+}
+
+template <typename T>
+int multi_launch(dpml_multi *H, hipStream_t s, int parity)
+{
+    const dim3 grid((unsigned)round8((int)H->ntiles)), block(256);
+    const auto *probs = (const dpmlk::StepArgs<T> *)(H->ws + H->off_desc[parity]);
+    const auto *tiles = (const dpmlk::TileRef *)(H->ws + H->off_tiles);
+    if (H->vx == 2)
+        hipLaunchKernelGGL((dpmlk::k_step_multi2d<T, (sizeof(T) == 4 ? 2 : 1)>), grid, block, 0, s, probs, tiles,
+                           (int)H->ntiles);
+    else
+        hipLaunchKernelGGL((dpmlk::k_step_multi2d<T, 1>), grid, block, 0, s, probs, tiles, (int)H->ntiles);
+    HIP_TRY(nullptr, hipGetLastError());
+    return DPML_OK;
+}
+
+template <typename T>
+int multi_step_impl(dpml_multi *H, int64_t nsteps, bool use_graph)
+{
+    if (!use_graph) {
+        for (int64_t k = 0; k < nsteps; ++k) {
+            int rc = multi_launch<T>(H, H->stream, H->parity);
+            if (rc) return H->fail(rc, g_create_error);
+            H->parity ^= 1;
+        }
+        H->n += nsteps;
+        return DPML_OK;
+    }
+    if (!(H->exec && H->graph_steps == nsteps && H->graph_parity == H->parity)) {
+        if (H->exec) { (void)hipGraphExecDestroy(H->exec); H->exec = nullptr; }
+        if (H->graph) { (void)hipGraphDestroy(H->graph); H->graph = nullptr; }
+        if (!H->cap) {
+            hipError_t e = hipStreamCreateWithFlags(&H->cap, hipStreamNonBlocking);
+            if (e != hipSuccess) return H->fail(DPML_EHIP, hipGetErrorString(e));
+        }
+        hipError_t e = hipStreamBeginCapture(H->cap, hipStreamCaptureModeRelaxed);
+        if (e != hipSuccess) return H->fail(DPML_EHIP, hipGetErrorString(e));
+        int q = H->parity, rc = DPML_OK;
+        for (int64_t k = 0; k < nsteps && rc == DPML_OK; ++k, q ^= 1) rc = multi_launch<T>(H, H->cap, q);
+        e = hipStreamEndCapture(H->cap, &H->graph);
+        if (rc) return H->fail(rc, g_create_error);
+        if (e != hipSuccess) return H->fail(DPML_EHIP, hipGetErrorString(e));
+        e = hipGraphInstantiate(&H->exec, H->graph, nullptr, nullptr, 0);
+        if (e != hipSuccess) return H->fail(DPML_EHIP, hipGetErrorString(e));
+        H->graph_steps = nsteps;
+        H->graph_parity = H->parity;
+    }
+    hipError_t e = hipGraphLaunch(H->exec, H->stream);
+    if (e != hipSuccess) return H->fail(DPML_EHIP, hipGetErrorString(e));
+    H->parity ^= (int)(nsteps & 1);
+    H->n += nsteps;
+    return DPML_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t dpml_multi_workspace_bytes(int64_t count, const dpml_grid_t *grids)
+{
+    MultiLayout M;
+    if (!multi_layout(count, grids, M).empty()) return 0;
+    return M.total;
+}
+
+int dpml_multi_create(int64_t count, const dpml_grid_t *grids, const double *h, const double *dt,
+                      const double *const *sigmas, void *workspace, size_t ws_bytes, void *stream,
+                      dpml_multi_t **out)
+{
+    if (!out) { g_multi_error = "out is NULL"; return DPML_EINVAL; }
+    *out = nullptr;
+    MultiLayout M;
+    std::string e = multi_layout(count, grids, M);
+    if (!e.empty()) { g_multi_error = e; return DPML_EINVAL; }
+    if (!h || !dt || !sigmas) { g_multi_error = "h, dt and sigmas are required"; return DPML_EINVAL; }
+    for (int64_t p = 0; p < count; ++p) {
+        const Layout &L = M.L[p];
+        if (!(h[p] > 0) || !(dt[p] > 0) || !std::isfinite(h[p]) || !std::isfinite(dt[p])) {
+            g_multi_error = "problem " + std::to_string(p) + ": h and dt must be positive"; return DPML_EINVAL;
+        }
+        if (dt[p] / h[p] * std::sqrt(2.0) > 1.0) {
+            g_multi_error = "problem " + std::to_string(p) + ": time step violates dt/h sqrt(2) <= 1"; return DPML_EINVAL;
+        }
+        for (int a = 0; a < 2; ++a) {
+            const double *sg = sigmas[3 * p + a];
+            if (!sg) continue;
+            for (int64_t i = 0; i < L.N[a]; ++i) {
+                if (!(sg[i] >= 0) || !std::isfinite(sg[i]) || dt[p] * sg[i] > 4.0 ||
+                    (sg[i] != 0 && i >= L.lo[a] && i < L.lo[a] + L.n[a])) {
+                    g_multi_error = "problem " + std::to_string(p) + ": invalid sigma"; return DPML_EINVAL;
+                }
+            }
+        }
+    }
+    if (!workspace || ws_bytes < M.total) { g_multi_error = "workspace too small"; return DPML_ENOMEM; }
+    if (((uintptr_t)workspace) % kAlign != 0) { g_multi_error = "workspace must be 256-byte aligned"; return DPML_ENOMEM; }
+    dpml_multi *H = new (std::nothrow) dpml_multi();
+    if (!H) { g_multi_error = "out of host memory"; return DPML_ENOMEM; }
+    H->count = count;
+    H->dtype = grids[0].dtype;
+    H->esize = H->dtype == DPML_F32 ? 4 : 8;
+    H->L = M.L;
+    H->base = M.base;
+    H->h.assign(h, h + count);
+    H->dt.assign(dt, dt + count);
+    H->ws = (char *)workspace;
+    H->stream = (hipStream_t)stream;
+    H->off_desc[0] = M.off_desc[0];
+    H->off_desc[1] = M.off_desc[1];
+    H->off_tiles = M.off_tiles;
+    H->ntiles = M.ntiles;
+    H->vx = M.vx;
+    H->tile_rows = kMultiTileRows;
+    int rc = H->dtype == DPML_F32 ? multi_tables<float>(H, sigmas) : multi_tables<double>(H, sigmas);
+    if (rc) { g_multi_error = H->err.empty() ? g_create_error : H->err; delete H; return rc; }
+    *out = H;
+    return DPML_OK;
+}
+
+int dpml_multi_set_state(dpml_multi_t *H, const void *const *U0)
+{
+    if (!H) return DPML_EINVAL;
+    if (!U0) return H->fail(DPML_EINVAL, "U0 is NULL");
+    for (int64_t p = 0; p < H->count; ++p) {
+        if (!U0[p]) return H->fail(DPML_EINVAL, "U0[" + std::to_string(p) + "] is NULL");
+        dpml v = problem_view(H, p, 0);
+        v.stream = H->stream;
+        int rc = H->dtype == DPML_F32 ? set_state_impl<float>(&v, U0[p], nullptr)
+                                      : set_state_impl<double>(&v, U0[p], nullptr);
+        if (rc) return H->fail(rc, v.err);
+    }
+    H->parity = 0;
+    H->n = 0;
+    H->state_set = true;
+    return DPML_OK;
+}
+
+int dpml_multi_step(dpml_multi_t *H, int64_t nsteps, int32_t use_graph)
+{
+    if (!H) return DPML_EINVAL;
+    if (nsteps < 0) return H->fail(DPML_EINVAL, "nsteps < 0");
+    if (!H->state_set) return H->fail(DPML_ESTATE, "dpml_multi_set_state has not been called");
+    if (nsteps == 0) return DPML_OK;
+    return H->dtype == DPML_F32 ? multi_step_impl<float>(H, nsteps, use_graph != 0)
+                                : multi_step_impl<double>(H, nsteps, use_graph != 0);
+}
+
+int dpml_multi_field(dpml_multi_t *H, int64_t prob, int32_t which, void **ptr, int64_t shape[3])
+{
+    if (!H || !ptr || !shape || prob < 0 || prob >= H->count) return DPML_EINVAL;
+    if (!H->state_set) return H->fail(DPML_ESTATE, "dpml_multi_set_state has not been called");
+    const Layout &L = H->L[prob];
+    char *b = H->ws + H->base[prob];
+    for (int a = 0; a < 3; ++a) shape[a] = L.N[a];
+    const int q = H->parity;
+    if (which == DPML_FIELD_U) { *ptr = b + L.off_u[q]; return DPML_OK; }
+    if (which == DPML_FIELD_UPREV) { *ptr = b + L.off_u[1 - q]; return DPML_OK; }
+    const int a = (which - 2) / 2;
+    if (which < 2 || a >= L.ndim || L.M[a] == 0) return H->fail(DPML_EINVAL, "no such field");
+    shape[a] = L.M[a] + 1;
+    *ptr = b + ((which % 2 == 0) ? L.off_phi[a][q] : L.off_psi[a][q]);
+    return DPML_OK;
+}
+
+int64_t dpml_multi_tiles(const dpml_multi_t *H) { return H ? H->ntiles : -1; }
+
+int dpml_multi_sync(dpml_multi_t *H)
+{
+    if (!H) return DPML_EINVAL;
+    hipError_t e = hipStreamSynchronize(H->stream);
+    if (e != hipSuccess) return H->fail(DPML_EHIP, hipGetErrorString(e));
+    return DPML_OK;
+}
+
+void dpml_multi_destroy(dpml_multi_t *H)
+{
+    if (!H) return;
+    (void)hipStreamSynchronize(H->stream);
+    if (H->exec) (void)hipGraphExecDestroy(H->exec);
+    if (H->graph) (void)hipGraphDestroy(H->graph);
+    if (H->cap) (void)hipStreamDestroy(H->cap);
+    delete H;
+}
+
+const char *dpml_multi_last_error(const dpml_multi_t *H) { return H ? H->err.c_str() : g_multi_error.c_str(); }
 
 }  // extern "C"

@@ -10,6 +10,11 @@
 //   Psi_a^{n+1} = Psi_a - dt/2 (sigma_a(i-1) Psi_a(i) + sigma_a(i) Psi_a(i+e_a))
 //                 - dt/(2h) (U(i+e_a) - U(i-e_a))
 //
+// Every expression is evaluated in the plain order of the equations (sum
+// over axes x, y, z; no contraction into FMAs: the library is compiled with
+// -ffp-contract=off), so with h and dt powers of two the FP64 results do not
+// depend on how the sweep is tiled.
+//
 // U^{n+1} overwrites U^{n-1} in place (each cell reads its own old value
 // before writing it; neighbours are read from U^n only).  Phi/Psi are double
 // buffered because the update of band slot j reads slots j-1 / j+1.
@@ -45,16 +50,39 @@ struct StepArgs {
     const T *u;       // U^n
     T *uo;            // U^{n-1} on entry, U^{n+1} on exit
     const T *c2;      // per-cell c^2, or nullptr
-    T k_lap;          // dt^2 c^2 / h^2 (constant c^2) or dt^2 / h^2 (c^2 field)
-    T k_damp;         // dt^2 / h
-    T half_dt;        // dt / 2
-    T dt_2h;          // dt / (2h)
+    T c2_const;       // c^2 when c2 == nullptr
+    T inv_h2;         // 1 / h^2
+    T inv_h;          // 1 / h
+    T inv_2h;         // 1 / (2h)
+    T dt;             // dt
+    T dt2;            // dt * dt
     int32_t nx, ny, nz;
     int32_t tiles_x;  // tiles along x (marching kernels)
     int32_t tiles_y;  // tiles along y (3D marching kernel)
     int32_t tile_rows;// rows (2D) or planes (3D) per marching tile
     int32_t n_tiles;  // real tiles (the grid may be padded to a multiple of 8)
+    int64_t bstride;  // elements between batch members in U
+    int64_t bstride_aux[3];  // elements between batch members in Phi_a/Psi_a
+    T *hist;          // optional: also store U^{n+1} here (same layout as U), or nullptr
 };
+
+// Point the step arguments at batch member bi.
+template <typename T>
+__device__ __forceinline__ void select_member(StepArgs<T> &p, int bi)
+{
+    const int64_t o = (int64_t)bi * p.bstride;
+    p.u += o;
+    p.uo += o;
+    if (p.hist) p.hist += o;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const int64_t oa = (int64_t)bi * p.bstride_aux[a];
+        p.ax[a].phi += oa;
+        p.ax[a].psi += oa;
+        p.ax[a].phi_o += oa;
+        p.ax[a].psi_o += oa;
+    }
+}
 
 __device__ __forceinline__ int wrap_dec(int i, int n) { return i == 0 ? n - 1 : i - 1; }
 __device__ __forceinline__ int wrap_inc(int i, int n) { return i == n - 1 ? 0 : i + 1; }
@@ -69,26 +97,29 @@ __device__ __forceinline__ int band_coord(const Axis<T> &A, int i)
 
 // Damping terms of one axis at a cell with band coordinate j <= M: returns
 // the contribution sigma(i) Psi(i+e) - sigma(i-1) Phi(i-e) (to be scaled by
-// dt^2/h) and writes Phi^{n+1}, Psi^{n+1} of the cell.
+// 1/h) and writes Phi^{n+1}, Psi^{n+1} of the cell (Eqs. (DiscretePML b, c)
+// with a forward step):
+//   Phi' = Phi + dt (-1/2 (sigma(i-1) Phi(i-e) + sigma(i) Phi) - (U(i+e) - U(i-e))/(2h))
+//   Psi' = Psi + dt (-1/2 (sigma(i-1) Psi + sigma(i) Psi(i+e)) - (U(i+e) - U(i-e))/(2h))
 //   cbase: compact index of slot j = 0 for this cell's line along the axis;
-//   cstr : stride of the axis in the compact array;  du = U(i+e) - U(i-e).
+//   cstr : stride of the axis in the compact array;  um, up = U(i-e), U(i+e).
 template <typename T>
 __device__ __forceinline__ T layer_terms(const Axis<T> &A, int j, int64_t cbase, int64_t cstr,
-                                         T du, T half_dt, T dt_2h)
+                                         T um, T up, T dt, T inv_2h)
 {
     const int64_t c = cbase + (int64_t)j * cstr;
     const T s = A.sig[j];                              // sigma_a(i)
     const T sl = j > 0 ? A.sig[j - 1] : T(0);          // sigma_a(i-1)
     const T phi_l = j > 0 ? A.phi[c - cstr] : T(0);    // Phi_a(i-e)
     const T psi_r = j < A.M ? A.psi[c + cstr] : T(0);  // Psi_a(i+e)
-    const T grad = dt_2h * du;
+    const T grad = (up - um) * inv_2h;
     if (j < A.M) {
         const T phi_c = A.phi[c];
-        A.phi_o[c] = phi_c - half_dt * (sl * phi_l + s * phi_c) - grad;
+        A.phi_o[c] = phi_c + dt * (T(-0.5) * (sl * phi_l + s * phi_c) - grad);
     }
     if (j > 0) {
         const T psi_c = A.psi[c];
-        A.psi_o[c] = psi_c - half_dt * (sl * psi_c + s * psi_r) - grad;
+        A.psi_o[c] = psi_c + dt * (T(-0.5) * (sl * psi_c + s * psi_r) - grad);
     }
     return s * psi_r - sl * phi_l;
 }
@@ -99,11 +130,12 @@ template <typename T, int D>
 __device__ __forceinline__ T cell_update(const StepArgs<T> &p, int x, int y, int z, int64_t idx,
                                          T uc, T uxm, T uxp, T uym, T uyp, T uzm, T uzp, T uold)
 {
-    T lap = (uxm + uxp - T(2) * uc) + (uym + uyp - T(2) * uc);
-    if (D == 3) lap += (uzm + uzp - T(2) * uc);
-    T k = p.k_lap;
-    if (p.c2) k *= p.c2[idx];
-    T acc = T(2) * uc - uold + k * lap;
+    // Eq. (DiscretePML a): c^2 sum_a (U(i-e) - 2U + U(i+e))/h^2 + sum_a (...)/h
+    T lap = T(0);
+    lap += ((uxm - T(2) * uc) + uxp) * p.inv_h2;
+    lap += ((uym - T(2) * uc) + uyp) * p.inv_h2;
+    if (D == 3) lap += ((uzm - T(2) * uc) + uzp) * p.inv_h2;
+    const T c2 = p.c2 ? p.c2[idx] : p.c2_const;
     T damp = T(0);
     const int64_t nx = p.nx, ny = p.ny;
     // x-axis layer: compact [z][y][Mx+1]
@@ -111,7 +143,7 @@ __device__ __forceinline__ T cell_update(const StepArgs<T> &p, int x, int y, int
         const int j = band_coord(p.ax[0], x);
         if (j <= p.ax[0].M) {
             const int64_t base = ((int64_t)z * ny + y) * (p.ax[0].M + 1);
-            damp += layer_terms(p.ax[0], j, base, 1, uxp - uxm, p.half_dt, p.dt_2h);
+            damp += layer_terms(p.ax[0], j, base, 1, uxm, uxp, p.dt, p.inv_2h) * p.inv_h;
         }
     }
     // y-axis layer: compact [z][My+1][x]
@@ -119,7 +151,7 @@ __device__ __forceinline__ T cell_update(const StepArgs<T> &p, int x, int y, int
         const int j = band_coord(p.ax[1], y);
         if (j <= p.ax[1].M) {
             const int64_t base = (int64_t)z * (p.ax[1].M + 1) * nx + x;
-            damp += layer_terms(p.ax[1], j, base, nx, uyp - uym, p.half_dt, p.dt_2h);
+            damp += layer_terms(p.ax[1], j, base, nx, uym, uyp, p.dt, p.inv_2h) * p.inv_h;
         }
     }
     // z-axis layer: compact [Mz+1][y][x]
@@ -127,10 +159,11 @@ __device__ __forceinline__ T cell_update(const StepArgs<T> &p, int x, int y, int
         const int j = band_coord(p.ax[2], z);
         if (j <= p.ax[2].M) {
             const int64_t base = (int64_t)y * nx + x;
-            damp += layer_terms(p.ax[2], j, base, nx * ny, uzp - uzm, p.half_dt, p.dt_2h);
+            damp += layer_terms(p.ax[2], j, base, nx * ny, uzm, uzp, p.dt, p.inv_2h) * p.inv_h;
         }
     }
-    return acc + p.k_damp * damp;
+    const T rhs = c2 * lap + damp;
+    return (T(2) * uc - uold) + p.dt2 * rhs;
 }
 
 // ---------------------------------------------------------------------------
@@ -141,8 +174,10 @@ __global__ void __launch_bounds__(256) k_step_cell(StepArgs<T> p)
 {
     const int x = blockIdx.x * 64 + threadIdx.x;
     const int y = blockIdx.y * 4 + threadIdx.y;
-    const int z = D == 3 ? (int)blockIdx.z : 0;
+    const int z = D == 3 ? (int)(blockIdx.z % p.nz) : 0;
+    const int bi = D == 3 ? (int)(blockIdx.z / p.nz) : (int)blockIdx.z;
     if (x >= p.nx || y >= p.ny) return;
+    select_member(p, bi);
     const int64_t nx = p.nx, ny = p.ny;
     const int64_t row = ((int64_t)z * ny + y) * nx;
     const int64_t idx = row + x;
@@ -160,6 +195,7 @@ __global__ void __launch_bounds__(256) k_step_cell(StepArgs<T> p)
                                   u[plane + (int64_t)ym * nx + x], u[plane + (int64_t)yp * nx + x],
                                   uzm, uzp, p.uo[idx]);
     p.uo[idx] = r;
+    if (p.hist) p.hist[idx] = r;
 }
 
 // Map a hardware block id to a logical tile so that the blocks one XCD
@@ -213,13 +249,10 @@ __device__ __forceinline__ void store_row(T *ptr, const Row<T, VX> &r)
     *reinterpret_cast<V *>(ptr) = w;
 }
 
+// One 2D marching tile (tile column tx, tile row ty) of one problem.
 template <typename T, int VX>
-__global__ void __launch_bounds__(256) k_step_march2d(StepArgs<T> p)
+__device__ __forceinline__ void march2d_tile(const StepArgs<T> &p, int tx, int ty)
 {
-    const int tile = xcd_tile(blockIdx.x, gridDim.x);
-    if (tile >= p.n_tiles) return;
-    const int tx = tile % p.tiles_x;          // tiles along x vary fastest
-    const int ty = tile / p.tiles_x;
     const int x0 = (tx * 256 + (int)threadIdx.x) * VX;
     if (x0 >= p.nx) return;
     const int nx = p.nx, ny = p.ny;
@@ -249,10 +282,41 @@ __global__ void __launch_bounds__(256) k_step_march2d(StepArgs<T> p)
                                          um.v[k], up.v[k], T(0), T(0), old.v[k]);
         }
         store_row<T, VX>(p.uo + row + x0, out);
+        if (p.hist) store_row<T, VX>(p.hist + row + x0, out);
         um = uc;
         uc = up;
         up = upp;
     }
+}
+
+template <typename T, int VX>
+__global__ void __launch_bounds__(256) k_step_march2d(StepArgs<T> p)
+{
+    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+    if (tile >= p.n_tiles) return;
+    select_member(p, (int)blockIdx.y);
+    march2d_tile<T, VX>(p, tile % p.tiles_x, tile / p.tiles_x);
+}
+
+// ---------------------------------------------------------------------------
+// Many independent 2D problems of different sizes in one launch: a flat
+// work list of tiles (problem, tile column, tile row) over all problems; each
+// block looks up its problem's arguments (uniform, read through the scalar
+// cache) and runs one marching tile.
+// ---------------------------------------------------------------------------
+struct TileRef {
+    int32_t prob, tx, ty, pad;
+};
+
+template <typename T, int VX>
+__global__ void __launch_bounds__(256) k_step_multi2d(const StepArgs<T> *__restrict__ probs,
+                                                      const TileRef *__restrict__ tiles, int ntiles)
+{
+    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+    if (tile >= ntiles) return;
+    const TileRef t = tiles[tile];
+    const StepArgs<T> p = probs[t.prob];
+    march2d_tile<T, VX>(p, t.tx, t.ty);
 }
 
 // ---------------------------------------------------------------------------
@@ -265,6 +329,7 @@ __global__ void __launch_bounds__(256) k_step_march3d(StepArgs<T> p)
 {
     const int tile = xcd_tile(blockIdx.x, gridDim.x);
     if (tile >= p.n_tiles) return;
+    select_member(p, (int)blockIdx.y);
     const int per_plane = p.tiles_x * p.tiles_y;
     const int tz = tile / per_plane;
     const int rem = tile - tz * per_plane;
@@ -307,8 +372,10 @@ __global__ void __launch_bounds__(256) k_step_march3d(StepArgs<T> p)
                 const T uym = u[plane + (int64_t)wrap_dec(y, ny) * nx + x];
                 const T uyp = u[plane + (int64_t)wrap_inc(y, ny) * nx + x];
                 const T old = p.uo[idx];
-                p.uo[idx] = cell_update<T, 3>(p, x, y, z, idx, uc[r], uxm, uxp, uym, uyp,
-                                              um[r], up[r], old);
+                const T res = cell_update<T, 3>(p, x, y, z, idx, uc[r], uxm, uxp, uym, uyp,
+                                                um[r], up[r], old);
+                p.uo[idx] = res;
+                if (p.hist) p.hist[idx] = res;
             }
             um[r] = uc[r];
             uc[r] = up[r];
@@ -323,26 +390,32 @@ __global__ void __launch_bounds__(256) k_step_march3d(StepArgs<T> p)
 template <typename T, int D>
 __global__ void __launch_bounds__(256) k_start(const T *__restrict__ u0, const T *__restrict__ v0,
                                                T *__restrict__ um1, const T *__restrict__ c2,
-                                               T half_k_lap, T dt, int nx, int ny, int nz)
+                                               T c2_const, T inv_h2, T dt, T half_dt2,
+                                               int nx, int ny, int nz)
 {
     const int x = blockIdx.x * 64 + threadIdx.x;
     const int y = blockIdx.y * 4 + threadIdx.y;
-    const int z = D == 3 ? (int)blockIdx.z : 0;
+    const int z = D == 3 ? (int)(blockIdx.z % nz) : 0;
+    const int bi = D == 3 ? (int)(blockIdx.z / nz) : (int)blockIdx.z;
     if (x >= nx || y >= ny) return;
+    const int64_t boff = (int64_t)bi * nx * ny * nz;
+    u0 += boff;
+    um1 += boff;
+    if (v0) v0 += boff;
     const int64_t sx = nx, sxy = (int64_t)nx * ny;
     const int64_t idx = (int64_t)z * sxy + (int64_t)y * sx + x;
     const int64_t plane = (int64_t)z * sxy;
     const T c = u0[idx];
-    T lap = (u0[plane + (int64_t)y * sx + wrap_dec(x, nx)] + u0[plane + (int64_t)y * sx + wrap_inc(x, nx)] - T(2) * c)
-          + (u0[plane + (int64_t)wrap_dec(y, ny) * sx + x] + u0[plane + (int64_t)wrap_inc(y, ny) * sx + x] - T(2) * c);
+    T lap = T(0);
+    lap += ((u0[plane + (int64_t)y * sx + wrap_dec(x, nx)] - T(2) * c) + u0[plane + (int64_t)y * sx + wrap_inc(x, nx)]) * inv_h2;
+    lap += ((u0[plane + (int64_t)wrap_dec(y, ny) * sx + x] - T(2) * c) + u0[plane + (int64_t)wrap_inc(y, ny) * sx + x]) * inv_h2;
     if (D == 3)
-        lap += u0[(int64_t)wrap_dec(z, nz) * sxy + (int64_t)y * sx + x]
-             + u0[(int64_t)wrap_inc(z, nz) * sxy + (int64_t)y * sx + x] - T(2) * c;
-    T k = half_k_lap;
-    if (c2) k *= c2[idx];
-    T r = c + k * lap;
-    if (v0) r -= dt * v0[idx];
-    um1[idx] = r;
+        lap += ((u0[(int64_t)wrap_dec(z, nz) * sxy + (int64_t)y * sx + x] - T(2) * c)
+                + u0[(int64_t)wrap_inc(z, nz) * sxy + (int64_t)y * sx + x]) * inv_h2;
+    const T a = (c2 ? c2[idx] : c2_const) * lap;
+    // U^{-1} = U^0 - dt V^0 + (dt^2/2) A(U^0)
+    const T v = v0 ? v0[idx] : T(0);
+    um1[idx] = (c - dt * v) + half_dt2 * a;
 }
 
 // Point sources: U[cell_s] += amp * w[s][n]   (amp = dt^2 / h^d).  The host
@@ -404,6 +477,182 @@ __global__ void __launch_bounds__(256) k_nonfinite(const T *__restrict__ u, int6
     if (bad) any = 1;              // benign race: every writer stores 1
     __syncthreads();
     if (threadIdx.x == 0) flags[blockIdx.x] = any;
+}
+
+// ---------------------------------------------------------------------------
+// Discrete adjoint of one step (transpose of the step map), reverse time.
+// With a^k the adjoint of U^k and p_a, q_a those of Phi_a, Psi_a at level n+1:
+//   a^n     = 2 a^{n+1} - a^{n+2} + dt^2 L(c^2 a^{n+1}) + dt sum_a G_a(p_a + q_a)
+//   p_a^n   = p_a - dt/2 sigma(i)  (p_a(i) + p_a(i+e)) - dt^2/h sigma(i)   a^{n+1}(i+e)
+//   q_a^n   = q_a - dt/2 sigma(i-1)(q_a(i) + q_a(i-e)) + dt^2/h sigma(i-1) a^{n+1}(i-e)
+//   grad_c2 += dt^2 a^{n+1} (L U^n)           (summed over batch members in FP64)
+// G_a U = (U(i+e) - U(i-e))/(2h), L the periodic Laplacian.  p_a is kept at
+// band slots [0, M-1] and q_a at [1, M]; the other slot of each stays 0, so
+// (p+q) can be read at any slot j <= M.  a^n overwrites a^{n+2} in place.
+// ---------------------------------------------------------------------------
+template <typename T>
+struct AdjArgs {
+    Axis<T> ax[3];    // sig; phi/psi = p, q at n+1; phi_o/psi_o = p, q at n
+    const T *lam;     // a^{n+1}
+    T *lam_o;         // a^{n+2} on entry, a^n on exit
+    const T *un;      // U^n
+    const T *c2;      // per-cell c^2 or nullptr
+    double *grad;     // dJ/dc^2, accumulated (+=), one value per cell
+    T c2_const;       // c^2 when c2 == nullptr
+    T inv_h2;         // 1 / h^2
+    T inv_2h;         // 1 / (2h)
+    T dt;             // dt
+    T dt2;            // dt * dt
+    T half_dt;        // dt / 2
+    T k_damp;         // dt^2 / h
+    int32_t nx, ny, nz, batch;
+    int64_t bstride;
+    int64_t bstride_aux[3];
+};
+
+// (p + q) of axis A at band slot j (0 outside the band).
+template <typename T>
+__device__ __forceinline__ T pq_at(const Axis<T> &A, int j, int64_t cbase, int64_t cstr, int64_t boff)
+{
+    if (A.M == 0 || j > A.M) return T(0);
+    const int64_t c = boff + cbase + (int64_t)j * cstr;
+    return A.phi[c] + A.psi[c];
+}
+
+template <typename T, int D>
+__global__ void __launch_bounds__(256) k_adjoint_cell(AdjArgs<T> p)
+{
+    const int x = blockIdx.x * 64 + threadIdx.x;
+    const int y = blockIdx.y * 4 + threadIdx.y;
+    const int z = D == 3 ? (int)blockIdx.z : 0;
+    if (x >= p.nx || y >= p.ny) return;
+    const int nx = p.nx, ny = p.ny, nz = p.nz;
+    const int64_t sy = nx, sz = (int64_t)nx * ny;
+    const int64_t idx = (int64_t)z * sz + (int64_t)y * sy + x;
+    const int xm = wrap_dec(x, nx), xp = wrap_inc(x, nx);
+    const int ym = wrap_dec(y, ny), yp = wrap_inc(y, ny);
+    const int zm = D == 3 ? wrap_dec(z, nz) : 0, zp = D == 3 ? wrap_inc(z, nz) : 0;
+    const int64_t nb[6] = {idx - x + xm, idx - x + xp, idx + (int64_t)(ym - y) * sy, idx + (int64_t)(yp - y) * sy,
+                           idx + (int64_t)(zm - z) * sz, idx + (int64_t)(zp - z) * sz};
+    const int nnb = 2 * D;
+    // c^2 at the cell and its neighbours (shared by all batch members)
+    T cc = p.c2 ? p.c2[idx] : p.c2_const;
+    T cn[6];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) cn[k] = (k < nnb) ? (p.c2 ? p.c2[nb[k]] : p.c2_const) : T(0);
+    // per-axis band coordinates of the cell and of its two neighbours
+    int jc[3], jm[3], jp[3];
+    int64_t cbase[3], cstr[3];
+    const int coord[3] = {x, y, z};
+    const int cm_[3] = {xm, ym, zm};
+    const int cp_[3] = {xp, yp, zp};
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const Axis<T> &A = p.ax[a];
+        jc[a] = jm[a] = jp[a] = 1 << 30;
+        cbase[a] = 0;
+        cstr[a] = 1;
+        if (a < D && A.M > 0) {
+            jc[a] = band_coord(A, coord[a]);
+            jm[a] = band_coord(A, cm_[a]);
+            jp[a] = band_coord(A, cp_[a]);
+            if (a == 0) { cbase[a] = ((int64_t)z * ny + y) * (A.M + 1); cstr[a] = 1; }
+            if (a == 1) { cbase[a] = (int64_t)z * (A.M + 1) * nx + x; cstr[a] = nx; }
+            if (a == 2) { cbase[a] = (int64_t)y * nx + x; cstr[a] = (int64_t)nx * ny; }
+        }
+    }
+    double gsum = 0.0;
+    for (int bi = 0; bi < p.batch; ++bi) {
+        const int64_t bo = (int64_t)bi * p.bstride;
+        const T *lam = p.lam + bo;
+        const T *un = p.un + bo;
+        const T lc = lam[idx];
+        T ln[6], uu[6];
+#pragma unroll
+        for (int k = 0; k < 6; ++k) {
+            ln[k] = (k < nnb) ? lam[nb[k]] : T(0);
+            uu[k] = (k < nnb) ? un[nb[k]] : T(0);
+        }
+        const T uc = un[idx];
+        const T clc = cc * lc;
+        T lapc = T(0), lapu = T(0);
+#pragma unroll
+        for (int k = 0; k < 6; k += 2) {
+            if (k < nnb) {
+                lapc += ((cn[k] * ln[k] - T(2) * clc) + cn[k + 1] * ln[k + 1]) * p.inv_h2;
+                lapu += ((uu[k] - T(2) * uc) + uu[k + 1]) * p.inv_h2;
+            }
+        }
+        T v = (T(2) * lc - p.lam_o[bo + idx]) + p.dt2 * lapc;
+#pragma unroll
+        for (int a = 0; a < D; ++a) {
+            const Axis<T> &A = p.ax[a];
+            if (A.M == 0) continue;
+            const int64_t ba = (int64_t)bi * p.bstride_aux[a];
+            // G_a(p + q) from the neighbours' band slots
+            if (jm[a] <= A.M || jp[a] <= A.M) {
+                // neighbours' compact bases: same line, slot differs
+                const T up_ = pq_at(A, jp[a], cbase[a], cstr[a], ba);
+                const T dn_ = pq_at(A, jm[a], cbase[a], cstr[a], ba);
+                v += (p.dt * (up_ - dn_)) * p.inv_2h;
+            }
+            if (jc[a] <= A.M) {
+                const int j = jc[a];
+                const int64_t c = ba + cbase[a] + (int64_t)j * cstr[a];
+                const T s = A.sig[j];
+                const T sl = j > 0 ? A.sig[j - 1] : T(0);
+                if (j < A.M) {
+                    const T pc = A.phi[c], pr = A.phi[c + cstr[a]];
+                    A.phi_o[c] = (pc - (p.half_dt * s) * (pc + pr)) - (p.k_damp * s) * ln[2 * a + 1];
+                }
+                if (j > 0) {
+                    const T qc = A.psi[c], ql = A.psi[c - cstr[a]];
+                    A.psi_o[c] = (qc - (p.half_dt * sl) * (qc + ql)) + (p.k_damp * sl) * ln[2 * a];
+                }
+            }
+        }
+        p.lam_o[bo + idx] = v;
+        gsum += (double)(p.dt2 * lc) * (double)lapu;
+    }
+    p.grad[idx] += gsum;
+}
+
+// Adjoint of the start U^{-1} = U^0 + dt^2/2 c^2 L U^0 with a^{-1} = -a^1:
+// grad_c2 += dt^2/2 (-a^1) (L U^0), summed over batch members.
+template <typename T, int D>
+__global__ void __launch_bounds__(256) k_adjoint_start(const T *__restrict__ a1, const T *__restrict__ u0,
+                                                       double *__restrict__ grad, T half_dt2, T inv_h2,
+                                                       int nx, int ny, int nz, int batch, int64_t bstride)
+{
+    const int x = blockIdx.x * 64 + threadIdx.x;
+    const int y = blockIdx.y * 4 + threadIdx.y;
+    const int z = D == 3 ? (int)blockIdx.z : 0;
+    if (x >= nx || y >= ny) return;
+    const int64_t sy = nx, sz = (int64_t)nx * ny;
+    const int64_t idx = (int64_t)z * sz + (int64_t)y * sy + x;
+    double g = 0.0;
+    for (int bi = 0; bi < batch; ++bi) {
+        const T *u = u0 + (int64_t)bi * bstride;
+        const T c = u[idx];
+        T lap = T(0);
+        lap += ((u[idx - x + wrap_dec(x, nx)] - T(2) * c) + u[idx - x + wrap_inc(x, nx)]) * inv_h2;
+        lap += ((u[idx + (int64_t)(wrap_dec(y, ny) - y) * sy] - T(2) * c) + u[idx + (int64_t)(wrap_inc(y, ny) - y) * sy]) * inv_h2;
+        if (D == 3)
+            lap += ((u[idx + (int64_t)(wrap_dec(z, nz) - z) * sz] - T(2) * c) + u[idx + (int64_t)(wrap_inc(z, nz) - z) * sz]) * inv_h2;
+        g += (double)(half_dt2 * -a1[(int64_t)bi * bstride + idx]) * (double)lap;
+    }
+    grad[idx] += g;
+}
+
+// out[order[q] * nt + n] = amp * u[cells[q]]  (gather, e.g. the wavelet gradient).
+template <typename T>
+__global__ void __launch_bounds__(256) k_gather_scaled(const T *__restrict__ u, const int64_t *__restrict__ cells,
+                                                       const int64_t *__restrict__ order, T *__restrict__ out,
+                                                       int64_t count, int64_t nt, int64_t n, T amp)
+{
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= count) return;
+    out[order[q] * nt + n] = amp * u[cells[q]];
 }
 
 }  // namespace dpmlk
