@@ -141,6 +141,157 @@ def copy_probe(mib: int = 1024, reps: int = 20):
                       "ms": round(ms, 4), "GB_per_s": round(gbs, 1)}), flush=True)
 
 
+def _events():
+    import torch
+    return torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+
+def bench_ricker3d(steps: int):
+    """3D, 512^3 interior + 24-cell layer on all faces (560^3 cells), FP32,
+    dt = 0.4 h, Ricker point source at the centre, the z plane through it
+    recorded every step."""
+    import torch
+    import paper_1804_01390_amd as dp
+    import synthetic
+    w = synthetic.ricker3d(n=512, m=24, steps=steps)
+    sim = dp.Simulation(w.n, w.lo, w.hi, w.h, w.dt, w.sigma, dtype=torch.float32)
+    sim.set_state(torch.zeros(tuple(reversed(w.N)), dtype=torch.float32, device="cuda"))
+    sim.inject(w.sources, torch.from_numpy(w.wavelets))
+    axis, index = w.plane
+    sim.record_plane(axis, index, w.steps)
+    sim.step(5)
+    sim.sync()
+    e0, e1 = _events()
+    # restart from rest so the timed run is the workload's steps 0..steps-1
+    sim.set_state(torch.zeros(tuple(reversed(w.N)), dtype=torch.float32, device="cuda"))
+    sim.sync()
+    e0.record()
+    sim.step(w.steps)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    plane_cells = w.N[0] * w.N[1]
+    ab = alg_bytes_per_step(w, 4) + plane_cells * 4
+    peak = float(sim._keep["planes"][-1].abs().max().item())
+    sim.close()
+    return {"workload": "3D 512^3 interior + 24-cell layer (560^3 cells), FP32, Ricker source, "
+                        "plane recorded every step, %d steps" % w.steps,
+            "value": round(w.cells * w.steps / (ms * 1e-3) / 1e9, 3), "unit": "Gcell/s",
+            "ms_per_step": round(ms / w.steps, 5),
+            "alg_GBps": round(ab * w.steps / (ms * 1e-3) / 1e9, 1),
+            "frac_of_8TBps": round(ab * w.steps / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+            "last_plane_peak": peak}
+
+
+def bench_batch(steps: int, count: int):
+    """``count`` independent 2D problems (sides log-uniform in [256, 1536],
+    16-32-cell layers), FP32, one Gaussian each: one HIP-graph launch for the
+    whole run (one kernel per step over a tile list of all problems) against
+    separate runs of each problem."""
+    import torch
+    import paper_1804_01390_amd as dp
+    import synthetic
+    probs = synthetic.batch2d(count=count, steps=steps)
+    cells = sum(w.cells for w in probs)
+    multi = dp.MultiSimulation(probs, dtype=torch.float32)
+    multi.set_state([w.U0 for w in probs])
+    multi.step(steps, graph=True)          # capture + instantiate + one run
+    multi.sync()
+    multi.set_state([w.U0 for w in probs])
+    multi.sync()
+    e0, e1 = _events()
+    e0.record()
+    multi.step(steps, graph=True)          # the cached graph: one launch
+    e1.record()
+    torch.cuda.synchronize()
+    ms_graph = e0.elapsed_time(e1)
+    multi.close()
+    sims = []
+    for w in probs:
+        s = dp.Simulation(w.n, w.lo, w.hi, w.h, w.dt, w.sigma, dtype=torch.float32)
+        s.set_state(torch.from_numpy(w.U0))
+        sims.append(s)
+    torch.cuda.synchronize()
+    e0, e1 = _events()
+    e0.record()
+    for s in sims:
+        s.step(steps)
+    e1.record()
+    torch.cuda.synchronize()
+    ms_sep = e0.elapsed_time(e1)
+    for s in sims:
+        s.close()
+    return {"workload": "%d 2D problems, sides log-uniform in [256,1536], 16-32-cell layers, FP32, "
+                        "%d steps (%d cells per step)" % (count, steps, cells),
+            "graph_value": round(cells * steps / (ms_graph * 1e-3) / 1e9, 3),
+            "separate_value": round(cells * steps / (ms_sep * 1e-3) / 1e9, 3), "unit": "Gcell/s",
+            "graph_ms": round(ms_graph, 3), "separate_ms": round(ms_sep, 3),
+            "speedup": round(ms_sep / ms_graph, 3)}
+
+
+def bench_adjoint(steps: int, shots: int):
+    """2D 1024^2 + 32-cell layer, FP32 fields, smooth random c^2, ``shots``
+    Ricker shots, 1024 receivers: observed traces from a second c^2, then the
+    checkpointed forward and the reverse-time adjoint (FP64 gradient)."""
+    import torch
+    import paper_1804_01390_amd as dp
+    import synthetic
+    w = synthetic.shots2d(shots=shots, steps=steps)
+    B, cells = shots, w.cells
+    src = [b * cells + w.sources[b][0] for b in range(B)]
+    rec = [b * cells + r for b in range(B) for r in w.receivers]
+
+    def make(c2):
+        sim = dp.Simulation(w.n, w.lo, w.hi, w.h, w.dt, w.sigma, c2=c2, dtype=torch.float32, batch=B)
+        sim.set_state(torch.zeros(sim.shape, dtype=torch.float32, device="cuda"))
+        sim.inject(src, torch.from_numpy(w.wavelets))
+        tr = sim.record(rec, steps)
+        return sim, tr
+
+    sim, obs = make(w.c2_true)
+    sim.step(steps)
+    sim.sync()
+    obs = obs.clone()
+    sim.close()
+    sim, tr = make(w.c2_model)
+    # plain forward (no checkpoints) for reference
+    sim.sync()
+    e0, e1 = _events()
+    e0.record()
+    sim.step(steps)
+    e1.record()
+    torch.cuda.synchronize()
+    ms_plain = e0.elapsed_time(e1)
+    sim.set_state(torch.zeros(sim.shape, dtype=torch.float32, device="cuda"))
+    sim.sync()
+    e0, e1 = _events()
+    e0.record()
+    sim.forward_checkpointed(steps)
+    e1.record()
+    torch.cuda.synchronize()
+    ms_fwd = e0.elapsed_time(e1)
+    resid = (tr - obs).contiguous()
+    grad = torch.zeros(tuple(reversed(w.N)), dtype=torch.float64, device="cuda")
+    torch.cuda.synchronize()
+    e0, e1 = _events()
+    e0.record()
+    gc2, gw = sim.adjoint(resid, grad_c2=grad)
+    e1.record()
+    torch.cuda.synchronize()
+    ms_bwd = e0.elapsed_time(e1)
+    misfit = 0.5 * float((resid.double() ** 2).sum().item())
+    gnorm = float(gc2.abs().max().item())
+    finite = bool(torch.isfinite(gc2).all().item())
+    sim.close()
+    return {"workload": "2D 1024^2 + 32-cell layer (1088^2 cells) x %d shots, FP32 fields, FP64 c^2 "
+                        "gradient, 1024 receivers, %d steps, sqrt(T) checkpoints" % (B, steps),
+            "forward_ms": round(ms_fwd, 3), "forward_plain_ms": round(ms_plain, 3),
+            "backward_ms": round(ms_bwd, 3),
+            "adjoint_forward_ratio": round(ms_bwd / ms_fwd, 3),
+            "forward_value": round(B * cells * steps / (ms_fwd * 1e-3) / 1e9, 3), "unit": "Gcell/s",
+            "misfit": misfit, "grad_c2_max": gnorm, "grad_finite": finite}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -153,6 +304,12 @@ def main():
     ap.add_argument("--tile-rows", type=int, default=0)
     ap.add_argument("--copy-probe", action="store_true",
                     help="only time a plain 1 GiB device copy and exit")
+    ap.add_argument("--quick", action="store_true",
+                    help="only the 4160^2 workload (skip the 3D, batched and adjoint workloads)")
+    ap.add_argument("--adjoint-steps", type=int, default=3000)
+    ap.add_argument("--batch-steps", type=int, default=1500)
+    ap.add_argument("--batch-count", type=int, default=256)
+    ap.add_argument("--steps-3d", type=int, default=1000)
     args = ap.parse_args()
     if args.copy_probe:
         copy_probe()
@@ -207,6 +364,16 @@ def main():
         "roofline": main_run["roofline"],
         "runs": runs,
     }
+    if not args.quick:
+        log("ricker3d: %d steps" % args.steps_3d)
+        out["ricker3d"] = bench_ricker3d(args.steps_3d)
+        log("  %s" % out["ricker3d"])
+        log("batch: %d problems x %d steps" % (args.batch_count, args.batch_steps))
+        out["batch"] = bench_batch(args.batch_steps, args.batch_count)
+        log("  %s" % out["batch"])
+        log("adjoint: 32 shots x %d steps" % args.adjoint_steps)
+        out["adjoint"] = bench_adjoint(args.adjoint_steps, 32)
+        log("  %s" % out["adjoint"])
     if not args.no_cpu:
         log("cpu baseline: oracle, %d steps" % args.cpu_steps)
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_steps)

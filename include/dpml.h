@@ -224,6 +224,34 @@ int dpml_adjoint(dpml_t *h, const void *resid, double *grad_c2, void *grad_w);
 /* Wait for the handle's stream and report any deferred HIP error. */
 int dpml_sync(dpml_t *h);
 
+/* ---- The paper's own integrator: RK4 ---------------------------------------
+ * Classic fourth-order Runge-Kutta on the first-order system U_t = V,
+ * V_t = A(U, Phi, Psi), Phi_a,t = B_a, Psi_a,t = C_a with the right-hand
+ * sides of Eq. (DiscretePML a, b, c) (the time stepping of the paper's runs,
+ * Sec. 1.1.3).  Exactly reflectionless as well: the continued plane waves of
+ * Thm. 1 are eigenvectors of the semi-discrete system, hence of any
+ * polynomial one-step map.  Four fused stage sweeps per step.  Uses the
+ * handle's grid, damping tables and c^2 (batch must be 1); its state lives in
+ * a separate caller-owned workspace; no sources or receivers. */
+
+/* Bytes of that workspace (four copies of U, V, Phi_a, Psi_a); 0 if the
+ * handle has batch > 1. */
+size_t dpml_rk4_workspace_bytes(const dpml_t *h);
+
+/* Bind the workspace (borrowed, 256-byte aligned) and set U = U0,
+ * V = V0 (NULL: zero), Phi = Psi = 0; RK4 time index 0. */
+int dpml_rk4_set_state(dpml_t *h, void *rk_ws, size_t bytes, const void *U0, const void *V0);
+
+/* Enqueue nsteps RK4 steps (asynchronous). */
+int dpml_rk4_step(dpml_t *h, int64_t nsteps);
+
+/* Borrowed pointer/extents of the RK4 state: which = DPML_FIELD_U (U),
+ * 1 (V = U_t), DPML_FIELD_PHI(a), DPML_FIELD_PSI(a) (compact, as above). */
+int dpml_rk4_field(dpml_t *h, int32_t which, void **ptr, int64_t shape[3]);
+
+/* RK4 step count since dpml_rk4_set_state, or -1. */
+int64_t dpml_rk4_time_index(const dpml_t *h);
+
 /* ---- Many independent 2D problems of different sizes --------------------
  * Each problem is its own grid (Eq. (DiscretePML) with unit wave speed, the
  * time placement above and its own h, dt, sigma); one kernel launch per step

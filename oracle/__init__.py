@@ -17,6 +17,9 @@ Parity status of each function (see the pins in ``tests/test_oracle_pins.py``):
                             energy conservation; reflection against free space,
                             Figs. 2/3; 1-D light-cone Green's function)
   wave_run               -- pinned (exact Fourier modes)
+  rk4_run                -- pinned (exact one-step layer eigenmodes of the
+                            semi-discrete system, Fourier modes, reflection
+                            against the RK4 free-space run)
   adjoint                -- pinned (dot-product identity for the wavelet map,
                             which is linear; central differences for c^2)
 """
@@ -87,6 +90,8 @@ def _load():
         lib.orc_adjoint.argtypes = [gp, _DP, ctypes.c_int64, ctypes.c_int64, _I64P, _DP,
                                     ctypes.c_int64, _I64P, _DP, _DP, _DP]
         lib.orc_adjoint.restype = ctypes.c_int
+        lib.orc_rk4_run.argtypes = [gp, _DP, _DP, _DP3, _DP3, ctypes.c_int64]
+        lib.orc_rk4_run.restype = ctypes.c_int
         _lib = lib
     return _lib
 
@@ -272,3 +277,33 @@ def adjoint(g: Grid, U0, nsteps: int, sources, wavelets, receivers, resid):
     if rc != 0:
         raise MemoryError("oracle adjoint: out of memory")
     return gc2, gw
+
+
+@dataclass
+class RKState:
+    """First-order state of the RK4 integrator: U, V = U_t, Phi_a, Psi_a."""
+    U: np.ndarray
+    V: np.ndarray
+    Phi: list
+    Psi: list
+    n: int = 0
+
+
+def rk4_start(g: Grid, U0, V0=None) -> RKState:
+    U0 = _f64(U0).copy()
+    V = np.zeros_like(U0) if V0 is None else _f64(V0).copy()
+    return RKState(U0, V, [np.zeros_like(U0) for _ in range(g.ndim)],
+                   [np.zeros_like(U0) for _ in range(g.ndim)], 0)
+
+
+def rk4_run(g: Grid, s: RKState, nsteps: int) -> RKState:
+    """Classic RK4 on (U, V, Phi, Psi) (the paper's integrator); returns a new state."""
+    lib = _load()
+    gs, keep = g._struct()
+    out = RKState(_f64(s.U).copy(), _f64(s.V).copy(), [_f64(p).copy() for p in s.Phi],
+                  [_f64(p).copy() for p in s.Psi], s.n)
+    rc = lib.orc_rk4_run(ctypes.byref(gs), _dp(out.U), _dp(out.V), _aux3(out.Phi), _aux3(out.Psi), nsteps)
+    if rc != 0:
+        raise MemoryError("oracle rk4: out of memory")
+    out.n += nsteps
+    return out

@@ -143,3 +143,34 @@ def leapfrog_energy(U_new: np.ndarray, U_old: np.ndarray, h: float, dt: float,
         kin = kin[box]
         pot = pot[box]
     return 0.5 * float(np.sum(kin)) + 0.5 * float(np.sum(pot))
+
+
+def semidiscrete_layer_mode(N, b, sigma, k, h: float):
+    """Exact solution of the semi-discrete system (continuous time) of
+    Eq. (DiscretePML): the plane wave prod_a W_{k_a} e^{-i omega t} with
+    omega^2 h^2 = sum_a 4 sin^2(k_a h/2) (Eq. DiscreteDispersion), continued
+    into the layer by Thm. 1 (omega' = omega).  Returns U, V = -i omega U, Phi,
+    Psi at t = 0 and omega; any one-step method that is a polynomial P in the
+    system matrix (RK4: P(x) = 1 + x + x^2/2 + x^3/6 + x^4/24) maps it to
+    P(-i omega dt) times itself."""
+    d = len(N)
+    lam = sum((4.0 / h ** 2) * np.sin(np.complex128(ka) * h / 2.0) ** 2 for ka in k)
+    omega = np.sqrt(np.complex128(lam))
+    facs = [_axis_factors(int(N[a]), int(b[a]), np.asarray(sigma[a], dtype=np.float64),
+                          np.complex128(k[a]), omega, h) for a in range(d)]
+
+    def outer(parts):
+        out = np.ones((), dtype=np.complex128)
+        for a in reversed(range(d)):
+            out = np.multiply.outer(out, parts[a])
+        return out
+
+    U = outer([f[0] for f in facs])
+    Phi = [outer([facs[c][1] if c == a else facs[c][0] for c in range(d)]) for a in range(d)]
+    Psi = [outer([facs[c][2] if c == a else facs[c][0] for c in range(d)]) for a in range(d)]
+    return {"U": U, "V": -1j * omega * U, "Phi": Phi, "Psi": Psi, "omega": omega}
+
+
+def rk4_factor(x: complex) -> complex:
+    """Amplification polynomial of classic RK4 for y' = lambda y, x = lambda dt."""
+    return 1.0 + x + x * x / 2.0 + x ** 3 / 6.0 + x ** 4 / 24.0

@@ -434,3 +434,74 @@ int orc_adjoint(const orc_grid *g, const double *U0, int64_t nsteps,
     }
     return ok ? 0 : -1;
 }
+
+/* ------------------------------------------------------------------------
+ * The paper's own time integrator (Sec. 1.1.3: the runs use RK4): classic
+ * fourth-order Runge-Kutta on the first-order system
+ *   U_t = V,  V_t = A(U, Phi, Psi),  Phi_a,t = B_a(U, Phi_a),  Psi_a,t = C_a(U, Psi_a)
+ * with A, B, C the right-hand sides of Eq. (DiscretePML a, b, c).
+ * ------------------------------------------------------------------------ */
+static void orc_rk_rhs(const orc_grid *g, const double *U, const double *V,
+                       double *const Phi[3], double *const Psi[3],
+                       double *dU, double *dV, double *const dPhi[3], double *const dPsi[3])
+{
+    int64_t n = orc_ncells(g);
+    #pragma omp parallel for schedule(static)
+    for (int64_t c = 0; c < n; ++c) {
+        dU[c] = V[c];
+        dV[c] = orc_rhs_u(g, U, Phi, Psi, c);
+        for (int a = 0; a < g->ndim; ++a) {
+            dPhi[a][c] = orc_rhs_phi(g, U, Phi[a], a, c);
+            dPsi[a][c] = orc_rhs_psi(g, U, Psi[a], a, c);
+        }
+    }
+}
+
+/* nsteps RK4 steps in place on (U, V, Phi, Psi).  Returns 0 or -1 (memory). */
+int orc_rk4_run(const orc_grid *g, double *U, double *V,
+                double *const Phi[3], double *const Psi[3], int64_t nsteps)
+{
+    int64_t n = orc_ncells(g);
+    int d = g->ndim;
+    size_t bytes = (size_t)n * sizeof(double);
+    /* 4 stage derivatives k[s] and one stage state y, each (U, V, Phi_a, Psi_a) */
+    int nf = 2 + 2 * d;
+    double *buf[5][8];
+    int ok = 1;
+    for (int s = 0; s < 5; ++s)
+        for (int f = 0; f < 8; ++f) {
+            buf[s][f] = NULL;
+            if (f < nf) ok &= (buf[s][f] = malloc(bytes)) != NULL;
+        }
+    if (ok) {
+        double dt = g->dt;
+        const double cst[4] = {0.0, 0.5, 0.5, 1.0};   /* stage offsets */
+        const double wgt[4] = {1.0 / 6.0, 2.0 / 6.0, 2.0 / 6.0, 1.0 / 6.0};
+        double *y0[8] = {U, V, 0, 0, 0, 0, 0, 0};
+        for (int a = 0; a < d; ++a) { y0[2 + a] = Phi[a]; y0[2 + d + a] = Psi[a]; }
+        double **ys = buf[4];
+        for (int64_t k = 0; k < nsteps; ++k) {
+            for (int s = 0; s < 4; ++s) {
+                /* stage state y_s = y0 + cst[s] dt k_{s-1} */
+                for (int f = 0; f < nf; ++f) {
+                    if (s == 0) { memcpy(ys[f], y0[f], bytes); continue; }
+                    const double *kp = buf[s - 1][f];
+                    for (int64_t c = 0; c < n; ++c) ys[f][c] = y0[f][c] + cst[s] * dt * kp[c];
+                }
+                double *phs[3] = {0, 0, 0}, *pss[3] = {0, 0, 0}, *dph[3] = {0, 0, 0}, *dps[3] = {0, 0, 0};
+                for (int a = 0; a < d; ++a) {
+                    phs[a] = ys[2 + a]; pss[a] = ys[2 + d + a];
+                    dph[a] = buf[s][2 + a]; dps[a] = buf[s][2 + d + a];
+                }
+                orc_rk_rhs(g, ys[0], ys[1], phs, pss, buf[s][0], buf[s][1], dph, dps);
+            }
+            for (int f = 0; f < nf; ++f)
+                for (int64_t c = 0; c < n; ++c)
+                    y0[f][c] = y0[f][c] + dt * (wgt[0] * buf[0][f][c] + wgt[1] * buf[1][f][c]
+                                                + wgt[2] * buf[2][f][c] + wgt[3] * buf[3][f][c]);
+        }
+    }
+    for (int s = 0; s < 5; ++s)
+        for (int f = 0; f < 8; ++f) free(buf[s][f]);
+    return ok ? 0 : -1;
+}

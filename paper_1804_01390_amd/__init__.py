@@ -46,6 +46,8 @@ EXPORTED = [
     "dpml_multi_workspace_bytes", "dpml_multi_create", "dpml_multi_set_state", "dpml_multi_step",
     "dpml_multi_field", "dpml_multi_tiles", "dpml_multi_sync", "dpml_multi_destroy",
     "dpml_multi_last_error",
+    "dpml_rk4_workspace_bytes", "dpml_rk4_set_state", "dpml_rk4_step", "dpml_rk4_field",
+    "dpml_rk4_time_index",
 ]
 
 
@@ -110,6 +112,11 @@ def load_library():
         "dpml_multi_sync": (ctypes.c_int, [_VP]),
         "dpml_multi_destroy": (None, [_VP]),
         "dpml_multi_last_error": (ctypes.c_char_p, [_VP]),
+        "dpml_rk4_workspace_bytes": (ctypes.c_size_t, [_VP]),
+        "dpml_rk4_set_state": (ctypes.c_int, [_VP, _VP, ctypes.c_size_t, _VP, _VP]),
+        "dpml_rk4_step": (ctypes.c_int, [_VP, ctypes.c_int64]),
+        "dpml_rk4_field": (ctypes.c_int, [_VP, ctypes.c_int32, ctypes.POINTER(_VP), ctypes.c_int64 * 3]),
+        "dpml_rk4_time_index": (ctypes.c_int64, [_VP]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -290,6 +297,35 @@ class Simulation:
 
     def sync(self):
         self._check(self.lib.dpml_sync(self.handle))
+
+    # -- RK4 (the paper's integrator) -----------------------------------------
+    def rk4_set_state(self, U0, V0=None):
+        nb = int(self.lib.dpml_rk4_workspace_bytes(self.handle))
+        if nb == 0:
+            raise DpmlError(DPML_EINVAL, "RK4 needs batch == 1")
+        if self._keep.get("rk_ws") is None or self._keep["rk_ws"].numel() < nb:
+            self._keep["rk_ws"] = self.torch.empty(nb, dtype=self.torch.uint8, device=self.device)
+        ws = self._keep["rk_ws"]
+        U0 = self._dev(U0)
+        V = None if V0 is None else self._dev(V0)
+        self._keep["rk_U0"], self._keep["rk_V0"] = U0, V
+        self._check(self.lib.dpml_rk4_set_state(self.handle, ctypes.c_void_p(ws.data_ptr()), ws.numel(),
+                                                ctypes.c_void_p(U0.data_ptr()),
+                                                ctypes.c_void_p(V.data_ptr() if V is not None else 0)))
+
+    def rk4_step(self, nsteps: int = 1):
+        self._check(self.lib.dpml_rk4_step(self.handle, int(nsteps)))
+
+    def rk4_field(self, which: int):
+        ptr = _VP()
+        shape = (ctypes.c_int64 * 3)()
+        self._check(self.lib.dpml_rk4_field(self.handle, which, ctypes.byref(ptr), shape))
+        ext = [shape[a] for a in range(self.ndim)]
+        ws = self._keep["rk_ws"]
+        off = ptr.value - ws.data_ptr()
+        esize = 4 if self.code == DPML_F32 else 8
+        count = int(np.prod(ext))
+        return ws[off: off + count * esize].view(self.dtype).view(tuple(reversed(ext)))
 
     # -- adjoint --------------------------------------------------------------
     def forward_checkpointed(self, nsteps: int, ckpt_every: int = 0):

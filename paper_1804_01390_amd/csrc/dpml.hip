@@ -127,6 +127,11 @@ struct dpml {
     size_t adj_bytes = 0;
     int64_t adj_nsteps = 0, adj_every = 0;
     bool adj_ready = false;
+    // RK4 integrator state (caller-owned workspace)
+    char *rk_ws = nullptr;
+    int rk_role[4] = {0, 1, 2, 3};   // buffer sets holding Y0, YS0, YS1, S
+    int64_t rk_n = 0;
+    bool rk_set = false;
     // plane recorder
     int plane_axis = -1;
     int64_t plane_index = 0, nt_plane = 0;
@@ -1234,5 +1239,147 @@ void dpml_multi_destroy(dpml_multi_t *H)
 }
 
 const char *dpml_multi_last_error(const dpml_multi_t *H) { return H ? H->err.c_str() : g_multi_error.c_str(); }
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// RK4 (the paper's integrator) on the handle's grid
+// ---------------------------------------------------------------------------
+namespace {
+
+struct RKLayout {
+    size_t off_u[4], off_v[4], off_phi[4][3], off_psi[4][3], total;
+};
+
+RKLayout rk_layout(const Layout &L)
+{
+    RKLayout R{};
+    size_t off = 0;
+    const size_t ub = align_up((size_t)L.ncell * L.esize);
+    for (int k = 0; k < 4; ++k) {
+        R.off_u[k] = off; off += ub;
+        R.off_v[k] = off; off += ub;
+        for (int a = 0; a < L.ndim; ++a) {
+            if (L.M[a] == 0) continue;
+            const size_t ab = align_up((size_t)L.aux_elems[a] * L.esize);
+            R.off_phi[k][a] = off; off += ab;
+            R.off_psi[k][a] = off; off += ab;
+        }
+    }
+    R.total = off;
+    return R;
+}
+
+template <typename T>
+dpmlk::RKFields<T> rk_fields(dpml *H, const RKLayout &R, int set)
+{
+    dpmlk::RKFields<T> f{};
+    f.u = (T *)(H->rk_ws + R.off_u[set]);
+    f.v = (T *)(H->rk_ws + R.off_v[set]);
+    for (int a = 0; a < 3; ++a) {
+        f.phi[a] = (a < H->L.ndim && H->L.M[a] > 0) ? (T *)(H->rk_ws + R.off_phi[set][a]) : nullptr;
+        f.psi[a] = (a < H->L.ndim && H->L.M[a] > 0) ? (T *)(H->rk_ws + R.off_psi[set][a]) : nullptr;
+    }
+    return f;
+}
+
+template <typename T>
+int rk4_step_impl(dpml *H, int64_t nsteps)
+{
+    const Layout &L = H->L;
+    const RKLayout R = rk_layout(L);
+    const double cst[4] = {0.0, 0.5, 0.5, 1.0};
+    const double wgt[4] = {1.0 / 6.0, 2.0 / 6.0, 2.0 / 6.0, 1.0 / 6.0};
+    dim3 block(64, 4, 1);
+    dim3 grid((unsigned)((L.N[0] + 63) / 64), (unsigned)((L.N[1] + 3) / 4), (unsigned)(L.ndim == 3 ? L.N[2] : 1));
+    for (int64_t k = 0; k < nsteps; ++k) {
+        int *role = H->rk_role;   // role[0] = Y0, role[1] = YS0, role[2] = YS1, role[3] = S
+        for (int st = 0; st < 4; ++st) {
+            dpmlk::RKArgs<T> q{};
+            for (int a = 0; a < 3; ++a) q.ax[a] = make_axis<T>(H, a, false);
+            q.y0 = rk_fields<T>(H, R, role[0]);
+            q.yin = st == 0 ? q.y0 : rk_fields<T>(H, R, role[1 + (st - 1) % 2]);
+            q.yout = rk_fields<T>(H, R, role[1 + st % 2]);
+            q.s = rk_fields<T>(H, R, role[3]);
+            q.c2 = H->c2_field ? (const T *)H->at(L.off_c2) : nullptr;
+            q.c2_const = (T)H->c2_const;
+            q.inv_h2 = (T)(1.0 / (H->h * H->h));
+            q.inv_h = (T)(1.0 / H->h);
+            q.inv_2h = (T)(1.0 / (2.0 * H->h));
+            q.w = (T)wgt[st];
+            q.w3 = (T)wgt[3];
+            q.cdt = st < 3 ? (T)(cst[st + 1] * H->dt) : T(0);
+            q.dt = (T)H->dt;
+            q.stage = st;
+            q.nx = (int32_t)L.N[0];
+            q.ny = (int32_t)L.N[1];
+            q.nz = (int32_t)L.N[2];
+            if (L.ndim == 2)
+                hipLaunchKernelGGL((dpmlk::k_rk4_stage<T, 2>), grid, block, 0, H->stream, q);
+            else
+                hipLaunchKernelGGL((dpmlk::k_rk4_stage<T, 3>), grid, block, 0, H->stream, q);
+            HIP_TRY(H, hipGetLastError());
+        }
+        std::swap(role[0], role[3]);   // S now holds y^{n+1}
+        H->rk_n += 1;
+    }
+    return DPML_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t dpml_rk4_workspace_bytes(const dpml_t *H)
+{
+    if (!H || H->L.batch != 1) return 0;
+    return rk_layout(H->L).total;
+}
+
+int dpml_rk4_set_state(dpml_t *H, void *rk_ws, size_t bytes, const void *U0, const void *V0)
+{
+    if (!H) return DPML_EINVAL;
+    if (H->L.batch != 1) return H->fail(DPML_EINVAL, "RK4 stepping takes no batch");
+    if (!rk_ws || !U0) return H->fail(DPML_EINVAL, "rk_ws and U0 are required");
+    const RKLayout R = rk_layout(H->L);
+    if (bytes < R.total) return H->fail(DPML_ENOMEM, "RK4 workspace too small");
+    if (((uintptr_t)rk_ws) % kAlign != 0) return H->fail(DPML_ENOMEM, "RK4 workspace must be 256-byte aligned");
+    H->rk_ws = (char *)rk_ws;
+    for (int k = 0; k < 4; ++k) H->rk_role[k] = k;
+    HIP_TRY(H, hipMemsetAsync(rk_ws, 0, R.total, H->stream));
+    const size_t ub = (size_t)H->L.ncell * H->L.esize;
+    HIP_TRY(H, hipMemcpyAsync(H->rk_ws + R.off_u[0], U0, ub, hipMemcpyDeviceToDevice, H->stream));
+    if (V0) HIP_TRY(H, hipMemcpyAsync(H->rk_ws + R.off_v[0], V0, ub, hipMemcpyDeviceToDevice, H->stream));
+    H->rk_n = 0;
+    H->rk_set = true;
+    return DPML_OK;
+}
+
+int dpml_rk4_step(dpml_t *H, int64_t nsteps)
+{
+    if (!H) return DPML_EINVAL;
+    if (nsteps < 0) return H->fail(DPML_EINVAL, "nsteps < 0");
+    if (!H->rk_set) return H->fail(DPML_ESTATE, "dpml_rk4_set_state has not been called");
+    return H->L.dtype == DPML_F32 ? rk4_step_impl<float>(H, nsteps) : rk4_step_impl<double>(H, nsteps);
+}
+
+int dpml_rk4_field(dpml_t *H, int32_t which, void **ptr, int64_t shape[3])
+{
+    if (!H || !ptr || !shape) return DPML_EINVAL;
+    if (!H->rk_set) return H->fail(DPML_ESTATE, "dpml_rk4_set_state has not been called");
+    const Layout &L = H->L;
+    const RKLayout R = rk_layout(L);
+    const int set = H->rk_role[0];
+    for (int a = 0; a < 3; ++a) shape[a] = L.N[a];
+    if (which == DPML_FIELD_U) { *ptr = H->rk_ws + R.off_u[set]; return DPML_OK; }
+    if (which == 1) { *ptr = H->rk_ws + R.off_v[set]; return DPML_OK; }
+    const int a = (which - 2) / 2;
+    if (which < 2 || a >= L.ndim || L.M[a] == 0) return H->fail(DPML_EINVAL, "no such field");
+    shape[a] = L.M[a] + 1;
+    *ptr = H->rk_ws + ((which % 2 == 0) ? R.off_phi[set][a] : R.off_psi[set][a]);
+    return DPML_OK;
+}
+
+int64_t dpml_rk4_time_index(const dpml_t *H) { return H && H->rk_set ? H->rk_n : -1; }
 
 }  // extern "C"

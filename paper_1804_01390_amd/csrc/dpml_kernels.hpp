@@ -655,4 +655,102 @@ __global__ void __launch_bounds__(256) k_gather_scaled(const T *__restrict__ u, 
     out[order[q] * nt + n] = amp * u[cells[q]];
 }
 
+// ---------------------------------------------------------------------------
+// The paper's own integrator: classic RK4 on (U, V = U_t, Phi_a, Psi_a) with
+// the right-hand sides of Eq. (DiscretePML a, b, c).  One launch per stage:
+//   k      = f(Y_in)                       (Y_in = Y0 at stage 0)
+//   S      = w_0 k (stage 0), S + w_s k (stages 1, 2)
+//   Y_out  = Y0 + (c_{s+1} dt) k           (stages 0..2)
+//   Y_new  = Y0 + dt (S + w_3 k)           (stage 3, written over S)
+// with c = (0, 1/2, 1/2, 1), w = (1/6, 2/6, 2/6, 1/6).
+// ---------------------------------------------------------------------------
+template <typename T>
+struct RKFields {
+    T *u, *v;
+    T *phi[3], *psi[3];
+};
+
+template <typename T>
+struct RKArgs {
+    Axis<T> ax[3];          // sig and geometry only
+    RKFields<T> yin, y0, s, yout;
+    const T *c2;
+    T c2_const, inv_h2, inv_h, inv_2h;
+    T w;                    // w_s
+    T w3;                   // w_3 (stage 3)
+    T cdt;                  // c_{s+1} dt (stages 0..2)
+    T dt;
+    int32_t stage;
+    int32_t nx, ny, nz;
+};
+
+template <typename T, int D>
+__global__ void __launch_bounds__(256) k_rk4_stage(RKArgs<T> p)
+{
+    const int x = blockIdx.x * 64 + threadIdx.x;
+    const int y = blockIdx.y * 4 + threadIdx.y;
+    const int z = D == 3 ? (int)blockIdx.z : 0;
+    if (x >= p.nx || y >= p.ny) return;
+    const int nx = p.nx, ny = p.ny, nz = p.nz;
+    const int64_t sy = nx, sz = (int64_t)nx * ny;
+    const int64_t idx = (int64_t)z * sz + (int64_t)y * sy + x;
+    const int coord[3] = {x, y, z};
+    const int64_t stride[3] = {1, sy, sz};
+    const int ext[3] = {nx, ny, nz};
+    const T *U = p.yin.u;
+    const T uc = U[idx];
+    T lap = T(0), damp = T(0);
+    T dphi[3] = {T(0), T(0), T(0)}, dpsi[3] = {T(0), T(0), T(0)};
+    int jj[3] = {1 << 30, 1 << 30, 1 << 30};
+    int64_t cidx[3] = {0, 0, 0};
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+        const int i = coord[a];
+        const int64_t cm = idx + (int64_t)(wrap_dec(i, ext[a]) - i) * stride[a];
+        const int64_t cp = idx + (int64_t)(wrap_inc(i, ext[a]) - i) * stride[a];
+        const T um = U[cm], up = U[cp];
+        lap += ((um - T(2) * uc) + up) * p.inv_h2;
+        const Axis<T> &A = p.ax[a];
+        if (A.M > 0) {
+            const int j = band_coord(A, i);
+            if (j <= A.M) {
+                int64_t base, cstr;
+                if (a == 0) { base = ((int64_t)z * ny + y) * (A.M + 1); cstr = 1; }
+                else if (a == 1) { base = (int64_t)z * (A.M + 1) * nx + x; cstr = nx; }
+                else { base = (int64_t)y * nx + x; cstr = (int64_t)nx * ny; }
+                const int64_t c = base + (int64_t)j * cstr;
+                const T *phi = p.yin.phi[a], *psi = p.yin.psi[a];
+                const T sg = A.sig[j];
+                const T sl = j > 0 ? A.sig[j - 1] : T(0);
+                const T phi_l = j > 0 ? phi[c - cstr] : T(0);
+                const T psi_r = j < A.M ? psi[c + cstr] : T(0);
+                damp += (sg * psi_r - sl * phi_l) * p.inv_h;
+                const T grad = (up - um) * p.inv_2h;
+                dphi[a] = T(-0.5) * (sl * phi_l + sg * phi[c]) - grad;
+                dpsi[a] = T(-0.5) * (sl * psi[c] + sg * psi_r) - grad;
+                jj[a] = j;
+                cidx[a] = c;
+            }
+        }
+    }
+    const T ku = p.yin.v[idx];
+    const T kv = (p.c2 ? p.c2[idx] : p.c2_const) * lap + damp;
+    // combine one field value: k is its derivative, c its index
+    auto combine = [&](const T *y0, T *sacc, T *yout, int64_t c, T k) {
+        if (p.stage == 0) sacc[c] = p.w * k;
+        else if (p.stage < 3) sacc[c] = sacc[c] + p.w * k;
+        else sacc[c] = y0[c] + p.dt * (sacc[c] + p.w3 * k);
+        if (p.stage < 3) yout[c] = y0[c] + p.cdt * k;
+    };
+    combine(p.y0.u, p.s.u, p.yout.u, idx, ku);
+    combine(p.y0.v, p.s.v, p.yout.v, idx, kv);
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+        const int j = jj[a];
+        if (j > p.ax[a].M) continue;
+        if (j < p.ax[a].M) combine(p.y0.phi[a], p.s.phi[a], p.yout.phi[a], cidx[a], dphi[a]);
+        if (j > 0) combine(p.y0.psi[a], p.s.psi[a], p.yout.psi[a], cidx[a], dpsi[a]);
+    }
+}
+
 }  // namespace dpmlk

@@ -265,3 +265,55 @@ def batch2d(count: int = 256, seed: int = 0, steps: int = 1500, smin: int = 256,
         w.name = "batch%d_%d_m%d" % (b, sides[b], ms[b])
         out.append(w)
     return out
+
+
+@dataclass
+class ShotWorkload:
+    """A batch of shots on one 2D grid for the adjoint: shared c^2 (model and
+    'true'), one Ricker source per shot, receivers shared by all shots."""
+    n: List[int]
+    lo: List[int]
+    hi: List[int]
+    h: float
+    dt: float
+    steps: int
+    sigma: List[np.ndarray]
+    c2_model: np.ndarray
+    c2_true: np.ndarray
+    sources: List[List[int]]        # per shot, flat cells within one member
+    receivers: List[int]            # flat cells within one member
+    wavelets: np.ndarray            # [shots][steps]
+
+    @property
+    def N(self) -> List[int]:
+        return [self.lo[a] + self.n[a] + self.hi[a] for a in range(len(self.n))]
+
+    @property
+    def cells(self) -> int:
+        return int(np.prod(self.N))
+
+
+def shots2d(n: int = 1024, m: int = 32, shots: int = 32, steps: int = 3000, seed: int = 0,
+            src_row: int = 16, rec_row: int = 24, spacing: int = 32, ppw: float = 15.0,
+            count: int = 32, wmin: float = 20.0, wmax: float = 80.0, margin: int = 8) -> ShotWorkload:
+    """2D, n^2 interior + m-cell layer, c^2 = 1 + 0.5 g (g: ``count`` seeded
+    Gaussians of widths U(wmin, wmax), scaled to max|g| = 1, held at 0 within
+    ``margin`` cells of the layer); a second seed gives the 'true' c^2.
+    ``shots`` Ricker sources on interior row ``src_row`` at x = 16 + spacing*s
+    (f = 1/(ppw h), delay 1.5/f), receivers on every interior cell of row
+    ``rec_row``, dt = 0.5 h / c_max.  Defaults: the 1024^2 + 32-cell,
+    32-shot, 3000-step adjoint case."""
+    rng = np.random.default_rng(seed)
+    c2m = smooth_c2([n, n], [m, m], [m, m], count, wmin, wmax, 0.5, margin, rng)
+    c2t = smooth_c2([n, n], [m, m], [m, m], count, wmin, wmax, 0.5, margin,
+                    np.random.default_rng(seed + 1))
+    h = 1.0
+    cmax = math.sqrt(max(float(np.max(c2m)), float(np.max(c2t))))
+    dt = 0.5 * h / cmax
+    sig = sigma_ramp(n, m, m, 2.0 / h)
+    N = [m + n + m] * 2
+    srcs = [[flat_index(N, [m + 16 + spacing * s, m + src_row])] for s in range(shots)]
+    rec = [flat_index(N, [m + x, m + rec_row]) for x in range(n)]
+    f = 1.0 / (ppw * h)
+    wav = np.vstack([ricker(steps, dt, f, 1.5 / f) for _ in range(shots)])
+    return ShotWorkload([n, n], [m, m], [m, m], h, dt, steps, [sig, sig.copy()], c2m, c2t, srcs, rec, wav)
