@@ -95,6 +95,14 @@ typedef struct dpml_grid {
                         layout below; cell indices passed to dpml_inject /
                         dpml_record address the whole batch
                         (member * prod N + cell). */
+    int32_t walls[3];/* per axis: 0 = periodic wrap (the layer sides form one
+                        band, the paper's runs); 1 = reflecting walls: U, Phi
+                        and Psi vanish on ghost cells -1 and N, and the ghost
+                        edge [-1, 0] is undamped (the truncation the paper
+                        bounds with Eq. (IntroReflectedDecayBound)).  Walls
+                        are supported by dpml_step only (not by the adjoint,
+                        RK4 or multi-problem paths: DPML_EINVAL there). */
+    int32_t reserved;
 } dpml_grid_t;
 
 typedef struct dpml dpml_t;

@@ -59,6 +59,8 @@ class _Grid(ctypes.Structure):
         ("dt", ctypes.c_double),
         ("c2", ctypes.POINTER(ctypes.c_double)),
         ("sigma", ctypes.POINTER(ctypes.c_double) * 3),
+        ("wall", ctypes.c_int32 * 3),
+        ("pad2_", ctypes.c_int32),
     ]
 
 
@@ -113,6 +115,7 @@ class Grid:
     dt: float
     sigma: Sequence[Optional[np.ndarray]] = field(default_factory=list)
     c2: Optional[np.ndarray] = None
+    walls: Sequence[bool] = ()     # per axis: True = reflecting walls, else periodic
 
     @property
     def ndim(self) -> int:
@@ -130,6 +133,8 @@ class Grid:
             g.N[a] = ext[a]
         g.h = float(self.h)
         g.dt = float(self.dt)
+        for a in range(3):
+            g.wall[a] = 1 if (a < len(self.walls) and self.walls[a]) else 0
         keep = []
         if self.c2 is not None:
             c2 = np.ascontiguousarray(self.c2, dtype=np.float64)

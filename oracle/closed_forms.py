@@ -125,7 +125,7 @@ def green_1d_cfl1(n: int, i: np.ndarray) -> np.ndarray:
 
 
 def leapfrog_energy(U_new: np.ndarray, U_old: np.ndarray, h: float, dt: float,
-                    c2=None, box=None) -> float:
+                    c2=None, box=None, walls=False) -> float:
     """Spring-mass energy of Eq. (Energy) in the time-staggered form that the
     leapfrog scheme conserves (periodic grid, no damping):
     E^{n+1/2} = 1/2 sum |(U^{n+1} - U^n)/dt|^2 / c^2
@@ -134,6 +134,19 @@ def leapfrog_energy(U_new: np.ndarray, U_old: np.ndarray, h: float, dt: float,
     physical domain) -- then it is a diagnostic, not a conserved quantity."""
     v = (U_new - U_old) / dt
     kin = v * v if c2 is None else v * v / c2
+    if walls:
+        # Dirichlet ghosts at -1 and N on every axis: sum over all edges,
+        # including the two boundary edges of each line
+        if box is not None:
+            raise ValueError("box and walls are exclusive")
+        pot = 0.0
+        for ax in range(U_new.ndim):
+            pad = [(0, 0)] * U_new.ndim
+            pad[ax] = (1, 1)
+            dn = np.diff(np.pad(U_new, pad), axis=ax)
+            do = np.diff(np.pad(U_old, pad), axis=ax)
+            pot += float(np.sum(dn * do)) / (h * h)
+        return 0.5 * float(np.sum(kin)) + 0.5 * pot
     pot = np.zeros_like(U_new)
     for ax in range(U_new.ndim):
         dn = np.roll(U_new, -1, axis=ax) - U_new

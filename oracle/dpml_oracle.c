@@ -22,8 +22,11 @@
  *
  * The equations are evaluated at EVERY cell of the grid (the paper states
  * them on all of Z^d; the restriction of Phi/Psi to the layer in Sec. 1.1.2
- * is an economy, not part of the definition).  The truncation is periodic
- * (Sec. 1.1.3, the runs of Figs. 2 and 3).  The coefficient c^2 multiplies the
+ * is an economy, not part of the definition).  Each axis is truncated either
+ * periodically (Sec. 1.1.3, the runs of Figs. 2 and 3) or by reflecting walls
+ * (the truncation the paper analyses with Eq. (IntroReflectedDecayBound)):
+ * U, Phi and Psi vanish on the ghost cells -1 and N, and the ghost edge
+ * [-1, 0] carries no damping.  The coefficient c^2 multiplies the
  * Laplacian only; it must equal 1 wherever a damping term acts (the paper
  * uses unit wave speed).
  *
@@ -66,6 +69,10 @@ typedef struct {
     double dt;               /* time step */
     const double *c2;        /* NULL: c^2 = 1; else one value per cell */
     const double *sigma[3];  /* sigma_a(i_a), N[a] values each; NULL = all 0 */
+    int32_t wall[3];         /* 0: periodic axis; 1: reflecting walls, i.e. U, Phi,
+                                Psi vanish on ghost cells -1 and N[a], and the
+                                ghost edge [-1, 0] carries no damping */
+    int32_t pad2_;
 } orc_grid;
 
 static int64_t orc_wrap(int64_t i, int64_t n)
@@ -77,7 +84,14 @@ static int64_t orc_wrap(int64_t i, int64_t n)
 
 static double orc_sigma(const orc_grid *g, int a, int64_t i)
 {
+    if (i < 0) return 0.0;          /* ghost edge outside a wall */
     return g->sigma[a] ? g->sigma[a][i] : 0.0;
+}
+
+/* Value of array X at flat index c, or 0 for a ghost cell (c < 0). */
+static double orc_at(const double *X, int64_t c)
+{
+    return c < 0 ? 0.0 : X[c];
 }
 
 /* Decompose a flat cell index into per-axis indices. */
@@ -95,11 +109,21 @@ static int64_t orc_stride(const orc_grid *g, int a)
     return g->N[0] * g->N[1];
 }
 
-/* Flat index of the cell one step along axis a (dir = +1 or -1), periodic. */
+/* Flat index of the cell one step along axis a (dir = +1 or -1): periodic,
+ * or -1 (a ghost cell) past a wall. */
 static int64_t orc_shift(const orc_grid *g, int64_t c, const int64_t ii[3], int a, int dir)
 {
-    int64_t j = orc_wrap(ii[a] + dir, g->N[a]);
+    int64_t t = ii[a] + dir;
+    if (g->wall[a] && (t < 0 || t >= g->N[a])) return -1;
+    int64_t j = orc_wrap(t, g->N[a]);
     return c + (j - ii[a]) * orc_stride(g, a);
+}
+
+/* Index of the edge left of cell i along axis a: i-1, periodic or -1 at a wall. */
+static int64_t orc_left(const orc_grid *g, int a, int64_t i)
+{
+    if (g->wall[a] && i == 0) return -1;
+    return orc_wrap(i - 1, g->N[a]);
 }
 
 static int64_t orc_ncells(const orc_grid *g)
@@ -118,12 +142,12 @@ static double orc_rhs_u(const orc_grid *g, const double *U,
     for (int a = 0; a < g->ndim; ++a) {
         int64_t cp = orc_shift(g, c, ii, a, +1);
         int64_t cm = orc_shift(g, c, ii, a, -1);
-        int64_t im = orc_wrap(ii[a] - 1, g->N[a]);
-        lap += (U[cm] - 2.0 * U[c] + U[cp]) / (g->h * g->h);
+        int64_t im = orc_left(g, a, ii[a]);
+        lap += (orc_at(U, cm) - 2.0 * U[c] + orc_at(U, cp)) / (g->h * g->h);
         if (Phi && Psi) {
             double s_here = orc_sigma(g, a, ii[a]);   /* sigma_a        */
             double s_left = orc_sigma(g, a, im);      /* tau^-1 sigma_a */
-            damp += (s_here * Psi[a][cp] - s_left * Phi[a][cm]) / g->h;
+            damp += (s_here * orc_at(Psi[a], cp) - s_left * orc_at(Phi[a], cm)) / g->h;
         }
     }
     return (g->c2 ? g->c2[c] : 1.0) * lap + damp;
@@ -137,11 +161,11 @@ static double orc_rhs_phi(const orc_grid *g, const double *U, const double *Phi_
     orc_coords(g, c, ii);
     int64_t cp = orc_shift(g, c, ii, a, +1);
     int64_t cm = orc_shift(g, c, ii, a, -1);
-    int64_t im = orc_wrap(ii[a] - 1, g->N[a]);
+    int64_t im = orc_left(g, a, ii[a]);
     double s_here = orc_sigma(g, a, ii[a]);
     double s_left = orc_sigma(g, a, im);
-    return -0.5 * (s_left * Phi_a[cm] + s_here * Phi_a[c])
-           - (U[cp] - U[cm]) / (2.0 * g->h);
+    return -0.5 * (s_left * orc_at(Phi_a, cm) + s_here * Phi_a[c])
+           - (orc_at(U, cp) - orc_at(U, cm)) / (2.0 * g->h);
 }
 
 /* Right-hand side of Eq. (DiscretePML c) for Psi_a at cell c. */
@@ -152,11 +176,11 @@ static double orc_rhs_psi(const orc_grid *g, const double *U, const double *Psi_
     orc_coords(g, c, ii);
     int64_t cp = orc_shift(g, c, ii, a, +1);
     int64_t cm = orc_shift(g, c, ii, a, -1);
-    int64_t im = orc_wrap(ii[a] - 1, g->N[a]);
+    int64_t im = orc_left(g, a, ii[a]);
     double s_here = orc_sigma(g, a, ii[a]);
     double s_left = orc_sigma(g, a, im);
-    return -0.5 * (s_left * Psi_a[c] + s_here * Psi_a[cp])
-           - (U[cp] - U[cm]) / (2.0 * g->h);
+    return -0.5 * (s_left * Psi_a[c] + s_here * orc_at(Psi_a, cp))
+           - (orc_at(U, cp) - orc_at(U, cm)) / (2.0 * g->h);
 }
 
 /* Evaluate A(U, Phi, Psi) of Eq. (DiscretePML a) on the whole grid. */
@@ -303,7 +327,7 @@ int orc_wave_run(const orc_grid *g, double *U, double *Uprev, int64_t nsteps)
             for (int a = 0; a < g->ndim; ++a) {
                 int64_t cp = orc_shift(g, c, ii, a, +1);
                 int64_t cm = orc_shift(g, c, ii, a, -1);
-                lap += (un[cm] - 2.0 * un[c] + un[cp]) / (g->h * g->h);
+                lap += (orc_at(un, cm) - 2.0 * un[c] + orc_at(un, cp)) / (g->h * g->h);
             }
             uw[c] = 2.0 * un[c] - uo[c] + dt2 * (g->c2 ? g->c2[c] : 1.0) * lap;
         }
@@ -343,7 +367,7 @@ static double orc_lap(const orc_grid *g, const double *U, int64_t c)
     for (int a = 0; a < g->ndim; ++a) {
         int64_t cp = orc_shift(g, c, ii, a, +1);
         int64_t cm = orc_shift(g, c, ii, a, -1);
-        lap += (U[cm] - 2.0 * U[c] + U[cp]) / (g->h * g->h);
+        lap += (orc_at(U, cm) - 2.0 * U[c] + orc_at(U, cp)) / (g->h * g->h);
     }
     return lap;
 }
@@ -407,14 +431,15 @@ int orc_adjoint(const orc_grid *g, const double *U0, int64_t nsteps,
                 for (int a = 0; a < d; ++a) {
                     int64_t cp = orc_shift(g, c, ii, a, +1);
                     int64_t cm = orc_shift(g, c, ii, a, -1);
-                    int64_t im = orc_wrap(ii[a] - 1, g->N[a]);
+                    int64_t im = orc_left(g, a, ii[a]);
                     double s_here = orc_sigma(g, a, ii[a]);
                     double s_left = orc_sigma(g, a, im);
-                    v += dt * ((p[a][cp] + q[a][cp]) - (p[a][cm] + q[a][cm])) / (2.0 * g->h);
-                    pn[a][c] = p[a][c] - 0.5 * dt * s_here * (p[a][c] + p[a][cp])
-                               - dt2 / g->h * s_here * a_cur[cp];
-                    qn[a][c] = q[a][c] - 0.5 * dt * s_left * (q[a][c] + q[a][cm])
-                               + dt2 / g->h * s_left * a_cur[cm];
+                    v += dt * ((orc_at(p[a], cp) + orc_at(q[a], cp)) - (orc_at(p[a], cm) + orc_at(q[a], cm)))
+                         / (2.0 * g->h);
+                    pn[a][c] = p[a][c] - 0.5 * dt * s_here * (p[a][c] + orc_at(p[a], cp))
+                               - dt2 / g->h * s_here * orc_at(a_cur, cp);
+                    qn[a][c] = q[a][c] - 0.5 * dt * s_left * (q[a][c] + orc_at(q[a], cm))
+                               + dt2 / g->h * s_left * orc_at(a_cur, cm);
                 }
                 a_new[c] = v;
             }

@@ -60,7 +60,7 @@ class DpmlError(RuntimeError):
 class GridT(ctypes.Structure):
     _fields_ = [("ndim", ctypes.c_int32), ("dtype", ctypes.c_int32),
                 ("n", ctypes.c_int64 * 3), ("lo", ctypes.c_int32 * 3), ("hi", ctypes.c_int32 * 3),
-                ("batch", ctypes.c_int64)]
+                ("batch", ctypes.c_int64), ("walls", ctypes.c_int32 * 3), ("reserved", ctypes.c_int32)]
 
 
 _lib = None
@@ -126,11 +126,13 @@ def load_library():
     return lib
 
 
-def _grid(n, lo, hi, dtype_code, batch: int = 1) -> GridT:
+def _grid(n, lo, hi, dtype_code, batch: int = 1, walls=()) -> GridT:
     g = GridT()
     g.ndim = len(n)
     g.dtype = dtype_code
     g.batch = int(batch)
+    for a in range(3):
+        g.walls[a] = 1 if (a < len(walls) and walls[a]) else 0
     for a in range(3):
         g.n[a] = int(n[a]) if a < len(n) else 1
         g.lo[a] = int(lo[a]) if a < len(n) else 0
@@ -154,11 +156,12 @@ class Simulation:
     dtype     : torch.float32 or torch.float64
     batch     : independent problems (shots) sharing c2 and sigma; fields are
                 then [batch, *reversed(N)] and cell indices address the batch
+    walls     : per axis, True for reflecting walls instead of periodic wrap
     """
 
     def __init__(self, n: Sequence[int], lo: Sequence[int], hi: Sequence[int], h: float, dt: float,
                  sigma: Sequence[Optional[np.ndarray]], c2=1.0, dtype=None, device=None,
-                 batch: int = 1):
+                 batch: int = 1, walls=()):
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("paper_1804_01390_amd needs a ROCm GPU; none is visible")
@@ -179,7 +182,8 @@ class Simulation:
         self.h, self.dt = float(h), float(dt)
         c2a = np.ascontiguousarray(np.asarray(c2, dtype=np.float64).reshape(-1))
         field = c2a.size != 1
-        g = _grid(self.n, self.lo, self.hi, self.code, self.batch)
+        self.walls = tuple(bool(w) for w in walls)
+        g = _grid(self.n, self.lo, self.hi, self.code, self.batch, self.walls)
         nbytes = self.lib.dpml_workspace_bytes(ctypes.byref(g), 1 if field else 0)
         if nbytes == 0:
             raise DpmlError(DPML_EINVAL, "invalid grid")

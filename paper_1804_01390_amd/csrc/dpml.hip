@@ -36,6 +36,7 @@ struct Layout {
     int32_t lo[3] = {0, 0, 0};
     int32_t hi[3] = {0, 0, 0};
     int32_t M[3] = {0, 0, 0};
+    int32_t wall[3] = {0, 0, 0};        // reflecting walls instead of periodic wrap
     int64_t ncell = 0;                  // cells of one problem
     int64_t batch = 1;                  // independent problems sharing c^2 and sigma
     int64_t aux_elems[3] = {0, 0, 0};   // elements of one compact aux array (one problem)
@@ -71,6 +72,8 @@ std::string make_layout(const dpml_grid_t *g, bool c2_field, Layout &L)
             if (L.N[a] < 3) return "each axis needs at least 3 cells";
             if (L.N[a] > (int64_t)1 << 30) return "axis too long";
             L.M[a] = g->lo[a] + g->hi[a];
+            if (g->walls[a] != 0 && g->walls[a] != 1) return "walls[a] must be 0 or 1";
+            L.wall[a] = g->walls[a];
         }
         L.ncell *= L.N[a];
     }
@@ -166,6 +169,7 @@ dpmlk::Axis<T> make_axis(dpml *H, int a, bool next)
     A.b = (int32_t)(L.lo[a] + L.n[a]);
     A.M = a < L.ndim ? L.M[a] : 0;
     A.hi = L.hi[a];
+    A.wall = a < L.ndim ? L.wall[a] : 0;
     if (A.M > 0) {
         const int in = H->cur, out = 1 - H->cur;
         A.sig = (const T *)H->at(L.off_sig[a]);
@@ -325,11 +329,11 @@ int set_state_impl(dpml *H, const void *U0, const void *V0)
     if (L.ndim == 2)
         hipLaunchKernelGGL((dpmlk::k_start<T, 2>), grid, block, 0, H->stream, (const T *)U0, (const T *)V0,
                            (T *)H->u_old, c2, (T)H->c2_const, inv_h2, (T)H->dt, half_dt2,
-                           (int)L.N[0], (int)L.N[1], (int)L.N[2]);
+                           (int)L.N[0], (int)L.N[1], (int)L.N[2], L.wall[0] | (L.wall[1] << 1) | (L.wall[2] << 2));
     else
         hipLaunchKernelGGL((dpmlk::k_start<T, 3>), grid, block, 0, H->stream, (const T *)U0, (const T *)V0,
                            (T *)H->u_old, c2, (T)H->c2_const, inv_h2, (T)H->dt, half_dt2,
-                           (int)L.N[0], (int)L.N[1], (int)L.N[2]);
+                           (int)L.N[0], (int)L.N[1], (int)L.N[2], L.wall[0] | (L.wall[1] << 1) | (L.wall[2] << 2));
     HIP_TRY(H, hipGetLastError());
     H->n = 0;
     H->state_set = true;
@@ -900,6 +904,7 @@ int dpml_forward_checkpointed(dpml_t *H, int64_t nsteps, int64_t ckpt_every, voi
     if (!H) return DPML_EINVAL;
     if (nsteps < 1 || ckpt_every < 1 || !adj_ws) return H->fail(DPML_EINVAL, "bad checkpoint arguments");
     if (!H->state_set || H->n != 0) return H->fail(DPML_ESTATE, "the forward run must start at time index 0");
+    if (H->L.wall[0] || H->L.wall[1] || H->L.wall[2]) return H->fail(DPML_EINVAL, "the adjoint supports periodic grids only");
     if (bytes < adj_layout(H, nsteps, ckpt_every).total) return H->fail(DPML_ENOMEM, "adjoint workspace too small");
     if (((uintptr_t)adj_ws) % kAlign != 0) return H->fail(DPML_ENOMEM, "adjoint workspace must be 256-byte aligned");
     H->adj_ws = (char *)adj_ws;
@@ -981,6 +986,7 @@ std::string multi_layout(int64_t count, const dpml_grid_t *grids, MultiLayout &M
         if (grids[p].ndim != 2) return "multi-problem stepping is 2D only";
         if (grids[p].dtype != dtype) return "all problems must share one dtype";
         if (grids[p].batch > 1) return "multi-problem grids take no batch";
+        if (grids[p].walls[0] || grids[p].walls[1]) return "multi-problem grids are periodic";
         std::string e = make_layout(&grids[p], false, M.L[p]);
         if (!e.empty()) return "problem " + std::to_string(p) + ": " + e;
         M.base[p] = off;
@@ -1340,6 +1346,7 @@ int dpml_rk4_set_state(dpml_t *H, void *rk_ws, size_t bytes, const void *U0, con
 {
     if (!H) return DPML_EINVAL;
     if (H->L.batch != 1) return H->fail(DPML_EINVAL, "RK4 stepping takes no batch");
+    if (H->L.wall[0] || H->L.wall[1] || H->L.wall[2]) return H->fail(DPML_EINVAL, "RK4 stepping supports periodic grids only");
     if (!rk_ws || !U0) return H->fail(DPML_EINVAL, "rk_ws and U0 are required");
     const RKLayout R = rk_layout(H->L);
     if (bytes < R.total) return H->fail(DPML_ENOMEM, "RK4 workspace too small");

@@ -37,6 +37,8 @@ struct Axis {
     int32_t b;        // first band cell (lo + n)
     int32_t M;        // band thickness lo + hi (0: no layer on this axis)
     int32_t hi;       // N - b
+    int32_t wall;     // 0: periodic; 1: reflecting walls (ghost cells -1, N hold 0)
+    int32_t pad_;
     const T *sig;     // sig[j], j in [0, M]
     const T *phi;     // Phi_a^n   (compact)
     const T *psi;     // Psi_a^n   (compact)
@@ -108,10 +110,14 @@ __device__ __forceinline__ T layer_terms(const Axis<T> &A, int j, int64_t cbase,
                                          T um, T up, T dt, T inv_2h)
 {
     const int64_t c = cbase + (int64_t)j * cstr;
-    const T s = A.sig[j];                              // sigma_a(i)
-    const T sl = j > 0 ? A.sig[j - 1] : T(0);          // sigma_a(i-1)
-    const T phi_l = j > 0 ? A.phi[c - cstr] : T(0);    // Phi_a(i-e)
-    const T psi_r = j < A.M ? A.psi[c + cstr] : T(0);  // Psi_a(i+e)
+    // with walls, slot hi is cell 0 (its left neighbour is a ghost and the
+    // ghost edge is undamped) and slot hi-1 is cell N-1 (right neighbour ghost)
+    const bool left_ghost = A.wall && j == A.hi;
+    const bool right_ghost = A.wall && j == A.hi - 1;
+    const T s = A.sig[j];                                              // sigma_a(i)
+    const T sl = (j > 0 && !left_ghost) ? A.sig[j - 1] : T(0);         // sigma_a(i-1)
+    const T phi_l = (j > 0 && !left_ghost) ? A.phi[c - cstr] : T(0);   // Phi_a(i-e)
+    const T psi_r = (j < A.M && !right_ghost) ? A.psi[c + cstr] : T(0); // Psi_a(i+e)
     const T grad = (up - um) * inv_2h;
     if (j < A.M) {
         const T phi_c = A.phi[c];
@@ -187,13 +193,15 @@ __global__ void __launch_bounds__(256) k_step_cell(StepArgs<T> p)
     T uzm = T(0), uzp = T(0);
     if (D == 3) {
         const int zm = wrap_dec(z, p.nz), zp = wrap_inc(z, p.nz);
-        uzm = u[((int64_t)zm * ny + y) * nx + x];
-        uzp = u[((int64_t)zp * ny + y) * nx + x];
+        uzm = (p.ax[2].wall && z == 0) ? T(0) : u[((int64_t)zm * ny + y) * nx + x];
+        uzp = (p.ax[2].wall && z == p.nz - 1) ? T(0) : u[((int64_t)zp * ny + y) * nx + x];
     }
     const int64_t plane = (int64_t)z * ny * nx;
-    const T r = cell_update<T, D>(p, x, y, z, idx, u[idx], u[row + xm], u[row + xp],
-                                  u[plane + (int64_t)ym * nx + x], u[plane + (int64_t)yp * nx + x],
-                                  uzm, uzp, p.uo[idx]);
+    const T uxm = (p.ax[0].wall && x == 0) ? T(0) : u[row + xm];
+    const T uxp = (p.ax[0].wall && x == p.nx - 1) ? T(0) : u[row + xp];
+    const T uym = (p.ax[1].wall && y == 0) ? T(0) : u[plane + (int64_t)ym * nx + x];
+    const T uyp = (p.ax[1].wall && y == p.ny - 1) ? T(0) : u[plane + (int64_t)yp * nx + x];
+    const T r = cell_update<T, D>(p, x, y, z, idx, u[idx], uxm, uxp, uym, uyp, uzm, uzp, p.uo[idx]);
     p.uo[idx] = r;
     if (p.hist) p.hist[idx] = r;
 }
@@ -261,18 +269,32 @@ __device__ __forceinline__ void march2d_tile(const StepArgs<T> &p, int tx, int t
     const T *u = p.u;
     const int xl = wrap_dec(x0, nx);          // left neighbour of the vector
     const int xr = wrap_inc(x0 + VX - 1, nx); // right neighbour of the vector
+    const bool lghost = p.ax[0].wall && x0 == 0;
+    const bool rghost = p.ax[0].wall && x0 + VX == nx;
+    const bool wy = p.ax[1].wall;
+    // row yy of U^n (a zero row past a wall)
+    auto nb_row = [&](int yy) -> Row<T, VX> {
+        if (wy && (yy < 0 || yy >= ny)) {
+            Row<T, VX> z;
+#pragma unroll
+            for (int k = 0; k < VX; ++k) z.v[k] = T(0);
+            return z;
+        }
+        const int w = yy < 0 ? yy + ny : (yy >= ny ? yy - ny : yy);
+        return load_row<T, VX>(u + (int64_t)w * nx + x0);
+    };
 
-    Row<T, VX> um = load_row<T, VX>(u + (int64_t)wrap_dec(y0, ny) * nx + x0);
+    Row<T, VX> um = nb_row(y0 - 1);
     Row<T, VX> uc = load_row<T, VX>(u + (int64_t)y0 * nx + x0);
-    Row<T, VX> up = load_row<T, VX>(u + (int64_t)wrap_inc(y0, ny) * nx + x0);
+    Row<T, VX> up = nb_row(y0 + 1);
     for (int y = y0; y < y1; ++y) {
         const int64_t row = (int64_t)y * nx;
         // prefetch the row after next while this one is computed
         Row<T, VX> upp = up;
-        if (y + 1 < y1) upp = load_row<T, VX>(u + (int64_t)wrap_inc(y + 1, ny) * nx + x0);
+        if (y + 1 < y1) upp = nb_row(y + 2);
         const Row<T, VX> old = load_row<T, VX>(p.uo + row + x0);
-        const T left = u[row + xl];
-        const T right = u[row + xr];
+        const T left = lghost ? T(0) : u[row + xl];
+        const T right = rghost ? T(0) : u[row + xr];
         Row<T, VX> out;
 #pragma unroll
         for (int k = 0; k < VX; ++k) {
@@ -342,6 +364,8 @@ __global__ void __launch_bounds__(256) k_step_march3d(StepArgs<T> p)
     const int z0 = tz * p.tile_rows;
     const int z1 = min(z0 + p.tile_rows, nz);
     const int xm = wrap_dec(x, nx), xp = wrap_inc(x, nx);
+    const bool xlg = p.ax[0].wall && x == 0, xrg = p.ax[0].wall && x == nx - 1;
+    const bool wyy = p.ax[1].wall, wz = p.ax[2].wall;
     const T *u = p.u;
     int yy[RY];
     bool ok[RY];
@@ -351,26 +375,27 @@ __global__ void __launch_bounds__(256) k_step_march3d(StepArgs<T> p)
         yy[r] = (ty * 4 + (int)threadIdx.y) * RY + r;
         ok[r] = yy[r] < ny;
         const int64_t col = (int64_t)(ok[r] ? yy[r] : 0) * nx + x;
-        um[r] = u[(int64_t)wrap_dec(z0, nz) * sxy + col];
+        um[r] = (wz && z0 == 0) ? T(0) : u[(int64_t)wrap_dec(z0, nz) * sxy + col];
         uc[r] = u[(int64_t)z0 * sxy + col];
-        up[r] = u[(int64_t)wrap_inc(z0, nz) * sxy + col];
+        up[r] = (wz && z0 == nz - 1) ? T(0) : u[(int64_t)wrap_inc(z0, nz) * sxy + col];
     }
     for (int z = z0; z < z1; ++z) {
         const int64_t plane = (int64_t)z * sxy;
         const bool more = z + 1 < z1;
+        const bool zghost = wz && z + 2 >= nz;      // plane z+2 lies past the wall
         const int64_t nplane = (int64_t)(more ? wrap_inc(z + 1, nz) : z) * sxy;
         T upp[RY];
 #pragma unroll
         for (int r = 0; r < RY; ++r) {
             const int y = ok[r] ? yy[r] : 0;
             const int64_t col = (int64_t)y * nx + x;
-            upp[r] = more ? u[nplane + col] : T(0);
+            upp[r] = (more && !zghost) ? u[nplane + col] : T(0);
             if (ok[r]) {
                 const int64_t idx = plane + col;
-                const T uxm = u[plane + (int64_t)y * nx + xm];
-                const T uxp = u[plane + (int64_t)y * nx + xp];
-                const T uym = u[plane + (int64_t)wrap_dec(y, ny) * nx + x];
-                const T uyp = u[plane + (int64_t)wrap_inc(y, ny) * nx + x];
+                const T uxm = xlg ? T(0) : u[plane + (int64_t)y * nx + xm];
+                const T uxp = xrg ? T(0) : u[plane + (int64_t)y * nx + xp];
+                const T uym = (wyy && y == 0) ? T(0) : u[plane + (int64_t)wrap_dec(y, ny) * nx + x];
+                const T uyp = (wyy && y == ny - 1) ? T(0) : u[plane + (int64_t)wrap_inc(y, ny) * nx + x];
                 const T old = p.uo[idx];
                 const T res = cell_update<T, 3>(p, x, y, z, idx, uc[r], uxm, uxp, uym, uyp,
                                                 um[r], up[r], old);
@@ -391,7 +416,7 @@ template <typename T, int D>
 __global__ void __launch_bounds__(256) k_start(const T *__restrict__ u0, const T *__restrict__ v0,
                                                T *__restrict__ um1, const T *__restrict__ c2,
                                                T c2_const, T inv_h2, T dt, T half_dt2,
-                                               int nx, int ny, int nz)
+                                               int nx, int ny, int nz, int walls)
 {
     const int x = blockIdx.x * 64 + threadIdx.x;
     const int y = blockIdx.y * 4 + threadIdx.y;
@@ -406,12 +431,20 @@ __global__ void __launch_bounds__(256) k_start(const T *__restrict__ u0, const T
     const int64_t idx = (int64_t)z * sxy + (int64_t)y * sx + x;
     const int64_t plane = (int64_t)z * sxy;
     const T c = u0[idx];
+    // neighbour values (0 on ghost cells past a wall; bit a of `walls` set for axis a)
+    const bool wx = walls & 1, wy = walls & 2, wz = walls & 4;
+    const T xm_ = (wx && x == 0) ? T(0) : u0[plane + (int64_t)y * sx + wrap_dec(x, nx)];
+    const T xp_ = (wx && x == nx - 1) ? T(0) : u0[plane + (int64_t)y * sx + wrap_inc(x, nx)];
+    const T ym_ = (wy && y == 0) ? T(0) : u0[plane + (int64_t)wrap_dec(y, ny) * sx + x];
+    const T yp_ = (wy && y == ny - 1) ? T(0) : u0[plane + (int64_t)wrap_inc(y, ny) * sx + x];
     T lap = T(0);
-    lap += ((u0[plane + (int64_t)y * sx + wrap_dec(x, nx)] - T(2) * c) + u0[plane + (int64_t)y * sx + wrap_inc(x, nx)]) * inv_h2;
-    lap += ((u0[plane + (int64_t)wrap_dec(y, ny) * sx + x] - T(2) * c) + u0[plane + (int64_t)wrap_inc(y, ny) * sx + x]) * inv_h2;
-    if (D == 3)
-        lap += ((u0[(int64_t)wrap_dec(z, nz) * sxy + (int64_t)y * sx + x] - T(2) * c)
-                + u0[(int64_t)wrap_inc(z, nz) * sxy + (int64_t)y * sx + x]) * inv_h2;
+    lap += ((xm_ - T(2) * c) + xp_) * inv_h2;
+    lap += ((ym_ - T(2) * c) + yp_) * inv_h2;
+    if (D == 3) {
+        const T zm_ = (wz && z == 0) ? T(0) : u0[(int64_t)wrap_dec(z, nz) * sxy + (int64_t)y * sx + x];
+        const T zp_ = (wz && z == nz - 1) ? T(0) : u0[(int64_t)wrap_inc(z, nz) * sxy + (int64_t)y * sx + x];
+        lap += ((zm_ - T(2) * c) + zp_) * inv_h2;
+    }
     const T a = (c2 ? c2[idx] : c2_const) * lap;
     // U^{-1} = U^0 - dt V^0 + (dt^2/2) A(U^0)
     const T v = v0 ? v0[idx] : T(0);

@@ -211,3 +211,32 @@ def test_step_before_state_is_an_error():
         sim.step(1)
     assert ei.value.code == dp.DPML_ESTATE
     sim.close()
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("ndim,variant,walls", [
+    (2, dp.VARIANT_CELL, (True, True)), (2, dp.VARIANT_MARCH, (True, True)),
+    (2, dp.VARIANT_MARCH, (True, False)), (2, dp.VARIANT_MARCH, (False, True)),
+    (3, dp.VARIANT_CELL, (True, True, True)), (3, dp.VARIANT_MARCH, (True, False, True)),
+])
+def test_reflecting_walls_match_oracle(dtype, ndim, variant, walls):
+    """Layers truncated by reflecting walls (ghost cells hold 0) instead of the
+    periodic wrap; long enough for the wall echo to return."""
+    rng = np.random.default_rng(44)
+    if ndim == 2:
+        n, lo, hi, steps, dt = [170, 121], [7, 12], [10, 5], 160, 0.5
+    else:
+        n, lo, hi, steps, dt = [34, 27, 23], [5, 3, 6], [4, 7, 5], 60, 0.4
+    sig = [synthetic.sigma_random(n[a], lo[a], hi[a], 2.0, rng) for a in range(ndim)]
+    U0 = synthetic.gaussian_sum(n, lo, hi, 6, 2.0, 6.0, rng)
+    N = [lo[a] + n[a] + hi[a] for a in range(ndim)]
+    print("case walls=%s %dD %s variant=%d" % (walls, ndim, dtype, variant), flush=True)
+    sim = dp.Simulation(n, lo, hi, 1.0, dt, sig, dtype=_dtype(dtype), walls=walls)
+    sim.set_variant(variant, 0)
+    sim.set_state(torch.from_numpy(U0))
+    sim.step(steps)
+    gs = gpu_state(sim)
+    g = oracle.Grid(N, 1.0, dt, sig, walls=walls)
+    ref, _ = oracle.run(g, oracle.start(g, U0), steps)
+    sim.close()
+    _assert_errs(compare_states(gs, ref, n, lo, hi), dtype)
