@@ -48,9 +48,17 @@ def log(msg):
 def time_gpu(w, dtype_name, steps, warmup, variant=0, tile_rows=0):
     import torch
     import paper_1804_01390_amd as dp
+    from paper_1804_01390_amd import autotune
     dtype = torch.float32 if dtype_name == "f32" else torch.float64
     sim = dp.Simulation(w.n, w.lo, w.hi, w.h, w.dt, w.sigma, dtype=dtype)
-    sim.set_variant(variant, tile_rows)
+    sim.set_state(torch.from_numpy(w.U0))
+    if variant == 0:
+        choice = autotune.tune(sim)           # cached per grid after the first run
+        launch = {"variant": choice["variant"], "tile_rows": choice["tile_rows"],
+                  "autotuned": True, "cached": choice["cached"]}
+    else:
+        sim.set_variant(variant, tile_rows)
+        launch = {"variant": variant, "tile_rows": tile_rows, "autotuned": False}
     sim.set_state(torch.from_numpy(w.U0))
     sim.step(warmup)
     sim.sync()
@@ -78,7 +86,7 @@ def time_gpu(w, dtype_name, steps, warmup, variant=0, tile_rows=0):
     sim.close()
     return {"total_ms": total_ms, "ms_per_step": total_ms / steps,
             "kernel_ms_mean": float(np.mean(per)), "kernel_ms_median": float(np.median(per)),
-            "finite": ok}
+            "finite": ok, "launch": launch}
 
 
 def cpu_baseline(w, sample_steps: int):
@@ -340,6 +348,7 @@ def main():
                          "kernel_ms_mean": round(r["kernel_ms_mean"], 5),
                          "kernel_ms_median": round(r["kernel_ms_median"], 5)},
             "finite": r["finite"],
+            "launch": r["launch"],
         })
         log("  %s: %.1f Gcell/s, %.4f ms/step, kernel %.4f ms, %.0f GB/s" % (
             dn, runs[-1]["value"], r["ms_per_step"], r["kernel_ms_mean"], achieved))

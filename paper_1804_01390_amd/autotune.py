@@ -1,0 +1,86 @@
+"""Tile-shape autotuner for the fused step kernels.
+
+For a given grid (dimension, extents, dtype, batch) it times the candidate
+launch shapes -- the marching kernel with several tile heights, and the
+one-thread-per-cell kernel -- on the GPU with HIP events, keeps the fastest,
+and caches the choice in a JSON file keyed by the grid so later runs reuse
+it without timing.  Every candidate computes the same result (the kernels
+evaluate the scheme in the same operation order), so tuning never changes
+numerics.
+"""
+from __future__ import annotations
+
+import json
+import os
+from typing import Dict, List, Optional, Sequence, Tuple
+
+from . import VARIANT_CELL, VARIANT_MARCH
+
+DEFAULT_CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "autotune_cache.json")
+
+CANDIDATES_2D: List[Tuple[int, int]] = [(VARIANT_MARCH, r) for r in (8, 16, 24, 32, 48, 64, 96, 128)] + [
+    (VARIANT_CELL, 0)]
+CANDIDATES_3D: List[Tuple[int, int]] = [(VARIANT_MARCH, r) for r in (8, 16, 24, 32, 40, 56, 80, 112)] + [
+    (VARIANT_CELL, 0)]
+
+
+def grid_key(sim) -> str:
+    return "d%d_%s_N%s_b%d_w%s" % (sim.ndim, "f32" if sim.code == 0 else "f64",
+                                   "x".join(str(n) for n in sim.N), sim.batch,
+                                   "".join("1" if w else "0" for w in getattr(sim, "walls", ())) or "0")
+
+
+def _load(path: str) -> Dict:
+    try:
+        with open(path) as f:
+            return json.load(f)
+    except (OSError, ValueError):
+        return {}
+
+
+def _time_candidate(sim, variant: int, tile_rows: int, steps: int) -> float:
+    torch = sim.torch
+    sim.set_variant(variant, tile_rows)
+    blob, n = sim.get_state()
+    blob = blob.clone()
+    sim.step(2)                                   # warm the code path
+    sim.sync()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    sim.step(steps)
+    e1.record()
+    torch.cuda.synchronize()
+    sim.put_state(blob, n)                       # leave the simulation where it was
+    sim.sync()
+    return e0.elapsed_time(e1) / steps
+
+
+def tune(sim, steps: int = 50, candidates: Optional[Sequence[Tuple[int, int]]] = None,
+         cache: Optional[str] = DEFAULT_CACHE, force: bool = False) -> Dict:
+    """Pick and apply the fastest (variant, tile_rows) for ``sim`` (whose state
+    must be set).  Returns {"variant", "tile_rows", "ms_per_step", "timings"}."""
+    key = grid_key(sim)
+    db = _load(cache) if cache else {}
+    if not force and key in db:
+        best = db[key]
+        sim.set_variant(best["variant"], best["tile_rows"])
+        return dict(best, cached=True)
+    if candidates is None:
+        candidates = CANDIDATES_2D if sim.ndim == 2 else CANDIDATES_3D
+    timings = []
+    for variant, rows in candidates:
+        ms = _time_candidate(sim, variant, rows, steps)
+        timings.append({"variant": variant, "tile_rows": rows, "ms_per_step": ms})
+    best = min(timings, key=lambda t: t["ms_per_step"])
+    rec = {"variant": best["variant"], "tile_rows": best["tile_rows"],
+           "ms_per_step": best["ms_per_step"], "timings": timings}
+    sim.set_variant(rec["variant"], rec["tile_rows"])
+    if cache:
+        db = _load(cache)
+        db[key] = rec
+        tmp = cache + ".tmp%d" % os.getpid()
+        with open(tmp, "w") as f:
+            json.dump(db, f, indent=1)
+        os.replace(tmp, cache)
+    return dict(rec, cached=False)

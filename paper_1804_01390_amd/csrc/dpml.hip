@@ -245,7 +245,10 @@ int launch_step(dpml *H, T *hist = nullptr)
         const int tiles_z = (int)((L.N[2] + p.tile_rows - 1) / p.tile_rows);
         p.n_tiles = p.tiles_x * p.tiles_y * tiles_z;
         dim3 grid((unsigned)round8(p.n_tiles), B), block(64, 4);
-        hipLaunchKernelGGL((dpmlk::k_step_march3d<T, RY>), grid, block, 0, H->stream, p);
+        if (sizeof(T) == 4)
+            hipLaunchKernelGGL((dpmlk::k_step_march3d<T, RY, 4>), grid, block, 0, H->stream, p);
+        else
+            hipLaunchKernelGGL((dpmlk::k_step_march3d<T, RY, 2>), grid, block, 0, H->stream, p);
     }
     HIP_TRY(H, hipGetLastError());
     return DPML_OK;

@@ -257,8 +257,14 @@ __device__ __forceinline__ void store_row(T *ptr, const Row<T, VX> &r)
     *reinterpret_cast<V *>(ptr) = w;
 }
 
-// One 2D marching tile (tile column tx, tile row ty) of one problem.
-template <typename T, int VX>
+// One 2D marching tile (tile column tx, tile row ty) of one problem.  The
+// thread keeps a window of U^n rows in registers and walks down the tile in
+// groups of R rows: all HBM loads of a group (R new U^n rows, R U^{n-1}
+// rows, and the 2R outer x neighbours, which hit L1) are issued before any
+// of its arithmetic, so each wave has R times more loads in flight than a
+// row-at-a-time loop.  Register arrays are only indexed with compile-time
+// constants (full groups); the last rows of a tile take a one-row loop.
+template <typename T, int VX, int R>
 __device__ __forceinline__ void march2d_tile(const StepArgs<T> &p, int tx, int ty)
 {
     const int x0 = (tx * 256 + (int)threadIdx.x) * VX;
@@ -283,18 +289,9 @@ __device__ __forceinline__ void march2d_tile(const StepArgs<T> &p, int tx, int t
         const int w = yy < 0 ? yy + ny : (yy >= ny ? yy - ny : yy);
         return load_row<T, VX>(u + (int64_t)w * nx + x0);
     };
-
-    Row<T, VX> um = nb_row(y0 - 1);
-    Row<T, VX> uc = load_row<T, VX>(u + (int64_t)y0 * nx + x0);
-    Row<T, VX> up = nb_row(y0 + 1);
-    for (int y = y0; y < y1; ++y) {
+    auto row_out = [&](int y, const Row<T, VX> &um, const Row<T, VX> &uc, const Row<T, VX> &up,
+                       const Row<T, VX> &old, T left, T right) {
         const int64_t row = (int64_t)y * nx;
-        // prefetch the row after next while this one is computed
-        Row<T, VX> upp = up;
-        if (y + 1 < y1) upp = nb_row(y + 2);
-        const Row<T, VX> old = load_row<T, VX>(p.uo + row + x0);
-        const T left = lghost ? T(0) : u[row + xl];
-        const T right = rghost ? T(0) : u[row + xr];
         Row<T, VX> out;
 #pragma unroll
         for (int k = 0; k < VX; ++k) {
@@ -305,9 +302,37 @@ __device__ __forceinline__ void march2d_tile(const StepArgs<T> &p, int tx, int t
         }
         store_row<T, VX>(p.uo + row + x0, out);
         if (p.hist) store_row<T, VX>(p.hist + row + x0, out);
-        um = uc;
-        uc = up;
-        up = upp;
+    };
+
+    Row<T, VX> w[R + 2];       // w[0] = row y-1, w[1] = row y, w[2 + r] = row y+1+r
+    w[0] = nb_row(y0 - 1);
+    w[1] = load_row<T, VX>(u + (int64_t)y0 * nx + x0);
+    int y = y0;
+    for (; y + R <= y1; y += R) {
+        Row<T, VX> old[R];
+        T left[R], right[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int64_t row = (int64_t)(y + r) * nx;
+            w[2 + r] = nb_row(y + 1 + r);
+            old[r] = load_row<T, VX>(p.uo + row + x0);
+            left[r] = lghost ? T(0) : u[row + xl];
+            right[r] = rghost ? T(0) : u[row + xr];
+        }
+#pragma unroll
+        for (int r = 0; r < R; ++r) row_out(y + r, w[r], w[r + 1], w[r + 2], old[r], left[r], right[r]);
+        w[0] = w[R];
+        w[1] = w[R + 1];
+    }
+    for (; y < y1; ++y) {
+        const int64_t row = (int64_t)y * nx;
+        w[2] = nb_row(y + 1);
+        const Row<T, VX> old = load_row<T, VX>(p.uo + row + x0);
+        const T left = lghost ? T(0) : u[row + xl];
+        const T right = rghost ? T(0) : u[row + xr];
+        row_out(y, w[0], w[1], w[2], old, left, right);
+        w[0] = w[1];
+        w[1] = w[2];
     }
 }
 
@@ -317,7 +342,7 @@ __global__ void __launch_bounds__(256) k_step_march2d(StepArgs<T> p)
     const int tile = xcd_tile(blockIdx.x, gridDim.x);
     if (tile >= p.n_tiles) return;
     select_member(p, (int)blockIdx.y);
-    march2d_tile<T, VX>(p, tile % p.tiles_x, tile / p.tiles_x);
+    march2d_tile<T, VX, 4>(p, tile % p.tiles_x, tile / p.tiles_x);
 }
 
 // ---------------------------------------------------------------------------
@@ -338,15 +363,17 @@ __global__ void __launch_bounds__(256) k_step_multi2d(const StepArgs<T> *__restr
     if (tile >= ntiles) return;
     const TileRef t = tiles[tile];
     const StepArgs<T> p = probs[t.prob];
-    march2d_tile<T, VX>(p, t.tx, t.ty);
+    march2d_tile<T, VX, 4>(p, t.tx, t.ty);
 }
 
 // ---------------------------------------------------------------------------
 // Variant MARCH, 3D: a block of 64 x 4 threads owns a 64 x (4*RY) tile of an
-// (x, y) plane and marches over `tile_rows` planes in z, keeping U^n of
-// planes z-1, z, z+1 in registers; x and y neighbours come from L1/L2.
+// (x, y) plane and marches over `tile_rows` planes in z in groups of R
+// planes, keeping U^n of planes z-1, z, ... in registers; every load of a
+// group (R new planes, R U^{n-1} planes and the x/y neighbours, mostly L1/L2
+// hits) is issued before its arithmetic.
 // ---------------------------------------------------------------------------
-template <typename T, int RY>
+template <typename T, int RY, int R>
 __global__ void __launch_bounds__(256) k_step_march3d(StepArgs<T> p)
 {
     const int tile = xcd_tile(blockIdx.x, gridDim.x);
@@ -367,44 +394,87 @@ __global__ void __launch_bounds__(256) k_step_march3d(StepArgs<T> p)
     const bool xlg = p.ax[0].wall && x == 0, xrg = p.ax[0].wall && x == nx - 1;
     const bool wyy = p.ax[1].wall, wz = p.ax[2].wall;
     const T *u = p.u;
-    int yy[RY];
-    bool ok[RY];
-    T um[RY], uc[RY], up[RY];
+    int yy[RY], ymv[RY], ypv[RY];
+    bool ok[RY], ymg[RY], ypg[RY];
 #pragma unroll
-    for (int r = 0; r < RY; ++r) {
-        yy[r] = (ty * 4 + (int)threadIdx.y) * RY + r;
-        ok[r] = yy[r] < ny;
-        const int64_t col = (int64_t)(ok[r] ? yy[r] : 0) * nx + x;
-        um[r] = (wz && z0 == 0) ? T(0) : u[(int64_t)wrap_dec(z0, nz) * sxy + col];
-        uc[r] = u[(int64_t)z0 * sxy + col];
-        up[r] = (wz && z0 == nz - 1) ? T(0) : u[(int64_t)wrap_inc(z0, nz) * sxy + col];
+    for (int q = 0; q < RY; ++q) {
+        yy[q] = (ty * 4 + (int)threadIdx.y) * RY + q;
+        ok[q] = yy[q] < ny;
+        if (!ok[q]) yy[q] = 0;
+        ymv[q] = wrap_dec(yy[q], ny);
+        ypv[q] = wrap_inc(yy[q], ny);
+        ymg[q] = wyy && yy[q] == 0;
+        ypg[q] = wyy && yy[q] == ny - 1;
     }
-    for (int z = z0; z < z1; ++z) {
-        const int64_t plane = (int64_t)z * sxy;
-        const bool more = z + 1 < z1;
-        const bool zghost = wz && z + 2 >= nz;      // plane z+2 lies past the wall
-        const int64_t nplane = (int64_t)(more ? wrap_inc(z + 1, nz) : z) * sxy;
-        T upp[RY];
+    // plane index of z-neighbour zz, or -1 past a wall
+    auto plane_of = [&](int zz) -> int {
+        if (zz < 0) return wz ? -1 : zz + nz;
+        if (zz >= nz) return wz ? -1 : zz - nz;
+        return zz;
+    };
+    auto col = [&](int q) -> int64_t { return (int64_t)yy[q] * nx + x; };
+
+    T w[R + 2][RY];
+    {
+        const int pm = plane_of(z0 - 1);
 #pragma unroll
-        for (int r = 0; r < RY; ++r) {
-            const int y = ok[r] ? yy[r] : 0;
-            const int64_t col = (int64_t)y * nx + x;
-            upp[r] = (more && !zghost) ? u[nplane + col] : T(0);
-            if (ok[r]) {
-                const int64_t idx = plane + col;
-                const T uxm = xlg ? T(0) : u[plane + (int64_t)y * nx + xm];
-                const T uxp = xrg ? T(0) : u[plane + (int64_t)y * nx + xp];
-                const T uym = (wyy && y == 0) ? T(0) : u[plane + (int64_t)wrap_dec(y, ny) * nx + x];
-                const T uyp = (wyy && y == ny - 1) ? T(0) : u[plane + (int64_t)wrap_inc(y, ny) * nx + x];
-                const T old = p.uo[idx];
-                const T res = cell_update<T, 3>(p, x, y, z, idx, uc[r], uxm, uxp, uym, uyp,
-                                                um[r], up[r], old);
-                p.uo[idx] = res;
-                if (p.hist) p.hist[idx] = res;
+        for (int q = 0; q < RY; ++q) {
+            w[0][q] = (pm < 0 || !ok[q]) ? T(0) : u[(int64_t)pm * sxy + col(q)];
+            w[1][q] = ok[q] ? u[(int64_t)z0 * sxy + col(q)] : T(0);
+        }
+    }
+    auto compute = [&](int z, int q, T um, T uc, T up, T old, T uxm, T uxp, T uym, T uyp) {
+        const int64_t idx = (int64_t)z * sxy + col(q);
+        const T res = cell_update<T, 3>(p, x, yy[q], z, idx, uc, uxm, uxp, uym, uyp, um, up, old);
+        p.uo[idx] = res;
+        if (p.hist) p.hist[idx] = res;
+    };
+    int z = z0;
+    for (; z + R <= z1; z += R) {
+        T old[R][RY], nxm[R][RY], nxp[R][RY], nym[R][RY], nyp[R][RY];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int pz = plane_of(z + 1 + r);
+            const int64_t plane = (int64_t)(z + r) * sxy;
+#pragma unroll
+            for (int q = 0; q < RY; ++q) {
+                w[2 + r][q] = (pz < 0 || !ok[q]) ? T(0) : u[(int64_t)pz * sxy + col(q)];
+                if (ok[q]) {
+                    const int64_t rowq = plane + (int64_t)yy[q] * nx;
+                    old[r][q] = p.uo[rowq + x];
+                    nxm[r][q] = xlg ? T(0) : u[rowq + xm];
+                    nxp[r][q] = xrg ? T(0) : u[rowq + xp];
+                    nym[r][q] = ymg[q] ? T(0) : u[plane + (int64_t)ymv[q] * nx + x];
+                    nyp[r][q] = ypg[q] ? T(0) : u[plane + (int64_t)ypv[q] * nx + x];
+                }
             }
-            um[r] = uc[r];
-            uc[r] = up[r];
-            up[r] = upp[r];
+        }
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+#pragma unroll
+            for (int q = 0; q < RY; ++q)
+                if (ok[q]) compute(z + r, q, w[r][q], w[r + 1][q], w[r + 2][q], old[r][q], nxm[r][q],
+                                   nxp[r][q], nym[r][q], nyp[r][q]);
+#pragma unroll
+        for (int q = 0; q < RY; ++q) {
+            w[0][q] = w[R][q];
+            w[1][q] = w[R + 1][q];
+        }
+    }
+    for (; z < z1; ++z) {
+        const int pz = plane_of(z + 1);
+        const int64_t plane = (int64_t)z * sxy;
+#pragma unroll
+        for (int q = 0; q < RY; ++q) {
+            w[2][q] = (pz < 0 || !ok[q]) ? T(0) : u[(int64_t)pz * sxy + col(q)];
+            if (ok[q]) {
+                const int64_t rowq = plane + (int64_t)yy[q] * nx;
+                compute(z, q, w[0][q], w[1][q], w[2][q], p.uo[rowq + x], xlg ? T(0) : u[rowq + xm],
+                        xrg ? T(0) : u[rowq + xp], ymg[q] ? T(0) : u[plane + (int64_t)ymv[q] * nx + x],
+                        ypg[q] ? T(0) : u[plane + (int64_t)ypv[q] * nx + x]);
+            }
+            w[0][q] = w[1][q];
+            w[1][q] = w[2][q];
         }
     }
 }

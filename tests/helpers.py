@@ -74,12 +74,56 @@ def rel_err(got, ref, mask=None) -> float:
     return float(np.max(np.abs(got - ref)) / peak)
 
 
-def compare_states(gs, os_, n, lo, hi):
-    """Per-field peak-normalised errors: U, Uprev, Phi_a/Psi_a on their supports."""
-    errs = {"U": rel_err(gs.U, os_.U), "Uprev": rel_err(gs.Uprev, os_.Uprev)}
+def compare_states(gs, os_, n, lo, hi, peaks=None):
+    """Per-field normalised max errors: U, Uprev, Phi_a/Psi_a on their
+    supports.  Normalised by the oracle field's peak at the compared step, or,
+    when ``peaks`` is given, by the field's peak over the whole run (see
+    run_peaks) -- the FP32 reading: FP32 rounding scales with the largest
+    values a run has carried, not with what is left after the layer has
+    absorbed most of the wave."""
+    def e(key, got, ref, mask=None):
+        if peaks is None:
+            return rel_err(got, ref, mask)
+        g = got[mask] if mask is not None else got
+        r = ref[mask] if mask is not None else ref
+        return float(np.max(np.abs(g - r))) / peaks[key] if r.size else 0.0
+
+    errs = {"U": e("U", gs.U, os_.U), "Uprev": e("U", gs.Uprev, os_.Uprev)}
     for a in range(len(n)):
         if lo[a] + hi[a] == 0:
             continue
-        errs["Phi%d" % a] = rel_err(gs.Phi[a], os_.Phi[a], support_mask(a, n, lo, hi, "phi"))
-        errs["Psi%d" % a] = rel_err(gs.Psi[a], os_.Psi[a], support_mask(a, n, lo, hi, "psi"))
+        errs["Phi%d" % a] = e("Phi%d" % a, gs.Phi[a], os_.Phi[a], support_mask(a, n, lo, hi, "phi"))
+        errs["Psi%d" % a] = e("Psi%d" % a, gs.Psi[a], os_.Psi[a], support_mask(a, n, lo, hi, "psi"))
     return errs
+
+
+def run_with_peaks(g, state, steps, n, lo, hi, chunks=10, **kw):
+    """Run the oracle in chunks and return (final state, traces, peaks) where
+    peaks[field] is the field's max magnitude over the run (U over the whole
+    grid, Phi_a/Psi_a over their supports), sampled at chunk ends."""
+    peaks = {}
+
+    def upd(s):
+        peaks["U"] = max(peaks.get("U", 0.0), float(np.max(np.abs(s.U))), float(np.max(np.abs(s.Uprev))))
+        for a in range(len(n)):
+            if lo[a] + hi[a] == 0:
+                continue
+            for kind, arr in (("Phi", s.Phi[a]), ("Psi", s.Psi[a])):
+                m = support_mask(a, n, lo, hi, kind.lower())
+                key = "%s%d" % (kind, a)
+                peaks[key] = max(peaks.get(key, 0.0), float(np.max(np.abs(arr[m]))))
+
+    upd(state)
+    done = 0
+    traces = None
+    step = max(1, steps // chunks)
+    while done < steps:
+        k = min(step, steps - done)
+        state, tr = oracle.run(g, state, k, **kw)
+        traces = tr if traces is None else traces + tr   # each chunk fills its own columns
+        done += k
+        upd(state)
+    for key in list(peaks):
+        if peaks[key] == 0.0:
+            peaks[key] = 1.0
+    return state, traces, peaks

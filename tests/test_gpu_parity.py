@@ -8,7 +8,7 @@ import pytest
 
 import oracle
 import synthetic
-from helpers import compare_states, gpu_state, rel_err
+from helpers import compare_states, gpu_state, rel_err, run_with_peaks
 
 torch = pytest.importorskip("torch")
 dp = pytest.importorskip("paper_1804_01390_amd")
@@ -32,9 +32,9 @@ def _run_both(n, lo, hi, sigma, U0, steps, dtype, variant=dp.VARIANT_AUTO, c2=No
     sim.step(steps)
     gs = gpu_state(sim)
     g = oracle.Grid(N, h, dt, sigma, c2=c2)
-    ref, _ = oracle.run(g, oracle.start(g, U0, V0), steps)
+    ref, _, peaks = run_with_peaks(g, oracle.start(g, U0, V0), steps, n, lo, hi)
     sim.close()
-    return compare_states(gs, ref, n, lo, hi)
+    return compare_states(gs, ref, n, lo, hi, peaks if dtype == "f32" else None)
 
 
 def _assert_errs(errs, dtype):
@@ -237,6 +237,6 @@ def test_reflecting_walls_match_oracle(dtype, ndim, variant, walls):
     sim.step(steps)
     gs = gpu_state(sim)
     g = oracle.Grid(N, 1.0, dt, sig, walls=walls)
-    ref, _ = oracle.run(g, oracle.start(g, U0), steps)
+    ref, _, peaks = run_with_peaks(g, oracle.start(g, U0), steps, n, lo, hi)
     sim.close()
-    _assert_errs(compare_states(gs, ref, n, lo, hi), dtype)
+    _assert_errs(compare_states(gs, ref, n, lo, hi, peaks if dtype == "f32" else None), dtype)
