@@ -161,12 +161,14 @@ def bench_ricker3d(steps: int):
     import torch
     import paper_1804_01390_amd as dp
     import synthetic
+    from paper_1804_01390_amd import autotune
     w = synthetic.ricker3d(n=512, m=24, steps=steps)
     sim = dp.Simulation(w.n, w.lo, w.hi, w.h, w.dt, w.sigma, dtype=torch.float32)
     sim.set_state(torch.zeros(tuple(reversed(w.N)), dtype=torch.float32, device="cuda"))
     sim.inject(w.sources, torch.from_numpy(w.wavelets))
     axis, index = w.plane
     sim.record_plane(axis, index, w.steps)
+    choice = autotune.tune(sim, steps=10)
     sim.step(5)
     sim.sync()
     e0, e1 = _events()
@@ -188,7 +190,8 @@ def bench_ricker3d(steps: int):
             "ms_per_step": round(ms / w.steps, 5),
             "alg_GBps": round(ab * w.steps / (ms * 1e-3) / 1e9, 1),
             "frac_of_8TBps": round(ab * w.steps / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
-            "last_plane_peak": peak}
+            "last_plane_peak": peak,
+            "launch": {"variant": choice["variant"], "tile_rows": choice["tile_rows"], "autotuned": True}}
 
 
 def bench_batch(steps: int, count: int):

@@ -78,10 +78,14 @@ extern "C" {
 #define DPML_FIELD_PHI(a) (2 + 2 * (a))  /* Phi_a^n, compact band array */
 #define DPML_FIELD_PSI(a) (3 + 2 * (a))  /* Psi_a^n, compact band array */
 
-/* Kernel variants (dpml_set_variant). */
-#define DPML_VARIANT_AUTO 0   /* library default for the grid             */
-#define DPML_VARIANT_CELL 1   /* one thread per cell, 2D thread blocks     */
-#define DPML_VARIANT_MARCH 2  /* row tiles marching along the slowest axis */
+/* Kernel variants (dpml_set_variant); all compute identical results. */
+#define DPML_VARIANT_AUTO 0   /* library default (CELL)                               */
+#define DPML_VARIANT_CELL 1   /* one thread per cell; tile_rows = block rows TH in
+                                 {1, 2, 4, 8} (block of 256/TH x TH cells)            */
+#define DPML_VARIANT_MARCH 2  /* tiles marching along the slowest axis, the loads of
+                                 4 (2D; 3D FP32) or 2 (3D FP64) rows/planes issued
+                                 together; tile_rows = rows (planes) per tile        */
+#define DPML_VARIANT_MARCH1 3 /* as MARCH, one row (plane) at a time                 */
 
 typedef struct dpml_grid {
     int32_t ndim;    /* 2 or 3 */
@@ -172,6 +176,13 @@ int dpml_set_variant(dpml_t *h, int32_t variant, int32_t tile_rows);
  * before the work completes.  DPML_ESTATE before dpml_set_state;
  * DPML_EINVAL if nsteps < 0. */
 int dpml_step(dpml_t *h, int64_t nsteps);
+
+/* As dpml_step for a run without sources, receivers or planes (DPML_EINVAL
+ * otherwise), but the nsteps launches are captured once into a HIP graph
+ * (cached for the same nsteps, buffer parity and kernel variant) and
+ * replayed with a single launch: for small grids whose steps are shorter
+ * than a kernel launch. */
+int dpml_step_graph(dpml_t *h, int64_t nsteps);
 
 /* As dpml_step, but every `every` steps (and at the end) synchronises and
  * scans U^n for NaN/Inf; returns DPML_ENONFINITE at the first hit (the state

@@ -25,7 +25,7 @@ LIB_PATH = os.path.join(_HERE, "libdpml.so")
 
 DPML_OK, DPML_EINVAL, DPML_ENOMEM, DPML_EHIP, DPML_ESTATE, DPML_ENONFINITE = 0, -1, -2, -3, -4, -5
 DPML_F32, DPML_F64 = 0, 1
-VARIANT_AUTO, VARIANT_CELL, VARIANT_MARCH = 0, 1, 2
+VARIANT_AUTO, VARIANT_CELL, VARIANT_MARCH, VARIANT_MARCH1 = 0, 1, 2, 3
 FIELD_U, FIELD_UPREV = 0, 1
 
 
@@ -40,7 +40,7 @@ def FIELD_PSI(a: int) -> int:
 EXPORTED = [
     "dpml_workspace_bytes", "dpml_create", "dpml_set_state", "dpml_inject", "dpml_record",
     "dpml_record_plane", "dpml_set_variant", "dpml_step", "dpml_step_checked", "dpml_field",
-    "dpml_time_index", "dpml_state_bytes", "dpml_get_state", "dpml_put_state", "dpml_sync",
+    "dpml_time_index", "dpml_step_graph", "dpml_state_bytes", "dpml_get_state", "dpml_put_state", "dpml_sync",
     "dpml_destroy", "dpml_strerror", "dpml_last_error",
     "dpml_adjoint_workspace_bytes", "dpml_forward_checkpointed", "dpml_adjoint",
     "dpml_multi_workspace_bytes", "dpml_multi_create", "dpml_multi_set_state", "dpml_multi_step",
@@ -89,6 +89,7 @@ def load_library():
         "dpml_set_variant": (ctypes.c_int, [_VP, ctypes.c_int32, ctypes.c_int32]),
         "dpml_step": (ctypes.c_int, [_VP, ctypes.c_int64]),
         "dpml_step_checked": (ctypes.c_int, [_VP, ctypes.c_int64, ctypes.c_int64]),
+        "dpml_step_graph": (ctypes.c_int, [_VP, ctypes.c_int64]),
         "dpml_field": (ctypes.c_int, [_VP, ctypes.c_int32, ctypes.POINTER(_VP), ctypes.c_int64 * 3]),
         "dpml_time_index": (ctypes.c_int64, [_VP]),
         "dpml_state_bytes": (ctypes.c_size_t, [_VP]),
@@ -265,6 +266,10 @@ class Simulation:
 
     def step(self, nsteps: int = 1):
         self._check(self.lib.dpml_step(self.handle, int(nsteps)))
+
+    def step_graph(self, nsteps: int):
+        """nsteps steps replayed from a cached HIP graph (no sources/receivers)."""
+        self._check(self.lib.dpml_step_graph(self.handle, int(nsteps)))
 
     def step_checked(self, nsteps: int, every: int):
         self._check(self.lib.dpml_step_checked(self.handle, int(nsteps), int(every)))

@@ -14,14 +14,16 @@ import json
 import os
 from typing import Dict, List, Optional, Sequence, Tuple
 
-from . import VARIANT_CELL, VARIANT_MARCH
+from . import VARIANT_CELL, VARIANT_MARCH, VARIANT_MARCH1
 
 DEFAULT_CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "autotune_cache.json")
 
-CANDIDATES_2D: List[Tuple[int, int]] = [(VARIANT_MARCH, r) for r in (8, 16, 24, 32, 48, 64, 96, 128)] + [
-    (VARIANT_CELL, 0)]
-CANDIDATES_3D: List[Tuple[int, int]] = [(VARIANT_MARCH, r) for r in (8, 16, 24, 32, 40, 56, 80, 112)] + [
-    (VARIANT_CELL, 0)]
+CANDIDATES_2D: List[Tuple[int, int]] = ([(VARIANT_CELL, th) for th in (1, 2, 4, 8)]
+                                        + [(VARIANT_MARCH, r) for r in (4, 8, 16)]
+                                        + [(VARIANT_MARCH1, r) for r in (4, 8, 16)])
+CANDIDATES_3D: List[Tuple[int, int]] = ([(VARIANT_CELL, th) for th in (1, 2, 4, 8)]
+                                        + [(VARIANT_MARCH, r) for r in (4, 8, 16, 32)]
+                                        + [(VARIANT_MARCH1, r) for r in (4, 8, 16, 32, 64)])
 
 
 def grid_key(sim) -> str:

@@ -130,6 +130,14 @@ struct dpml {
     size_t adj_bytes = 0;
     int64_t adj_nsteps = 0, adj_every = 0;
     bool adj_ready = false;
+    // cached HIP graph of a run of steps (no sources/receivers/planes)
+    hipStream_t cap = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    int64_t graph_steps = -1;
+    int graph_cur = -1;
+    void *graph_unow = nullptr;
+    int graph_variant = -1, graph_rows = -1;
     // RK4 integrator state (caller-owned workspace)
     char *rk_ws = nullptr;
     int rk_role[4] = {0, 1, 2, 3};   // buffer sets holding Y0, YS0, YS1, S
@@ -215,40 +223,56 @@ int launch_step(dpml *H, T *hist = nullptr)
     dpmlk::StepArgs<T> p = make_args<T>(H);
     p.hist = hist;
     const unsigned B = (unsigned)L.batch;
-    int variant = H->variant == DPML_VARIANT_AUTO ? DPML_VARIANT_MARCH : H->variant;
+    int variant = H->variant == DPML_VARIANT_AUTO ? DPML_VARIANT_CELL : H->variant;
     if (variant == DPML_VARIANT_CELL) {
-        dim3 block(64, 4, 1);
-        dim3 grid((unsigned)((L.N[0] + 63) / 64), (unsigned)((L.N[1] + 3) / 4),
-                  (unsigned)(L.ndim == 3 ? L.N[2] : 1) * B);
-        if (L.ndim == 2)
-            hipLaunchKernelGGL((dpmlk::k_step_cell<T, 2>), grid, block, 0, H->stream, p);
-        else
-            hipLaunchKernelGGL((dpmlk::k_step_cell<T, 3>), grid, block, 0, H->stream, p);
+        // tile_rows selects the block shape: TH rows of 256/TH cells (TH = 1, 2, 4, 8)
+        const int th = (H->tile_rows == 1 || H->tile_rows == 2 || H->tile_rows == 8) ? H->tile_rows : 4;
+        const int tw = 256 / th;
+        p.tiles_x = (int)((L.N[0] + tw - 1) / tw);
+        p.tiles_y = (int)((L.N[1] + th - 1) / th);
+        p.n_tiles = p.tiles_x * p.tiles_y * (int)(L.ndim == 3 ? L.N[2] : 1);
+        dim3 grid((unsigned)round8(p.n_tiles), B), block(256);
+#define DPML_CELL_LAUNCH(TH_)                                                                    \
+        if (L.ndim == 2) hipLaunchKernelGGL((dpmlk::k_step_cell<T, 2, TH_>), grid, block, 0, H->stream, p); \
+        else hipLaunchKernelGGL((dpmlk::k_step_cell<T, 3, TH_>), grid, block, 0, H->stream, p);
+        if (th == 1) { DPML_CELL_LAUNCH(1) }
+        else if (th == 2) { DPML_CELL_LAUNCH(2) }
+        else if (th == 8) { DPML_CELL_LAUNCH(8) }
+        else { DPML_CELL_LAUNCH(4) }
+#undef DPML_CELL_LAUNCH
     } else if (L.ndim == 2) {
         // vector width: 8 bytes per thread when the rows allow it
         constexpr int VX = sizeof(T) == 4 ? 2 : 1;
         const int vx = (L.N[0] % VX == 0) ? VX : 1;
-        p.tile_rows = H->tile_rows > 0 ? H->tile_rows : 32;
+        const bool grouped = variant == DPML_VARIANT_MARCH;
+        p.tile_rows = H->tile_rows > 0 ? H->tile_rows : 16;
         p.tiles_x = (int)((L.N[0] + 256 * vx - 1) / (256 * vx));
         const int tiles_y = (int)((L.N[1] + p.tile_rows - 1) / p.tile_rows);
         p.n_tiles = p.tiles_x * tiles_y;
         dim3 grid((unsigned)round8(p.n_tiles), B), block(256);
-        if (vx == 2)
-            hipLaunchKernelGGL((dpmlk::k_step_march2d<T, (sizeof(T) == 4 ? 2 : 1)>), grid, block, 0, H->stream, p);
+        if (vx == 2 && grouped)
+            hipLaunchKernelGGL((dpmlk::k_step_march2d<T, (sizeof(T) == 4 ? 2 : 1), 4>), grid, block, 0, H->stream, p);
+        else if (vx == 2)
+            hipLaunchKernelGGL((dpmlk::k_step_march2d<T, (sizeof(T) == 4 ? 2 : 1), 1>), grid, block, 0, H->stream, p);
+        else if (grouped)
+            hipLaunchKernelGGL((dpmlk::k_step_march2d<T, 1, 4>), grid, block, 0, H->stream, p);
         else
-            hipLaunchKernelGGL((dpmlk::k_step_march2d<T, 1>), grid, block, 0, H->stream, p);
+            hipLaunchKernelGGL((dpmlk::k_step_march2d<T, 1, 1>), grid, block, 0, H->stream, p);
     } else {
         constexpr int RY = 2;
-        p.tile_rows = H->tile_rows > 0 ? H->tile_rows : 40;
+        const bool grouped = variant == DPML_VARIANT_MARCH;
+        p.tile_rows = H->tile_rows > 0 ? H->tile_rows : 16;
         p.tiles_x = (int)((L.N[0] + 63) / 64);
         p.tiles_y = (int)((L.N[1] + 4 * RY - 1) / (4 * RY));
         const int tiles_z = (int)((L.N[2] + p.tile_rows - 1) / p.tile_rows);
         p.n_tiles = p.tiles_x * p.tiles_y * tiles_z;
         dim3 grid((unsigned)round8(p.n_tiles), B), block(64, 4);
-        if (sizeof(T) == 4)
+        if (grouped && sizeof(T) == 4)
             hipLaunchKernelGGL((dpmlk::k_step_march3d<T, RY, 4>), grid, block, 0, H->stream, p);
-        else
+        else if (grouped)
             hipLaunchKernelGGL((dpmlk::k_step_march3d<T, RY, 2>), grid, block, 0, H->stream, p);
+        else
+            hipLaunchKernelGGL((dpmlk::k_step_march3d<T, RY, 1>), grid, block, 0, H->stream, p);
     }
     HIP_TRY(H, hipGetLastError());
     return DPML_OK;
@@ -564,7 +588,7 @@ int dpml_record_plane(dpml_t *H, int32_t axis, int64_t index, void *planes, int6
 int dpml_set_variant(dpml_t *H, int32_t variant, int32_t tile_rows)
 {
     if (!H) return DPML_EINVAL;
-    if (variant < DPML_VARIANT_AUTO || variant > DPML_VARIANT_MARCH || tile_rows < 0 || tile_rows > 4096)
+    if (variant < DPML_VARIANT_AUTO || variant > DPML_VARIANT_MARCH1 || tile_rows < 0 || tile_rows > 4096)
         return H->fail(DPML_EINVAL, "bad variant");
     H->variant = variant;
     H->tile_rows = tile_rows;
@@ -693,6 +717,9 @@ void dpml_destroy(dpml_t *H)
 {
     if (!H) return;
     (void)hipStreamSynchronize(H->stream);
+    if (H->exec) (void)hipGraphExecDestroy(H->exec);
+    if (H->graph) (void)hipGraphDestroy(H->graph);
+    if (H->cap) (void)hipStreamDestroy(H->cap);
     if (H->d_src_cells) (void)hipFree(H->d_src_cells);
     if (H->d_src_order) (void)hipFree(H->d_src_order);
     if (H->d_rec_cells) (void)hipFree(H->d_rec_cells);
@@ -975,7 +1002,8 @@ struct MultiLayout {
     int vx = 1;
 };
 
-constexpr int kMultiTileRows = 32;
+constexpr int kMultiTileRows = 4;     // tiles of 64 x 4 cells, one thread per cell
+constexpr int kMultiTileCols = 64;
 
 std::string multi_layout(int64_t count, const dpml_grid_t *grids, MultiLayout &M)
 {
@@ -996,10 +1024,11 @@ std::string multi_layout(int64_t count, const dpml_grid_t *grids, MultiLayout &M
         off += align_up(M.L[p].total);
         even &= M.L[p].N[0] % 2 == 0;
     }
-    M.vx = (dtype == DPML_F32 && even) ? 2 : 1;
+    M.vx = 1;
+    (void)even;
     int64_t nt = 0;
     for (int64_t p = 0; p < count; ++p) {
-        const int64_t tx = (M.L[p].N[0] + 256 * M.vx - 1) / (256 * M.vx);
+        const int64_t tx = (M.L[p].N[0] + kMultiTileCols - 1) / kMultiTileCols;
         const int64_t ty = (M.L[p].N[1] + kMultiTileRows - 1) / kMultiTileRows;
         nt += tx * ty;
     }
@@ -1046,7 +1075,7 @@ int multi_tables(dpml_multi *H, const double *const *sigmas)
             dpml v = problem_view(H, p, q);
             args[p] = make_args<T>(&v);
             args[p].tile_rows = H->tile_rows;
-            args[p].tiles_x = (int)((v.L.N[0] + 256 * H->vx - 1) / (256 * H->vx));
+            args[p].tiles_x = (int)((v.L.N[0] + kMultiTileCols - 1) / kMultiTileCols);
         }
         HIP_TRY(nullptr, hipMemcpy(H->ws + H->off_desc[q], args.data(), args.size() * sizeof(args[0]),
                                    hipMemcpyHostToDevice));
@@ -1054,7 +1083,7 @@ int multi_tables(dpml_multi *H, const double *const *sigmas)
     std::vector<dpmlk::TileRef> tiles;
     tiles.reserve((size_t)H->ntiles);
     for (int64_t p = 0; p < H->count; ++p) {
-        const int tx = (int)((H->L[p].N[0] + 256 * H->vx - 1) / (256 * H->vx));
+        const int tx = (int)((H->L[p].N[0] + kMultiTileCols - 1) / kMultiTileCols);
         const int ty = (int)((H->L[p].N[1] + H->tile_rows - 1) / H->tile_rows);
         for (int y = 0; y < ty; ++y)
             for (int x = 0; x < tx; ++x) tiles.push_back({(int32_t)p, x, y, 0});
@@ -1070,11 +1099,7 @@ int multi_launch(dpml_multi *H, hipStream_t s, int parity)
     const dim3 grid((unsigned)round8((int)H->ntiles)), block(256);
     const auto *probs = (const dpmlk::StepArgs<T> *)(H->ws + H->off_desc[parity]);
     const auto *tiles = (const dpmlk::TileRef *)(H->ws + H->off_tiles);
-    if (H->vx == 2)
-        hipLaunchKernelGGL((dpmlk::k_step_multi2d<T, (sizeof(T) == 4 ? 2 : 1)>), grid, block, 0, s, probs, tiles,
-                           (int)H->ntiles);
-    else
-        hipLaunchKernelGGL((dpmlk::k_step_multi2d<T, 1>), grid, block, 0, s, probs, tiles, (int)H->ntiles);
+    hipLaunchKernelGGL((dpmlk::k_step_multi2d<T>), grid, block, 0, s, probs, tiles, (int)H->ntiles);
     HIP_TRY(nullptr, hipGetLastError());
     return DPML_OK;
 }
@@ -1393,3 +1418,65 @@ int dpml_rk4_field(dpml_t *H, int32_t which, void **ptr, int64_t shape[3])
 int64_t dpml_rk4_time_index(const dpml_t *H) { return H && H->rk_set ? H->rk_n : -1; }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------------------
+// HIP-graph replay of a run of steps on the single-problem handle
+// ---------------------------------------------------------------------------
+namespace {
+
+template <typename T>
+int step_graph_impl(dpml *H, int64_t nsteps)
+{
+    const bool reuse = H->exec && H->graph_steps == nsteps && H->graph_cur == H->cur &&
+                       H->graph_unow == H->u_now && H->graph_variant == H->variant &&
+                       H->graph_rows == H->tile_rows;
+    if (!reuse) {
+        if (H->exec) { (void)hipGraphExecDestroy(H->exec); H->exec = nullptr; }
+        if (H->graph) { (void)hipGraphDestroy(H->graph); H->graph = nullptr; }
+        if (!H->cap) HIP_TRY(H, hipStreamCreateWithFlags(&H->cap, hipStreamNonBlocking));
+        // capture on a private stream with a throw-away copy of the rotation state
+        dpml view = *H;
+        view.stream = H->cap;
+        view.err.clear();
+        HIP_TRY(H, hipStreamBeginCapture(H->cap, hipStreamCaptureModeRelaxed));
+        int rc = DPML_OK;
+        for (int64_t k = 0; k < nsteps && rc == DPML_OK; ++k) {
+            rc = launch_step<T>(&view);
+            std::swap(view.u_now, view.u_old);
+            view.cur = 1 - view.cur;
+        }
+        hipGraph_t g = nullptr;
+        hipError_t e = hipStreamEndCapture(H->cap, &g);
+        view.cap = nullptr; view.graph = nullptr; view.exec = nullptr;   // not owned by the view
+        view.d_src_cells = view.d_src_order = view.d_rec_cells = view.d_rec_sorted = view.d_rec_order = nullptr;
+        if (rc) return H->fail(rc, view.err);
+        if (e != hipSuccess) return hip_fail(H, e, "hipStreamEndCapture");
+        H->graph = g;
+        HIP_TRY(H, hipGraphInstantiate(&H->exec, H->graph, nullptr, nullptr, 0));
+        H->graph_steps = nsteps;
+        H->graph_cur = H->cur;
+        H->graph_unow = H->u_now;
+        H->graph_variant = H->variant;
+        H->graph_rows = H->tile_rows;
+    }
+    HIP_TRY(H, hipGraphLaunch(H->exec, H->stream));
+    if (nsteps & 1) {
+        std::swap(H->u_now, H->u_old);
+        H->cur = 1 - H->cur;
+    }
+    H->n += nsteps;
+    return DPML_OK;
+}
+
+}  // namespace
+
+extern "C" int dpml_step_graph(dpml_t *H, int64_t nsteps)
+{
+    if (!H) return DPML_EINVAL;
+    if (nsteps < 0) return H->fail(DPML_EINVAL, "nsteps < 0");
+    if (!H->state_set) return H->fail(DPML_ESTATE, "dpml_set_state has not been called");
+    if (H->ns > 0 || H->nr > 0 || H->plane_axis >= 0)
+        return H->fail(DPML_EINVAL, "graph replay needs a run without sources, receivers or planes");
+    if (nsteps == 0) return DPML_OK;
+    return H->L.dtype == DPML_F32 ? step_graph_impl<float>(H, nsteps) : step_graph_impl<double>(H, nsteps);
+}

@@ -172,18 +172,37 @@ __device__ __forceinline__ T cell_update(const StepArgs<T> &p, int x, int y, int
     return (T(2) * uc - uold) + p.dt2 * rhs;
 }
 
+// Map a hardware block id to a logical tile so that the blocks one XCD
+// executes (ids congruent mod 8) get consecutive tiles: neighbouring tiles
+// then share their halo rows in that XCD's L2.
+__device__ __forceinline__ int xcd_tile(int b, int nblocks)
+{
+    const int per = nblocks >> 3;   // nblocks is a multiple of 8
+    return (b & 7) * per + (b >> 3);
+}
+
 // ---------------------------------------------------------------------------
-// Variant CELL: one thread per cell, blocks of 64 x 4 (x 1) threads.
+// Variant CELL: one thread per cell; a block of 256 threads covers a
+// (256/TH) x TH tile of an (x, y) row band.  The launch is 1-D and goes
+// through xcd_tile, so the tiles one XCD runs are consecutive in row-major
+// tile order: a tile's halo rows are read by its vertical neighbours on the
+// same XCD at nearly the same time and are served by that XCD's L2.
 // ---------------------------------------------------------------------------
-template <typename T, int D>
+template <typename T, int D, int TH>
 __global__ void __launch_bounds__(256) k_step_cell(StepArgs<T> p)
 {
-    const int x = blockIdx.x * 64 + threadIdx.x;
-    const int y = blockIdx.y * 4 + threadIdx.y;
-    const int z = D == 3 ? (int)(blockIdx.z % p.nz) : 0;
-    const int bi = D == 3 ? (int)(blockIdx.z / p.nz) : (int)blockIdx.z;
+    constexpr int TW = 256 / TH;
+    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+    if (tile >= p.n_tiles) return;
+    select_member(p, (int)blockIdx.y);
+    const int per_plane = p.tiles_x * p.tiles_y;
+    const int z = D == 3 ? tile / per_plane : 0;
+    const int rem = tile - z * per_plane;
+    const int ty = rem / p.tiles_x;
+    const int tx = rem - ty * p.tiles_x;
+    const int x = tx * TW + (int)(threadIdx.x % TW);
+    const int y = ty * TH + (int)(threadIdx.x / TW);
     if (x >= p.nx || y >= p.ny) return;
-    select_member(p, bi);
     const int64_t nx = p.nx, ny = p.ny;
     const int64_t row = ((int64_t)z * ny + y) * nx;
     const int64_t idx = row + x;
@@ -204,15 +223,6 @@ __global__ void __launch_bounds__(256) k_step_cell(StepArgs<T> p)
     const T r = cell_update<T, D>(p, x, y, z, idx, u[idx], uxm, uxp, uym, uyp, uzm, uzp, p.uo[idx]);
     p.uo[idx] = r;
     if (p.hist) p.hist[idx] = r;
-}
-
-// Map a hardware block id to a logical tile so that the blocks one XCD
-// executes (ids congruent mod 8) get consecutive tiles: neighbouring tiles
-// then share their halo rows in that XCD's L2.
-__device__ __forceinline__ int xcd_tile(int b, int nblocks)
-{
-    const int per = nblocks >> 3;   // nblocks is a multiple of 8
-    return (b & 7) * per + (b >> 3);
 }
 
 // ---------------------------------------------------------------------------
@@ -336,13 +346,13 @@ __device__ __forceinline__ void march2d_tile(const StepArgs<T> &p, int tx, int t
     }
 }
 
-template <typename T, int VX>
+template <typename T, int VX, int R>
 __global__ void __launch_bounds__(256) k_step_march2d(StepArgs<T> p)
 {
     const int tile = xcd_tile(blockIdx.x, gridDim.x);
     if (tile >= p.n_tiles) return;
     select_member(p, (int)blockIdx.y);
-    march2d_tile<T, VX, 4>(p, tile % p.tiles_x, tile / p.tiles_x);
+    march2d_tile<T, VX, R>(p, tile % p.tiles_x, tile / p.tiles_x);
 }
 
 // ---------------------------------------------------------------------------
@@ -355,7 +365,31 @@ struct TileRef {
     int32_t prob, tx, ty, pad;
 };
 
-template <typename T, int VX>
+// One (256/TH) x TH cell tile of a 2D problem, one thread per cell (the body
+// of the CELL variant, shared with the multi-problem kernel).
+template <typename T, int TH>
+__device__ __forceinline__ void cell2d_tile(const StepArgs<T> &p, int tx, int ty)
+{
+    constexpr int TW = 256 / TH;
+    const int x = tx * TW + (int)(threadIdx.x % TW);
+    const int y = ty * TH + (int)(threadIdx.x / TW);
+    if (x >= p.nx || y >= p.ny) return;
+    const int64_t nx = p.nx;
+    const int64_t row = (int64_t)y * nx;
+    const int64_t idx = row + x;
+    const T *u = p.u;
+    const int xm = wrap_dec(x, p.nx), xp = wrap_inc(x, p.nx);
+    const int ym = wrap_dec(y, p.ny), yp = wrap_inc(y, p.ny);
+    const T uxm = (p.ax[0].wall && x == 0) ? T(0) : u[row + xm];
+    const T uxp = (p.ax[0].wall && x == p.nx - 1) ? T(0) : u[row + xp];
+    const T uym = (p.ax[1].wall && y == 0) ? T(0) : u[(int64_t)ym * nx + x];
+    const T uyp = (p.ax[1].wall && y == p.ny - 1) ? T(0) : u[(int64_t)yp * nx + x];
+    const T r = cell_update<T, 2>(p, x, y, 0, idx, u[idx], uxm, uxp, uym, uyp, T(0), T(0), p.uo[idx]);
+    p.uo[idx] = r;
+    if (p.hist) p.hist[idx] = r;
+}
+
+template <typename T>
 __global__ void __launch_bounds__(256) k_step_multi2d(const StepArgs<T> *__restrict__ probs,
                                                       const TileRef *__restrict__ tiles, int ntiles)
 {
@@ -363,7 +397,7 @@ __global__ void __launch_bounds__(256) k_step_multi2d(const StepArgs<T> *__restr
     if (tile >= ntiles) return;
     const TileRef t = tiles[tile];
     const StepArgs<T> p = probs[t.prob];
-    march2d_tile<T, VX, 4>(p, t.tx, t.ty);
+    cell2d_tile<T, 4>(p, t.tx, t.ty);
 }
 
 // ---------------------------------------------------------------------------

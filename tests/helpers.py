@@ -113,6 +113,7 @@ def run_with_peaks(g, state, steps, n, lo, hi, chunks=10, **kw):
                 key = "%s%d" % (kind, a)
                 peaks[key] = max(peaks.get(key, 0.0), float(np.max(np.abs(arr[m]))))
 
+    kw.setdefault("nt", state.n + steps)
     upd(state)
     done = 0
     traces = None

@@ -54,8 +54,9 @@ def test_bump2d_parity(dtype, variant):
 
 
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
-@pytest.mark.parametrize("variant,tile_rows", [(dp.VARIANT_CELL, 0), (dp.VARIANT_MARCH, 0),
-                                               (dp.VARIANT_MARCH, 7)])
+@pytest.mark.parametrize("variant,tile_rows", [(dp.VARIANT_CELL, 0), (dp.VARIANT_CELL, 1), (dp.VARIANT_CELL, 8),
+                                               (dp.VARIANT_MARCH, 0), (dp.VARIANT_MARCH, 7),
+                                               (dp.VARIANT_MARCH1, 5)])
 def test_ragged_2d_random_damping(dtype, variant, tile_rows):
     """Odd extents (several tiles plus ragged tails), unequal sides, one side
     without a layer, random damping (Fig. 3 profile), white-noise data."""
@@ -80,13 +81,15 @@ def test_axis_without_layer_and_odd_width(dtype):
 
 
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
-@pytest.mark.parametrize("variant", [dp.VARIANT_CELL, dp.VARIANT_MARCH])
-def test_3d_parity(dtype, variant):
+@pytest.mark.parametrize("variant,tile_rows", [(dp.VARIANT_CELL, 4), (dp.VARIANT_CELL, 2),
+                                               (dp.VARIANT_MARCH, 0), (dp.VARIANT_MARCH, 9),
+                                               (dp.VARIANT_MARCH1, 7)])
+def test_3d_parity(dtype, variant, tile_rows):
     rng = np.random.default_rng(8)
     n, lo, hi = [45, 38, 33], [6, 3, 7], [4, 8, 5]
     sig = [synthetic.sigma_random(n[a], lo[a], hi[a], 2.0, rng) for a in range(3)]
     U0 = synthetic.gaussian_sum(n, lo, hi, 6, 2.0, 5.0, rng)
-    errs = _run_both(n, lo, hi, sig, U0, 80, dtype, variant, dt=0.4)
+    errs = _run_both(n, lo, hi, sig, U0, 80, dtype, variant, dt=0.4, tile_rows=tile_rows)
     _assert_errs(errs, dtype)
 
 
@@ -240,3 +243,28 @@ def test_reflecting_walls_match_oracle(dtype, ndim, variant, walls):
     ref, _, peaks = run_with_peaks(g, oracle.start(g, U0), steps, n, lo, hi)
     sim.close()
     _assert_errs(compare_states(gs, ref, n, lo, hi, peaks if dtype == "f32" else None), dtype)
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_graph_replay_matches_eager(dtype):
+    """Steps replayed from a captured HIP graph: every replay (with eager work
+    and synchronisations between replays) equals eager stepping bit for bit;
+    odd lengths flip the buffer parity and force a recapture."""
+    w = synthetic.bump2d(128, 16, 0)
+    a = dp.Simulation(w.n, w.lo, w.hi, w.h, w.dt, w.sigma, dtype=_dtype(dtype))
+    b = dp.Simulation(w.n, w.lo, w.hi, w.h, w.dt, w.sigma, dtype=_dtype(dtype))
+    a.set_state(torch.from_numpy(w.U0))
+    b.set_state(torch.from_numpy(w.U0))
+    for rep, k in enumerate([10, 10, 10, 7, 7, 10]):
+        a.step_graph(k)
+        b.step(k)
+        _ = torch.ones(4096, device="cuda").sum().item()
+        a.sync()
+        b.sync()
+        assert np.array_equal(a.U.cpu().numpy(), b.U.cpu().numpy()), rep
+        assert a.time_index == b.time_index
+    sa, sb = gpu_state(a), gpu_state(b)
+    for k in range(2):
+        assert np.array_equal(sa.Phi[k], sb.Phi[k]) and np.array_equal(sa.Psi[k], sb.Psi[k])
+    a.close()
+    b.close()
