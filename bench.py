@@ -194,6 +194,34 @@ def bench_ricker3d(steps: int):
             "launch": {"variant": choice["variant"], "tile_rows": choice["tile_rows"], "autotuned": True}}
 
 
+def bench_small(steps: int = 500):
+    """The 128^2 + 16-cell (160^2 cells) FP64 parity workload, 500 steps: a
+    step is far shorter than a kernel launch, so it measures the step loop:
+    eager launches against one HIP-graph replay of the whole run."""
+    import torch
+    import paper_1804_01390_amd as dp
+    import synthetic
+    w = synthetic.bump2d(128, 16, steps)
+    sim = dp.Simulation(w.n, w.lo, w.hi, w.h, w.dt, w.sigma, dtype=torch.float64)
+    out = {"workload": "2D 128^2 + 16-cell layer (160^2 cells), FP64, %d steps" % steps}
+    for mode in ("eager", "graph"):
+        sim.set_state(torch.from_numpy(w.U0))
+        (sim.step_graph if mode == "graph" else sim.step)(steps)    # warm (graph: capture)
+        sim.set_state(torch.from_numpy(w.U0))
+        sim.sync()
+        e0, e1 = _events()
+        e0.record()
+        (sim.step_graph if mode == "graph" else sim.step)(steps)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        out[mode + "_us_per_step"] = round(ms * 1e3 / steps, 3)
+        out[mode + "_value"] = round(w.cells * steps / (ms * 1e-3) / 1e9, 3)
+    out["unit"] = "Gcell/s"
+    sim.close()
+    return out
+
+
 def bench_batch(steps: int, count: int):
     """``count`` independent 2D problems (sides log-uniform in [256, 1536],
     16-32-cell layers), FP32, one Gaussian each: one HIP-graph launch for the
@@ -377,6 +405,9 @@ def main():
         "runs": runs,
     }
     if not args.quick:
+        log("small: 160^2 FP64 x 500 steps, eager vs graph")
+        out["small"] = bench_small()
+        log("  %s" % out["small"])
         log("ricker3d: %d steps" % args.steps_3d)
         out["ricker3d"] = bench_ricker3d(args.steps_3d)
         log("  %s" % out["ricker3d"])
