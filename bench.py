@@ -349,6 +349,7 @@ def main():
     ap.add_argument("--batch-steps", type=int, default=1500)
     ap.add_argument("--batch-count", type=int, default=256)
     ap.add_argument("--steps-3d", type=int, default=1000)
+    ap.add_argument("--only", default="", help="run a single section: ricker3d, batch, adjoint or small")
     args = ap.parse_args()
     if args.copy_probe:
         copy_probe()
@@ -358,6 +359,13 @@ def main():
               "with halo exchange; that path is not built); use --gpus 1", file=sys.stderr)
         sys.exit(2)
 
+    if args.only:
+        fn = {"ricker3d": lambda: bench_ricker3d(args.steps_3d),
+              "batch": lambda: bench_batch(args.batch_steps, args.batch_count),
+              "adjoint": lambda: bench_adjoint(args.adjoint_steps, 32),
+              "small": bench_small}[args.only]
+        print(json.dumps({args.only: fn()}), flush=True)
+        return
     import synthetic
     w = synthetic.bumps2d(n=4096, m=32, steps=2000, seed=0)
     runs = []

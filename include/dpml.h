@@ -86,6 +86,11 @@ extern "C" {
                                  4 (2D; 3D FP32) or 2 (3D FP64) rows/planes issued
                                  together; tile_rows = rows (planes) per tile        */
 #define DPML_VARIANT_MARCH1 3 /* as MARCH, one row (plane) at a time                 */
+#define DPML_VARIANT_TWOSTEP 4 /* 2D periodic runs without sources/receivers/planes:
+                                  two steps per pass over the layer-free core
+                                  (temporal blocking: U^n and U^{n+1} staged in LDS,
+                                  2 words per cell per step), the frame holding the
+                                  layer in single steps; otherwise as CELL            */
 
 typedef struct dpml_grid {
     int32_t ndim;    /* 2 or 3 */

@@ -41,7 +41,7 @@ struct Layout {
     int64_t batch = 1;                  // independent problems sharing c^2 and sigma
     int64_t aux_elems[3] = {0, 0, 0};   // elements of one compact aux array (one problem)
     // byte offsets into the workspace
-    size_t off_u[2] = {0, 0};
+    size_t off_u[4] = {0, 0, 0, 0};     // U^n, U^{n-1} and two spares (two-step variant)
     size_t off_c2 = 0;
     size_t off_phi[3][2] = {{0, 0}, {0, 0}, {0, 0}};
     size_t off_psi[3][2] = {{0, 0}, {0, 0}, {0, 0}};
@@ -82,8 +82,7 @@ std::string make_layout(const dpml_grid_t *g, bool c2_field, Layout &L)
     if (L.ncell * L.batch > ((int64_t)1 << 40)) return "grid too large";
     size_t off = 0;
     const size_t ubytes = align_up((size_t)(L.ncell * L.batch) * L.esize);
-    L.off_u[0] = off; off += ubytes;
-    L.off_u[1] = off; off += ubytes;
+    for (int k = 0; k < 4; ++k) { L.off_u[k] = off; off += ubytes; }
     if (c2_field) { L.off_c2 = off; off += align_up((size_t)L.ncell * L.esize); }
     for (int a = 0; a < L.ndim; ++a) {
         if (L.M[a] == 0) continue;
@@ -100,6 +99,8 @@ std::string make_layout(const dpml_grid_t *g, bool c2_field, Layout &L)
     return "";
 }
 
+using TileRefVec = std::vector<dpmlk::TileRef>;
+
 }  // namespace
 
 struct dpml {
@@ -115,6 +116,9 @@ struct dpml {
     bool state_set = false;
     int variant = DPML_VARIANT_AUTO;
     int tile_rows = 0;
+    TileRefVec frame;                // frame tiles of the two-step variant (host copy)
+    dpmlk::TileRef *d_frame = nullptr;
+    int64_t n_frame = 0;
     // sources
     int64_t ns = 0, nt_src = 0;
     int64_t *d_src_cells = nullptr, *d_src_order = nullptr;
@@ -136,8 +140,10 @@ struct dpml {
     hipGraphExec_t exec = nullptr;
     int64_t graph_steps = -1;
     int graph_cur = -1;
-    void *graph_unow = nullptr;
+    void *graph_unow = nullptr, *graph_uold = nullptr;
     int graph_variant = -1, graph_rows = -1;
+    void *graph_end_unow = nullptr, *graph_end_uold = nullptr;
+    int graph_end_cur = 0;
     // RK4 integrator state (caller-owned workspace)
     char *rk_ws = nullptr;
     int rk_role[4] = {0, 1, 2, 3};   // buffer sets holding Y0, YS0, YS1, S
@@ -211,6 +217,8 @@ dpmlk::StepArgs<T> make_args(dpml *H)
     p.bstride = L.ncell;
     for (int a = 0; a < 3; ++a) p.bstride_aux[a] = L.aux_elems[a];
     p.hist = nullptr;
+    p.uout = nullptr;
+    p.skip[0] = p.skip[1] = p.skip[2] = p.skip[3] = 0;
     return p;
 }
 
@@ -223,7 +231,8 @@ int launch_step(dpml *H, T *hist = nullptr)
     dpmlk::StepArgs<T> p = make_args<T>(H);
     p.hist = hist;
     const unsigned B = (unsigned)L.batch;
-    int variant = H->variant == DPML_VARIANT_AUTO ? DPML_VARIANT_CELL : H->variant;
+    int variant = (H->variant == DPML_VARIANT_AUTO || H->variant == DPML_VARIANT_TWOSTEP) ? DPML_VARIANT_CELL
+                                                                                        : H->variant;
     if (variant == DPML_VARIANT_CELL) {
         // tile_rows selects the block shape: TH rows of 256/TH cells (TH = 1, 2, 4, 8)
         const int th = (H->tile_rows == 1 || H->tile_rows == 2 || H->tile_rows == 8) ? H->tile_rows : 4;
@@ -316,10 +325,113 @@ int launch_epilogue(dpml *H)
     return DPML_OK;
 }
 
+// Core rectangle of the two-step variant: cells whose one-cell halo is free
+// of damping terms, [lo+2, lo+n-1) per axis (empty when n < 4).
+void core_rect(const Layout &L, int r[4])
+{
+    for (int a = 0; a < 2; ++a) {
+        r[2 * a] = L.lo[a] + 2;
+        r[2 * a + 1] = (int)(L.lo[a] + L.n[a] - 1);
+        if (L.M[a] == 0) { r[2 * a] = 0; r[2 * a + 1] = (int)L.N[a]; }   // no layer: the whole axis
+    }
+}
+
+// Can this handle take two steps per launch right now?
+bool twostep_ok(const dpml *H)
+{
+    const Layout &L = H->L;
+    if (H->variant != DPML_VARIANT_TWOSTEP || L.ndim != 2) return false;
+    if (L.wall[0] || L.wall[1]) return false;
+    if (H->ns > 0 || (H->recording && (H->nr > 0 || H->plane_axis >= 0))) return false;
+    int r[4];
+    core_rect(L, r);
+    // the core kernel's tiles are 64 x (32 or 16) cells; its halo indices stay within one
+    // periodic wrap of the grid when each extent covers a tile plus its 2-cell halos
+    return r[1] - r[0] >= 1 && r[3] - r[2] >= 1 && L.N[0] >= 64 + 4 && L.N[1] >= 32 + 4;
+}
+
+int ensure_frame(dpml *H)
+{
+    if (H->d_frame) return DPML_OK;
+    const Layout &L = H->L;
+    int r[4];
+    core_rect(L, r);
+    const int tx = (int)((L.N[0] + 63) / 64), ty = (int)((L.N[1] + 3) / 4);
+    H->frame.clear();
+    for (int y = 0; y < ty; ++y)
+        for (int x = 0; x < tx; ++x) {
+            const int xa = x * 64, xb = std::min<int>(xa + 64, (int)L.N[0]);
+            const int ya = y * 4, yb = std::min<int>(ya + 4, (int)L.N[1]);
+            const bool inside = xa >= r[0] && xb <= r[1] && ya >= r[2] && yb <= r[3];
+            if (!inside) H->frame.push_back({0, x, y, 0});
+        }
+    H->n_frame = (int64_t)H->frame.size();
+    if (H->n_frame == 0) return DPML_OK;
+    HIP_TRY(H, hipMalloc((void **)&H->d_frame, H->frame.size() * sizeof(dpmlk::TileRef)));
+    HIP_TRY(H, hipMemcpy(H->d_frame, H->frame.data(), H->frame.size() * sizeof(dpmlk::TileRef),
+                         hipMemcpyHostToDevice));
+    return DPML_OK;
+}
+
+// Two steps: core tiles in one launch, the frame in two single steps.
+template <typename T>
+int launch_twostep(dpml *H)
+{
+    const Layout &L = H->L;
+    const unsigned B = (unsigned)L.batch;
+    void *bufs[4] = {H->at(L.off_u[0]), H->at(L.off_u[1]), H->at(L.off_u[2]), H->at(L.off_u[3])};
+    void *spare[2];
+    int k = 0;
+    for (int q = 0; q < 4; ++q)
+        if (bufs[q] != H->u_now && bufs[q] != H->u_old) spare[k++] = bufs[q];
+    T *A = (T *)H->u_now, *Bv = (T *)H->u_old, *C = (T *)spare[0], *D = (T *)spare[1];
+    int r[4];
+    core_rect(L, r);
+    constexpr int TW = 64, TH = sizeof(T) == 4 ? 32 : 16;
+    const int tiles_x = (r[1] - r[0] + TW - 1) / TW, tiles_y = (r[3] - r[2] + TH - 1) / TH;
+    const int n_tiles = tiles_x * tiles_y;
+    dpmlk::StepArgs<T> p = make_args<T>(H);
+    if (n_tiles > 0) {
+        dim3 grid((unsigned)round8(n_tiles), B), block(256);
+        hipLaunchKernelGGL((dpmlk::k_step2_core<T, TW, TH>), grid, block, 0, H->stream, p, (const T *)Bv, C, D,
+                           r[0], r[1], r[2], r[3], tiles_x, n_tiles);
+    }
+    if (H->n_frame > 0) {
+        dim3 grid((unsigned)round8((int)H->n_frame), B), block(256);
+        // step n -> n+1 on the frame: read A (U^n), B (U^{n-1}); write C
+        p.uout = C;
+        for (int q = 0; q < 4; ++q) p.skip[q] = r[q];
+        hipLaunchKernelGGL((dpmlk::k_step_frame<T>), grid, block, 0, H->stream, p, H->d_frame, (int)H->n_frame);
+        // step n+1 -> n+2 on the frame: read C (U^{n+1}), A (U^n); write D; aux buffers swap
+        H->cur = 1 - H->cur;
+        dpmlk::StepArgs<T> p2 = make_args<T>(H);
+        H->cur = 1 - H->cur;
+        p2.u = C;
+        p2.uo = A;
+        p2.uout = D;
+        for (int q = 0; q < 4; ++q) p2.skip[q] = r[q];
+        hipLaunchKernelGGL((dpmlk::k_step_frame<T>), grid, block, 0, H->stream, p2, H->d_frame, (int)H->n_frame);
+    }
+    HIP_TRY(H, hipGetLastError());
+    H->u_now = D;
+    H->u_old = C;
+    H->n += 2;      // H->cur flips twice
+    return DPML_OK;
+}
+
 template <typename T>
 int step_impl(dpml *H, int64_t nsteps)
 {
-    for (int64_t k = 0; k < nsteps; ++k) {
+    int64_t k = 0;
+    if (nsteps >= 2 && twostep_ok(H)) {
+        int rc = ensure_frame(H);
+        if (rc) return rc;
+        for (; k + 2 <= nsteps; k += 2) {
+            rc = launch_twostep<T>(H);
+            if (rc) return rc;
+        }
+    }
+    for (; k < nsteps; ++k) {
         int rc = launch_step<T>(H);
         if (rc) return rc;
         rc = launch_epilogue<T>(H);
@@ -588,7 +700,7 @@ int dpml_record_plane(dpml_t *H, int32_t axis, int64_t index, void *planes, int6
 int dpml_set_variant(dpml_t *H, int32_t variant, int32_t tile_rows)
 {
     if (!H) return DPML_EINVAL;
-    if (variant < DPML_VARIANT_AUTO || variant > DPML_VARIANT_MARCH1 || tile_rows < 0 || tile_rows > 4096)
+    if (variant < DPML_VARIANT_AUTO || variant > DPML_VARIANT_TWOSTEP || tile_rows < 0 || tile_rows > 4096)
         return H->fail(DPML_EINVAL, "bad variant");
     H->variant = variant;
     H->tile_rows = tile_rows;
@@ -723,6 +835,7 @@ void dpml_destroy(dpml_t *H)
     if (H->d_src_cells) (void)hipFree(H->d_src_cells);
     if (H->d_src_order) (void)hipFree(H->d_src_order);
     if (H->d_rec_cells) (void)hipFree(H->d_rec_cells);
+    if (H->d_frame) (void)hipFree(H->d_frame);
     if (H->d_rec_sorted) (void)hipFree(H->d_rec_sorted);
     if (H->d_rec_order) (void)hipFree(H->d_rec_order);
     delete H;
@@ -825,6 +938,8 @@ int adjoint_impl(dpml *H, const void *resid, double *grad, void *grad_w)
     H->recording = false;
     dim3 block(64, 4, 1);
     dim3 grid((unsigned)((L.N[0] + 63) / 64), (unsigned)((L.N[1] + 3) / 4), (unsigned)(L.ndim == 3 ? L.N[2] : 1));
+    const int adj_tiles = (int)(((L.N[0] + 63) / 64) * ((L.N[1] + 3) / 4) * (L.ndim == 3 ? L.N[2] : 1));
+    const dim3 agrid((unsigned)round8(adj_tiles)), ablock(256);
     for (int64_t seg = A.nck - 1; seg >= 0; --seg) {
         const int64_t t0 = seg * every, t1 = std::min(t0 + every, nsteps);
         // restore the checkpoint and recompute U^{t0} .. U^{t1-1} into the history
@@ -894,9 +1009,9 @@ int adjoint_impl(dpml *H, const void *resid, double *grad, void *grad_w)
             q.batch = (int32_t)L.batch;
             q.bstride = L.ncell;
             if (L.ndim == 2)
-                hipLaunchKernelGGL((dpmlk::k_adjoint_cell<T, 2>), grid, block, 0, H->stream, q);
+                hipLaunchKernelGGL((dpmlk::k_adjoint_cell<T, 2>), agrid, ablock, 0, H->stream, q);
             else
-                hipLaunchKernelGGL((dpmlk::k_adjoint_cell<T, 3>), grid, block, 0, H->stream, q);
+                hipLaunchKernelGGL((dpmlk::k_adjoint_cell<T, 3>), agrid, ablock, 0, H->stream, q);
             HIP_TRY(H, hipGetLastError());
             lcur = 1 - lcur;
             acur = 1 - acur;
@@ -1428,8 +1543,8 @@ template <typename T>
 int step_graph_impl(dpml *H, int64_t nsteps)
 {
     const bool reuse = H->exec && H->graph_steps == nsteps && H->graph_cur == H->cur &&
-                       H->graph_unow == H->u_now && H->graph_variant == H->variant &&
-                       H->graph_rows == H->tile_rows;
+                       H->graph_unow == H->u_now && H->graph_uold == H->u_old &&
+                       H->graph_variant == H->variant && H->graph_rows == H->tile_rows;
     if (!reuse) {
         if (H->exec) { (void)hipGraphExecDestroy(H->exec); H->exec = nullptr; }
         if (H->graph) { (void)hipGraphDestroy(H->graph); H->graph = nullptr; }
@@ -1438,17 +1553,21 @@ int step_graph_impl(dpml *H, int64_t nsteps)
         dpml view = *H;
         view.stream = H->cap;
         view.err.clear();
-        HIP_TRY(H, hipStreamBeginCapture(H->cap, hipStreamCaptureModeRelaxed));
-        int rc = DPML_OK;
-        for (int64_t k = 0; k < nsteps && rc == DPML_OK; ++k) {
-            rc = launch_step<T>(&view);
-            std::swap(view.u_now, view.u_old);
-            view.cur = 1 - view.cur;
+        if (twostep_ok(H)) {                 // the frame table must exist before capture
+            int rcf = ensure_frame(H);
+            if (rcf) return rcf;
+            view.d_frame = H->d_frame;
+            view.n_frame = H->n_frame;
         }
-        hipGraph_t g = nullptr;
+        HIP_TRY(H, hipStreamBeginCapture(H->cap, hipStreamCaptureModeRelaxed));
+        int rc = step_impl<T>(&view, nsteps);        hipGraph_t g = nullptr;
         hipError_t e = hipStreamEndCapture(H->cap, &g);
         view.cap = nullptr; view.graph = nullptr; view.exec = nullptr;   // not owned by the view
         view.d_src_cells = view.d_src_order = view.d_rec_cells = view.d_rec_sorted = view.d_rec_order = nullptr;
+        view.d_frame = nullptr;
+        H->graph_end_unow = view.u_now;
+        H->graph_end_uold = view.u_old;
+        H->graph_end_cur = view.cur;
         if (rc) return H->fail(rc, view.err);
         if (e != hipSuccess) return hip_fail(H, e, "hipStreamEndCapture");
         H->graph = g;
@@ -1456,14 +1575,14 @@ int step_graph_impl(dpml *H, int64_t nsteps)
         H->graph_steps = nsteps;
         H->graph_cur = H->cur;
         H->graph_unow = H->u_now;
+        H->graph_uold = H->u_old;
         H->graph_variant = H->variant;
         H->graph_rows = H->tile_rows;
     }
     HIP_TRY(H, hipGraphLaunch(H->exec, H->stream));
-    if (nsteps & 1) {
-        std::swap(H->u_now, H->u_old);
-        H->cur = 1 - H->cur;
-    }
+    H->u_now = H->graph_end_unow;
+    H->u_old = H->graph_end_uold;
+    H->cur = H->graph_end_cur;
     H->n += nsteps;
     return DPML_OK;
 }

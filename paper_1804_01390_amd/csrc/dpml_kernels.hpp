@@ -66,6 +66,8 @@ struct StepArgs {
     int64_t bstride;  // elements between batch members in U
     int64_t bstride_aux[3];  // elements between batch members in Phi_a/Psi_a
     T *hist;          // optional: also store U^{n+1} here (same layout as U), or nullptr
+    T *uout;          // optional: write U^{n+1} here instead of over U^{n-1}
+    int32_t skip[4];  // cells with skip[0] <= x < skip[1], skip[2] <= y < skip[3] are left alone
 };
 
 // Point the step arguments at batch member bi.
@@ -76,6 +78,7 @@ __device__ __forceinline__ void select_member(StepArgs<T> &p, int bi)
     p.u += o;
     p.uo += o;
     if (p.hist) p.hist += o;
+    if (p.uout) p.uout += o;
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         const int64_t oa = (int64_t)bi * p.bstride_aux[a];
@@ -85,6 +88,10 @@ __device__ __forceinline__ void select_member(StepArgs<T> &p, int bi)
         p.ax[a].psi_o += oa;
     }
 }
+
+struct TileRef {
+    int32_t prob, tx, ty, pad;
+};
 
 __device__ __forceinline__ int wrap_dec(int i, int n) { return i == 0 ? n - 1 : i - 1; }
 __device__ __forceinline__ int wrap_inc(int i, int n) { return i == n - 1 ? 0 : i + 1; }
@@ -361,10 +368,6 @@ __global__ void __launch_bounds__(256) k_step_march2d(StepArgs<T> p)
 // block looks up its problem's arguments (uniform, read through the scalar
 // cache) and runs one marching tile.
 // ---------------------------------------------------------------------------
-struct TileRef {
-    int32_t prob, tx, ty, pad;
-};
-
 // One (256/TH) x TH cell tile of a 2D problem, one thread per cell (the body
 // of the CELL variant, shared with the multi-problem kernel).
 template <typename T, int TH>
@@ -385,8 +388,92 @@ __device__ __forceinline__ void cell2d_tile(const StepArgs<T> &p, int tx, int ty
     const T uym = (p.ax[1].wall && y == 0) ? T(0) : u[(int64_t)ym * nx + x];
     const T uyp = (p.ax[1].wall && y == p.ny - 1) ? T(0) : u[(int64_t)yp * nx + x];
     const T r = cell_update<T, 2>(p, x, y, 0, idx, u[idx], uxm, uxp, uym, uyp, T(0), T(0), p.uo[idx]);
-    p.uo[idx] = r;
+    (p.uout ? p.uout : p.uo)[idx] = r;
     if (p.hist) p.hist[idx] = r;
+}
+
+// ---------------------------------------------------------------------------
+// Two steps per launch (temporal blocking), 2D, periodic grids.
+//
+// Interior tiles -- tiles whose cells and one-cell halo lie where no damping
+// term acts (the "core" [lo+2, lo+n-2) per axis) -- advance two levels in one
+// pass: U^n with a 2-cell halo is staged in LDS, U^{n+1} is computed on the
+// tile plus a 1-cell halo into LDS (and stored), then U^{n+2} on the tile.
+// Reads U^n, U^{n-1}; writes U^{n+1}, U^{n+2} into two other buffers: 2 words
+// per cell per step instead of 3.  The frame outside the core (the layer plus
+// a 2-cell margin) takes two ordinary steps with k_step_frame.  The scheme is
+// evaluated in the same operation order as cell_update (no damping terms act
+// in the core), so results are bit-identical to single steps.
+// ---------------------------------------------------------------------------
+template <typename T, int TW, int TH>
+__global__ void __launch_bounds__(256) k_step2_core(StepArgs<T> p, const T *__restrict__ u_prev,
+                                                    T *__restrict__ u_next1, T *__restrict__ u_next2,
+                                                    int cx0, int cx1, int cy0, int cy1, int tiles_x, int n_tiles)
+{
+    __shared__ T s0[TH + 4][TW + 4];     // U^n, tile + 2-cell halo
+    __shared__ T s1[TH + 2][TW + 2];     // U^{n+1}, tile + 1-cell halo
+    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+    if (tile >= n_tiles) return;         // uniform per block: no barrier is skipped by part of it
+    const int64_t boff = (int64_t)blockIdx.y * p.bstride;
+    const T *u = p.u + boff;
+    u_prev += boff;
+    u_next1 += boff;
+    u_next2 += boff;
+    const int nx = p.nx, ny = p.ny;
+    const int x0 = cx0 + (tile % tiles_x) * TW;
+    const int y0 = cy0 + (tile / tiles_x) * TH;
+    auto wrapx = [&](int x) { return x < 0 ? x + nx : (x >= nx ? x - nx : x); };
+    auto wrapy = [&](int y) { return y < 0 ? y + ny : (y >= ny ? y - ny : y); };
+    // stage U^n
+    for (int k = threadIdx.x; k < (TH + 4) * (TW + 4); k += 256) {
+        const int r = k / (TW + 4), c = k % (TW + 4);
+        s0[r][c] = u[(int64_t)wrapy(y0 - 2 + r) * nx + wrapx(x0 - 2 + c)];
+    }
+    __syncthreads();
+    // U^{n+1} on the tile and its 1-cell halo
+    for (int k = threadIdx.x; k < (TH + 2) * (TW + 2); k += 256) {
+        const int r = k / (TW + 2), c = k % (TW + 2);
+        const int x = wrapx(x0 - 1 + c), y = wrapy(y0 - 1 + r);
+        const int64_t idx = (int64_t)y * nx + x;
+        const T uc = s0[r + 1][c + 1];
+        T lap = T(0);
+        lap += ((s0[r + 1][c] - T(2) * uc) + s0[r + 1][c + 2]) * p.inv_h2;
+        lap += ((s0[r][c + 1] - T(2) * uc) + s0[r + 2][c + 1]) * p.inv_h2;
+        const T c2 = p.c2 ? p.c2[idx] : p.c2_const;
+        const T v = (T(2) * uc - u_prev[idx]) + p.dt2 * (c2 * lap);
+        s1[r][c] = v;
+        const int gx = x0 - 1 + c, gy = y0 - 1 + r;
+        if (r >= 1 && r <= TH && c >= 1 && c <= TW && gx < cx1 && gy < cy1) u_next1[idx] = v;
+    }
+    __syncthreads();
+    // U^{n+2} on the tile
+    for (int k = threadIdx.x; k < TH * TW; k += 256) {
+        const int r = k / TW, c = k % TW;
+        const int x = x0 + c, y = y0 + r;
+        if (x >= cx1 || y >= cy1) continue;
+        const int64_t idx = (int64_t)y * nx + x;
+        const T uc = s1[r + 1][c + 1];
+        T lap = T(0);
+        lap += ((s1[r + 1][c] - T(2) * uc) + s1[r + 1][c + 2]) * p.inv_h2;
+        lap += ((s1[r][c + 1] - T(2) * uc) + s1[r + 2][c + 1]) * p.inv_h2;
+        const T c2 = p.c2 ? p.c2[idx] : p.c2_const;
+        u_next2[idx] = (T(2) * uc - s0[r + 2][c + 2]) + p.dt2 * (c2 * lap);
+    }
+}
+
+// One ordinary step over a list of 64 x 4 cell tiles (the frame around the
+// core), leaving the core cells (p.skip) alone.
+template <typename T>
+__global__ void __launch_bounds__(256) k_step_frame(StepArgs<T> p, const TileRef *__restrict__ tiles, int ntiles)
+{
+    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+    if (tile >= ntiles) return;
+    select_member(p, (int)blockIdx.y);
+    const TileRef t = tiles[tile];
+    const int x = t.tx * 64 + (int)(threadIdx.x % 64);
+    const int y = t.ty * 4 + (int)(threadIdx.x / 64);
+    if (x >= p.skip[0] && x < p.skip[1] && y >= p.skip[2] && y < p.skip[3]) return;
+    cell2d_tile<T, 4>(p, t.tx, t.ty);
 }
 
 template <typename T>
@@ -659,9 +746,14 @@ __device__ __forceinline__ T pq_at(const Axis<T> &A, int j, int64_t cbase, int64
 template <typename T, int D>
 __global__ void __launch_bounds__(256) k_adjoint_cell(AdjArgs<T> p)
 {
-    const int x = blockIdx.x * 64 + threadIdx.x;
-    const int y = blockIdx.y * 4 + threadIdx.y;
-    const int z = D == 3 ? (int)blockIdx.z : 0;
+    // 1-D XCD-aware launch over 64 x 4 cell tiles (as the forward CELL kernel)
+    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+    const int tiles_x = (p.nx + 63) / 64, tiles_y = (p.ny + 3) / 4;
+    if (tile >= tiles_x * tiles_y * (D == 3 ? p.nz : 1)) return;
+    const int z = D == 3 ? tile / (tiles_x * tiles_y) : 0;
+    const int rem = tile - z * tiles_x * tiles_y;
+    const int x = (rem % tiles_x) * 64 + (int)(threadIdx.x % 64);
+    const int y = (rem / tiles_x) * 4 + (int)(threadIdx.x / 64);
     if (x >= p.nx || y >= p.ny) return;
     const int nx = p.nx, ny = p.ny, nz = p.nz;
     const int64_t sy = nx, sz = (int64_t)nx * ny;
@@ -699,6 +791,7 @@ __global__ void __launch_bounds__(256) k_adjoint_cell(AdjArgs<T> p)
         }
     }
     double gsum = 0.0;
+#pragma unroll 1
     for (int bi = 0; bi < p.batch; ++bi) {
         const int64_t bo = (int64_t)bi * p.bstride;
         const T *lam = p.lam + bo;

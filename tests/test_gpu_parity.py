@@ -268,3 +268,79 @@ def test_graph_replay_matches_eager(dtype):
         assert np.array_equal(sa.Phi[k], sb.Phi[k]) and np.array_equal(sa.Psi[k], sb.Psi[k])
     a.close()
     b.close()
+
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("case", ["bump", "ragged", "onesided", "c2", "batch"])
+def test_twostep_matches_single_steps_and_oracle(dtype, case):
+    """Two steps per pass over the layer-free core (temporal blocking) plus
+    single steps on the frame: bit-identical to single steps, and the oracle
+    agrees; odd step counts end with one single step."""
+    rng = np.random.default_rng(17)
+    c2 = None
+    batch = 1
+    if case == "bump":
+        w = synthetic.bump2d(128, 16, 0)
+        n, lo, hi, sig, U0 = w.n, w.lo, w.hi, w.sigma, w.U0
+    elif case == "ragged":
+        n, lo, hi = [611, 203], [5, 9], [13, 2]
+        sig = [synthetic.sigma_random(n[a], lo[a], hi[a], 2.0, rng) for a in range(2)]
+        U0 = synthetic.white_noise_disk(n, lo, hi, 60.0, 0.25, rng)
+    elif case == "onesided":
+        n, lo, hi = [300, 190], [0, 12], [0, 0]
+        sig = [None, synthetic.sigma_ramp(n[1], 12, 0, 2.0)]
+        U0 = synthetic.gaussian_sum(n, lo, hi, 8, 2.0, 6.0, rng)
+    elif case == "c2":
+        n, lo, hi = [220, 170], [10, 10], [10, 10]
+        sig = [synthetic.sigma_ramp(n[a], 10, 10, 2.0) for a in range(2)]
+        c2 = synthetic.smooth_c2(n, lo, hi, 6, 10.0, 30.0, 0.5, 8, rng)
+        U0 = synthetic.gaussian_sum(n, lo, hi, 10, 2.0, 6.0, rng)
+    else:
+        batch = 3
+        n, lo, hi = [150, 140], [8, 8], [8, 8]
+        sig = [synthetic.sigma_ramp(n[a], 8, 8, 2.0) for a in range(2)]
+        U0 = np.stack([synthetic.gaussian_sum(n, lo, hi, 5, 2.0, 6.0, rng) for _ in range(batch)])
+    dt = 0.5 if c2 is None else 0.5 / math.sqrt(float(np.max(c2)))
+    steps = 121
+    print("case twostep %s %s" % (case, dtype), flush=True)
+    outs = []
+    for variant in (dp.VARIANT_TWOSTEP, dp.VARIANT_CELL):
+        sim = dp.Simulation(n, lo, hi, 1.0, dt, sig, c2=1.0 if c2 is None else c2, dtype=_dtype(dtype), batch=batch)
+        sim.set_variant(variant, 0)
+        sim.set_state(torch.from_numpy(U0))
+        sim.step(steps)
+        sim.sync()
+        outs.append((sim.U.cpu().numpy().copy(), sim.field(dp.FIELD_UPREV).cpu().numpy().copy(),
+                     [sim.field(dp.FIELD_PHI(a)).cpu().numpy().copy() for a in range(2) if lo[a] + hi[a] > 0],
+                     [sim.field(dp.FIELD_PSI(a)).cpu().numpy().copy() for a in range(2) if lo[a] + hi[a] > 0]))
+        if variant == dp.VARIANT_TWOSTEP and batch == 1:
+            gs = gpu_state(sim)
+        sim.close()
+    (a0, a1, a2, a3), (b0, b1, b2, b3) = outs
+    assert np.array_equal(a0, b0) and np.array_equal(a1, b1)
+    for x, y in zip(a2 + a3, b2 + b3):
+        assert np.array_equal(x, y)
+    if batch == 1:
+        N = [lo[a] + n[a] + hi[a] for a in range(2)]
+        g = oracle.Grid(N, 1.0, dt, sig, c2=c2)
+        ref, _, peaks = run_with_peaks(g, oracle.start(g, U0), steps, n, lo, hi)
+        _assert_errs(compare_states(gs, ref, n, lo, hi, peaks if dtype == "f32" else None), dtype)
+
+
+def test_twostep_graph_replay_matches_eager():
+    w = synthetic.bump2d(200, 20, 0)
+    a = dp.Simulation(w.n, w.lo, w.hi, w.h, w.dt, w.sigma, dtype=torch.float32)
+    b = dp.Simulation(w.n, w.lo, w.hi, w.h, w.dt, w.sigma, dtype=torch.float32)
+    a.set_variant(dp.VARIANT_TWOSTEP, 0)
+    a.set_state(torch.from_numpy(w.U0))
+    b.set_state(torch.from_numpy(w.U0))
+    for rep, k in enumerate([10, 10, 7, 7, 10]):
+        a.step_graph(k)
+        b.step(k)
+        _ = torch.ones(4096, device="cuda").sum().item()
+        a.sync()
+        b.sync()
+        assert np.array_equal(a.U.cpu().numpy(), b.U.cpu().numpy()), rep
+    a.close()
+    b.close()
