@@ -260,8 +260,11 @@ def bench_batch(steps: int, count: int):
     ms_sep = e0.elapsed_time(e1)
     for s in sims:
         s.close()
+    ab = sum(alg_bytes_per_step(w, 4) for w in probs)
     return {"workload": "%d 2D problems, sides log-uniform in [256,1536], 16-32-cell layers, FP32, "
                         "%d steps (%d cells per step)" % (count, steps, cells),
+            "alg_bytes_per_step": ab,
+            "graph_alg_GBps": round(ab * steps / (ms_graph * 1e-3) / 1e9, 1),
             "graph_value": round(cells * steps / (ms_graph * 1e-3) / 1e9, 3),
             "separate_value": round(cells * steps / (ms_sep * 1e-3) / 1e9, 3), "unit": "Gcell/s",
             "graph_ms": round(ms_graph, 3), "separate_ms": round(ms_sep, 3),

@@ -82,15 +82,19 @@ extern "C" {
 #define DPML_VARIANT_AUTO 0   /* library default (CELL)                               */
 #define DPML_VARIANT_CELL 1   /* one thread per cell; tile_rows = block rows TH in
                                  {1, 2, 4, 8} (block of 256/TH x TH cells)            */
-#define DPML_VARIANT_MARCH 2  /* tiles marching along the slowest axis, the loads of
-                                 4 (2D; 3D FP32) or 2 (3D FP64) rows/planes issued
-                                 together; tile_rows = rows (planes) per tile        */
-#define DPML_VARIANT_MARCH1 3 /* as MARCH, one row (plane) at a time                 */
+#define DPML_VARIANT_MARCH 2  /* tiles marching along the slowest axis; tile_rows =
+                                 rows (2D) or planes (3D) per tile.  2D: the loads
+                                 of 4 rows issued together.  3D: each wave holds
+                                 64 columns x 4 rows of three planes in registers  */
+#define DPML_VARIANT_MARCH1 3 /* as MARCH; 2D: one row at a time; 3D: waves of 64
+                                 columns x 2 rows                                    */
 #define DPML_VARIANT_TWOSTEP 4 /* 2D periodic runs without sources/receivers/planes:
                                   two steps per pass over the layer-free core
-                                  (temporal blocking: U^n and U^{n+1} staged in LDS,
-                                  2 words per cell per step), the frame holding the
-                                  layer in single steps; otherwise as CELL            */
+                                  (temporal blocking: each wave marches down a
+                                  strip keeping U^n and U^{n+1} rows in registers,
+                                  2 words per cell per step; tile_rows = rows per
+                                  wave, 0 = 32), the frame holding the layer in
+                                  single steps; otherwise as CELL                     */
 
 typedef struct dpml_grid {
     int32_t ndim;    /* 2 or 3 */

@@ -18,12 +18,12 @@ from . import VARIANT_CELL, VARIANT_MARCH, VARIANT_MARCH1, VARIANT_TWOSTEP
 
 DEFAULT_CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "autotune_cache.json")
 
-CANDIDATES_2D: List[Tuple[int, int]] = ([(VARIANT_TWOSTEP, 0)] + [(VARIANT_CELL, th) for th in (1, 2, 4, 8)]
+CANDIDATES_2D: List[Tuple[int, int]] = ([(VARIANT_TWOSTEP, r) for r in (16, 32, 64)] + [(VARIANT_CELL, th) for th in (1, 2, 4, 8)]
                                         + [(VARIANT_MARCH, r) for r in (4, 8, 16)]
                                         + [(VARIANT_MARCH1, r) for r in (4, 8, 16)])
-CANDIDATES_3D: List[Tuple[int, int]] = ([(VARIANT_CELL, th) for th in (1, 2, 4, 8)]
-                                        + [(VARIANT_MARCH, r) for r in (4, 8, 16, 32)]
-                                        + [(VARIANT_MARCH1, r) for r in (4, 8, 16, 32, 64)])
+CANDIDATES_3D: List[Tuple[int, int]] = ([(VARIANT_CELL, th) for th in (2, 4, 8)]
+                                        + [(VARIANT_MARCH, r) for r in (16, 32, 64, 128)]
+                                        + [(VARIANT_MARCH1, r) for r in (16, 32, 64, 128)])
 
 
 def grid_key(sim) -> str:

@@ -268,20 +268,18 @@ int launch_step(dpml *H, T *hist = nullptr)
         else
             hipLaunchKernelGGL((dpmlk::k_step_march2d<T, 1, 1>), grid, block, 0, H->stream, p);
     } else {
-        constexpr int RY = 2;
-        const bool grouped = variant == DPML_VARIANT_MARCH;
-        p.tile_rows = H->tile_rows > 0 ? H->tile_rows : 16;
+        // MARCH: waves of 64 columns x 4 rows; MARCH1: 64 columns x 2 rows
+        const int ry = variant == DPML_VARIANT_MARCH ? 4 : 2;
+        p.tile_rows = H->tile_rows > 0 ? H->tile_rows : 32;
         p.tiles_x = (int)((L.N[0] + 63) / 64);
-        p.tiles_y = (int)((L.N[1] + 4 * RY - 1) / (4 * RY));
+        p.tiles_y = (int)((L.N[1] + 4 * ry - 1) / (4 * ry));
         const int tiles_z = (int)((L.N[2] + p.tile_rows - 1) / p.tile_rows);
         p.n_tiles = p.tiles_x * p.tiles_y * tiles_z;
-        dim3 grid((unsigned)round8(p.n_tiles), B), block(64, 4);
-        if (grouped && sizeof(T) == 4)
-            hipLaunchKernelGGL((dpmlk::k_step_march3d<T, RY, 4>), grid, block, 0, H->stream, p);
-        else if (grouped)
-            hipLaunchKernelGGL((dpmlk::k_step_march3d<T, RY, 2>), grid, block, 0, H->stream, p);
+        dim3 grid((unsigned)round8(p.n_tiles), B), block(256);
+        if (ry == 4)
+            hipLaunchKernelGGL((dpmlk::k_step_zmarch3d<T, 4>), grid, block, 0, H->stream, p);
         else
-            hipLaunchKernelGGL((dpmlk::k_step_march3d<T, RY, 1>), grid, block, 0, H->stream, p);
+            hipLaunchKernelGGL((dpmlk::k_step_zmarch3d<T, 2>), grid, block, 0, H->stream, p);
     }
     HIP_TRY(H, hipGetLastError());
     return DPML_OK;
@@ -325,14 +323,29 @@ int launch_epilogue(dpml *H)
     return DPML_OK;
 }
 
+// Columns per lane of the two-step core kernel.
+int twostep_vx(const Layout &L) { return L.dtype == DPML_F32 ? 4 : 2; }
+
 // Core rectangle of the two-step variant: cells whose one-cell halo is free
-// of damping terms, [lo+2, lo+n-1) per axis (empty when n < 4).
+// of damping terms, inside [lo+2, lo+n-1) per axis; along x it starts on a
+// multiple of the kernel's vector width and spans a multiple of it.  An axis
+// without a layer is core over its whole (periodic) extent.
 void core_rect(const Layout &L, int r[4])
 {
+    const int vx = twostep_vx(L);
     for (int a = 0; a < 2; ++a) {
-        r[2 * a] = L.lo[a] + 2;
-        r[2 * a + 1] = (int)(L.lo[a] + L.n[a] - 1);
-        if (L.M[a] == 0) { r[2 * a] = 0; r[2 * a + 1] = (int)L.N[a]; }   // no layer: the whole axis
+        if (L.M[a] == 0) {
+            r[2 * a] = 0;
+            r[2 * a + 1] = (int)L.N[a];
+            continue;
+        }
+        int b0 = L.lo[a] + 2, b1 = (int)(L.lo[a] + L.n[a] - 1);
+        if (a == 0) {
+            b0 = (b0 + vx - 1) / vx * vx;
+            b1 = b1 > b0 ? b0 + (b1 - b0) / vx * vx : b0;
+        }
+        r[2 * a] = b0;
+        r[2 * a + 1] = std::max(b0, b1);
     }
 }
 
@@ -345,9 +358,8 @@ bool twostep_ok(const dpml *H)
     if (H->ns > 0 || (H->recording && (H->nr > 0 || H->plane_axis >= 0))) return false;
     int r[4];
     core_rect(L, r);
-    // the core kernel's tiles are 64 x (32 or 16) cells; its halo indices stay within one
-    // periodic wrap of the grid when each extent covers a tile plus its 2-cell halos
-    return r[1] - r[0] >= 1 && r[3] - r[2] >= 1 && L.N[0] >= 64 + 4 && L.N[1] >= 32 + 4;
+    // the core kernel wraps halo rows once: each extent must hold its 2-cell halos
+    return r[1] - r[0] >= 1 && r[3] - r[2] >= 1 && L.N[0] >= 4 && L.N[1] >= 4;
 }
 
 int ensure_frame(dpml *H)
@@ -373,7 +385,8 @@ int ensure_frame(dpml *H)
     return DPML_OK;
 }
 
-// Two steps: core tiles in one launch, the frame in two single steps.
+// Two steps: the core and the frame's first step in one launch, the frame's
+// second step in another.
 template <typename T>
 int launch_twostep(dpml *H)
 {
@@ -384,25 +397,33 @@ int launch_twostep(dpml *H)
     int k = 0;
     for (int q = 0; q < 4; ++q)
         if (bufs[q] != H->u_now && bufs[q] != H->u_old) spare[k++] = bufs[q];
-    T *A = (T *)H->u_now, *Bv = (T *)H->u_old, *C = (T *)spare[0], *D = (T *)spare[1];
+    T *A = (T *)H->u_now, *C = (T *)spare[0], *D = (T *)spare[1];
     int r[4];
     core_rect(L, r);
-    constexpr int TW = 64, TH = sizeof(T) == 4 ? 32 : 16;
-    const int tiles_x = (r[1] - r[0] + TW - 1) / TW, tiles_y = (r[3] - r[2] + TH - 1) / TH;
-    const int n_tiles = tiles_x * tiles_y;
+    constexpr int VX = sizeof(T) == 4 ? 4 : 2;
+    const int rows = H->tile_rows > 0 ? H->tile_rows : 32;
+    const int strips = (r[1] - r[0] + 62 * VX - 1) / (62 * VX);
+    const int n_waves = strips * ((r[3] - r[2] + rows - 1) / rows);
+    const int core_blocks = round8((n_waves + 3) / 4);
+    const int frame_blocks = H->n_frame > 0 ? round8((int)H->n_frame) : 0;
+    // step n -> n+1 on the frame reads A (U^n), B (U^{n-1}) and writes C; the
+    // core reads A, B and writes C (U^{n+1}) and D (U^{n+2})
     dpmlk::StepArgs<T> p = make_args<T>(H);
-    if (n_tiles > 0) {
-        dim3 grid((unsigned)round8(n_tiles), B), block(256);
-        hipLaunchKernelGGL((dpmlk::k_step2_core<T, TW, TH>), grid, block, 0, H->stream, p, (const T *)Bv, C, D,
-                           r[0], r[1], r[2], r[3], tiles_x, n_tiles);
-    }
+    p.uout = C;
+    p.tile_rows = rows;
+    for (int q = 0; q < 4; ++q) p.skip[q] = r[q];
+    const dim3 grid((unsigned)(frame_blocks + core_blocks), B), block(256);
+    if (p.c2)
+        hipLaunchKernelGGL((dpmlk::k_step2_march<T, VX, 4, true>), grid, block, 0, H->stream, p, D, r[0], r[1],
+                           r[2], r[3], strips, n_waves, (const dpmlk::TileRef *)H->d_frame, (int)H->n_frame,
+                           frame_blocks);
+    else
+        hipLaunchKernelGGL((dpmlk::k_step2_march<T, VX, 4, false>), grid, block, 0, H->stream, p, D, r[0], r[1],
+                           r[2], r[3], strips, n_waves, (const dpmlk::TileRef *)H->d_frame, (int)H->n_frame,
+                           frame_blocks);
     if (H->n_frame > 0) {
-        dim3 grid((unsigned)round8((int)H->n_frame), B), block(256);
-        // step n -> n+1 on the frame: read A (U^n), B (U^{n-1}); write C
-        p.uout = C;
-        for (int q = 0; q < 4; ++q) p.skip[q] = r[q];
-        hipLaunchKernelGGL((dpmlk::k_step_frame<T>), grid, block, 0, H->stream, p, H->d_frame, (int)H->n_frame);
         // step n+1 -> n+2 on the frame: read C (U^{n+1}), A (U^n); write D; aux buffers swap
+        dim3 g2((unsigned)frame_blocks, B);
         H->cur = 1 - H->cur;
         dpmlk::StepArgs<T> p2 = make_args<T>(H);
         H->cur = 1 - H->cur;
@@ -410,7 +431,7 @@ int launch_twostep(dpml *H)
         p2.uo = A;
         p2.uout = D;
         for (int q = 0; q < 4; ++q) p2.skip[q] = r[q];
-        hipLaunchKernelGGL((dpmlk::k_step_frame<T>), grid, block, 0, H->stream, p2, H->d_frame, (int)H->n_frame);
+        hipLaunchKernelGGL((dpmlk::k_step_frame<T>), g2, block, 0, H->stream, p2, H->d_frame, (int)H->n_frame);
     }
     HIP_TRY(H, hipGetLastError());
     H->u_now = D;
@@ -950,19 +971,34 @@ int adjoint_impl(dpml *H, const void *resid, double *grad, void *grad_w)
         int rc = copy_state(H, ws + A.off_ckpt + (size_t)seg * A.state, false);
         if (rc) return rc;
         H->n = t0;
+        // U^{t0} goes to history slot 0; each recomputed level is then written
+        // straight into the next slot (reading the two previous slots), so the
+        // recompute moves the same 3 words per cell as a forward step
         HIP_TRY(H, hipMemcpyAsync(ws + A.off_hist, H->u_now, lb, hipMemcpyDeviceToDevice, H->stream));
         for (int64_t k = t0; k + 1 < t1; ++k) {
-            T *hist = (T *)(ws + A.off_hist + (size_t)(k - t0 + 1) * A.level);
-            rc = launch_step<T>(H, hist);
-            if (rc) return rc;
-            rc = launch_epilogue<T>(H);       // sources only (recording is off)
-            if (rc) return rc;
-            if (H->ns > 0 && H->n < H->nt_src) {   // the history must include the sources too
+            T *slot = (T *)(ws + A.off_hist + (size_t)(k - t0 + 1) * A.level);
+            T *cur = (T *)(ws + A.off_hist + (size_t)(k - t0) * A.level);
+            dpmlk::StepArgs<T> p = make_args<T>(H);
+            p.u = cur;
+            p.uo = (T *)H->u_old;           // U^{k-1}: the checkpoint's level or the previous slot
+            p.uout = slot;
+            const int th = 4;
+            p.tiles_x = (int)((L.N[0] + 63) / 64);
+            p.tiles_y = (int)((L.N[1] + th - 1) / th);
+            p.n_tiles = p.tiles_x * p.tiles_y * (int)(L.ndim == 3 ? L.N[2] : 1);
+            dim3 g1((unsigned)round8(p.n_tiles), (unsigned)L.batch), b1(256);
+            if (L.ndim == 2)
+                hipLaunchKernelGGL((dpmlk::k_step_cell<T, 2, 4>), g1, b1, 0, H->stream, p);
+            else
+                hipLaunchKernelGGL((dpmlk::k_step_cell<T, 3, 4>), g1, b1, 0, H->stream, p);
+            HIP_TRY(H, hipGetLastError());
+            if (H->ns > 0 && H->n < H->nt_src) {
                 dim3 g2((unsigned)((H->ns + 255) / 256)), b2(256);
-                hipLaunchKernelGGL((dpmlk::k_inject<T>), g2, b2, 0, H->stream, hist, H->d_src_cells,
+                hipLaunchKernelGGL((dpmlk::k_inject<T>), g2, b2, 0, H->stream, slot, H->d_src_cells,
                                    H->d_src_order, (const T *)H->wavelets, H->ns, H->nt_src, H->n, wamp);
             }
-            std::swap(H->u_now, H->u_old);
+            H->u_old = cur;
+            H->u_now = slot;
             H->cur = 1 - H->cur;
             H->n += 1;
         }
@@ -1031,6 +1067,9 @@ int adjoint_impl(dpml *H, const void *resid, double *grad, void *grad_w)
     HIP_TRY(H, hipGetLastError());
     H->recording = true;
     H->state_set = false;     // the fields now hold a recomputed intermediate level
+    H->u_now = H->at(L.off_u[0]);     // and never point into the caller's workspace
+    H->u_old = H->at(L.off_u[1]);
+    H->cur = 0;
     return DPML_OK;
 }
 
@@ -1117,8 +1156,7 @@ struct MultiLayout {
     int vx = 1;
 };
 
-constexpr int kMultiTileRows = 4;     // tiles of 64 x 4 cells, one thread per cell
-constexpr int kMultiTileCols = 64;
+constexpr int kMultiTileRows = 4;     // marching tiles of 256 VX columns x 4 rows
 
 std::string multi_layout(int64_t count, const dpml_grid_t *grids, MultiLayout &M)
 {
@@ -1139,11 +1177,10 @@ std::string multi_layout(int64_t count, const dpml_grid_t *grids, MultiLayout &M
         off += align_up(M.L[p].total);
         even &= M.L[p].N[0] % 2 == 0;
     }
-    M.vx = 1;
-    (void)even;
+    M.vx = (dtype == DPML_F32 && even) ? 2 : 1;
     int64_t nt = 0;
     for (int64_t p = 0; p < count; ++p) {
-        const int64_t tx = (M.L[p].N[0] + kMultiTileCols - 1) / kMultiTileCols;
+        const int64_t tx = (M.L[p].N[0] + 256 * M.vx - 1) / (256 * M.vx);
         const int64_t ty = (M.L[p].N[1] + kMultiTileRows - 1) / kMultiTileRows;
         nt += tx * ty;
     }
@@ -1190,7 +1227,7 @@ int multi_tables(dpml_multi *H, const double *const *sigmas)
             dpml v = problem_view(H, p, q);
             args[p] = make_args<T>(&v);
             args[p].tile_rows = H->tile_rows;
-            args[p].tiles_x = (int)((v.L.N[0] + kMultiTileCols - 1) / kMultiTileCols);
+            args[p].tiles_x = (int)((v.L.N[0] + 256 * H->vx - 1) / (256 * H->vx));
         }
         HIP_TRY(nullptr, hipMemcpy(H->ws + H->off_desc[q], args.data(), args.size() * sizeof(args[0]),
                                    hipMemcpyHostToDevice));
@@ -1198,7 +1235,7 @@ int multi_tables(dpml_multi *H, const double *const *sigmas)
     std::vector<dpmlk::TileRef> tiles;
     tiles.reserve((size_t)H->ntiles);
     for (int64_t p = 0; p < H->count; ++p) {
-        const int tx = (int)((H->L[p].N[0] + kMultiTileCols - 1) / kMultiTileCols);
+        const int tx = (int)((H->L[p].N[0] + 256 * H->vx - 1) / (256 * H->vx));
         const int ty = (int)((H->L[p].N[1] + H->tile_rows - 1) / H->tile_rows);
         for (int y = 0; y < ty; ++y)
             for (int x = 0; x < tx; ++x) tiles.push_back({(int32_t)p, x, y, 0});
@@ -1214,7 +1251,11 @@ int multi_launch(dpml_multi *H, hipStream_t s, int parity)
     const dim3 grid((unsigned)round8((int)H->ntiles)), block(256);
     const auto *probs = (const dpmlk::StepArgs<T> *)(H->ws + H->off_desc[parity]);
     const auto *tiles = (const dpmlk::TileRef *)(H->ws + H->off_tiles);
-    hipLaunchKernelGGL((dpmlk::k_step_multi2d<T>), grid, block, 0, s, probs, tiles, (int)H->ntiles);
+    if (H->vx == 2)
+        hipLaunchKernelGGL((dpmlk::k_step_multi2d<T, (sizeof(T) == 4 ? 2 : 1)>), grid, block, 0, s, probs, tiles,
+                           (int)H->ntiles);
+    else
+        hipLaunchKernelGGL((dpmlk::k_step_multi2d<T, 1>), grid, block, 0, s, probs, tiles, (int)H->ntiles);
     HIP_TRY(nullptr, hipGetLastError());
     return DPML_OK;
 }

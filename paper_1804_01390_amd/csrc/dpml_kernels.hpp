@@ -228,7 +228,7 @@ __global__ void __launch_bounds__(256) k_step_cell(StepArgs<T> p)
     const T uym = (p.ax[1].wall && y == 0) ? T(0) : u[plane + (int64_t)ym * nx + x];
     const T uyp = (p.ax[1].wall && y == p.ny - 1) ? T(0) : u[plane + (int64_t)yp * nx + x];
     const T r = cell_update<T, D>(p, x, y, z, idx, u[idx], uxm, uxp, uym, uyp, uzm, uzp, p.uo[idx]);
-    p.uo[idx] = r;
+    (p.uout ? p.uout : p.uo)[idx] = r;
     if (p.hist) p.hist[idx] = r;
 }
 
@@ -395,70 +395,189 @@ __device__ __forceinline__ void cell2d_tile(const StepArgs<T> &p, int tx, int ty
 // ---------------------------------------------------------------------------
 // Two steps per launch (temporal blocking), 2D, periodic grids.
 //
-// Interior tiles -- tiles whose cells and one-cell halo lie where no damping
-// term acts (the "core" [lo+2, lo+n-2) per axis) -- advance two levels in one
-// pass: U^n with a 2-cell halo is staged in LDS, U^{n+1} is computed on the
-// tile plus a 1-cell halo into LDS (and stored), then U^{n+2} on the tile.
-// Reads U^n, U^{n-1}; writes U^{n+1}, U^{n+2} into two other buffers: 2 words
-// per cell per step instead of 3.  The frame outside the core (the layer plus
-// a 2-cell margin) takes two ordinary steps with k_step_frame.  The scheme is
-// evaluated in the same operation order as cell_update (no damping terms act
-// in the core), so results are bit-identical to single steps.
+// The "core" -- cells whose one-cell halo lies where no damping term acts,
+// inside [lo+2, lo+n-1) per axis -- advances two levels in one pass.  Each
+// wave works alone (no barriers, no LDS): it owns a strip of 64 lanes x VX
+// columns, lanes 1..62 produce output and lanes 0 and 63 carry the halo, and
+// it marches down a tile of rows.  For every row r it reads U^n(r+1) and
+// U^{n-1}(r), computes U^{n+1}(r) and then U^{n+2}(r-1) from the three newest
+// U^{n+1} rows held in registers; x neighbours across lanes come from
+// cross-lane shuffles.  Reads U^n, U^{n-1}; writes U^{n+1}, U^{n+2} (into two
+// further buffers): 2 words per cell per step instead of 3.
+//
+// The same launch also takes the frame's first step: blocks below
+// frame_blocks run one ordinary step (U^n -> U^{n+1}, aux fields included)
+// on a list of 64 x 4 tiles that covers everything outside the core; the
+// frame's second step is a separate launch.  The core evaluates the scheme
+// in the operation order of cell_update (no damping terms there), so results
+// are bit-identical to single steps.
 // ---------------------------------------------------------------------------
-template <typename T, int TW, int TH>
-__global__ void __launch_bounds__(256) k_step2_core(StepArgs<T> p, const T *__restrict__ u_prev,
-                                                    T *__restrict__ u_next1, T *__restrict__ u_next2,
-                                                    int cx0, int cx1, int cy0, int cy1, int tiles_x, int n_tiles)
+template <typename T, int VX, bool C2F>
+struct March2Ctx {
+    using R = Row<T, VX>;
+    const T *u, *up, *c2;          // U^n, U^{n-1}, c^2 field
+    T *o1, *o2;                    // U^{n+1}, U^{n+2}
+    T inv_h2, dt2, c2c;
+    int nx, ny, xs, xw, cx1;
+    bool need, vec, out;
+
+    __device__ __forceinline__ int wrapy(int y) const { return y < 0 ? y + ny : (y >= ny ? y - ny : y); }
+
+    // this lane's VX cells of row y of field f (row index already wrapped)
+    __device__ __forceinline__ R load(const T *f, int y) const
+    {
+        R r;
+        const T *row = f + (int64_t)y * nx;
+        if (!need) {
+#pragma unroll
+            for (int k = 0; k < VX; ++k) r.v[k] = T(0);
+        } else if (vec) {
+            r = load_row<T, VX>(row + xw);
+        } else {
+#pragma unroll
+            for (int k = 0; k < VX; ++k) {
+                int x = (xs + k) % nx;
+                if (x < 0) x += nx;
+                r.v[k] = row[x];
+            }
+        }
+        return r;
+    }
+
+    __device__ __forceinline__ void store(T *f, int y, const R &r) const
+    {
+        if (!out) return;
+        T *row = f + (int64_t)y * nx + xs;
+        if (xs + VX <= cx1) {
+            store_row<T, VX>(row, r);
+        } else {
+#pragma unroll
+            for (int k = 0; k < VX; ++k)
+                if (xs + k < cx1) row[k] = r.v[k];
+        }
+    }
+
+    // one undamped leapfrog level for this lane's cells (Eq. (DiscretePML a)
+    // with every damping term zero), in cell_update's operation order
+    __device__ __forceinline__ R level(const R &um, const R &uc, const R &upr, const R &old, const R &c) const
+    {
+        const T left = __shfl_up(uc.v[VX - 1], 1);
+        const T right = __shfl_down(uc.v[0], 1);
+        R o;
+#pragma unroll
+        for (int k = 0; k < VX; ++k) {
+            const T uxm = k == 0 ? left : uc.v[k - 1];
+            const T uxp = k == VX - 1 ? right : uc.v[k + 1];
+            T lap = T(0);
+            lap += ((uxm - T(2) * uc.v[k]) + uxp) * inv_h2;
+            lap += ((um.v[k] - T(2) * uc.v[k]) + upr.v[k]) * inv_h2;
+            const T cc = C2F ? c.v[k] : c2c;
+            o.v[k] = (T(2) * uc.v[k] - old.v[k]) + dt2 * (cc * lap);
+        }
+        return o;
+    }
+
+    // rolling state at row r: U^n rows r-1, r; U^{n+1} rows r-2, r-1; c^2 row r-1
+    struct State {
+        R n0, n1, v0, v1, c0;
+    };
+
+    // G rows r .. r+G-1 of U^{n+1} and rows r-1 .. r+G-2 of U^{n+2}; every load
+    // of the group is issued before its arithmetic
+    template <int G>
+    __device__ __forceinline__ void group(State &s, int r, int yb) const
+    {
+        R wn[G + 2], po[G], v[G + 2], cw[G + 1];
+        wn[0] = s.n0;
+        wn[1] = s.n1;
+        v[0] = s.v0;
+        v[1] = s.v1;
+        cw[0] = s.c0;
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+            wn[2 + g] = load(u, wrapy(r + 1 + g));
+            po[g] = load(up, wrapy(r + g));
+            if (C2F) cw[1 + g] = load(c2, wrapy(r + g));
+        }
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+            v[2 + g] = level(wn[g], wn[g + 1], wn[g + 2], po[g], cw[1 + g]);
+            if (r + g < yb) store(o1, r + g, v[2 + g]);
+            store(o2, r - 1 + g, level(v[g], v[g + 1], v[g + 2], wn[g], cw[g]));
+        }
+        s.n0 = wn[G];
+        s.n1 = wn[G + 1];
+        s.v0 = v[G];
+        s.v1 = v[G + 1];
+        s.c0 = cw[G];
+    }
+};
+
+template <typename T, int VX, int G, bool C2F>
+__global__ void __launch_bounds__(256) k_step2_march(StepArgs<T> p, T *__restrict__ u_next2, int cx0, int cx1,
+                                                     int cy0, int cy1, int strips, int n_waves,
+                                                     const TileRef *__restrict__ frame, int n_frame,
+                                                     int frame_blocks)
 {
-    __shared__ T s0[TH + 4][TW + 4];     // U^n, tile + 2-cell halo
-    __shared__ T s1[TH + 2][TW + 2];     // U^{n+1}, tile + 1-cell halo
-    const int tile = xcd_tile(blockIdx.x, gridDim.x);
-    if (tile >= n_tiles) return;         // uniform per block: no barrier is skipped by part of it
+    if ((int)blockIdx.x < frame_blocks) {          // the frame's first step
+        const int t = (int)blockIdx.x;
+        if (t >= n_frame) return;
+        select_member(p, (int)blockIdx.y);
+        const int x = frame[t].tx * 64 + (int)(threadIdx.x % 64);
+        const int y = frame[t].ty * 4 + (int)(threadIdx.x / 64);
+        if (x >= p.skip[0] && x < p.skip[1] && y >= p.skip[2] && y < p.skip[3]) return;
+        cell2d_tile<T, 4>(p, frame[t].tx, frame[t].ty);
+        return;
+    }
+    const int cb = (int)blockIdx.x - frame_blocks;           // frame_blocks is a multiple of 8
+    const int w = xcd_tile(cb, (int)gridDim.x - frame_blocks) * 4 + (int)(threadIdx.x >> 6);
+    if (w >= n_waves) return;                                // whole waves; no barriers below
+    const int lane = (int)(threadIdx.x & 63);
+    const int strip = w % strips, ty = w / strips;
     const int64_t boff = (int64_t)blockIdx.y * p.bstride;
-    const T *u = p.u + boff;
-    u_prev += boff;
-    u_next1 += boff;
-    u_next2 += boff;
-    const int nx = p.nx, ny = p.ny;
-    const int x0 = cx0 + (tile % tiles_x) * TW;
-    const int y0 = cy0 + (tile / tiles_x) * TH;
-    auto wrapx = [&](int x) { return x < 0 ? x + nx : (x >= nx ? x - nx : x); };
-    auto wrapy = [&](int y) { return y < 0 ? y + ny : (y >= ny ? y - ny : y); };
-    // stage U^n
-    for (int k = threadIdx.x; k < (TH + 4) * (TW + 4); k += 256) {
-        const int r = k / (TW + 4), c = k % (TW + 4);
-        s0[r][c] = u[(int64_t)wrapy(y0 - 2 + r) * nx + wrapx(x0 - 2 + c)];
+    March2Ctx<T, VX, C2F> c;
+    c.u = p.u + boff;
+    c.up = p.uo + boff;
+    c.c2 = C2F ? p.c2 : nullptr;
+    c.o1 = p.uout + boff;
+    c.o2 = u_next2 + boff;
+    c.inv_h2 = p.inv_h2;
+    c.dt2 = p.dt2;
+    c.c2c = p.c2_const;
+    c.nx = p.nx;
+    c.ny = p.ny;
+    c.cx1 = cx1;
+    c.xs = cx0 + (strip * 62 + lane - 1) * VX;
+    c.need = c.xs < cx1 + VX;                                // lanes further right feed nobody
+    c.xw = c.xs % c.nx;
+    if (c.xw < 0) c.xw += c.nx;
+    c.vec = c.xw % VX == 0 && c.xw + VX <= c.nx;
+    c.out = lane >= 1 && lane <= 62 && c.xs < cx1;
+    const int rows = p.tile_rows;
+    const int ya = cy0 + ty * rows, yb = min(ya + rows, cy1);
+    using R = Row<T, VX>;
+    typename March2Ctx<T, VX, C2F>::State s;
+    {
+        // rows ya-1 and ya of U^{n+1}
+        const R a0 = c.load(c.u, c.wrapy(ya - 2)), a1 = c.load(c.u, c.wrapy(ya - 1));
+        const R a2 = c.load(c.u, ya), a3 = c.load(c.u, c.wrapy(ya + 1));
+        const R p0 = c.load(c.up, c.wrapy(ya - 1)), p1 = c.load(c.up, ya);
+        R k0{}, k1{};
+        if (C2F) {
+            k0 = c.load(c.c2, c.wrapy(ya - 1));
+            k1 = c.load(c.c2, ya);
+        }
+        s.v0 = c.level(a0, a1, a2, p0, k0);
+        s.v1 = c.level(a1, a2, a3, p1, k1);
+        c.store(c.o1, ya, s.v1);
+        s.n0 = a2;
+        s.n1 = a3;
+        s.c0 = k1;
     }
-    __syncthreads();
-    // U^{n+1} on the tile and its 1-cell halo
-    for (int k = threadIdx.x; k < (TH + 2) * (TW + 2); k += 256) {
-        const int r = k / (TW + 2), c = k % (TW + 2);
-        const int x = wrapx(x0 - 1 + c), y = wrapy(y0 - 1 + r);
-        const int64_t idx = (int64_t)y * nx + x;
-        const T uc = s0[r + 1][c + 1];
-        T lap = T(0);
-        lap += ((s0[r + 1][c] - T(2) * uc) + s0[r + 1][c + 2]) * p.inv_h2;
-        lap += ((s0[r][c + 1] - T(2) * uc) + s0[r + 2][c + 1]) * p.inv_h2;
-        const T c2 = p.c2 ? p.c2[idx] : p.c2_const;
-        const T v = (T(2) * uc - u_prev[idx]) + p.dt2 * (c2 * lap);
-        s1[r][c] = v;
-        const int gx = x0 - 1 + c, gy = y0 - 1 + r;
-        if (r >= 1 && r <= TH && c >= 1 && c <= TW && gx < cx1 && gy < cy1) u_next1[idx] = v;
-    }
-    __syncthreads();
-    // U^{n+2} on the tile
-    for (int k = threadIdx.x; k < TH * TW; k += 256) {
-        const int r = k / TW, c = k % TW;
-        const int x = x0 + c, y = y0 + r;
-        if (x >= cx1 || y >= cy1) continue;
-        const int64_t idx = (int64_t)y * nx + x;
-        const T uc = s1[r + 1][c + 1];
-        T lap = T(0);
-        lap += ((s1[r + 1][c] - T(2) * uc) + s1[r + 1][c + 2]) * p.inv_h2;
-        lap += ((s1[r][c + 1] - T(2) * uc) + s1[r + 2][c + 1]) * p.inv_h2;
-        const T c2 = p.c2 ? p.c2[idx] : p.c2_const;
-        u_next2[idx] = (T(2) * uc - s0[r + 2][c + 2]) + p.dt2 * (c2 * lap);
-    }
+    // rows r = ya+1 .. yb of U^{n+1} (row yb is the lower halo) and r-1 of U^{n+2}
+    int r = ya + 1;
+    for (; r + G - 1 <= yb; r += G) c.template group<G>(s, r, yb);
+    for (; r <= yb; ++r) c.template group<1>(s, r, yb);
 }
 
 // One ordinary step over a list of 64 x 4 cell tiles (the frame around the
@@ -476,7 +595,11 @@ __global__ void __launch_bounds__(256) k_step_frame(StepArgs<T> p, const TileRef
     cell2d_tile<T, 4>(p, t.tx, t.ty);
 }
 
-template <typename T>
+// Many problems: each block takes one tile of (256 VX) columns x tile_rows
+// rows of one problem from the work list and marches down it (the shape the
+// tuner prefers for single 2D grids), so the per-block lookup of the
+// problem's arguments is amortised over 1024 VX cells.
+template <typename T, int VX>
 __global__ void __launch_bounds__(256) k_step_multi2d(const StepArgs<T> *__restrict__ probs,
                                                       const TileRef *__restrict__ tiles, int ntiles)
 {
@@ -484,18 +607,21 @@ __global__ void __launch_bounds__(256) k_step_multi2d(const StepArgs<T> *__restr
     if (tile >= ntiles) return;
     const TileRef t = tiles[tile];
     const StepArgs<T> p = probs[t.prob];
-    cell2d_tile<T, 4>(p, t.tx, t.ty);
+    march2d_tile<T, VX, 1>(p, t.tx, t.ty);
 }
 
 // ---------------------------------------------------------------------------
-// Variant MARCH, 3D: a block of 64 x 4 threads owns a 64 x (4*RY) tile of an
-// (x, y) plane and marches over `tile_rows` planes in z in groups of R
-// planes, keeping U^n of planes z-1, z, ... in registers; every load of a
-// group (R new planes, R U^{n-1} planes and the x/y neighbours, mostly L1/L2
-// hits) is issued before its arithmetic.
+// Variant MARCH, 3D: each wave owns 64 consecutive columns x RY rows of an
+// (x, y) plane and marches through `tile_rows` planes in z, keeping U^n of
+// planes z-1, z, z+1 for its RY rows in registers, so every plane of U^n is
+// read once per chunk.  x neighbours come from the adjacent lanes (cross-lane
+// shuffles; lanes 0 and 63 read the one column beyond the strip), y
+// neighbours from the adjacent register rows (the rows just above and below
+// the wave come from the L2 cache, where the neighbouring waves read them as
+// their own).  A block's 4 waves take 4 consecutive row groups.
 // ---------------------------------------------------------------------------
-template <typename T, int RY, int R>
-__global__ void __launch_bounds__(256) k_step_march3d(StepArgs<T> p)
+template <typename T, int RY>
+__global__ void __launch_bounds__(256) k_step_zmarch3d(StepArgs<T> p)
 {
     const int tile = xcd_tile(blockIdx.x, gridDim.x);
     if (tile >= p.n_tiles) return;
@@ -503,99 +629,95 @@ __global__ void __launch_bounds__(256) k_step_march3d(StepArgs<T> p)
     const int per_plane = p.tiles_x * p.tiles_y;
     const int tz = tile / per_plane;
     const int rem = tile - tz * per_plane;
-    const int ty = rem / p.tiles_x;           // y tiles fastest after x
+    const int ty = rem / p.tiles_x;
     const int tx = rem - ty * p.tiles_x;
-    const int x = tx * 64 + (int)threadIdx.x;
-    if (x >= p.nx) return;
+    const int lane = (int)(threadIdx.x & 63);
     const int nx = p.nx, ny = p.ny, nz = p.nz;
+    const int y0 = (ty * 4 + (int)(threadIdx.x >> 6)) * RY;
+    if (y0 >= ny) return;                                  // whole wave; no barriers below
+    const int x0 = tx * 64, x = x0 + lane;
+    const bool wx = p.ax[0].wall, wy = p.ax[1].wall, wz = p.ax[2].wall;
     const int64_t sxy = (int64_t)nx * ny;
-    const int z0 = tz * p.tile_rows;
-    const int z1 = min(z0 + p.tile_rows, nz);
-    const int xm = wrap_dec(x, nx), xp = wrap_inc(x, nx);
-    const bool xlg = p.ax[0].wall && x == 0, xrg = p.ax[0].wall && x == nx - 1;
-    const bool wyy = p.ax[1].wall, wz = p.ax[2].wall;
-    const T *u = p.u;
-    int yy[RY], ymv[RY], ypv[RY];
-    bool ok[RY], ymg[RY], ypg[RY];
-#pragma unroll
-    for (int q = 0; q < RY; ++q) {
-        yy[q] = (ty * 4 + (int)threadIdx.y) * RY + q;
-        ok[q] = yy[q] < ny;
-        if (!ok[q]) yy[q] = 0;
-        ymv[q] = wrap_dec(yy[q], ny);
-        ypv[q] = wrap_inc(yy[q], ny);
-        ymg[q] = wyy && yy[q] == 0;
-        ypg[q] = wyy && yy[q] == ny - 1;
+    // each lane reads column x (wrapped; the ghost column of a wall reads 0), so
+    // the lane right of the last real column supplies that column's neighbour
+    const bool xin = x < nx;
+    const bool xzero = x >= nx && (wx || x - nx >= nx);
+    const int xc = xin ? x : (x - nx < nx ? x - nx : 0);
+    // lanes 0 and 63 also read the column just outside the strip
+    int xe = 0;
+    bool ezero = false;
+    if (lane == 0) {
+        xe = x0 == 0 ? nx - 1 : x0 - 1;
+        ezero = x0 == 0 && wx;
+    } else if (lane == 63) {
+        const int xr = x0 + 64;
+        xe = xr < nx ? xr : 0;
+        ezero = xr > nx || (xr == nx && wx);
     }
-    // plane index of z-neighbour zz, or -1 past a wall
+    // register rows q = 0..RY-1 and the halo rows -1, RY, each as a row index
+    // into the plane, or -1 for a zero row (past a wall or beyond the grid)
+    auto row_of = [&](int yy) -> int {
+        if (yy < 0) return wy ? -1 : yy + ny;
+        if (yy >= ny) return (wy || yy - ny >= ny) ? -1 : yy - ny;
+        return yy;
+    };
+    int ry[RY];
+#pragma unroll
+    for (int q = 0; q < RY; ++q) ry[q] = row_of(y0 + q);
+    const int rlo = row_of(y0 - 1), rhi = row_of(y0 + RY);
     auto plane_of = [&](int zz) -> int {
         if (zz < 0) return wz ? -1 : zz + nz;
         if (zz >= nz) return wz ? -1 : zz - nz;
         return zz;
     };
-    auto col = [&](int q) -> int64_t { return (int64_t)yy[q] * nx + x; };
-
-    T w[R + 2][RY];
+    const T *u = p.u;
+    auto ld = [&](int pz, int r) -> T {
+        return (pz < 0 || r < 0 || xzero) ? T(0) : u[(int64_t)pz * sxy + (int64_t)r * nx + xc];
+    };
+    const int z0 = tz * p.tile_rows;
+    const int z1 = min(z0 + p.tile_rows, nz);
+    T um[RY], uc[RY];
     {
         const int pm = plane_of(z0 - 1);
 #pragma unroll
         for (int q = 0; q < RY; ++q) {
-            w[0][q] = (pm < 0 || !ok[q]) ? T(0) : u[(int64_t)pm * sxy + col(q)];
-            w[1][q] = ok[q] ? u[(int64_t)z0 * sxy + col(q)] : T(0);
+            um[q] = ld(pm, ry[q]);
+            uc[q] = ld(z0, ry[q]);
         }
     }
-    auto compute = [&](int z, int q, T um, T uc, T up, T old, T uxm, T uxp, T uym, T uyp) {
-        const int64_t idx = (int64_t)z * sxy + col(q);
-        const T res = cell_update<T, 3>(p, x, yy[q], z, idx, uc, uxm, uxp, uym, uyp, um, up, old);
-        p.uo[idx] = res;
-        if (p.hist) p.hist[idx] = res;
-    };
-    int z = z0;
-    for (; z + R <= z1; z += R) {
-        T old[R][RY], nxm[R][RY], nxp[R][RY], nym[R][RY], nyp[R][RY];
-#pragma unroll
-        for (int r = 0; r < R; ++r) {
-            const int pz = plane_of(z + 1 + r);
-            const int64_t plane = (int64_t)(z + r) * sxy;
-#pragma unroll
-            for (int q = 0; q < RY; ++q) {
-                w[2 + r][q] = (pz < 0 || !ok[q]) ? T(0) : u[(int64_t)pz * sxy + col(q)];
-                if (ok[q]) {
-                    const int64_t rowq = plane + (int64_t)yy[q] * nx;
-                    old[r][q] = p.uo[rowq + x];
-                    nxm[r][q] = xlg ? T(0) : u[rowq + xm];
-                    nxp[r][q] = xrg ? T(0) : u[rowq + xp];
-                    nym[r][q] = ymg[q] ? T(0) : u[plane + (int64_t)ymv[q] * nx + x];
-                    nyp[r][q] = ypg[q] ? T(0) : u[plane + (int64_t)ypv[q] * nx + x];
-                }
-            }
-        }
-#pragma unroll
-        for (int r = 0; r < R; ++r)
-#pragma unroll
-            for (int q = 0; q < RY; ++q)
-                if (ok[q]) compute(z + r, q, w[r][q], w[r + 1][q], w[r + 2][q], old[r][q], nxm[r][q],
-                                   nxp[r][q], nym[r][q], nyp[r][q]);
-#pragma unroll
-        for (int q = 0; q < RY; ++q) {
-            w[0][q] = w[R][q];
-            w[1][q] = w[R + 1][q];
-        }
-    }
-    for (; z < z1; ++z) {
+    T *out = p.uout ? p.uout : p.uo;
+    for (int z = z0; z < z1; ++z) {
         const int pz = plane_of(z + 1);
         const int64_t plane = (int64_t)z * sxy;
+        T upn[RY], old[RY], edge[RY];
 #pragma unroll
         for (int q = 0; q < RY; ++q) {
-            w[2][q] = (pz < 0 || !ok[q]) ? T(0) : u[(int64_t)pz * sxy + col(q)];
-            if (ok[q]) {
-                const int64_t rowq = plane + (int64_t)yy[q] * nx;
-                compute(z, q, w[0][q], w[1][q], w[2][q], p.uo[rowq + x], xlg ? T(0) : u[rowq + xm],
-                        xrg ? T(0) : u[rowq + xp], ymg[q] ? T(0) : u[plane + (int64_t)ymv[q] * nx + x],
-                        ypg[q] ? T(0) : u[plane + (int64_t)ypv[q] * nx + x]);
+            upn[q] = ld(pz, ry[q]);
+            old[q] = (xin && y0 + q < ny) ? p.uo[plane + (int64_t)(y0 + q) * nx + x] : T(0);
+            edge[q] = T(0);
+            if ((lane == 0 || lane == 63) && ry[q] >= 0 && !ezero) edge[q] = u[plane + (int64_t)ry[q] * nx + xe];
+        }
+        const T hlo = ld(z, rlo), hhi = ld(z, rhi);
+#pragma unroll
+        for (int q = 0; q < RY; ++q) {
+            T uxm = __shfl_up(uc[q], 1);
+            T uxp = __shfl_down(uc[q], 1);
+            if (lane == 0) uxm = edge[q];
+            if (lane == 63) uxp = edge[q];
+            const T uym = q == 0 ? hlo : uc[q - 1];
+            const T uyp = q == RY - 1 ? hhi : uc[q + 1];
+            const int y = y0 + q;
+            if (xin && y < ny) {
+                const int64_t idx = plane + (int64_t)y * nx + x;
+                const T r = cell_update<T, 3>(p, x, y, z, idx, uc[q], uxm, uxp, uym, uyp, um[q], upn[q], old[q]);
+                out[idx] = r;
+                if (p.hist) p.hist[idx] = r;
             }
-            w[0][q] = w[1][q];
-            w[1][q] = w[2][q];
+        }
+#pragma unroll
+        for (int q = 0; q < RY; ++q) {
+            um[q] = uc[q];
+            uc[q] = upn[q];
         }
     }
 }

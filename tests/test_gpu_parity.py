@@ -94,6 +94,36 @@ def test_3d_parity(dtype, variant, tile_rows):
 
 
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("variant,tile_rows", [(dp.VARIANT_MARCH, 5), (dp.VARIANT_MARCH1, 0)])
+@pytest.mark.parametrize("shape,walls", [("wide", (False, False, False)), ("wide", (True, True, True)),
+                                         ("x128", (False, False, False)), ("x128", (True, False, True))])
+def test_3d_march_strips_and_edges(dtype, variant, tile_rows, shape, walls):
+    """3D marching waves across several 64-column strips (lanes 0 and 63 read
+    the columns beyond their strip), an x extent that is a multiple of 64 (the
+    last strip ends on the grid's edge), ragged row groups, with and without
+    reflecting walls."""
+    rng = np.random.default_rng(81)
+    if shape == "wide":
+        n, lo, hi = [150, 23, 14], [7, 4, 3], [6, 5, 4]
+    else:
+        n, lo, hi = [118, 13, 12], [4, 3, 5], [6, 2, 3]
+    sig = [synthetic.sigma_random(n[a], lo[a], hi[a], 2.0, rng) for a in range(3)]
+    U0 = synthetic.gaussian_sum(n, lo, hi, 5, 2.0, 5.0, rng)
+    N = [lo[a] + n[a] + hi[a] for a in range(3)]
+    steps, dt = 50, 0.4
+    print("case 3d strips %s walls=%s %s variant=%d rows=%d" % (shape, walls, dtype, variant, tile_rows), flush=True)
+    sim = dp.Simulation(n, lo, hi, 1.0, dt, sig, dtype=_dtype(dtype), walls=walls)
+    sim.set_variant(variant, tile_rows)
+    sim.set_state(torch.from_numpy(U0))
+    sim.step(steps)
+    gs = gpu_state(sim)
+    g = oracle.Grid(N, 1.0, dt, sig, walls=walls)
+    ref, _, peaks = run_with_peaks(g, oracle.start(g, U0), steps, n, lo, hi)
+    sim.close()
+    _assert_errs(compare_states(gs, ref, n, lo, hi, peaks if dtype == "f32" else None), dtype)
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
 def test_c2_field_and_initial_velocity(dtype):
     rng = np.random.default_rng(5)
     n, lo, hi = [200, 150], [10, 10], [10, 10]
@@ -271,12 +301,14 @@ def test_graph_replay_matches_eager(dtype):
 
 
 
+@pytest.mark.parametrize("rows", [0, 5])
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
-@pytest.mark.parametrize("case", ["bump", "ragged", "onesided", "c2", "batch"])
-def test_twostep_matches_single_steps_and_oracle(dtype, case):
+@pytest.mark.parametrize("case", ["bump", "ragged", "onesided", "c2", "batch", "nolayer"])
+def test_twostep_matches_single_steps_and_oracle(dtype, case, rows):
     """Two steps per pass over the layer-free core (temporal blocking) plus
     single steps on the frame: bit-identical to single steps, and the oracle
-    agrees; odd step counts end with one single step."""
+    agrees; odd step counts end with one single step.  rows = 5 makes the
+    kernel's tiles end in a one-row remainder."""
     rng = np.random.default_rng(17)
     c2 = None
     batch = 1
@@ -296,6 +328,10 @@ def test_twostep_matches_single_steps_and_oracle(dtype, case):
         sig = [synthetic.sigma_ramp(n[a], 10, 10, 2.0) for a in range(2)]
         c2 = synthetic.smooth_c2(n, lo, hi, 6, 10.0, 30.0, 0.5, 8, rng)
         U0 = synthetic.gaussian_sum(n, lo, hi, 10, 2.0, 6.0, rng)
+    elif case == "nolayer":
+        n, lo, hi = [130, 45], [0, 0], [0, 0]
+        sig = [None, None]
+        U0 = synthetic.gaussian_sum(n, lo, hi, 6, 2.0, 6.0, rng)
     else:
         batch = 3
         n, lo, hi = [150, 140], [8, 8], [8, 8]
@@ -303,11 +339,11 @@ def test_twostep_matches_single_steps_and_oracle(dtype, case):
         U0 = np.stack([synthetic.gaussian_sum(n, lo, hi, 5, 2.0, 6.0, rng) for _ in range(batch)])
     dt = 0.5 if c2 is None else 0.5 / math.sqrt(float(np.max(c2)))
     steps = 121
-    print("case twostep %s %s" % (case, dtype), flush=True)
+    print("case twostep %s %s rows %d" % (case, dtype, rows), flush=True)
     outs = []
     for variant in (dp.VARIANT_TWOSTEP, dp.VARIANT_CELL):
         sim = dp.Simulation(n, lo, hi, 1.0, dt, sig, c2=1.0 if c2 is None else c2, dtype=_dtype(dtype), batch=batch)
-        sim.set_variant(variant, 0)
+        sim.set_variant(variant, rows if variant == dp.VARIANT_TWOSTEP else 0)
         sim.set_state(torch.from_numpy(U0))
         sim.step(steps)
         sim.sync()
