@@ -9,7 +9,9 @@ workload's 2000 steps in FP32 (the reported value) and in FP64.
 
 Prints ONE JSON line:
   value         Gcell-updates/s (all 4160^2 cells per step, layer included)
-  roofline      algorithmic bytes per step / measured kernel time vs 8 TB/s
+  roofline      the dominant step kernel: algorithmic bytes per launch over its
+                mean launch duration (HIP events around each launch, on the
+                library's stream) vs 8 TB/s
   cpu_baseline  the FP64 CPU oracle on a bounded sample of the same workload
 
     python bench.py [--gpus 1] [--steps 2000] [--warmup 50]
@@ -72,21 +74,35 @@ def time_gpu(w, dtype_name, steps, warmup, variant=0, tile_rows=0):
     e1.record(stream)
     torch.cuda.synchronize()
     total_ms = e0.elapsed_time(e1)
-    # per-launch duration of the step kernel: one event pair per step
-    # (a step of this workload is exactly one kernel launch)
-    k = min(steps, 200)
-    evs = [torch.cuda.Event(enable_timing=True) for _ in range(k + 1)]
-    evs[0].record(stream)
-    for i in range(k):
-        sim.step(1)
-        evs[i + 1].record(stream)
-    torch.cuda.synchronize()
-    per = [evs[i].elapsed_time(evs[i + 1]) for i in range(k)]
+    # per-launch durations of the step kernels: the library brackets each
+    # launch with a HIP event pair on its own stream (timing off above)
+    k = min(steps, 200) // 2 * 2
+    sim.set_timing(True)
+    sim.step(k)
+    kernels = sim.get_timing()
+    sim.set_timing(False)
     ok = bool(np.isfinite(sim.U.float().abs().max().item()))
     sim.close()
-    return {"total_ms": total_ms, "ms_per_step": total_ms / steps,
-            "kernel_ms_mean": float(np.mean(per)), "kernel_ms_median": float(np.median(per)),
+    return {"total_ms": total_ms, "ms_per_step": total_ms / steps, "kernels": kernels, "timed_steps": k,
             "finite": ok, "launch": launch}
+
+
+def roofline_from_timing(kernels, timed_steps):
+    """Roofline of the dominant step kernel (most time) from the library's
+    per-launch timing: its algorithmic bytes per launch over its mean launch
+    duration; also the whole path's algorithmic rate over all step kernels."""
+    name, k = max(kernels.items(), key=lambda kv: kv[1]["ms"])
+    ms = k["ms"] / k["launches"]
+    bpl = k["bytes"] / k["launches"]
+    achieved = bpl / (ms * 1e-3) / 1e9
+    tot_ms = sum(v["ms"] for v in kernels.values())
+    tot_b = sum(v["bytes"] for v in kernels.values())
+    return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "kernel": name,
+            "alg_bytes_per_launch": int(round(bpl)), "kernel_ms_mean": round(ms, 5),
+            "launches": k["launches"],
+            "path_alg_GBps": round(tot_b / (tot_ms * 1e-3) / 1e9, 1),
+            "path_kernel_ms_per_step": round(tot_ms / timed_steps, 5)}
 
 
 def cpu_baseline(w, sample_steps: int):
@@ -107,10 +123,10 @@ def cpu_baseline(w, sample_steps: int):
             "seconds": round(dt, 3)}
 
 
-def traffic_from_profile(workload: str, dtype_name: str):
-    """HBM bytes per launch measured by rocprofv3 counters, if a summary for
-    this kernel source is committed under profiles/."""
-    path = os.path.join(ROOT, "profiles", "traffic_%s_%s.json" % (workload, dtype_name))
+def traffic_from_profile(workload: str, dtype_name: str, kernel: str):
+    """HBM bytes per launch of a step-kernel class measured by rocprofv3
+    counters, if a summary for this kernel source is committed under profiles/."""
+    path = os.path.join(ROOT, "profiles", "traffic_%s_%s_%s.json" % (workload, dtype_name, kernel))
     if not os.path.exists(path):
         return None
     with open(path) as f:
@@ -183,6 +199,13 @@ def bench_ricker3d(steps: int):
     plane_cells = w.N[0] * w.N[1]
     ab = alg_bytes_per_step(w, 4) + plane_cells * 4
     peak = float(sim._keep["planes"][-1].abs().max().item())
+    # the step kernel alone (library launch timing), on a restarted run
+    sim.set_state(torch.zeros(tuple(reversed(w.N)), dtype=torch.float32, device="cuda"))
+    sim.set_timing(True)
+    sim.step(50)
+    roof = roofline_from_timing(sim.get_timing(), 50)
+    sim.set_timing(False)
+    roof["traffic"] = traffic_from_profile("ricker3d_512_m24", "f32", roof["kernel"])
     sim.close()
     return {"workload": "3D 512^3 interior + 24-cell layer (560^3 cells), FP32, Ricker source, "
                         "plane recorded every step, %d steps" % w.steps,
@@ -190,7 +213,64 @@ def bench_ricker3d(steps: int):
             "ms_per_step": round(ms / w.steps, 5),
             "alg_GBps": round(ab * w.steps / (ms * 1e-3) / 1e9, 1),
             "frac_of_8TBps": round(ab * w.steps / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
-            "last_plane_peak": peak,
+            "last_plane_peak": peak, "roofline": roof,
+            "launch": {"variant": choice["variant"], "tile_rows": choice["tile_rows"], "autotuned": True}}
+
+
+def bench_rk4(steps: int = 200):
+    """The paper's own integrator (classic RK4 on U, V, Phi, Psi; four fused
+    stage sweeps per step) on the 4160^2 FP32 workload, against leapfrog
+    steps of the same grid."""
+    import torch
+    import paper_1804_01390_amd as dp
+    import synthetic
+    w = synthetic.bumps2d(n=4096, m=32, steps=steps, seed=0)
+    sim = dp.Simulation(w.n, w.lo, w.hi, w.h, w.dt, w.sigma, dtype=torch.float32)
+    sim.set_state(torch.from_numpy(w.U0))
+    sim.rk4_set_state(torch.from_numpy(w.U0))
+    sim.rk4_step(4)
+    sim.sync()
+    e0, e1 = _events()
+    e0.record()
+    sim.rk4_step(steps)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    peak = float(sim.rk4_field(dp.FIELD_U).abs().max().item())
+    sim.close()
+    return {"workload": "2D 4096^2 + 32-cell layer (4160^2 cells), FP32, classic RK4, %d steps" % steps,
+            "value": round(w.cells * steps / (ms * 1e-3) / 1e9, 3), "unit": "Gcell/s",
+            "ms_per_step": round(ms / steps, 5), "finite": bool(np.isfinite(peak))}
+
+
+def bench_walls(steps: int = 500):
+    """The 4160^2 FP32 workload truncated by reflecting walls (Dirichlet
+    ghosts) instead of the periodic wrap, autotuned launch."""
+    import torch
+    import paper_1804_01390_amd as dp
+    import synthetic
+    from paper_1804_01390_amd import autotune
+    w = synthetic.bumps2d(n=4096, m=32, steps=steps, seed=0)
+    sim = dp.Simulation(w.n, w.lo, w.hi, w.h, w.dt, w.sigma, dtype=torch.float32, walls=(True, True))
+    sim.set_state(torch.from_numpy(w.U0))
+    choice = autotune.tune(sim)
+    sim.set_state(torch.from_numpy(w.U0))
+    sim.step(10)
+    sim.sync()
+    e0, e1 = _events()
+    e0.record()
+    sim.step(steps)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    sim.set_timing(True)
+    sim.step(50)
+    roof = roofline_from_timing(sim.get_timing(), 50)
+    sim.set_timing(False)
+    sim.close()
+    return {"workload": "2D 4096^2 + 32-cell layer (4160^2 cells) inside reflecting walls, FP32, %d steps" % steps,
+            "value": round(w.cells * steps / (ms * 1e-3) / 1e9, 3), "unit": "Gcell/s",
+            "ms_per_step": round(ms / steps, 5), "roofline": roof,
             "launch": {"variant": choice["variant"], "tile_rows": choice["tile_rows"], "autotuned": True}}
 
 
@@ -296,6 +376,9 @@ def bench_adjoint(steps: int, shots: int):
     obs = obs.clone()
     sim.close()
     sim, tr = make(w.c2_model)
+    from paper_1804_01390_amd import autotune
+    choice = autotune.tune(sim, steps=10)      # the forward and the adjoint's recompute use it
+    sim.set_state(torch.zeros(sim.shape, dtype=torch.float32, device="cuda"))
     # plain forward (no checkpoints) for reference
     sim.sync()
     e0, e1 = _events()
@@ -331,7 +414,8 @@ def bench_adjoint(steps: int, shots: int):
             "backward_ms": round(ms_bwd, 3),
             "adjoint_forward_ratio": round(ms_bwd / ms_fwd, 3),
             "forward_value": round(B * cells * steps / (ms_fwd * 1e-3) / 1e9, 3), "unit": "Gcell/s",
-            "misfit": misfit, "grad_c2_max": gnorm, "grad_finite": finite}
+            "misfit": misfit, "grad_c2_max": gnorm, "grad_finite": finite,
+            "launch": {"variant": choice["variant"], "tile_rows": choice["tile_rows"], "autotuned": True}}
 
 
 def main():
@@ -352,7 +436,8 @@ def main():
     ap.add_argument("--batch-steps", type=int, default=1500)
     ap.add_argument("--batch-count", type=int, default=256)
     ap.add_argument("--steps-3d", type=int, default=1000)
-    ap.add_argument("--only", default="", help="run a single section: ricker3d, batch, adjoint or small")
+    ap.add_argument("--only", default="",
+                    help="run a single section: ricker3d, batch, adjoint, small, rk4 or walls")
     args = ap.parse_args()
     if args.copy_probe:
         copy_probe()
@@ -366,7 +451,7 @@ def main():
         fn = {"ricker3d": lambda: bench_ricker3d(args.steps_3d),
               "batch": lambda: bench_batch(args.batch_steps, args.batch_count),
               "adjoint": lambda: bench_adjoint(args.adjoint_steps, 32),
-              "small": bench_small}[args.only]
+              "small": bench_small, "rk4": bench_rk4, "walls": bench_walls}[args.only]
         print(json.dumps({args.only: fn()}), flush=True)
         return
     import synthetic
@@ -375,25 +460,20 @@ def main():
     for dn in args.dtypes.split(","):
         log("timing %s %s: %d warmup + %d steps" % (w.name, dn, args.warmup, args.steps))
         r = time_gpu(w, dn, args.steps, args.warmup, args.variant, args.tile_rows)
-        esize = 4 if dn == "f32" else 8
-        ab = alg_bytes_per_step(w, esize)
-        achieved = ab / (r["kernel_ms_mean"] * 1e-3) / 1e9
-        traffic = traffic_from_profile(w.name, dn)
+        roof = roofline_from_timing(r["kernels"], r["timed_steps"])
+        roof["traffic"] = traffic_from_profile(w.name, dn, roof["kernel"])
         runs.append({
             "dtype": dn,
             "value": round(w.cells * args.steps / (r["total_ms"] * 1e-3) / 1e9, 3),
             "ms_per_step": round(r["ms_per_step"], 5),
-            "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                         "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                         "traffic": traffic,
-                         "alg_bytes_per_launch": ab,
-                         "kernel_ms_mean": round(r["kernel_ms_mean"], 5),
-                         "kernel_ms_median": round(r["kernel_ms_median"], 5)},
+            "roofline": roof,
+            "kernels": r["kernels"],
             "finite": r["finite"],
             "launch": r["launch"],
         })
-        log("  %s: %.1f Gcell/s, %.4f ms/step, kernel %.4f ms, %.0f GB/s" % (
-            dn, runs[-1]["value"], r["ms_per_step"], r["kernel_ms_mean"], achieved))
+        log("  %s: %.1f Gcell/s, %.4f ms/step; %s kernel %.4f ms/launch, %.0f GB/s algorithmic (path %.0f GB/s)" % (
+            dn, runs[-1]["value"], r["ms_per_step"], roof["kernel"], roof["kernel_ms_mean"], roof["achieved"],
+            roof["path_alg_GBps"]))
     main_run = runs[0]
     out = {
         "metric": METRIC,
@@ -425,6 +505,12 @@ def main():
         log("batch: %d problems x %d steps" % (args.batch_count, args.batch_steps))
         out["batch"] = bench_batch(args.batch_steps, args.batch_count)
         log("  %s" % out["batch"])
+        log("rk4: 4160^2 FP32")
+        out["rk4"] = bench_rk4()
+        log("  %s" % out["rk4"])
+        log("walls: 4160^2 FP32")
+        out["walls"] = bench_walls()
+        log("  %s" % out["walls"])
         log("adjoint: 32 shots x %d steps" % args.adjoint_steps)
         out["adjoint"] = bench_adjoint(args.adjoint_steps, 32)
         log("  %s" % out["adjoint"])

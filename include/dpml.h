@@ -323,6 +323,36 @@ int dpml_multi_sync(dpml_multi_t *h);
 void dpml_multi_destroy(dpml_multi_t *h);
 const char *dpml_multi_last_error(const dpml_multi_t *h);
 
+/* ---- launch timing (measurement) ------------------------------------------
+ * With timing on, the library brackets every launch of a step kernel with a
+ * pair of HIP events on the handle's stream and records, per kernel class,
+ * the launch count, the summed launch durations and the summed algorithmic
+ * bytes of those launches (the byte model of the roofline: 3 words per cell
+ * per step, 4 words per layer axis-cell per step, 1 word per cell per step
+ * of a c^2 field; a two-step core launch counts its cells twice).  Launches
+ * inside a HIP-graph capture are not timed; at most 4096 launches are kept
+ * between two reads.  The events slightly delay back-to-back launches, so
+ * throughput should be timed with timing off. */
+#define DPML_KERNEL_STEP 0   /* one step over all cells (any variant)                */
+#define DPML_KERNEL_PAIR 1   /* two-step core kernel with the frame's first step     */
+#define DPML_KERNEL_FRAME 2  /* the frame's second step (two-step variant); the
+                                layer slabs of a split 3D marching step             */
+#define DPML_KERNEL_CORE 3   /* the marching box of a split 3D marching step        */
+
+typedef struct dpml_timing {
+    int64_t launches[4];     /* indexed by DPML_KERNEL_*                               */
+    double ms[4];            /* summed launch durations, milliseconds                  */
+    double bytes[4];         /* summed algorithmic bytes                               */
+} dpml_timing_t;
+
+/* Turn launch timing on (enable != 0; clears earlier records) or off (keeps
+ * them for dpml_get_timing).  DPML_EINVAL for a NULL handle. */
+int dpml_set_timing(dpml_t *h, int32_t enable);
+
+/* Wait for the recorded launches, write their per-class totals to *out and
+ * clear the records.  Returns DPML_EHIP if an event query fails. */
+int dpml_get_timing(dpml_t *h, dpml_timing_t *out);
+
 /* Release the handle (not the caller's workspace or buffers). */
 void dpml_destroy(dpml_t *h);
 

@@ -47,14 +47,21 @@ EXPORTED = [
     "dpml_multi_field", "dpml_multi_tiles", "dpml_multi_sync", "dpml_multi_destroy",
     "dpml_multi_last_error",
     "dpml_rk4_workspace_bytes", "dpml_rk4_set_state", "dpml_rk4_step", "dpml_rk4_field",
-    "dpml_rk4_time_index",
+    "dpml_rk4_time_index", "dpml_set_timing", "dpml_get_timing",
 ]
+
+KERNEL_STEP, KERNEL_PAIR, KERNEL_FRAME, KERNEL_CORE = 0, 1, 2, 3
+KERNEL_NAMES = {KERNEL_STEP: "step", KERNEL_PAIR: "pair", KERNEL_FRAME: "frame", KERNEL_CORE: "core"}
 
 
 class DpmlError(RuntimeError):
     def __init__(self, code: int, msg: str):
         super().__init__("dpml error %d: %s" % (code, msg))
         self.code = code
+
+
+class TimingT(ctypes.Structure):
+    _fields_ = [("launches", ctypes.c_int64 * 4), ("ms", ctypes.c_double * 4), ("bytes", ctypes.c_double * 4)]
 
 
 class GridT(ctypes.Structure):
@@ -118,6 +125,8 @@ def load_library():
         "dpml_rk4_step": (ctypes.c_int, [_VP, ctypes.c_int64]),
         "dpml_rk4_field": (ctypes.c_int, [_VP, ctypes.c_int32, ctypes.POINTER(_VP), ctypes.c_int64 * 3]),
         "dpml_rk4_time_index": (ctypes.c_int64, [_VP]),
+        "dpml_set_timing": (ctypes.c_int, [_VP, ctypes.c_int32]),
+        "dpml_get_timing": (ctypes.c_int, [_VP, ctypes.POINTER(TimingT)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -306,6 +315,18 @@ class Simulation:
 
     def sync(self):
         self._check(self.lib.dpml_sync(self.handle))
+
+    def set_timing(self, enable: bool = True):
+        """Bracket each step-kernel launch with HIP events on the handle's stream."""
+        self._check(self.lib.dpml_set_timing(self.handle, 1 if enable else 0))
+
+    def get_timing(self):
+        """Per kernel class ("step", "pair", "frame", "core"): launches, summed milliseconds
+        and summed algorithmic bytes of the launches since timing was enabled."""
+        t = TimingT()
+        self._check(self.lib.dpml_get_timing(self.handle, ctypes.byref(t)))
+        return {KERNEL_NAMES[k]: {"launches": int(t.launches[k]), "ms": float(t.ms[k]), "bytes": float(t.bytes[k])}
+                for k in KERNEL_NAMES if t.launches[k] > 0}
 
     # -- RK4 (the paper's integrator) -----------------------------------------
     def rk4_set_state(self, U0, V0=None):

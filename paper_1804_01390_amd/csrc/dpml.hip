@@ -119,6 +119,10 @@ struct dpml {
     TileRefVec frame;                // frame tiles of the two-step variant (host copy)
     dpmlk::TileRef *d_frame = nullptr;
     int64_t n_frame = 0;
+    dpmlk::TileRef *d_adj_frame = nullptr;  // 2D adjoint: tiles outside the marching core
+    int64_t n_adj_frame = -1;               // -1: not built yet
+    dpmlk::Tile3 *d_slabs = nullptr;  // 3D marching variants: tiles of the y/z layer slabs
+    int64_t n_slabs = -1;             // -1: not built yet
     // sources
     int64_t ns = 0, nt_src = 0;
     int64_t *d_src_cells = nullptr, *d_src_order = nullptr;
@@ -153,6 +157,16 @@ struct dpml {
     int plane_axis = -1;
     int64_t plane_index = 0, nt_plane = 0;
     void *planes = nullptr;
+    // optional per-launch timing of the step kernels (event pairs on `stream`)
+    struct Timed {
+        int kind;
+        hipEvent_t e0, e1;
+        double bytes;
+    };
+    bool timing = false;
+    std::vector<Timed> timed;
+    std::vector<hipEvent_t> events;      // pool, reused after each dpml_get_timing
+    size_t events_used = 0;
     std::string err;
 
     void *at(size_t off) { return ws + off; }
@@ -173,6 +187,53 @@ int hip_fail(dpml *h, hipError_t e, const char *what)
         hipError_t e_ = (call);                            \
         if (e_ != hipSuccess) return hip_fail(h, e_, #call); \
     } while (0)
+
+constexpr size_t kMaxTimed = 4096;    // launches recorded between two dpml_get_timing calls
+
+// Layer axis-cells per member: M_a cells on every line along each axis a.
+double aux_cells(const Layout &L)
+{
+    double aux = 0;
+    for (int a = 0; a < L.ndim; ++a) aux += (double)L.M[a] * (double)(L.ncell / L.N[a]);
+    return aux;
+}
+
+// Algorithmic bytes of one step over `cells` cells and `aux` layer
+// axis-cells per member: 3 words per cell, 4 words per layer axis-cell and 1
+// word per cell of a c^2 field.
+double step_bytes(const dpml *H, double cells, double aux)
+{
+    const Layout &L = H->L;
+    const double words = (3.0 * cells + 4.0 * aux) * (double)L.batch + (H->c2_field ? cells : 0.0);
+    return words * (double)L.esize;
+}
+
+hipEvent_t take_event(dpml *H)
+{
+    if (H->events_used == H->events.size()) {
+        hipEvent_t e = nullptr;
+        if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        H->events.push_back(e);
+    }
+    return H->events[H->events_used++];
+}
+
+// Record the start of a timed launch of class `kind`; returns its slot or -1.
+int timed_begin(dpml *H, int kind, double bytes)
+{
+    if (!H->timing || H->timed.size() >= kMaxTimed) return -1;
+    hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(H->stream, &st) != hipSuccess || st != hipStreamCaptureStatusNone) return -1;
+    dpml::Timed t{kind, take_event(H), take_event(H), bytes};
+    if (!t.e0 || !t.e1 || hipEventRecord(t.e0, H->stream) != hipSuccess) return -1;
+    H->timed.push_back(t);
+    return (int)H->timed.size() - 1;
+}
+
+void timed_end(dpml *H, int slot)
+{
+    if (slot >= 0) (void)hipEventRecord(H->timed[(size_t)slot].e1, H->stream);
+}
 
 template <typename T>
 dpmlk::Axis<T> make_axis(dpml *H, int a, bool next)
@@ -224,15 +285,132 @@ dpmlk::StepArgs<T> make_args(dpml *H)
 
 int round8(int v) { return (v + 7) / 8 * 8; }
 
+// Box of a 3D step where no y or z damping term acts: [lo+1, lo+n) on an
+// axis with a layer (cell lo still meets sigma(lo-1)), the whole axis
+// without one.  Returns {y0, y1, z0, z1}.
+void march_box3d(const Layout &L, int b[4])
+{
+    for (int a = 1; a < 3; ++a) {
+        const int k = 2 * (a - 1);
+        if (L.M[a] == 0) {
+            b[k] = 0;
+            b[k + 1] = (int)L.N[a];
+        } else {
+            b[k] = L.lo[a] + 1;
+            b[k + 1] = (int)(L.lo[a] + L.n[a]);
+        }
+    }
+}
+
+// Tiles (64 x 4 cells of one plane) covering everything outside the box.
+int ensure_slabs(dpml *H)
+{
+    if (H->n_slabs >= 0) return DPML_OK;
+    const Layout &L = H->L;
+    int b[4];
+    march_box3d(L, b);
+    const int tx = (int)((L.N[0] + 63) / 64), ty = (int)((L.N[1] + 3) / 4);
+    std::vector<dpmlk::Tile3> t;
+    for (int z = 0; z < (int)L.N[2]; ++z) {
+        const bool zin = z >= b[2] && z < b[3];
+        for (int y = 0; y < ty; ++y) {
+            const int ya = 4 * y, yb = std::min<int>(ya + 4, (int)L.N[1]);
+            if (zin && ya >= b[0] && yb <= b[1]) continue;
+            for (int x = 0; x < tx; ++x) t.push_back({x, y, z, 0});
+        }
+    }
+    H->n_slabs = (int64_t)t.size();
+    if (t.empty()) return DPML_OK;
+    HIP_TRY(H, hipMalloc((void **)&H->d_slabs, t.size() * sizeof(dpmlk::Tile3)));
+    HIP_TRY(H, hipMemcpy(H->d_slabs, t.data(), t.size() * sizeof(dpmlk::Tile3), hipMemcpyHostToDevice));
+    return DPML_OK;
+}
+
+// 3D marching launch: the strips of the box [lo+1, lo+n) in y and z that no
+// x damping term reaches, without any layer code; the other strips with the
+// x-layer terms; the y/z layer slabs one thread per cell.
 template <typename T>
-int launch_step(dpml *H, T *hist = nullptr)
+int launch_march3d(dpml *H, dpmlk::StepArgs<T> p, int ry)
+{
+    const Layout &L = H->L;
+    const unsigned B = (unsigned)L.batch;
+    int b[4];
+    march_box3d(L, b);
+    const bool split = L.M[1] > 0 || L.M[2] > 0;
+    if (split) {
+        int rc = ensure_slabs(H);
+        if (rc) return rc;
+    }
+    // strips of 64 columns [64 t, 64 t + 64) free of x damping terms: inside [lo+1, lo+n)
+    const int nstrips = (int)((L.N[0] + 63) / 64);
+    int s0 = 0, s1 = nstrips;
+    if (L.M[0] > 0) {
+        s0 = (L.lo[0] + 1 + 63) / 64;
+        s1 = (int)((L.lo[0] + L.n[0]) / 64);
+        if (s1 < s0) s1 = s0;
+    }
+    p.tile_rows = H->tile_rows > 0 ? H->tile_rows : 32;
+    p.tiles_y = (b[1] - b[0] + 4 * ry - 1) / (4 * ry);
+    const double rows = (double)(b[1] - b[0]) * (double)(b[3] - b[2]);
+    const double inner_cols = 64.0 * (s1 - s0);
+    const double box = (double)L.N[0] * rows;
+    const double box_aux = (double)L.M[0] * rows;
+    const dim3 block(256);
+    if (split && H->n_slabs > 0) {
+        const int slot = timed_begin(H, DPML_KERNEL_FRAME,
+                                     step_bytes(H, (double)L.ncell - box, aux_cells(L) - box_aux));
+        const dim3 g2((unsigned)round8((int)H->n_slabs), B);
+        hipLaunchKernelGGL((dpmlk::k_step_slabs3d<T>), g2, block, 0, H->stream, p, H->d_slabs, (int)H->n_slabs,
+                           b[0], b[1], b[2], b[3]);
+        timed_end(H, slot);
+    }
+    // launch the strips [t0, t1) with or without the x-layer code; the two
+    // edge strips alone are few tiles, so they march shorter chunks
+    auto strips = [&](int t0, int t1, bool layer, int kind, double bytes) {
+        if (t1 <= t0 || p.tiles_y <= 0) return;
+        dpmlk::StepArgs<T> q = p;
+        if (layer) q.tile_rows = std::max(8, p.tile_rows / 4);
+        const int tz = (b[3] - b[2] + q.tile_rows - 1) / q.tile_rows;
+        if (tz <= 0) return;
+        q.tiles_x = t1 - t0;
+        q.n_tiles = q.tiles_x * q.tiles_y * tz;
+        const int slot = timed_begin(H, kind, bytes);
+        const dim3 grid((unsigned)round8(q.n_tiles), B);
+        if (ry == 4 && layer)
+            hipLaunchKernelGGL((dpmlk::k_step_zmarch3d<T, 4, 1>), grid, block, 0, H->stream, q, t0, b[0], b[1], b[2], b[3]);
+        else if (ry == 4)
+            hipLaunchKernelGGL((dpmlk::k_step_zmarch3d<T, 4, 0>), grid, block, 0, H->stream, q, t0, b[0], b[1], b[2], b[3]);
+        else if (layer)
+            hipLaunchKernelGGL((dpmlk::k_step_zmarch3d<T, 2, 1>), grid, block, 0, H->stream, q, t0, b[0], b[1], b[2], b[3]);
+        else
+            hipLaunchKernelGGL((dpmlk::k_step_zmarch3d<T, 2, 0>), grid, block, 0, H->stream, q, t0, b[0], b[1], b[2], b[3]);
+        timed_end(H, slot);
+    };
+    const bool whole = !split && s0 == 0 && s1 == nstrips;
+    strips(s0, s1, false, whole ? DPML_KERNEL_STEP : DPML_KERNEL_CORE, step_bytes(H, inner_cols * rows, 0.0));
+    // the edge strips hold the x layer: frame work
+    const double edge_cells = box - inner_cols * rows;
+    const double edge_bytes = step_bytes(H, edge_cells, box_aux);
+    const double left = 64.0 * s0 * rows;
+    strips(0, s0, true, DPML_KERNEL_FRAME, edge_cells > 0 ? edge_bytes * left / edge_cells : 0.0);
+    strips(s1, nstrips, true, DPML_KERNEL_FRAME, edge_cells > 0 ? edge_bytes * (edge_cells - left) / edge_cells : 0.0);
+    HIP_TRY(H, hipGetLastError());
+    return DPML_OK;
+}
+
+template <typename T>
+int launch_step(dpml *H, T *hist = nullptr, T *uout = nullptr)
 {
     const Layout &L = H->L;
     dpmlk::StepArgs<T> p = make_args<T>(H);
     p.hist = hist;
+    p.uout = uout;
     const unsigned B = (unsigned)L.batch;
     int variant = (H->variant == DPML_VARIANT_AUTO || H->variant == DPML_VARIANT_TWOSTEP) ? DPML_VARIANT_CELL
                                                                                         : H->variant;
+    if (L.ndim == 3 && variant != DPML_VARIANT_CELL)
+        return launch_march3d<T>(H, p, variant == DPML_VARIANT_MARCH ? 4 : 2);
+    const int slot = timed_begin(H, DPML_KERNEL_STEP, step_bytes(H, (double)L.ncell, aux_cells(L)));
     if (variant == DPML_VARIANT_CELL) {
         // tile_rows selects the block shape: TH rows of 256/TH cells (TH = 1, 2, 4, 8)
         const int th = (H->tile_rows == 1 || H->tile_rows == 2 || H->tile_rows == 8) ? H->tile_rows : 4;
@@ -249,7 +427,7 @@ int launch_step(dpml *H, T *hist = nullptr)
         else if (th == 8) { DPML_CELL_LAUNCH(8) }
         else { DPML_CELL_LAUNCH(4) }
 #undef DPML_CELL_LAUNCH
-    } else if (L.ndim == 2) {
+    } else {
         // vector width: 8 bytes per thread when the rows allow it
         constexpr int VX = sizeof(T) == 4 ? 2 : 1;
         const int vx = (L.N[0] % VX == 0) ? VX : 1;
@@ -267,20 +445,8 @@ int launch_step(dpml *H, T *hist = nullptr)
             hipLaunchKernelGGL((dpmlk::k_step_march2d<T, 1, 4>), grid, block, 0, H->stream, p);
         else
             hipLaunchKernelGGL((dpmlk::k_step_march2d<T, 1, 1>), grid, block, 0, H->stream, p);
-    } else {
-        // MARCH: waves of 64 columns x 4 rows; MARCH1: 64 columns x 2 rows
-        const int ry = variant == DPML_VARIANT_MARCH ? 4 : 2;
-        p.tile_rows = H->tile_rows > 0 ? H->tile_rows : 32;
-        p.tiles_x = (int)((L.N[0] + 63) / 64);
-        p.tiles_y = (int)((L.N[1] + 4 * ry - 1) / (4 * ry));
-        const int tiles_z = (int)((L.N[2] + p.tile_rows - 1) / p.tile_rows);
-        p.n_tiles = p.tiles_x * p.tiles_y * tiles_z;
-        dim3 grid((unsigned)round8(p.n_tiles), B), block(256);
-        if (ry == 4)
-            hipLaunchKernelGGL((dpmlk::k_step_zmarch3d<T, 4>), grid, block, 0, H->stream, p);
-        else
-            hipLaunchKernelGGL((dpmlk::k_step_zmarch3d<T, 2>), grid, block, 0, H->stream, p);
     }
+    timed_end(H, slot);
     HIP_TRY(H, hipGetLastError());
     return DPML_OK;
 }
@@ -413,6 +579,8 @@ int launch_twostep(dpml *H)
     p.tile_rows = rows;
     for (int q = 0; q < 4; ++q) p.skip[q] = r[q];
     const dim3 grid((unsigned)(frame_blocks + core_blocks), B), block(256);
+    const double core = (double)(r[1] - r[0]) * (double)(r[3] - r[2]), frame = (double)L.ncell - core;
+    int slot = timed_begin(H, DPML_KERNEL_PAIR, step_bytes(H, 2.0 * core + frame, aux_cells(L)));
     if (p.c2)
         hipLaunchKernelGGL((dpmlk::k_step2_march<T, VX, 4, true>), grid, block, 0, H->stream, p, D, r[0], r[1],
                            r[2], r[3], strips, n_waves, (const dpmlk::TileRef *)H->d_frame, (int)H->n_frame,
@@ -421,6 +589,7 @@ int launch_twostep(dpml *H)
         hipLaunchKernelGGL((dpmlk::k_step2_march<T, VX, 4, false>), grid, block, 0, H->stream, p, D, r[0], r[1],
                            r[2], r[3], strips, n_waves, (const dpmlk::TileRef *)H->d_frame, (int)H->n_frame,
                            frame_blocks);
+    timed_end(H, slot);
     if (H->n_frame > 0) {
         // step n+1 -> n+2 on the frame: read C (U^{n+1}), A (U^n); write D; aux buffers swap
         dim3 g2((unsigned)frame_blocks, B);
@@ -431,7 +600,9 @@ int launch_twostep(dpml *H)
         p2.uo = A;
         p2.uout = D;
         for (int q = 0; q < 4; ++q) p2.skip[q] = r[q];
+        slot = timed_begin(H, DPML_KERNEL_FRAME, step_bytes(H, frame, aux_cells(L)));
         hipLaunchKernelGGL((dpmlk::k_step_frame<T>), g2, block, 0, H->stream, p2, H->d_frame, (int)H->n_frame);
+        timed_end(H, slot);
     }
     HIP_TRY(H, hipGetLastError());
     H->u_now = D;
@@ -846,6 +1017,34 @@ int dpml_sync(dpml_t *H)
     return DPML_OK;
 }
 
+int dpml_set_timing(dpml_t *H, int32_t enable)
+{
+    if (!H) return DPML_EINVAL;
+    if (enable && !H->timing) {
+        H->timed.clear();
+        H->events_used = 0;
+    }
+    H->timing = enable != 0;
+    return DPML_OK;
+}
+
+int dpml_get_timing(dpml_t *H, dpml_timing_t *out)
+{
+    if (!H || !out) return DPML_EINVAL;
+    *out = dpml_timing_t{};
+    if (!H->timed.empty()) HIP_TRY(H, hipEventSynchronize(H->timed.back().e1));
+    for (const dpml::Timed &t : H->timed) {
+        float ms = 0.f;
+        HIP_TRY(H, hipEventElapsedTime(&ms, t.e0, t.e1));
+        out->launches[t.kind] += 1;
+        out->ms[t.kind] += ms;
+        out->bytes[t.kind] += t.bytes;
+    }
+    H->timed.clear();
+    H->events_used = 0;
+    return DPML_OK;
+}
+
 void dpml_destroy(dpml_t *H)
 {
     if (!H) return;
@@ -857,8 +1056,11 @@ void dpml_destroy(dpml_t *H)
     if (H->d_src_order) (void)hipFree(H->d_src_order);
     if (H->d_rec_cells) (void)hipFree(H->d_rec_cells);
     if (H->d_frame) (void)hipFree(H->d_frame);
+    if (H->d_slabs) (void)hipFree(H->d_slabs);
+    if (H->d_adj_frame) (void)hipFree(H->d_adj_frame);
     if (H->d_rec_sorted) (void)hipFree(H->d_rec_sorted);
     if (H->d_rec_order) (void)hipFree(H->d_rec_order);
+    for (hipEvent_t e : H->events) (void)hipEventDestroy(e);
     delete H;
 }
 
@@ -934,6 +1136,46 @@ int forward_ckpt_impl(dpml *H, int64_t nsteps)
     return DPML_OK;
 }
 
+constexpr int kAdjRows = 4;   // rows per wave of the 2D marching adjoint kernel
+
+// Core of the 2D adjoint: cells whose update, and whose neighbours' band
+// slots, carry no layer term: [lo+2, lo+n-1) on an axis with a layer, the
+// whole axis without one.  Returns {x0, x1, y0, y1}.
+void adj_core(const Layout &L, int r[4])
+{
+    for (int a = 0; a < 2; ++a) {
+        if (L.M[a] == 0) {
+            r[2 * a] = 0;
+            r[2 * a + 1] = (int)L.N[a];
+        } else {
+            r[2 * a] = L.lo[a] + 2;
+            r[2 * a + 1] = std::max(r[2 * a], (int)(L.lo[a] + L.n[a] - 1));
+        }
+    }
+}
+
+// 64 x 4 tiles holding any cell outside the adjoint core.
+int ensure_adj_frame(dpml *H)
+{
+    if (H->n_adj_frame >= 0) return DPML_OK;
+    const Layout &L = H->L;
+    int r[4];
+    adj_core(L, r);
+    std::vector<dpmlk::TileRef> t;
+    const int tx = (int)((L.N[0] + 63) / 64), ty = (int)((L.N[1] + 3) / 4);
+    for (int y = 0; y < ty; ++y)
+        for (int x = 0; x < tx; ++x) {
+            const int xa = x * 64, xb = std::min<int>(xa + 64, (int)L.N[0]);
+            const int ya = y * 4, yb = std::min<int>(ya + 4, (int)L.N[1]);
+            if (!(xa >= r[0] && xb <= r[1] && ya >= r[2] && yb <= r[3])) t.push_back({0, x, y, 0});
+        }
+    H->n_adj_frame = (int64_t)t.size();
+    if (t.empty()) return DPML_OK;
+    HIP_TRY(H, hipMalloc((void **)&H->d_adj_frame, t.size() * sizeof(dpmlk::TileRef)));
+    HIP_TRY(H, hipMemcpy(H->d_adj_frame, t.data(), t.size() * sizeof(dpmlk::TileRef), hipMemcpyHostToDevice));
+    return DPML_OK;
+}
+
 template <typename T>
 int adjoint_impl(dpml *H, const void *resid, double *grad, void *grad_w)
 {
@@ -961,6 +1203,19 @@ int adjoint_impl(dpml *H, const void *resid, double *grad, void *grad_w)
     dim3 grid((unsigned)((L.N[0] + 63) / 64), (unsigned)((L.N[1] + 3) / 4), (unsigned)(L.ndim == 3 ? L.N[2] : 1));
     const int adj_tiles = (int)(((L.N[0] + 63) / 64) * ((L.N[1] + 3) / 4) * (L.ndim == 3 ? L.N[2] : 1));
     const dim3 agrid((unsigned)round8(adj_tiles)), ablock(256);
+    // 2D: the core in marching waves of 64 columns x kAdjRows rows, the
+    // frame one thread per cell over a tile list
+    int core[4] = {0, 0, 0, 0};
+    int adj_tiles_x = 0, adj_waves = 0;
+    if (L.ndim == 2) {
+        int rc = ensure_adj_frame(H);
+        if (rc) return rc;
+        adj_core(L, core);
+        adj_tiles_x = (core[1] - core[0] + 63) / 64;
+        adj_waves = adj_tiles_x * ((core[3] - core[2] + kAdjRows - 1) / kAdjRows);
+    }
+    const dim3 mgrid((unsigned)round8((adj_waves + 3) / 4));
+    const dim3 fgrid((unsigned)round8((int)std::max<int64_t>(H->n_adj_frame, 0)));
     for (int64_t seg = A.nck - 1; seg >= 0; --seg) {
         const int64_t t0 = seg * every, t1 = std::min(t0 + every, nsteps);
         // restore the checkpoint and recompute U^{t0} .. U^{t1-1} into the history
@@ -978,20 +1233,9 @@ int adjoint_impl(dpml *H, const void *resid, double *grad, void *grad_w)
         for (int64_t k = t0; k + 1 < t1; ++k) {
             T *slot = (T *)(ws + A.off_hist + (size_t)(k - t0 + 1) * A.level);
             T *cur = (T *)(ws + A.off_hist + (size_t)(k - t0) * A.level);
-            dpmlk::StepArgs<T> p = make_args<T>(H);
-            p.u = cur;
-            p.uo = (T *)H->u_old;           // U^{k-1}: the checkpoint's level or the previous slot
-            p.uout = slot;
-            const int th = 4;
-            p.tiles_x = (int)((L.N[0] + 63) / 64);
-            p.tiles_y = (int)((L.N[1] + th - 1) / th);
-            p.n_tiles = p.tiles_x * p.tiles_y * (int)(L.ndim == 3 ? L.N[2] : 1);
-            dim3 g1((unsigned)round8(p.n_tiles), (unsigned)L.batch), b1(256);
-            if (L.ndim == 2)
-                hipLaunchKernelGGL((dpmlk::k_step_cell<T, 2, 4>), g1, b1, 0, H->stream, p);
-            else
-                hipLaunchKernelGGL((dpmlk::k_step_cell<T, 3, 4>), g1, b1, 0, H->stream, p);
-            HIP_TRY(H, hipGetLastError());
+            H->u_now = cur;                 // U^k; u_old holds U^{k-1}
+            rc = launch_step<T>(H, nullptr, slot);
+            if (rc) return rc;
             if (H->ns > 0 && H->n < H->nt_src) {
                 dim3 g2((unsigned)((H->ns + 255) / 256)), b2(256);
                 hipLaunchKernelGGL((dpmlk::k_inject<T>), g2, b2, 0, H->stream, slot, H->d_src_cells,
@@ -1044,10 +1288,20 @@ int adjoint_impl(dpml *H, const void *resid, double *grad, void *grad_w)
             q.nz = (int32_t)L.N[2];
             q.batch = (int32_t)L.batch;
             q.bstride = L.ncell;
-            if (L.ndim == 2)
-                hipLaunchKernelGGL((dpmlk::k_adjoint_cell<T, 2>), agrid, ablock, 0, H->stream, q);
-            else
+            if (L.ndim == 2) {
+                if (H->n_adj_frame > 0) {
+                    dpmlk::AdjArgs<T> f = q;
+                    f.tiles = H->d_adj_frame;
+                    f.ntiles = (int32_t)H->n_adj_frame;
+                    for (int k = 0; k < 4; ++k) f.skip[k] = core[k];
+                    hipLaunchKernelGGL((dpmlk::k_adjoint_cell<T, 2>), fgrid, ablock, 0, H->stream, f);
+                }
+                if (adj_waves > 0)
+                    hipLaunchKernelGGL((dpmlk::k_adjoint_march2d<T, kAdjRows>), mgrid, ablock, 0, H->stream, q,
+                                       core[0], core[1], core[2], core[3], adj_tiles_x, adj_waves);
+            } else {
                 hipLaunchKernelGGL((dpmlk::k_adjoint_cell<T, 3>), agrid, ablock, 0, H->stream, q);
+            }
             HIP_TRY(H, hipGetLastError());
             lcur = 1 - lcur;
             acur = 1 - acur;
@@ -1594,18 +1848,27 @@ int step_graph_impl(dpml *H, int64_t nsteps)
         dpml view = *H;
         view.stream = H->cap;
         view.err.clear();
+        view.timing = false;
         if (twostep_ok(H)) {                 // the frame table must exist before capture
             int rcf = ensure_frame(H);
             if (rcf) return rcf;
             view.d_frame = H->d_frame;
             view.n_frame = H->n_frame;
         }
+        if (H->L.ndim == 3 && (H->L.M[1] > 0 || H->L.M[2] > 0)) {   // likewise the slab table
+            int rcs = ensure_slabs(H);
+            if (rcs) return rcs;
+            view.d_slabs = H->d_slabs;
+            view.n_slabs = H->n_slabs;
+        }
         HIP_TRY(H, hipStreamBeginCapture(H->cap, hipStreamCaptureModeRelaxed));
-        int rc = step_impl<T>(&view, nsteps);        hipGraph_t g = nullptr;
+        int rc = step_impl<T>(&view, nsteps);
+        hipGraph_t g = nullptr;
         hipError_t e = hipStreamEndCapture(H->cap, &g);
         view.cap = nullptr; view.graph = nullptr; view.exec = nullptr;   // not owned by the view
         view.d_src_cells = view.d_src_order = view.d_rec_cells = view.d_rec_sorted = view.d_rec_order = nullptr;
         view.d_frame = nullptr;
+        view.d_slabs = nullptr;
         H->graph_end_unow = view.u_now;
         H->graph_end_uold = view.u_old;
         H->graph_end_cur = view.cur;

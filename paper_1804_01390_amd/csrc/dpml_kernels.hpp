@@ -104,21 +104,78 @@ __device__ __forceinline__ int band_coord(const Axis<T> &A, int i)
     return i >= A.b ? i - A.b : i + A.hi;
 }
 
-// Damping terms of one axis at a cell with band coordinate j <= M: returns
-// the contribution sigma(i) Psi(i+e) - sigma(i-1) Phi(i-e) (to be scaled by
-// 1/h) and writes Phi^{n+1}, Psi^{n+1} of the cell (Eqs. (DiscretePML b, c)
-// with a forward step):
+// Damping terms of one axis at a cell with band coordinate j <= M (Eqs.
+// (DiscretePML b, c) with a forward step):
 //   Phi' = Phi + dt (-1/2 (sigma(i-1) Phi(i-e) + sigma(i) Phi) - (U(i+e) - U(i-e))/(2h))
 //   Psi' = Psi + dt (-1/2 (sigma(i-1) Psi + sigma(i) Psi(i+e)) - (U(i+e) - U(i-e))/(2h))
-//   cbase: compact index of slot j = 0 for this cell's line along the axis;
-//   cstr : stride of the axis in the compact array;  um, up = U(i-e), U(i+e).
+// and the contribution sigma(i) Psi(i+e) - sigma(i-1) Phi(i-e) to Eq.
+// (DiscretePML a) (to be scaled by 1/h).  Split in two: layer_load reads
+// everything one axis needs, layer_finish computes and stores; a cell
+// issues the loads of all its axes before the first store, so the (possibly
+// aliasing) stores of one axis do not hold back the loads of the next.
+// um, up = U(i-e), U(i+e).
 template <typename T>
-__device__ __forceinline__ T layer_terms(const Axis<T> &A, int j, int64_t cbase, int64_t cstr,
-                                         T um, T up, T dt, T inv_2h)
+struct LayerIn {
+    T s, sl, phi_l, psi_r, phi_c, psi_c;
+    int64_t c;
+    bool on;          // the cell has this axis's terms (j <= M)
+};
+
+// Axis a's compact index of slot 0 for the line through (x, y, z), and the
+// axis's stride in the compact array.
+template <int A_>
+__device__ __forceinline__ int64_t layer_base(int M, int64_t nx, int64_t ny, int x, int y, int z)
 {
-    const int64_t c = cbase + (int64_t)j * cstr;
+    if (A_ == 0) return ((int64_t)z * ny + y) * (M + 1);      // [z][y][Mx+1]
+    if (A_ == 1) return (int64_t)z * (M + 1) * nx + x;         // [z][My+1][x]
+    return (int64_t)y * nx + x;                                // [Mz+1][y][x]
+}
+
+template <int A_, typename T>
+__device__ __forceinline__ LayerIn<T> layer_load(const Axis<T> &A, int j, int64_t nx, int64_t ny, int x, int y,
+                                                 int z)
+{
+    LayerIn<T> L;
+    L.on = j <= A.M;
+    L.s = L.sl = L.phi_l = L.psi_r = L.phi_c = L.psi_c = T(0);
+    L.c = 0;
+    if (!L.on) return L;
+    const int64_t cstr = A_ == 0 ? 1 : (A_ == 1 ? nx : nx * ny);
+    L.c = layer_base<A_>(A.M, nx, ny, x, y, z) + (int64_t)j * cstr;
     // with walls, slot hi is cell 0 (its left neighbour is a ghost and the
     // ghost edge is undamped) and slot hi-1 is cell N-1 (right neighbour ghost)
+    const bool left_ghost = A.wall && j == A.hi;
+    const bool right_ghost = A.wall && j == A.hi - 1;
+    L.s = A.sig[j];                                                      // sigma_a(i)
+    if (j > 0 && !left_ghost) {
+        L.sl = A.sig[j - 1];                                             // sigma_a(i-1)
+        L.phi_l = A.phi[L.c - cstr];                                     // Phi_a(i-e)
+    }
+    if (j < A.M && !right_ghost) L.psi_r = A.psi[L.c + cstr];           // Psi_a(i+e)
+    if (j < A.M) L.phi_c = A.phi[L.c];
+    if (j > 0) L.psi_c = A.psi[L.c];
+    return L;
+}
+
+template <typename T>
+__device__ __forceinline__ T layer_finish(const Axis<T> &A, const LayerIn<T> &L, int j, T um, T up, T dt, T inv_2h)
+{
+    // (L.c is only meaningful when L.on; callers test it)
+    const T grad = (up - um) * inv_2h;
+    if (j < A.M) A.phi_o[L.c] = L.phi_c + dt * (T(-0.5) * (L.sl * L.phi_l + L.s * L.phi_c) - grad);
+    if (j > 0) A.psi_o[L.c] = L.psi_c + dt * (T(-0.5) * (L.sl * L.psi_c + L.s * L.psi_r) - grad);
+    return L.s * L.psi_r - L.sl * L.phi_l;
+}
+
+// The same terms in one piece (loads, arithmetic and stores of one axis
+// together): fewer instructions and registers where most cells lie off the
+// layer.
+template <int A_, typename T>
+__device__ __forceinline__ T layer_terms(const Axis<T> &A, int j, int64_t nx, int64_t ny, int x, int y, int z,
+                                         T um, T up, T dt, T inv_2h)
+{
+    const int64_t cstr = A_ == 0 ? 1 : (A_ == 1 ? nx : nx * ny);
+    const int64_t c = layer_base<A_>(A.M, nx, ny, x, y, z) + (int64_t)j * cstr;
     const bool left_ghost = A.wall && j == A.hi;
     const bool right_ghost = A.wall && j == A.hi - 1;
     const T s = A.sig[j];                                              // sigma_a(i)
@@ -138,43 +195,69 @@ __device__ __forceinline__ T layer_terms(const Axis<T> &A, int j, int64_t cbase,
 }
 
 // Complete update of one cell given its stencil values.  (x, y, z) are the
-// cell coordinates; for 2D z = 0 and the z values are unused.
-template <typename T, int D>
+// cell coordinates; for 2D z = 0 and the z values are unused.  AX is the set
+// of axes (bit a for axis a) whose layer terms the caller may meet; the
+// others are left out of the code (callers that only see cells off those
+// bands).  HOIST: issue the layer loads of all axes before any of their
+// stores (kernels whose cells mostly lie in the layer); otherwise each
+// axis's terms are evaluated in one piece (kernels whose cells mostly lie
+// off it).  Both evaluate the same expressions in the same order.
+template <typename T, int D, int AX = 7, bool HOIST = false>
 __device__ __forceinline__ T cell_update(const StepArgs<T> &p, int x, int y, int z, int64_t idx,
                                          T uc, T uxm, T uxp, T uym, T uyp, T uzm, T uzp, T uold)
 {
+    const int64_t nx = p.nx, ny = p.ny;
+    if (!HOIST) {
+        // Eq. (DiscretePML a): c^2 sum_a (U(i-e) - 2U + U(i+e))/h^2 + sum_a (...)/h
+        T lap = T(0);
+        lap += ((uxm - T(2) * uc) + uxp) * p.inv_h2;
+        lap += ((uym - T(2) * uc) + uyp) * p.inv_h2;
+        if (D == 3) lap += ((uzm - T(2) * uc) + uzp) * p.inv_h2;
+        const T c2 = p.c2 ? p.c2[idx] : p.c2_const;
+        T damp = T(0);
+        if ((AX & 1) && p.ax[0].M > 0) {
+            const int j = band_coord(p.ax[0], x);
+            if (j <= p.ax[0].M) damp += layer_terms<0>(p.ax[0], j, nx, ny, x, y, z, uxm, uxp, p.dt, p.inv_2h) * p.inv_h;
+        }
+        if ((AX & 2) && p.ax[1].M > 0) {
+            const int j = band_coord(p.ax[1], y);
+            if (j <= p.ax[1].M) damp += layer_terms<1>(p.ax[1], j, nx, ny, x, y, z, uym, uyp, p.dt, p.inv_2h) * p.inv_h;
+        }
+        if (D == 3 && (AX & 4) && p.ax[2].M > 0) {
+            const int j = band_coord(p.ax[2], z);
+            if (j <= p.ax[2].M) damp += layer_terms<2>(p.ax[2], j, nx, ny, x, y, z, uzm, uzp, p.dt, p.inv_2h) * p.inv_h;
+        }
+        const T rhs = c2 * lap + damp;
+        return (T(2) * uc - uold) + p.dt2 * rhs;
+    }
+    // loads first: c^2 and the layer inputs of every axis
+    const T c2 = p.c2 ? p.c2[idx] : p.c2_const;
+    const bool lx = (AX & 1) && p.ax[0].M > 0, ly = (AX & 2) && p.ax[1].M > 0;
+    const bool lz = D == 3 && (AX & 4) && p.ax[2].M > 0;
+    int jx = 0, jy = 0, jz = 0;
+    LayerIn<T> Lx, Ly, Lz;
+    Lx.on = Ly.on = Lz.on = false;
+    if (lx) {
+        jx = band_coord(p.ax[0], x);
+        Lx = layer_load<0>(p.ax[0], jx, nx, ny, x, y, z);
+    }
+    if (ly) {
+        jy = band_coord(p.ax[1], y);
+        Ly = layer_load<1>(p.ax[1], jy, nx, ny, x, y, z);
+    }
+    if (lz) {
+        jz = band_coord(p.ax[2], z);
+        Lz = layer_load<2>(p.ax[2], jz, nx, ny, x, y, z);
+    }
     // Eq. (DiscretePML a): c^2 sum_a (U(i-e) - 2U + U(i+e))/h^2 + sum_a (...)/h
     T lap = T(0);
     lap += ((uxm - T(2) * uc) + uxp) * p.inv_h2;
     lap += ((uym - T(2) * uc) + uyp) * p.inv_h2;
     if (D == 3) lap += ((uzm - T(2) * uc) + uzp) * p.inv_h2;
-    const T c2 = p.c2 ? p.c2[idx] : p.c2_const;
     T damp = T(0);
-    const int64_t nx = p.nx, ny = p.ny;
-    // x-axis layer: compact [z][y][Mx+1]
-    if (p.ax[0].M > 0) {
-        const int j = band_coord(p.ax[0], x);
-        if (j <= p.ax[0].M) {
-            const int64_t base = ((int64_t)z * ny + y) * (p.ax[0].M + 1);
-            damp += layer_terms(p.ax[0], j, base, 1, uxm, uxp, p.dt, p.inv_2h) * p.inv_h;
-        }
-    }
-    // y-axis layer: compact [z][My+1][x]
-    if (p.ax[1].M > 0) {
-        const int j = band_coord(p.ax[1], y);
-        if (j <= p.ax[1].M) {
-            const int64_t base = (int64_t)z * (p.ax[1].M + 1) * nx + x;
-            damp += layer_terms(p.ax[1], j, base, nx, uym, uyp, p.dt, p.inv_2h) * p.inv_h;
-        }
-    }
-    // z-axis layer: compact [Mz+1][y][x]
-    if (D == 3 && p.ax[2].M > 0) {
-        const int j = band_coord(p.ax[2], z);
-        if (j <= p.ax[2].M) {
-            const int64_t base = (int64_t)y * nx + x;
-            damp += layer_terms(p.ax[2], j, base, nx * ny, uzm, uzp, p.dt, p.inv_2h) * p.inv_h;
-        }
-    }
+    if (lx && Lx.on) damp += layer_finish(p.ax[0], Lx, jx, uxm, uxp, p.dt, p.inv_2h) * p.inv_h;
+    if (ly && Ly.on) damp += layer_finish(p.ax[1], Ly, jy, uym, uyp, p.dt, p.inv_2h) * p.inv_h;
+    if (lz && Lz.on) damp += layer_finish(p.ax[2], Lz, jz, uzm, uzp, p.dt, p.inv_2h) * p.inv_h;
     const T rhs = c2 * lap + damp;
     return (T(2) * uc - uold) + p.dt2 * rhs;
 }
@@ -281,7 +364,7 @@ __device__ __forceinline__ void store_row(T *ptr, const Row<T, VX> &r)
 // of its arithmetic, so each wave has R times more loads in flight than a
 // row-at-a-time loop.  Register arrays are only indexed with compile-time
 // constants (full groups); the last rows of a tile take a one-row loop.
-template <typename T, int VX, int R>
+template <typename T, int VX, int R, bool HOIST = false>
 __device__ __forceinline__ void march2d_tile(const StepArgs<T> &p, int tx, int ty)
 {
     const int x0 = (tx * 256 + (int)threadIdx.x) * VX;
@@ -314,10 +397,10 @@ __device__ __forceinline__ void march2d_tile(const StepArgs<T> &p, int tx, int t
         for (int k = 0; k < VX; ++k) {
             const T uxm = k == 0 ? left : uc.v[k - 1];
             const T uxp = k == VX - 1 ? right : uc.v[k + 1];
-            out.v[k] = cell_update<T, 2>(p, x0 + k, y, 0, row + x0 + k, uc.v[k], uxm, uxp,
+            out.v[k] = cell_update<T, 2, 7, HOIST>(p, x0 + k, y, 0, row + x0 + k, uc.v[k], uxm, uxp,
                                          um.v[k], up.v[k], T(0), T(0), old.v[k]);
         }
-        store_row<T, VX>(p.uo + row + x0, out);
+        store_row<T, VX>((p.uout ? p.uout : p.uo) + row + x0, out);
         if (p.hist) store_row<T, VX>(p.hist + row + x0, out);
     };
 
@@ -362,14 +445,9 @@ __global__ void __launch_bounds__(256) k_step_march2d(StepArgs<T> p)
     march2d_tile<T, VX, R>(p, tile % p.tiles_x, tile / p.tiles_x);
 }
 
-// ---------------------------------------------------------------------------
-// Many independent 2D problems of different sizes in one launch: a flat
-// work list of tiles (problem, tile column, tile row) over all problems; each
-// block looks up its problem's arguments (uniform, read through the scalar
-// cache) and runs one marching tile.
-// ---------------------------------------------------------------------------
-// One (256/TH) x TH cell tile of a 2D problem, one thread per cell (the body
-// of the CELL variant, shared with the multi-problem kernel).
+// One (256/TH) x TH cell tile of a 2D problem, one thread per cell, with
+// the layer loads hoisted (the body of the frame kernels, whose cells mostly
+// lie in the layer).
 template <typename T, int TH>
 __device__ __forceinline__ void cell2d_tile(const StepArgs<T> &p, int tx, int ty)
 {
@@ -387,7 +465,7 @@ __device__ __forceinline__ void cell2d_tile(const StepArgs<T> &p, int tx, int ty
     const T uxp = (p.ax[0].wall && x == p.nx - 1) ? T(0) : u[row + xp];
     const T uym = (p.ax[1].wall && y == 0) ? T(0) : u[(int64_t)ym * nx + x];
     const T uyp = (p.ax[1].wall && y == p.ny - 1) ? T(0) : u[(int64_t)yp * nx + x];
-    const T r = cell_update<T, 2>(p, x, y, 0, idx, u[idx], uxm, uxp, uym, uyp, T(0), T(0), p.uo[idx]);
+    const T r = cell_update<T, 2, 7, true>(p, x, y, 0, idx, u[idx], uxm, uxp, uym, uyp, T(0), T(0), p.uo[idx]);
     (p.uout ? p.uout : p.uo)[idx] = r;
     if (p.hist) p.hist[idx] = r;
 }
@@ -477,15 +555,26 @@ struct March2Ctx {
         return o;
     }
 
-    // rolling state at row r: U^n rows r-1, r; U^{n+1} rows r-2, r-1; c^2 row r-1
+    // A tile's rows are visited in march order k = 0, 1, ..., L-1 (L rows):
+    // row base + DIR k.  Odd tile rows march upwards (DIR = -1), so two
+    // neighbouring tiles reach their shared halo rows at the same time (both
+    // at the start, or both at the end) and the second read hits the L2.
+    // level() takes rows in grid order (y-1, y, y+1), whatever DIR is.
+    template <int DIR>
+    __device__ __forceinline__ R lev(const R &prev, const R &cur, const R &next, const R &old, const R &c) const
+    {
+        return DIR > 0 ? level(prev, cur, next, old, c) : level(next, cur, prev, old, c);
+    }
+
+    // rolling state at march index k: U^n at k-1, k; U^{n+1} at k-2, k-1; c^2 at k-1
     struct State {
         R n0, n1, v0, v1, c0;
     };
 
-    // G rows r .. r+G-1 of U^{n+1} and rows r-1 .. r+G-2 of U^{n+2}; every load
-    // of the group is issued before its arithmetic
-    template <int G>
-    __device__ __forceinline__ void group(State &s, int r, int yb) const
+    // U^{n+1} at march indices k .. k+G-1 and U^{n+2} at k-1 .. k+G-2; every
+    // load of the group is issued before its arithmetic
+    template <int G, int DIR>
+    __device__ __forceinline__ void group(State &s, int base, int k, int L) const
     {
         R wn[G + 2], po[G], v[G + 2], cw[G + 1];
         wn[0] = s.n0;
@@ -495,21 +584,49 @@ struct March2Ctx {
         cw[0] = s.c0;
 #pragma unroll
         for (int g = 0; g < G; ++g) {
-            wn[2 + g] = load(u, wrapy(r + 1 + g));
-            po[g] = load(up, wrapy(r + g));
-            if (C2F) cw[1 + g] = load(c2, wrapy(r + g));
+            wn[2 + g] = load(u, wrapy(base + DIR * (k + 1 + g)));
+            po[g] = load(up, wrapy(base + DIR * (k + g)));
+            if (C2F) cw[1 + g] = load(c2, wrapy(base + DIR * (k + g)));
         }
 #pragma unroll
         for (int g = 0; g < G; ++g) {
-            v[2 + g] = level(wn[g], wn[g + 1], wn[g + 2], po[g], cw[1 + g]);
-            if (r + g < yb) store(o1, r + g, v[2 + g]);
-            store(o2, r - 1 + g, level(v[g], v[g + 1], v[g + 2], wn[g], cw[g]));
+            v[2 + g] = lev<DIR>(wn[g], wn[g + 1], wn[g + 2], po[g], cw[1 + g]);
+            if (k + g < L) store(o1, base + DIR * (k + g), v[2 + g]);
+            store(o2, base + DIR * (k - 1 + g), lev<DIR>(v[g], v[g + 1], v[g + 2], wn[g], cw[g]));
         }
         s.n0 = wn[G];
         s.n1 = wn[G + 1];
         s.v0 = v[G];
         s.v1 = v[G + 1];
         s.c0 = cw[G];
+    }
+
+    // the whole tile: rows base, base + DIR, ..., L rows
+    template <int G, int DIR>
+    __device__ __forceinline__ void march(int base, int L) const
+    {
+        State s;
+        {
+            // U^{n+1} at march indices -1 and 0
+            const R a0 = load(u, wrapy(base - 2 * DIR)), a1 = load(u, wrapy(base - DIR));
+            const R a2 = load(u, base), a3 = load(u, wrapy(base + DIR));
+            const R p0 = load(up, wrapy(base - DIR)), p1 = load(up, base);
+            R k0{}, k1{};
+            if (C2F) {
+                k0 = load(c2, wrapy(base - DIR));
+                k1 = load(c2, base);
+            }
+            s.v0 = lev<DIR>(a0, a1, a2, p0, k0);
+            s.v1 = lev<DIR>(a1, a2, a3, p1, k1);
+            store(o1, base, s.v1);
+            s.n0 = a2;
+            s.n1 = a3;
+            s.c0 = k1;
+        }
+        // march indices k = 1 .. L of U^{n+1} (index L is the far halo) and k-1 of U^{n+2}
+        int k = 1;
+        for (; k + G - 1 <= L; k += G) group<G, DIR>(s, base, k, L);
+        for (; k <= L; ++k) group<1, DIR>(s, base, k, L);
     }
 };
 
@@ -555,29 +672,10 @@ __global__ void __launch_bounds__(256) k_step2_march(StepArgs<T> p, T *__restric
     c.out = lane >= 1 && lane <= 62 && c.xs < cx1;
     const int rows = p.tile_rows;
     const int ya = cy0 + ty * rows, yb = min(ya + rows, cy1);
-    using R = Row<T, VX>;
-    typename March2Ctx<T, VX, C2F>::State s;
-    {
-        // rows ya-1 and ya of U^{n+1}
-        const R a0 = c.load(c.u, c.wrapy(ya - 2)), a1 = c.load(c.u, c.wrapy(ya - 1));
-        const R a2 = c.load(c.u, ya), a3 = c.load(c.u, c.wrapy(ya + 1));
-        const R p0 = c.load(c.up, c.wrapy(ya - 1)), p1 = c.load(c.up, ya);
-        R k0{}, k1{};
-        if (C2F) {
-            k0 = c.load(c.c2, c.wrapy(ya - 1));
-            k1 = c.load(c.c2, ya);
-        }
-        s.v0 = c.level(a0, a1, a2, p0, k0);
-        s.v1 = c.level(a1, a2, a3, p1, k1);
-        c.store(c.o1, ya, s.v1);
-        s.n0 = a2;
-        s.n1 = a3;
-        s.c0 = k1;
-    }
-    // rows r = ya+1 .. yb of U^{n+1} (row yb is the lower halo) and r-1 of U^{n+2}
-    int r = ya + 1;
-    for (; r + G - 1 <= yb; r += G) c.template group<G>(s, r, yb);
-    for (; r <= yb; ++r) c.template group<1>(s, r, yb);
+    if (ty & 1)
+        c.template march<G, -1>(yb - 1, yb - ya);
+    else
+        c.template march<G, 1>(ya, yb - ya);
 }
 
 // One ordinary step over a list of 64 x 4 cell tiles (the frame around the
@@ -595,6 +693,12 @@ __global__ void __launch_bounds__(256) k_step_frame(StepArgs<T> p, const TileRef
     cell2d_tile<T, 4>(p, t.tx, t.ty);
 }
 
+// ---------------------------------------------------------------------------
+// Many independent 2D problems of different sizes in one launch: a flat
+// work list of tiles (problem, tile column, tile row) over all problems; each
+// block looks up its problem's arguments (uniform, read through the scalar
+// cache) and runs one marching tile.
+// ---------------------------------------------------------------------------
 // Many problems: each block takes one tile of (256 VX) columns x tile_rows
 // rows of one problem from the work list and marches down it (the shape the
 // tuner prefers for single 2D grids), so the per-block lookup of the
@@ -607,7 +711,7 @@ __global__ void __launch_bounds__(256) k_step_multi2d(const StepArgs<T> *__restr
     if (tile >= ntiles) return;
     const TileRef t = tiles[tile];
     const StepArgs<T> p = probs[t.prob];
-    march2d_tile<T, VX, 1>(p, t.tx, t.ty);
+    march2d_tile<T, VX, 1, true>(p, t.tx, t.ty);
 }
 
 // ---------------------------------------------------------------------------
@@ -619,9 +723,16 @@ __global__ void __launch_bounds__(256) k_step_multi2d(const StepArgs<T> *__restr
 // neighbours from the adjacent register rows (the rows just above and below
 // the wave come from the L2 cache, where the neighbouring waves read them as
 // their own).  A block's 4 waves take 4 consecutive row groups.
+//
+// The kernel sweeps the strips tx0, tx0+1, ... of the box [y0c, y1c) x
+// [z0c, z1c) (its tiles counted from (tx0, y0c, z0c)) and carries the layer
+// terms of the axes in AX only.  The library runs it without any layer
+// terms (AX = 0) on the strips where no damping term acts, with the x-layer
+// terms on the two edge strips, and takes the y/z layer slabs outside the
+// box with k_step_slabs3d: each kernel keeps only the code its cells need.
 // ---------------------------------------------------------------------------
-template <typename T, int RY>
-__global__ void __launch_bounds__(256) k_step_zmarch3d(StepArgs<T> p)
+template <typename T, int RY, int AX>
+__global__ void __launch_bounds__(256) k_step_zmarch3d(StepArgs<T> p, int tx0, int y0c, int y1c, int z0c, int z1c)
 {
     const int tile = xcd_tile(blockIdx.x, gridDim.x);
     if (tile >= p.n_tiles) return;
@@ -633,9 +744,9 @@ __global__ void __launch_bounds__(256) k_step_zmarch3d(StepArgs<T> p)
     const int tx = rem - ty * p.tiles_x;
     const int lane = (int)(threadIdx.x & 63);
     const int nx = p.nx, ny = p.ny, nz = p.nz;
-    const int y0 = (ty * 4 + (int)(threadIdx.x >> 6)) * RY;
-    if (y0 >= ny) return;                                  // whole wave; no barriers below
-    const int x0 = tx * 64, x = x0 + lane;
+    const int y0 = y0c + (ty * 4 + (int)(threadIdx.x >> 6)) * RY;
+    if (y0 >= y1c) return;                                 // whole wave; no barriers below
+    const int x0 = (tx0 + tx) * 64, x = x0 + lane;
     const bool wx = p.ax[0].wall, wy = p.ax[1].wall, wz = p.ax[2].wall;
     const int64_t sxy = (int64_t)nx * ny;
     // each lane reads column x (wrapped; the ghost column of a wall reads 0), so
@@ -674,8 +785,8 @@ __global__ void __launch_bounds__(256) k_step_zmarch3d(StepArgs<T> p)
     auto ld = [&](int pz, int r) -> T {
         return (pz < 0 || r < 0 || xzero) ? T(0) : u[(int64_t)pz * sxy + (int64_t)r * nx + xc];
     };
-    const int z0 = tz * p.tile_rows;
-    const int z1 = min(z0 + p.tile_rows, nz);
+    const int z0 = z0c + tz * p.tile_rows;
+    const int z1 = min(z0 + p.tile_rows, z1c);
     T um[RY], uc[RY];
     {
         const int pm = plane_of(z0 - 1);
@@ -686,30 +797,45 @@ __global__ void __launch_bounds__(256) k_step_zmarch3d(StepArgs<T> p)
         }
     }
     T *out = p.uout ? p.uout : p.uo;
-    for (int z = z0; z < z1; ++z) {
+    // the loads plane z needs beyond the window: U^n of plane z+1, U^{n-1}
+    // of plane z, the strip-edge columns and the halo rows of plane z.  They
+    // are issued one plane ahead, so a wave computes plane z while the
+    // loads of plane z+1 are in flight.
+    struct Fetch {
+        T upn[RY], old[RY], edge[RY], hlo, hhi;
+    };
+    auto fetch = [&](int z, Fetch &f) {
         const int pz = plane_of(z + 1);
         const int64_t plane = (int64_t)z * sxy;
-        T upn[RY], old[RY], edge[RY];
 #pragma unroll
         for (int q = 0; q < RY; ++q) {
-            upn[q] = ld(pz, ry[q]);
-            old[q] = (xin && y0 + q < ny) ? p.uo[plane + (int64_t)(y0 + q) * nx + x] : T(0);
-            edge[q] = T(0);
-            if ((lane == 0 || lane == 63) && ry[q] >= 0 && !ezero) edge[q] = u[plane + (int64_t)ry[q] * nx + xe];
+            f.upn[q] = ld(pz, ry[q]);
+            f.old[q] = (xin && y0 + q < y1c) ? p.uo[plane + (int64_t)(y0 + q) * nx + x] : T(0);
+            f.edge[q] = T(0);
+            if ((lane == 0 || lane == 63) && ry[q] >= 0 && !ezero) f.edge[q] = u[plane + (int64_t)ry[q] * nx + xe];
         }
-        const T hlo = ld(z, rlo), hhi = ld(z, rhi);
+        f.hlo = ld(z, rlo);
+        f.hhi = ld(z, rhi);
+    };
+    Fetch cur;
+    if (z0 < z1) fetch(z0, cur);
+    for (int z = z0; z < z1; ++z) {
+        Fetch nxt;
+        if (z + 1 < z1) fetch(z + 1, nxt);
+        const int64_t plane = (int64_t)z * sxy;
 #pragma unroll
         for (int q = 0; q < RY; ++q) {
             T uxm = __shfl_up(uc[q], 1);
             T uxp = __shfl_down(uc[q], 1);
-            if (lane == 0) uxm = edge[q];
-            if (lane == 63) uxp = edge[q];
-            const T uym = q == 0 ? hlo : uc[q - 1];
-            const T uyp = q == RY - 1 ? hhi : uc[q + 1];
+            if (lane == 0) uxm = cur.edge[q];
+            if (lane == 63) uxp = cur.edge[q];
+            const T uym = q == 0 ? cur.hlo : uc[q - 1];
+            const T uyp = q == RY - 1 ? cur.hhi : uc[q + 1];
             const int y = y0 + q;
-            if (xin && y < ny) {
+            if (xin && y < y1c) {
                 const int64_t idx = plane + (int64_t)y * nx + x;
-                const T r = cell_update<T, 3>(p, x, y, z, idx, uc[q], uxm, uxp, uym, uyp, um[q], upn[q], old[q]);
+                const T r = cell_update<T, 3, AX, (AX != 0)>(p, x, y, z, idx, uc[q], uxm, uxp, uym, uyp, um[q],
+                                                              cur.upn[q], cur.old[q]);
                 out[idx] = r;
                 if (p.hist) p.hist[idx] = r;
             }
@@ -717,9 +843,49 @@ __global__ void __launch_bounds__(256) k_step_zmarch3d(StepArgs<T> p)
 #pragma unroll
         for (int q = 0; q < RY; ++q) {
             um[q] = uc[q];
-            uc[q] = upn[q];
+            uc[q] = cur.upn[q];
         }
+        cur = nxt;
     }
+}
+
+// The slabs of a 3D step outside the marching box [y0c, y1c) x [z0c, z1c):
+// one thread per cell over a list of 64 x 4 tiles (tx, ty, z) that covers
+// them, leaving the box's cells alone.
+struct Tile3 {
+    int32_t tx, ty, z, pad;
+};
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_step_slabs3d(StepArgs<T> p, const Tile3 *__restrict__ tiles, int ntiles,
+                                                      int y0c, int y1c, int z0c, int z1c)
+{
+    const int t = xcd_tile(blockIdx.x, gridDim.x);
+    if (t >= ntiles) return;
+    select_member(p, (int)blockIdx.y);
+    const Tile3 tl = tiles[t];
+    const int x = tl.tx * 64 + (int)(threadIdx.x % 64);
+    const int y = tl.ty * 4 + (int)(threadIdx.x / 64);
+    const int z = tl.z;
+    if (x >= p.nx || y >= p.ny) return;
+    if (y >= y0c && y < y1c && z >= z0c && z < z1c) return;
+    const int64_t nx = p.nx, ny = p.ny;
+    const int64_t plane = (int64_t)z * ny * nx;
+    const int64_t row = plane + (int64_t)y * nx;
+    const int64_t idx = row + x;
+    const T *u = p.u;
+    const int xm = wrap_dec(x, p.nx), xp = wrap_inc(x, p.nx);
+    const int ym = wrap_dec(y, p.ny), yp = wrap_inc(y, p.ny);
+    const int zm = wrap_dec(z, p.nz), zp = wrap_inc(z, p.nz);
+    const T uzm = (p.ax[2].wall && z == 0) ? T(0) : u[((int64_t)zm * ny + y) * nx + x];
+    const T uzp = (p.ax[2].wall && z == p.nz - 1) ? T(0) : u[((int64_t)zp * ny + y) * nx + x];
+    const T uxm = (p.ax[0].wall && x == 0) ? T(0) : u[row + xm];
+    const T uxp = (p.ax[0].wall && x == p.nx - 1) ? T(0) : u[row + xp];
+    const T uym = (p.ax[1].wall && y == 0) ? T(0) : u[plane + (int64_t)ym * nx + x];
+    const T uyp = (p.ax[1].wall && y == p.ny - 1) ? T(0) : u[plane + (int64_t)yp * nx + x];
+    const T r = cell_update<T, 3, 7, true>(p, x, y, z, idx, u[idx], uxm, uxp, uym, uyp, uzm, uzp, p.uo[idx]);
+    (p.uout ? p.uout : p.uo)[idx] = r;
+    if (p.hist) p.hist[idx] = r;
 }
 
 // ---------------------------------------------------------------------------
@@ -854,6 +1020,9 @@ struct AdjArgs {
     int32_t nx, ny, nz, batch;
     int64_t bstride;
     int64_t bstride_aux[3];
+    const TileRef *tiles;  // optional 64 x 4 tile list (2D) instead of the whole grid
+    int32_t ntiles;
+    int32_t skip[4];       // with a tile list: cells in [skip0, skip1) x [skip2, skip3) are left alone
 };
 
 // (p + q) of axis A at band slot j (0 outside the band).
@@ -868,14 +1037,25 @@ __device__ __forceinline__ T pq_at(const Axis<T> &A, int j, int64_t cbase, int64
 template <typename T, int D>
 __global__ void __launch_bounds__(256) k_adjoint_cell(AdjArgs<T> p)
 {
-    // 1-D XCD-aware launch over 64 x 4 cell tiles (as the forward CELL kernel)
+    // 1-D XCD-aware launch over 64 x 4 cell tiles (as the forward CELL kernel),
+    // either all tiles of the grid or those of a list (2D; cells of the skip
+    // box are then left to the marching kernel)
     const int tile = xcd_tile(blockIdx.x, gridDim.x);
     const int tiles_x = (p.nx + 63) / 64, tiles_y = (p.ny + 3) / 4;
-    if (tile >= tiles_x * tiles_y * (D == 3 ? p.nz : 1)) return;
-    const int z = D == 3 ? tile / (tiles_x * tiles_y) : 0;
-    const int rem = tile - z * tiles_x * tiles_y;
-    const int x = (rem % tiles_x) * 64 + (int)(threadIdx.x % 64);
-    const int y = (rem / tiles_x) * 4 + (int)(threadIdx.x / 64);
+    int x, y, z = 0;
+    if (p.tiles) {
+        if (tile >= p.ntiles) return;
+        const TileRef t = p.tiles[tile];
+        x = t.tx * 64 + (int)(threadIdx.x % 64);
+        y = t.ty * 4 + (int)(threadIdx.x / 64);
+        if (x >= p.skip[0] && x < p.skip[1] && y >= p.skip[2] && y < p.skip[3]) return;
+    } else {
+        if (tile >= tiles_x * tiles_y * (D == 3 ? p.nz : 1)) return;
+        z = D == 3 ? tile / (tiles_x * tiles_y) : 0;
+        const int rem = tile - z * tiles_x * tiles_y;
+        x = (rem % tiles_x) * 64 + (int)(threadIdx.x % 64);
+        y = (rem / tiles_x) * 4 + (int)(threadIdx.x / 64);
+    }
     if (x >= p.nx || y >= p.ny) return;
     const int nx = p.nx, ny = p.ny, nz = p.nz;
     const int64_t sy = nx, sz = (int64_t)nx * ny;
@@ -967,6 +1147,111 @@ __global__ void __launch_bounds__(256) k_adjoint_cell(AdjArgs<T> p)
         gsum += (double)(p.dt2 * lc) * (double)lapu;
     }
     p.grad[idx] += gsum;
+}
+
+// Load / store through a base pointer plus a 32-bit byte offset: with a
+// wave-uniform base the hardware adds a scalar base to a vector offset, so a
+// run of loads from different rows shares one offset register.
+template <typename T>
+__device__ __forceinline__ T ld_off(const T *base, uint32_t off)
+{
+    return *reinterpret_cast<const T *>(reinterpret_cast<const char *>(base) + off);
+}
+
+template <typename T>
+__device__ __forceinline__ void st_off(T *base, uint32_t off, T v)
+{
+    *reinterpret_cast<T *>(reinterpret_cast<char *>(base) + off) = v;
+}
+
+// Marching form of the same transposed step on the core of a 2D periodic
+// grid -- the cells [cx0, cx1) x [cy0, cy1) whose update and neighbours
+// carry no layer term (k_adjoint_cell takes the rest): each wave owns 64
+// columns x R rows.  For every shot it issues the loads of its whole tile
+// at once (rows -1..R of a^{n+1} and U^n, rows 0..R-1 of a^{n+2}, and the
+// column beyond each strip edge), takes x neighbours from the adjacent lanes
+// and y neighbours from the adjacent rows, and keeps the FP64 c^2 gradient
+// of its R cells in registers across the shots (same order as the cell
+// kernel: shots ascending, one add into grad at the end).  The expressions
+// are those of k_adjoint_cell, evaluated in the same order.
+template <typename T, int R>
+__global__ void __launch_bounds__(256) k_adjoint_march2d(AdjArgs<T> p, int cx0, int cx1, int cy0, int cy1,
+                                                         int tiles_x, int n_waves)
+{
+    // the wave index is uniform across the wave: keep it (and every row
+    // index derived from it) in scalar registers
+    const int w = __builtin_amdgcn_readfirstlane(xcd_tile(blockIdx.x, gridDim.x) * 4 + (int)(threadIdx.x >> 6));
+    if (w >= n_waves) return;                                // whole waves; no barriers below
+    const int lane = (int)(threadIdx.x & 63);
+    const int nx = p.nx, ny = p.ny;
+    const int tx = w % tiles_x, ty = w / tiles_x;
+    const int x0 = cx0 + tx * 64, x = x0 + lane, y0 = cy0 + ty * R;
+    const bool xout = x < cx1;                               // this lane's cell is the kernel's
+    const int xc = x % nx;                                   // lanes past the edge read a wrapped column
+    const int xe = lane == 0 ? (x0 - 1 + nx) % nx : (x0 + 64) % nx;   // lanes 0 / 63: outer column
+    const bool edge = lane == 0 || lane == 63;
+    constexpr uint32_t E = sizeof(T);
+    const uint32_t oc = (uint32_t)xc * E, oe = (uint32_t)xe * E;
+    // row y0-1+r (wrapped) as an element offset of the row start
+    auto rowoff = [&](int r) -> int64_t {
+        int y = y0 - 1 + r;
+        y = y < 0 ? y + ny : (y >= ny ? y - ny : y);
+        return (int64_t)y * nx;
+    };
+    // c^2 of the column (rows -1..R) and of the outer columns (edge lanes)
+    T cl[R + 2], ce[R];
+#pragma unroll
+    for (int r = 0; r < R + 2; ++r) cl[r] = p.c2 ? ld_off(p.c2 + rowoff(r), oc) : p.c2_const;
+#pragma unroll
+    for (int r = 0; r < R; ++r) ce[r] = (p.c2 && edge) ? ld_off(p.c2 + rowoff(r + 1), oe) : p.c2_const;
+    double g[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) g[r] = 0.0;
+#pragma unroll 1
+    for (int bi = 0; bi < p.batch; ++bi) {
+        const int64_t bo = (int64_t)bi * p.bstride;
+        const T *lam = p.lam + bo, *un = p.un + bo;
+        T *lamo = p.lam_o + bo;
+        T L[R + 2], U[R + 2], LO[R], LE[R], UE[R];
+#pragma unroll
+        for (int r = 0; r < R + 2; ++r) {
+            L[r] = ld_off(lam + rowoff(r), oc);
+            U[r] = ld_off(un + rowoff(r), oc);
+        }
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            LO[r] = ld_off((const T *)lamo + rowoff(r + 1), oc);
+            LE[r] = UE[r] = T(0);
+            if (edge) {
+                LE[r] = ld_off(lam + rowoff(r + 1), oe);
+                UE[r] = ld_off(un + rowoff(r + 1), oe);
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            if (y0 + r >= cy1) break;                        // uniform
+            const T lc = L[r + 1], uc = U[r + 1];
+            const T clc = cl[r + 1] * lc;
+            // neighbours across lanes (every lane shuffles; the edge lanes then
+            // take the outer column): c^2 a and U of columns x-1 and x+1
+            T cxm = __shfl_up(clc, 1), cxp = __shfl_down(clc, 1);
+            T uxm = __shfl_up(uc, 1), uxp = __shfl_down(uc, 1);
+            if (lane == 0) { cxm = ce[r] * LE[r]; uxm = UE[r]; }
+            if (lane == 63) { cxp = ce[r] * LE[r]; uxp = UE[r]; }
+            T lapc = T(0), lapu = T(0);
+            lapc += ((cxm - T(2) * clc) + cxp) * p.inv_h2;
+            lapu += ((uxm - T(2) * uc) + uxp) * p.inv_h2;
+            lapc += ((cl[r] * L[r] - T(2) * clc) + cl[r + 2] * L[r + 2]) * p.inv_h2;
+            lapu += ((U[r] - T(2) * uc) + U[r + 2]) * p.inv_h2;
+            const T v = (T(2) * lc - LO[r]) + p.dt2 * lapc;
+            if (xout) st_off(lamo + rowoff(r + 1), oc, v);
+            g[r] += (double)(p.dt2 * lc) * (double)lapu;
+        }
+    }
+    if (!xout) return;
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+        if (y0 + r < cy1) p.grad[(int64_t)(y0 + r) * nx + x] += g[r];
 }
 
 // Adjoint of the start U^{-1} = U^0 + dt^2/2 c^2 L U^0 with a^{-1} = -a^1:

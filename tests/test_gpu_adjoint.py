@@ -15,9 +15,11 @@ pytestmark = pytest.mark.gpu
 TOL = {"f64": 1e-12, "f32": 2e-5}
 
 
-def _shots(ndim=2, batch=3, steps=70, seed=0):
+def _shots(ndim=2, batch=3, steps=70, seed=0, wide=False):
     rng = np.random.default_rng(seed)
-    if ndim == 2:
+    if ndim == 2 and wide:
+        n, lo, hi = [150, 27], [6, 5], [7, 6]   # several 64-column strips, ragged row groups
+    elif ndim == 2:
         n, lo, hi = [40, 34], [6, 5], [7, 6]
     else:
         n, lo, hi = [18, 16, 14], [4, 3, 5], [5, 4, 3]
@@ -58,10 +60,11 @@ def _rel(a, b):
     return float(np.max(np.abs(a - b)) / np.max(np.abs(b)))
 
 
-@pytest.mark.parametrize("dtype,ndim,every", [("f64", 2, 7), ("f32", 2, 9), ("f64", 3, 11), ("f32", 3, 70)])
-def test_adjoint_matches_oracle(dtype, ndim, every):
-    n, lo, hi, N, sig, c2, dt, srcs, rec, wav, obs, steps = _shots(ndim=ndim)
-    print("case adjoint %dD %s ckpt_every=%d" % (ndim, dtype, every), flush=True)
+@pytest.mark.parametrize("dtype,ndim,every,wide", [("f64", 2, 7, False), ("f32", 2, 9, False), ("f64", 3, 11, False),
+                                                  ("f32", 3, 70, False), ("f64", 2, 8, True), ("f32", 2, 13, True)])
+def test_adjoint_matches_oracle(dtype, ndim, every, wide):
+    n, lo, hi, N, sig, c2, dt, srcs, rec, wav, obs, steps = _shots(ndim=ndim, wide=wide)
+    print("case adjoint %dD %s ckpt_every=%d wide=%s" % (ndim, dtype, every, wide), flush=True)
     B = len(srcs)
     tdt = torch.float64 if dtype == "f64" else torch.float32
     sim = dp.Simulation(n, lo, hi, 1.0, dt, sig, c2=c2, dtype=tdt, batch=B)

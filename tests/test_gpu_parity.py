@@ -380,3 +380,37 @@ def test_twostep_graph_replay_matches_eager():
         assert np.array_equal(a.U.cpu().numpy(), b.U.cpu().numpy()), rep
     a.close()
     b.close()
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_launch_timing_counts_and_bytes(dtype):
+    """The library's per-launch timing: one record per step-kernel launch,
+    the algorithmic byte model per launch (3 words per cell, 4 per layer
+    axis-cell), and a two-step pass (core + frame) that carries exactly the
+    bytes of two single steps; graph replays are not timed."""
+    w = synthetic.bump2d(200, 20, 0)
+    esize = 4 if dtype == "f32" else 8
+    cells = w.N[0] * w.N[1]
+    aux = sum((w.lo[a] + w.hi[a]) * (cells // w.N[a]) for a in range(2))
+    step_bytes = (3 * cells + 4 * aux) * esize
+    sim = dp.Simulation(w.n, w.lo, w.hi, w.h, w.dt, w.sigma, dtype=_dtype(dtype))
+    sim.set_state(torch.from_numpy(w.U0))
+    sim.set_variant(dp.VARIANT_CELL, 0)
+    sim.set_timing(True)
+    sim.step(6)
+    t = sim.get_timing()
+    assert set(t) == {"step"} and t["step"]["launches"] == 6
+    assert t["step"]["bytes"] == 6 * step_bytes and t["step"]["ms"] > 0
+    sim.set_variant(dp.VARIANT_TWOSTEP, 0)
+    sim.step(7)                                   # three pairs and one single step
+    t = sim.get_timing()
+    assert t["pair"]["launches"] == 3 and t["frame"]["launches"] == 3 and t["step"]["launches"] == 1
+    assert t["pair"]["bytes"] + t["frame"]["bytes"] == 3 * 2 * step_bytes
+    assert t["step"]["bytes"] == step_bytes
+    sim.step_graph(4)
+    sim.sync()
+    assert sim.get_timing() == {}
+    sim.set_timing(False)
+    sim.step(2)
+    assert sim.get_timing() == {}
+    sim.close()
