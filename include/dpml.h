@@ -95,6 +95,11 @@ extern "C" {
                                   2 words per cell per step; tile_rows = rows per
                                   wave, 0 = 32), the frame holding the layer in
                                   single steps; otherwise as CELL                     */
+#define DPML_VARIANT_THREESTEP 5 /* as TWOSTEP with three steps per pass over a core
+                                  one cell smaller (4 words per cell per three steps:
+                                  U^{n+1} is stored on the core's boundary ring only;
+                                  tile_rows = rows per wave, 0 = 32); a remaining
+                                  pair takes the two-step pass                        */
 
 typedef struct dpml_grid {
     int32_t ndim;    /* 2 or 3 */

@@ -25,7 +25,7 @@ LIB_PATH = os.path.join(_HERE, "libdpml.so")
 
 DPML_OK, DPML_EINVAL, DPML_ENOMEM, DPML_EHIP, DPML_ESTATE, DPML_ENONFINITE = 0, -1, -2, -3, -4, -5
 DPML_F32, DPML_F64 = 0, 1
-VARIANT_AUTO, VARIANT_CELL, VARIANT_MARCH, VARIANT_MARCH1, VARIANT_TWOSTEP = 0, 1, 2, 3, 4
+VARIANT_AUTO, VARIANT_CELL, VARIANT_MARCH, VARIANT_MARCH1, VARIANT_TWOSTEP, VARIANT_THREESTEP = 0, 1, 2, 3, 4, 5
 FIELD_U, FIELD_UPREV = 0, 1
 
 

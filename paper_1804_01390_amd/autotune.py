@@ -14,11 +14,12 @@ import json
 import os
 from typing import Dict, List, Optional, Sequence, Tuple
 
-from . import VARIANT_CELL, VARIANT_MARCH, VARIANT_MARCH1, VARIANT_TWOSTEP
+from . import VARIANT_CELL, VARIANT_MARCH, VARIANT_MARCH1, VARIANT_THREESTEP, VARIANT_TWOSTEP
 
 DEFAULT_CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "autotune_cache.json")
 
-CANDIDATES_2D: List[Tuple[int, int]] = ([(VARIANT_TWOSTEP, r) for r in (16, 32, 64)] + [(VARIANT_CELL, th) for th in (1, 2, 4, 8)]
+CANDIDATES_2D: List[Tuple[int, int]] = ([(VARIANT_THREESTEP, r) for r in (16, 32, 64)]
+                                        + [(VARIANT_TWOSTEP, r) for r in (16, 32, 64)] + [(VARIANT_CELL, th) for th in (1, 2, 4, 8)]
                                         + [(VARIANT_MARCH, r) for r in (4, 8, 16)]
                                         + [(VARIANT_MARCH1, r) for r in (4, 8, 16)])
 CANDIDATES_3D: List[Tuple[int, int]] = ([(VARIANT_CELL, th) for th in (2, 4, 8)]
@@ -45,7 +46,7 @@ def _time_candidate(sim, variant: int, tile_rows: int, steps: int) -> float:
     sim.set_variant(variant, tile_rows)
     blob, n = sim.get_state()
     blob = blob.clone()
-    sim.step(2)                                   # warm the code path (even: two-step pairs)
+    sim.step(6)                                   # warm the code path (whole multi-step passes)
     sim.sync()
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)

@@ -41,7 +41,8 @@ struct Layout {
     int64_t batch = 1;                  // independent problems sharing c^2 and sigma
     int64_t aux_elems[3] = {0, 0, 0};   // elements of one compact aux array (one problem)
     // byte offsets into the workspace
-    size_t off_u[4] = {0, 0, 0, 0};     // U^n, U^{n-1} and two spares (two-step variant)
+    int n_ubuf = 2;                     // U buffers: U^n, U^{n-1} (+ spares of the multi-step variants)
+    size_t off_u[5] = {0, 0, 0, 0, 0};
     size_t off_c2 = 0;
     size_t off_phi[3][2] = {{0, 0}, {0, 0}, {0, 0}};
     size_t off_psi[3][2] = {{0, 0}, {0, 0}, {0, 0}};
@@ -52,8 +53,13 @@ struct Layout {
 
 constexpr int kFlagBlocks = 1024;
 
+// U buffers of a single-grid handle: 2D grids carry three spares for the
+// two- and three-step variants (which write U^{n+1} .. U^{n+3} beside U^n and
+// U^{n-1}); 3D grids only U^n and U^{n-1}.
+int handle_ubufs(const dpml_grid_t *g) { return g && g->ndim == 2 ? 5 : 2; }
+
 // Validate the grid and compute the workspace layout.  Returns "" or an error.
-std::string make_layout(const dpml_grid_t *g, bool c2_field, Layout &L)
+std::string make_layout(const dpml_grid_t *g, bool c2_field, Layout &L, int n_ubuf)
 {
     if (!g) return "grid is NULL";
     if (g->ndim != 2 && g->ndim != 3) return "ndim must be 2 or 3";
@@ -82,7 +88,8 @@ std::string make_layout(const dpml_grid_t *g, bool c2_field, Layout &L)
     if (L.ncell * L.batch > ((int64_t)1 << 40)) return "grid too large";
     size_t off = 0;
     const size_t ubytes = align_up((size_t)(L.ncell * L.batch) * L.esize);
-    for (int k = 0; k < 4; ++k) { L.off_u[k] = off; off += ubytes; }
+    L.n_ubuf = n_ubuf;
+    for (int k = 0; k < n_ubuf; ++k) { L.off_u[k] = off; off += ubytes; }
     if (c2_field) { L.off_c2 = off; off += align_up((size_t)L.ncell * L.esize); }
     for (int a = 0; a < L.ndim; ++a) {
         if (L.M[a] == 0) continue;
@@ -116,9 +123,9 @@ struct dpml {
     bool state_set = false;
     int variant = DPML_VARIANT_AUTO;
     int tile_rows = 0;
-    TileRefVec frame;                // frame tiles of the two-step variant (host copy)
-    dpmlk::TileRef *d_frame = nullptr;
-    int64_t n_frame = 0;
+    // frame tiles of the two- and three-step variants (index: levels - 2)
+    dpmlk::TileRef *d_frame[2] = {nullptr, nullptr};
+    int64_t n_frame[2] = {-1, -1};   // -1: not built yet
     dpmlk::TileRef *d_adj_frame = nullptr;  // 2D adjoint: tiles outside the marching core
     int64_t n_adj_frame = -1;               // -1: not built yet
     dpmlk::Tile3 *d_slabs = nullptr;  // 3D marching variants: tiles of the y/z layer slabs
@@ -406,8 +413,8 @@ int launch_step(dpml *H, T *hist = nullptr, T *uout = nullptr)
     p.hist = hist;
     p.uout = uout;
     const unsigned B = (unsigned)L.batch;
-    int variant = (H->variant == DPML_VARIANT_AUTO || H->variant == DPML_VARIANT_TWOSTEP) ? DPML_VARIANT_CELL
-                                                                                        : H->variant;
+    int variant = (H->variant == DPML_VARIANT_AUTO || H->variant == DPML_VARIANT_TWOSTEP ||
+                   H->variant == DPML_VARIANT_THREESTEP) ? DPML_VARIANT_CELL : H->variant;
     if (L.ndim == 3 && variant != DPML_VARIANT_CELL)
         return launch_march3d<T>(H, p, variant == DPML_VARIANT_MARCH ? 4 : 2);
     const int slot = timed_begin(H, DPML_KERNEL_STEP, step_bytes(H, (double)L.ncell, aux_cells(L)));
@@ -489,23 +496,24 @@ int launch_epilogue(dpml *H)
     return DPML_OK;
 }
 
-// Columns per lane of the two-step core kernel.
-int twostep_vx(const Layout &L) { return L.dtype == DPML_F32 ? 4 : 2; }
+// Columns per lane of the multi-step core kernels.
+int multistep_vx(const Layout &L) { return L.dtype == DPML_F32 ? 4 : 2; }
 
-// Core rectangle of the two-step variant: cells whose one-cell halo is free
-// of damping terms, inside [lo+2, lo+n-1) per axis; along x it starts on a
-// multiple of the kernel's vector width and spans a multiple of it.  An axis
-// without a layer is core over its whole (periodic) extent.
-void core_rect(const Layout &L, int r[4])
+// Core rectangle of a multi-step pass over `levels` levels: cells whose
+// (levels-1)-cell halo is free of damping terms, inside [lo+levels,
+// lo+n+1-levels) per axis (the undamped cells are [lo+1, lo+n)); along x it
+// starts on a multiple of the kernel's vector width and spans a multiple of
+// it.  An axis without a layer is core over its whole (periodic) extent.
+void core_rect(const Layout &L, int levels, int r[4])
 {
-    const int vx = twostep_vx(L);
+    const int vx = multistep_vx(L);
     for (int a = 0; a < 2; ++a) {
         if (L.M[a] == 0) {
             r[2 * a] = 0;
             r[2 * a + 1] = (int)L.N[a];
             continue;
         }
-        int b0 = L.lo[a] + 2, b1 = (int)(L.lo[a] + L.n[a] - 1);
+        int b0 = L.lo[a] + levels, b1 = (int)(L.lo[a] + L.n[a] + 1 - levels);
         if (a == 0) {
             b0 = (b0 + vx - 1) / vx * vx;
             b1 = b1 > b0 ? b0 + (b1 - b0) / vx * vx : b0;
@@ -515,99 +523,119 @@ void core_rect(const Layout &L, int r[4])
     }
 }
 
-// Can this handle take two steps per launch right now?
-bool twostep_ok(const dpml *H)
+// Levels per pass this handle may take right now: 3 (VARIANT_THREESTEP), 2
+// (VARIANT_TWOSTEP, or THREESTEP for a last pair), or 1.
+int multistep_levels(const dpml *H, int64_t nsteps)
 {
     const Layout &L = H->L;
-    if (H->variant != DPML_VARIANT_TWOSTEP || L.ndim != 2) return false;
-    if (L.wall[0] || L.wall[1]) return false;
-    if (H->ns > 0 || (H->recording && (H->nr > 0 || H->plane_axis >= 0))) return false;
-    int r[4];
-    core_rect(L, r);
-    // the core kernel wraps halo rows once: each extent must hold its 2-cell halos
-    return r[1] - r[0] >= 1 && r[3] - r[2] >= 1 && L.N[0] >= 4 && L.N[1] >= 4;
+    if (L.ndim != 2 || L.wall[0] || L.wall[1]) return 1;
+    if (H->ns > 0 || (H->recording && (H->nr > 0 || H->plane_axis >= 0))) return 1;
+    int want = H->variant == DPML_VARIANT_THREESTEP ? 3 : (H->variant == DPML_VARIANT_TWOSTEP ? 2 : 1);
+    if (want > nsteps) want = (int)nsteps;
+    // the core kernels wrap halo rows once: each extent must hold its halos
+    if (L.N[0] < 8 || L.N[1] < 8) return 1;
+    for (; want >= 2; --want) {
+        int r[4];
+        core_rect(L, want, r);
+        if (r[1] - r[0] >= 1 && r[3] - r[2] >= 1) return want;
+    }
+    return 1;
 }
 
-int ensure_frame(dpml *H)
+int ensure_frame(dpml *H, int levels)
 {
-    if (H->d_frame) return DPML_OK;
+    const int q = levels - 2;
+    if (H->n_frame[q] >= 0) return DPML_OK;
     const Layout &L = H->L;
     int r[4];
-    core_rect(L, r);
+    core_rect(L, levels, r);
     const int tx = (int)((L.N[0] + 63) / 64), ty = (int)((L.N[1] + 3) / 4);
-    H->frame.clear();
+    std::vector<dpmlk::TileRef> t;
     for (int y = 0; y < ty; ++y)
         for (int x = 0; x < tx; ++x) {
             const int xa = x * 64, xb = std::min<int>(xa + 64, (int)L.N[0]);
             const int ya = y * 4, yb = std::min<int>(ya + 4, (int)L.N[1]);
             const bool inside = xa >= r[0] && xb <= r[1] && ya >= r[2] && yb <= r[3];
-            if (!inside) H->frame.push_back({0, x, y, 0});
+            if (!inside) t.push_back({0, x, y, 0});
         }
-    H->n_frame = (int64_t)H->frame.size();
-    if (H->n_frame == 0) return DPML_OK;
-    HIP_TRY(H, hipMalloc((void **)&H->d_frame, H->frame.size() * sizeof(dpmlk::TileRef)));
-    HIP_TRY(H, hipMemcpy(H->d_frame, H->frame.data(), H->frame.size() * sizeof(dpmlk::TileRef),
-                         hipMemcpyHostToDevice));
+    H->n_frame[q] = (int64_t)t.size();
+    if (t.empty()) return DPML_OK;
+    HIP_TRY(H, hipMalloc((void **)&H->d_frame[q], t.size() * sizeof(dpmlk::TileRef)));
+    HIP_TRY(H, hipMemcpy(H->d_frame[q], t.data(), t.size() * sizeof(dpmlk::TileRef), hipMemcpyHostToDevice));
     return DPML_OK;
 }
 
-// Two steps: the core and the frame's first step in one launch, the frame's
-// second step in another.
+// `levels` (2 or 3) steps: the core and the frame's first step in one
+// launch, each further frame step in a launch of its own.
 template <typename T>
-int launch_twostep(dpml *H)
+int launch_multistep(dpml *H, int levels)
 {
     const Layout &L = H->L;
     const unsigned B = (unsigned)L.batch;
-    void *bufs[4] = {H->at(L.off_u[0]), H->at(L.off_u[1]), H->at(L.off_u[2]), H->at(L.off_u[3])};
-    void *spare[2];
+    const int q = levels - 2;
+    // buffers: A = U^n, Bv = U^{n-1}, then U^{n+1} .. U^{n+levels} in the spares
+    T *A = (T *)H->u_now, *Bv = (T *)H->u_old;
+    T *nxt[3] = {nullptr, nullptr, nullptr};
     int k = 0;
-    for (int q = 0; q < 4; ++q)
-        if (bufs[q] != H->u_now && bufs[q] != H->u_old) spare[k++] = bufs[q];
-    T *A = (T *)H->u_now, *C = (T *)spare[0], *D = (T *)spare[1];
+    for (int i = 0; i < L.n_ubuf && k < levels; ++i) {
+        void *b = H->at(L.off_u[i]);
+        if (b != H->u_now && b != H->u_old) nxt[k++] = (T *)b;
+    }
+    if (k < levels) return H->fail(DPML_EINVAL, "not enough field buffers for a multi-step pass");
     int r[4];
-    core_rect(L, r);
+    core_rect(L, levels, r);
     constexpr int VX = sizeof(T) == 4 ? 4 : 2;
-    const int rows = H->tile_rows > 0 ? H->tile_rows : 32;
-    const int strips = (r[1] - r[0] + 62 * VX - 1) / (62 * VX);
+    const int HL = (levels + VX - 1) / VX;                      // halo lanes per strip side
+    const int rows = H->tile_rows > 0 ? H->tile_rows : (levels == 3 ? 32 : 16);
+    const int strips = (r[1] - r[0] + (64 - 2 * HL) * VX - 1) / ((64 - 2 * HL) * VX);
     const int n_waves = strips * ((r[3] - r[2] + rows - 1) / rows);
     const int core_blocks = round8((n_waves + 3) / 4);
-    const int frame_blocks = H->n_frame > 0 ? round8((int)H->n_frame) : 0;
-    // step n -> n+1 on the frame reads A (U^n), B (U^{n-1}) and writes C; the
-    // core reads A, B and writes C (U^{n+1}) and D (U^{n+2})
+    const int nf = (int)std::max<int64_t>(H->n_frame[q], 0);
+    const int frame_blocks = nf > 0 ? round8(nf) : 0;
+    const dpmlk::TileRef *ft = H->d_frame[q];
+    // the frame's first step reads A, Bv and writes nxt[0]; the core reads
+    // A, Bv and writes nxt[0] (all of it, or its ring), nxt[1] (, nxt[2])
     dpmlk::StepArgs<T> p = make_args<T>(H);
-    p.uout = C;
+    (void)Bv;
+    p.uout = nxt[0];
     p.tile_rows = rows;
-    for (int q = 0; q < 4; ++q) p.skip[q] = r[q];
+    for (int i = 0; i < 4; ++i) p.skip[i] = r[i];
     const dim3 grid((unsigned)(frame_blocks + core_blocks), B), block(256);
     const double core = (double)(r[1] - r[0]) * (double)(r[3] - r[2]), frame = (double)L.ncell - core;
-    int slot = timed_begin(H, DPML_KERNEL_PAIR, step_bytes(H, 2.0 * core + frame, aux_cells(L)));
-    if (p.c2)
-        hipLaunchKernelGGL((dpmlk::k_step2_march<T, VX, 4, true>), grid, block, 0, H->stream, p, D, r[0], r[1],
-                           r[2], r[3], strips, n_waves, (const dpmlk::TileRef *)H->d_frame, (int)H->n_frame,
-                           frame_blocks);
+    int slot = timed_begin(H, DPML_KERNEL_PAIR, step_bytes(H, levels * core + frame, aux_cells(L)));
+    if (levels == 2 && p.c2)
+        hipLaunchKernelGGL((dpmlk::k_step2_march<T, VX, 4, true>), grid, block, 0, H->stream, p, nxt[1], r[0], r[1],
+                           r[2], r[3], strips, n_waves, ft, nf, frame_blocks);
+    else if (levels == 2)
+        hipLaunchKernelGGL((dpmlk::k_step2_march<T, VX, 4, false>), grid, block, 0, H->stream, p, nxt[1], r[0], r[1],
+                           r[2], r[3], strips, n_waves, ft, nf, frame_blocks);
+    else if (p.c2)
+        hipLaunchKernelGGL((dpmlk::k_step3_march<T, VX, 2, true>), grid, block, 0, H->stream, p, nxt[1], nxt[2],
+                           r[0], r[1], r[2], r[3], strips, n_waves, ft, nf, frame_blocks);
     else
-        hipLaunchKernelGGL((dpmlk::k_step2_march<T, VX, 4, false>), grid, block, 0, H->stream, p, D, r[0], r[1],
-                           r[2], r[3], strips, n_waves, (const dpmlk::TileRef *)H->d_frame, (int)H->n_frame,
-                           frame_blocks);
+        hipLaunchKernelGGL((dpmlk::k_step3_march<T, VX, 2, false>), grid, block, 0, H->stream, p, nxt[1], nxt[2],
+                           r[0], r[1], r[2], r[3], strips, n_waves, ft, nf, frame_blocks);
     timed_end(H, slot);
-    if (H->n_frame > 0) {
-        // step n+1 -> n+2 on the frame: read C (U^{n+1}), A (U^n); write D; aux buffers swap
-        dim3 g2((unsigned)frame_blocks, B);
-        H->cur = 1 - H->cur;
-        dpmlk::StepArgs<T> p2 = make_args<T>(H);
-        H->cur = 1 - H->cur;
-        p2.u = C;
-        p2.uo = A;
-        p2.uout = D;
-        for (int q = 0; q < 4; ++q) p2.skip[q] = r[q];
+    // further frame steps: level j+1 from nxt[j] (U^{n+j+1}) and the level
+    // before it, aux buffers alternating
+    for (int j = 1; j < levels && nf > 0; ++j) {
+        const dim3 g2((unsigned)frame_blocks, B);
+        if (j % 2 == 1) H->cur = 1 - H->cur;
+        dpmlk::StepArgs<T> pj = make_args<T>(H);
+        if (j % 2 == 1) H->cur = 1 - H->cur;
+        pj.u = nxt[j - 1];
+        pj.uo = j == 1 ? A : nxt[j - 2];
+        pj.uout = nxt[j];
+        for (int i = 0; i < 4; ++i) pj.skip[i] = r[i];
         slot = timed_begin(H, DPML_KERNEL_FRAME, step_bytes(H, frame, aux_cells(L)));
-        hipLaunchKernelGGL((dpmlk::k_step_frame<T>), g2, block, 0, H->stream, p2, H->d_frame, (int)H->n_frame);
+        hipLaunchKernelGGL((dpmlk::k_step_frame<T>), g2, block, 0, H->stream, pj, ft, nf);
         timed_end(H, slot);
     }
     HIP_TRY(H, hipGetLastError());
-    H->u_now = D;
-    H->u_old = C;
-    H->n += 2;      // H->cur flips twice
+    H->u_now = nxt[levels - 1];
+    H->u_old = nxt[levels - 2];
+    if (levels % 2) H->cur = 1 - H->cur;
+    H->n += levels;
     return DPML_OK;
 }
 
@@ -615,13 +643,14 @@ template <typename T>
 int step_impl(dpml *H, int64_t nsteps)
 {
     int64_t k = 0;
-    if (nsteps >= 2 && twostep_ok(H)) {
-        int rc = ensure_frame(H);
+    for (;;) {
+        const int lv = multistep_levels(H, nsteps - k);
+        if (lv < 2) break;
+        int rc = ensure_frame(H, lv);
         if (rc) return rc;
-        for (; k + 2 <= nsteps; k += 2) {
-            rc = launch_twostep<T>(H);
-            if (rc) return rc;
-        }
+        rc = launch_multistep<T>(H, lv);
+        if (rc) return rc;
+        k += lv;
     }
     for (; k < nsteps; ++k) {
         int rc = launch_step<T>(H);
@@ -730,7 +759,7 @@ extern "C" {
 size_t dpml_workspace_bytes(const dpml_grid_t *g, int32_t c2_is_field)
 {
     Layout L;
-    if (!make_layout(g, c2_is_field != 0, L).empty()) return 0;
+    if (!make_layout(g, c2_is_field != 0, L, handle_ubufs(g)).empty()) return 0;
     return L.total;
 }
 
@@ -742,7 +771,7 @@ int dpml_create(const dpml_grid_t *g, double h, double dt, const double *c2, int
     *out = nullptr;
     Layout L;
     const bool field = c2_len != 1;
-    std::string e = make_layout(g, field, L);
+    std::string e = make_layout(g, field, L, handle_ubufs(g));
     if (!e.empty()) { g_create_error = e; return DPML_EINVAL; }
     if (!(h > 0) || !(dt > 0) || !std::isfinite(h) || !std::isfinite(dt)) {
         g_create_error = "h and dt must be positive and finite"; return DPML_EINVAL;
@@ -892,7 +921,7 @@ int dpml_record_plane(dpml_t *H, int32_t axis, int64_t index, void *planes, int6
 int dpml_set_variant(dpml_t *H, int32_t variant, int32_t tile_rows)
 {
     if (!H) return DPML_EINVAL;
-    if (variant < DPML_VARIANT_AUTO || variant > DPML_VARIANT_TWOSTEP || tile_rows < 0 || tile_rows > 4096)
+    if (variant < DPML_VARIANT_AUTO || variant > DPML_VARIANT_THREESTEP || tile_rows < 0 || tile_rows > 4096)
         return H->fail(DPML_EINVAL, "bad variant");
     H->variant = variant;
     H->tile_rows = tile_rows;
@@ -1055,7 +1084,8 @@ void dpml_destroy(dpml_t *H)
     if (H->d_src_cells) (void)hipFree(H->d_src_cells);
     if (H->d_src_order) (void)hipFree(H->d_src_order);
     if (H->d_rec_cells) (void)hipFree(H->d_rec_cells);
-    if (H->d_frame) (void)hipFree(H->d_frame);
+    for (int k = 0; k < 2; ++k)
+        if (H->d_frame[k]) (void)hipFree(H->d_frame[k]);
     if (H->d_slabs) (void)hipFree(H->d_slabs);
     if (H->d_adj_frame) (void)hipFree(H->d_adj_frame);
     if (H->d_rec_sorted) (void)hipFree(H->d_rec_sorted);
@@ -1425,7 +1455,7 @@ std::string multi_layout(int64_t count, const dpml_grid_t *grids, MultiLayout &M
         if (grids[p].dtype != dtype) return "all problems must share one dtype";
         if (grids[p].batch > 1) return "multi-problem grids take no batch";
         if (grids[p].walls[0] || grids[p].walls[1]) return "multi-problem grids are periodic";
-        std::string e = make_layout(&grids[p], false, M.L[p]);
+        std::string e = make_layout(&grids[p], false, M.L[p], 2);
         if (!e.empty()) return "problem " + std::to_string(p) + ": " + e;
         M.base[p] = off;
         off += align_up(M.L[p].total);
@@ -1849,11 +1879,12 @@ int step_graph_impl(dpml *H, int64_t nsteps)
         view.stream = H->cap;
         view.err.clear();
         view.timing = false;
-        if (twostep_ok(H)) {                 // the frame table must exist before capture
-            int rcf = ensure_frame(H);
+        for (int lv = 2; lv <= 3; ++lv) {      // the frame tables must exist before capture
+            if (multistep_levels(H, nsteps) < 2) break;
+            int rcf = ensure_frame(H, lv);
             if (rcf) return rcf;
-            view.d_frame = H->d_frame;
-            view.n_frame = H->n_frame;
+            view.d_frame[lv - 2] = H->d_frame[lv - 2];
+            view.n_frame[lv - 2] = H->n_frame[lv - 2];
         }
         if (H->L.ndim == 3 && (H->L.M[1] > 0 || H->L.M[2] > 0)) {   // likewise the slab table
             int rcs = ensure_slabs(H);
@@ -1867,7 +1898,7 @@ int step_graph_impl(dpml *H, int64_t nsteps)
         hipError_t e = hipStreamEndCapture(H->cap, &g);
         view.cap = nullptr; view.graph = nullptr; view.exec = nullptr;   // not owned by the view
         view.d_src_cells = view.d_src_order = view.d_rec_cells = view.d_rec_sorted = view.d_rec_order = nullptr;
-        view.d_frame = nullptr;
+        view.d_frame[0] = view.d_frame[1] = nullptr;
         view.d_slabs = nullptr;
         H->graph_end_unow = view.u_now;
         H->graph_end_uold = view.u_old;

@@ -678,6 +678,175 @@ __global__ void __launch_bounds__(256) k_step2_march(StepArgs<T> p, T *__restric
         c.template march<G, 1>(ya, yb - ya);
 }
 
+// ---------------------------------------------------------------------------
+// Three steps per launch, 2D periodic grids: the same marching scheme one
+// level deeper.  For march index k a wave reads U^n(k+1) and U^{n-1}(k) and
+// computes U^{n+1}(k), U^{n+2}(k-1) and U^{n+3}(k-2) from rows held in
+// registers.  It writes U^{n+2} and U^{n+3} of its tile, and U^{n+1} only on
+// the core's one-cell boundary ring (the frame's second step needs it
+// there): 4 words per core cell per three steps instead of 6 for two
+// two-step passes.  Each side of a strip carries HL = ceil(3/VX) halo lanes.
+// Buffers: reads U^n, U^{n-1}; writes U^{n+1} (ring), U^{n+2}, U^{n+3} into
+// three further buffers.  The launch also runs the frame's first step; the
+// frame's second and third steps are separate launches.
+// ---------------------------------------------------------------------------
+template <typename T, int VX, bool C2F>
+struct March3Ctx : March2Ctx<T, VX, C2F> {
+    using Base = March2Ctx<T, VX, C2F>;
+    using R = Row<T, VX>;
+    T *o3;                         // U^{n+3}
+    bool ring_lane;                // this lane's cells touch the core's first or last column
+    int cy0, cy1;                  // core rows
+
+    // rolling state at march index k: U^n at k-1, k; U^{n+1} at k-2, k-1;
+    // U^{n+2} at k-3, k-2; c^2 at k-2, k-1
+    struct State {
+        R n0, n1, a0, a1, b0, b1, c0, c1;
+    };
+
+    template <int DIR>
+    __device__ __forceinline__ void put1(int base, int k, int L, const R &v) const
+    {
+        // U^{n+1} on the ring only: the core's first/last row, or its first/last column
+        const int y = base + DIR * k;
+        if (k >= 0 && k < L && (ring_lane || y == cy0 || y == cy1 - 1)) this->store(this->o1, y, v);
+    }
+
+    // one march index k with every level guarded (prologue and tail)
+    template <int DIR>
+    __device__ __forceinline__ void one(State &s, int base, int k, int L) const
+    {
+        const R nn = this->load(this->u, this->wrapy(base + DIR * (k + 1)));
+        const R pm = this->load(this->up, this->wrapy(base + DIR * k));
+        R cn{};
+        if (C2F) cn = this->load(this->c2, this->wrapy(base + DIR * k));
+        const R v1 = this->template lev<DIR>(s.n0, s.n1, nn, pm, cn);           // U^{n+1}(k)
+        put1<DIR>(base, k, L, v1);
+        R v2{};
+        if (k - 1 >= -1) {
+            v2 = this->template lev<DIR>(s.a0, s.a1, v1, s.n0, s.c1);           // U^{n+2}(k-1)
+            if (k - 1 >= 0 && k - 1 < L) this->store(this->o2, base + DIR * (k - 1), v2);
+        }
+        if (k - 2 >= 0 && k - 2 < L)
+            this->store(o3, base + DIR * (k - 2), this->template lev<DIR>(s.b0, s.b1, v2, s.a0, s.c0));
+        s.n0 = s.n1;
+        s.n1 = nn;
+        s.a0 = s.a1;
+        s.a1 = v1;
+        s.b0 = s.b1;
+        s.b1 = v2;
+        s.c0 = s.c1;
+        s.c1 = cn;
+    }
+
+    // G march indices k .. k+G-1 in the steady state (every level inside the
+    // tile's range), all loads of the group issued first
+    template <int G, int DIR>
+    __device__ __forceinline__ void group(State &s, int base, int k, int L) const
+    {
+        R wn[G + 2], pm[G], v1[G + 2], v2[G + 2], cw[G + 2];
+        wn[0] = s.n0;
+        wn[1] = s.n1;
+        v1[0] = s.a0;
+        v1[1] = s.a1;
+        v2[0] = s.b0;
+        v2[1] = s.b1;
+        cw[0] = s.c0;
+        cw[1] = s.c1;
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+            wn[2 + g] = this->load(this->u, this->wrapy(base + DIR * (k + 1 + g)));
+            pm[g] = this->load(this->up, this->wrapy(base + DIR * (k + g)));
+            if (C2F) cw[2 + g] = this->load(this->c2, this->wrapy(base + DIR * (k + g)));
+        }
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+            v1[2 + g] = this->template lev<DIR>(wn[g], wn[g + 1], wn[g + 2], pm[g], cw[2 + g]);
+            put1<DIR>(base, k + g, L, v1[2 + g]);
+            v2[2 + g] = this->template lev<DIR>(v1[g], v1[g + 1], v1[g + 2], wn[g], cw[g + 1]);
+            this->store(this->o2, base + DIR * (k - 1 + g), v2[2 + g]);
+            this->store(o3, base + DIR * (k - 2 + g), this->template lev<DIR>(v2[g], v2[g + 1], v2[g + 2], v1[g], cw[g]));
+        }
+        s.n0 = wn[G];
+        s.n1 = wn[G + 1];
+        s.a0 = v1[G];
+        s.a1 = v1[G + 1];
+        s.b0 = v2[G];
+        s.b1 = v2[G + 1];
+        s.c0 = cw[G];
+        s.c1 = cw[G + 1];
+    }
+
+    template <int G, int DIR>
+    __device__ __forceinline__ void march(int base, int L) const
+    {
+        State s;
+        s.n0 = this->load(this->u, this->wrapy(base - 3 * DIR));
+        s.n1 = this->load(this->u, this->wrapy(base - 2 * DIR));
+        s.a0 = s.a1 = s.b0 = s.b1 = s.c0 = s.c1 = R{};
+        // march indices -2 .. 1: the levels fill up
+        int k = -2;
+        for (; k <= 1 && k <= L + 1; ++k) one<DIR>(s, base, k, L);
+        // steady state: U^{n+1}(k) .. with k-2 >= 0 and k+G-1 <= L-1 (no guards needed)
+        for (; k + G - 1 <= L - 1; k += G) group<G, DIR>(s, base, k, L);
+        for (; k <= L + 1; ++k) one<DIR>(s, base, k, L);
+    }
+};
+
+template <typename T, int VX, int G, bool C2F>
+__global__ void __launch_bounds__(256) k_step3_march(StepArgs<T> p, T *__restrict__ u_next2, T *__restrict__ u_next3,
+                                                     int cx0, int cx1, int cy0, int cy1, int strips, int n_waves,
+                                                     const TileRef *__restrict__ frame, int n_frame,
+                                                     int frame_blocks)
+{
+    if ((int)blockIdx.x < frame_blocks) {          // the frame's first step
+        const int t = (int)blockIdx.x;
+        if (t >= n_frame) return;
+        select_member(p, (int)blockIdx.y);
+        const int x = frame[t].tx * 64 + (int)(threadIdx.x % 64);
+        const int y = frame[t].ty * 4 + (int)(threadIdx.x / 64);
+        if (x >= p.skip[0] && x < p.skip[1] && y >= p.skip[2] && y < p.skip[3]) return;
+        cell2d_tile<T, 4>(p, frame[t].tx, frame[t].ty);
+        return;
+    }
+    constexpr int HL = (3 + VX - 1) / VX;                    // halo lanes per side
+    const int cb = (int)blockIdx.x - frame_blocks;           // frame_blocks is a multiple of 8
+    const int w = __builtin_amdgcn_readfirstlane(xcd_tile(cb, (int)gridDim.x - frame_blocks) * 4 +
+                                                 (int)(threadIdx.x >> 6));
+    if (w >= n_waves) return;                                // whole waves; no barriers below
+    const int lane = (int)(threadIdx.x & 63);
+    const int strip = w % strips, ty = w / strips;
+    const int64_t boff = (int64_t)blockIdx.y * p.bstride;
+    March3Ctx<T, VX, C2F> c;
+    c.u = p.u + boff;
+    c.up = p.uo + boff;
+    c.c2 = C2F ? p.c2 : nullptr;
+    c.o1 = p.uout + boff;
+    c.o2 = u_next2 + boff;
+    c.o3 = u_next3 + boff;
+    c.inv_h2 = p.inv_h2;
+    c.dt2 = p.dt2;
+    c.c2c = p.c2_const;
+    c.nx = p.nx;
+    c.ny = p.ny;
+    c.cx1 = cx1;
+    c.cy0 = cy0;
+    c.cy1 = cy1;
+    c.xs = cx0 + (strip * (64 - 2 * HL) + lane - HL) * VX;
+    c.need = c.xs < cx1 + HL * VX;                           // lanes further right feed nobody
+    c.xw = c.xs % c.nx;
+    if (c.xw < 0) c.xw += c.nx;
+    c.vec = c.xw % VX == 0 && c.xw + VX <= c.nx;
+    c.out = lane >= HL && lane < 64 - HL && c.xs < cx1;
+    c.ring_lane = c.xs == cx0 || c.xs + VX >= cx1;
+    const int rows = p.tile_rows;
+    const int ya = cy0 + ty * rows, yb = min(ya + rows, cy1);
+    if (ty & 1)
+        c.template march<G, -1>(yb - 1, yb - ya);
+    else
+        c.template march<G, 1>(ya, yb - ya);
+}
+
 // One ordinary step over a list of 64 x 4 cell tiles (the frame around the
 // core), leaving the core cells (p.skip) alone.
 template <typename T>

@@ -301,14 +301,17 @@ def test_graph_replay_matches_eager(dtype):
 
 
 
+@pytest.mark.parametrize("multi", ["two", "three"])
 @pytest.mark.parametrize("rows", [0, 5])
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
 @pytest.mark.parametrize("case", ["bump", "ragged", "onesided", "c2", "batch", "nolayer"])
-def test_twostep_matches_single_steps_and_oracle(dtype, case, rows):
-    """Two steps per pass over the layer-free core (temporal blocking) plus
-    single steps on the frame: bit-identical to single steps, and the oracle
-    agrees; odd step counts end with one single step.  rows = 5 makes the
-    kernel's tiles end in a one-row remainder."""
+def test_twostep_matches_single_steps_and_oracle(dtype, case, rows, multi):
+    """Two (three) steps per pass over the layer-free core (temporal blocking)
+    plus single steps on the frame: bit-identical to single steps, and the
+    oracle agrees; step counts that are not a multiple end with a two-step
+    pass and/or a single step.  rows = 5 makes the kernel's tiles end in a
+    remainder of rows."""
+    MULTI = dp.VARIANT_TWOSTEP if multi == "two" else dp.VARIANT_THREESTEP
     rng = np.random.default_rng(17)
     c2 = None
     batch = 1
@@ -339,18 +342,18 @@ def test_twostep_matches_single_steps_and_oracle(dtype, case, rows):
         U0 = np.stack([synthetic.gaussian_sum(n, lo, hi, 5, 2.0, 6.0, rng) for _ in range(batch)])
     dt = 0.5 if c2 is None else 0.5 / math.sqrt(float(np.max(c2)))
     steps = 121
-    print("case twostep %s %s rows %d" % (case, dtype, rows), flush=True)
+    print("case %s-step %s %s rows %d" % (multi, case, dtype, rows), flush=True)
     outs = []
-    for variant in (dp.VARIANT_TWOSTEP, dp.VARIANT_CELL):
+    for variant in (MULTI, dp.VARIANT_CELL):
         sim = dp.Simulation(n, lo, hi, 1.0, dt, sig, c2=1.0 if c2 is None else c2, dtype=_dtype(dtype), batch=batch)
-        sim.set_variant(variant, rows if variant == dp.VARIANT_TWOSTEP else 0)
+        sim.set_variant(variant, rows if variant == MULTI else 0)
         sim.set_state(torch.from_numpy(U0))
         sim.step(steps)
         sim.sync()
         outs.append((sim.U.cpu().numpy().copy(), sim.field(dp.FIELD_UPREV).cpu().numpy().copy(),
                      [sim.field(dp.FIELD_PHI(a)).cpu().numpy().copy() for a in range(2) if lo[a] + hi[a] > 0],
                      [sim.field(dp.FIELD_PSI(a)).cpu().numpy().copy() for a in range(2) if lo[a] + hi[a] > 0]))
-        if variant == dp.VARIANT_TWOSTEP and batch == 1:
+        if variant == MULTI and batch == 1:
             gs = gpu_state(sim)
         sim.close()
     (a0, a1, a2, a3), (b0, b1, b2, b3) = outs
@@ -364,11 +367,12 @@ def test_twostep_matches_single_steps_and_oracle(dtype, case, rows):
         _assert_errs(compare_states(gs, ref, n, lo, hi, peaks if dtype == "f32" else None), dtype)
 
 
-def test_twostep_graph_replay_matches_eager():
+@pytest.mark.parametrize("variant", [dp.VARIANT_TWOSTEP, dp.VARIANT_THREESTEP])
+def test_twostep_graph_replay_matches_eager(variant):
     w = synthetic.bump2d(200, 20, 0)
     a = dp.Simulation(w.n, w.lo, w.hi, w.h, w.dt, w.sigma, dtype=torch.float32)
     b = dp.Simulation(w.n, w.lo, w.hi, w.h, w.dt, w.sigma, dtype=torch.float32)
-    a.set_variant(dp.VARIANT_TWOSTEP, 0)
+    a.set_variant(variant, 0)
     a.set_state(torch.from_numpy(w.U0))
     b.set_state(torch.from_numpy(w.U0))
     for rep, k in enumerate([10, 10, 7, 7, 10]):
@@ -407,6 +411,11 @@ def test_launch_timing_counts_and_bytes(dtype):
     assert t["pair"]["launches"] == 3 and t["frame"]["launches"] == 3 and t["step"]["launches"] == 1
     assert t["pair"]["bytes"] + t["frame"]["bytes"] == 3 * 2 * step_bytes
     assert t["step"]["bytes"] == step_bytes
+    sim.set_variant(dp.VARIANT_THREESTEP, 0)
+    sim.step(8)                                   # two triples and one pair
+    t = sim.get_timing()
+    assert t["pair"]["launches"] == 3 and t["frame"]["launches"] == 2 * 2 + 1 and "step" not in t
+    assert t["pair"]["bytes"] + t["frame"]["bytes"] == 8 * step_bytes
     sim.step_graph(4)
     sim.sync()
     assert sim.get_timing() == {}
