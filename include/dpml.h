@@ -92,14 +92,16 @@ extern "C" {
                                   two steps per pass over the layer-free core
                                   (temporal blocking: each wave marches down a
                                   strip keeping U^n and U^{n+1} rows in registers,
-                                  2 words per cell per step; tile_rows = rows per
-                                  wave, 0 = 32), the frame holding the layer in
-                                  single steps; otherwise as CELL                     */
+                                  2 words per cell per step; tile_rows: rows per
+                                  wave in bits 0-11 (0 = 8), rows whose loads are
+                                  issued together in bits 12-15 (1, 2 or 4; 0 = 2)),
+                                  the frame holding the layer in single steps;
+                                  otherwise as CELL                                   */
 #define DPML_VARIANT_THREESTEP 5 /* as TWOSTEP with three steps per pass over a core
                                   one cell smaller (4 words per cell per three steps:
                                   U^{n+1} is stored on the core's boundary ring only;
-                                  tile_rows = rows per wave, 0 = 32); a remaining
-                                  pair takes the two-step pass                        */
+                                  tile_rows as for TWOSTEP); a remaining pair takes
+                                  the two-step pass                                   */
 
 typedef struct dpml_grid {
     int32_t ndim;    /* 2 or 3 */
@@ -181,9 +183,11 @@ int dpml_record(dpml_t *h, int64_t nr, const int64_t *cells, void *traces,
 int dpml_record_plane(dpml_t *h, int32_t axis, int64_t index, void *planes,
                       int64_t nt);
 
-/* Choose the kernel variant (DPML_VARIANT_*) and, for the marching variant,
- * the tile height in rows (0 = default).  Results are identical up to
- * rounding order between variants. */
+/* Choose the kernel variant (DPML_VARIANT_*) and its launch shape
+ * tile_rows (meaning per variant above; 0 = default).  All variants
+ * evaluate the scheme in the same operation order, so results do not
+ * depend on the choice.  DPML_EINVAL for an unknown variant or tile_rows
+ * outside [0, 65535]. */
 int dpml_set_variant(dpml_t *h, int32_t variant, int32_t tile_rows);
 
 /* Enqueue nsteps fused steps (U, Phi, Psi, sources, receivers).  Returns

@@ -18,8 +18,9 @@ from . import VARIANT_CELL, VARIANT_MARCH, VARIANT_MARCH1, VARIANT_THREESTEP, VA
 
 DEFAULT_CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "autotune_cache.json")
 
-CANDIDATES_2D: List[Tuple[int, int]] = ([(VARIANT_THREESTEP, r) for r in (16, 32, 64)]
-                                        + [(VARIANT_TWOSTEP, r) for r in (16, 32, 64)] + [(VARIANT_CELL, th) for th in (1, 2, 4, 8)]
+# multi-step variants: rows per wave in the low 12 bits, load group size above
+CANDIDATES_2D: List[Tuple[int, int]] = ([(VARIANT_THREESTEP, (g << 12) | r) for g in (2, 4) for r in (4, 6, 8, 12, 16)]
+                                        + [(VARIANT_TWOSTEP, (g << 12) | r) for g in (2, 4) for r in (8, 16)] + [(VARIANT_CELL, th) for th in (1, 2, 4, 8)]
                                         + [(VARIANT_MARCH, r) for r in (4, 8, 16)]
                                         + [(VARIANT_MARCH1, r) for r in (4, 8, 16)])
 CANDIDATES_3D: List[Tuple[int, int]] = ([(VARIANT_CELL, th) for th in (2, 4, 8)]

@@ -123,9 +123,13 @@ struct dpml {
     bool state_set = false;
     int variant = DPML_VARIANT_AUTO;
     int tile_rows = 0;
-    // frame tiles of the two- and three-step variants (index: levels - 2)
-    dpmlk::TileRef *d_frame[2] = {nullptr, nullptr};
-    int64_t n_frame[2] = {-1, -1};   // -1: not built yet
+    // frame tiles of the two- and three-step variants: [levels - 2][s] covers
+    // everything outside the core shrunk by s cells (-1: not built yet)
+    dpmlk::TileRef *d_frame[2][3] = {{nullptr, nullptr, nullptr}, {nullptr, nullptr, nullptr}};
+    int64_t n_frame[2][3] = {{-1, -1, -1}, {-1, -1, -1}};
+    // the frame's steps run on a second stream beside the core kernel
+    hipStream_t side = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     dpmlk::TileRef *d_adj_frame = nullptr;  // 2D adjoint: tiles outside the marching core
     int64_t n_adj_frame = -1;               // -1: not built yet
     dpmlk::Tile3 *d_slabs = nullptr;  // 3D marching variants: tiles of the y/z layer slabs
@@ -225,21 +229,23 @@ hipEvent_t take_event(dpml *H)
     return H->events[H->events_used++];
 }
 
-// Record the start of a timed launch of class `kind`; returns its slot or -1.
-int timed_begin(dpml *H, int kind, double bytes)
+// Record the start of a timed launch of class `kind` on stream s (default:
+// the handle's); returns its slot or -1.
+int timed_begin(dpml *H, int kind, double bytes, hipStream_t s = nullptr)
 {
     if (!H->timing || H->timed.size() >= kMaxTimed) return -1;
+    if (!s) s = H->stream;
     hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
     if (hipStreamIsCapturing(H->stream, &st) != hipSuccess || st != hipStreamCaptureStatusNone) return -1;
     dpml::Timed t{kind, take_event(H), take_event(H), bytes};
-    if (!t.e0 || !t.e1 || hipEventRecord(t.e0, H->stream) != hipSuccess) return -1;
+    if (!t.e0 || !t.e1 || hipEventRecord(t.e0, s) != hipSuccess) return -1;
     H->timed.push_back(t);
     return (int)H->timed.size() - 1;
 }
 
-void timed_end(dpml *H, int slot)
+void timed_end(dpml *H, int slot, hipStream_t s = nullptr)
 {
-    if (slot >= 0) (void)hipEventRecord(H->timed[(size_t)slot].e1, H->stream);
+    if (slot >= 0) (void)hipEventRecord(H->timed[(size_t)slot].e1, s ? s : H->stream);
 }
 
 template <typename T>
@@ -333,9 +339,22 @@ int ensure_slabs(dpml *H)
     return DPML_OK;
 }
 
+// The second stream (and its fork/join events) on which the layer parts of a
+// split step run beside the main kernel.
+int ensure_side(dpml *H)
+{
+    if (!H->side) HIP_TRY(H, hipStreamCreateWithFlags(&H->side, hipStreamNonBlocking));
+    if (!H->ev_fork) HIP_TRY(H, hipEventCreateWithFlags(&H->ev_fork, hipEventDisableTiming));
+    if (!H->ev_join) HIP_TRY(H, hipEventCreateWithFlags(&H->ev_join, hipEventDisableTiming));
+    return DPML_OK;
+}
+
 // 3D marching launch: the strips of the box [lo+1, lo+n) in y and z that no
 // x damping term reaches, without any layer code; the other strips with the
-// x-layer terms; the y/z layer slabs one thread per cell.
+// x-layer terms; the y/z layer slabs one thread per cell.  The layer parts
+// (slabs and edge strips) run on the side stream while the layer-free
+// strips run on the handle's stream; they write disjoint cells and the
+// step ends with the handle's stream waiting for the side stream.
 template <typename T>
 int launch_march3d(dpml *H, dpmlk::StepArgs<T> p, int ry)
 {
@@ -348,6 +367,14 @@ int launch_march3d(dpml *H, dpmlk::StepArgs<T> p, int ry)
         int rc = ensure_slabs(H);
         if (rc) return rc;
     }
+    const bool fork = split || L.M[0] > 0;
+    if (fork) {
+        int rc = ensure_side(H);
+        if (rc) return rc;
+        HIP_TRY(H, hipEventRecord(H->ev_fork, H->stream));
+        HIP_TRY(H, hipStreamWaitEvent(H->side, H->ev_fork, 0));
+    }
+    hipStream_t ls = fork ? H->side : H->stream;      // stream of the layer parts
     // strips of 64 columns [64 t, 64 t + 64) free of x damping terms: inside [lo+1, lo+n)
     const int nstrips = (int)((L.N[0] + 63) / 64);
     int s0 = 0, s1 = nstrips;
@@ -365,11 +392,11 @@ int launch_march3d(dpml *H, dpmlk::StepArgs<T> p, int ry)
     const dim3 block(256);
     if (split && H->n_slabs > 0) {
         const int slot = timed_begin(H, DPML_KERNEL_FRAME,
-                                     step_bytes(H, (double)L.ncell - box, aux_cells(L) - box_aux));
+                                     step_bytes(H, (double)L.ncell - box, aux_cells(L) - box_aux), ls);
         const dim3 g2((unsigned)round8((int)H->n_slabs), B);
-        hipLaunchKernelGGL((dpmlk::k_step_slabs3d<T>), g2, block, 0, H->stream, p, H->d_slabs, (int)H->n_slabs,
+        hipLaunchKernelGGL((dpmlk::k_step_slabs3d<T>), g2, block, 0, ls, p, H->d_slabs, (int)H->n_slabs,
                            b[0], b[1], b[2], b[3]);
-        timed_end(H, slot);
+        timed_end(H, slot, ls);
     }
     // launch the strips [t0, t1) with or without the x-layer code; the two
     // edge strips alone are few tiles, so they march shorter chunks
@@ -381,17 +408,18 @@ int launch_march3d(dpml *H, dpmlk::StepArgs<T> p, int ry)
         if (tz <= 0) return;
         q.tiles_x = t1 - t0;
         q.n_tiles = q.tiles_x * q.tiles_y * tz;
-        const int slot = timed_begin(H, kind, bytes);
+        hipStream_t st = layer ? ls : H->stream;
+        const int slot = timed_begin(H, kind, bytes, st);
         const dim3 grid((unsigned)round8(q.n_tiles), B);
         if (ry == 4 && layer)
-            hipLaunchKernelGGL((dpmlk::k_step_zmarch3d<T, 4, 1>), grid, block, 0, H->stream, q, t0, b[0], b[1], b[2], b[3]);
+            hipLaunchKernelGGL((dpmlk::k_step_zmarch3d<T, 4, 1>), grid, block, 0, st, q, t0, b[0], b[1], b[2], b[3]);
         else if (ry == 4)
-            hipLaunchKernelGGL((dpmlk::k_step_zmarch3d<T, 4, 0>), grid, block, 0, H->stream, q, t0, b[0], b[1], b[2], b[3]);
+            hipLaunchKernelGGL((dpmlk::k_step_zmarch3d<T, 4, 0>), grid, block, 0, st, q, t0, b[0], b[1], b[2], b[3]);
         else if (layer)
-            hipLaunchKernelGGL((dpmlk::k_step_zmarch3d<T, 2, 1>), grid, block, 0, H->stream, q, t0, b[0], b[1], b[2], b[3]);
+            hipLaunchKernelGGL((dpmlk::k_step_zmarch3d<T, 2, 1>), grid, block, 0, st, q, t0, b[0], b[1], b[2], b[3]);
         else
-            hipLaunchKernelGGL((dpmlk::k_step_zmarch3d<T, 2, 0>), grid, block, 0, H->stream, q, t0, b[0], b[1], b[2], b[3]);
-        timed_end(H, slot);
+            hipLaunchKernelGGL((dpmlk::k_step_zmarch3d<T, 2, 0>), grid, block, 0, st, q, t0, b[0], b[1], b[2], b[3]);
+        timed_end(H, slot, st);
     };
     const bool whole = !split && s0 == 0 && s1 == nstrips;
     strips(s0, s1, false, whole ? DPML_KERNEL_STEP : DPML_KERNEL_CORE, step_bytes(H, inner_cols * rows, 0.0));
@@ -401,6 +429,10 @@ int launch_march3d(dpml *H, dpmlk::StepArgs<T> p, int ry)
     const double left = 64.0 * s0 * rows;
     strips(0, s0, true, DPML_KERNEL_FRAME, edge_cells > 0 ? edge_bytes * left / edge_cells : 0.0);
     strips(s1, nstrips, true, DPML_KERNEL_FRAME, edge_cells > 0 ? edge_bytes * (edge_cells - left) / edge_cells : 0.0);
+    if (fork) {
+        HIP_TRY(H, hipEventRecord(H->ev_join, H->side));
+        HIP_TRY(H, hipStreamWaitEvent(H->stream, H->ev_join, 0));
+    }
     HIP_TRY(H, hipGetLastError());
     return DPML_OK;
 }
@@ -542,13 +574,17 @@ int multistep_levels(const dpml *H, int64_t nsteps)
     return 1;
 }
 
-int ensure_frame(dpml *H, int levels)
+int ensure_frame(dpml *H, int levels, int shrink)
 {
     const int q = levels - 2;
-    if (H->n_frame[q] >= 0) return DPML_OK;
+    if (H->n_frame[q][shrink] >= 0) return DPML_OK;
     const Layout &L = H->L;
     int r[4];
     core_rect(L, levels, r);
+    r[0] += shrink;
+    r[1] -= shrink;
+    r[2] += shrink;
+    r[3] -= shrink;
     const int tx = (int)((L.N[0] + 63) / 64), ty = (int)((L.N[1] + 3) / 4);
     std::vector<dpmlk::TileRef> t;
     for (int y = 0; y < ty; ++y)
@@ -558,15 +594,32 @@ int ensure_frame(dpml *H, int levels)
             const bool inside = xa >= r[0] && xb <= r[1] && ya >= r[2] && yb <= r[3];
             if (!inside) t.push_back({0, x, y, 0});
         }
-    H->n_frame[q] = (int64_t)t.size();
+    H->n_frame[q][shrink] = (int64_t)t.size();
     if (t.empty()) return DPML_OK;
-    HIP_TRY(H, hipMalloc((void **)&H->d_frame[q], t.size() * sizeof(dpmlk::TileRef)));
-    HIP_TRY(H, hipMemcpy(H->d_frame[q], t.data(), t.size() * sizeof(dpmlk::TileRef), hipMemcpyHostToDevice));
+    HIP_TRY(H, hipMalloc((void **)&H->d_frame[q][shrink], t.size() * sizeof(dpmlk::TileRef)));
+    HIP_TRY(H, hipMemcpy(H->d_frame[q][shrink], t.data(), t.size() * sizeof(dpmlk::TileRef), hipMemcpyHostToDevice));
     return DPML_OK;
 }
 
-// `levels` (2 or 3) steps: the core and the frame's first step in one
-// launch, each further frame step in a launch of its own.
+// Everything a multi-step pass over `levels` levels needs before it can be
+// enqueued (or captured): the frame tables and the side stream with its
+// fork/join events.
+int ensure_multistep(dpml *H, int levels)
+{
+    for (int sh = 0; sh < levels; ++sh) {
+        int rc = ensure_frame(H, levels, sh);
+        if (rc) return rc;
+    }
+    return ensure_side(H);
+}
+
+// `levels` (2 or 3) steps.  The core kernel runs on the handle's stream;
+// the frame takes `levels` ordinary steps on the side stream at the same
+// time, step j (1-based) over everything outside the core shrunk by
+// levels - j cells, which is where the later frame steps need level j.  The
+// core writes no level-j value on those cells, so every cell of every
+// buffer has one writer.  The pass ends with the handle's stream waiting
+// for the side stream.
 template <typename T>
 int launch_multistep(dpml *H, int levels)
 {
@@ -586,51 +639,66 @@ int launch_multistep(dpml *H, int levels)
     core_rect(L, levels, r);
     constexpr int VX = sizeof(T) == 4 ? 4 : 2;
     const int HL = (levels + VX - 1) / VX;                      // halo lanes per strip side
-    const int rows = H->tile_rows > 0 ? H->tile_rows : (levels == 3 ? 32 : 16);
+    // tile_rows: rows per wave in the low 12 bits (0: 8), loads issued G rows at a
+    // time with G in the bits above (0: 2)
+    const int rows = (H->tile_rows & 0xFFF) > 0 ? (H->tile_rows & 0xFFF) : 8;
+    const int G = (H->tile_rows >> 12) > 0 ? (H->tile_rows >> 12) : 2;
     const int strips = (r[1] - r[0] + (64 - 2 * HL) * VX - 1) / ((64 - 2 * HL) * VX);
     const int n_waves = strips * ((r[3] - r[2] + rows - 1) / rows);
-    const int core_blocks = round8((n_waves + 3) / 4);
-    const int nf = (int)std::max<int64_t>(H->n_frame[q], 0);
-    const int frame_blocks = nf > 0 ? round8(nf) : 0;
-    const dpmlk::TileRef *ft = H->d_frame[q];
-    // the frame's first step reads A, Bv and writes nxt[0]; the core reads
-    // A, Bv and writes nxt[0] (all of it, or its ring), nxt[1] (, nxt[2])
-    dpmlk::StepArgs<T> p = make_args<T>(H);
-    (void)Bv;
-    p.uout = nxt[0];
-    p.tile_rows = rows;
-    for (int i = 0; i < 4; ++i) p.skip[i] = r[i];
-    const dim3 grid((unsigned)(frame_blocks + core_blocks), B), block(256);
-    const double core = (double)(r[1] - r[0]) * (double)(r[3] - r[2]), frame = (double)L.ncell - core;
-    int slot = timed_begin(H, DPML_KERNEL_PAIR, step_bytes(H, levels * core + frame, aux_cells(L)));
-    if (levels == 2 && p.c2)
-        hipLaunchKernelGGL((dpmlk::k_step2_march<T, VX, 4, true>), grid, block, 0, H->stream, p, nxt[1], r[0], r[1],
-                           r[2], r[3], strips, n_waves, ft, nf, frame_blocks);
-    else if (levels == 2)
-        hipLaunchKernelGGL((dpmlk::k_step2_march<T, VX, 4, false>), grid, block, 0, H->stream, p, nxt[1], r[0], r[1],
-                           r[2], r[3], strips, n_waves, ft, nf, frame_blocks);
-    else if (p.c2)
-        hipLaunchKernelGGL((dpmlk::k_step3_march<T, VX, 2, true>), grid, block, 0, H->stream, p, nxt[1], nxt[2],
-                           r[0], r[1], r[2], r[3], strips, n_waves, ft, nf, frame_blocks);
-    else
-        hipLaunchKernelGGL((dpmlk::k_step3_march<T, VX, 2, false>), grid, block, 0, H->stream, p, nxt[1], nxt[2],
-                           r[0], r[1], r[2], r[3], strips, n_waves, ft, nf, frame_blocks);
-    timed_end(H, slot);
-    // further frame steps: level j+1 from nxt[j] (U^{n+j+1}) and the level
-    // before it, aux buffers alternating
-    for (int j = 1; j < levels && nf > 0; ++j) {
-        const dim3 g2((unsigned)frame_blocks, B);
-        if (j % 2 == 1) H->cur = 1 - H->cur;
-        dpmlk::StepArgs<T> pj = make_args<T>(H);
-        if (j % 2 == 1) H->cur = 1 - H->cur;
-        pj.u = nxt[j - 1];
-        pj.uo = j == 1 ? A : nxt[j - 2];
-        pj.uout = nxt[j];
-        for (int i = 0; i < 4; ++i) pj.skip[i] = r[i];
-        slot = timed_begin(H, DPML_KERNEL_FRAME, step_bytes(H, frame, aux_cells(L)));
-        hipLaunchKernelGGL((dpmlk::k_step_frame<T>), g2, block, 0, H->stream, pj, ft, nf);
+    const dim3 block(256);
+    const double core = (double)(r[1] - r[0]) * (double)(r[3] - r[2]);
+    // fork: the side stream starts once everything before this pass is done
+    HIP_TRY(H, hipEventRecord(H->ev_fork, H->stream));
+    HIP_TRY(H, hipStreamWaitEvent(H->side, H->ev_fork, 0));
+    if (n_waves > 0) {
+        dpmlk::StepArgs<T> p = make_args<T>(H);
+        p.uout = nxt[0];
+        p.tile_rows = rows;
+        const dim3 grid((unsigned)round8((n_waves + 3) / 4), B);
+        const int slot = timed_begin(H, DPML_KERNEL_PAIR, step_bytes(H, levels * core, 0.0));
+#define DPML_MULTI_LAUNCH(GG, C2)                                                                           \
+        if (levels == 2)                                                                                    \
+            hipLaunchKernelGGL((dpmlk::k_step2_march<T, VX, GG, C2>), grid, block, 0, H->stream, p, nxt[1],     \
+                               r[0], r[1], r[2], r[3], strips, n_waves);                                    \
+        else                                                                                                \
+            hipLaunchKernelGGL((dpmlk::k_step3_march<T, VX, GG, C2>), grid, block, 0, H->stream, p, nxt[1],     \
+                               nxt[2], r[0], r[1], r[2], r[3], strips, n_waves);
+        if (G == 4) {
+            if (p.c2) { DPML_MULTI_LAUNCH(4, true) } else { DPML_MULTI_LAUNCH(4, false) }
+        } else if (G == 1) {
+            if (p.c2) { DPML_MULTI_LAUNCH(1, true) } else { DPML_MULTI_LAUNCH(1, false) }
+        } else {
+            if (p.c2) { DPML_MULTI_LAUNCH(2, true) } else { DPML_MULTI_LAUNCH(2, false) }
+        }
+#undef DPML_MULTI_LAUNCH
         timed_end(H, slot);
     }
+    // the frame's steps on the side stream: level j from level j-1 (U^n at
+    // j = 1) and the level before it, aux buffers alternating
+    for (int j = 1; j <= levels; ++j) {
+        const int sh = levels - j;
+        const int nf = (int)H->n_frame[q][sh];
+        if (nf <= 0) continue;
+        if (j % 2 == 0) H->cur = 1 - H->cur;
+        dpmlk::StepArgs<T> pj = make_args<T>(H);
+        if (j % 2 == 0) H->cur = 1 - H->cur;
+        pj.u = j == 1 ? A : nxt[j - 2];
+        pj.uo = j == 1 ? Bv : (j == 2 ? A : nxt[j - 3]);
+        pj.uout = nxt[j - 1];
+        pj.skip[0] = r[0] + sh;
+        pj.skip[1] = r[1] - sh;
+        pj.skip[2] = r[2] + sh;
+        pj.skip[3] = r[3] - sh;
+        // algorithmic share: the frame's own cells (the ring cells it recomputes
+        // are the core's, counted there)
+        const int slot = timed_begin(H, DPML_KERNEL_FRAME, step_bytes(H, (double)L.ncell - core, aux_cells(L)), H->side);
+        hipLaunchKernelGGL((dpmlk::k_step_frame<T>), dim3((unsigned)round8(nf), B), block, 0, H->side, pj,
+                           H->d_frame[q][sh], nf);
+        timed_end(H, slot, H->side);
+    }
+    // join
+    HIP_TRY(H, hipEventRecord(H->ev_join, H->side));
+    HIP_TRY(H, hipStreamWaitEvent(H->stream, H->ev_join, 0));
     HIP_TRY(H, hipGetLastError());
     H->u_now = nxt[levels - 1];
     H->u_old = nxt[levels - 2];
@@ -646,7 +714,7 @@ int step_impl(dpml *H, int64_t nsteps)
     for (;;) {
         const int lv = multistep_levels(H, nsteps - k);
         if (lv < 2) break;
-        int rc = ensure_frame(H, lv);
+        int rc = ensure_multistep(H, lv);
         if (rc) return rc;
         rc = launch_multistep<T>(H, lv);
         if (rc) return rc;
@@ -921,7 +989,7 @@ int dpml_record_plane(dpml_t *H, int32_t axis, int64_t index, void *planes, int6
 int dpml_set_variant(dpml_t *H, int32_t variant, int32_t tile_rows)
 {
     if (!H) return DPML_EINVAL;
-    if (variant < DPML_VARIANT_AUTO || variant > DPML_VARIANT_THREESTEP || tile_rows < 0 || tile_rows > 4096)
+    if (variant < DPML_VARIANT_AUTO || variant > DPML_VARIANT_THREESTEP || tile_rows < 0 || tile_rows > 65535)
         return H->fail(DPML_EINVAL, "bad variant");
     H->variant = variant;
     H->tile_rows = tile_rows;
@@ -1061,7 +1129,7 @@ int dpml_get_timing(dpml_t *H, dpml_timing_t *out)
 {
     if (!H || !out) return DPML_EINVAL;
     *out = dpml_timing_t{};
-    if (!H->timed.empty()) HIP_TRY(H, hipEventSynchronize(H->timed.back().e1));
+    for (const dpml::Timed &t : H->timed) HIP_TRY(H, hipEventSynchronize(t.e1));
     for (const dpml::Timed &t : H->timed) {
         float ms = 0.f;
         HIP_TRY(H, hipEventElapsedTime(&ms, t.e0, t.e1));
@@ -1085,7 +1153,11 @@ void dpml_destroy(dpml_t *H)
     if (H->d_src_order) (void)hipFree(H->d_src_order);
     if (H->d_rec_cells) (void)hipFree(H->d_rec_cells);
     for (int k = 0; k < 2; ++k)
-        if (H->d_frame[k]) (void)hipFree(H->d_frame[k]);
+        for (int j = 0; j < 3; ++j)
+            if (H->d_frame[k][j]) (void)hipFree(H->d_frame[k][j]);
+    if (H->ev_fork) (void)hipEventDestroy(H->ev_fork);
+    if (H->ev_join) (void)hipEventDestroy(H->ev_join);
+    if (H->side) (void)hipStreamDestroy(H->side);
     if (H->d_slabs) (void)hipFree(H->d_slabs);
     if (H->d_adj_frame) (void)hipFree(H->d_adj_frame);
     if (H->d_rec_sorted) (void)hipFree(H->d_rec_sorted);
@@ -1239,6 +1311,7 @@ int adjoint_impl(dpml *H, const void *resid, double *grad, void *grad_w)
     int adj_tiles_x = 0, adj_waves = 0;
     if (L.ndim == 2) {
         int rc = ensure_adj_frame(H);
+        if (!rc) rc = ensure_side(H);
         if (rc) return rc;
         adj_core(L, core);
         adj_tiles_x = (core[1] - core[0] + 63) / 64;
@@ -1319,16 +1392,27 @@ int adjoint_impl(dpml *H, const void *resid, double *grad, void *grad_w)
             q.batch = (int32_t)L.batch;
             q.bstride = L.ncell;
             if (L.ndim == 2) {
+                // the frame's cells on the side stream while the core marches on the
+                // handle's stream (disjoint cells; joined before the next level)
+                const bool fork = H->n_adj_frame > 0 && adj_waves > 0;
+                if (fork) {
+                    HIP_TRY(H, hipEventRecord(H->ev_fork, H->stream));
+                    HIP_TRY(H, hipStreamWaitEvent(H->side, H->ev_fork, 0));
+                }
                 if (H->n_adj_frame > 0) {
                     dpmlk::AdjArgs<T> f = q;
                     f.tiles = H->d_adj_frame;
                     f.ntiles = (int32_t)H->n_adj_frame;
                     for (int k = 0; k < 4; ++k) f.skip[k] = core[k];
-                    hipLaunchKernelGGL((dpmlk::k_adjoint_cell<T, 2>), fgrid, ablock, 0, H->stream, f);
+                    hipLaunchKernelGGL((dpmlk::k_adjoint_cell<T, 2>), fgrid, ablock, 0, fork ? H->side : H->stream, f);
                 }
                 if (adj_waves > 0)
                     hipLaunchKernelGGL((dpmlk::k_adjoint_march2d<T, kAdjRows>), mgrid, ablock, 0, H->stream, q,
                                        core[0], core[1], core[2], core[3], adj_tiles_x, adj_waves);
+                if (fork) {
+                    HIP_TRY(H, hipEventRecord(H->ev_join, H->side));
+                    HIP_TRY(H, hipStreamWaitEvent(H->stream, H->ev_join, 0));
+                }
             } else {
                 hipLaunchKernelGGL((dpmlk::k_adjoint_cell<T, 3>), agrid, ablock, 0, H->stream, q);
             }
@@ -1879,13 +1963,22 @@ int step_graph_impl(dpml *H, int64_t nsteps)
         view.stream = H->cap;
         view.err.clear();
         view.timing = false;
-        for (int lv = 2; lv <= 3; ++lv) {      // the frame tables must exist before capture
+        for (int lv = 2; lv <= 3; ++lv) {      // frame tables, side stream, events before capture
             if (multistep_levels(H, nsteps) < 2) break;
-            int rcf = ensure_frame(H, lv);
+            int rcf = ensure_multistep(H, lv);
             if (rcf) return rcf;
-            view.d_frame[lv - 2] = H->d_frame[lv - 2];
-            view.n_frame[lv - 2] = H->n_frame[lv - 2];
+            for (int sh = 0; sh < 3; ++sh) {
+                view.d_frame[lv - 2][sh] = H->d_frame[lv - 2][sh];
+                view.n_frame[lv - 2][sh] = H->n_frame[lv - 2][sh];
+            }
         }
+        {
+            int rcs = ensure_side(H);
+            if (rcs) return rcs;
+        }
+        view.side = H->side;
+        view.ev_fork = H->ev_fork;
+        view.ev_join = H->ev_join;
         if (H->L.ndim == 3 && (H->L.M[1] > 0 || H->L.M[2] > 0)) {   // likewise the slab table
             int rcs = ensure_slabs(H);
             if (rcs) return rcs;
@@ -1898,7 +1991,10 @@ int step_graph_impl(dpml *H, int64_t nsteps)
         hipError_t e = hipStreamEndCapture(H->cap, &g);
         view.cap = nullptr; view.graph = nullptr; view.exec = nullptr;   // not owned by the view
         view.d_src_cells = view.d_src_order = view.d_rec_cells = view.d_rec_sorted = view.d_rec_order = nullptr;
-        view.d_frame[0] = view.d_frame[1] = nullptr;
+        for (int lv = 0; lv < 2; ++lv)
+            for (int sh = 0; sh < 3; ++sh) view.d_frame[lv][sh] = nullptr;
+        view.side = nullptr;
+        view.ev_fork = view.ev_join = nullptr;
         view.d_slabs = nullptr;
         H->graph_end_unow = view.u_now;
         H->graph_end_uold = view.u_old;

@@ -483,12 +483,12 @@ __device__ __forceinline__ void cell2d_tile(const StepArgs<T> &p, int tx, int ty
 // cross-lane shuffles.  Reads U^n, U^{n-1}; writes U^{n+1}, U^{n+2} (into two
 // further buffers): 2 words per cell per step instead of 3.
 //
-// The same launch also takes the frame's first step: blocks below
-// frame_blocks run one ordinary step (U^n -> U^{n+1}, aux fields included)
-// on a list of 64 x 4 tiles that covers everything outside the core; the
-// frame's second step is a separate launch.  The core evaluates the scheme
-// in the operation order of cell_update (no damping terms there), so results
-// are bit-identical to single steps.
+// The frame (everything outside the core, layer included) advances by
+// ordinary steps on a second stream at the same time: its first step also
+// covers the core's one-cell boundary ring, so the core leaves U^{n+1} there
+// to it (store_inner) and the two never write the same cell.  The core
+// evaluates the scheme in the operation order of cell_update (no damping
+// terms there), so results are bit-identical to single steps.
 // ---------------------------------------------------------------------------
 template <typename T, int VX, bool C2F>
 struct March2Ctx {
@@ -496,8 +496,23 @@ struct March2Ctx {
     const T *u, *up, *c2;          // U^n, U^{n-1}, c^2 field
     T *o1, *o2;                    // U^{n+1}, U^{n+2}
     T inv_h2, dt2, c2c;
-    int nx, ny, xs, xw, cx1;
+    int nx, ny, xs, xw, cx0, cx1, cy0, cy1;
     bool need, vec, out;
+
+    // store of a row that leaves the core's boundary ring (first/last row and
+    // column of the core) alone: the frame steps own those cells there
+    __device__ __forceinline__ void store_inner(T *f, int y, const R &r) const
+    {
+        if (!out || y == cy0 || y == cy1 - 1) return;
+        T *row = f + (int64_t)y * nx + xs;
+        if (xs > cx0 && xs + VX < cx1) {
+            store_row<T, VX>(row, r);
+        } else {
+#pragma unroll
+            for (int k = 0; k < VX; ++k)
+                if (xs + k > cx0 && xs + k < cx1 - 1) row[k] = r.v[k];
+        }
+    }
 
     __device__ __forceinline__ int wrapy(int y) const { return y < 0 ? y + ny : (y >= ny ? y - ny : y); }
 
@@ -591,7 +606,7 @@ struct March2Ctx {
 #pragma unroll
         for (int g = 0; g < G; ++g) {
             v[2 + g] = lev<DIR>(wn[g], wn[g + 1], wn[g + 2], po[g], cw[1 + g]);
-            if (k + g < L) store(o1, base + DIR * (k + g), v[2 + g]);
+            if (k + g < L) store_inner(o1, base + DIR * (k + g), v[2 + g]);
             store(o2, base + DIR * (k - 1 + g), lev<DIR>(v[g], v[g + 1], v[g + 2], wn[g], cw[g]));
         }
         s.n0 = wn[G];
@@ -618,7 +633,7 @@ struct March2Ctx {
             }
             s.v0 = lev<DIR>(a0, a1, a2, p0, k0);
             s.v1 = lev<DIR>(a1, a2, a3, p1, k1);
-            store(o1, base, s.v1);
+            store_inner(o1, base, s.v1);
             s.n0 = a2;
             s.n1 = a3;
             s.c0 = k1;
@@ -632,22 +647,9 @@ struct March2Ctx {
 
 template <typename T, int VX, int G, bool C2F>
 __global__ void __launch_bounds__(256) k_step2_march(StepArgs<T> p, T *__restrict__ u_next2, int cx0, int cx1,
-                                                     int cy0, int cy1, int strips, int n_waves,
-                                                     const TileRef *__restrict__ frame, int n_frame,
-                                                     int frame_blocks)
+                                                     int cy0, int cy1, int strips, int n_waves)
 {
-    if ((int)blockIdx.x < frame_blocks) {          // the frame's first step
-        const int t = (int)blockIdx.x;
-        if (t >= n_frame) return;
-        select_member(p, (int)blockIdx.y);
-        const int x = frame[t].tx * 64 + (int)(threadIdx.x % 64);
-        const int y = frame[t].ty * 4 + (int)(threadIdx.x / 64);
-        if (x >= p.skip[0] && x < p.skip[1] && y >= p.skip[2] && y < p.skip[3]) return;
-        cell2d_tile<T, 4>(p, frame[t].tx, frame[t].ty);
-        return;
-    }
-    const int cb = (int)blockIdx.x - frame_blocks;           // frame_blocks is a multiple of 8
-    const int w = xcd_tile(cb, (int)gridDim.x - frame_blocks) * 4 + (int)(threadIdx.x >> 6);
+    const int w = __builtin_amdgcn_readfirstlane(xcd_tile(blockIdx.x, gridDim.x) * 4 + (int)(threadIdx.x >> 6));
     if (w >= n_waves) return;                                // whole waves; no barriers below
     const int lane = (int)(threadIdx.x & 63);
     const int strip = w % strips, ty = w / strips;
@@ -663,7 +665,10 @@ __global__ void __launch_bounds__(256) k_step2_march(StepArgs<T> p, T *__restric
     c.c2c = p.c2_const;
     c.nx = p.nx;
     c.ny = p.ny;
+    c.cx0 = cx0;
     c.cx1 = cx1;
+    c.cy0 = cy0;
+    c.cy1 = cy1;
     c.xs = cx0 + (strip * 62 + lane - 1) * VX;
     c.need = c.xs < cx1 + VX;                                // lanes further right feed nobody
     c.xw = c.xs % c.nx;
@@ -682,35 +687,24 @@ __global__ void __launch_bounds__(256) k_step2_march(StepArgs<T> p, T *__restric
 // Three steps per launch, 2D periodic grids: the same marching scheme one
 // level deeper.  For march index k a wave reads U^n(k+1) and U^{n-1}(k) and
 // computes U^{n+1}(k), U^{n+2}(k-1) and U^{n+3}(k-2) from rows held in
-// registers.  It writes U^{n+2} and U^{n+3} of its tile, and U^{n+1} only on
-// the core's one-cell boundary ring (the frame's second step needs it
-// there): 4 words per core cell per three steps instead of 6 for two
-// two-step passes.  Each side of a strip carries HL = ceil(3/VX) halo lanes.
-// Buffers: reads U^n, U^{n-1}; writes U^{n+1} (ring), U^{n+2}, U^{n+3} into
-// three further buffers.  The launch also runs the frame's first step; the
-// frame's second and third steps are separate launches.
+// registers.  It writes U^{n+3} of its tile and U^{n+2} off the core's
+// boundary ring; U^{n+1} stays in registers: 4 words per core cell per
+// three steps instead of 6 for two two-step passes.  Each side of a strip
+// carries HL = ceil(3/VX) halo lanes.  The frame's three ordinary steps run
+// on a second stream meanwhile and reach two (first step) and one (second
+// step) cells into the core, which is where they need U^{n+1} and U^{n+2}.
 // ---------------------------------------------------------------------------
 template <typename T, int VX, bool C2F>
 struct March3Ctx : March2Ctx<T, VX, C2F> {
     using Base = March2Ctx<T, VX, C2F>;
     using R = Row<T, VX>;
     T *o3;                         // U^{n+3}
-    bool ring_lane;                // this lane's cells touch the core's first or last column
-    int cy0, cy1;                  // core rows
 
     // rolling state at march index k: U^n at k-1, k; U^{n+1} at k-2, k-1;
     // U^{n+2} at k-3, k-2; c^2 at k-2, k-1
     struct State {
         R n0, n1, a0, a1, b0, b1, c0, c1;
     };
-
-    template <int DIR>
-    __device__ __forceinline__ void put1(int base, int k, int L, const R &v) const
-    {
-        // U^{n+1} on the ring only: the core's first/last row, or its first/last column
-        const int y = base + DIR * k;
-        if (k >= 0 && k < L && (ring_lane || y == cy0 || y == cy1 - 1)) this->store(this->o1, y, v);
-    }
 
     // one march index k with every level guarded (prologue and tail)
     template <int DIR>
@@ -721,11 +715,10 @@ struct March3Ctx : March2Ctx<T, VX, C2F> {
         R cn{};
         if (C2F) cn = this->load(this->c2, this->wrapy(base + DIR * k));
         const R v1 = this->template lev<DIR>(s.n0, s.n1, nn, pm, cn);           // U^{n+1}(k)
-        put1<DIR>(base, k, L, v1);
         R v2{};
         if (k - 1 >= -1) {
             v2 = this->template lev<DIR>(s.a0, s.a1, v1, s.n0, s.c1);           // U^{n+2}(k-1)
-            if (k - 1 >= 0 && k - 1 < L) this->store(this->o2, base + DIR * (k - 1), v2);
+            if (k - 1 >= 0 && k - 1 < L) this->store_inner(this->o2, base + DIR * (k - 1), v2);
         }
         if (k - 2 >= 0 && k - 2 < L)
             this->store(o3, base + DIR * (k - 2), this->template lev<DIR>(s.b0, s.b1, v2, s.a0, s.c0));
@@ -762,9 +755,8 @@ struct March3Ctx : March2Ctx<T, VX, C2F> {
 #pragma unroll
         for (int g = 0; g < G; ++g) {
             v1[2 + g] = this->template lev<DIR>(wn[g], wn[g + 1], wn[g + 2], pm[g], cw[2 + g]);
-            put1<DIR>(base, k + g, L, v1[2 + g]);
             v2[2 + g] = this->template lev<DIR>(v1[g], v1[g + 1], v1[g + 2], wn[g], cw[g + 1]);
-            this->store(this->o2, base + DIR * (k - 1 + g), v2[2 + g]);
+            this->store_inner(this->o2, base + DIR * (k - 1 + g), v2[2 + g]);
             this->store(o3, base + DIR * (k - 2 + g), this->template lev<DIR>(v2[g], v2[g + 1], v2[g + 2], v1[g], cw[g]));
         }
         s.n0 = wn[G];
@@ -795,24 +787,10 @@ struct March3Ctx : March2Ctx<T, VX, C2F> {
 
 template <typename T, int VX, int G, bool C2F>
 __global__ void __launch_bounds__(256) k_step3_march(StepArgs<T> p, T *__restrict__ u_next2, T *__restrict__ u_next3,
-                                                     int cx0, int cx1, int cy0, int cy1, int strips, int n_waves,
-                                                     const TileRef *__restrict__ frame, int n_frame,
-                                                     int frame_blocks)
+                                                     int cx0, int cx1, int cy0, int cy1, int strips, int n_waves)
 {
-    if ((int)blockIdx.x < frame_blocks) {          // the frame's first step
-        const int t = (int)blockIdx.x;
-        if (t >= n_frame) return;
-        select_member(p, (int)blockIdx.y);
-        const int x = frame[t].tx * 64 + (int)(threadIdx.x % 64);
-        const int y = frame[t].ty * 4 + (int)(threadIdx.x / 64);
-        if (x >= p.skip[0] && x < p.skip[1] && y >= p.skip[2] && y < p.skip[3]) return;
-        cell2d_tile<T, 4>(p, frame[t].tx, frame[t].ty);
-        return;
-    }
     constexpr int HL = (3 + VX - 1) / VX;                    // halo lanes per side
-    const int cb = (int)blockIdx.x - frame_blocks;           // frame_blocks is a multiple of 8
-    const int w = __builtin_amdgcn_readfirstlane(xcd_tile(cb, (int)gridDim.x - frame_blocks) * 4 +
-                                                 (int)(threadIdx.x >> 6));
+    const int w = __builtin_amdgcn_readfirstlane(xcd_tile(blockIdx.x, gridDim.x) * 4 + (int)(threadIdx.x >> 6));
     if (w >= n_waves) return;                                // whole waves; no barriers below
     const int lane = (int)(threadIdx.x & 63);
     const int strip = w % strips, ty = w / strips;
@@ -829,6 +807,7 @@ __global__ void __launch_bounds__(256) k_step3_march(StepArgs<T> p, T *__restric
     c.c2c = p.c2_const;
     c.nx = p.nx;
     c.ny = p.ny;
+    c.cx0 = cx0;
     c.cx1 = cx1;
     c.cy0 = cy0;
     c.cy1 = cy1;
@@ -838,7 +817,6 @@ __global__ void __launch_bounds__(256) k_step3_march(StepArgs<T> p, T *__restric
     if (c.xw < 0) c.xw += c.nx;
     c.vec = c.xw % VX == 0 && c.xw + VX <= c.nx;
     c.out = lane >= HL && lane < 64 - HL && c.xs < cx1;
-    c.ring_lane = c.xs == cx0 || c.xs + VX >= cx1;
     const int rows = p.tile_rows;
     const int ya = cy0 + ty * rows, yb = min(ya + rows, cy1);
     if (ty & 1)
@@ -970,9 +948,13 @@ __global__ void __launch_bounds__(256) k_step_zmarch3d(StepArgs<T> p, int tx0, i
     // of plane z, the strip-edge columns and the halo rows of plane z.  They
     // are issued one plane ahead, so a wave computes plane z while the
     // loads of plane z+1 are in flight.
+    // With the x-layer terms (AX = 1) the layer inputs of the plane (Phi_x,
+    // Psi_x around the cell's band slot) are fetched one plane ahead too.
     struct Fetch {
         T upn[RY], old[RY], edge[RY], hlo, hhi;
+        LayerIn<T> lx[AX == 1 ? RY : 1];
     };
+    const int jx = (AX == 1 && p.ax[0].M > 0 && xin) ? band_coord(p.ax[0], x) : (1 << 30);
     auto fetch = [&](int z, Fetch &f) {
         const int pz = plane_of(z + 1);
         const int64_t plane = (int64_t)z * sxy;
@@ -982,6 +964,10 @@ __global__ void __launch_bounds__(256) k_step_zmarch3d(StepArgs<T> p, int tx0, i
             f.old[q] = (xin && y0 + q < y1c) ? p.uo[plane + (int64_t)(y0 + q) * nx + x] : T(0);
             f.edge[q] = T(0);
             if ((lane == 0 || lane == 63) && ry[q] >= 0 && !ezero) f.edge[q] = u[plane + (int64_t)ry[q] * nx + xe];
+            if constexpr (AX == 1) {
+                f.lx[q].on = false;
+                if (y0 + q < y1c && jx <= p.ax[0].M) f.lx[q] = layer_load<0>(p.ax[0], jx, nx, ny, x, y0 + q, z);
+            }
         }
         f.hlo = ld(z, rlo);
         f.hhi = ld(z, rhi);
@@ -1003,8 +989,22 @@ __global__ void __launch_bounds__(256) k_step_zmarch3d(StepArgs<T> p, int tx0, i
             const int y = y0 + q;
             if (xin && y < y1c) {
                 const int64_t idx = plane + (int64_t)y * nx + x;
-                const T r = cell_update<T, 3, AX, (AX != 0)>(p, x, y, z, idx, uc[q], uxm, uxp, uym, uyp, um[q],
-                                                              cur.upn[q], cur.old[q]);
+                T r;
+                if constexpr (AX == 1) {
+                    // cell_update's hoisted form with the prefetched x-layer inputs
+                    const T c2 = p.c2 ? p.c2[idx] : p.c2_const;
+                    T lap = T(0);
+                    lap += ((uxm - T(2) * uc[q]) + uxp) * p.inv_h2;
+                    lap += ((uym - T(2) * uc[q]) + uyp) * p.inv_h2;
+                    lap += ((um[q] - T(2) * uc[q]) + cur.upn[q]) * p.inv_h2;
+                    T damp = T(0);
+                    if (cur.lx[q].on) damp += layer_finish(p.ax[0], cur.lx[q], jx, uxm, uxp, p.dt, p.inv_2h) * p.inv_h;
+                    const T rhs = c2 * lap + damp;
+                    r = (T(2) * uc[q] - cur.old[q]) + p.dt2 * rhs;
+                } else {
+                    r = cell_update<T, 3, AX, (AX != 0)>(p, x, y, z, idx, uc[q], uxm, uxp, uym, uyp, um[q],
+                                                         cur.upn[q], cur.old[q]);
+                }
                 out[idx] = r;
                 if (p.hist) p.hist[idx] = r;
             }

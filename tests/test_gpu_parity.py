@@ -367,6 +367,34 @@ def test_twostep_matches_single_steps_and_oracle(dtype, case, rows, multi):
         _assert_errs(compare_states(gs, ref, n, lo, hi, peaks if dtype == "f32" else None), dtype)
 
 
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("variant", [dp.VARIANT_TWOSTEP, dp.VARIANT_THREESTEP])
+@pytest.mark.parametrize("group,rows", [(1, 3), (4, 7), (4, 4), (2, 1)])
+def test_multistep_launch_shapes_bit_identical(dtype, variant, group, rows):
+    """Every load-group size and tile height of the two- and three-step
+    kernels (tiles shorter than a group, one-row tiles) gives the single-step
+    result bit for bit, with a c^2 field and a ragged grid."""
+    rng = np.random.default_rng(5)
+    n, lo, hi = [333, 157], [7, 11], [9, 4]
+    sig = [synthetic.sigma_random(n[a], lo[a], hi[a], 2.0, rng) for a in range(2)]
+    c2 = synthetic.smooth_c2(n, lo, hi, 6, 10.0, 30.0, 0.5, 8, rng)
+    U0 = synthetic.gaussian_sum(n, lo, hi, 8, 2.0, 6.0, rng)
+    dt = 0.5 / math.sqrt(float(np.max(c2)))
+    outs = []
+    for v, tr in ((variant, (group << 12) | rows), (dp.VARIANT_CELL, 0)):
+        sim = dp.Simulation(n, lo, hi, 1.0, dt, sig, c2=c2, dtype=_dtype(dtype))
+        sim.set_variant(v, tr)
+        sim.set_state(torch.from_numpy(U0))
+        sim.step(47)
+        sim.sync()
+        outs.append((sim.U.cpu().numpy().copy(), sim.field(dp.FIELD_UPREV).cpu().numpy().copy(),
+                     [sim.field(dp.FIELD_PHI(a)).cpu().numpy().copy() for a in range(2)]))
+        sim.close()
+    assert np.array_equal(outs[0][0], outs[1][0]) and np.array_equal(outs[0][1], outs[1][1])
+    for x, y in zip(outs[0][2], outs[1][2]):
+        assert np.array_equal(x, y)
+
+
 @pytest.mark.parametrize("variant", [dp.VARIANT_TWOSTEP, dp.VARIANT_THREESTEP])
 def test_twostep_graph_replay_matches_eager(variant):
     w = synthetic.bump2d(200, 20, 0)
@@ -408,13 +436,13 @@ def test_launch_timing_counts_and_bytes(dtype):
     sim.set_variant(dp.VARIANT_TWOSTEP, 0)
     sim.step(7)                                   # three pairs and one single step
     t = sim.get_timing()
-    assert t["pair"]["launches"] == 3 and t["frame"]["launches"] == 3 and t["step"]["launches"] == 1
+    assert t["pair"]["launches"] == 3 and t["frame"]["launches"] == 3 * 2 and t["step"]["launches"] == 1
     assert t["pair"]["bytes"] + t["frame"]["bytes"] == 3 * 2 * step_bytes
     assert t["step"]["bytes"] == step_bytes
     sim.set_variant(dp.VARIANT_THREESTEP, 0)
     sim.step(8)                                   # two triples and one pair
     t = sim.get_timing()
-    assert t["pair"]["launches"] == 3 and t["frame"]["launches"] == 2 * 2 + 1 and "step" not in t
+    assert t["pair"]["launches"] == 3 and t["frame"]["launches"] == 2 * 3 + 2 and "step" not in t
     assert t["pair"]["bytes"] + t["frame"]["bytes"] == 8 * step_bytes
     sim.step_graph(4)
     sim.sync()
