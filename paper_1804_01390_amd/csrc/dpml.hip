@@ -400,35 +400,33 @@ int launch_march3d(dpml *H, dpmlk::StepArgs<T> p, int ry)
     }
     // launch the strips [t0, t1) with or without the x-layer code; the two
     // edge strips alone are few tiles, so they march shorter chunks
-    auto strips = [&](int t0, int t1, bool layer, int kind, double bytes) {
-        if (t1 <= t0 || p.tiles_y <= 0) return;
+    // strips [t0, t1) except [gap_at, gap_at + gap)
+    auto strips = [&](int t0, int t1, int gap_at, int gap, bool layer, int kind, double bytes) {
+        if (t1 - t0 - gap <= 0 || p.tiles_y <= 0) return;
         dpmlk::StepArgs<T> q = p;
         if (layer) q.tile_rows = std::max(8, p.tile_rows / 4);
         const int tz = (b[3] - b[2] + q.tile_rows - 1) / q.tile_rows;
         if (tz <= 0) return;
-        q.tiles_x = t1 - t0;
+        q.tiles_x = t1 - t0 - gap;
         q.n_tiles = q.tiles_x * q.tiles_y * tz;
         hipStream_t st = layer ? ls : H->stream;
         const int slot = timed_begin(H, kind, bytes, st);
         const dim3 grid((unsigned)round8(q.n_tiles), B);
         if (ry == 4 && layer)
-            hipLaunchKernelGGL((dpmlk::k_step_zmarch3d<T, 4, 1>), grid, block, 0, st, q, t0, b[0], b[1], b[2], b[3]);
+            hipLaunchKernelGGL((dpmlk::k_step_zmarch3d<T, 4, 1>), grid, block, 0, st, q, t0, gap_at, gap, b[0], b[1], b[2], b[3]);
         else if (ry == 4)
-            hipLaunchKernelGGL((dpmlk::k_step_zmarch3d<T, 4, 0>), grid, block, 0, st, q, t0, b[0], b[1], b[2], b[3]);
+            hipLaunchKernelGGL((dpmlk::k_step_zmarch3d<T, 4, 0>), grid, block, 0, st, q, t0, gap_at, gap, b[0], b[1], b[2], b[3]);
         else if (layer)
-            hipLaunchKernelGGL((dpmlk::k_step_zmarch3d<T, 2, 1>), grid, block, 0, st, q, t0, b[0], b[1], b[2], b[3]);
+            hipLaunchKernelGGL((dpmlk::k_step_zmarch3d<T, 2, 1>), grid, block, 0, st, q, t0, gap_at, gap, b[0], b[1], b[2], b[3]);
         else
-            hipLaunchKernelGGL((dpmlk::k_step_zmarch3d<T, 2, 0>), grid, block, 0, st, q, t0, b[0], b[1], b[2], b[3]);
+            hipLaunchKernelGGL((dpmlk::k_step_zmarch3d<T, 2, 0>), grid, block, 0, st, q, t0, gap_at, gap, b[0], b[1], b[2], b[3]);
         timed_end(H, slot, st);
     };
     const bool whole = !split && s0 == 0 && s1 == nstrips;
-    strips(s0, s1, false, whole ? DPML_KERNEL_STEP : DPML_KERNEL_CORE, step_bytes(H, inner_cols * rows, 0.0));
-    // the edge strips hold the x layer: frame work
+    strips(s0, s1, s1, 0, false, whole ? DPML_KERNEL_STEP : DPML_KERNEL_CORE, step_bytes(H, inner_cols * rows, 0.0));
+    // the edge strips hold the x layer: frame work, both in one launch
     const double edge_cells = box - inner_cols * rows;
-    const double edge_bytes = step_bytes(H, edge_cells, box_aux);
-    const double left = 64.0 * s0 * rows;
-    strips(0, s0, true, DPML_KERNEL_FRAME, edge_cells > 0 ? edge_bytes * left / edge_cells : 0.0);
-    strips(s1, nstrips, true, DPML_KERNEL_FRAME, edge_cells > 0 ? edge_bytes * (edge_cells - left) / edge_cells : 0.0);
+    strips(0, nstrips, s0, s1 - s0, true, DPML_KERNEL_FRAME, step_bytes(H, edge_cells, box_aux));
     if (fork) {
         HIP_TRY(H, hipEventRecord(H->ev_join, H->side));
         HIP_TRY(H, hipStreamWaitEvent(H->stream, H->ev_join, 0));
@@ -1318,7 +1316,7 @@ int adjoint_impl(dpml *H, const void *resid, double *grad, void *grad_w)
         adj_waves = adj_tiles_x * ((core[3] - core[2] + kAdjRows - 1) / kAdjRows);
     }
     const dim3 mgrid((unsigned)round8((adj_waves + 3) / 4));
-    const dim3 fgrid((unsigned)round8((int)std::max<int64_t>(H->n_adj_frame, 0)));
+    const dim3 fgrid((unsigned)round8(4 * (int)std::max<int64_t>(H->n_adj_frame, 0)));   // a block per tile row
     for (int64_t seg = A.nck - 1; seg >= 0; --seg) {
         const int64_t t0 = seg * every, t1 = std::min(t0 + every, nsteps);
         // restore the checkpoint and recompute U^{t0} .. U^{t1-1} into the history
@@ -1404,7 +1402,7 @@ int adjoint_impl(dpml *H, const void *resid, double *grad, void *grad_w)
                     f.tiles = H->d_adj_frame;
                     f.ntiles = (int32_t)H->n_adj_frame;
                     for (int k = 0; k < 4; ++k) f.skip[k] = core[k];
-                    hipLaunchKernelGGL((dpmlk::k_adjoint_cell<T, 2>), fgrid, ablock, 0, fork ? H->side : H->stream, f);
+                    hipLaunchKernelGGL((dpmlk::k_adjoint_frame2d<T>), fgrid, ablock, 0, fork ? H->side : H->stream, f);
                 }
                 if (adj_waves > 0)
                     hipLaunchKernelGGL((dpmlk::k_adjoint_march2d<T, kAdjRows>), mgrid, ablock, 0, H->stream, q,

@@ -871,15 +871,17 @@ __global__ void __launch_bounds__(256) k_step_multi2d(const StepArgs<T> *__restr
 // the wave come from the L2 cache, where the neighbouring waves read them as
 // their own).  A block's 4 waves take 4 consecutive row groups.
 //
-// The kernel sweeps the strips tx0, tx0+1, ... of the box [y0c, y1c) x
-// [z0c, z1c) (its tiles counted from (tx0, y0c, z0c)) and carries the layer
+// The kernel sweeps the strips tx0, tx0+1, ... (with `gap` strips left out
+// from strip gap_at on) of the box [y0c, y1c) x [z0c, z1c) (its tiles
+// counted from (tx0, y0c, z0c)) and carries the layer
 // terms of the axes in AX only.  The library runs it without any layer
 // terms (AX = 0) on the strips where no damping term acts, with the x-layer
 // terms on the two edge strips, and takes the y/z layer slabs outside the
 // box with k_step_slabs3d: each kernel keeps only the code its cells need.
 // ---------------------------------------------------------------------------
 template <typename T, int RY, int AX>
-__global__ void __launch_bounds__(256) k_step_zmarch3d(StepArgs<T> p, int tx0, int y0c, int y1c, int z0c, int z1c)
+__global__ void __launch_bounds__(256) k_step_zmarch3d(StepArgs<T> p, int tx0, int gap_at, int gap, int y0c, int y1c,
+                                                       int z0c, int z1c)
 {
     const int tile = xcd_tile(blockIdx.x, gridDim.x);
     if (tile >= p.n_tiles) return;
@@ -893,7 +895,9 @@ __global__ void __launch_bounds__(256) k_step_zmarch3d(StepArgs<T> p, int tx0, i
     const int nx = p.nx, ny = p.ny, nz = p.nz;
     const int y0 = y0c + (ty * 4 + (int)(threadIdx.x >> 6)) * RY;
     if (y0 >= y1c) return;                                 // whole wave; no barriers below
-    const int x0 = (tx0 + tx) * 64, x = x0 + lane;
+    // strip tx0 + tx, skipping `gap` strips from strip gap_at on (both edge strips in one launch)
+    const int strip = tx0 + tx >= gap_at ? tx0 + tx + gap : tx0 + tx;
+    const int x0 = strip * 64, x = x0 + lane;
     const bool wx = p.ax[0].wall, wy = p.ax[1].wall, wz = p.ax[2].wall;
     const int64_t sxy = (int64_t)nx * ny;
     // each lane reads column x (wrapped; the ghost column of a wall reads 0), so
@@ -1203,29 +1207,13 @@ __device__ __forceinline__ T pq_at(const Axis<T> &A, int j, int64_t cbase, int64
     return A.phi[c] + A.psi[c];
 }
 
+// The transposed step at cell (x, y, z) for the shots bi0, bi0 + bstep, ...
+// (reverse mode of Eqs. (DiscretePML a-c)): writes a^n and the adjoint
+// auxiliaries of those shots and returns their c^2-gradient terms summed in
+// FP64 in shot order.
 template <typename T, int D>
-__global__ void __launch_bounds__(256) k_adjoint_cell(AdjArgs<T> p)
+__device__ __forceinline__ double adj_cell(const AdjArgs<T> &p, int x, int y, int z, int bi0, int bstep)
 {
-    // 1-D XCD-aware launch over 64 x 4 cell tiles (as the forward CELL kernel),
-    // either all tiles of the grid or those of a list (2D; cells of the skip
-    // box are then left to the marching kernel)
-    const int tile = xcd_tile(blockIdx.x, gridDim.x);
-    const int tiles_x = (p.nx + 63) / 64, tiles_y = (p.ny + 3) / 4;
-    int x, y, z = 0;
-    if (p.tiles) {
-        if (tile >= p.ntiles) return;
-        const TileRef t = p.tiles[tile];
-        x = t.tx * 64 + (int)(threadIdx.x % 64);
-        y = t.ty * 4 + (int)(threadIdx.x / 64);
-        if (x >= p.skip[0] && x < p.skip[1] && y >= p.skip[2] && y < p.skip[3]) return;
-    } else {
-        if (tile >= tiles_x * tiles_y * (D == 3 ? p.nz : 1)) return;
-        z = D == 3 ? tile / (tiles_x * tiles_y) : 0;
-        const int rem = tile - z * tiles_x * tiles_y;
-        x = (rem % tiles_x) * 64 + (int)(threadIdx.x % 64);
-        y = (rem / tiles_x) * 4 + (int)(threadIdx.x / 64);
-    }
-    if (x >= p.nx || y >= p.ny) return;
     const int nx = p.nx, ny = p.ny, nz = p.nz;
     const int64_t sy = nx, sz = (int64_t)nx * ny;
     const int64_t idx = (int64_t)z * sz + (int64_t)y * sy + x;
@@ -1263,7 +1251,7 @@ __global__ void __launch_bounds__(256) k_adjoint_cell(AdjArgs<T> p)
     }
     double gsum = 0.0;
 #pragma unroll 1
-    for (int bi = 0; bi < p.batch; ++bi) {
+    for (int bi = bi0; bi < p.batch; bi += bstep) {
         const int64_t bo = (int64_t)bi * p.bstride;
         const T *lam = p.lam + bo;
         const T *un = p.un + bo;
@@ -1315,7 +1303,49 @@ __global__ void __launch_bounds__(256) k_adjoint_cell(AdjArgs<T> p)
         p.lam_o[bo + idx] = v;
         gsum += (double)(p.dt2 * lc) * (double)lapu;
     }
-    p.grad[idx] += gsum;
+    return gsum;
+}
+
+template <typename T, int D>
+__global__ void __launch_bounds__(256) k_adjoint_cell(AdjArgs<T> p)
+{
+    // 1-D XCD-aware launch over 64 x 4 cell tiles (as the forward CELL kernel),
+    // one thread per cell looping over all shots
+    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+    const int tiles_x = (p.nx + 63) / 64, tiles_y = (p.ny + 3) / 4;
+    if (tile >= tiles_x * tiles_y * (D == 3 ? p.nz : 1)) return;
+    const int z = D == 3 ? tile / (tiles_x * tiles_y) : 0;
+    const int rem = tile - z * tiles_x * tiles_y;
+    const int x = (rem % tiles_x) * 64 + (int)(threadIdx.x % 64);
+    const int y = (rem / tiles_x) * 4 + (int)(threadIdx.x / 64);
+    if (x >= p.nx || y >= p.ny) return;
+    const double g = adj_cell<T, D>(p, x, y, z, 0, 1);
+    p.grad[((int64_t)z * p.ny + y) * p.nx + x] += g;
+}
+
+// The 2D frame of the adjoint (cells outside the marching core) over a list
+// of 64 x 4 tiles: a block takes one row of 64 cells of a tile, and its four
+// waves split the shots (wave w takes shots w, w+4, ...), so a frame cell's
+// shot loop is four times shorter.  The four FP64 partial gradients of a
+// cell are added in LDS in a fixed order (no atomics).
+template <typename T>
+__global__ void __launch_bounds__(256) k_adjoint_frame2d(AdjArgs<T> p)
+{
+    __shared__ double part[4][64];
+    const int b = xcd_tile(blockIdx.x, gridDim.x);
+    const int t = b >> 2, row = b & 3;
+    const int lane = (int)(threadIdx.x & 63), w = (int)(threadIdx.x >> 6);
+    bool ok = t < p.ntiles;
+    int x = 0, y = 0;
+    if (ok) {
+        const TileRef tl = p.tiles[t];
+        x = tl.tx * 64 + lane;
+        y = tl.ty * 4 + row;
+        ok = x < p.nx && y < p.ny && !(x >= p.skip[0] && x < p.skip[1] && y >= p.skip[2] && y < p.skip[3]);
+    }
+    part[w][lane] = ok ? adj_cell<T, 2>(p, x, y, 0, w, 4) : 0.0;
+    __syncthreads();
+    if (ok && w == 0) p.grad[(int64_t)y * p.nx + x] += ((part[0][lane] + part[1][lane]) + part[2][lane]) + part[3][lane];
 }
 
 // Load / store through a base pointer plus a 32-bit byte offset: with a
