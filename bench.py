@@ -438,7 +438,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2000)
     ap.add_argument("--warmup", type=int, default=50)
-    ap.add_argument("--cpu-steps", type=int, default=20)
+    ap.add_argument("--cpu-steps", type=int, default=160)   # ~10 s of the oracle on 16 host cores
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--dtypes", default="f32,f64")
     ap.add_argument("--variant", type=int, default=0)

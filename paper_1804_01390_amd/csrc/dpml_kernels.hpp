@@ -209,8 +209,7 @@ __device__ __forceinline__ T cell_update(const StepArgs<T> &p, int x, int y, int
     const int64_t nx = p.nx, ny = p.ny;
     if (!HOIST) {
         // Eq. (DiscretePML a): c^2 sum_a (U(i-e) - 2U + U(i+e))/h^2 + sum_a (...)/h
-        T lap = T(0);
-        lap += ((uxm - T(2) * uc) + uxp) * p.inv_h2;
+        T lap = ((uxm - T(2) * uc) + uxp) * p.inv_h2;
         lap += ((uym - T(2) * uc) + uyp) * p.inv_h2;
         if (D == 3) lap += ((uzm - T(2) * uc) + uzp) * p.inv_h2;
         const T c2 = p.c2 ? p.c2[idx] : p.c2_const;
@@ -250,8 +249,7 @@ __device__ __forceinline__ T cell_update(const StepArgs<T> &p, int x, int y, int
         Lz = layer_load<2>(p.ax[2], jz, nx, ny, x, y, z);
     }
     // Eq. (DiscretePML a): c^2 sum_a (U(i-e) - 2U + U(i+e))/h^2 + sum_a (...)/h
-    T lap = T(0);
-    lap += ((uxm - T(2) * uc) + uxp) * p.inv_h2;
+    T lap = ((uxm - T(2) * uc) + uxp) * p.inv_h2;
     lap += ((uym - T(2) * uc) + uyp) * p.inv_h2;
     if (D == 3) lap += ((uzm - T(2) * uc) + uzp) * p.inv_h2;
     T damp = T(0);
@@ -561,8 +559,7 @@ struct March2Ctx {
         for (int k = 0; k < VX; ++k) {
             const T uxm = k == 0 ? left : uc.v[k - 1];
             const T uxp = k == VX - 1 ? right : uc.v[k + 1];
-            T lap = T(0);
-            lap += ((uxm - T(2) * uc.v[k]) + uxp) * inv_h2;
+            T lap = ((uxm - T(2) * uc.v[k]) + uxp) * inv_h2;
             lap += ((um.v[k] - T(2) * uc.v[k]) + upr.v[k]) * inv_h2;
             const T cc = C2F ? c.v[k] : c2c;
             o.v[k] = (T(2) * uc.v[k] - old.v[k]) + dt2 * (cc * lap);
@@ -997,8 +994,7 @@ __global__ void __launch_bounds__(256) k_step_zmarch3d(StepArgs<T> p, int tx0, i
                 if constexpr (AX == 1) {
                     // cell_update's hoisted form with the prefetched x-layer inputs
                     const T c2 = p.c2 ? p.c2[idx] : p.c2_const;
-                    T lap = T(0);
-                    lap += ((uxm - T(2) * uc[q]) + uxp) * p.inv_h2;
+                    T lap = ((uxm - T(2) * uc[q]) + uxp) * p.inv_h2;
                     lap += ((uym - T(2) * uc[q]) + uyp) * p.inv_h2;
                     lap += ((um[q] - T(2) * uc[q]) + cur.upn[q]) * p.inv_h2;
                     T damp = T(0);
