@@ -105,10 +105,13 @@ def time_gpu(w, dtype_name, steps, warmup, variant=0, tile_rows=0):
 
 
 def roofline_from_timing(kernels, timed_steps):
-    """Roofline of the dominant step kernel (most time) from the library's
-    per-launch timing: its algorithmic bytes per launch over its mean launch
-    duration; also the whole path's algorithmic rate over all step kernels."""
-    name, k = max(kernels.items(), key=lambda kv: kv[1]["ms"])
+    """Roofline of the dominant step kernel from the library's per-launch
+    timing: its algorithmic bytes per launch over its mean launch duration.
+    The dominant kernel is the class that moves the most algorithmic bytes:
+    frame launches run on a second stream beside the core, so their event
+    durations include time spent sharing the GPU and are no measure of which
+    kernel carries the step."""
+    name, k = max(((n, v) for n, v in kernels.items() if v["launches"]), key=lambda kv: kv[1]["bytes"])
     ms = k["ms"] / k["launches"]
     bpl = k["bytes"] / k["launches"]
     achieved = bpl / (ms * 1e-3) / 1e9

@@ -488,6 +488,34 @@ __device__ __forceinline__ void cell2d_tile(const StepArgs<T> &p, int tx, int ty
 // evaluates the scheme in the operation order of cell_update (no damping
 // terms there), so results are bit-identical to single steps.
 // ---------------------------------------------------------------------------
+// Whole-wave shifts by one lane through DPP (a modifier on a VALU move, no
+// LDS round trip): lane i receives lane i-1's value (from_left) or lane
+// i+1's (from_right); the lane with no source keeps its own value.
+template <int CTRL>
+__device__ __forceinline__ int dpp_move(int v)
+{
+    return __builtin_amdgcn_update_dpp(v, v, CTRL, 0xf, 0xf, false);
+}
+
+template <int CTRL, typename T>
+__device__ __forceinline__ T dpp_shift(T v)
+{
+    if constexpr (sizeof(T) == 4) {
+        return __builtin_bit_cast(T, dpp_move<CTRL>(__builtin_bit_cast(int, v)));
+    } else {
+        const uint64_t b = __builtin_bit_cast(uint64_t, v);
+        const uint32_t lo = (uint32_t)dpp_move<CTRL>((int)(uint32_t)b);
+        const uint32_t hi = (uint32_t)dpp_move<CTRL>((int)(uint32_t)(b >> 32));
+        return __builtin_bit_cast(T, ((uint64_t)hi << 32) | lo);
+    }
+}
+
+template <typename T>
+__device__ __forceinline__ T from_left(T v) { return dpp_shift<0x138>(v); }    // wave_shr:1
+
+template <typename T>
+__device__ __forceinline__ T from_right(T v) { return dpp_shift<0x130>(v); }   // wave_shl:1
+
 template <typename T, int VX, bool C2F>
 struct March2Ctx {
     using R = Row<T, VX>;
@@ -552,8 +580,8 @@ struct March2Ctx {
     // with every damping term zero), in cell_update's operation order
     __device__ __forceinline__ R level(const R &um, const R &uc, const R &upr, const R &old, const R &c) const
     {
-        const T left = __shfl_up(uc.v[VX - 1], 1);
-        const T right = __shfl_down(uc.v[0], 1);
+        const T left = from_left(uc.v[VX - 1]);
+        const T right = from_right(uc.v[0]);
         R o;
 #pragma unroll
         for (int k = 0; k < VX; ++k) {
