@@ -132,8 +132,6 @@ struct dpml {
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     dpmlk::TileRef *d_adj_frame = nullptr;  // 2D adjoint: tiles outside the marching core
     int64_t n_adj_frame = -1;               // -1: not built yet
-    dpmlk::Tile3 *d_slabs = nullptr;  // 3D marching variants: tiles of the y/z layer slabs
-    int64_t n_slabs = -1;             // -1: not built yet
     // sources
     int64_t ns = 0, nt_src = 0;
     int64_t *d_src_cells = nullptr, *d_src_order = nullptr;
@@ -315,30 +313,6 @@ void march_box3d(const Layout &L, int b[4])
     }
 }
 
-// Tiles (64 x 4 cells of one plane) covering everything outside the box.
-int ensure_slabs(dpml *H)
-{
-    if (H->n_slabs >= 0) return DPML_OK;
-    const Layout &L = H->L;
-    int b[4];
-    march_box3d(L, b);
-    const int tx = (int)((L.N[0] + 63) / 64), ty = (int)((L.N[1] + 3) / 4);
-    std::vector<dpmlk::Tile3> t;
-    for (int z = 0; z < (int)L.N[2]; ++z) {
-        const bool zin = z >= b[2] && z < b[3];
-        for (int y = 0; y < ty; ++y) {
-            const int ya = 4 * y, yb = std::min<int>(ya + 4, (int)L.N[1]);
-            if (zin && ya >= b[0] && yb <= b[1]) continue;
-            for (int x = 0; x < tx; ++x) t.push_back({x, y, z, 0});
-        }
-    }
-    H->n_slabs = (int64_t)t.size();
-    if (t.empty()) return DPML_OK;
-    HIP_TRY(H, hipMalloc((void **)&H->d_slabs, t.size() * sizeof(dpmlk::Tile3)));
-    HIP_TRY(H, hipMemcpy(H->d_slabs, t.data(), t.size() * sizeof(dpmlk::Tile3), hipMemcpyHostToDevice));
-    return DPML_OK;
-}
-
 // The second stream (and its fork/join events) on which the layer parts of a
 // split step run beside the main kernel.
 int ensure_side(dpml *H)
@@ -349,85 +323,140 @@ int ensure_side(dpml *H)
     return DPML_OK;
 }
 
-// 3D marching launch: the strips of the box [lo+1, lo+n) in y and z that no
-// x damping term reaches, without any layer code; the other strips with the
-// x-layer terms; the y/z layer slabs one thread per cell.  The layer parts
-// (slabs and edge strips) run on the side stream while the layer-free
-// strips run on the handle's stream; they write disjoint cells and the
-// step ends with the handle's stream waiting for the side stream.
+// Algorithmic layer axis-cells of a 3D box: per axis, the weight of each band
+// slot in the box's range along it (a half word pair for each of Phi and Psi
+// the slot holds, so a whole band counts M) times the box's other extents.
+double box_aux(const Layout &L, const dpmlk::Box3 &bx)
+{
+    const int r0[3] = {bx.xs, bx.ys, bx.zs}, r1[3] = {bx.xe, bx.ye, bx.ze};
+    double aux = 0;
+    for (int a = 0; a < 3; ++a) {
+        if (L.M[a] == 0) continue;
+        const int64_t b = L.lo[a] + L.n[a], N = L.N[a];
+        double w = 0;
+        for (int i = r0[a]; i < r1[a]; ++i) {
+            const int64_t ic = i % N;
+            const int64_t j = ic >= b ? ic - b : ic + (N - b);
+            if (j <= L.M[a]) w += 0.5 * ((j < L.M[a]) + (j > 0));
+        }
+        double other = 1;
+        for (int c = 0; c < 3; ++c)
+            if (c != a) other *= (double)(r1[c] - r0[c]);
+        aux += w * other;
+    }
+    return aux;
+}
+
+double box_cells(const dpmlk::Box3 &bx)
+{
+    return (double)(bx.xe - bx.xs) * (double)(bx.ye - bx.ys) * (double)(bx.ze - bx.zs);
+}
+
+// One thread-per-cell launch over a box with the layer code of the axes in
+// `ax` (x and z, or all).
+template <typename T>
+int launch_box(dpml *H, dpmlk::StepArgs<T> p, const dpmlk::Box3 &bx, int ax, hipStream_t st, int kind)
+{
+    if (bx.xe <= bx.xs || bx.ye <= bx.ys || bx.ze <= bx.zs) return DPML_OK;
+    p.tiles_x = (bx.xe - bx.xs + 63) / 64;
+    p.tiles_y = (bx.ye - bx.ys + 3) / 4;
+    p.n_tiles = p.tiles_x * p.tiles_y * (bx.ze - bx.zs);
+    const int slot = H->timing ? timed_begin(H, kind, step_bytes(H, box_cells(bx), box_aux(H->L, bx)), st) : -1;
+    const dim3 grid((unsigned)round8(p.n_tiles), (unsigned)H->L.batch), block(256);
+    if (ax == 5) hipLaunchKernelGGL((dpmlk::k_step_box3d<T, 5>), grid, block, 0, st, p, bx);
+    else hipLaunchKernelGGL((dpmlk::k_step_box3d<T, 7>), grid, block, 0, st, p, bx);
+    if (slot >= 0) timed_end(H, slot, st);
+    return DPML_OK;
+}
+
+// One z-march launch over a box with the layer code of the axes in `ax`
+// (none or x alone), `ry` register rows per wave and `zchunk` planes per
+// tile.
+template <typename T>
+int launch_zmarch(dpml *H, dpmlk::StepArgs<T> p, const dpmlk::Box3 &bx, int ry, int ax, int zchunk,
+                  hipStream_t st, int kind)
+{
+    if (bx.xe <= bx.xs || bx.ye <= bx.ys || bx.ze <= bx.zs) return DPML_OK;
+    p.tile_rows = zchunk;
+    p.tiles_x = (bx.xe - bx.xs + 63) / 64;
+    p.tiles_y = (bx.ye - bx.ys + 4 * ry - 1) / (4 * ry);
+    const int tz = (bx.ze - bx.zs + zchunk - 1) / zchunk;
+    p.n_tiles = p.tiles_x * p.tiles_y * tz;
+    const int slot = H->timing ? timed_begin(H, kind, step_bytes(H, box_cells(bx), box_aux(H->L, bx)), st) : -1;
+    const dim3 grid((unsigned)round8(p.n_tiles), (unsigned)H->L.batch), block(256);
+#define DPML_ZMARCH(RY_, AX_) hipLaunchKernelGGL((dpmlk::k_step_zmarch3d<T, RY_, AX_>), grid, block, 0, st, p, bx)
+    if (ry == 4) {
+        if (ax == 0) DPML_ZMARCH(4, 0);
+        else DPML_ZMARCH(4, 1);
+    } else {
+        if (ax == 0) DPML_ZMARCH(2, 0);
+        else DPML_ZMARCH(2, 1);
+    }
+#undef DPML_ZMARCH
+    if (slot >= 0) timed_end(H, slot, st);
+    return DPML_OK;
+}
+
+// 3D marching step as boxes:
+//   core    x strips [64 s0, 64 s1) that no x damping term reaches, rows and
+//           planes [lo+1, lo+n) (the box of march_box3d): no layer code;
+//   x band  the remaining columns [64 s1, 64 s0 + N) of the same rows and
+//           planes (one box across the periodic wrap): x-layer code;
+//   y band  every column and plane of the rows [lo+n, lo+n+M] (wrapped):
+//           all layer code, one thread per cell;
+//   z band  every column of the box's rows, planes [lo+n, lo+n+M]: x and z
+//           layer code, one thread per cell.
+// The boxes partition the grid.  The layer boxes run on the side stream
+// while the core runs on the handle's stream; they write disjoint cells and
+// the step ends with the handle's stream waiting for the side stream.
 template <typename T>
 int launch_march3d(dpml *H, dpmlk::StepArgs<T> p, int ry)
 {
     const Layout &L = H->L;
-    const unsigned B = (unsigned)L.batch;
     int b[4];
     march_box3d(L, b);
-    const bool split = L.M[1] > 0 || L.M[2] > 0;
-    if (split) {
-        int rc = ensure_slabs(H);
-        if (rc) return rc;
-    }
-    const bool fork = split || L.M[0] > 0;
-    if (fork) {
+    const int NX = (int)L.N[0], NY = (int)L.N[1], NZ = (int)L.N[2];
+    const bool layers = L.M[0] > 0 || L.M[1] > 0 || L.M[2] > 0;
+    if (layers) {
         int rc = ensure_side(H);
         if (rc) return rc;
         HIP_TRY(H, hipEventRecord(H->ev_fork, H->stream));
         HIP_TRY(H, hipStreamWaitEvent(H->side, H->ev_fork, 0));
     }
-    hipStream_t ls = fork ? H->side : H->stream;      // stream of the layer parts
-    // strips of 64 columns [64 t, 64 t + 64) free of x damping terms: inside [lo+1, lo+n)
-    const int nstrips = (int)((L.N[0] + 63) / 64);
-    int s0 = 0, s1 = nstrips;
+    hipStream_t ls = layers ? H->side : H->stream;     // stream of the layer parts
+    const int nstrips = (NX + 63) / 64;
+    int x0 = 0, x1 = NX;
     if (L.M[0] > 0) {
-        s0 = (L.lo[0] + 1 + 63) / 64;
-        s1 = (int)((L.lo[0] + L.n[0]) / 64);
+        const int s0 = (L.lo[0] + 1 + 63) / 64;
+        int s1 = (int)((L.lo[0] + L.n[0]) / 64);
         if (s1 < s0) s1 = s0;
+        x0 = 64 * s0;
+        x1 = std::min(64 * s1, NX);
     }
-    p.tile_rows = H->tile_rows > 0 ? H->tile_rows : 32;
-    p.tiles_y = (b[1] - b[0] + 4 * ry - 1) / (4 * ry);
-    const double rows = (double)(b[1] - b[0]) * (double)(b[3] - b[2]);
-    const double inner_cols = 64.0 * (s1 - s0);
-    const double box = (double)L.N[0] * rows;
-    const double box_aux = (double)L.M[0] * rows;
-    const dim3 block(256);
-    if (split && H->n_slabs > 0) {
-        const int slot = timed_begin(H, DPML_KERNEL_FRAME,
-                                     step_bytes(H, (double)L.ncell - box, aux_cells(L) - box_aux), ls);
-        const dim3 g2((unsigned)round8((int)H->n_slabs), B);
-        hipLaunchKernelGGL((dpmlk::k_step_slabs3d<T>), g2, block, 0, ls, p, H->d_slabs, (int)H->n_slabs,
-                           b[0], b[1], b[2], b[3]);
-        timed_end(H, slot, ls);
+    (void)nstrips;
+    const int zc = H->tile_rows > 0 ? H->tile_rows : 32;
+    const int zl = std::max(8, zc / 4);               // layer boxes: few tiles, shorter chunks
+    int rc;
+    if (L.M[1] > 0) {
+        const int yb = L.lo[1] + (int)L.n[1];
+        rc = launch_box<T>(H, p, dpmlk::Box3{0, NX, yb, yb + L.M[1] + 1, 0, NZ}, 7, ls, DPML_KERNEL_FRAME);
+        if (rc) return rc;
     }
-    // launch the strips [t0, t1) with or without the x-layer code; the two
-    // edge strips alone are few tiles, so they march shorter chunks
-    // strips [t0, t1) except [gap_at, gap_at + gap)
-    auto strips = [&](int t0, int t1, int gap_at, int gap, bool layer, int kind, double bytes) {
-        if (t1 - t0 - gap <= 0 || p.tiles_y <= 0) return;
-        dpmlk::StepArgs<T> q = p;
-        if (layer) q.tile_rows = std::max(8, p.tile_rows / 4);
-        const int tz = (b[3] - b[2] + q.tile_rows - 1) / q.tile_rows;
-        if (tz <= 0) return;
-        q.tiles_x = t1 - t0 - gap;
-        q.n_tiles = q.tiles_x * q.tiles_y * tz;
-        hipStream_t st = layer ? ls : H->stream;
-        const int slot = timed_begin(H, kind, bytes, st);
-        const dim3 grid((unsigned)round8(q.n_tiles), B);
-        if (ry == 4 && layer)
-            hipLaunchKernelGGL((dpmlk::k_step_zmarch3d<T, 4, 1>), grid, block, 0, st, q, t0, gap_at, gap, b[0], b[1], b[2], b[3]);
-        else if (ry == 4)
-            hipLaunchKernelGGL((dpmlk::k_step_zmarch3d<T, 4, 0>), grid, block, 0, st, q, t0, gap_at, gap, b[0], b[1], b[2], b[3]);
-        else if (layer)
-            hipLaunchKernelGGL((dpmlk::k_step_zmarch3d<T, 2, 1>), grid, block, 0, st, q, t0, gap_at, gap, b[0], b[1], b[2], b[3]);
-        else
-            hipLaunchKernelGGL((dpmlk::k_step_zmarch3d<T, 2, 0>), grid, block, 0, st, q, t0, gap_at, gap, b[0], b[1], b[2], b[3]);
-        timed_end(H, slot, st);
-    };
-    const bool whole = !split && s0 == 0 && s1 == nstrips;
-    strips(s0, s1, s1, 0, false, whole ? DPML_KERNEL_STEP : DPML_KERNEL_CORE, step_bytes(H, inner_cols * rows, 0.0));
-    // the edge strips hold the x layer: frame work, both in one launch
-    const double edge_cells = box - inner_cols * rows;
-    strips(0, nstrips, s0, s1 - s0, true, DPML_KERNEL_FRAME, step_bytes(H, edge_cells, box_aux));
-    if (fork) {
+    if (L.M[2] > 0) {
+        const int zb = L.lo[2] + (int)L.n[2];
+        rc = launch_box<T>(H, p, dpmlk::Box3{0, NX, b[0], b[1], zb, zb + L.M[2] + 1}, 5, ls, DPML_KERNEL_FRAME);
+        if (rc) return rc;
+    }
+    const bool whole = !layers;
+    rc = launch_zmarch<T>(H, p, dpmlk::Box3{x0, x1, b[0], b[1], b[2], b[3]}, ry, 0, zc, H->stream,
+                          whole ? DPML_KERNEL_STEP : DPML_KERNEL_CORE);
+    if (rc) return rc;
+    if (L.M[0] > 0) {
+        rc = launch_zmarch<T>(H, p, dpmlk::Box3{x1, x0 + NX, b[0], b[1], b[2], b[3]}, ry, 1, zl, ls,
+                              DPML_KERNEL_FRAME);
+        if (rc) return rc;
+    }
+    if (layers) {
         HIP_TRY(H, hipEventRecord(H->ev_join, H->side));
         HIP_TRY(H, hipStreamWaitEvent(H->stream, H->ev_join, 0));
     }
@@ -1156,7 +1185,6 @@ void dpml_destroy(dpml_t *H)
     if (H->ev_fork) (void)hipEventDestroy(H->ev_fork);
     if (H->ev_join) (void)hipEventDestroy(H->ev_join);
     if (H->side) (void)hipStreamDestroy(H->side);
-    if (H->d_slabs) (void)hipFree(H->d_slabs);
     if (H->d_adj_frame) (void)hipFree(H->d_adj_frame);
     if (H->d_rec_sorted) (void)hipFree(H->d_rec_sorted);
     if (H->d_rec_order) (void)hipFree(H->d_rec_order);
@@ -1977,12 +2005,6 @@ int step_graph_impl(dpml *H, int64_t nsteps)
         view.side = H->side;
         view.ev_fork = H->ev_fork;
         view.ev_join = H->ev_join;
-        if (H->L.ndim == 3 && (H->L.M[1] > 0 || H->L.M[2] > 0)) {   // likewise the slab table
-            int rcs = ensure_slabs(H);
-            if (rcs) return rcs;
-            view.d_slabs = H->d_slabs;
-            view.n_slabs = H->n_slabs;
-        }
         HIP_TRY(H, hipStreamBeginCapture(H->cap, hipStreamCaptureModeRelaxed));
         int rc = step_impl<T>(&view, nsteps);
         hipGraph_t g = nullptr;
@@ -1993,7 +2015,6 @@ int step_graph_impl(dpml *H, int64_t nsteps)
             for (int sh = 0; sh < 3; ++sh) view.d_frame[lv][sh] = nullptr;
         view.side = nullptr;
         view.ev_fork = view.ev_join = nullptr;
-        view.d_slabs = nullptr;
         H->graph_end_unow = view.u_now;
         H->graph_end_uold = view.u_old;
         H->graph_end_cur = view.cur;

@@ -896,17 +896,22 @@ __global__ void __launch_bounds__(256) k_step_multi2d(const StepArgs<T> *__restr
 // the wave come from the L2 cache, where the neighbouring waves read them as
 // their own).  A block's 4 waves take 4 consecutive row groups.
 //
-// The kernel sweeps the strips tx0, tx0+1, ... (with `gap` strips left out
-// from strip gap_at on) of the box [y0c, y1c) x [z0c, z1c) (its tiles
-// counted from (tx0, y0c, z0c)) and carries the layer
-// terms of the axes in AX only.  The library runs it without any layer
-// terms (AX = 0) on the strips where no damping term acts, with the x-layer
-// terms on the two edge strips, and takes the y/z layer slabs outside the
-// box with k_step_slabs3d: each kernel keeps only the code its cells need.
+// The kernel updates the cells of one box: columns [xs, xe), rows [ys, ye)
+// and planes [zs, ze), each start inside the array and each extent at most
+// the axis length; indices past the array end continue at its start.  That
+// wrap is the periodic one, so the two halves of a layer band are one box;
+// with reflecting walls the neighbours across a wall read zero instead.
+// AX is the set of axes whose layer terms the box's cells may meet: none on
+// the layer-free core, x on the x-band strip (its layer inputs fetched one
+// plane ahead).  The library splits a step into such boxes so that each
+// kernel keeps only the code its cells need.
 // ---------------------------------------------------------------------------
+struct Box3 {
+    int32_t xs, xe, ys, ye, zs, ze;
+};
+
 template <typename T, int RY, int AX>
-__global__ void __launch_bounds__(256) k_step_zmarch3d(StepArgs<T> p, int tx0, int gap_at, int gap, int y0c, int y1c,
-                                                       int z0c, int z1c)
+__global__ void __launch_bounds__(256) k_step_zmarch3d(StepArgs<T> p, Box3 bx)
 {
     const int tile = xcd_tile(blockIdx.x, gridDim.x);
     if (tile >= p.n_tiles) return;
@@ -918,58 +923,39 @@ __global__ void __launch_bounds__(256) k_step_zmarch3d(StepArgs<T> p, int tx0, i
     const int tx = rem - ty * p.tiles_x;
     const int lane = (int)(threadIdx.x & 63);
     const int nx = p.nx, ny = p.ny, nz = p.nz;
-    const int y0 = y0c + (ty * 4 + (int)(threadIdx.x >> 6)) * RY;
-    if (y0 >= y1c) return;                                 // whole wave; no barriers below
-    // strip tx0 + tx, skipping `gap` strips from strip gap_at on (both edge strips in one launch)
-    const int strip = tx0 + tx >= gap_at ? tx0 + tx + gap : tx0 + tx;
-    const int x0 = strip * 64, x = x0 + lane;
+    const int y0 = bx.ys + (ty * 4 + (int)(threadIdx.x >> 6)) * RY;
+    if (y0 >= bx.ye) return;                               // whole wave; no barriers below
     const bool wx = p.ax[0].wall, wy = p.ax[1].wall, wz = p.ax[2].wall;
     const int64_t sxy = (int64_t)nx * ny;
-    // each lane reads column x (wrapped; the ghost column of a wall reads 0), so
-    // the lane right of the last real column supplies that column's neighbour
-    const bool xin = x < nx;
-    const bool xzero = x >= nx && (wx || x - nx >= nx);
-    const int xc = xin ? x : (x - nx < nx ? x - nx : 0);
+    // lane column x (unwrapped) and the array column it reads; the lane just
+    // past the box's last column still reads, as that column's neighbour
+    const int x0 = bx.xs + tx * 64, x = x0 + lane;
+    const bool act = x < bx.xe;
+    const bool need = x <= bx.xe;
+    const int xc = x % nx;
     // lanes 0 and 63 also read the column just outside the strip
-    int xe = 0;
-    bool ezero = false;
-    if (lane == 0) {
-        xe = x0 == 0 ? nx - 1 : x0 - 1;
-        ezero = x0 == 0 && wx;
-    } else if (lane == 63) {
-        const int xr = x0 + 64;
-        xe = xr < nx ? xr : 0;
-        ezero = xr > nx || (xr == nx && wx);
-    }
-    // register rows q = 0..RY-1 and the halo rows -1, RY, each as a row index
-    // into the plane, or -1 for a zero row (past a wall or beyond the grid)
-    auto row_of = [&](int yy) -> int {
-        if (yy < 0) return wy ? -1 : yy + ny;
-        if (yy >= ny) return (wy || yy - ny >= ny) ? -1 : yy - ny;
-        return yy;
-    };
+    int xo = 0;
+    if (lane == 0) xo = x0 == 0 ? nx - 1 : (x0 - 1) % nx;
+    else if (lane == 63) xo = (x0 + 64) % nx;
+    const bool edge = (lane == 0 || lane == 63) && act;
+    // walls: neighbours across the wall are zero (the ghost cells)
+    const bool x_lo_wall = wx && xc == 0, x_hi_wall = wx && xc == nx - 1;
+    // register rows q = 0..RY-1 and the halo rows above and below, as array rows
     int ry[RY];
 #pragma unroll
-    for (int q = 0; q < RY; ++q) ry[q] = row_of(y0 + q);
-    const int rlo = row_of(y0 - 1), rhi = row_of(y0 + RY);
-    auto plane_of = [&](int zz) -> int {
-        if (zz < 0) return wz ? -1 : zz + nz;
-        if (zz >= nz) return wz ? -1 : zz - nz;
-        return zz;
-    };
+    for (int q = 0; q < RY; ++q) ry[q] = (y0 + q) % ny;
+    const int rlo = y0 == 0 ? ny - 1 : (y0 - 1) % ny, rhi = (y0 + RY) % ny;
     const T *u = p.u;
-    auto ld = [&](int pz, int r) -> T {
-        return (pz < 0 || r < 0 || xzero) ? T(0) : u[(int64_t)pz * sxy + (int64_t)r * nx + xc];
-    };
-    const int z0 = z0c + tz * p.tile_rows;
-    const int z1 = min(z0 + p.tile_rows, z1c);
+    auto ld = [&](int pz, int r) -> T { return need ? u[(int64_t)pz * sxy + (int64_t)r * nx + xc] : T(0); };
+    const int z0 = bx.zs + tz * p.tile_rows;
+    const int z1 = min(z0 + p.tile_rows, bx.ze);
     T um[RY], uc[RY];
     {
-        const int pm = plane_of(z0 - 1);
+        const int zc = z0 % nz, pm = zc == 0 ? nz - 1 : zc - 1;
 #pragma unroll
         for (int q = 0; q < RY; ++q) {
             um[q] = ld(pm, ry[q]);
-            uc[q] = ld(z0, ry[q]);
+            uc[q] = ld(zc, ry[q]);
         }
     }
     T *out = p.uout ? p.uout : p.uo;
@@ -977,61 +963,69 @@ __global__ void __launch_bounds__(256) k_step_zmarch3d(StepArgs<T> p, int tx0, i
     // of plane z, the strip-edge columns and the halo rows of plane z.  They
     // are issued one plane ahead, so a wave computes plane z while the
     // loads of plane z+1 are in flight.
-    // With the x-layer terms (AX = 1) the layer inputs of the plane (Phi_x,
-    // Psi_x around the cell's band slot) are fetched one plane ahead too.
+    // With the x-layer terms alone (AX = 1) the layer inputs of the plane
+    // (Phi_x, Psi_x around the cell's band slot) are fetched one plane ahead too.
     struct Fetch {
         T upn[RY], old[RY], edge[RY], hlo, hhi;
         LayerIn<T> lx[AX == 1 ? RY : 1];
     };
-    const int jx = (AX == 1 && p.ax[0].M > 0 && xin) ? band_coord(p.ax[0], x) : (1 << 30);
+    const int jx = (AX == 1 && p.ax[0].M > 0 && act) ? band_coord(p.ax[0], xc) : (1 << 30);
     auto fetch = [&](int z, Fetch &f) {
-        const int pz = plane_of(z + 1);
-        const int64_t plane = (int64_t)z * sxy;
+        const int zc = z % nz;
+        const int pz = zc == nz - 1 ? 0 : zc + 1;
+        const int64_t plane = (int64_t)zc * sxy;
 #pragma unroll
         for (int q = 0; q < RY; ++q) {
+            const bool row = y0 + q < bx.ye;
             f.upn[q] = ld(pz, ry[q]);
-            f.old[q] = (xin && y0 + q < y1c) ? p.uo[plane + (int64_t)(y0 + q) * nx + x] : T(0);
-            f.edge[q] = T(0);
-            if ((lane == 0 || lane == 63) && ry[q] >= 0 && !ezero) f.edge[q] = u[plane + (int64_t)ry[q] * nx + xe];
+            f.old[q] = (act && row) ? p.uo[plane + (int64_t)ry[q] * nx + xc] : T(0);
+            f.edge[q] = (edge && row) ? u[plane + (int64_t)ry[q] * nx + xo] : T(0);
             if constexpr (AX == 1) {
                 f.lx[q].on = false;
-                if (y0 + q < y1c && jx <= p.ax[0].M) f.lx[q] = layer_load<0>(p.ax[0], jx, nx, ny, x, y0 + q, z);
+                if (row && jx <= p.ax[0].M) f.lx[q] = layer_load<0>(p.ax[0], jx, nx, ny, xc, ry[q], zc);
             }
         }
-        f.hlo = ld(z, rlo);
-        f.hhi = ld(z, rhi);
+        f.hlo = ld(zc, rlo);
+        f.hhi = ld(zc, rhi);
     };
     Fetch cur;
     if (z0 < z1) fetch(z0, cur);
     for (int z = z0; z < z1; ++z) {
         Fetch nxt;
         if (z + 1 < z1) fetch(z + 1, nxt);
-        const int64_t plane = (int64_t)z * sxy;
+        const int zc = z % nz;
+        const int64_t plane = (int64_t)zc * sxy;
+        const bool z_lo_wall = wz && zc == 0, z_hi_wall = wz && zc == nz - 1;
 #pragma unroll
         for (int q = 0; q < RY; ++q) {
             T uxm = __shfl_up(uc[q], 1);
             T uxp = __shfl_down(uc[q], 1);
             if (lane == 0) uxm = cur.edge[q];
             if (lane == 63) uxp = cur.edge[q];
-            const T uym = q == 0 ? cur.hlo : uc[q - 1];
-            const T uyp = q == RY - 1 ? cur.hhi : uc[q + 1];
-            const int y = y0 + q;
-            if (xin && y < y1c) {
-                const int64_t idx = plane + (int64_t)y * nx + x;
+            if (x_lo_wall) uxm = T(0);
+            if (x_hi_wall) uxp = T(0);
+            T uym = q == 0 ? cur.hlo : uc[q - 1];
+            T uyp = q == RY - 1 ? cur.hhi : uc[q + 1];
+            if (wy && ry[q] == 0) uym = T(0);
+            if (wy && ry[q] == ny - 1) uyp = T(0);
+            const T uzm = z_lo_wall ? T(0) : um[q];
+            const T uzp = z_hi_wall ? T(0) : cur.upn[q];
+            if (act && y0 + q < bx.ye) {
+                const int64_t idx = plane + (int64_t)ry[q] * nx + xc;
                 T r;
                 if constexpr (AX == 1) {
                     // cell_update's hoisted form with the prefetched x-layer inputs
                     const T c2 = p.c2 ? p.c2[idx] : p.c2_const;
                     T lap = ((uxm - T(2) * uc[q]) + uxp) * p.inv_h2;
                     lap += ((uym - T(2) * uc[q]) + uyp) * p.inv_h2;
-                    lap += ((um[q] - T(2) * uc[q]) + cur.upn[q]) * p.inv_h2;
+                    lap += ((uzm - T(2) * uc[q]) + uzp) * p.inv_h2;
                     T damp = T(0);
                     if (cur.lx[q].on) damp += layer_finish(p.ax[0], cur.lx[q], jx, uxm, uxp, p.dt, p.inv_2h) * p.inv_h;
                     const T rhs = c2 * lap + damp;
                     r = (T(2) * uc[q] - cur.old[q]) + p.dt2 * rhs;
                 } else {
-                    r = cell_update<T, 3, AX, (AX != 0)>(p, x, y, z, idx, uc[q], uxm, uxp, uym, uyp, um[q],
-                                                         cur.upn[q], cur.old[q]);
+                    r = cell_update<T, 3, AX, (AX != 0)>(p, xc, ry[q], zc, idx, uc[q], uxm, uxp, uym, uyp, uzm,
+                                                         uzp, cur.old[q]);
                 }
                 out[idx] = r;
                 if (p.hist) p.hist[idx] = r;
@@ -1046,41 +1040,40 @@ __global__ void __launch_bounds__(256) k_step_zmarch3d(StepArgs<T> p, int tx0, i
     }
 }
 
-// The slabs of a 3D step outside the marching box [y0c, y1c) x [z0c, z1c):
-// one thread per cell over a list of 64 x 4 tiles (tx, ty, z) that covers
-// them, leaving the box's cells alone.
-struct Tile3 {
-    int32_t tx, ty, z, pad;
-};
-
-template <typename T>
-__global__ void __launch_bounds__(256) k_step_slabs3d(StepArgs<T> p, const Tile3 *__restrict__ tiles, int ntiles,
-                                                      int y0c, int y1c, int z0c, int z1c)
+// The same box update one thread per cell (64 x 4 cells of a plane per
+// block): for boxes whose cells mostly carry layer terms, where many waves in
+// flight hide the latency of the layer loads better than a plane march.
+template <typename T, int AX>
+__global__ void __launch_bounds__(256) k_step_box3d(StepArgs<T> p, Box3 bx)
 {
-    const int t = xcd_tile(blockIdx.x, gridDim.x);
-    if (t >= ntiles) return;
+    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+    if (tile >= p.n_tiles) return;
     select_member(p, (int)blockIdx.y);
-    const Tile3 tl = tiles[t];
-    const int x = tl.tx * 64 + (int)(threadIdx.x % 64);
-    const int y = tl.ty * 4 + (int)(threadIdx.x / 64);
-    const int z = tl.z;
-    if (x >= p.nx || y >= p.ny) return;
-    if (y >= y0c && y < y1c && z >= z0c && z < z1c) return;
-    const int64_t nx = p.nx, ny = p.ny;
-    const int64_t plane = (int64_t)z * ny * nx;
+    const int per_plane = p.tiles_x * p.tiles_y;
+    const int tz = tile / per_plane;
+    const int rem = tile - tz * per_plane;
+    const int ty = rem / p.tiles_x;
+    const int tx = rem - ty * p.tiles_x;
+    const int xu = bx.xs + tx * 64 + (int)(threadIdx.x & 63);
+    const int yu = bx.ys + ty * 4 + (int)(threadIdx.x >> 6);
+    if (xu >= bx.xe || yu >= bx.ye) return;
+    const int nx = p.nx, ny = p.ny, nz = p.nz;
+    const int x = xu % nx, y = yu % ny, z = (bx.zs + tz) % nz;
+    const int64_t sxy = (int64_t)nx * ny;
+    const int64_t plane = (int64_t)z * sxy;
     const int64_t row = plane + (int64_t)y * nx;
     const int64_t idx = row + x;
     const T *u = p.u;
-    const int xm = wrap_dec(x, p.nx), xp = wrap_inc(x, p.nx);
-    const int ym = wrap_dec(y, p.ny), yp = wrap_inc(y, p.ny);
-    const int zm = wrap_dec(z, p.nz), zp = wrap_inc(z, p.nz);
-    const T uzm = (p.ax[2].wall && z == 0) ? T(0) : u[((int64_t)zm * ny + y) * nx + x];
-    const T uzp = (p.ax[2].wall && z == p.nz - 1) ? T(0) : u[((int64_t)zp * ny + y) * nx + x];
+    const int xm = wrap_dec(x, nx), xp = wrap_inc(x, nx);
+    const int ym = wrap_dec(y, ny), yp = wrap_inc(y, ny);
+    const int zm = wrap_dec(z, nz), zp = wrap_inc(z, nz);
+    const T uzm = (p.ax[2].wall && z == 0) ? T(0) : u[(int64_t)zm * sxy + (int64_t)y * nx + x];
+    const T uzp = (p.ax[2].wall && z == nz - 1) ? T(0) : u[(int64_t)zp * sxy + (int64_t)y * nx + x];
     const T uxm = (p.ax[0].wall && x == 0) ? T(0) : u[row + xm];
-    const T uxp = (p.ax[0].wall && x == p.nx - 1) ? T(0) : u[row + xp];
+    const T uxp = (p.ax[0].wall && x == nx - 1) ? T(0) : u[row + xp];
     const T uym = (p.ax[1].wall && y == 0) ? T(0) : u[plane + (int64_t)ym * nx + x];
-    const T uyp = (p.ax[1].wall && y == p.ny - 1) ? T(0) : u[plane + (int64_t)yp * nx + x];
-    const T r = cell_update<T, 3, 7, true>(p, x, y, z, idx, u[idx], uxm, uxp, uym, uyp, uzm, uzp, p.uo[idx]);
+    const T uyp = (p.ax[1].wall && y == ny - 1) ? T(0) : u[plane + (int64_t)yp * nx + x];
+    const T r = cell_update<T, 3, AX, true>(p, x, y, z, idx, u[idx], uxm, uxp, uym, uyp, uzm, uzp, p.uo[idx]);
     (p.uout ? p.uout : p.uo)[idx] = r;
     if (p.hist) p.hist[idx] = r;
 }
