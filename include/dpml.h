@@ -95,13 +95,22 @@ extern "C" {
                                   2 words per cell per step; tile_rows: rows per
                                   wave in bits 0-11 (0 = 8), rows whose loads are
                                   issued together in bits 12-15 (1, 2 or 4; 0 = 2)),
-                                  the frame holding the layer in single steps;
-                                  otherwise as CELL                                   */
-#define DPML_VARIANT_THREESTEP 5 /* as TWOSTEP with three steps per pass over a core
-                                  one cell smaller (4 words per cell per three steps:
-                                  U^{n+1} is stored on the core's boundary ring only;
-                                  tile_rows as for TWOSTEP); a remaining pair takes
-                                  the two-step pass                                   */
+                                  the frame holding the layer in single steps.
+                                  3D periodic runs with a constant c^2, one batch
+                                  member and at most 32 sources, all at least 3
+                                  cells inside the layer-free region: the same
+                                  with each wave marching in z over 64 columns x
+                                  RY rows (tile_rows: planes per chunk in bits
+                                  0-11 (0 = 32), RY in bits 12-19 (4, 8 or 16;
+                                  0 = 8)); sources are added inside the pass,
+                                  receivers and planes recorded after it.
+                                  Otherwise single steps as CELL (2D) or MARCH
+                                  (3D)                                                */
+#define DPML_VARIANT_THREESTEP 5 /* 2D: as TWOSTEP with three steps per pass over a
+                                  core one cell smaller (4 words per cell per three
+                                  steps: U^{n+1} is stored on the core's boundary
+                                  ring only; tile_rows as for TWOSTEP); a remaining
+                                  pair takes the two-step pass.  3D: as TWOSTEP    */
 
 typedef struct dpml_grid {
     int32_t ndim;    /* 2 or 3 */
@@ -187,7 +196,7 @@ int dpml_record_plane(dpml_t *h, int32_t axis, int64_t index, void *planes,
  * tile_rows (meaning per variant above; 0 = default).  All variants
  * evaluate the scheme in the same operation order, so results do not
  * depend on the choice.  DPML_EINVAL for an unknown variant or tile_rows
- * outside [0, 65535]. */
+ * outside [0, 2^20). */
 int dpml_set_variant(dpml_t *h, int32_t variant, int32_t tile_rows);
 
 /* Enqueue nsteps fused steps (U, Phi, Psi, sources, receivers).  Returns

@@ -56,7 +56,7 @@ constexpr int kFlagBlocks = 1024;
 // U buffers of a single-grid handle: 2D grids carry three spares for the
 // two- and three-step variants (which write U^{n+1} .. U^{n+3} beside U^n and
 // U^{n-1}); 3D grids only U^n and U^{n-1}.
-int handle_ubufs(const dpml_grid_t *g) { return g && g->ndim == 2 ? 5 : 2; }
+int handle_ubufs(const dpml_grid_t *g) { return g && g->ndim == 2 ? 5 : 4; }
 
 // Validate the grid and compute the workspace layout.  Returns "" or an error.
 std::string make_layout(const dpml_grid_t *g, bool c2_field, Layout &L, int n_ubuf)
@@ -135,6 +135,7 @@ struct dpml {
     // sources
     int64_t ns = 0, nt_src = 0;
     int64_t *d_src_cells = nullptr, *d_src_order = nullptr;
+    std::vector<int64_t> src_sorted;      // host copy of d_src_cells
     const void *wavelets = nullptr;
     // receivers
     int64_t nr = 0, nt_rec = 0;
@@ -355,13 +356,15 @@ double box_cells(const dpmlk::Box3 &bx)
 // One thread-per-cell launch over a box with the layer code of the axes in
 // `ax` (x and z, or all).
 template <typename T>
-int launch_box(dpml *H, dpmlk::StepArgs<T> p, const dpmlk::Box3 &bx, int ax, hipStream_t st, int kind)
+int launch_box(dpml *H, dpmlk::StepArgs<T> p, const dpmlk::Box3 &bx, int ax, hipStream_t st, int kind,
+               double bytes = -1)
 {
     if (bx.xe <= bx.xs || bx.ye <= bx.ys || bx.ze <= bx.zs) return DPML_OK;
     p.tiles_x = (bx.xe - bx.xs + 63) / 64;
     p.tiles_y = (bx.ye - bx.ys + 3) / 4;
     p.n_tiles = p.tiles_x * p.tiles_y * (bx.ze - bx.zs);
-    const int slot = H->timing ? timed_begin(H, kind, step_bytes(H, box_cells(bx), box_aux(H->L, bx)), st) : -1;
+    if (H->timing && bytes < 0) bytes = step_bytes(H, box_cells(bx), box_aux(H->L, bx));
+    const int slot = H->timing ? timed_begin(H, kind, bytes, st) : -1;
     const dim3 grid((unsigned)round8(p.n_tiles), (unsigned)H->L.batch), block(256);
     if (ax == 5) hipLaunchKernelGGL((dpmlk::k_step_box3d<T, 5>), grid, block, 0, st, p, bx);
     else hipLaunchKernelGGL((dpmlk::k_step_box3d<T, 7>), grid, block, 0, st, p, bx);
@@ -374,7 +377,7 @@ int launch_box(dpml *H, dpmlk::StepArgs<T> p, const dpmlk::Box3 &bx, int ax, hip
 // tile.
 template <typename T>
 int launch_zmarch(dpml *H, dpmlk::StepArgs<T> p, const dpmlk::Box3 &bx, int ry, int ax, int zchunk,
-                  hipStream_t st, int kind)
+                  hipStream_t st, int kind, double bytes = -1)
 {
     if (bx.xe <= bx.xs || bx.ye <= bx.ys || bx.ze <= bx.zs) return DPML_OK;
     p.tile_rows = zchunk;
@@ -382,7 +385,8 @@ int launch_zmarch(dpml *H, dpmlk::StepArgs<T> p, const dpmlk::Box3 &bx, int ry, 
     p.tiles_y = (bx.ye - bx.ys + 4 * ry - 1) / (4 * ry);
     const int tz = (bx.ze - bx.zs + zchunk - 1) / zchunk;
     p.n_tiles = p.tiles_x * p.tiles_y * tz;
-    const int slot = H->timing ? timed_begin(H, kind, step_bytes(H, box_cells(bx), box_aux(H->L, bx)), st) : -1;
+    if (H->timing && bytes < 0) bytes = step_bytes(H, box_cells(bx), box_aux(H->L, bx));
+    const int slot = H->timing ? timed_begin(H, kind, bytes, st) : -1;
     const dim3 grid((unsigned)round8(p.n_tiles), (unsigned)H->L.batch), block(256);
 #define DPML_ZMARCH(RY_, AX_) hipLaunchKernelGGL((dpmlk::k_step_zmarch3d<T, RY_, AX_>), grid, block, 0, st, p, bx)
     if (ry == 4) {
@@ -434,7 +438,7 @@ int launch_march3d(dpml *H, dpmlk::StepArgs<T> p, int ry)
         x1 = std::min(64 * s1, NX);
     }
     (void)nstrips;
-    const int zc = H->tile_rows > 0 ? H->tile_rows : 32;
+    const int zc = (H->tile_rows & 0xFFF) > 0 ? (H->tile_rows & 0xFFF) : 32;
     const int zl = std::max(8, zc / 4);               // layer boxes: few tiles, shorter chunks
     int rc;
     if (L.M[1] > 0) {
@@ -472,8 +476,10 @@ int launch_step(dpml *H, T *hist = nullptr, T *uout = nullptr)
     p.hist = hist;
     p.uout = uout;
     const unsigned B = (unsigned)L.batch;
-    int variant = (H->variant == DPML_VARIANT_AUTO || H->variant == DPML_VARIANT_TWOSTEP ||
-                   H->variant == DPML_VARIANT_THREESTEP) ? DPML_VARIANT_CELL : H->variant;
+    const bool multi = H->variant == DPML_VARIANT_TWOSTEP || H->variant == DPML_VARIANT_THREESTEP;
+    int variant = (H->variant == DPML_VARIANT_AUTO || multi) ? DPML_VARIANT_CELL : H->variant;
+    // 3D single steps of the multi-step variants march like MARCH
+    if (L.ndim == 3 && multi) variant = DPML_VARIANT_MARCH;
     if (L.ndim == 3 && variant != DPML_VARIANT_CELL)
         return launch_march3d<T>(H, p, variant == DPML_VARIANT_MARCH ? 4 : 2);
     const int slot = timed_begin(H, DPML_KERNEL_STEP, step_bytes(H, (double)L.ncell, aux_cells(L)));
@@ -518,6 +524,9 @@ int launch_step(dpml *H, T *hist = nullptr, T *uout = nullptr)
 }
 
 template <typename T>
+int launch_record(dpml *H, const T *unew, int64_t n);
+
+template <typename T>
 int launch_epilogue(dpml *H)
 {
     // U^{n+1} now sits in u_old (before the rotation)
@@ -531,12 +540,20 @@ int launch_epilogue(dpml *H)
         hipLaunchKernelGGL((dpmlk::k_inject<T>), grid, block, 0, H->stream, unew, H->d_src_cells,
                            H->d_src_order, (const T *)H->wavelets, H->ns, H->nt_src, H->n, amp);
     }
-    if (H->recording && H->nr > 0 && H->n < H->nt_rec) {
+    return launch_record<T>(H, unew, H->n);
+}
+
+// Receivers and the recorded plane of time index n from the field `unew`.
+template <typename T>
+int launch_record(dpml *H, const T *unew, int64_t n)
+{
+    const Layout &L = H->L;
+    if (H->recording && H->nr > 0 && n < H->nt_rec) {
         dim3 grid((unsigned)((H->nr + 255) / 256)), block(256);
-        hipLaunchKernelGGL((dpmlk::k_record<T>), grid, block, 0, H->stream, (const T *)unew,
-                           H->d_rec_cells, (T *)H->traces, H->nr, H->nt_rec, H->n);
+        hipLaunchKernelGGL((dpmlk::k_record<T>), grid, block, 0, H->stream, unew,
+                           H->d_rec_cells, (T *)H->traces, H->nr, H->nt_rec, n);
     }
-    if (H->recording && H->plane_axis >= 0 && H->n < H->nt_plane) {
+    if (H->recording && H->plane_axis >= 0 && n < H->nt_plane) {
         int a0 = -1, a1 = -1;
         for (int a = 0; a < L.ndim; ++a) {
             if (a == H->plane_axis) continue;
@@ -546,9 +563,9 @@ int launch_epilogue(dpml *H)
         const int64_t e0 = L.N[a0], e1 = a1 >= 0 ? L.N[a1] : 1;
         const int64_t s0 = stride[a0], s1 = a1 >= 0 ? stride[a1] : 0;
         const int64_t cells = e0 * e1;
-        T *out = (T *)H->planes + H->n * cells;
+        T *out = (T *)H->planes + n * cells;
         dim3 grid((unsigned)((cells + 255) / 256)), block(256);
-        hipLaunchKernelGGL((dpmlk::k_record_plane<T>), grid, block, 0, H->stream, (const T *)unew, out,
+        hipLaunchKernelGGL((dpmlk::k_record_plane<T>), grid, block, 0, H->stream, unew, out,
                            e0, e1, s0, s1, H->plane_index * stride[H->plane_axis]);
     }
     HIP_TRY(H, hipGetLastError());
@@ -582,12 +599,51 @@ void core_rect(const Layout &L, int levels, int r[4])
     }
 }
 
+// Core box of a 3D two-step pass shrunk by `shrink` cells: [lo+2+shrink,
+// lo+n-1-shrink) along an axis with a layer (the cells whose one-cell halo is
+// free of damping terms), the whole periodic axis without one.
+dpmlk::Box3 core_box3d(const Layout &L, int shrink)
+{
+    int r[6];
+    for (int a = 0; a < 3; ++a) {
+        if (L.M[a] == 0) {
+            r[2 * a] = 0;
+            r[2 * a + 1] = (int)L.N[a];
+            continue;
+        }
+        const int b0 = L.lo[a] + 2 + shrink, b1 = (int)(L.lo[a] + L.n[a]) - 1 - shrink;
+        r[2 * a] = b0;
+        r[2 * a + 1] = std::max(b0, b1);
+    }
+    return dpmlk::Box3{r[0], r[1], r[2], r[3], r[4], r[5]};
+}
+
+// 3D: two levels per pass for variants TWOSTEP and THREESTEP on periodic
+// single-member grids with a constant c^2, at most 32 sources, all inside the
+// core shrunk by one (the frame's steps then add none); otherwise 1.
+int multistep_levels3d(const dpml *H, int64_t nsteps)
+{
+    const Layout &L = H->L;
+    if (H->variant != DPML_VARIANT_TWOSTEP && H->variant != DPML_VARIANT_THREESTEP) return 1;
+    if (nsteps < 2 || L.batch != 1 || H->c2_field || L.wall[0] || L.wall[1] || L.wall[2]) return 1;
+    if (L.N[0] < 8 || L.N[1] < 8 || L.N[2] < 8 || H->ns > 32) return 1;
+    const dpmlk::Box3 c = core_box3d(L, 0), in1 = core_box3d(L, 1);
+    if (in1.xe <= in1.xs || in1.ye <= in1.ys || in1.ze <= in1.zs) return 1;
+    (void)c;
+    for (int64_t cell : H->src_sorted) {
+        const int x = (int)(cell % L.N[0]), y = (int)((cell / L.N[0]) % L.N[1]), z = (int)(cell / (L.N[0] * L.N[1]));
+        if (x < in1.xs || x >= in1.xe || y < in1.ys || y >= in1.ye || z < in1.zs || z >= in1.ze) return 1;
+    }
+    return 2;
+}
+
 // Levels per pass this handle may take right now: 3 (VARIANT_THREESTEP), 2
 // (VARIANT_TWOSTEP, or THREESTEP for a last pair), or 1.
 int multistep_levels(const dpml *H, int64_t nsteps)
 {
     const Layout &L = H->L;
-    if (L.ndim != 2 || L.wall[0] || L.wall[1]) return 1;
+    if (L.ndim == 3) return multistep_levels3d(H, nsteps);
+    if (L.wall[0] || L.wall[1]) return 1;
     if (H->ns > 0 || (H->recording && (H->nr > 0 || H->plane_axis >= 0))) return 1;
     int want = H->variant == DPML_VARIANT_THREESTEP ? 3 : (H->variant == DPML_VARIANT_TWOSTEP ? 2 : 1);
     if (want > nsteps) want = (int)nsteps;
@@ -633,6 +689,7 @@ int ensure_frame(dpml *H, int levels, int shrink)
 // fork/join events.
 int ensure_multistep(dpml *H, int levels)
 {
+    if (H->L.ndim == 3) return ensure_side(H);
     for (int sh = 0; sh < levels; ++sh) {
         int rc = ensure_frame(H, levels, sh);
         if (rc) return rc;
@@ -734,6 +791,120 @@ int launch_multistep(dpml *H, int levels)
     return DPML_OK;
 }
 
+// One step over everything outside the box S (a frame step of a 3D pass):
+// the rows outside S (every column and plane; all layer code), S's rows on
+// the planes outside S (every column; x and z layer code) and S's rows and
+// planes on the columns outside S (the x-band march).  `share` is the
+// algorithmic byte count the three launches report together.
+template <typename T>
+int launch_outside3d(dpml *H, const dpmlk::StepArgs<T> &p, const dpmlk::Box3 &S, double share, hipStream_t st)
+{
+    const Layout &L = H->L;
+    const int NX = (int)L.N[0], NY = (int)L.N[1], NZ = (int)L.N[2];
+    const dpmlk::Box3 by{0, NX, S.ye, S.ys + NY, 0, NZ};
+    const dpmlk::Box3 bz{0, NX, S.ys, S.ye, S.ze, S.zs + NZ};
+    const dpmlk::Box3 bx{S.xe, S.xs + NX, S.ys, S.ye, S.zs, S.ze};
+    const bool hy = S.ye - S.ys < NY, hz = S.ze - S.zs < NZ, hx = S.xe - S.xs < NX;
+    // each launch reports its part of the share, by its own algorithmic bytes
+    double w[3] = {0, 0, 0};
+    if (H->timing) {
+        if (hy) w[0] = step_bytes(H, box_cells(by), box_aux(L, by));
+        if (hz) w[1] = step_bytes(H, box_cells(bz), box_aux(L, bz));
+        if (hx) w[2] = step_bytes(H, box_cells(bx), box_aux(L, bx));
+        const double sum = w[0] + w[1] + w[2];
+        for (double &v : w) v = sum > 0 ? share * v / sum : 0;
+    }
+    int rc = DPML_OK;
+    if (hy) rc = launch_box<T>(H, p, by, 7, st, DPML_KERNEL_FRAME, w[0]);
+    if (rc) return rc;
+    if (hz) rc = launch_box<T>(H, p, bz, 5, st, DPML_KERNEL_FRAME, w[1]);
+    if (rc) return rc;
+    if (hx) {
+        const int zc = (H->tile_rows & 0xFFF) > 0 ? (H->tile_rows & 0xFFF) : 32;
+        rc = launch_zmarch<T>(H, p, bx, 4, 1, std::max(8, zc / 4), st, DPML_KERNEL_FRAME, w[2]);
+    }
+    return rc;
+}
+
+// Two steps of a 3D grid.  The core kernel runs on the handle's stream; the
+// frame takes two ordinary steps on the side stream at the same time, step
+// j over everything outside the core shrunk by 2 - j cells.  The core writes
+// U^{n+1} only on the core shrunk by one, so every cell of every buffer has
+// one writer.  Receivers and the plane record both levels once the side
+// stream has joined.
+template <typename T>
+int launch_multistep3d(dpml *H)
+{
+    const Layout &L = H->L;
+    T *A = (T *)H->u_now, *Bv = (T *)H->u_old;
+    T *nxt[2] = {nullptr, nullptr};
+    int k = 0;
+    for (int i = 0; i < L.n_ubuf && k < 2; ++i) {
+        void *b = H->at(L.off_u[i]);
+        if (b != H->u_now && b != H->u_old) nxt[k++] = (T *)b;
+    }
+    if (k < 2) return H->fail(DPML_EINVAL, "not enough field buffers for a multi-step pass");
+    const dpmlk::Box3 c = core_box3d(L, 0), in1 = core_box3d(L, 1);
+    // tile_rows: planes per chunk in the low 12 bits (0: 32), rows per wave
+    // in the bits above (4, 8 or 16; 0: 8)
+    const int chunk = (H->tile_rows & 0xFFF) > 0 ? (H->tile_rows & 0xFFF) : 32;
+    const int ryb = H->tile_rows >> 12;
+    const int ry = (ryb == 4 || ryb == 16) ? ryb : 8;
+    HIP_TRY(H, hipEventRecord(H->ev_fork, H->stream));
+    HIP_TRY(H, hipStreamWaitEvent(H->side, H->ev_fork, 0));
+    {
+        dpmlk::StepArgs<T> p = make_args<T>(H);
+        p.uout = nxt[0];
+        p.tile_rows = chunk;
+        p.tiles_x = (c.xe - c.xs + 59) / 60;
+        p.tiles_y = (c.ye - c.ys + 4 * ry - 1) / (4 * ry);
+        p.n_tiles = p.tiles_x * p.tiles_y * ((c.ze - c.zs + chunk - 1) / chunk);
+        dpmlk::Src3<T> src{};
+        src.cells = H->d_src_cells;
+        src.order = H->d_src_order;
+        src.wav = (const T *)H->wavelets;
+        src.ns = H->ns;
+        src.nt = H->nt_src;
+        src.n = H->n;
+        src.amp = (T)(H->dt * H->dt / (H->h * H->h * H->h));
+        const double core = box_cells(c);
+        const int slot = timed_begin(H, DPML_KERNEL_PAIR, step_bytes(H, 2 * core, 0.0));
+        const dim3 grid((unsigned)round8(p.n_tiles)), block(256);
+        if (ry == 4)
+            hipLaunchKernelGGL((dpmlk::k_step2_zmarch3d<T, 4>), grid, block, 0, H->stream, p, nxt[1], c, in1, src);
+        else if (ry == 16)
+            hipLaunchKernelGGL((dpmlk::k_step2_zmarch3d<T, 16>), grid, block, 0, H->stream, p, nxt[1], c, in1, src);
+        else
+            hipLaunchKernelGGL((dpmlk::k_step2_zmarch3d<T, 8>), grid, block, 0, H->stream, p, nxt[1], c, in1, src);
+        timed_end(H, slot);
+    }
+    // the frame's steps on the side stream, aux buffers alternating
+    for (int j = 1; j <= 2; ++j) {
+        if (j == 2) H->cur = 1 - H->cur;
+        dpmlk::StepArgs<T> pj = make_args<T>(H);
+        if (j == 2) H->cur = 1 - H->cur;
+        pj.u = j == 1 ? A : nxt[0];
+        pj.uo = j == 1 ? Bv : A;
+        pj.uout = nxt[j - 1];
+        // algorithmic share: the frame's own cells (the ring cells it recomputes
+        // are the core's, counted there)
+        const double share = step_bytes(H, (double)L.ncell - box_cells(c), aux_cells(L));
+        int rc = launch_outside3d<T>(H, pj, core_box3d(L, 2 - j), share, H->side);
+        if (rc) return rc;
+    }
+    HIP_TRY(H, hipEventRecord(H->ev_join, H->side));
+    HIP_TRY(H, hipStreamWaitEvent(H->stream, H->ev_join, 0));
+    HIP_TRY(H, hipGetLastError());
+    int rc = launch_record<T>(H, nxt[0], H->n);
+    if (rc) return rc;
+    rc = launch_record<T>(H, nxt[1], H->n + 1);
+    if (rc) return rc;
+    H->u_now = nxt[1];
+    H->u_old = nxt[0];
+    H->n += 2;
+    return DPML_OK;
+}
+
 template <typename T>
 int step_impl(dpml *H, int64_t nsteps)
 {
@@ -743,7 +914,7 @@ int step_impl(dpml *H, int64_t nsteps)
         if (lv < 2) break;
         int rc = ensure_multistep(H, lv);
         if (rc) return rc;
-        rc = launch_multistep<T>(H, lv);
+        rc = H->L.ndim == 3 ? launch_multistep3d<T>(H) : launch_multistep<T>(H, lv);
         if (rc) return rc;
         k += lv;
     }
@@ -956,6 +1127,7 @@ int dpml_inject(dpml_t *H, int64_t ns, const int64_t *cells, const void *wavelet
     if (H->d_src_cells) { HIP_TRY(H, hipFree(H->d_src_cells)); H->d_src_cells = nullptr; }
     if (H->d_src_order) { HIP_TRY(H, hipFree(H->d_src_order)); H->d_src_order = nullptr; }
     H->ns = 0;
+    H->src_sorted.clear();
     if (ns == 0) return DPML_OK;
     std::vector<int64_t> order((size_t)ns);
     std::iota(order.begin(), order.end(), 0);
@@ -969,6 +1141,7 @@ int dpml_inject(dpml_t *H, int64_t ns, const int64_t *cells, const void *wavelet
     H->ns = ns;
     H->nt_src = nt;
     H->wavelets = wavelets;
+    H->src_sorted = sorted;
     return DPML_OK;
 }
 
@@ -1016,7 +1189,7 @@ int dpml_record_plane(dpml_t *H, int32_t axis, int64_t index, void *planes, int6
 int dpml_set_variant(dpml_t *H, int32_t variant, int32_t tile_rows)
 {
     if (!H) return DPML_EINVAL;
-    if (variant < DPML_VARIANT_AUTO || variant > DPML_VARIANT_THREESTEP || tile_rows < 0 || tile_rows > 65535)
+    if (variant < DPML_VARIANT_AUTO || variant > DPML_VARIANT_THREESTEP || tile_rows < 0 || tile_rows >= (1 << 20))
         return H->fail(DPML_EINVAL, "bad variant");
     H->variant = variant;
     H->tile_rows = tile_rows;

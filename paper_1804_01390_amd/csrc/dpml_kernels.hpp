@@ -1079,6 +1079,194 @@ __global__ void __launch_bounds__(256) k_step_box3d(StepArgs<T> p, Box3 bx)
 }
 
 // ---------------------------------------------------------------------------
+// Variant TWOSTEP, 3D: two steps per pass over the core box, where no damping
+// term acts within two cells.  A wave holds 64 consecutive columns (the two
+// outer lanes on each side are halo) x RY rows and marches through a chunk of
+// planes.  At march plane k it forms U^{n+1} on plane k for the rows
+// -1 .. RY (from U^n of planes k-1, k, k+1 and U^{n-1} of plane k), then
+// U^{n+2} on plane k-1 for the rows 0 .. RY-1 from the U^{n+1} planes k-2,
+// k-1, k, all held in registers: per cell it reads U^n and U^{n-1} and
+// writes U^{n+1} (on the inner box only: the frame's own steps write the
+// ring around it) and U^{n+2}.  Both levels evaluate cell_update's
+// expressions in its order with no damping terms, so the results are
+// bit-identical to single steps.  Point sources within the wave's reach are
+// added to both levels as the single steps add them.
+// ---------------------------------------------------------------------------
+template <typename T>
+struct Src3 {
+    const int64_t *cells;   // source cells in ascending order
+    const int64_t *order;   // caller's index of each sorted source
+    const T *wav;           // wavelets [ns][nt]
+    int64_t ns, nt;
+    int64_t n;              // time index of the first level
+    T amp;                  // dt^2 / h^3
+};
+
+// d = (s - start) mod n in [0, n): is s within `len` cells from start?
+__device__ __forceinline__ bool in_window(int s, int start, int len, int n)
+{
+    int d = (s - start) % n;
+    if (d < 0) d += n;
+    return len >= n || d < len;
+}
+
+template <typename T, int RY>
+__global__ void __launch_bounds__(256) k_step2_zmarch3d(StepArgs<T> p, T *__restrict__ u_next2, Box3 c, Box3 in1,
+                                                        Src3<T> src)
+{
+    constexpr int NR = RY + 2;                               // rows of the first level: -1 .. RY
+    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+    if (tile >= p.n_tiles) return;
+    const int per_plane = p.tiles_x * p.tiles_y;
+    const int tz = tile / per_plane;
+    const int rem = tile - tz * per_plane;
+    const int ty = rem / p.tiles_x;
+    const int tx = rem - ty * p.tiles_x;
+    const int lane = (int)(threadIdx.x & 63);
+    const int nx = p.nx, ny = p.ny, nz = p.nz;
+    const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int y0 = c.ys + (ty * 4 + wv) * RY;                 // first output row (unwrapped)
+    if (y0 >= c.ye) return;                                   // whole wave; no barriers below
+    const int64_t sxy = (int64_t)nx * ny;
+    const int xw0 = c.xs - 2 + tx * 60;                       // the wave's first column (unwrapped)
+    const int xu = xw0 + lane;
+    const int xc = ((xu % nx) + nx) % nx;
+    const bool xout = lane >= 2 && lane < 62 && xu < c.xe;   // U^{n+2} column
+    const bool xin1 = xout && xu >= in1.xs && xu < in1.xe;   // U^{n+1} stored too
+    const bool need = xu < c.xe + 2;                          // lanes past the reach read nothing
+    // array rows of the relative rows -2 .. RY+1
+    int ra[RY + 4];
+#pragma unroll
+    for (int r = 0; r < RY + 4; ++r) ra[r] = (((y0 - 2 + r) % ny) + ny) % ny;
+    const int z0 = c.zs + tz * p.tile_rows;
+    const int z1 = min(z0 + p.tile_rows, c.ze);
+    // planes z0-2 .. z1+1 lie in [-2, 2 nz): one conditional wrap
+    auto zwrap = [&](int z) -> int { return z < 0 ? z + nz : (z >= nz ? z - nz : z); };
+    const T *u = p.u;
+    // a row's base is the same for the whole wave, the lane adds its column
+    const uint32_t xo = (uint32_t)xc;
+    auto ld = [&](const T *b, int zc, int row) -> T {
+        const T *rp = b + ((int64_t)zc * sxy + (int64_t)row * nx);
+        return need ? rp[xo] : T(0);
+    };
+    // sources whose cell lies in the wave's reach (first level: rows -1..RY,
+    // planes z0-1 .. z1): bit q for the run of equal cells starting at q
+    uint32_t smask = 0;
+    for (int q = 0; q < (int)src.ns && q < 32; ++q) {
+        const int64_t cell = src.cells[q];
+        if (q > 0 && src.cells[q - 1] == cell) continue;
+        const int sz = (int)(cell / sxy), sy = (int)((cell / nx) % ny), sx = (int)(cell % nx);
+        if (in_window(sx, xw0, 64, nx) && in_window(sy, y0 - 1, NR, ny) && in_window(sz, z0 - 1, z1 - z0 + 2, nz))
+            smask |= 1u << q;
+    }
+    // add the sources on plane zc at time index tn to the rows of v (relative rows r0 ..)
+    auto inject = [&](auto &v, int r0, int zc, int64_t tn) {
+        constexpr int NV = (int)(sizeof(v) / sizeof(v[0]));
+        if (tn >= src.nt) return;
+        for (uint32_t m = smask; m; m &= m - 1) {
+            const int q = __builtin_ctz(m);
+            const int64_t cell = src.cells[q];
+            if ((int)(cell / sxy) != zc) continue;
+            const int sy = (int)((cell / nx) % ny), sx = (int)(cell % nx);
+            T add = T(0);
+            for (int64_t r = q; r < src.ns && src.cells[r] == cell; ++r) add += src.wav[src.order[r] * src.nt + tn];
+#pragma unroll
+            for (int i = 0; i < NV; ++i)
+                if (ra[r0 + 2 + i] == sy && xc == sx) v[i] = v[i] + src.amp * add;
+        }
+    };
+    // one step of a cell in cell_update's order (c^2 constant, no damping terms)
+    const T inv_h2 = p.inv_h2, dt2 = p.dt2, c2c = p.c2_const;
+    auto upd = [&](T uc, T uxm, T uxp, T uym, T uyp, T uzm, T uzp, T old) -> T {
+        T lap = ((uxm - T(2) * uc) + uxp) * inv_h2;
+        lap += ((uym - T(2) * uc) + uyp) * inv_h2;
+        lap += ((uzm - T(2) * uc) + uzp) * inv_h2;
+        const T rhs = c2c * lap + T(0);
+        return (T(2) * uc - old) + dt2 * rhs;
+    };
+    // U^n of planes k-1, k, k+1 (rows -1 .. RY); U^{n+1} of planes k-2 (rows
+    // 0 .. RY-1), k-1 and k (rows -1 .. RY)
+    T n0[NR], n1[NR], a0[RY], a1[NR];
+    struct Fetch {
+        T n2[NR], old[NR], hlo, hhi;
+    };
+    auto fetch = [&](int k, Fetch &f) {
+        const int zc = zwrap(k), zn = zwrap(k + 1);
+#pragma unroll
+        for (int i = 0; i < NR; ++i) {
+            f.n2[i] = ld(u, zn, ra[i + 1]);
+            f.old[i] = ld(p.uo, zc, ra[i + 1]);
+        }
+        f.hlo = ld(u, zc, ra[0]);
+        f.hhi = ld(u, zc, ra[RY + 3]);
+    };
+    {
+        const int zm = zwrap(z0 - 2), zc = zwrap(z0 - 1);
+#pragma unroll
+        for (int i = 0; i < NR; ++i) {
+            n0[i] = ld(u, zm, ra[i + 1]);
+            n1[i] = ld(u, zc, ra[i + 1]);
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < NR; ++i) a1[i] = T(0);
+#pragma unroll
+    for (int i = 0; i < RY; ++i) a0[i] = T(0);
+    T *out1 = p.uout;
+    Fetch cur;
+    fetch(z0 - 1, cur);
+    for (int k = z0 - 1; k <= z1; ++k) {
+        Fetch nxt;
+        if (k + 1 <= z1) fetch(k + 1, nxt);
+        const int zc = zwrap(k);
+        // level 1: U^{n+1} on plane k, rows -1 .. RY
+        T a2[NR];
+#pragma unroll
+        for (int i = 0; i < NR; ++i) {
+            const T uc = n1[i];
+            const T uxm = from_left(uc), uxp = from_right(uc);
+            const T uym = i == 0 ? cur.hlo : n1[i - 1];
+            const T uyp = i == NR - 1 ? cur.hhi : n1[i + 1];
+            a2[i] = upd(uc, uxm, uxp, uym, uyp, n0[i], cur.n2[i], cur.old[i]);
+        }
+        if (smask) inject(a2, -1, zc, src.n);
+        if (k >= z0 && k < z1 && k >= in1.zs && k < in1.ze) {
+            const int64_t plane = (int64_t)zc * sxy;
+#pragma unroll
+            for (int r = 0; r < RY; ++r) {
+                const int y = y0 + r;
+                if (xin1 && y < c.ye && y >= in1.ys && y < in1.ye) (out1 + (plane + (int64_t)ra[r + 2] * nx))[xo] = a2[r + 1];
+            }
+        }
+        // level 2: U^{n+2} on plane k-1, rows 0 .. RY-1
+        if (k >= z0 + 1) {
+            const int zp = zwrap(k - 1);
+            T v[RY];
+#pragma unroll
+            for (int r = 0; r < RY; ++r) {
+                const T uc = a1[r + 1];
+                const T uxm = from_left(uc), uxp = from_right(uc);
+                v[r] = upd(uc, uxm, uxp, a1[r], a1[r + 2], a0[r], a2[r + 1], n0[r + 1]);
+            }
+            if (smask) inject(v, 0, zp, src.n + 1);
+            const int64_t plane = (int64_t)zp * sxy;
+#pragma unroll
+            for (int r = 0; r < RY; ++r)
+                if (xout && y0 + r < c.ye) (u_next2 + (plane + (int64_t)ra[r + 2] * nx))[xo] = v[r];
+        }
+#pragma unroll
+        for (int r = 0; r < RY; ++r) a0[r] = a1[r + 1];
+#pragma unroll
+        for (int i = 0; i < NR; ++i) {
+            a1[i] = a2[i];
+            n0[i] = n1[i];
+            n1[i] = cur.n2[i];
+        }
+        cur = nxt;
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Start: U^{-1} = U^0 - dt V^0 + dt^2/2 c^2 Lap(U^0)  (Phi = Psi = 0).
 // ---------------------------------------------------------------------------
 template <typename T, int D>

@@ -1,0 +1,142 @@
+"""3D two-step passes (variant TWOSTEP on a 3D grid): the core kernel forms
+two levels per pass while the frame takes single steps beside it.  Every
+field must equal the single-step result bit for bit (the same expressions in
+the same order), and match the FP64 oracle at the parity tolerances."""
+import numpy as np
+import pytest
+
+import oracle
+import synthetic
+from helpers import compare_states, gpu_state, rel_err, run_with_peaks
+
+torch = pytest.importorskip("torch")
+dp = pytest.importorskip("paper_1804_01390_amd")
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"f64": 1e-12, "f32": 2e-5}
+
+
+def _dtype(name):
+    return torch.float64 if name == "f64" else torch.float32
+
+
+def _fields(sim, lo, hi):
+    out = [sim.U.cpu().numpy().copy(), sim.field(dp.FIELD_UPREV).cpu().numpy().copy()]
+    for a in range(3):
+        if lo[a] + hi[a] > 0:
+            out.append(sim.field(dp.FIELD_PHI(a)).cpu().numpy().copy())
+            out.append(sim.field(dp.FIELD_PSI(a)).cpu().numpy().copy())
+    return out
+
+
+def _case(name, rng):
+    if name == "ragged":
+        n, lo, hi = [150, 47, 41], [7, 5, 6], [6, 8, 4]
+    elif name == "z_periodic":
+        n, lo, hi = [70, 40, 36], [5, 6, 0], [7, 4, 0]
+    else:   # "x_periodic": the core spans the whole x axis and its strips wrap
+        n, lo, hi = [100, 30, 34], [0, 4, 5], [0, 6, 3]
+    sig = [synthetic.sigma_random(n[a], lo[a], hi[a], 2.0, rng) if lo[a] + hi[a] > 0 else None for a in range(3)]
+    U0 = synthetic.gaussian_sum(n, lo, hi, 6, 2.0, 5.0, rng)
+    return n, lo, hi, sig, U0
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("case", ["ragged", "z_periodic", "x_periodic"])
+@pytest.mark.parametrize("tile_rows", [0, (4 << 12) | 5, (16 << 12) | 7, (8 << 12) | 64])
+def test_3d_twostep_bit_identical_and_oracle(dtype, case, tile_rows):
+    rng = np.random.default_rng(17)
+    n, lo, hi, sig, U0 = _case(case, rng)
+    N = [lo[a] + n[a] + hi[a] for a in range(3)]
+    steps, dt = 23, 0.4          # 11 two-step passes and one single step
+    print("case 3d two-step %s %s rows %d" % (case, dtype, tile_rows), flush=True)
+    outs = []
+    for variant, tr in ((dp.VARIANT_TWOSTEP, tile_rows), (dp.VARIANT_MARCH, 0)):
+        sim = dp.Simulation(n, lo, hi, 1.0, dt, sig, dtype=_dtype(dtype))
+        sim.set_variant(variant, tr)
+        sim.set_state(torch.from_numpy(U0))
+        sim.step(steps)
+        sim.sync()
+        outs.append(_fields(sim, lo, hi))
+        if variant == dp.VARIANT_TWOSTEP:
+            gs = gpu_state(sim)
+        sim.close()
+    for k, (x, y) in enumerate(zip(outs[0], outs[1])):
+        assert np.array_equal(x, y), k
+    g = oracle.Grid(N, 1.0, dt, sig)
+    ref, _, peaks = run_with_peaks(g, oracle.start(g, U0), steps, n, lo, hi)
+    errs = compare_states(gs, ref, n, lo, hi, peaks if dtype == "f32" else None)
+    print("errors:", {k: "%.2e" % v for k, v in errs.items()}, flush=True)
+    for k, v in errs.items():
+        assert v <= TOL[dtype], (k, v)
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("where", ["core", "frame"])
+def test_3d_twostep_sources_receivers_plane(dtype, where):
+    """Sources inside the core are added by the core kernel at both levels
+    (two of them on one cell, summed in the caller's order); a source in the
+    frame makes the run take single steps.  Traces, the recorded plane and
+    the fields equal the single-step run bit for bit and match the oracle."""
+    w = synthetic.ricker3d(n=40, m=6, steps=61, ppw=8.0)
+    extra = [20, 17, 29] if where == "core" else [7, 20, 20]
+    w.sources.append(synthetic.flat_index(w.N, extra))
+    w.sources.append(synthetic.flat_index(w.N, extra))
+    wav = np.vstack([w.wavelets, 0.5 * np.roll(w.wavelets[0], 7)[None, :], -0.3 * np.roll(w.wavelets[0], 3)[None, :]])
+    rec = [w.sources[0], synthetic.flat_index(w.N, [3, 3, 3]), synthetic.flat_index(w.N, [30, 25, 20]),
+           w.sources[1]]
+    axis, index = w.plane
+    print("case 3d two-step sources in %s %s" % (where, dtype), flush=True)
+    res = []
+    for variant in (dp.VARIANT_TWOSTEP, dp.VARIANT_MARCH):
+        sim = dp.Simulation(w.n, w.lo, w.hi, w.h, w.dt, w.sigma, dtype=_dtype(dtype))
+        sim.set_variant(variant, 0)
+        sim.set_state(torch.zeros(tuple(reversed(w.N)), dtype=torch.float64))
+        sim.inject(w.sources, torch.from_numpy(wav))
+        tr = sim.record(rec, w.steps)
+        pl = sim.record_plane(axis, index, w.steps)
+        sim.step(w.steps)
+        sim.sync()
+        res.append((tr.cpu().numpy().copy(), pl.cpu().numpy().copy(), _fields(sim, w.lo, w.hi)))
+        if variant == dp.VARIANT_TWOSTEP:
+            gs = gpu_state(sim)
+        sim.close()
+    (ta, pa, fa), (tb, pb, fb) = res
+    assert np.array_equal(ta, tb)
+    assert np.array_equal(pa, pb)
+    for k, (x, y) in enumerate(zip(fa, fb)):
+        assert np.array_equal(x, y), k
+    g = oracle.Grid(w.N, w.h, w.dt, w.sigma)
+    ref, rtr = oracle.run(g, oracle.start(g, np.zeros(tuple(reversed(w.N)))), w.steps,
+                          sources=w.sources, wavelets=wav, receivers=rec, nt=w.steps)
+    errs = compare_states(gs, ref, w.n, w.lo, w.hi)
+    errs["traces"] = rel_err(ta.astype(np.float64), rtr)
+    errs["plane_final"] = rel_err(pa[-1].astype(np.float64), ref.U[index])
+    print("errors:", {k: "%.2e" % v for k, v in errs.items()}, flush=True)
+    for k, v in errs.items():
+        assert v <= TOL[dtype], (k, v)
+
+
+def test_3d_twostep_timing_counts_and_bytes():
+    """Per-launch timing of a 3D two-step run: one core launch per pass
+    counting both levels of the core's cells, three frame launches per frame
+    step, and the frame's share of the byte model per pass."""
+    rng = np.random.default_rng(4)
+    n, lo, hi, sig, U0 = _case("ragged", rng)
+    N = [lo[a] + n[a] + hi[a] for a in range(3)]
+    sim = dp.Simulation(n, lo, hi, 1.0, 0.4, sig, dtype=torch.float32)
+    sim.set_variant(dp.VARIANT_TWOSTEP, 0)
+    sim.set_state(torch.from_numpy(U0))
+    sim.set_timing(True)
+    sim.step(8)
+    t = sim.get_timing()
+    sim.close()
+    core = [n[a] - 3 for a in range(3)]                  # [lo+2, lo+n-1) per axis
+    core_cells = core[0] * core[1] * core[2]
+    cells = N[0] * N[1] * N[2]
+    aux = sum((lo[a] + hi[a]) * cells // N[a] for a in range(3))
+    assert t["pair"]["launches"] == 4
+    assert t["pair"]["bytes"] == pytest.approx(4 * 2 * 3 * core_cells * 4, rel=1e-12)
+    assert t["frame"]["launches"] == 4 * 2 * 3
+    assert t["frame"]["bytes"] == pytest.approx(4 * 2 * (3 * (cells - core_cells) + 4 * aux) * 4, rel=1e-9)
