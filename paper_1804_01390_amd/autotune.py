@@ -23,9 +23,12 @@ CANDIDATES_2D: List[Tuple[int, int]] = ([(VARIANT_THREESTEP, (g << 12) | r) for 
                                         + [(VARIANT_TWOSTEP, (g << 12) | r) for g in (2, 4) for r in (8, 16)] + [(VARIANT_CELL, th) for th in (1, 2, 4, 8)]
                                         + [(VARIANT_MARCH, r) for r in (4, 8, 16)]
                                         + [(VARIANT_MARCH1, r) for r in (4, 8, 16)])
+# 3D two-step passes: rows per wave above bit 12, planes per chunk below
 CANDIDATES_3D: List[Tuple[int, int]] = ([(VARIANT_CELL, th) for th in (2, 4, 8)]
                                         + [(VARIANT_MARCH, r) for r in (16, 32, 64, 128)]
-                                        + [(VARIANT_MARCH1, r) for r in (16, 32, 64, 128)])
+                                        + [(VARIANT_MARCH1, r) for r in (16, 32, 64, 128)]
+                                        + [(VARIANT_TWOSTEP, (ry << 12) | ch) for ry in (4, 8, 16)
+                                           for ch in (32, 64, 128)])
 
 
 def grid_key(sim) -> str:

@@ -1058,7 +1058,9 @@ __global__ void __launch_bounds__(256) k_step_box3d(StepArgs<T> p, Box3 bx)
     const int yu = bx.ys + ty * 4 + (int)(threadIdx.x >> 6);
     if (xu >= bx.xe || yu >= bx.ye) return;
     const int nx = p.nx, ny = p.ny, nz = p.nz;
-    const int x = xu % nx, y = yu % ny, z = (bx.zs + tz) % nz;
+    // box starts lie in the array and extents are at most its length: one wrap
+    const int zu = bx.zs + tz;
+    const int x = xu >= nx ? xu - nx : xu, y = yu >= ny ? yu - ny : yu, z = zu >= nz ? zu - nz : zu;
     const int64_t sxy = (int64_t)nx * ny;
     const int64_t plane = (int64_t)z * sxy;
     const int64_t row = plane + (int64_t)y * nx;
