@@ -1043,17 +1043,25 @@ __global__ void __launch_bounds__(256) k_step_zmarch3d(StepArgs<T> p, Box3 bx)
 // The same box update one thread per cell (64 x 4 cells of a plane per
 // block): for boxes whose cells mostly carry layer terms, where many waves in
 // flight hide the latency of the layer loads better than a plane march.
+// Consecutive tiles take the same (x, y) tile on up to 8 consecutive planes,
+// then the next (x, y) tile: the planes above and below a tile are read by
+// its neighbours in launch order (L2 hits), and the tiles sharing its halo
+// rows are at most 8 tiles-per-row further on.
 template <typename T, int AX>
 __global__ void __launch_bounds__(256) k_step_box3d(StepArgs<T> p, Box3 bx)
 {
+    constexpr int ZG = 8;
     const int tile = xcd_tile(blockIdx.x, gridDim.x);
     if (tile >= p.n_tiles) return;
     select_member(p, (int)blockIdx.y);
     const int per_plane = p.tiles_x * p.tiles_y;
-    const int tz = tile / per_plane;
-    const int rem = tile - tz * per_plane;
-    const int ty = rem / p.tiles_x;
-    const int tx = rem - ty * p.tiles_x;
+    const int g = tile / (per_plane * ZG);                 // group of ZG planes
+    const int zn = min(ZG, bx.ze - bx.zs - g * ZG);        // planes in this group
+    const int rem = tile - g * per_plane * ZG;
+    const int xy = rem / zn;
+    const int tz = g * ZG + (rem - xy * zn);
+    const int ty = xy / p.tiles_x;
+    const int tx = xy - ty * p.tiles_x;
     const int xu = bx.xs + tx * 64 + (int)(threadIdx.x & 63);
     const int yu = bx.ys + ty * 4 + (int)(threadIdx.x >> 6);
     if (xu >= bx.xe || yu >= bx.ye) return;
