@@ -330,7 +330,9 @@ def bench_batch(steps: int, count: int):
     import synthetic
     probs = synthetic.batch2d(count=count, steps=steps)
     cells = sum(w.cells for w in probs)
+    from paper_1804_01390_amd import autotune
     multi = dp.MultiSimulation(probs, dtype=torch.float32)
+    choice = autotune.tune_multi(multi, [w.U0 for w in probs], steps=20)
     multi.set_state([w.U0 for w in probs])
     multi.step(steps, graph=True)          # capture + instantiate + one run
     multi.sync()
@@ -342,6 +344,7 @@ def bench_batch(steps: int, count: int):
     e1.record()
     torch.cuda.synchronize()
     ms_graph = e0.elapsed_time(e1)
+    multi_tiles = multi.tiles
     multi.close()
     sims = []
     for w in probs:
@@ -366,7 +369,9 @@ def bench_batch(steps: int, count: int):
             "graph_value": round(cells * steps / (ms_graph * 1e-3) / 1e9, 3),
             "separate_value": round(cells * steps / (ms_sep * 1e-3) / 1e9, 3), "unit": "Gcell/s",
             "graph_ms": round(ms_graph, 3), "separate_ms": round(ms_sep, 3),
-            "speedup": round(ms_sep / ms_graph, 3)}
+            "speedup": round(ms_sep / ms_graph, 3),
+            "launch": {"tile_rows": choice["tile_rows"], "group": choice["group"], "autotuned": True,
+                       "tiles": multi_tiles}}
 
 
 def bench_adjoint(steps: int, shots: int):

@@ -337,6 +337,14 @@ int dpml_multi_field(dpml_multi_t *h, int64_t prob, int32_t which, void **ptr,
 /* Tiles in the work list of one step (for reporting). */
 int64_t dpml_multi_tiles(const dpml_multi_t *h);
 
+/* Launch shape of the many-problem kernel: each tile is 256 (FP32 with
+ * even widths: 512) columns x tile_rows rows of one problem, marched down
+ * with the loads of `group` rows issued together (1, 2 or 4).  0 selects
+ * the default (32 rows, group 4).  Results do not depend on the shape.
+ * Drops a captured graph.  DPML_EINVAL for tile_rows outside [4, 4096] or
+ * another group. */
+int dpml_multi_set_variant(dpml_multi_t *h, int32_t tile_rows, int32_t group);
+
 int dpml_multi_sync(dpml_multi_t *h);
 void dpml_multi_destroy(dpml_multi_t *h);
 const char *dpml_multi_last_error(const dpml_multi_t *h);

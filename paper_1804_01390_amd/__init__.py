@@ -44,7 +44,7 @@ EXPORTED = [
     "dpml_destroy", "dpml_strerror", "dpml_last_error",
     "dpml_adjoint_workspace_bytes", "dpml_forward_checkpointed", "dpml_adjoint",
     "dpml_multi_workspace_bytes", "dpml_multi_create", "dpml_multi_set_state", "dpml_multi_step",
-    "dpml_multi_field", "dpml_multi_tiles", "dpml_multi_sync", "dpml_multi_destroy",
+    "dpml_multi_field", "dpml_multi_tiles", "dpml_multi_set_variant", "dpml_multi_sync", "dpml_multi_destroy",
     "dpml_multi_last_error",
     "dpml_rk4_workspace_bytes", "dpml_rk4_set_state", "dpml_rk4_step", "dpml_rk4_field",
     "dpml_rk4_time_index", "dpml_set_timing", "dpml_get_timing",
@@ -117,6 +117,7 @@ def load_library():
         "dpml_multi_field": (ctypes.c_int, [_VP, ctypes.c_int64, ctypes.c_int32, ctypes.POINTER(_VP),
                                             ctypes.c_int64 * 3]),
         "dpml_multi_tiles": (ctypes.c_int64, [_VP]),
+        "dpml_multi_set_variant": (ctypes.c_int, [_VP, ctypes.c_int32, ctypes.c_int32]),
         "dpml_multi_sync": (ctypes.c_int, [_VP]),
         "dpml_multi_destroy": (None, [_VP]),
         "dpml_multi_last_error": (ctypes.c_char_p, [_VP]),
@@ -470,6 +471,13 @@ class MultiSimulation:
 
     def step(self, nsteps: int, graph: bool = False):
         self._check(self.lib.dpml_multi_step(self.handle, int(nsteps), 1 if graph else 0))
+
+    def set_variant(self, tile_rows: int = 0, group: int = 0):
+        """Tile height and row-load group of the many-problem kernel (0:
+        default); results do not depend on them."""
+        self._check(self.lib.dpml_multi_set_variant(self.handle, int(tile_rows), int(group)))
+        self.tiles = int(self.lib.dpml_multi_tiles(self.handle))
+        self.launch = (int(tile_rows), int(group))
 
     def field(self, prob: int, which: int):
         ptr = _VP()

@@ -1699,7 +1699,8 @@ struct dpml_multi {
     size_t off_tiles = 0;
     int64_t ntiles = 0;
     int vx = 1;
-    int tile_rows = 32;
+    int tile_rows = 32;              // rows per marching tile
+    int group = 4;                   // rows whose loads are issued together
     int parity = 0;                  // 0: buffers u0/aux0 hold level n
     int64_t n = 0;
     bool state_set = false;
@@ -1723,7 +1724,11 @@ struct MultiLayout {
     int vx = 1;
 };
 
-constexpr int kMultiTileRows = 4;     // marching tiles of 256 VX columns x 4 rows
+// The tile list is sized for the shortest tiles allowed (kMultiMinRows rows);
+// the default tiles are 256 VX columns x 32 rows, marched 4 rows at a time.
+constexpr int kMultiMinRows = 4;
+constexpr int kMultiTileRows = 32;
+constexpr int kMultiGroup = 4;
 
 std::string multi_layout(int64_t count, const dpml_grid_t *grids, MultiLayout &M)
 {
@@ -1748,7 +1753,7 @@ std::string multi_layout(int64_t count, const dpml_grid_t *grids, MultiLayout &M
     int64_t nt = 0;
     for (int64_t p = 0; p < count; ++p) {
         const int64_t tx = (M.L[p].N[0] + 256 * M.vx - 1) / (256 * M.vx);
-        const int64_t ty = (M.L[p].N[1] + kMultiTileRows - 1) / kMultiTileRows;
+        const int64_t ty = (M.L[p].N[1] + kMultiMinRows - 1) / kMultiMinRows;
         nt += tx * ty;
     }
     M.ntiles = nt;
@@ -1777,6 +1782,9 @@ dpml problem_view(const dpml_multi *H, int64_t p, int q)
 }
 
 template <typename T>
+int multi_shape(dpml_multi *H);
+
+template <typename T>
 int multi_tables(dpml_multi *H, const double *const *sigmas)
 {
     // damping tables of every problem
@@ -1787,7 +1795,14 @@ int multi_tables(dpml_multi *H, const double *const *sigmas)
         int rc = upload_tables<T>(&v, &one, 1, sg);
         if (rc) return H->fail(rc, v.err);
     }
-    // argument tables for both parities and the tile list
+    return multi_shape<T>(H);
+}
+
+// Argument tables for both buffer parities and the tile list, for the
+// handle's tile height.
+template <typename T>
+int multi_shape(dpml_multi *H)
+{
     for (int q = 0; q < 2; ++q) {
         std::vector<dpmlk::StepArgs<T>> args((size_t)H->count);
         for (int64_t p = 0; p < H->count; ++p) {
@@ -1809,6 +1824,7 @@ int multi_tables(dpml_multi *H, const double *const *sigmas)
     }
     HIP_TRY(nullptr, hipMemcpy(H->ws + H->off_tiles, tiles.data(), tiles.size() * sizeof(tiles[0]),
                                hipMemcpyHostToDevice));
+    H->ntiles = (int64_t)tiles.size();
     return DPML_OK;
 }
 
@@ -1818,11 +1834,19 @@ int multi_launch(dpml_multi *H, hipStream_t s, int parity)
     const dim3 grid((unsigned)round8((int)H->ntiles)), block(256);
     const auto *probs = (const dpmlk::StepArgs<T> *)(H->ws + H->off_desc[parity]);
     const auto *tiles = (const dpmlk::TileRef *)(H->ws + H->off_tiles);
-    if (H->vx == 2)
-        hipLaunchKernelGGL((dpmlk::k_step_multi2d<T, (sizeof(T) == 4 ? 2 : 1)>), grid, block, 0, s, probs, tiles,
-                           (int)H->ntiles);
-    else
-        hipLaunchKernelGGL((dpmlk::k_step_multi2d<T, 1>), grid, block, 0, s, probs, tiles, (int)H->ntiles);
+    constexpr int V2 = sizeof(T) == 4 ? 2 : 1;
+#define DPML_MULTI2D(VX_, R_) \
+    hipLaunchKernelGGL((dpmlk::k_step_multi2d<T, VX_, R_>), grid, block, 0, s, probs, tiles, (int)H->ntiles)
+    if (H->vx == 2) {
+        if (H->group == 4) DPML_MULTI2D(V2, 4);
+        else if (H->group == 2) DPML_MULTI2D(V2, 2);
+        else DPML_MULTI2D(V2, 1);
+    } else {
+        if (H->group == 4) DPML_MULTI2D(1, 4);
+        else if (H->group == 2) DPML_MULTI2D(1, 2);
+        else DPML_MULTI2D(1, 1);
+    }
+#undef DPML_MULTI2D
     HIP_TRY(nullptr, hipGetLastError());
     return DPML_OK;
 }
@@ -1924,6 +1948,7 @@ int dpml_multi_create(int64_t count, const dpml_grid_t *grids, const double *h, 
     H->ntiles = M.ntiles;
     H->vx = M.vx;
     H->tile_rows = kMultiTileRows;
+    H->group = kMultiGroup;
     int rc = H->dtype == DPML_F32 ? multi_tables<float>(H, sigmas) : multi_tables<double>(H, sigmas);
     if (rc) { g_multi_error = H->err.empty() ? g_create_error : H->err; delete H; return rc; }
     *out = H;
@@ -1976,6 +2001,25 @@ int dpml_multi_field(dpml_multi_t *H, int64_t prob, int32_t which, void **ptr, i
 }
 
 int64_t dpml_multi_tiles(const dpml_multi_t *H) { return H ? H->ntiles : -1; }
+
+int dpml_multi_set_variant(dpml_multi_t *H, int32_t tile_rows, int32_t group)
+{
+    if (!H) return DPML_EINVAL;
+    if (tile_rows == 0) tile_rows = kMultiTileRows;
+    if (group == 0) group = kMultiGroup;
+    if (tile_rows < kMultiMinRows || tile_rows > 4096 || (group != 1 && group != 2 && group != 4))
+        return H->fail(DPML_EINVAL, "tile_rows must be in [4, 4096] and group 1, 2 or 4");
+    if (tile_rows == H->tile_rows && group == H->group) return DPML_OK;
+    hipError_t e = hipStreamSynchronize(H->stream);       // the tables may be in use
+    if (e != hipSuccess) return H->fail(DPML_EHIP, hipGetErrorString(e));
+    H->tile_rows = tile_rows;
+    H->group = group;
+    if (H->exec) { (void)hipGraphExecDestroy(H->exec); H->exec = nullptr; }
+    if (H->graph) { (void)hipGraphDestroy(H->graph); H->graph = nullptr; }
+    H->graph_steps = -1;
+    int rc = H->dtype == DPML_F32 ? multi_shape<float>(H) : multi_shape<double>(H);
+    return rc ? H->fail(rc, H->err.empty() ? g_create_error : H->err) : DPML_OK;
+}
 
 int dpml_multi_sync(dpml_multi_t *H)
 {

@@ -875,7 +875,7 @@ __global__ void __launch_bounds__(256) k_step_frame(StepArgs<T> p, const TileRef
 // rows of one problem from the work list and marches down it (the shape the
 // tuner prefers for single 2D grids), so the per-block lookup of the
 // problem's arguments is amortised over 1024 VX cells.
-template <typename T, int VX>
+template <typename T, int VX, int R>
 __global__ void __launch_bounds__(256) k_step_multi2d(const StepArgs<T> *__restrict__ probs,
                                                       const TileRef *__restrict__ tiles, int ntiles)
 {
@@ -883,7 +883,7 @@ __global__ void __launch_bounds__(256) k_step_multi2d(const StepArgs<T> *__restr
     if (tile >= ntiles) return;
     const TileRef t = tiles[tile];
     const StepArgs<T> p = probs[t.prob];
-    march2d_tile<T, VX, 1, true>(p, t.tx, t.ty);
+    march2d_tile<T, VX, R, true>(p, t.tx, t.ty);
 }
 
 // ---------------------------------------------------------------------------

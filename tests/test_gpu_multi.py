@@ -89,3 +89,53 @@ def test_multi_single_problem_agrees_with_simulation():
     assert np.array_equal(m.field(0, dp.FIELD_U).cpu().numpy(), s.U.cpu().numpy())
     m.close()
     s.close()
+
+
+@pytest.mark.parametrize("dtype,sides", [(torch.float32, [64, 130, 256, 96, 300]),
+                                         (torch.float32, [64, 131, 257, 96, 300]),
+                                         (torch.float64, [64, 130, 257, 96, 300])])
+def test_multi_launch_shapes_bit_identical(dtype, sides):
+    """Every tile height and row-load group (tiles taller than a problem,
+    ragged last tiles) gives the same fields bit for bit; a captured graph is
+    dropped and recaptured after a shape change."""
+    probs = _problems(sides, [8, 13, 16, 9, 20])
+    print("case multi shapes %s sides=%s" % (dtype, sides), flush=True)
+    outs = []
+    for rows, group in [(4, 1), (5, 2), (32, 4), (64, 1), (333, 4), (0, 0)]:
+        sim = dp.MultiSimulation(probs, dtype=dtype)
+        sim.set_state([w.U0 for w in probs])
+        sim.step(10, graph=True)
+        sim.set_variant(rows, group)
+        sim.step(31, graph=True)
+        sim.step(20)
+        sim.sync()
+        outs.append([sim.field(i, f).cpu().numpy().copy() for i in range(len(probs))
+                     for f in (dp.FIELD_U, dp.FIELD_UPREV, dp.FIELD_PHI(0), dp.FIELD_PSI(1))])
+        sim.close()
+    for o in outs[1:]:
+        for a, b in zip(outs[0], o):
+            assert np.array_equal(a, b)
+
+
+def test_multi_set_variant_rejects_bad_shapes():
+    probs = _problems([64, 96], [8, 9])
+    sim = dp.MultiSimulation(probs, dtype=torch.float32)
+    for rows, group in [(3, 4), (5000, 4), (32, 3)]:
+        with pytest.raises(dp.DpmlError):
+            sim.set_variant(rows, group)
+    sim.close()
+
+
+def test_multi_tuner_picks_a_candidate_and_keeps_the_state(tmp_path):
+    from paper_1804_01390_amd import autotune
+    probs = _problems([200, 130, 96], [10, 13, 8])
+    sim = dp.MultiSimulation(probs, dtype=torch.float32)
+    U0s = [w.U0 for w in probs]
+    cands = [(8, 1), (32, 4)]
+    rec = autotune.tune_multi(sim, U0s, steps=3, candidates=cands, cache=str(tmp_path / "c.json"))
+    assert (rec["tile_rows"], rec["group"]) in cands and not rec["cached"]
+    for i, w in enumerate(probs):
+        assert np.array_equal(sim.field(i, dp.FIELD_U).cpu().numpy(), w.U0.astype(np.float32))
+    again = autotune.tune_multi(sim, U0s, steps=3, candidates=cands, cache=str(tmp_path / "c.json"))
+    assert again["cached"] and again["tile_rows"] == rec["tile_rows"]
+    sim.close()
