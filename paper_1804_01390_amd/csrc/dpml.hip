@@ -1817,10 +1817,21 @@ int multi_shape(dpml_multi *H)
     std::vector<dpmlk::TileRef> tiles;
     tiles.reserve((size_t)H->ntiles);
     for (int64_t p = 0; p < H->count; ++p) {
-        const int tx = (int)((H->L[p].N[0] + 256 * H->vx - 1) / (256 * H->vx));
-        const int ty = (int)((H->L[p].N[1] + H->tile_rows - 1) / H->tile_rows);
+        const Layout &L = H->L[p];
+        const int cw = 256 * H->vx;
+        const int tx = (int)((L.N[0] + cw - 1) / cw);
+        const int ty = (int)((L.N[1] + H->tile_rows - 1) / H->tile_rows);
+        // cells [lo+1, lo+n) of an axis with a layer meet no damping term
+        auto free_range = [&](int a, int64_t i0, int64_t i1) {
+            return L.M[a] == 0 || (i0 >= L.lo[a] + 1 && i1 <= L.lo[a] + L.n[a]);
+        };
         for (int y = 0; y < ty; ++y)
-            for (int x = 0; x < tx; ++x) tiles.push_back({(int32_t)p, x, y, 0});
+            for (int x = 0; x < tx; ++x) {
+                const int64_t x1 = std::min<int64_t>((int64_t)(x + 1) * cw, L.N[0]);
+                const int64_t y1 = std::min<int64_t>((int64_t)(y + 1) * H->tile_rows, L.N[1]);
+                const bool layer = !(free_range(0, (int64_t)x * cw, x1) && free_range(1, (int64_t)y * H->tile_rows, y1));
+                tiles.push_back({(int32_t)p, x, y, layer ? 1 : 0});
+            }
     }
     HIP_TRY(nullptr, hipMemcpy(H->ws + H->off_tiles, tiles.data(), tiles.size() * sizeof(tiles[0]),
                                hipMemcpyHostToDevice));

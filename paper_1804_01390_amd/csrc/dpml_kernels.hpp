@@ -362,7 +362,7 @@ __device__ __forceinline__ void store_row(T *ptr, const Row<T, VX> &r)
 // of its arithmetic, so each wave has R times more loads in flight than a
 // row-at-a-time loop.  Register arrays are only indexed with compile-time
 // constants (full groups); the last rows of a tile take a one-row loop.
-template <typename T, int VX, int R, bool HOIST = false>
+template <typename T, int VX, int R, bool HOIST = false, int AX = 7>
 __device__ __forceinline__ void march2d_tile(const StepArgs<T> &p, int tx, int ty)
 {
     const int x0 = (tx * 256 + (int)threadIdx.x) * VX;
@@ -395,8 +395,8 @@ __device__ __forceinline__ void march2d_tile(const StepArgs<T> &p, int tx, int t
         for (int k = 0; k < VX; ++k) {
             const T uxm = k == 0 ? left : uc.v[k - 1];
             const T uxp = k == VX - 1 ? right : uc.v[k + 1];
-            out.v[k] = cell_update<T, 2, 7, HOIST>(p, x0 + k, y, 0, row + x0 + k, uc.v[k], uxm, uxp,
-                                         um.v[k], up.v[k], T(0), T(0), old.v[k]);
+            out.v[k] = cell_update<T, 2, AX, HOIST>(p, x0 + k, y, 0, row + x0 + k, uc.v[k], uxm, uxp,
+                                          um.v[k], up.v[k], T(0), T(0), old.v[k]);
         }
         store_row<T, VX>((p.uout ? p.uout : p.uo) + row + x0, out);
         if (p.hist) store_row<T, VX>(p.hist + row + x0, out);
@@ -883,7 +883,12 @@ __global__ void __launch_bounds__(256) k_step_multi2d(const StepArgs<T> *__restr
     if (tile >= ntiles) return;
     const TileRef t = tiles[tile];
     const StepArgs<T> p = probs[t.prob];
-    march2d_tile<T, VX, R, true>(p, t.tx, t.ty);
+    // pad != 0: the tile holds cells with damping terms (layer code, hoisted
+    // loads); otherwise the plain stencil
+    if (t.pad)
+        march2d_tile<T, VX, R, true>(p, t.tx, t.ty);
+    else
+        march2d_tile<T, VX, R, false, 0>(p, t.tx, t.ty);
 }
 
 // ---------------------------------------------------------------------------
