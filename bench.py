@@ -370,8 +370,8 @@ def bench_batch(steps: int, count: int):
             "separate_value": round(cells * steps / (ms_sep * 1e-3) / 1e9, 3), "unit": "Gcell/s",
             "graph_ms": round(ms_graph, 3), "separate_ms": round(ms_sep, 3),
             "speedup": round(ms_sep / ms_graph, 3),
-            "launch": {"tile_rows": choice["tile_rows"], "group": choice["group"], "autotuned": True,
-                       "tiles": multi_tiles}}
+            "launch": {"variant": choice["variant"], "tile_rows": choice["tile_rows"], "group": choice["group"],
+                       "autotuned": True, "tiles": multi_tiles}}
 
 
 def bench_adjoint(steps: int, shots: int):

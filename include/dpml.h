@@ -337,13 +337,21 @@ int dpml_multi_field(dpml_multi_t *h, int64_t prob, int32_t which, void **ptr,
 /* Tiles in the work list of one step (for reporting). */
 int64_t dpml_multi_tiles(const dpml_multi_t *h);
 
-/* Launch shape of the many-problem kernel: each tile is 256 (FP32 with
- * even widths: 512) columns x tile_rows rows of one problem, marched down
- * with the loads of `group` rows issued together (1, 2 or 4).  0 selects
- * the default (32 rows, group 4).  Results do not depend on the shape.
- * Drops a captured graph.  DPML_EINVAL for tile_rows outside [4, 4096] or
- * another group. */
-int dpml_multi_set_variant(dpml_multi_t *h, int32_t tile_rows, int32_t group);
+/* Stepping scheme and launch shape of the many-problem path.
+ *   DPML_VARIANT_MARCH (or AUTO; the default): single steps, each tile 256
+ *     (FP32 with even widths: 512) columns x tile_rows rows of one problem
+ *     marched down with the loads of `group` rows issued together;
+ *     tile_rows in [4, 4096] (0: 32), group 1, 2 or 4 (0: 4).
+ *   DPML_VARIANT_TWOSTEP: two steps per pass (if every problem has a core
+ *     free of damping terms two cells deep; otherwise single steps): the
+ *     cores of all problems in one launch (each wave marches a strip of
+ *     tile_rows rows keeping U^n and U^{n+1} rows in registers, `group` rows
+ *     of loads at a time; tile_rows in [1, 4096] (0: 8), group 0: 2), the
+ *     frames of all problems as two single steps on a second stream
+ *     meanwhile; an odd last step is a single step.
+ * Results do not depend on the choice.  Drops a captured graph.
+ * DPML_EINVAL for another variant or a shape out of range. */
+int dpml_multi_set_variant(dpml_multi_t *h, int32_t variant, int32_t tile_rows, int32_t group);
 
 int dpml_multi_sync(dpml_multi_t *h);
 void dpml_multi_destroy(dpml_multi_t *h);

@@ -117,7 +117,7 @@ def load_library():
         "dpml_multi_field": (ctypes.c_int, [_VP, ctypes.c_int64, ctypes.c_int32, ctypes.POINTER(_VP),
                                             ctypes.c_int64 * 3]),
         "dpml_multi_tiles": (ctypes.c_int64, [_VP]),
-        "dpml_multi_set_variant": (ctypes.c_int, [_VP, ctypes.c_int32, ctypes.c_int32]),
+        "dpml_multi_set_variant": (ctypes.c_int, [_VP, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]),
         "dpml_multi_sync": (ctypes.c_int, [_VP]),
         "dpml_multi_destroy": (None, [_VP]),
         "dpml_multi_last_error": (ctypes.c_char_p, [_VP]),
@@ -472,12 +472,13 @@ class MultiSimulation:
     def step(self, nsteps: int, graph: bool = False):
         self._check(self.lib.dpml_multi_step(self.handle, int(nsteps), 1 if graph else 0))
 
-    def set_variant(self, tile_rows: int = 0, group: int = 0):
-        """Tile height and row-load group of the many-problem kernel (0:
-        default); results do not depend on them."""
-        self._check(self.lib.dpml_multi_set_variant(self.handle, int(tile_rows), int(group)))
+    def set_variant(self, variant: int = 0, tile_rows: int = 0, group: int = 0):
+        """Stepping scheme (VARIANT_MARCH single steps, VARIANT_TWOSTEP
+        two-step passes) and its tile height and row-load group (0:
+        defaults); results do not depend on them."""
+        self._check(self.lib.dpml_multi_set_variant(self.handle, int(variant), int(tile_rows), int(group)))
         self.tiles = int(self.lib.dpml_multi_tiles(self.handle))
-        self.launch = (int(tile_rows), int(group))
+        self.launch = (int(variant), int(tile_rows), int(group))
 
     def field(self, prob: int, which: int):
         ptr = _VP()

@@ -93,8 +93,9 @@ def tune(sim, steps: int = 50, candidates: Optional[Sequence[Tuple[int, int]]] =
     return dict(rec, cached=False)
 
 
-# many-problem kernel: (tile rows, rows loaded together)
-CANDIDATES_MULTI: List[Tuple[int, int]] = [(r, g) for r in (8, 16, 32, 64) for g in (1, 2, 4)]
+# many-problem path: (variant, tile rows, rows loaded together)
+CANDIDATES_MULTI: List[Tuple[int, int, int]] = ([(VARIANT_MARCH, r, g) for r in (8, 16, 32, 64) for g in (1, 2, 4)]
+                                              + [(VARIANT_TWOSTEP, r, g) for r in (4, 8, 16) for g in (2, 4)])
 
 
 def multi_key(multi) -> str:
@@ -102,23 +103,23 @@ def multi_key(multi) -> str:
                                     "-".join("x".join(str(n) for n in sh) for sh in multi.shapes[:4]))
 
 
-def tune_multi(multi, U0s, steps: int = 20, candidates: Optional[Sequence[Tuple[int, int]]] = None,
+def tune_multi(multi, U0s, steps: int = 20, candidates: Optional[Sequence[Tuple[int, int, int]]] = None,
                cache: Optional[str] = DEFAULT_CACHE, force: bool = False) -> Dict:
-    """Pick and apply the fastest (tile_rows, group) of the many-problem
-    kernel for ``multi``, timing ``steps`` eager steps from ``U0s`` per
-    candidate.  Leaves the problems at ``U0s``.  Returns {"tile_rows",
-    "group", "ms_per_step", "timings"}."""
+    """Pick and apply the fastest (variant, tile_rows, group) of the
+    many-problem path for ``multi``, timing ``steps`` eager steps from
+    ``U0s`` per candidate.  Leaves the problems at ``U0s``.  Returns
+    {"variant", "tile_rows", "group", "ms_per_step", "timings"}."""
     torch = multi.torch
     key = multi_key(multi)
     db = _load(cache) if cache else {}
     if not force and key in db:
         best = db[key]
-        multi.set_variant(best["tile_rows"], best["group"])
+        multi.set_variant(best["variant"], best["tile_rows"], best["group"])
         multi.set_state(U0s)
         return dict(best, cached=True)
     timings = []
-    for rows, group in (candidates if candidates is not None else CANDIDATES_MULTI):
-        multi.set_variant(rows, group)
+    for variant, rows, group in (candidates if candidates is not None else CANDIDATES_MULTI):
+        multi.set_variant(variant, rows, group)
         multi.set_state(U0s)
         multi.step(2)
         multi.sync()
@@ -128,11 +129,12 @@ def tune_multi(multi, U0s, steps: int = 20, candidates: Optional[Sequence[Tuple[
         multi.step(steps)
         e1.record()
         torch.cuda.synchronize()
-        timings.append({"tile_rows": rows, "group": group, "ms_per_step": e0.elapsed_time(e1) / steps})
+        timings.append({"variant": variant, "tile_rows": rows, "group": group,
+                        "ms_per_step": e0.elapsed_time(e1) / steps})
     best = min(timings, key=lambda t: t["ms_per_step"])
-    rec = {"tile_rows": best["tile_rows"], "group": best["group"], "ms_per_step": best["ms_per_step"],
-           "timings": timings}
-    multi.set_variant(rec["tile_rows"], rec["group"])
+    rec = {"variant": best["variant"], "tile_rows": best["tile_rows"], "group": best["group"],
+           "ms_per_step": best["ms_per_step"], "timings": timings}
+    multi.set_variant(rec["variant"], rec["tile_rows"], rec["group"])
     multi.set_state(U0s)
     if cache:
         db = _load(cache)

@@ -1695,19 +1695,32 @@ struct dpml_multi {
     char *ws = nullptr;
     hipStream_t stream = nullptr;
     hipStream_t cap = nullptr;       // private stream used only for graph capture
-    size_t off_desc[2] = {0, 0};     // device StepArgs tables for buffer parity 0 / 1
-    size_t off_tiles = 0;
+    size_t off_tiles = 0;            // single-step tile list (workspace)
     int64_t ntiles = 0;
     int vx = 1;
-    int tile_rows = 32;              // rows per marching tile
-    int group = 4;                   // rows whose loads are issued together
-    int parity = 0;                  // 0: buffers u0/aux0 hold level n
+    int variant = DPML_VARIANT_MARCH;  // MARCH: single steps; TWOSTEP: two-step passes
+    int tile_rows = 32;              // single steps: rows per marching tile
+    int group = 4;                   // single steps: rows whose loads are issued together
+    int pass_rows = 8;               // two-step passes: rows per core wave
+    int pass_group = 2;              // two-step passes: rows whose loads are issued together
+    // rotation state: U buffers holding levels n and n-1, aux buffer of level n
+    int now = 0, old = 1, cur = 0;
     int64_t n = 0;
     bool state_set = false;
+    // library-owned tables: step arguments per rotation state and role, and
+    // the work lists of the two-step passes
+    std::vector<void *> d_args;      // [state * 4 + role]
+    dpmlk::TileRef *d_core_waves = nullptr;
+    int64_t n_core_waves = -1;       // -1: not built for pass_rows yet
+    dpmlk::TileRef *d_frame[2] = {nullptr, nullptr};
+    int64_t n_frame[2] = {-1, -1};
+    int pass_ok = -1;                // every problem has a two-step core (-1: not checked)
+    hipStream_t side = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     hipGraphExec_t exec = nullptr;
     hipGraph_t graph = nullptr;
     int64_t graph_steps = -1;
-    int graph_parity = -1;
+    int graph_state = -1;
     std::string err;
     int fail(int code, const std::string &m) { err = m; return code; }
 };
@@ -1719,16 +1732,27 @@ thread_local std::string g_multi_error;
 struct MultiLayout {
     std::vector<Layout> L;
     std::vector<size_t> base;
-    size_t off_desc[2] = {0, 0}, off_tiles = 0, total = 0;
+    size_t off_tiles = 0, total = 0;
     int64_t ntiles = 0;
     int vx = 1;
 };
 
-// The tile list is sized for the shortest tiles allowed (kMultiMinRows rows);
-// the default tiles are 256 VX columns x 32 rows, marched 4 rows at a time.
+// The single-step tile list is sized for the shortest tiles allowed
+// (kMultiMinRows rows); the default tiles are 256 VX columns x 32 rows,
+// marched 4 rows at a time.  Each problem holds four U buffers (the two-step
+// passes write U^{n+1} and U^{n+2} while other waves still read U^n and
+// U^{n-1}).
 constexpr int kMultiMinRows = 4;
 constexpr int kMultiTileRows = 32;
 constexpr int kMultiGroup = 4;
+constexpr int kMultiPassRows = 8;
+constexpr int kMultiPassGroup = 2;
+constexpr int kMultiUbufs = 4;
+
+// roles of the argument tables of one rotation state
+enum { kRoleStep = 0, kRoleCore = 1, kRoleFrame1 = 2, kRoleFrame2 = 3 };
+
+int state_key(int now, int old, int cur) { return (now * 4 + old) * 2 + cur; }
 
 std::string multi_layout(int64_t count, const dpml_grid_t *grids, MultiLayout &M)
 {
@@ -1743,7 +1767,7 @@ std::string multi_layout(int64_t count, const dpml_grid_t *grids, MultiLayout &M
         if (grids[p].dtype != dtype) return "all problems must share one dtype";
         if (grids[p].batch > 1) return "multi-problem grids take no batch";
         if (grids[p].walls[0] || grids[p].walls[1]) return "multi-problem grids are periodic";
-        std::string e = make_layout(&grids[p], false, M.L[p], 2);
+        std::string e = make_layout(&grids[p], false, M.L[p], kMultiUbufs);
         if (!e.empty()) return "problem " + std::to_string(p) + ": " + e;
         M.base[p] = off;
         off += align_up(M.L[p].total);
@@ -1757,16 +1781,15 @@ std::string multi_layout(int64_t count, const dpml_grid_t *grids, MultiLayout &M
         nt += tx * ty;
     }
     M.ntiles = nt;
-    const size_t argsz = dtype == DPML_F32 ? sizeof(dpmlk::StepArgs<float>) : sizeof(dpmlk::StepArgs<double>);
-    for (int k = 0; k < 2; ++k) { M.off_desc[k] = off; off += align_up((size_t)count * argsz); }
     M.off_tiles = off; off += align_up((size_t)nt * sizeof(dpmlk::TileRef));
     M.total = off;
     return "";
 }
 
-// A throw-away single-problem view of problem p at buffer parity q, so the
-// single-problem argument builders can be reused.
-dpml problem_view(const dpml_multi *H, int64_t p, int q)
+// A throw-away single-problem view of problem p with U buffers `now` and
+// `old` and aux buffer `cur` holding level n, so the single-problem argument
+// builders can be reused.
+dpml problem_view(const dpml_multi *H, int64_t p, int now, int old, int cur)
 {
     dpml v;
     v.L = H->L[p];
@@ -1775,10 +1798,18 @@ dpml problem_view(const dpml_multi *H, int64_t p, int q)
     v.dt = H->dt[p];
     v.c2_const = 1.0;
     v.c2_field = false;
-    v.cur = q;
-    v.u_now = v.at(v.L.off_u[q]);
-    v.u_old = v.at(v.L.off_u[1 - q]);
+    v.cur = cur;
+    v.u_now = v.at(v.L.off_u[now]);
+    v.u_old = v.at(v.L.off_u[old]);
     return v;
+}
+
+// The two spare U buffers of a rotation state, in ascending order.
+void spares(int now, int old, int s[2])
+{
+    int k = 0;
+    for (int i = 0; i < kMultiUbufs && k < 2; ++i)
+        if (i != now && i != old) s[k++] = i;
 }
 
 template <typename T>
@@ -1789,7 +1820,7 @@ int multi_tables(dpml_multi *H, const double *const *sigmas)
 {
     // damping tables of every problem
     for (int64_t p = 0; p < H->count; ++p) {
-        dpml v = problem_view(H, p, 0);
+        dpml v = problem_view(H, p, 0, 1, 0);
         const double *sg[3] = {sigmas[3 * p], sigmas[3 * p + 1], nullptr};
         double one = 1.0;
         int rc = upload_tables<T>(&v, &one, 1, sg);
@@ -1798,22 +1829,13 @@ int multi_tables(dpml_multi *H, const double *const *sigmas)
     return multi_shape<T>(H);
 }
 
-// Argument tables for both buffer parities and the tile list, for the
-// handle's tile height.
+// The single-step tile list for the handle's tile height (workspace); the
+// argument tables built for earlier shapes are dropped.
 template <typename T>
 int multi_shape(dpml_multi *H)
 {
-    for (int q = 0; q < 2; ++q) {
-        std::vector<dpmlk::StepArgs<T>> args((size_t)H->count);
-        for (int64_t p = 0; p < H->count; ++p) {
-            dpml v = problem_view(H, p, q);
-            args[p] = make_args<T>(&v);
-            args[p].tile_rows = H->tile_rows;
-            args[p].tiles_x = (int)((v.L.N[0] + 256 * H->vx - 1) / (256 * H->vx));
-        }
-        HIP_TRY(nullptr, hipMemcpy(H->ws + H->off_desc[q], args.data(), args.size() * sizeof(args[0]),
-                                   hipMemcpyHostToDevice));
-    }
+    for (void *&d : H->d_args)
+        if (d) { (void)hipFree(d); d = nullptr; }
     std::vector<dpmlk::TileRef> tiles;
     tiles.reserve((size_t)H->ntiles);
     for (int64_t p = 0; p < H->count; ++p) {
@@ -1840,10 +1862,124 @@ int multi_shape(dpml_multi *H)
 }
 
 template <typename T>
-int multi_launch(dpml_multi *H, hipStream_t s, int parity)
+int upload_table(dpml_multi *H, int slot, const void *data, size_t bytes)
+{
+    if ((size_t)slot >= H->d_args.size()) H->d_args.resize((size_t)slot + 1, nullptr);
+    if (!H->d_args[slot]) HIP_TRY(nullptr, hipMalloc(&H->d_args[slot], bytes));
+    HIP_TRY(nullptr, hipMemcpy(H->d_args[slot], data, bytes, hipMemcpyHostToDevice));
+    return DPML_OK;
+}
+
+// Argument tables of rotation state (now, old, cur): one step in place, and
+// for a two-step pass the core descriptors and the two frame steps.  Built
+// once per state (outside any capture) and kept.
+template <typename T>
+int ensure_state(dpml_multi *H, int now, int old, int cur, bool pass)
+{
+    const int key = state_key(now, old, cur);
+    const int need = pass ? kRoleFrame2 : kRoleStep;
+    bool have = true;
+    for (int role = 0; role <= need; ++role) {
+        const size_t slot = (size_t)key * 4 + role;
+        if (slot >= H->d_args.size() || !H->d_args[slot]) have = false;
+    }
+    if (have) return DPML_OK;
+    const size_t c = (size_t)H->count;
+    std::vector<dpmlk::StepArgs<T>> step(c), f1(c), f2(c);
+    std::vector<dpmlk::MultiCore<T>> core(c);
+    int sp[2];
+    spares(now, old, sp);
+    for (int64_t p = 0; p < H->count; ++p) {
+        dpml v = problem_view(H, p, now, old, cur);
+        step[p] = make_args<T>(&v);
+        step[p].tile_rows = H->tile_rows;
+        step[p].tiles_x = (int)((v.L.N[0] + 256 * H->vx - 1) / (256 * H->vx));
+        if (!pass) continue;
+        T *bufC = (T *)v.at(v.L.off_u[sp[0]]), *bufD = (T *)v.at(v.L.off_u[sp[1]]);
+        int r[4];
+        core_rect(v.L, 2, r);
+        core[p].p = make_args<T>(&v);
+        core[p].p.uout = bufC;
+        core[p].p.tile_rows = H->pass_rows;
+        for (int k = 0; k < 4; ++k) core[p].p.skip[k] = r[k];
+        core[p].next2 = bufD;
+        f1[p] = make_args<T>(&v);
+        f1[p].uout = bufC;
+        f1[p].skip[0] = r[0] + 1; f1[p].skip[1] = r[1] - 1; f1[p].skip[2] = r[2] + 1; f1[p].skip[3] = r[3] - 1;
+        dpml w = problem_view(H, p, sp[0], now, 1 - cur);
+        f2[p] = make_args<T>(&w);
+        f2[p].uout = bufD;
+        for (int k = 0; k < 4; ++k) f2[p].skip[k] = r[k];
+    }
+    int rc = upload_table<T>(H, key * 4 + kRoleStep, step.data(), c * sizeof(step[0]));
+    if (rc || !pass) return rc;
+    rc = upload_table<T>(H, key * 4 + kRoleCore, core.data(), c * sizeof(core[0]));
+    if (!rc) rc = upload_table<T>(H, key * 4 + kRoleFrame1, f1.data(), c * sizeof(f1[0]));
+    if (!rc) rc = upload_table<T>(H, key * 4 + kRoleFrame2, f2.data(), c * sizeof(f2[0]));
+    return rc;
+}
+
+// Do all problems have a core for two-step passes?
+bool multi_pass_ok(dpml_multi *H)
+{
+    if (H->pass_ok < 0) {
+        H->pass_ok = 1;
+        for (int64_t p = 0; p < H->count; ++p) {
+            int r[4];
+            core_rect(H->L[p], 2, r);
+            if (H->L[p].N[0] < 8 || H->L[p].N[1] < 8 || r[1] - r[0] < 1 || r[3] - r[2] < 1) H->pass_ok = 0;
+        }
+    }
+    return H->pass_ok == 1;
+}
+
+// Work lists of the two-step passes: the core waves (problem, strip, tile
+// row) for pass_rows, and the 64 x 4 frame tiles outside each core shrunk by
+// s = 1 (first frame step) and s = 0 (second).
+int ensure_pass_lists(dpml_multi *H)
+{
+    if (H->n_core_waves >= 0) return DPML_OK;
+    std::vector<dpmlk::TileRef> waves, fr[2];
+    for (int64_t p = 0; p < H->count; ++p) {
+        const Layout &L = H->L[p];
+        int r[4];
+        core_rect(L, 2, r);
+        const int VX = multistep_vx(L);
+        const int strips = (r[1] - r[0] + 62 * VX - 1) / (62 * VX);
+        const int tys = (r[3] - r[2] + H->pass_rows - 1) / H->pass_rows;
+        for (int ty = 0; ty < tys; ++ty)
+            for (int s = 0; s < strips; ++s) waves.push_back({(int32_t)p, s, ty, 0});
+        const int tx = (int)((L.N[0] + 63) / 64), ty4 = (int)((L.N[1] + 3) / 4);
+        for (int sh = 0; sh < 2; ++sh) {
+            const int q0 = r[0] + sh, q1 = r[1] - sh, q2 = r[2] + sh, q3 = r[3] - sh;
+            for (int y = 0; y < ty4; ++y)
+                for (int x = 0; x < tx; ++x) {
+                    const int xa = x * 64, xb = std::min<int>(xa + 64, (int)L.N[0]);
+                    const int ya = y * 4, yb = std::min<int>(ya + 4, (int)L.N[1]);
+                    if (!(xa >= q0 && xb <= q1 && ya >= q2 && yb <= q3)) fr[1 - sh].push_back({(int32_t)p, x, y, 0});
+                }
+        }
+    }
+    // fr[0]: outside the core shrunk by 1 (first frame step); fr[1]: outside the core
+    HIP_TRY(nullptr, hipMalloc((void **)&H->d_core_waves, std::max<size_t>(1, waves.size()) * sizeof(waves[0])));
+    HIP_TRY(nullptr, hipMemcpy(H->d_core_waves, waves.data(), waves.size() * sizeof(waves[0]), hipMemcpyHostToDevice));
+    for (int k = 0; k < 2; ++k) {
+        HIP_TRY(nullptr, hipMalloc((void **)&H->d_frame[k], std::max<size_t>(1, fr[k].size()) * sizeof(fr[k][0])));
+        HIP_TRY(nullptr, hipMemcpy(H->d_frame[k], fr[k].data(), fr[k].size() * sizeof(fr[k][0]), hipMemcpyHostToDevice));
+        H->n_frame[k] = (int64_t)fr[k].size();
+    }
+    H->n_core_waves = (int64_t)waves.size();
+    if (!H->side) HIP_TRY(nullptr, hipStreamCreateWithFlags(&H->side, hipStreamNonBlocking));
+    if (!H->ev_fork) HIP_TRY(nullptr, hipEventCreateWithFlags(&H->ev_fork, hipEventDisableTiming));
+    if (!H->ev_join) HIP_TRY(nullptr, hipEventCreateWithFlags(&H->ev_join, hipEventDisableTiming));
+    return DPML_OK;
+}
+
+template <typename T>
+int multi_launch_step(dpml_multi *H, hipStream_t s, int key)
 {
     const dim3 grid((unsigned)round8((int)H->ntiles)), block(256);
-    const auto *probs = (const dpmlk::StepArgs<T> *)(H->ws + H->off_desc[parity]);
+    const auto *probs = (const dpmlk::StepArgs<T> *)H->d_args[(size_t)key * 4 + kRoleStep];
     const auto *tiles = (const dpmlk::TileRef *)(H->ws + H->off_tiles);
     constexpr int V2 = sizeof(T) == 4 ? 2 : 1;
 #define DPML_MULTI2D(VX_, R_) \
@@ -1862,46 +1998,121 @@ int multi_launch(dpml_multi *H, hipStream_t s, int parity)
     return DPML_OK;
 }
 
+// One two-step pass of every problem: the core waves on stream s, the two
+// frame steps on the side stream meanwhile (fork/join events).
+template <typename T>
+int multi_launch_pass(dpml_multi *H, hipStream_t s, int key)
+{
+    constexpr int VX = sizeof(T) == 4 ? 4 : 2;
+    const auto *cores = (const dpmlk::MultiCore<T> *)H->d_args[(size_t)key * 4 + kRoleCore];
+    const auto *f1 = (const dpmlk::StepArgs<T> *)H->d_args[(size_t)key * 4 + kRoleFrame1];
+    const auto *f2 = (const dpmlk::StepArgs<T> *)H->d_args[(size_t)key * 4 + kRoleFrame2];
+    const dim3 block(256);
+    HIP_TRY(nullptr, hipEventRecord(H->ev_fork, s));
+    HIP_TRY(nullptr, hipStreamWaitEvent(H->side, H->ev_fork, 0));
+    const int nw = (int)H->n_core_waves;
+    const dim3 grid((unsigned)round8((nw + 3) / 4));
+    if (H->pass_group == 4)
+        hipLaunchKernelGGL((dpmlk::k_multi_step2_march<T, VX, 4>), grid, block, 0, s, cores, H->d_core_waves, nw);
+    else if (H->pass_group == 1)
+        hipLaunchKernelGGL((dpmlk::k_multi_step2_march<T, VX, 1>), grid, block, 0, s, cores, H->d_core_waves, nw);
+    else
+        hipLaunchKernelGGL((dpmlk::k_multi_step2_march<T, VX, 2>), grid, block, 0, s, cores, H->d_core_waves, nw);
+    for (int k = 0; k < 2; ++k) {
+        const int nf = (int)H->n_frame[k];
+        if (nf > 0)
+            hipLaunchKernelGGL((dpmlk::k_multi_frame<T>), dim3((unsigned)round8(nf)), block, 0, H->side,
+                               k == 0 ? f1 : f2, H->d_frame[k], nf);
+    }
+    HIP_TRY(nullptr, hipEventRecord(H->ev_join, H->side));
+    HIP_TRY(nullptr, hipStreamWaitEvent(s, H->ev_join, 0));
+    HIP_TRY(nullptr, hipGetLastError());
+    return DPML_OK;
+}
+
+// nsteps steps from the handle's rotation state: two-step passes while two
+// or more steps remain (variant TWOSTEP), then single steps.  kPrepare only
+// builds the tables the run needs (before a capture); kLaunch enqueues the
+// run on stream s and advances the rotation state; kAdvance only advances
+// it (after a graph replay).
+enum { kPrepare = 0, kLaunch = 1, kAdvance = 2 };
+
+template <typename T>
+int multi_run(dpml_multi *H, hipStream_t s, int64_t nsteps, int mode)
+{
+    const bool passes = H->variant == DPML_VARIANT_TWOSTEP && multi_pass_ok(H);
+    if (passes && nsteps >= 2 && mode != kAdvance) {
+        int rc = ensure_pass_lists(H);
+        if (rc) return rc;
+    }
+    int now = H->now, old = H->old, cur = H->cur;
+    int64_t k = 0;
+    for (; passes && nsteps - k >= 2; k += 2) {
+        int rc = mode == kAdvance ? DPML_OK : ensure_state<T>(H, now, old, cur, true);
+        if (!rc && mode == kLaunch) rc = multi_launch_pass<T>(H, s, state_key(now, old, cur));
+        if (rc) return rc;
+        int sp[2];
+        spares(now, old, sp);
+        now = sp[1];
+        old = sp[0];
+    }
+    for (; k < nsteps; ++k) {
+        int rc = mode == kAdvance ? DPML_OK : ensure_state<T>(H, now, old, cur, false);
+        if (!rc && mode == kLaunch) rc = multi_launch_step<T>(H, s, state_key(now, old, cur));
+        if (rc) return rc;
+        std::swap(now, old);
+        cur = 1 - cur;
+    }
+    if (mode != kPrepare) {
+        H->now = now;
+        H->old = old;
+        H->cur = cur;
+        H->n += nsteps;
+    }
+    return DPML_OK;
+}
+
 template <typename T>
 int multi_step_impl(dpml_multi *H, int64_t nsteps, bool use_graph)
 {
     if (!use_graph) {
-        for (int64_t k = 0; k < nsteps; ++k) {
-            int rc = multi_launch<T>(H, H->stream, H->parity);
-            if (rc) return H->fail(rc, g_create_error);
-            H->parity ^= 1;
-        }
-        H->n += nsteps;
-        return DPML_OK;
+        int rc = multi_run<T>(H, H->stream, nsteps, kLaunch);
+        return rc ? H->fail(rc, g_create_error) : DPML_OK;
     }
-    if (!(H->exec && H->graph_steps == nsteps && H->graph_parity == H->parity)) {
+    const int state = state_key(H->now, H->old, H->cur);
+    if (!(H->exec && H->graph_steps == nsteps && H->graph_state == state)) {
         if (H->exec) { (void)hipGraphExecDestroy(H->exec); H->exec = nullptr; }
         if (H->graph) { (void)hipGraphDestroy(H->graph); H->graph = nullptr; }
         if (!H->cap) {
             hipError_t e = hipStreamCreateWithFlags(&H->cap, hipStreamNonBlocking);
             if (e != hipSuccess) return H->fail(DPML_EHIP, hipGetErrorString(e));
         }
+        int rc = multi_run<T>(H, H->cap, nsteps, kPrepare);     // tables before the capture
+        if (rc) return H->fail(rc, g_create_error);
+        const int now = H->now, old = H->old, cur = H->cur;
+        const int64_t n0 = H->n;
         hipError_t e = hipStreamBeginCapture(H->cap, hipStreamCaptureModeRelaxed);
         if (e != hipSuccess) return H->fail(DPML_EHIP, hipGetErrorString(e));
-        int q = H->parity, rc = DPML_OK;
-        for (int64_t k = 0; k < nsteps && rc == DPML_OK; ++k, q ^= 1) rc = multi_launch<T>(H, H->cap, q);
+        rc = multi_run<T>(H, H->cap, nsteps, kLaunch);
         e = hipStreamEndCapture(H->cap, &H->graph);
+        // the capture only recorded the launches: the state advances at the replay
+        H->now = now;
+        H->old = old;
+        H->cur = cur;
+        H->n = n0;
         if (rc) return H->fail(rc, g_create_error);
         if (e != hipSuccess) return H->fail(DPML_EHIP, hipGetErrorString(e));
         e = hipGraphInstantiate(&H->exec, H->graph, nullptr, nullptr, 0);
         if (e != hipSuccess) return H->fail(DPML_EHIP, hipGetErrorString(e));
         H->graph_steps = nsteps;
-        H->graph_parity = H->parity;
+        H->graph_state = state;
     }
     hipError_t e = hipGraphLaunch(H->exec, H->stream);
     if (e != hipSuccess) return H->fail(DPML_EHIP, hipGetErrorString(e));
-    H->parity ^= (int)(nsteps & 1);
-    H->n += nsteps;
-    return DPML_OK;
+    return multi_run<T>(H, H->stream, nsteps, kAdvance);
 }
 
 }  // namespace
-
 extern "C" {
 
 size_t dpml_multi_workspace_bytes(int64_t count, const dpml_grid_t *grids)
@@ -1953,13 +2164,13 @@ int dpml_multi_create(int64_t count, const dpml_grid_t *grids, const double *h, 
     H->dt.assign(dt, dt + count);
     H->ws = (char *)workspace;
     H->stream = (hipStream_t)stream;
-    H->off_desc[0] = M.off_desc[0];
-    H->off_desc[1] = M.off_desc[1];
     H->off_tiles = M.off_tiles;
     H->ntiles = M.ntiles;
     H->vx = M.vx;
     H->tile_rows = kMultiTileRows;
     H->group = kMultiGroup;
+    H->pass_rows = kMultiPassRows;
+    H->pass_group = kMultiPassGroup;
     int rc = H->dtype == DPML_F32 ? multi_tables<float>(H, sigmas) : multi_tables<double>(H, sigmas);
     if (rc) { g_multi_error = H->err.empty() ? g_create_error : H->err; delete H; return rc; }
     *out = H;
@@ -1972,13 +2183,15 @@ int dpml_multi_set_state(dpml_multi_t *H, const void *const *U0)
     if (!U0) return H->fail(DPML_EINVAL, "U0 is NULL");
     for (int64_t p = 0; p < H->count; ++p) {
         if (!U0[p]) return H->fail(DPML_EINVAL, "U0[" + std::to_string(p) + "] is NULL");
-        dpml v = problem_view(H, p, 0);
+        dpml v = problem_view(H, p, 0, 1, 0);
         v.stream = H->stream;
         int rc = H->dtype == DPML_F32 ? set_state_impl<float>(&v, U0[p], nullptr)
                                       : set_state_impl<double>(&v, U0[p], nullptr);
         if (rc) return H->fail(rc, v.err);
     }
-    H->parity = 0;
+    H->now = 0;
+    H->old = 1;
+    H->cur = 0;
     H->n = 0;
     H->state_set = true;
     return DPML_OK;
@@ -2001,9 +2214,9 @@ int dpml_multi_field(dpml_multi_t *H, int64_t prob, int32_t which, void **ptr, i
     const Layout &L = H->L[prob];
     char *b = H->ws + H->base[prob];
     for (int a = 0; a < 3; ++a) shape[a] = L.N[a];
-    const int q = H->parity;
-    if (which == DPML_FIELD_U) { *ptr = b + L.off_u[q]; return DPML_OK; }
-    if (which == DPML_FIELD_UPREV) { *ptr = b + L.off_u[1 - q]; return DPML_OK; }
+    const int q = H->cur;
+    if (which == DPML_FIELD_U) { *ptr = b + L.off_u[H->now]; return DPML_OK; }
+    if (which == DPML_FIELD_UPREV) { *ptr = b + L.off_u[H->old]; return DPML_OK; }
     const int a = (which - 2) / 2;
     if (which < 2 || a >= L.ndim || L.M[a] == 0) return H->fail(DPML_EINVAL, "no such field");
     shape[a] = L.M[a] + 1;
@@ -2013,21 +2226,38 @@ int dpml_multi_field(dpml_multi_t *H, int64_t prob, int32_t which, void **ptr, i
 
 int64_t dpml_multi_tiles(const dpml_multi_t *H) { return H ? H->ntiles : -1; }
 
-int dpml_multi_set_variant(dpml_multi_t *H, int32_t tile_rows, int32_t group)
+int dpml_multi_set_variant(dpml_multi_t *H, int32_t variant, int32_t tile_rows, int32_t group)
 {
     if (!H) return DPML_EINVAL;
-    if (tile_rows == 0) tile_rows = kMultiTileRows;
-    if (group == 0) group = kMultiGroup;
-    if (tile_rows < kMultiMinRows || tile_rows > 4096 || (group != 1 && group != 2 && group != 4))
-        return H->fail(DPML_EINVAL, "tile_rows must be in [4, 4096] and group 1, 2 or 4");
-    if (tile_rows == H->tile_rows && group == H->group) return DPML_OK;
+    if (variant == DPML_VARIANT_AUTO) variant = DPML_VARIANT_MARCH;
+    if (variant != DPML_VARIANT_MARCH && variant != DPML_VARIANT_TWOSTEP)
+        return H->fail(DPML_EINVAL, "variant must be DPML_VARIANT_MARCH or DPML_VARIANT_TWOSTEP");
+    const bool pass = variant == DPML_VARIANT_TWOSTEP;
+    if (tile_rows == 0) tile_rows = pass ? kMultiPassRows : kMultiTileRows;
+    if (group == 0) group = pass ? kMultiPassGroup : kMultiGroup;
+    if (tile_rows < (pass ? 1 : kMultiMinRows) || tile_rows > 4096 || (group != 1 && group != 2 && group != 4))
+        return H->fail(DPML_EINVAL, "tile_rows must be in [4, 4096] ([1, 4096] for TWOSTEP) and group 1, 2 or 4");
     hipError_t e = hipStreamSynchronize(H->stream);       // the tables may be in use
     if (e != hipSuccess) return H->fail(DPML_EHIP, hipGetErrorString(e));
-    H->tile_rows = tile_rows;
-    H->group = group;
     if (H->exec) { (void)hipGraphExecDestroy(H->exec); H->exec = nullptr; }
     if (H->graph) { (void)hipGraphDestroy(H->graph); H->graph = nullptr; }
     H->graph_steps = -1;
+    H->variant = variant;
+    if (pass) {
+        if (tile_rows != H->pass_rows) {
+            if (H->d_core_waves) { (void)hipFree(H->d_core_waves); H->d_core_waves = nullptr; }
+            for (int k = 0; k < 2; ++k)
+                if (H->d_frame[k]) { (void)hipFree(H->d_frame[k]); H->d_frame[k] = nullptr; }
+            H->n_core_waves = H->n_frame[0] = H->n_frame[1] = -1;
+        }
+        H->pass_rows = tile_rows;
+        H->pass_group = group;
+        for (void *&d : H->d_args)                      // the core tables hold the wave height
+            if (d) { (void)hipFree(d); d = nullptr; }
+        return DPML_OK;
+    }
+    H->tile_rows = tile_rows;
+    H->group = group;
     int rc = H->dtype == DPML_F32 ? multi_shape<float>(H) : multi_shape<double>(H);
     return rc ? H->fail(rc, H->err.empty() ? g_create_error : H->err) : DPML_OK;
 }
@@ -2047,6 +2277,14 @@ void dpml_multi_destroy(dpml_multi_t *H)
     if (H->exec) (void)hipGraphExecDestroy(H->exec);
     if (H->graph) (void)hipGraphDestroy(H->graph);
     if (H->cap) (void)hipStreamDestroy(H->cap);
+    for (void *d : H->d_args)
+        if (d) (void)hipFree(d);
+    if (H->d_core_waves) (void)hipFree(H->d_core_waves);
+    for (int k = 0; k < 2; ++k)
+        if (H->d_frame[k]) (void)hipFree(H->d_frame[k]);
+    if (H->ev_fork) (void)hipEventDestroy(H->ev_fork);
+    if (H->ev_join) (void)hipEventDestroy(H->ev_join);
+    if (H->side) (void)hipStreamDestroy(H->side);
     delete H;
 }
 

@@ -708,6 +708,72 @@ __global__ void __launch_bounds__(256) k_step2_march(StepArgs<T> p, T *__restric
         c.template march<G, 1>(ya, yb - ya);
 }
 
+// Many problems, two-step passes: the waves of every problem's core in one
+// launch.  Each problem's descriptor holds its step arguments (U^n, U^{n-1},
+// U^{n+1} in u, uo, uout; the core rectangle in skip; tile rows in
+// tile_rows) and its U^{n+2}; the work list holds one (problem, strip, tile
+// row) entry per wave.
+template <typename T>
+struct MultiCore {
+    StepArgs<T> p;
+    T *next2;
+};
+
+template <typename T, int VX, int G>
+__global__ void __launch_bounds__(256) k_multi_step2_march(const MultiCore<T> *__restrict__ cores,
+                                                           const TileRef *__restrict__ waves, int n_waves)
+{
+    const int w = __builtin_amdgcn_readfirstlane(xcd_tile(blockIdx.x, gridDim.x) * 4 + (int)(threadIdx.x >> 6));
+    if (w >= n_waves) return;                                // whole waves; no barriers below
+    const int lane = (int)(threadIdx.x & 63);
+    const TileRef t = waves[w];
+    const StepArgs<T> &p = cores[t.prob].p;
+    March2Ctx<T, VX, false> c;
+    c.u = p.u;
+    c.up = p.uo;
+    c.c2 = nullptr;
+    c.o1 = p.uout;
+    c.o2 = cores[t.prob].next2;
+    c.inv_h2 = p.inv_h2;
+    c.dt2 = p.dt2;
+    c.c2c = p.c2_const;
+    c.nx = p.nx;
+    c.ny = p.ny;
+    c.cx0 = p.skip[0];
+    c.cx1 = p.skip[1];
+    c.cy0 = p.skip[2];
+    c.cy1 = p.skip[3];
+    c.xs = c.cx0 + (t.tx * 62 + lane - 1) * VX;
+    c.need = c.xs < c.cx1 + VX;
+    c.xw = c.xs % c.nx;
+    if (c.xw < 0) c.xw += c.nx;
+    c.vec = c.xw % VX == 0 && c.xw + VX <= c.nx;
+    c.out = lane >= 1 && lane <= 62 && c.xs < c.cx1;
+    const int rows = p.tile_rows;
+    const int ya = c.cy0 + t.ty * rows, yb = min(ya + rows, c.cy1);
+    if (t.ty & 1)
+        c.template march<G, -1>(yb - 1, yb - ya);
+    else
+        c.template march<G, 1>(ya, yb - ya);
+}
+
+// Many problems: one ordinary step over a list of 64 x 4 tiles of several
+// problems (their frames), leaving each problem's core (its skip rectangle)
+// alone.
+template <typename T>
+__global__ void __launch_bounds__(256) k_multi_frame(const StepArgs<T> *__restrict__ probs,
+                                                     const TileRef *__restrict__ tiles, int ntiles)
+{
+    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+    if (tile >= ntiles) return;
+    const TileRef t = tiles[tile];
+    const StepArgs<T> p = probs[t.prob];
+    const int x = t.tx * 64 + (int)(threadIdx.x % 64);
+    const int y = t.ty * 4 + (int)(threadIdx.x / 64);
+    if (x >= p.skip[0] && x < p.skip[1] && y >= p.skip[2] && y < p.skip[3]) return;
+    cell2d_tile<T, 4>(p, t.tx, t.ty);
+}
+
 // ---------------------------------------------------------------------------
 // Three steps per launch, 2D periodic grids: the same marching scheme one
 // level deeper.  For march index k a wave reads U^n(k+1) and U^{n-1}(k) and

@@ -101,11 +101,14 @@ def test_multi_launch_shapes_bit_identical(dtype, sides):
     probs = _problems(sides, [8, 13, 16, 9, 20])
     print("case multi shapes %s sides=%s" % (dtype, sides), flush=True)
     outs = []
-    for rows, group in [(4, 1), (5, 2), (32, 4), (64, 1), (333, 4), (0, 0)]:
+    for variant, rows, group in [(dp.VARIANT_MARCH, 4, 1), (dp.VARIANT_MARCH, 5, 2), (dp.VARIANT_MARCH, 32, 4),
+                                 (dp.VARIANT_MARCH, 64, 1), (dp.VARIANT_MARCH, 333, 4), (0, 0, 0),
+                                 (dp.VARIANT_TWOSTEP, 0, 0), (dp.VARIANT_TWOSTEP, 1, 1), (dp.VARIANT_TWOSTEP, 7, 4),
+                                 (dp.VARIANT_TWOSTEP, 64, 2)]:
         sim = dp.MultiSimulation(probs, dtype=dtype)
         sim.set_state([w.U0 for w in probs])
         sim.step(10, graph=True)
-        sim.set_variant(rows, group)
+        sim.set_variant(variant, rows, group)
         sim.step(31, graph=True)
         sim.step(20)
         sim.sync()
@@ -120,9 +123,10 @@ def test_multi_launch_shapes_bit_identical(dtype, sides):
 def test_multi_set_variant_rejects_bad_shapes():
     probs = _problems([64, 96], [8, 9])
     sim = dp.MultiSimulation(probs, dtype=torch.float32)
-    for rows, group in [(3, 4), (5000, 4), (32, 3)]:
+    for variant, rows, group in [(dp.VARIANT_MARCH, 3, 4), (dp.VARIANT_MARCH, 5000, 4), (dp.VARIANT_MARCH, 32, 3),
+                                 (dp.VARIANT_TWOSTEP, 5000, 2), (dp.VARIANT_CELL, 8, 2)]:
         with pytest.raises(dp.DpmlError):
-            sim.set_variant(rows, group)
+            sim.set_variant(variant, rows, group)
     sim.close()
 
 
@@ -131,11 +135,39 @@ def test_multi_tuner_picks_a_candidate_and_keeps_the_state(tmp_path):
     probs = _problems([200, 130, 96], [10, 13, 8])
     sim = dp.MultiSimulation(probs, dtype=torch.float32)
     U0s = [w.U0 for w in probs]
-    cands = [(8, 1), (32, 4)]
+    cands = [(dp.VARIANT_MARCH, 8, 1), (dp.VARIANT_TWOSTEP, 8, 2)]
     rec = autotune.tune_multi(sim, U0s, steps=3, candidates=cands, cache=str(tmp_path / "c.json"))
-    assert (rec["tile_rows"], rec["group"]) in cands and not rec["cached"]
+    assert (rec["variant"], rec["tile_rows"], rec["group"]) in cands and not rec["cached"]
     for i, w in enumerate(probs):
         assert np.array_equal(sim.field(i, dp.FIELD_U).cpu().numpy(), w.U0.astype(np.float32))
     again = autotune.tune_multi(sim, U0s, steps=3, candidates=cands, cache=str(tmp_path / "c.json"))
     assert again["cached"] and again["tile_rows"] == rec["tile_rows"]
+    sim.close()
+
+
+@pytest.mark.parametrize("dtype,sides", [(torch.float64, [64, 130, 257, 96, 300]),
+                                         (torch.float32, [64, 131, 256, 97, 300])])
+def test_multi_twostep_matches_oracle_and_graph(dtype, sides):
+    """Two-step passes over all problems (cores in one launch, frames on a
+    second stream) against the oracle per problem, eagerly and as graph
+    replays with odd step counts in between."""
+    ms = [8, 13, 16, 9, 20]
+    probs = _problems(sides, ms)
+    print("case multi two-step %s sides=%s" % (dtype, sides), flush=True)
+    sim = dp.MultiSimulation(probs, dtype=dtype)
+    sim.set_variant(dp.VARIANT_TWOSTEP, 0, 0)
+    sim.set_state([w.U0 for w in probs])
+    for k, graph in [(20, True), (7, False), (20, True), (20, True), (13, True), (10, False)]:
+        sim.step(k, graph=graph)
+        _ = torch.ones(1000, device="cuda").sum().item()
+    steps = 90
+    sim.sync()
+    tol = 1e-12 if dtype == torch.float64 else 2e-5
+    for i, w in enumerate(probs):
+        g = oracle.Grid(w.N, w.h, w.dt, w.sigma)
+        ref, _ = oracle.run(g, oracle.start(g, w.U0), steps)
+        got = sim.field(i, dp.FIELD_U).double().cpu().numpy()
+        err = rel_err(got, ref.U)
+        print("problem", i, "err %.2e" % err, flush=True)
+        assert err <= tol
     sim.close()
