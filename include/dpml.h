@@ -108,9 +108,11 @@ extern "C" {
                                   (3D)                                                */
 #define DPML_VARIANT_THREESTEP 5 /* 2D: as TWOSTEP with three steps per pass over a
                                   core one cell smaller (4 words per cell per three
-                                  steps: U^{n+1} is stored on the core's boundary
-                                  ring only; tile_rows as for TWOSTEP); a remaining
-                                  pair takes the two-step pass.  3D: as TWOSTEP    */
+                                  steps: U^{n+1} stays in registers and U^{n+2} is
+                                  stored off the core's boundary ring, where the
+                                  frame's steps write it; tile_rows as for
+                                  TWOSTEP); a remaining pair takes the two-step
+                                  pass.  3D: as TWOSTEP                            */
 
 typedef struct dpml_grid {
     int32_t ndim;    /* 2 or 3 */
