@@ -351,6 +351,9 @@ int64_t dpml_multi_tiles(const dpml_multi_t *h);
  *     of loads at a time; tile_rows in [1, 4096] (0: 8), group 0: 2), the
  *     frames of all problems as two single steps on a second stream
  *     meanwhile; an odd last step is a single step.
+ *   DPML_VARIANT_THREESTEP: as TWOSTEP with three steps per pass over cores
+ *     one cell smaller (U^{n+1} kept in registers), three frame steps, and
+ *     a two-step pass for a remaining pair.
  * Results do not depend on the choice.  Drops a captured graph.
  * DPML_EINVAL for another variant or a shape out of range. */
 int dpml_multi_set_variant(dpml_multi_t *h, int32_t variant, int32_t tile_rows, int32_t group);

@@ -95,7 +95,8 @@ def tune(sim, steps: int = 50, candidates: Optional[Sequence[Tuple[int, int]]] =
 
 # many-problem path: (variant, tile rows, rows loaded together)
 CANDIDATES_MULTI: List[Tuple[int, int, int]] = ([(VARIANT_MARCH, r, g) for r in (8, 16, 32, 64) for g in (1, 2, 4)]
-                                              + [(VARIANT_TWOSTEP, r, g) for r in (4, 8, 16) for g in (2, 4)])
+                                              + [(v, r, g) for v in (VARIANT_TWOSTEP, VARIANT_THREESTEP)
+                                                 for r in (4, 8, 16) for g in (2, 4)])
 
 
 def multi_key(multi) -> str:

@@ -1698,23 +1698,23 @@ struct dpml_multi {
     size_t off_tiles = 0;            // single-step tile list (workspace)
     int64_t ntiles = 0;
     int vx = 1;
-    int variant = DPML_VARIANT_MARCH;  // MARCH: single steps; TWOSTEP: two-step passes
+    int variant = DPML_VARIANT_MARCH;  // MARCH: single steps; TWOSTEP, THREESTEP: multi-step passes
     int tile_rows = 32;              // single steps: rows per marching tile
     int group = 4;                   // single steps: rows whose loads are issued together
-    int pass_rows = 8;               // two-step passes: rows per core wave
-    int pass_group = 2;              // two-step passes: rows whose loads are issued together
+    int pass_rows = 8;               // multi-step passes: rows per core wave
+    int pass_group = 2;              // multi-step passes: rows whose loads are issued together
     // rotation state: U buffers holding levels n and n-1, aux buffer of level n
     int now = 0, old = 1, cur = 0;
     int64_t n = 0;
     bool state_set = false;
     // library-owned tables: step arguments per rotation state and role, and
-    // the work lists of the two-step passes
-    std::vector<void *> d_args;      // [state * 4 + role]
-    dpmlk::TileRef *d_core_waves = nullptr;
-    int64_t n_core_waves = -1;       // -1: not built for pass_rows yet
-    dpmlk::TileRef *d_frame[2] = {nullptr, nullptr};
-    int64_t n_frame[2] = {-1, -1};
-    int pass_ok = -1;                // every problem has a two-step core (-1: not checked)
+    // the work lists of the two- and three-step passes ([levels - 2])
+    std::vector<void *> d_args;      // [state * kRoles + role]
+    dpmlk::TileRef *d_core_waves[2] = {nullptr, nullptr};
+    int64_t n_core_waves[2] = {-1, -1};   // -1: not built for pass_rows yet
+    dpmlk::TileRef *d_frame[2][3] = {{nullptr, nullptr, nullptr}, {nullptr, nullptr, nullptr}};
+    int64_t n_frame[2][3] = {{0, 0, 0}, {0, 0, 0}};
+    int pass_ok[2] = {-1, -1};       // every problem has a core for the pass (-1: not checked)
     hipStream_t side = nullptr;
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -1739,20 +1739,24 @@ struct MultiLayout {
 
 // The single-step tile list is sized for the shortest tiles allowed
 // (kMultiMinRows rows); the default tiles are 256 VX columns x 32 rows,
-// marched 4 rows at a time.  Each problem holds four U buffers (the two-step
-// passes write U^{n+1} and U^{n+2} while other waves still read U^n and
-// U^{n-1}).
+// marched 4 rows at a time.  Each problem holds five U buffers (a
+// three-step pass writes U^{n+1} .. U^{n+3} while other waves still read U^n
+// and U^{n-1}).
 constexpr int kMultiMinRows = 4;
 constexpr int kMultiTileRows = 32;
 constexpr int kMultiGroup = 4;
 constexpr int kMultiPassRows = 8;
 constexpr int kMultiPassGroup = 2;
-constexpr int kMultiUbufs = 4;
+constexpr int kMultiUbufs = 5;
 
-// roles of the argument tables of one rotation state
-enum { kRoleStep = 0, kRoleCore = 1, kRoleFrame1 = 2, kRoleFrame2 = 3 };
+// roles of the argument tables of one rotation state: a single step; the
+// core and two frame steps of a two-step pass; the core and three frame
+// steps of a three-step pass
+enum { kRoleStep = 0, kRoleCore2 = 1, kRoleCore3 = 4, kRoles = 8 };
 
-int state_key(int now, int old, int cur) { return (now * 4 + old) * 2 + cur; }
+int role_base(int levels) { return levels == 1 ? kRoleStep : (levels == 2 ? kRoleCore2 : kRoleCore3); }
+
+int state_key(int now, int old, int cur) { return (now * kMultiUbufs + old) * 2 + cur; }
 
 std::string multi_layout(int64_t count, const dpml_grid_t *grids, MultiLayout &M)
 {
@@ -1804,11 +1808,11 @@ dpml problem_view(const dpml_multi *H, int64_t p, int now, int old, int cur)
     return v;
 }
 
-// The two spare U buffers of a rotation state, in ascending order.
-void spares(int now, int old, int s[2])
+// The three spare U buffers of a rotation state, in ascending order.
+void spares(int now, int old, int s[3])
 {
     int k = 0;
-    for (int i = 0; i < kMultiUbufs && k < 2; ++i)
+    for (int i = 0; i < kMultiUbufs && k < 3; ++i)
         if (i != now && i != old) s[k++] = i;
 }
 
@@ -1870,116 +1874,143 @@ int upload_table(dpml_multi *H, int slot, const void *data, size_t bytes)
     return DPML_OK;
 }
 
-// Argument tables of rotation state (now, old, cur): one step in place, and
-// for a two-step pass the core descriptors and the two frame steps.  Built
-// once per state (outside any capture) and kept.
+// Argument tables of rotation state (now, old, cur) for a pass of `levels`
+// levels (1: one step in place; 2, 3: the core descriptors and the frame's
+// steps, frame step j over everything outside the core shrunk by levels - j).
+// Built once per state and depth (outside any capture) and kept.
 template <typename T>
-int ensure_state(dpml_multi *H, int now, int old, int cur, bool pass)
+int ensure_state(dpml_multi *H, int now, int old, int cur, int levels)
 {
-    const int key = state_key(now, old, cur);
-    const int need = pass ? kRoleFrame2 : kRoleStep;
+    const int key = state_key(now, old, cur), rb = role_base(levels);
+    const int nroles = levels == 1 ? 1 : levels + 1;
     bool have = true;
-    for (int role = 0; role <= need; ++role) {
-        const size_t slot = (size_t)key * 4 + role;
+    for (int role = rb; role < rb + nroles; ++role) {
+        const size_t slot = (size_t)key * kRoles + role;
         if (slot >= H->d_args.size() || !H->d_args[slot]) have = false;
     }
     if (have) return DPML_OK;
     const size_t c = (size_t)H->count;
-    std::vector<dpmlk::StepArgs<T>> step(c), f1(c), f2(c);
+    if (levels == 1) {
+        std::vector<dpmlk::StepArgs<T>> step(c);
+        for (int64_t p = 0; p < H->count; ++p) {
+            dpml v = problem_view(H, p, now, old, cur);
+            step[p] = make_args<T>(&v);
+            step[p].tile_rows = H->tile_rows;
+            step[p].tiles_x = (int)((v.L.N[0] + 256 * H->vx - 1) / (256 * H->vx));
+        }
+        return upload_table<T>(H, key * kRoles + kRoleStep, step.data(), c * sizeof(step[0]));
+    }
     std::vector<dpmlk::MultiCore<T>> core(c);
-    int sp[2];
+    std::vector<std::vector<dpmlk::StepArgs<T>>> fr((size_t)levels, std::vector<dpmlk::StepArgs<T>>(c));
+    int sp[3];
     spares(now, old, sp);
+    // levels: U^n = now, U^{n-1} = old, U^{n+j} = spare j-1
+    auto level_buf = [&](int j) { return j == 0 ? now : (j == -1 ? old : sp[j - 1]); };
     for (int64_t p = 0; p < H->count; ++p) {
         dpml v = problem_view(H, p, now, old, cur);
-        step[p] = make_args<T>(&v);
-        step[p].tile_rows = H->tile_rows;
-        step[p].tiles_x = (int)((v.L.N[0] + 256 * H->vx - 1) / (256 * H->vx));
-        if (!pass) continue;
-        T *bufC = (T *)v.at(v.L.off_u[sp[0]]), *bufD = (T *)v.at(v.L.off_u[sp[1]]);
         int r[4];
-        core_rect(v.L, 2, r);
+        core_rect(v.L, levels, r);
         core[p].p = make_args<T>(&v);
-        core[p].p.uout = bufC;
+        core[p].p.uout = (T *)v.at(v.L.off_u[sp[0]]);
         core[p].p.tile_rows = H->pass_rows;
         for (int k = 0; k < 4; ++k) core[p].p.skip[k] = r[k];
-        core[p].next2 = bufD;
-        f1[p] = make_args<T>(&v);
-        f1[p].uout = bufC;
-        f1[p].skip[0] = r[0] + 1; f1[p].skip[1] = r[1] - 1; f1[p].skip[2] = r[2] + 1; f1[p].skip[3] = r[3] - 1;
-        dpml w = problem_view(H, p, sp[0], now, 1 - cur);
-        f2[p] = make_args<T>(&w);
-        f2[p].uout = bufD;
-        for (int k = 0; k < 4; ++k) f2[p].skip[k] = r[k];
+        core[p].next2 = (T *)v.at(v.L.off_u[sp[1]]);
+        core[p].next3 = levels == 3 ? (T *)v.at(v.L.off_u[sp[2]]) : nullptr;
+        for (int j = 1; j <= levels; ++j) {
+            const int sh = levels - j;
+            dpml w = problem_view(H, p, level_buf(j - 1), level_buf(j - 2), (j % 2 == 0) ? 1 - cur : cur);
+            fr[j - 1][p] = make_args<T>(&w);
+            fr[j - 1][p].uout = (T *)w.at(w.L.off_u[sp[j - 1]]);
+            fr[j - 1][p].skip[0] = r[0] + sh;
+            fr[j - 1][p].skip[1] = r[1] - sh;
+            fr[j - 1][p].skip[2] = r[2] + sh;
+            fr[j - 1][p].skip[3] = r[3] - sh;
+        }
     }
-    int rc = upload_table<T>(H, key * 4 + kRoleStep, step.data(), c * sizeof(step[0]));
-    if (rc || !pass) return rc;
-    rc = upload_table<T>(H, key * 4 + kRoleCore, core.data(), c * sizeof(core[0]));
-    if (!rc) rc = upload_table<T>(H, key * 4 + kRoleFrame1, f1.data(), c * sizeof(f1[0]));
-    if (!rc) rc = upload_table<T>(H, key * 4 + kRoleFrame2, f2.data(), c * sizeof(f2[0]));
+    int rc = upload_table<T>(H, key * kRoles + rb, core.data(), c * sizeof(core[0]));
+    for (int j = 1; j <= levels && !rc; ++j)
+        rc = upload_table<T>(H, key * kRoles + rb + j, fr[j - 1].data(), c * sizeof(fr[j - 1][0]));
     return rc;
 }
 
-// Do all problems have a core for two-step passes?
-bool multi_pass_ok(dpml_multi *H)
+// Do all problems have a core for passes of `levels` levels?
+bool multi_pass_ok(dpml_multi *H, int levels)
 {
-    if (H->pass_ok < 0) {
-        H->pass_ok = 1;
+    int &ok = H->pass_ok[levels - 2];
+    if (ok < 0) {
+        ok = 1;
         for (int64_t p = 0; p < H->count; ++p) {
             int r[4];
-            core_rect(H->L[p], 2, r);
-            if (H->L[p].N[0] < 8 || H->L[p].N[1] < 8 || r[1] - r[0] < 1 || r[3] - r[2] < 1) H->pass_ok = 0;
+            core_rect(H->L[p], levels, r);
+            if (H->L[p].N[0] < 8 || H->L[p].N[1] < 8 || r[1] - r[0] < 1 || r[3] - r[2] < 1) ok = 0;
         }
     }
-    return H->pass_ok == 1;
+    return ok == 1;
 }
 
-// Work lists of the two-step passes: the core waves (problem, strip, tile
-// row) for pass_rows, and the 64 x 4 frame tiles outside each core shrunk by
-// s = 1 (first frame step) and s = 0 (second).
-int ensure_pass_lists(dpml_multi *H)
+// Work lists of the passes of `levels` levels: the core waves (problem,
+// strip, tile row) for pass_rows, and for frame step j the 64 x 4 tiles
+// outside each core shrunk by levels - j.
+int ensure_pass_lists(dpml_multi *H, int levels)
 {
-    if (H->n_core_waves >= 0) return DPML_OK;
-    std::vector<dpmlk::TileRef> waves, fr[2];
+    const int q = levels - 2;
+    if (H->n_core_waves[q] >= 0) return DPML_OK;
+    std::vector<dpmlk::TileRef> waves, fr[3];
     for (int64_t p = 0; p < H->count; ++p) {
         const Layout &L = H->L[p];
         int r[4];
-        core_rect(L, 2, r);
+        core_rect(L, levels, r);
         const int VX = multistep_vx(L);
-        const int strips = (r[1] - r[0] + 62 * VX - 1) / (62 * VX);
+        const int HL = (levels + VX - 1) / VX;
+        const int sw = (64 - 2 * HL) * VX;
+        const int strips = (r[1] - r[0] + sw - 1) / sw;
         const int tys = (r[3] - r[2] + H->pass_rows - 1) / H->pass_rows;
         for (int ty = 0; ty < tys; ++ty)
             for (int s = 0; s < strips; ++s) waves.push_back({(int32_t)p, s, ty, 0});
         const int tx = (int)((L.N[0] + 63) / 64), ty4 = (int)((L.N[1] + 3) / 4);
-        for (int sh = 0; sh < 2; ++sh) {
+        for (int j = 1; j <= levels; ++j) {
+            const int sh = levels - j;
             const int q0 = r[0] + sh, q1 = r[1] - sh, q2 = r[2] + sh, q3 = r[3] - sh;
             for (int y = 0; y < ty4; ++y)
                 for (int x = 0; x < tx; ++x) {
                     const int xa = x * 64, xb = std::min<int>(xa + 64, (int)L.N[0]);
                     const int ya = y * 4, yb = std::min<int>(ya + 4, (int)L.N[1]);
-                    if (!(xa >= q0 && xb <= q1 && ya >= q2 && yb <= q3)) fr[1 - sh].push_back({(int32_t)p, x, y, 0});
+                    if (!(xa >= q0 && xb <= q1 && ya >= q2 && yb <= q3)) fr[j - 1].push_back({(int32_t)p, x, y, 0});
                 }
         }
     }
-    // fr[0]: outside the core shrunk by 1 (first frame step); fr[1]: outside the core
-    HIP_TRY(nullptr, hipMalloc((void **)&H->d_core_waves, std::max<size_t>(1, waves.size()) * sizeof(waves[0])));
-    HIP_TRY(nullptr, hipMemcpy(H->d_core_waves, waves.data(), waves.size() * sizeof(waves[0]), hipMemcpyHostToDevice));
-    for (int k = 0; k < 2; ++k) {
-        HIP_TRY(nullptr, hipMalloc((void **)&H->d_frame[k], std::max<size_t>(1, fr[k].size()) * sizeof(fr[k][0])));
-        HIP_TRY(nullptr, hipMemcpy(H->d_frame[k], fr[k].data(), fr[k].size() * sizeof(fr[k][0]), hipMemcpyHostToDevice));
-        H->n_frame[k] = (int64_t)fr[k].size();
+    HIP_TRY(nullptr, hipMalloc((void **)&H->d_core_waves[q], std::max<size_t>(1, waves.size()) * sizeof(waves[0])));
+    HIP_TRY(nullptr, hipMemcpy(H->d_core_waves[q], waves.data(), waves.size() * sizeof(waves[0]),
+                               hipMemcpyHostToDevice));
+    for (int j = 0; j < levels; ++j) {
+        HIP_TRY(nullptr, hipMalloc((void **)&H->d_frame[q][j], std::max<size_t>(1, fr[j].size()) * sizeof(fr[j][0])));
+        HIP_TRY(nullptr, hipMemcpy(H->d_frame[q][j], fr[j].data(), fr[j].size() * sizeof(fr[j][0]),
+                                   hipMemcpyHostToDevice));
+        H->n_frame[q][j] = (int64_t)fr[j].size();
     }
-    H->n_core_waves = (int64_t)waves.size();
+    H->n_core_waves[q] = (int64_t)waves.size();
     if (!H->side) HIP_TRY(nullptr, hipStreamCreateWithFlags(&H->side, hipStreamNonBlocking));
     if (!H->ev_fork) HIP_TRY(nullptr, hipEventCreateWithFlags(&H->ev_fork, hipEventDisableTiming));
     if (!H->ev_join) HIP_TRY(nullptr, hipEventCreateWithFlags(&H->ev_join, hipEventDisableTiming));
     return DPML_OK;
 }
 
+// Drop the work lists (after a change of pass_rows).
+void drop_pass_lists(dpml_multi *H)
+{
+    for (int q = 0; q < 2; ++q) {
+        if (H->d_core_waves[q]) { (void)hipFree(H->d_core_waves[q]); H->d_core_waves[q] = nullptr; }
+        for (int j = 0; j < 3; ++j)
+            if (H->d_frame[q][j]) { (void)hipFree(H->d_frame[q][j]); H->d_frame[q][j] = nullptr; }
+        H->n_core_waves[q] = -1;
+    }
+}
+
 template <typename T>
 int multi_launch_step(dpml_multi *H, hipStream_t s, int key)
 {
     const dim3 grid((unsigned)round8((int)H->ntiles)), block(256);
-    const auto *probs = (const dpmlk::StepArgs<T> *)H->d_args[(size_t)key * 4 + kRoleStep];
+    const auto *probs = (const dpmlk::StepArgs<T> *)H->d_args[(size_t)key * kRoles + kRoleStep];
     const auto *tiles = (const dpmlk::TileRef *)(H->ws + H->off_tiles);
     constexpr int V2 = sizeof(T) == 4 ? 2 : 1;
 #define DPML_MULTI2D(VX_, R_) \
@@ -1998,31 +2029,33 @@ int multi_launch_step(dpml_multi *H, hipStream_t s, int key)
     return DPML_OK;
 }
 
-// One two-step pass of every problem: the core waves on stream s, the two
-// frame steps on the side stream meanwhile (fork/join events).
+// One pass of `levels` levels over every problem: the core waves on stream
+// s, the frame's steps on the side stream meanwhile (fork/join events).
 template <typename T>
-int multi_launch_pass(dpml_multi *H, hipStream_t s, int key)
+int multi_launch_pass(dpml_multi *H, hipStream_t s, int key, int levels)
 {
     constexpr int VX = sizeof(T) == 4 ? 4 : 2;
-    const auto *cores = (const dpmlk::MultiCore<T> *)H->d_args[(size_t)key * 4 + kRoleCore];
-    const auto *f1 = (const dpmlk::StepArgs<T> *)H->d_args[(size_t)key * 4 + kRoleFrame1];
-    const auto *f2 = (const dpmlk::StepArgs<T> *)H->d_args[(size_t)key * 4 + kRoleFrame2];
+    const int q = levels - 2, rb = role_base(levels);
+    const auto *cores = (const dpmlk::MultiCore<T> *)H->d_args[(size_t)key * kRoles + rb];
     const dim3 block(256);
     HIP_TRY(nullptr, hipEventRecord(H->ev_fork, s));
     HIP_TRY(nullptr, hipStreamWaitEvent(H->side, H->ev_fork, 0));
-    const int nw = (int)H->n_core_waves;
+    const int nw = (int)H->n_core_waves[q];
     const dim3 grid((unsigned)round8((nw + 3) / 4));
-    if (H->pass_group == 4)
-        hipLaunchKernelGGL((dpmlk::k_multi_step2_march<T, VX, 4>), grid, block, 0, s, cores, H->d_core_waves, nw);
-    else if (H->pass_group == 1)
-        hipLaunchKernelGGL((dpmlk::k_multi_step2_march<T, VX, 1>), grid, block, 0, s, cores, H->d_core_waves, nw);
-    else
-        hipLaunchKernelGGL((dpmlk::k_multi_step2_march<T, VX, 2>), grid, block, 0, s, cores, H->d_core_waves, nw);
-    for (int k = 0; k < 2; ++k) {
-        const int nf = (int)H->n_frame[k];
+    const dpmlk::TileRef *wl = H->d_core_waves[q];
+#define DPML_MULTI_PASS(KER)                                                                          \
+    if (H->pass_group == 4) hipLaunchKernelGGL((dpmlk::KER<T, VX, 4>), grid, block, 0, s, cores, wl, nw); \
+    else if (H->pass_group == 1) hipLaunchKernelGGL((dpmlk::KER<T, VX, 1>), grid, block, 0, s, cores, wl, nw); \
+    else hipLaunchKernelGGL((dpmlk::KER<T, VX, 2>), grid, block, 0, s, cores, wl, nw);
+    if (levels == 3) { DPML_MULTI_PASS(k_multi_step3_march) }
+    else { DPML_MULTI_PASS(k_multi_step2_march) }
+#undef DPML_MULTI_PASS
+    for (int j = 1; j <= levels; ++j) {
+        const int nf = (int)H->n_frame[q][j - 1];
+        const auto *fa = (const dpmlk::StepArgs<T> *)H->d_args[(size_t)key * kRoles + rb + j];
         if (nf > 0)
-            hipLaunchKernelGGL((dpmlk::k_multi_frame<T>), dim3((unsigned)round8(nf)), block, 0, H->side,
-                               k == 0 ? f1 : f2, H->d_frame[k], nf);
+            hipLaunchKernelGGL((dpmlk::k_multi_frame<T>), dim3((unsigned)round8(nf)), block, 0, H->side, fa,
+                               H->d_frame[q][j - 1], nf);
     }
     HIP_TRY(nullptr, hipEventRecord(H->ev_join, H->side));
     HIP_TRY(nullptr, hipStreamWaitEvent(s, H->ev_join, 0));
@@ -2030,8 +2063,9 @@ int multi_launch_pass(dpml_multi *H, hipStream_t s, int key)
     return DPML_OK;
 }
 
-// nsteps steps from the handle's rotation state: two-step passes while two
-// or more steps remain (variant TWOSTEP), then single steps.  kPrepare only
+// nsteps steps from the handle's rotation state: passes of three (variant
+// THREESTEP) or two (TWOSTEP, or a last pair) levels while that many steps
+// remain and every problem has a core for them, then single steps.  kPrepare only
 // builds the tables the run needs (before a capture); kLaunch enqueues the
 // run on stream s and advances the rotation state; kAdvance only advances
 // it (after a graph replay).
@@ -2040,28 +2074,31 @@ enum { kPrepare = 0, kLaunch = 1, kAdvance = 2 };
 template <typename T>
 int multi_run(dpml_multi *H, hipStream_t s, int64_t nsteps, int mode)
 {
-    const bool passes = H->variant == DPML_VARIANT_TWOSTEP && multi_pass_ok(H);
-    if (passes && nsteps >= 2 && mode != kAdvance) {
-        int rc = ensure_pass_lists(H);
-        if (rc) return rc;
-    }
+    const int want = H->variant == DPML_VARIANT_THREESTEP ? 3 : (H->variant == DPML_VARIANT_TWOSTEP ? 2 : 1);
     int now = H->now, old = H->old, cur = H->cur;
     int64_t k = 0;
-    for (; passes && nsteps - k >= 2; k += 2) {
-        int rc = mode == kAdvance ? DPML_OK : ensure_state<T>(H, now, old, cur, true);
-        if (!rc && mode == kLaunch) rc = multi_launch_pass<T>(H, s, state_key(now, old, cur));
+    while (k < nsteps) {
+        int lv = (int)std::min<int64_t>(want, nsteps - k);
+        while (lv >= 2 && !multi_pass_ok(H, lv)) --lv;
+        int rc = DPML_OK;
+        if (mode != kAdvance) {
+            if (lv >= 2) rc = ensure_pass_lists(H, lv);
+            if (!rc) rc = ensure_state<T>(H, now, old, cur, lv);
+        }
+        if (!rc && mode == kLaunch)
+            rc = lv == 1 ? multi_launch_step<T>(H, s, state_key(now, old, cur))
+                         : multi_launch_pass<T>(H, s, state_key(now, old, cur), lv);
         if (rc) return rc;
-        int sp[2];
-        spares(now, old, sp);
-        now = sp[1];
-        old = sp[0];
-    }
-    for (; k < nsteps; ++k) {
-        int rc = mode == kAdvance ? DPML_OK : ensure_state<T>(H, now, old, cur, false);
-        if (!rc && mode == kLaunch) rc = multi_launch_step<T>(H, s, state_key(now, old, cur));
-        if (rc) return rc;
-        std::swap(now, old);
-        cur = 1 - cur;
+        if (lv == 1) {
+            std::swap(now, old);
+        } else {
+            int sp[3];
+            spares(now, old, sp);
+            now = sp[lv - 1];
+            old = sp[lv - 2];
+        }
+        if (lv % 2) cur = 1 - cur;
+        k += lv;
     }
     if (mode != kPrepare) {
         H->now = now;
@@ -2230,9 +2267,9 @@ int dpml_multi_set_variant(dpml_multi_t *H, int32_t variant, int32_t tile_rows, 
 {
     if (!H) return DPML_EINVAL;
     if (variant == DPML_VARIANT_AUTO) variant = DPML_VARIANT_MARCH;
-    if (variant != DPML_VARIANT_MARCH && variant != DPML_VARIANT_TWOSTEP)
-        return H->fail(DPML_EINVAL, "variant must be DPML_VARIANT_MARCH or DPML_VARIANT_TWOSTEP");
-    const bool pass = variant == DPML_VARIANT_TWOSTEP;
+    if (variant != DPML_VARIANT_MARCH && variant != DPML_VARIANT_TWOSTEP && variant != DPML_VARIANT_THREESTEP)
+        return H->fail(DPML_EINVAL, "variant must be DPML_VARIANT_MARCH, TWOSTEP or THREESTEP");
+    const bool pass = variant != DPML_VARIANT_MARCH;
     if (tile_rows == 0) tile_rows = pass ? kMultiPassRows : kMultiTileRows;
     if (group == 0) group = pass ? kMultiPassGroup : kMultiGroup;
     if (tile_rows < (pass ? 1 : kMultiMinRows) || tile_rows > 4096 || (group != 1 && group != 2 && group != 4))
@@ -2244,12 +2281,7 @@ int dpml_multi_set_variant(dpml_multi_t *H, int32_t variant, int32_t tile_rows, 
     H->graph_steps = -1;
     H->variant = variant;
     if (pass) {
-        if (tile_rows != H->pass_rows) {
-            if (H->d_core_waves) { (void)hipFree(H->d_core_waves); H->d_core_waves = nullptr; }
-            for (int k = 0; k < 2; ++k)
-                if (H->d_frame[k]) { (void)hipFree(H->d_frame[k]); H->d_frame[k] = nullptr; }
-            H->n_core_waves = H->n_frame[0] = H->n_frame[1] = -1;
-        }
+        if (tile_rows != H->pass_rows) drop_pass_lists(H);
         H->pass_rows = tile_rows;
         H->pass_group = group;
         for (void *&d : H->d_args)                      // the core tables hold the wave height
@@ -2279,9 +2311,7 @@ void dpml_multi_destroy(dpml_multi_t *H)
     if (H->cap) (void)hipStreamDestroy(H->cap);
     for (void *d : H->d_args)
         if (d) (void)hipFree(d);
-    if (H->d_core_waves) (void)hipFree(H->d_core_waves);
-    for (int k = 0; k < 2; ++k)
-        if (H->d_frame[k]) (void)hipFree(H->d_frame[k]);
+    drop_pass_lists(H);
     if (H->ev_fork) (void)hipEventDestroy(H->ev_fork);
     if (H->ev_join) (void)hipEventDestroy(H->ev_join);
     if (H->side) (void)hipStreamDestroy(H->side);

@@ -708,15 +708,16 @@ __global__ void __launch_bounds__(256) k_step2_march(StepArgs<T> p, T *__restric
         c.template march<G, 1>(ya, yb - ya);
 }
 
-// Many problems, two-step passes: the waves of every problem's core in one
-// launch.  Each problem's descriptor holds its step arguments (U^n, U^{n-1},
-// U^{n+1} in u, uo, uout; the core rectangle in skip; tile rows in
-// tile_rows) and its U^{n+2}; the work list holds one (problem, strip, tile
-// row) entry per wave.
+// Many problems, two- and three-step passes: the waves of every problem's
+// core in one launch.  Each problem's descriptor holds its step arguments
+// (U^n, U^{n-1}, U^{n+1} in u, uo, uout; the core rectangle in skip; tile
+// rows in tile_rows) and its U^{n+2} (and U^{n+3}); the work list holds one
+// (problem, strip, tile row) entry per wave.
 template <typename T>
 struct MultiCore {
     StepArgs<T> p;
     T *next2;
+    T *next3;         // U^{n+3} (three-step passes)
 };
 
 template <typename T, int VX, int G>
@@ -911,6 +912,46 @@ __global__ void __launch_bounds__(256) k_step3_march(StepArgs<T> p, T *__restric
     const int rows = p.tile_rows;
     const int ya = cy0 + ty * rows, yb = min(ya + rows, cy1);
     if (ty & 1)
+        c.template march<G, -1>(yb - 1, yb - ya);
+    else
+        c.template march<G, 1>(ya, yb - ya);
+}
+
+template <typename T, int VX, int G>
+__global__ void __launch_bounds__(256) k_multi_step3_march(const MultiCore<T> *__restrict__ cores,
+                                                           const TileRef *__restrict__ waves, int n_waves)
+{
+    constexpr int HL = (3 + VX - 1) / VX;                    // halo lanes per side
+    const int w = __builtin_amdgcn_readfirstlane(xcd_tile(blockIdx.x, gridDim.x) * 4 + (int)(threadIdx.x >> 6));
+    if (w >= n_waves) return;                                // whole waves; no barriers below
+    const int lane = (int)(threadIdx.x & 63);
+    const TileRef t = waves[w];
+    const StepArgs<T> &p = cores[t.prob].p;
+    March3Ctx<T, VX, false> c;
+    c.u = p.u;
+    c.up = p.uo;
+    c.c2 = nullptr;
+    c.o1 = p.uout;
+    c.o2 = cores[t.prob].next2;
+    c.o3 = cores[t.prob].next3;
+    c.inv_h2 = p.inv_h2;
+    c.dt2 = p.dt2;
+    c.c2c = p.c2_const;
+    c.nx = p.nx;
+    c.ny = p.ny;
+    c.cx0 = p.skip[0];
+    c.cx1 = p.skip[1];
+    c.cy0 = p.skip[2];
+    c.cy1 = p.skip[3];
+    c.xs = c.cx0 + (t.tx * (64 - 2 * HL) + lane - HL) * VX;
+    c.need = c.xs < c.cx1 + HL * VX;
+    c.xw = c.xs % c.nx;
+    if (c.xw < 0) c.xw += c.nx;
+    c.vec = c.xw % VX == 0 && c.xw + VX <= c.nx;
+    c.out = lane >= HL && lane < 64 - HL && c.xs < c.cx1;
+    const int rows = p.tile_rows;
+    const int ya = c.cy0 + t.ty * rows, yb = min(ya + rows, c.cy1);
+    if (t.ty & 1)
         c.template march<G, -1>(yb - 1, yb - ya);
     else
         c.template march<G, 1>(ya, yb - ya);
