@@ -657,6 +657,26 @@ int multistep_levels(const dpml *H, int64_t nsteps)
     return 1;
 }
 
+// Rows per span of the marching frame steps.
+constexpr int kFrameRows = 32;
+
+// The spans (64 columns x up to kFrameRows rows, counted across the
+// periodic wrap) covering everything outside the rectangle S = [S0, S1) x
+// [S2, S3) of a 2D grid: the rows outside S on every column, and S's rows on
+// the columns outside S (one strip across the wrap).  An axis where S spans
+// the whole grid adds nothing.
+void frame_spans(const Layout &L, const int S[4], int prob, std::vector<dpmlk::Span2> &out)
+{
+    const int NX = (int)L.N[0], NY = (int)L.N[1];
+    auto rect = [&](int xs, int xe, int ys, int ye) {
+        for (int y = ys; y < ye; y += kFrameRows)
+            for (int x = xs; x < xe; x += 64)
+                out.push_back({prob, x, std::min(x + 64, xe), y, std::min(y + kFrameRows, ye), 0, 0, 0});
+    };
+    if (S[3] - S[2] < NY) rect(0, NX, S[3], S[2] + NY);
+    if (S[1] - S[0] < NX) rect(S[1], S[0] + NX, S[2], S[3]);
+}
+
 int ensure_frame(dpml *H, int levels, int shrink)
 {
     const int q = levels - 2;
@@ -668,6 +688,8 @@ int ensure_frame(dpml *H, int levels, int shrink)
     r[1] -= shrink;
     r[2] += shrink;
     r[3] -= shrink;
+    // one grid's frame: 64 x 4 tiles one thread per cell (many more waves
+    // than the frame has spans to march)
     const int tx = (int)((L.N[0] + 63) / 64), ty = (int)((L.N[1] + 3) / 4);
     std::vector<dpmlk::TileRef> t;
     for (int y = 0; y < ty; ++y)
@@ -1712,7 +1734,7 @@ struct dpml_multi {
     std::vector<void *> d_args;      // [state * kRoles + role]
     dpmlk::TileRef *d_core_waves[2] = {nullptr, nullptr};
     int64_t n_core_waves[2] = {-1, -1};   // -1: not built for pass_rows yet
-    dpmlk::TileRef *d_frame[2][3] = {{nullptr, nullptr, nullptr}, {nullptr, nullptr, nullptr}};
+    dpmlk::Span2 *d_frame[2][3] = {{nullptr, nullptr, nullptr}, {nullptr, nullptr, nullptr}};
     int64_t n_frame[2][3] = {{0, 0, 0}, {0, 0, 0}};
     int pass_ok[2] = {-1, -1};       // every problem has a core for the pass (-1: not checked)
     hipStream_t side = nullptr;
@@ -1949,13 +1971,14 @@ bool multi_pass_ok(dpml_multi *H, int levels)
 }
 
 // Work lists of the passes of `levels` levels: the core waves (problem,
-// strip, tile row) for pass_rows, and for frame step j the 64 x 4 tiles
-// outside each core shrunk by levels - j.
+// strip, tile row) for pass_rows, and for frame step j the spans outside
+// each core shrunk by levels - j.
 int ensure_pass_lists(dpml_multi *H, int levels)
 {
     const int q = levels - 2;
     if (H->n_core_waves[q] >= 0) return DPML_OK;
-    std::vector<dpmlk::TileRef> waves, fr[3];
+    std::vector<dpmlk::TileRef> waves;
+    std::vector<dpmlk::Span2> fr[3];
     for (int64_t p = 0; p < H->count; ++p) {
         const Layout &L = H->L[p];
         int r[4];
@@ -1967,16 +1990,10 @@ int ensure_pass_lists(dpml_multi *H, int levels)
         const int tys = (r[3] - r[2] + H->pass_rows - 1) / H->pass_rows;
         for (int ty = 0; ty < tys; ++ty)
             for (int s = 0; s < strips; ++s) waves.push_back({(int32_t)p, s, ty, 0});
-        const int tx = (int)((L.N[0] + 63) / 64), ty4 = (int)((L.N[1] + 3) / 4);
         for (int j = 1; j <= levels; ++j) {
             const int sh = levels - j;
-            const int q0 = r[0] + sh, q1 = r[1] - sh, q2 = r[2] + sh, q3 = r[3] - sh;
-            for (int y = 0; y < ty4; ++y)
-                for (int x = 0; x < tx; ++x) {
-                    const int xa = x * 64, xb = std::min<int>(xa + 64, (int)L.N[0]);
-                    const int ya = y * 4, yb = std::min<int>(ya + 4, (int)L.N[1]);
-                    if (!(xa >= q0 && xb <= q1 && ya >= q2 && yb <= q3)) fr[j - 1].push_back({(int32_t)p, x, y, 0});
-                }
+            const int S[4] = {r[0] + sh, r[1] - sh, r[2] + sh, r[3] - sh};
+            frame_spans(L, S, (int)p, fr[j - 1]);
         }
     }
     HIP_TRY(nullptr, hipMalloc((void **)&H->d_core_waves[q], std::max<size_t>(1, waves.size()) * sizeof(waves[0])));
@@ -2054,8 +2071,8 @@ int multi_launch_pass(dpml_multi *H, hipStream_t s, int key, int levels)
         const int nf = (int)H->n_frame[q][j - 1];
         const auto *fa = (const dpmlk::StepArgs<T> *)H->d_args[(size_t)key * kRoles + rb + j];
         if (nf > 0)
-            hipLaunchKernelGGL((dpmlk::k_multi_frame<T>), dim3((unsigned)round8(nf)), block, 0, H->side, fa,
-                               H->d_frame[q][j - 1], nf);
+            hipLaunchKernelGGL((dpmlk::k_multi_frame_march<T, 4>), dim3((unsigned)round8((nf + 3) / 4)), block, 0,
+                               H->side, fa, H->d_frame[q][j - 1], nf);
     }
     HIP_TRY(nullptr, hipEventRecord(H->ev_join, H->side));
     HIP_TRY(nullptr, hipStreamWaitEvent(s, H->ev_join, 0));

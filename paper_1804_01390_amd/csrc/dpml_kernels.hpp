@@ -708,6 +708,102 @@ __global__ void __launch_bounds__(256) k_step2_march(StepArgs<T> p, T *__restric
         c.template march<G, 1>(ya, yb - ya);
 }
 
+// ---------------------------------------------------------------------------
+// Frame steps of many problems as wave marches (a set of problems has enough
+// spans to fill the GPU; one grid's frame is better served one thread per
+// cell).  On a periodic 2D grid everything outside a
+// rectangle S is two wrapped rectangles: the rows outside S (every column)
+// and S's rows on the columns outside S (one strip across the x wrap).  A
+// span is 64 consecutive columns [xs, xe) of one of them and a chunk of its
+// rows [ys, ye), both counted past the array end where they wrap.  One wave
+// takes one span and marches down its rows keeping U^n of rows y-1, y, y+1
+// in registers, the loads of G rows issued together; x neighbours come from
+// the adjacent lanes (lane 0 and lane 63 read the column beyond the wave,
+// the lane past the last column reads that column's right neighbour).
+// Every cell takes cell_update with the layer loads hoisted.
+// ---------------------------------------------------------------------------
+struct Span2 {
+    int32_t prob, xs, xe, ys, ye, pad0, pad1, pad2;
+};
+
+template <typename T, int G>
+__device__ __forceinline__ void frame_march_wave(const StepArgs<T> &p, const Span2 &s)
+{
+    const int lane = (int)(threadIdx.x & 63);
+    const int nx = p.nx, ny = p.ny;
+    const int x = s.xs + lane;
+    const bool act = x < s.xe;
+    const bool need = x <= s.xe;
+    const int xc = x % nx;
+    int xo = 0;
+    bool edge = false;
+    if (lane == 0) {
+        xo = (s.xs + nx - 1) % nx;
+        edge = act;
+    } else if (lane == 63) {
+        xo = (s.xs + 64) % nx;
+        edge = act;
+    }
+    // rows ys-1 .. ye lie in [-1, 2 ny): one conditional wrap
+    auto row_of = [&](int y) -> int { return y < 0 ? y + ny : (y >= ny ? y - ny : y); };
+    const T *u = p.u;
+    T *out = p.uout ? p.uout : p.uo;
+    auto ld = [&](int yr) -> T { return need ? u[(int64_t)yr * nx + xc] : T(0); };
+    // the lane shifts run on the whole wave; only the span's own lanes update
+    // (cell_update also stores the cell's Phi/Psi, and a lane past the span
+    // may wrap onto a column another wave owns)
+    auto cell = [&](int yr, T um, T uc, T up, T old, T ed) {
+        T uxm = from_left(uc), uxp = from_right(uc);
+        if (lane == 0) uxm = ed;
+        if (lane == 63) uxp = ed;
+        if (act) {
+            const int64_t idx = (int64_t)yr * nx + xc;
+            const T r = cell_update<T, 2, 7, true>(p, xc, yr, 0, idx, uc, uxm, uxp, um, up, T(0), T(0), old);
+            out[idx] = r;
+            if (p.hist) p.hist[idx] = r;
+        }
+    };
+    T w[G + 2];                 // w[0] = row y-1, w[1] = row y, w[2 + g] = row y+1+g
+    w[0] = ld(row_of(s.ys - 1));
+    w[1] = ld(row_of(s.ys));
+    int y = s.ys;
+    for (; y + G <= s.ye; y += G) {
+        T old[G], ed[G];
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+            const int yr = row_of(y + g);
+            w[2 + g] = ld(row_of(y + g + 1));
+            old[g] = act ? p.uo[(int64_t)yr * nx + xc] : T(0);
+            ed[g] = edge ? u[(int64_t)yr * nx + xo] : T(0);
+        }
+#pragma unroll
+        for (int g = 0; g < G; ++g) cell(row_of(y + g), w[g], w[g + 1], w[g + 2], old[g], ed[g]);
+        w[0] = w[G];
+        w[1] = w[G + 1];
+    }
+    for (; y < s.ye; ++y) {
+        const int yr = row_of(y);
+        w[2] = ld(row_of(y + 1));
+        const T old = act ? p.uo[(int64_t)yr * nx + xc] : T(0);
+        const T ed = edge ? u[(int64_t)yr * nx + xo] : T(0);
+        cell(yr, w[0], w[1], w[2], old, ed);
+        w[0] = w[1];
+        w[1] = w[2];
+    }
+}
+
+// A frame step of many problems over one span list (span.prob selects the
+// problem's step arguments).
+template <typename T, int G>
+__global__ void __launch_bounds__(256) k_multi_frame_march(const StepArgs<T> *__restrict__ probs,
+                                                           const Span2 *__restrict__ spans, int n)
+{
+    const int w = __builtin_amdgcn_readfirstlane(xcd_tile(blockIdx.x, gridDim.x) * 4 + (int)(threadIdx.x >> 6));
+    if (w >= n) return;                                      // whole waves; no barriers below
+    const Span2 s = spans[w];
+    frame_march_wave<T, G>(probs[s.prob], s);
+}
+
 // Many problems, two- and three-step passes: the waves of every problem's
 // core in one launch.  Each problem's descriptor holds its step arguments
 // (U^n, U^{n-1}, U^{n+1} in u, uo, uout; the core rectangle in skip; tile
@@ -756,23 +852,6 @@ __global__ void __launch_bounds__(256) k_multi_step2_march(const MultiCore<T> *_
         c.template march<G, -1>(yb - 1, yb - ya);
     else
         c.template march<G, 1>(ya, yb - ya);
-}
-
-// Many problems: one ordinary step over a list of 64 x 4 tiles of several
-// problems (their frames), leaving each problem's core (its skip rectangle)
-// alone.
-template <typename T>
-__global__ void __launch_bounds__(256) k_multi_frame(const StepArgs<T> *__restrict__ probs,
-                                                     const TileRef *__restrict__ tiles, int ntiles)
-{
-    const int tile = xcd_tile(blockIdx.x, gridDim.x);
-    if (tile >= ntiles) return;
-    const TileRef t = tiles[tile];
-    const StepArgs<T> p = probs[t.prob];
-    const int x = t.tx * 64 + (int)(threadIdx.x % 64);
-    const int y = t.ty * 4 + (int)(threadIdx.x / 64);
-    if (x >= p.skip[0] && x < p.skip[1] && y >= p.skip[2] && y < p.skip[3]) return;
-    cell2d_tile<T, 4>(p, t.tx, t.ty);
 }
 
 // ---------------------------------------------------------------------------
