@@ -94,8 +94,11 @@ extern "C" {
                                   strip keeping U^n and U^{n+1} rows in registers,
                                   2 words per cell per step; tile_rows: rows per
                                   wave in bits 0-11 (0 = 8), rows whose loads are
-                                  issued together in bits 12-15 (1, 2 or 4; 0 = 2)),
-                                  the frame holding the layer in single steps.
+                                  issued together in bits 12-15 (1, 2 or 4; 0 = 2),
+                                  rows per marching span of the frame's steps in
+                                  bits 16-19 (0 = the frame one thread per
+                                  cell)), the frame holding the layer in single
+                                  steps.
                                   3D periodic runs with a constant c^2, one batch
                                   member and at most 32 sources, all at least 3
                                   cells inside the layer-free region: the same

@@ -19,7 +19,10 @@ from . import VARIANT_CELL, VARIANT_MARCH, VARIANT_MARCH1, VARIANT_THREESTEP, VA
 DEFAULT_CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "autotune_cache.json")
 
 # multi-step variants: rows per wave in the low 12 bits, load group size above
+# (frame span rows above bit 16: the frame's steps as wave marches)
 CANDIDATES_2D: List[Tuple[int, int]] = ([(VARIANT_THREESTEP, (g << 12) | r) for g in (2, 4) for r in (4, 6, 8, 12, 16)]
+                                        + [(VARIANT_THREESTEP, (f << 16) | (4 << 12) | r) for f in (2, 3, 4)
+                                           for r in (6, 8)]
                                         + [(VARIANT_TWOSTEP, (g << 12) | r) for g in (2, 4) for r in (8, 16)] + [(VARIANT_CELL, th) for th in (1, 2, 4, 8)]
                                         + [(VARIANT_MARCH, r) for r in (4, 8, 16)]
                                         + [(VARIANT_MARCH1, r) for r in (4, 8, 16)])

@@ -127,6 +127,10 @@ struct dpml {
     // everything outside the core shrunk by s cells (-1: not built yet)
     dpmlk::TileRef *d_frame[2][3] = {{nullptr, nullptr, nullptr}, {nullptr, nullptr, nullptr}};
     int64_t n_frame[2][3] = {{-1, -1, -1}, {-1, -1, -1}};
+    // the same frames as spans for the marching frame kernel (span rows fspan_rows)
+    dpmlk::Span2 *d_fspan[2][3] = {{nullptr, nullptr, nullptr}, {nullptr, nullptr, nullptr}};
+    int64_t n_fspan[2][3] = {{-1, -1, -1}, {-1, -1, -1}};
+    int fspan_rows = 0;
     // the frame's steps run on a second stream beside the core kernel
     hipStream_t side = nullptr;
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
@@ -657,30 +661,33 @@ int multistep_levels(const dpml *H, int64_t nsteps)
     return 1;
 }
 
-// Rows per span of the marching frame steps.
+// Rows per span of the marching frame steps of a problem set.
 constexpr int kFrameRows = 32;
 
-// The spans (64 columns x up to kFrameRows rows, counted across the
+// The spans (64 columns x up to `rows` rows, counted across the
 // periodic wrap) covering everything outside the rectangle S = [S0, S1) x
 // [S2, S3) of a 2D grid: the rows outside S on every column, and S's rows on
 // the columns outside S (one strip across the wrap).  An axis where S spans
 // the whole grid adds nothing.
-void frame_spans(const Layout &L, const int S[4], int prob, std::vector<dpmlk::Span2> &out)
+void frame_spans(const Layout &L, const int S[4], int prob, std::vector<dpmlk::Span2> &out, int rows = kFrameRows)
 {
     const int NX = (int)L.N[0], NY = (int)L.N[1];
     auto rect = [&](int xs, int xe, int ys, int ye) {
-        for (int y = ys; y < ye; y += kFrameRows)
+        for (int y = ys; y < ye; y += rows)
             for (int x = xs; x < xe; x += 64)
-                out.push_back({prob, x, std::min(x + 64, xe), y, std::min(y + kFrameRows, ye), 0, 0, 0});
+                out.push_back({prob, x, std::min(x + 64, xe), y, std::min(y + rows, ye), 0, 0, 0});
     };
     if (S[3] - S[2] < NY) rect(0, NX, S[3], S[2] + NY);
     if (S[1] - S[0] < NX) rect(S[1], S[0] + NX, S[2], S[3]);
 }
 
+// Frame span rows of the two- and three-step variants: bits 16-19 of
+// tile_rows (0: the frame one thread per cell).
+int frame_span_rows(const dpml *H) { return (H->tile_rows >> 16) & 0xF; }
+
 int ensure_frame(dpml *H, int levels, int shrink)
 {
     const int q = levels - 2;
-    if (H->n_frame[q][shrink] >= 0) return DPML_OK;
     const Layout &L = H->L;
     int r[4];
     core_rect(L, levels, r);
@@ -688,8 +695,28 @@ int ensure_frame(dpml *H, int levels, int shrink)
     r[1] -= shrink;
     r[2] += shrink;
     r[3] -= shrink;
-    // one grid's frame: 64 x 4 tiles one thread per cell (many more waves
-    // than the frame has spans to march)
+    const int fr = frame_span_rows(H);
+    if (fr > 0) {
+        if (H->fspan_rows != fr) {                    // span lists of another height
+            for (int a = 0; a < 2; ++a)
+                for (int b = 0; b < 3; ++b) {
+                    if (H->d_fspan[a][b]) HIP_TRY(H, hipFree(H->d_fspan[a][b]));
+                    H->d_fspan[a][b] = nullptr;
+                    H->n_fspan[a][b] = -1;
+                }
+            H->fspan_rows = fr;
+        }
+        if (H->n_fspan[q][shrink] >= 0) return DPML_OK;
+        std::vector<dpmlk::Span2> sp;
+        frame_spans(L, r, 0, sp, fr);
+        H->n_fspan[q][shrink] = (int64_t)sp.size();
+        if (sp.empty()) return DPML_OK;
+        HIP_TRY(H, hipMalloc((void **)&H->d_fspan[q][shrink], sp.size() * sizeof(dpmlk::Span2)));
+        HIP_TRY(H, hipMemcpy(H->d_fspan[q][shrink], sp.data(), sp.size() * sizeof(dpmlk::Span2), hipMemcpyHostToDevice));
+        return DPML_OK;
+    }
+    if (H->n_frame[q][shrink] >= 0) return DPML_OK;
+    // one thread per cell over 64 x 4 tiles
     const int tx = (int)((L.N[0] + 63) / 64), ty = (int)((L.N[1] + 3) / 4);
     std::vector<dpmlk::TileRef> t;
     for (int y = 0; y < ty; ++y)
@@ -783,7 +810,8 @@ int launch_multistep(dpml *H, int levels)
     // j = 1) and the level before it, aux buffers alternating
     for (int j = 1; j <= levels; ++j) {
         const int sh = levels - j;
-        const int nf = (int)H->n_frame[q][sh];
+        const int fr = frame_span_rows(H);
+        const int nf = (int)(fr > 0 ? H->n_fspan[q][sh] : H->n_frame[q][sh]);
         if (nf <= 0) continue;
         if (j % 2 == 0) H->cur = 1 - H->cur;
         dpmlk::StepArgs<T> pj = make_args<T>(H);
@@ -798,8 +826,12 @@ int launch_multistep(dpml *H, int levels)
         // algorithmic share: the frame's own cells (the ring cells it recomputes
         // are the core's, counted there)
         const int slot = timed_begin(H, DPML_KERNEL_FRAME, step_bytes(H, (double)L.ncell - core, aux_cells(L)), H->side);
-        hipLaunchKernelGGL((dpmlk::k_step_frame<T>), dim3((unsigned)round8(nf), B), block, 0, H->side, pj,
-                           H->d_frame[q][sh], nf);
+        if (fr > 0)
+            hipLaunchKernelGGL((dpmlk::k_step_frame_march<T, 4>), dim3((unsigned)round8((nf + 3) / 4), B), block, 0,
+                               H->side, pj, H->d_fspan[q][sh], nf);
+        else
+            hipLaunchKernelGGL((dpmlk::k_step_frame<T>), dim3((unsigned)round8(nf), B), block, 0, H->side, pj,
+                               H->d_frame[q][sh], nf);
         timed_end(H, slot, H->side);
     }
     // join
@@ -1375,8 +1407,10 @@ void dpml_destroy(dpml_t *H)
     if (H->d_src_order) (void)hipFree(H->d_src_order);
     if (H->d_rec_cells) (void)hipFree(H->d_rec_cells);
     for (int k = 0; k < 2; ++k)
-        for (int j = 0; j < 3; ++j)
+        for (int j = 0; j < 3; ++j) {
             if (H->d_frame[k][j]) (void)hipFree(H->d_frame[k][j]);
+            if (H->d_fspan[k][j]) (void)hipFree(H->d_fspan[k][j]);
+        }
     if (H->ev_fork) (void)hipEventDestroy(H->ev_fork);
     if (H->ev_join) (void)hipEventDestroy(H->ev_join);
     if (H->side) (void)hipStreamDestroy(H->side);
@@ -2509,6 +2543,9 @@ int step_graph_impl(dpml *H, int64_t nsteps)
             for (int sh = 0; sh < 3; ++sh) {
                 view.d_frame[lv - 2][sh] = H->d_frame[lv - 2][sh];
                 view.n_frame[lv - 2][sh] = H->n_frame[lv - 2][sh];
+                view.d_fspan[lv - 2][sh] = H->d_fspan[lv - 2][sh];
+                view.n_fspan[lv - 2][sh] = H->n_fspan[lv - 2][sh];
+                view.fspan_rows = H->fspan_rows;
             }
         }
         {
@@ -2525,7 +2562,10 @@ int step_graph_impl(dpml *H, int64_t nsteps)
         view.cap = nullptr; view.graph = nullptr; view.exec = nullptr;   // not owned by the view
         view.d_src_cells = view.d_src_order = view.d_rec_cells = view.d_rec_sorted = view.d_rec_order = nullptr;
         for (int lv = 0; lv < 2; ++lv)
-            for (int sh = 0; sh < 3; ++sh) view.d_frame[lv][sh] = nullptr;
+            for (int sh = 0; sh < 3; ++sh) {
+                view.d_frame[lv][sh] = nullptr;
+                view.d_fspan[lv][sh] = nullptr;
+            }
         view.side = nullptr;
         view.ev_fork = view.ev_join = nullptr;
         H->graph_end_unow = view.u_now;

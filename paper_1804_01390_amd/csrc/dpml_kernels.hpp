@@ -709,9 +709,9 @@ __global__ void __launch_bounds__(256) k_step2_march(StepArgs<T> p, T *__restric
 }
 
 // ---------------------------------------------------------------------------
-// Frame steps of many problems as wave marches (a set of problems has enough
-// spans to fill the GPU; one grid's frame is better served one thread per
-// cell).  On a periodic 2D grid everything outside a
+// Frame steps as wave marches (the frames of a problem set; one grid's frame
+// in spans of a few rows, as the tuner chooses).  On a periodic 2D grid
+// everything outside a
 // rectangle S is two wrapped rectangles: the rows outside S (every column)
 // and S's rows on the columns outside S (one strip across the x wrap).  A
 // span is 64 consecutive columns [xs, xe) of one of them and a chunk of its
@@ -790,6 +790,16 @@ __device__ __forceinline__ void frame_march_wave(const StepArgs<T> &p, const Spa
         w[0] = w[1];
         w[1] = w[2];
     }
+}
+
+// A frame step of one grid (and its batch members) over a span list.
+template <typename T, int G>
+__global__ void __launch_bounds__(256) k_step_frame_march(StepArgs<T> p, const Span2 *__restrict__ spans, int n)
+{
+    const int w = __builtin_amdgcn_readfirstlane(xcd_tile(blockIdx.x, gridDim.x) * 4 + (int)(threadIdx.x >> 6));
+    if (w >= n) return;                                      // whole waves; no barriers below
+    select_member(p, (int)blockIdx.y);
+    frame_march_wave<T, G>(p, spans[w]);
 }
 
 // A frame step of many problems over one span list (span.prob selects the

@@ -369,11 +369,14 @@ def test_twostep_matches_single_steps_and_oracle(dtype, case, rows, multi):
 
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
 @pytest.mark.parametrize("variant", [dp.VARIANT_TWOSTEP, dp.VARIANT_THREESTEP])
-@pytest.mark.parametrize("group,rows", [(1, 3), (4, 7), (4, 4), (2, 1)])
+@pytest.mark.parametrize("group,rows", [(1, 3), (4, 7), (4, 4), (2, 1), (1 << 4 | 4, 8), (3 << 4 | 2, 5),
+                                        (5 << 4 | 4, 6)])
 def test_multistep_launch_shapes_bit_identical(dtype, variant, group, rows):
     """Every load-group size and tile height of the two- and three-step
-    kernels (tiles shorter than a group, one-row tiles) gives the single-step
-    result bit for bit, with a c^2 field and a ragged grid."""
+    kernels (tiles shorter than a group, one-row tiles), and the frame's
+    steps one thread per cell or as wave marches over spans of 1, 3 or 5
+    rows (group's high bits), give the single-step result bit for bit, with
+    a c^2 field and a ragged grid."""
     rng = np.random.default_rng(5)
     n, lo, hi = [333, 157], [7, 11], [9, 4]
     sig = [synthetic.sigma_random(n[a], lo[a], hi[a], 2.0, rng) for a in range(2)]
@@ -395,12 +398,13 @@ def test_multistep_launch_shapes_bit_identical(dtype, variant, group, rows):
         assert np.array_equal(x, y)
 
 
+@pytest.mark.parametrize("tile_rows", [0, (3 << 16) | (4 << 12) | 8])
 @pytest.mark.parametrize("variant", [dp.VARIANT_TWOSTEP, dp.VARIANT_THREESTEP])
-def test_twostep_graph_replay_matches_eager(variant):
+def test_twostep_graph_replay_matches_eager(variant, tile_rows):
     w = synthetic.bump2d(200, 20, 0)
     a = dp.Simulation(w.n, w.lo, w.hi, w.h, w.dt, w.sigma, dtype=torch.float32)
     b = dp.Simulation(w.n, w.lo, w.hi, w.h, w.dt, w.sigma, dtype=torch.float32)
-    a.set_variant(variant, 0)
+    a.set_variant(variant, tile_rows)
     a.set_state(torch.from_numpy(w.U0))
     b.set_state(torch.from_numpy(w.U0))
     for rep, k in enumerate([10, 10, 7, 7, 10]):
