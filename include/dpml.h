@@ -88,7 +88,9 @@ extern "C" {
                                  64 columns x 4 rows of three planes in registers  */
 #define DPML_VARIANT_MARCH1 3 /* as MARCH; 2D: one row at a time; 3D: waves of 64
                                  columns x 2 rows                                    */
-#define DPML_VARIANT_TWOSTEP 4 /* 2D periodic runs without sources/receivers/planes:
+#define DPML_VARIANT_TWOSTEP 4 /* 2D runs without sources/receivers/planes (with
+                                  reflecting walls when every walled axis has a
+                                  layer with a cell above the interior):
                                   two steps per pass over the layer-free core
                                   (temporal blocking: each wave marches down a
                                   strip keeping U^n and U^{n+1} rows in registers,
@@ -99,9 +101,10 @@ extern "C" {
                                   bits 16-19 (0 = the frame one thread per
                                   cell)), the frame holding the layer in single
                                   steps.
-                                  3D periodic runs with a constant c^2, one batch
-                                  member and at most 32 sources, all at least 3
-                                  cells inside the layer-free region: the same
+                                  3D runs with a constant c^2, one batch member
+                                  (walls as in 2D) and at most 32 sources, all at
+                                  least 3 cells inside the layer-free region: the
+                                  same
                                   with each wave marching in z over 64 columns x
                                   RY rows (tile_rows: planes per chunk in bits
                                   0-11 (0 = 32), RY in bits 12-19 (4, 8 or 16;

@@ -603,6 +603,18 @@ void core_rect(const Layout &L, int levels, int r[4])
     }
 }
 
+// Multi-step passes with reflecting walls: the core kernels read `levels`
+// cells beyond their outputs, which stays inside the grid (the ghost cells
+// past a wall are never read) when every walled axis has a layer with at
+// least one cell above the interior; an axis without a layer is core over its
+// whole extent and wraps, so it must be periodic.
+bool walls_allow_multistep(const Layout &L)
+{
+    for (int a = 0; a < L.ndim; ++a)
+        if (L.wall[a] && (L.M[a] == 0 || L.N[a] - L.lo[a] - L.n[a] < 1)) return false;
+    return true;
+}
+
 // Core box of a 3D two-step pass shrunk by `shrink` cells: [lo+2+shrink,
 // lo+n-1-shrink) along an axis with a layer (the cells whose one-cell halo is
 // free of damping terms), the whole periodic axis without one.
@@ -622,14 +634,15 @@ dpmlk::Box3 core_box3d(const Layout &L, int shrink)
     return dpmlk::Box3{r[0], r[1], r[2], r[3], r[4], r[5]};
 }
 
-// 3D: two levels per pass for variants TWOSTEP and THREESTEP on periodic
-// single-member grids with a constant c^2, at most 32 sources, all inside the
-// core shrunk by one (the frame's steps then add none); otherwise 1.
+// 3D: two levels per pass for variants TWOSTEP and THREESTEP on
+// single-member grids with a constant c^2 (walls as walls_allow_multistep
+// admits), at most 32 sources, all inside the core shrunk by one (the frame's
+// steps then add none); otherwise 1.
 int multistep_levels3d(const dpml *H, int64_t nsteps)
 {
     const Layout &L = H->L;
     if (H->variant != DPML_VARIANT_TWOSTEP && H->variant != DPML_VARIANT_THREESTEP) return 1;
-    if (nsteps < 2 || L.batch != 1 || H->c2_field || L.wall[0] || L.wall[1] || L.wall[2]) return 1;
+    if (nsteps < 2 || L.batch != 1 || H->c2_field || !walls_allow_multistep(L)) return 1;
     if (L.N[0] < 8 || L.N[1] < 8 || L.N[2] < 8 || H->ns > 32) return 1;
     const dpmlk::Box3 c = core_box3d(L, 0), in1 = core_box3d(L, 1);
     if (in1.xe <= in1.xs || in1.ye <= in1.ys || in1.ze <= in1.zs) return 1;
@@ -647,7 +660,7 @@ int multistep_levels(const dpml *H, int64_t nsteps)
 {
     const Layout &L = H->L;
     if (L.ndim == 3) return multistep_levels3d(H, nsteps);
-    if (L.wall[0] || L.wall[1]) return 1;
+    if (!walls_allow_multistep(L)) return 1;
     if (H->ns > 0 || (H->recording && (H->nr > 0 || H->plane_axis >= 0))) return 1;
     int want = H->variant == DPML_VARIANT_THREESTEP ? 3 : (H->variant == DPML_VARIANT_TWOSTEP ? 2 : 1);
     if (want > nsteps) want = (int)nsteps;
@@ -682,8 +695,12 @@ void frame_spans(const Layout &L, const int S[4], int prob, std::vector<dpmlk::S
 }
 
 // Frame span rows of the two- and three-step variants: bits 16-19 of
-// tile_rows (0: the frame one thread per cell).
-int frame_span_rows(const dpml *H) { return (H->tile_rows >> 16) & 0xF; }
+// tile_rows (0: the frame one thread per cell, as always with walls: the
+// marching frame assumes the periodic wrap).
+int frame_span_rows(const dpml *H)
+{
+    return (H->L.wall[0] || H->L.wall[1]) ? 0 : (H->tile_rows >> 16) & 0xF;
+}
 
 int ensure_frame(dpml *H, int levels, int shrink)
 {
