@@ -1511,6 +1511,7 @@ int forward_ckpt_impl(dpml *H, int64_t nsteps)
 }
 
 constexpr int kAdjRows = 4;   // rows per wave of the 2D marching adjoint kernel
+constexpr int kAdjFrameGroups = 8;   // waves (shot groups) per block of the 2D adjoint frame
 
 // Core of the 2D adjoint: cells whose update, and whose neighbours' band
 // slots, carry no layer term: [lo+2, lo+n-1) on an axis with a layer, the
@@ -1676,7 +1677,8 @@ int adjoint_impl(dpml *H, const void *resid, double *grad, void *grad_w)
                     f.tiles = H->d_adj_frame;
                     f.ntiles = (int32_t)H->n_adj_frame;
                     for (int k = 0; k < 4; ++k) f.skip[k] = core[k];
-                    hipLaunchKernelGGL((dpmlk::k_adjoint_frame2d<T>), fgrid, ablock, 0, fork ? H->side : H->stream, f);
+                    hipLaunchKernelGGL((dpmlk::k_adjoint_frame2d<T, kAdjFrameGroups>), fgrid, dim3(64 * kAdjFrameGroups),
+                                       0, fork ? H->side : H->stream, f);
                 }
                 if (adj_waves > 0)
                     hipLaunchKernelGGL((dpmlk::k_adjoint_march2d<T, kAdjRows>), mgrid, ablock, 0, H->stream, q,
@@ -1938,11 +1940,14 @@ int multi_shape(dpml_multi *H)
     return DPML_OK;
 }
 
+// Upload a table into an empty slot (a filled slot may be read by work in
+// flight and is never rewritten; the tables are dropped only after a sync).
 template <typename T>
 int upload_table(dpml_multi *H, int slot, const void *data, size_t bytes)
 {
     if ((size_t)slot >= H->d_args.size()) H->d_args.resize((size_t)slot + 1, nullptr);
-    if (!H->d_args[slot]) HIP_TRY(nullptr, hipMalloc(&H->d_args[slot], bytes));
+    if (H->d_args[slot]) return DPML_OK;
+    HIP_TRY(nullptr, hipMalloc(&H->d_args[slot], bytes));
     HIP_TRY(nullptr, hipMemcpy(H->d_args[slot], data, bytes, hipMemcpyHostToDevice));
     return DPML_OK;
 }

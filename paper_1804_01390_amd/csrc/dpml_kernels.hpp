@@ -1740,14 +1740,14 @@ __global__ void __launch_bounds__(256) k_adjoint_cell(AdjArgs<T> p)
 }
 
 // The 2D frame of the adjoint (cells outside the marching core) over a list
-// of 64 x 4 tiles: a block takes one row of 64 cells of a tile, and its four
-// waves split the shots (wave w takes shots w, w+4, ...), so a frame cell's
-// shot loop is four times shorter.  The four FP64 partial gradients of a
-// cell are added in LDS in a fixed order (no atomics).
-template <typename T>
-__global__ void __launch_bounds__(256) k_adjoint_frame2d(AdjArgs<T> p)
+// of 64 x 4 tiles: a block takes one row of 64 cells of a tile, and its NG
+// waves split the shots (wave w takes shots w, w+NG, ...), so a frame cell's
+// shot loop is NG times shorter.  The NG FP64 partial gradients of a cell
+// are added in LDS in a fixed order (no atomics).
+template <typename T, int NG>
+__global__ void __launch_bounds__(64 * NG) k_adjoint_frame2d(AdjArgs<T> p)
 {
-    __shared__ double part[4][64];
+    __shared__ double part[NG][64];
     const int b = xcd_tile(blockIdx.x, gridDim.x);
     const int t = b >> 2, row = b & 3;
     const int lane = (int)(threadIdx.x & 63), w = (int)(threadIdx.x >> 6);
@@ -1759,9 +1759,14 @@ __global__ void __launch_bounds__(256) k_adjoint_frame2d(AdjArgs<T> p)
         y = tl.ty * 4 + row;
         ok = x < p.nx && y < p.ny && !(x >= p.skip[0] && x < p.skip[1] && y >= p.skip[2] && y < p.skip[3]);
     }
-    part[w][lane] = ok ? adj_cell<T, 2>(p, x, y, 0, w, 4) : 0.0;
+    part[w][lane] = ok ? adj_cell<T, 2>(p, x, y, 0, w, NG) : 0.0;
     __syncthreads();
-    if (ok && w == 0) p.grad[(int64_t)y * p.nx + x] += ((part[0][lane] + part[1][lane]) + part[2][lane]) + part[3][lane];
+    if (ok && w == 0) {
+        double g = part[0][lane];
+#pragma unroll
+        for (int k = 1; k < NG; ++k) g += part[k][lane];
+        p.grad[(int64_t)y * p.nx + x] += g;
+    }
 }
 
 // Load / store through a base pointer plus a 32-bit byte offset: with a
