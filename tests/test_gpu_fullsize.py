@@ -152,11 +152,15 @@ def test_ricker3d_full_size_sampled_steps():
 
 
 def test_batch_full_size_sampled_problems():
-    """The 256-problem batch (graph launch): the three smallest problems run
-    all 1500 steps against the oracle; three others are checked one step from
-    the GPU state after 1500 steps."""
+    """The 256-problem batch in the benchmark's launch (tuned scheme and shape,
+    graph launch): the three smallest problems run all 1500 steps against the
+    oracle; three others are checked one step from the GPU state after 1500
+    steps."""
+    from paper_1804_01390_amd import autotune
     probs = synthetic.batch2d(count=256, steps=1500)
     sim = dp.MultiSimulation(probs, dtype=torch.float32)
+    choice = autotune.tune_multi(sim, [w.U0 for w in probs], steps=20)
+    _log("launch variant=%d tile_rows=%d group=%d" % (choice["variant"], choice["tile_rows"], choice["group"]))
     sim.set_state([w.U0 for w in probs])
     sim.step(1499, graph=True)
     sim.sync()
