@@ -674,8 +674,10 @@ int multistep_levels(const dpml *H, int64_t nsteps)
     return 1;
 }
 
-// Rows per span of the marching frame steps of a problem set.
-constexpr int kFrameRows = 32;
+// Rows per span of the marching frame steps of a problem set, and rows
+// whose loads a wave issues together (measured on the 256-problem set).
+constexpr int kFrameRows = 16;
+constexpr int kFrameGroup = 8;
 
 // The spans (64 columns x up to `rows` rows, counted across the
 // periodic wrap) covering everything outside the rectangle S = [S0, S1) x
@@ -2127,8 +2129,8 @@ int multi_launch_pass(dpml_multi *H, hipStream_t s, int key, int levels)
         const int nf = (int)H->n_frame[q][j - 1];
         const auto *fa = (const dpmlk::StepArgs<T> *)H->d_args[(size_t)key * kRoles + rb + j];
         if (nf > 0)
-            hipLaunchKernelGGL((dpmlk::k_multi_frame_march<T, 4>), dim3((unsigned)round8((nf + 3) / 4)), block, 0,
-                               H->side, fa, H->d_frame[q][j - 1], nf);
+            hipLaunchKernelGGL((dpmlk::k_multi_frame_march<T, kFrameGroup>), dim3((unsigned)round8((nf + 3) / 4)),
+                               block, 0, H->side, fa, H->d_frame[q][j - 1], nf);
     }
     HIP_TRY(nullptr, hipEventRecord(H->ev_join, H->side));
     HIP_TRY(nullptr, hipStreamWaitEvent(s, H->ev_join, 0));
