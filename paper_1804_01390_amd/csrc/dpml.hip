@@ -423,7 +423,7 @@ int launch_march3d(dpml *H, dpmlk::StepArgs<T> p, int ry)
     const Layout &L = H->L;
     int b[4];
     march_box3d(L, b);
-    const int NX = (int)L.N[0], NY = (int)L.N[1], NZ = (int)L.N[2];
+    const int NX = (int)L.N[0], NZ = (int)L.N[2];
     const bool layers = L.M[0] > 0 || L.M[1] > 0 || L.M[2] > 0;
     if (layers) {
         int rc = ensure_side(H);
@@ -432,7 +432,6 @@ int launch_march3d(dpml *H, dpmlk::StepArgs<T> p, int ry)
         HIP_TRY(H, hipStreamWaitEvent(H->side, H->ev_fork, 0));
     }
     hipStream_t ls = layers ? H->side : H->stream;     // stream of the layer parts
-    const int nstrips = (NX + 63) / 64;
     int x0 = 0, x1 = NX;
     if (L.M[0] > 0) {
         const int s0 = (L.lo[0] + 1 + 63) / 64;
@@ -441,7 +440,6 @@ int launch_march3d(dpml *H, dpmlk::StepArgs<T> p, int ry)
         x0 = 64 * s0;
         x1 = std::min(64 * s1, NX);
     }
-    (void)nstrips;
     const int zc = (H->tile_rows & 0xFFF) > 0 ? (H->tile_rows & 0xFFF) : 32;
     const int zl = std::max(8, zc / 4);               // layer boxes: few tiles, shorter chunks
     int rc;

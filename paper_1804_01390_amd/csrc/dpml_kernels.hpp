@@ -916,7 +916,7 @@ struct March3Ctx : March2Ctx<T, VX, C2F> {
     // G march indices k .. k+G-1 in the steady state (every level inside the
     // tile's range), all loads of the group issued first
     template <int G, int DIR>
-    __device__ __forceinline__ void group(State &s, int base, int k, int L) const
+    __device__ __forceinline__ void group(State &s, int base, int k) const
     {
         R wn[G + 2], pm[G], v1[G + 2], v2[G + 2], cw[G + 2];
         wn[0] = s.n0;
@@ -961,7 +961,7 @@ struct March3Ctx : March2Ctx<T, VX, C2F> {
         int k = -2;
         for (; k <= 1 && k <= L + 1; ++k) one<DIR>(s, base, k, L);
         // steady state: U^{n+1}(k) .. with k-2 >= 0 and k+G-1 <= L-1 (no guards needed)
-        for (; k + G - 1 <= L - 1; k += G) group<G, DIR>(s, base, k, L);
+        for (; k + G - 1 <= L - 1; k += G) group<G, DIR>(s, base, k);
         for (; k <= L + 1; ++k) one<DIR>(s, base, k, L);
     }
 };
