@@ -1,12 +1,14 @@
-"""Tile-shape autotuner for the fused step kernels.
+"""Launch-shape autotuner for the fused step kernels.
 
-For a given grid (dimension, extents, dtype, batch) it times the candidate
-launch shapes -- the marching kernel with several tile heights, and the
-one-thread-per-cell kernel -- on the GPU with HIP events, keeps the fastest,
-and caches the choice in a JSON file keyed by the grid so later runs reuse
-it without timing.  Every candidate computes the same result (the kernels
-evaluate the scheme in the same operation order), so tuning never changes
-numerics.
+For a given grid (dimension, extents, dtype, batch, walls) it times the
+candidate (variant, tile_rows) pairs -- one thread per cell, the marching
+single-step kernels with several tile heights, and the two- and three-step
+passes with several wave heights, load groups and frame forms -- on the GPU
+with HIP events, keeps the fastest, and caches the choice in a JSON file
+keyed by the grid so later runs reuse it without timing.  ``tune_multi`` does
+the same for a set of problems (single steps, two- or three-step passes).
+Every candidate computes the same result (the kernels evaluate the scheme in
+the same operation order), so tuning never changes numerics.
 """
 from __future__ import annotations
 
@@ -23,7 +25,8 @@ DEFAULT_CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "autotu
 CANDIDATES_2D: List[Tuple[int, int]] = ([(VARIANT_THREESTEP, (g << 12) | r) for g in (2, 4) for r in (4, 6, 8, 12, 16)]
                                         + [(VARIANT_THREESTEP, (f << 16) | (4 << 12) | r) for f in (2, 3, 4)
                                            for r in (6, 8)]
-                                        + [(VARIANT_TWOSTEP, (g << 12) | r) for g in (2, 4) for r in (8, 16)] + [(VARIANT_CELL, th) for th in (1, 2, 4, 8)]
+                                        + [(VARIANT_TWOSTEP, (g << 12) | r) for g in (2, 4) for r in (8, 16)]
+                                        + [(VARIANT_CELL, th) for th in (1, 2, 4, 8)]
                                         + [(VARIANT_MARCH, r) for r in (4, 8, 16)]
                                         + [(VARIANT_MARCH1, r) for r in (4, 8, 16)])
 # 3D two-step passes: rows per wave above bit 12, planes per chunk below
