@@ -119,6 +119,12 @@ extern "C" {
                                   frame's steps write it; tile_rows as for
                                   TWOSTEP); a remaining pair takes the two-step
                                   pass.  3D: as TWOSTEP                            */
+#define DPML_VARIANT_FOURSTEP 6  /* 2D: as THREESTEP with four steps per pass over a
+                                  core one cell smaller again (4 words per cell per
+                                  four steps: U^{n+1} and U^{n+2} stay in
+                                  registers, U^{n+3} is stored off the core's
+                                  boundary ring); remaining steps take the three-
+                                  or two-step pass.  3D: as TWOSTEP               */
 
 typedef struct dpml_grid {
     int32_t ndim;    /* 2 or 3 */
@@ -360,6 +366,9 @@ int64_t dpml_multi_tiles(const dpml_multi_t *h);
  *   DPML_VARIANT_THREESTEP: as TWOSTEP with three steps per pass over cores
  *     one cell smaller (U^{n+1} kept in registers), three frame steps, and
  *     a two-step pass for a remaining pair.
+ *   DPML_VARIANT_FOURSTEP: four steps per pass over cores one cell smaller
+ *     again (U^{n+1} and U^{n+2} kept in registers), four frame steps, and
+ *     a three- or two-step pass for the remaining steps.
  * Results do not depend on the choice.  Drops a captured graph.
  * DPML_EINVAL for another variant or a shape out of range. */
 int dpml_multi_set_variant(dpml_multi_t *h, int32_t variant, int32_t tile_rows, int32_t group);

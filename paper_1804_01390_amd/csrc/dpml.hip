@@ -42,7 +42,7 @@ struct Layout {
     int64_t aux_elems[3] = {0, 0, 0};   // elements of one compact aux array (one problem)
     // byte offsets into the workspace
     int n_ubuf = 2;                     // U buffers: U^n, U^{n-1} (+ spares of the multi-step variants)
-    size_t off_u[5] = {0, 0, 0, 0, 0};
+    size_t off_u[6] = {0, 0, 0, 0, 0, 0};
     size_t off_c2 = 0;
     size_t off_phi[3][2] = {{0, 0}, {0, 0}, {0, 0}};
     size_t off_psi[3][2] = {{0, 0}, {0, 0}, {0, 0}};
@@ -53,10 +53,10 @@ struct Layout {
 
 constexpr int kFlagBlocks = 1024;
 
-// U buffers of a single-grid handle: 2D grids carry three spares for the
-// two- and three-step variants (which write U^{n+1} .. U^{n+3} beside U^n and
-// U^{n-1}); 3D grids only U^n and U^{n-1}.
-int handle_ubufs(const dpml_grid_t *g) { return g && g->ndim == 2 ? 5 : 4; }
+// U buffers of a single-grid handle: 2D grids carry four spares for the
+// multi-step variants (which write U^{n+1} .. U^{n+4} beside U^n and
+// U^{n-1}); 3D grids two (U^{n+1}, U^{n+2} of the two-step pass).
+int handle_ubufs(const dpml_grid_t *g) { return g && g->ndim == 2 ? 6 : 4; }
 
 // Validate the grid and compute the workspace layout.  Returns "" or an error.
 std::string make_layout(const dpml_grid_t *g, bool c2_field, Layout &L, int n_ubuf)
@@ -123,13 +123,13 @@ struct dpml {
     bool state_set = false;
     int variant = DPML_VARIANT_AUTO;
     int tile_rows = 0;
-    // frame tiles of the two- and three-step variants: [levels - 2][s] covers
+    // frame tiles of the multi-step variants: [levels - 2][s] covers
     // everything outside the core shrunk by s cells (-1: not built yet)
-    dpmlk::TileRef *d_frame[2][3] = {{nullptr, nullptr, nullptr}, {nullptr, nullptr, nullptr}};
-    int64_t n_frame[2][3] = {{-1, -1, -1}, {-1, -1, -1}};
+    dpmlk::TileRef *d_frame[3][4] = {};
+    int64_t n_frame[3][4] = {{-1, -1, -1, -1}, {-1, -1, -1, -1}, {-1, -1, -1, -1}};
     // the same frames as spans for the marching frame kernel (span rows fspan_rows)
-    dpmlk::Span2 *d_fspan[2][3] = {{nullptr, nullptr, nullptr}, {nullptr, nullptr, nullptr}};
-    int64_t n_fspan[2][3] = {{-1, -1, -1}, {-1, -1, -1}};
+    dpmlk::Span2 *d_fspan[3][4] = {};
+    int64_t n_fspan[3][4] = {{-1, -1, -1, -1}, {-1, -1, -1, -1}, {-1, -1, -1, -1}};
     int fspan_rows = 0;
     // the frame's steps run on a second stream beside the core kernel
     hipStream_t side = nullptr;
@@ -478,7 +478,8 @@ int launch_step(dpml *H, T *hist = nullptr, T *uout = nullptr)
     p.hist = hist;
     p.uout = uout;
     const unsigned B = (unsigned)L.batch;
-    const bool multi = H->variant == DPML_VARIANT_TWOSTEP || H->variant == DPML_VARIANT_THREESTEP;
+    const bool multi = H->variant == DPML_VARIANT_TWOSTEP || H->variant == DPML_VARIANT_THREESTEP ||
+                       H->variant == DPML_VARIANT_FOURSTEP;
     int variant = (H->variant == DPML_VARIANT_AUTO || multi) ? DPML_VARIANT_CELL : H->variant;
     // 3D single steps of the multi-step variants march like MARCH
     if (L.ndim == 3 && multi) variant = DPML_VARIANT_MARCH;
@@ -632,14 +633,16 @@ dpmlk::Box3 core_box3d(const Layout &L, int shrink)
     return dpmlk::Box3{r[0], r[1], r[2], r[3], r[4], r[5]};
 }
 
-// 3D: two levels per pass for variants TWOSTEP and THREESTEP on
+// 3D: two levels per pass for the multi-step variants on
 // single-member grids with a constant c^2 (walls as walls_allow_multistep
 // admits), at most 32 sources, all inside the core shrunk by one (the frame's
 // steps then add none); otherwise 1.
 int multistep_levels3d(const dpml *H, int64_t nsteps)
 {
     const Layout &L = H->L;
-    if (H->variant != DPML_VARIANT_TWOSTEP && H->variant != DPML_VARIANT_THREESTEP) return 1;
+    if (H->variant != DPML_VARIANT_TWOSTEP && H->variant != DPML_VARIANT_THREESTEP &&
+        H->variant != DPML_VARIANT_FOURSTEP)
+        return 1;
     if (nsteps < 2 || L.batch != 1 || H->c2_field || !walls_allow_multistep(L)) return 1;
     if (L.N[0] < 8 || L.N[1] < 8 || L.N[2] < 8 || H->ns > 32) return 1;
     const dpmlk::Box3 c = core_box3d(L, 0), in1 = core_box3d(L, 1);
@@ -652,15 +655,18 @@ int multistep_levels3d(const dpml *H, int64_t nsteps)
     return 2;
 }
 
-// Levels per pass this handle may take right now: 3 (VARIANT_THREESTEP), 2
-// (VARIANT_TWOSTEP, or THREESTEP for a last pair), or 1.
+// Levels per pass this handle may take right now: 4 (VARIANT_FOURSTEP), 3
+// (VARIANT_THREESTEP, or FOURSTEP for a last three), 2 (VARIANT_TWOSTEP, or
+// the deeper variants for a last pair), or 1.
 int multistep_levels(const dpml *H, int64_t nsteps)
 {
     const Layout &L = H->L;
     if (L.ndim == 3) return multistep_levels3d(H, nsteps);
     if (!walls_allow_multistep(L)) return 1;
     if (H->ns > 0 || (H->recording && (H->nr > 0 || H->plane_axis >= 0))) return 1;
-    int want = H->variant == DPML_VARIANT_THREESTEP ? 3 : (H->variant == DPML_VARIANT_TWOSTEP ? 2 : 1);
+    int want = H->variant == DPML_VARIANT_FOURSTEP ? 4
+               : H->variant == DPML_VARIANT_THREESTEP ? 3
+               : H->variant == DPML_VARIANT_TWOSTEP ? 2 : 1;
     if (want > nsteps) want = (int)nsteps;
     // the core kernels wrap halo rows once: each extent must hold its halos
     if (L.N[0] < 8 || L.N[1] < 8) return 1;
@@ -715,8 +721,8 @@ int ensure_frame(dpml *H, int levels, int shrink)
     const int fr = frame_span_rows(H);
     if (fr > 0) {
         if (H->fspan_rows != fr) {                    // span lists of another height
-            for (int a = 0; a < 2; ++a)
-                for (int b = 0; b < 3; ++b) {
+            for (int a = 0; a < 3; ++a)
+                for (int b = 0; b < 4; ++b) {
                     if (H->d_fspan[a][b]) HIP_TRY(H, hipFree(H->d_fspan[a][b]));
                     H->d_fspan[a][b] = nullptr;
                     H->n_fspan[a][b] = -1;
@@ -763,7 +769,7 @@ int ensure_multistep(dpml *H, int levels)
     return ensure_side(H);
 }
 
-// `levels` (2 or 3) steps.  The core kernel runs on the handle's stream;
+// `levels` (2, 3 or 4) steps.  The core kernel runs on the handle's stream;
 // the frame takes `levels` ordinary steps on the side stream at the same
 // time, step j (1-based) over everything outside the core shrunk by
 // levels - j cells, which is where the later frame steps need level j.  The
@@ -778,7 +784,7 @@ int launch_multistep(dpml *H, int levels)
     const int q = levels - 2;
     // buffers: A = U^n, Bv = U^{n-1}, then U^{n+1} .. U^{n+levels} in the spares
     T *A = (T *)H->u_now, *Bv = (T *)H->u_old;
-    T *nxt[3] = {nullptr, nullptr, nullptr};
+    T *nxt[4] = {nullptr, nullptr, nullptr, nullptr};
     int k = 0;
     for (int i = 0; i < L.n_ubuf && k < levels; ++i) {
         void *b = H->at(L.off_u[i]);
@@ -810,9 +816,12 @@ int launch_multistep(dpml *H, int levels)
         if (levels == 2)                                                                                    \
             hipLaunchKernelGGL((dpmlk::k_step2_march<T, VX, GG, C2>), grid, block, 0, H->stream, p, nxt[1],     \
                                r[0], r[1], r[2], r[3], strips, n_waves);                                    \
-        else                                                                                                \
+        else if (levels == 3)                                                                               \
             hipLaunchKernelGGL((dpmlk::k_step3_march<T, VX, GG, C2>), grid, block, 0, H->stream, p, nxt[1],     \
-                               nxt[2], r[0], r[1], r[2], r[3], strips, n_waves);
+                               nxt[2], r[0], r[1], r[2], r[3], strips, n_waves);                            \
+        else                                                                                                \
+            hipLaunchKernelGGL((dpmlk::k_step4_march<T, VX, GG, C2>), grid, block, 0, H->stream, p, nxt[2],     \
+                               nxt[3], r[0], r[1], r[2], r[3], strips, n_waves);
         if (G == 4) {
             if (p.c2) { DPML_MULTI_LAUNCH(4, true) } else { DPML_MULTI_LAUNCH(4, false) }
         } else if (G == 1) {
@@ -1260,7 +1269,7 @@ int dpml_record_plane(dpml_t *H, int32_t axis, int64_t index, void *planes, int6
 int dpml_set_variant(dpml_t *H, int32_t variant, int32_t tile_rows)
 {
     if (!H) return DPML_EINVAL;
-    if (variant < DPML_VARIANT_AUTO || variant > DPML_VARIANT_THREESTEP || tile_rows < 0 || tile_rows >= (1 << 20))
+    if (variant < DPML_VARIANT_AUTO || variant > DPML_VARIANT_FOURSTEP || tile_rows < 0 || tile_rows >= (1 << 20))
         return H->fail(DPML_EINVAL, "bad variant");
     H->variant = variant;
     H->tile_rows = tile_rows;
@@ -1423,8 +1432,8 @@ void dpml_destroy(dpml_t *H)
     if (H->d_src_cells) (void)hipFree(H->d_src_cells);
     if (H->d_src_order) (void)hipFree(H->d_src_order);
     if (H->d_rec_cells) (void)hipFree(H->d_rec_cells);
-    for (int k = 0; k < 2; ++k)
-        for (int j = 0; j < 3; ++j) {
+    for (int k = 0; k < 3; ++k)
+        for (int j = 0; j < 4; ++j) {
             if (H->d_frame[k][j]) (void)hipFree(H->d_frame[k][j]);
             if (H->d_fspan[k][j]) (void)hipFree(H->d_fspan[k][j]);
         }
@@ -1773,7 +1782,7 @@ struct dpml_multi {
     size_t off_tiles = 0;            // single-step tile list (workspace)
     int64_t ntiles = 0;
     int vx = 1;
-    int variant = DPML_VARIANT_MARCH;  // MARCH: single steps; TWOSTEP, THREESTEP: multi-step passes
+    int variant = DPML_VARIANT_MARCH;  // MARCH: single steps; TWOSTEP .. FOURSTEP: multi-step passes
     int tile_rows = 32;              // single steps: rows per marching tile
     int group = 4;                   // single steps: rows whose loads are issued together
     int pass_rows = 8;               // multi-step passes: rows per core wave
@@ -1783,13 +1792,13 @@ struct dpml_multi {
     int64_t n = 0;
     bool state_set = false;
     // library-owned tables: step arguments per rotation state and role, and
-    // the work lists of the two- and three-step passes ([levels - 2])
+    // the work lists of the multi-step passes ([levels - 2])
     std::vector<void *> d_args;      // [state * kRoles + role]
-    dpmlk::TileRef *d_core_waves[2] = {nullptr, nullptr};
-    int64_t n_core_waves[2] = {-1, -1};   // -1: not built for pass_rows yet
-    dpmlk::Span2 *d_frame[2][3] = {{nullptr, nullptr, nullptr}, {nullptr, nullptr, nullptr}};
-    int64_t n_frame[2][3] = {{0, 0, 0}, {0, 0, 0}};
-    int pass_ok[2] = {-1, -1};       // every problem has a core for the pass (-1: not checked)
+    dpmlk::TileRef *d_core_waves[3] = {nullptr, nullptr, nullptr};
+    int64_t n_core_waves[3] = {-1, -1, -1};   // -1: not built for pass_rows yet
+    dpmlk::Span2 *d_frame[3][4] = {};
+    int64_t n_frame[3][4] = {};
+    int pass_ok[3] = {-1, -1, -1};   // every problem has a core for the pass (-1: not checked)
     hipStream_t side = nullptr;
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -1814,22 +1823,24 @@ struct MultiLayout {
 
 // The single-step tile list is sized for the shortest tiles allowed
 // (kMultiMinRows rows); the default tiles are 256 VX columns x 32 rows,
-// marched 4 rows at a time.  Each problem holds five U buffers (a
-// three-step pass writes U^{n+1} .. U^{n+3} while other waves still read U^n
+// marched 4 rows at a time.  Each problem holds six U buffers (a
+// four-step pass writes U^{n+1} .. U^{n+4} while other waves still read U^n
 // and U^{n-1}).
 constexpr int kMultiMinRows = 4;
 constexpr int kMultiTileRows = 32;
 constexpr int kMultiGroup = 4;
 constexpr int kMultiPassRows = 8;
 constexpr int kMultiPassGroup = 2;
-constexpr int kMultiUbufs = 5;
+constexpr int kMultiUbufs = 6;
 
-// roles of the argument tables of one rotation state: a single step; the
-// core and two frame steps of a two-step pass; the core and three frame
-// steps of a three-step pass
-enum { kRoleStep = 0, kRoleCore2 = 1, kRoleCore3 = 4, kRoles = 8 };
+// roles of the argument tables of one rotation state: a single step; then
+// for passes of 2, 3 and 4 levels the core and the pass's frame steps
+enum { kRoleStep = 0, kRoleCore2 = 1, kRoleCore3 = 4, kRoleCore4 = 8, kRoles = 13 };
 
-int role_base(int levels) { return levels == 1 ? kRoleStep : (levels == 2 ? kRoleCore2 : kRoleCore3); }
+int role_base(int levels)
+{
+    return levels == 1 ? kRoleStep : levels == 2 ? kRoleCore2 : levels == 3 ? kRoleCore3 : kRoleCore4;
+}
 
 int state_key(int now, int old, int cur) { return (now * kMultiUbufs + old) * 2 + cur; }
 
@@ -1883,11 +1894,11 @@ dpml problem_view(const dpml_multi *H, int64_t p, int now, int old, int cur)
     return v;
 }
 
-// The three spare U buffers of a rotation state, in ascending order.
-void spares(int now, int old, int s[3])
+// The four spare U buffers of a rotation state, in ascending order.
+void spares(int now, int old, int s[4])
 {
     int k = 0;
-    for (int i = 0; i < kMultiUbufs && k < 3; ++i)
+    for (int i = 0; i < kMultiUbufs && k < 4; ++i)
         if (i != now && i != old) s[k++] = i;
 }
 
@@ -1953,7 +1964,7 @@ int upload_table(dpml_multi *H, int slot, const void *data, size_t bytes)
 }
 
 // Argument tables of rotation state (now, old, cur) for a pass of `levels`
-// levels (1: one step in place; 2, 3: the core descriptors and the frame's
+// levels (1: one step in place; 2 .. 4: the core descriptors and the frame's
 // steps, frame step j over everything outside the core shrunk by levels - j).
 // Built once per state and depth (outside any capture) and kept.
 template <typename T>
@@ -1980,7 +1991,7 @@ int ensure_state(dpml_multi *H, int now, int old, int cur, int levels)
     }
     std::vector<dpmlk::MultiCore<T>> core(c);
     std::vector<std::vector<dpmlk::StepArgs<T>>> fr((size_t)levels, std::vector<dpmlk::StepArgs<T>>(c));
-    int sp[3];
+    int sp[4];
     spares(now, old, sp);
     // levels: U^n = now, U^{n-1} = old, U^{n+j} = spare j-1
     auto level_buf = [&](int j) { return j == 0 ? now : (j == -1 ? old : sp[j - 1]); };
@@ -1993,7 +2004,8 @@ int ensure_state(dpml_multi *H, int now, int old, int cur, int levels)
         core[p].p.tile_rows = H->pass_rows;
         for (int k = 0; k < 4; ++k) core[p].p.skip[k] = r[k];
         core[p].next2 = (T *)v.at(v.L.off_u[sp[1]]);
-        core[p].next3 = levels == 3 ? (T *)v.at(v.L.off_u[sp[2]]) : nullptr;
+        core[p].next3 = levels >= 3 ? (T *)v.at(v.L.off_u[sp[2]]) : nullptr;
+        core[p].next4 = levels == 4 ? (T *)v.at(v.L.off_u[sp[3]]) : nullptr;
         for (int j = 1; j <= levels; ++j) {
             const int sh = levels - j;
             dpml w = problem_view(H, p, level_buf(j - 1), level_buf(j - 2), (j % 2 == 0) ? 1 - cur : cur);
@@ -2034,7 +2046,7 @@ int ensure_pass_lists(dpml_multi *H, int levels)
     const int q = levels - 2;
     if (H->n_core_waves[q] >= 0) return DPML_OK;
     std::vector<dpmlk::TileRef> waves;
-    std::vector<dpmlk::Span2> fr[3];
+    std::vector<dpmlk::Span2> fr[4];
     for (int64_t p = 0; p < H->count; ++p) {
         const Layout &L = H->L[p];
         int r[4];
@@ -2071,9 +2083,9 @@ int ensure_pass_lists(dpml_multi *H, int levels)
 // Drop the work lists (after a change of pass_rows).
 void drop_pass_lists(dpml_multi *H)
 {
-    for (int q = 0; q < 2; ++q) {
+    for (int q = 0; q < 3; ++q) {
         if (H->d_core_waves[q]) { (void)hipFree(H->d_core_waves[q]); H->d_core_waves[q] = nullptr; }
-        for (int j = 0; j < 3; ++j)
+        for (int j = 0; j < 4; ++j)
             if (H->d_frame[q][j]) { (void)hipFree(H->d_frame[q][j]); H->d_frame[q][j] = nullptr; }
         H->n_core_waves[q] = -1;
     }
@@ -2120,7 +2132,8 @@ int multi_launch_pass(dpml_multi *H, hipStream_t s, int key, int levels)
     if (H->pass_group == 4) hipLaunchKernelGGL((dpmlk::KER<T, VX, 4>), grid, block, 0, s, cores, wl, nw); \
     else if (H->pass_group == 1) hipLaunchKernelGGL((dpmlk::KER<T, VX, 1>), grid, block, 0, s, cores, wl, nw); \
     else hipLaunchKernelGGL((dpmlk::KER<T, VX, 2>), grid, block, 0, s, cores, wl, nw);
-    if (levels == 3) { DPML_MULTI_PASS(k_multi_step3_march) }
+    if (levels == 4) { DPML_MULTI_PASS(k_multi_step4_march) }
+    else if (levels == 3) { DPML_MULTI_PASS(k_multi_step3_march) }
     else { DPML_MULTI_PASS(k_multi_step2_march) }
 #undef DPML_MULTI_PASS
     for (int j = 1; j <= levels; ++j) {
@@ -2136,9 +2149,9 @@ int multi_launch_pass(dpml_multi *H, hipStream_t s, int key, int levels)
     return DPML_OK;
 }
 
-// nsteps steps from the handle's rotation state: passes of three (variant
-// THREESTEP) or two (TWOSTEP, or a last pair) levels while that many steps
-// remain and every problem has a core for them, then single steps.  kPrepare only
+// nsteps steps from the handle's rotation state: passes of four (variant
+// FOURSTEP), three (THREESTEP) or two (TWOSTEP) levels, shorter ones for the
+// last steps, while every problem has a core for them, then single steps.  kPrepare only
 // builds the tables the run needs (before a capture); kLaunch enqueues the
 // run on stream s and advances the rotation state; kAdvance only advances
 // it (after a graph replay).
@@ -2147,7 +2160,9 @@ enum { kPrepare = 0, kLaunch = 1, kAdvance = 2 };
 template <typename T>
 int multi_run(dpml_multi *H, hipStream_t s, int64_t nsteps, int mode)
 {
-    const int want = H->variant == DPML_VARIANT_THREESTEP ? 3 : (H->variant == DPML_VARIANT_TWOSTEP ? 2 : 1);
+    const int want = H->variant == DPML_VARIANT_FOURSTEP ? 4
+                     : H->variant == DPML_VARIANT_THREESTEP ? 3
+                     : H->variant == DPML_VARIANT_TWOSTEP ? 2 : 1;
     int now = H->now, old = H->old, cur = H->cur;
     int64_t k = 0;
     while (k < nsteps) {
@@ -2165,7 +2180,7 @@ int multi_run(dpml_multi *H, hipStream_t s, int64_t nsteps, int mode)
         if (lv == 1) {
             std::swap(now, old);
         } else {
-            int sp[3];
+            int sp[4];
             spares(now, old, sp);
             now = sp[lv - 1];
             old = sp[lv - 2];
@@ -2340,8 +2355,9 @@ int dpml_multi_set_variant(dpml_multi_t *H, int32_t variant, int32_t tile_rows, 
 {
     if (!H) return DPML_EINVAL;
     if (variant == DPML_VARIANT_AUTO) variant = DPML_VARIANT_MARCH;
-    if (variant != DPML_VARIANT_MARCH && variant != DPML_VARIANT_TWOSTEP && variant != DPML_VARIANT_THREESTEP)
-        return H->fail(DPML_EINVAL, "variant must be DPML_VARIANT_MARCH, TWOSTEP or THREESTEP");
+    if (variant != DPML_VARIANT_MARCH && variant != DPML_VARIANT_TWOSTEP && variant != DPML_VARIANT_THREESTEP &&
+        variant != DPML_VARIANT_FOURSTEP)
+        return H->fail(DPML_EINVAL, "variant must be DPML_VARIANT_MARCH, TWOSTEP, THREESTEP or FOURSTEP");
     const bool pass = variant != DPML_VARIANT_MARCH;
     if (tile_rows == 0) tile_rows = pass ? kMultiPassRows : kMultiTileRows;
     if (group == 0) group = pass ? kMultiPassGroup : kMultiGroup;
@@ -2558,11 +2574,11 @@ int step_graph_impl(dpml *H, int64_t nsteps)
         view.stream = H->cap;
         view.err.clear();
         view.timing = false;
-        for (int lv = 2; lv <= 3; ++lv) {      // frame tables, side stream, events before capture
-            if (multistep_levels(H, nsteps) < 2) break;
+        const int top = multistep_levels(H, nsteps);   // passes take at most this many levels
+        for (int lv = 2; lv <= top; ++lv) {    // frame tables, side stream, events before capture
             int rcf = ensure_multistep(H, lv);
             if (rcf) return rcf;
-            for (int sh = 0; sh < 3; ++sh) {
+            for (int sh = 0; sh < 4; ++sh) {
                 view.d_frame[lv - 2][sh] = H->d_frame[lv - 2][sh];
                 view.n_frame[lv - 2][sh] = H->n_frame[lv - 2][sh];
                 view.d_fspan[lv - 2][sh] = H->d_fspan[lv - 2][sh];
@@ -2583,8 +2599,8 @@ int step_graph_impl(dpml *H, int64_t nsteps)
         hipError_t e = hipStreamEndCapture(H->cap, &g);
         view.cap = nullptr; view.graph = nullptr; view.exec = nullptr;   // not owned by the view
         view.d_src_cells = view.d_src_order = view.d_rec_cells = view.d_rec_sorted = view.d_rec_order = nullptr;
-        for (int lv = 0; lv < 2; ++lv)
-            for (int sh = 0; sh < 3; ++sh) {
+        for (int lv = 0; lv < 3; ++lv)
+            for (int sh = 0; sh < 4; ++sh) {
                 view.d_frame[lv][sh] = nullptr;
                 view.d_fspan[lv][sh] = nullptr;
             }

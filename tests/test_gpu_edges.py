@@ -15,7 +15,8 @@ dp = pytest.importorskip("paper_1804_01390_amd")
 
 pytestmark = pytest.mark.gpu
 
-VARIANTS = [dp.VARIANT_CELL, dp.VARIANT_MARCH, dp.VARIANT_MARCH1, dp.VARIANT_TWOSTEP, dp.VARIANT_THREESTEP]
+VARIANTS = [dp.VARIANT_CELL, dp.VARIANT_MARCH, dp.VARIANT_MARCH1, dp.VARIANT_TWOSTEP, dp.VARIANT_THREESTEP,
+            dp.VARIANT_FOURSTEP]
 
 
 def _fields(sim, ndim):
@@ -80,7 +81,7 @@ def test_small_grids_and_thin_layers(dtype, ndim, n, lo, hi):
     assert max(errs.values()) <= tol, errs
 
 
-@pytest.mark.parametrize("variant", [dp.VARIANT_TWOSTEP, dp.VARIANT_THREESTEP])
+@pytest.mark.parametrize("variant", [dp.VARIANT_TWOSTEP, dp.VARIANT_THREESTEP, dp.VARIANT_FOURSTEP])
 def test_problem_set_with_a_problem_too_small_for_passes(variant):
     """One problem too small for a multi-step core makes the whole set take
     single steps (or two-step passes); the result does not change."""

@@ -105,7 +105,9 @@ def test_multi_launch_shapes_bit_identical(dtype, sides):
                                  (dp.VARIANT_MARCH, 64, 1), (dp.VARIANT_MARCH, 333, 4), (0, 0, 0),
                                  (dp.VARIANT_TWOSTEP, 0, 0), (dp.VARIANT_TWOSTEP, 1, 1), (dp.VARIANT_TWOSTEP, 7, 4),
                                  (dp.VARIANT_TWOSTEP, 64, 2), (dp.VARIANT_THREESTEP, 0, 0),
-                                 (dp.VARIANT_THREESTEP, 1, 1), (dp.VARIANT_THREESTEP, 5, 4)]:
+                                 (dp.VARIANT_THREESTEP, 1, 1), (dp.VARIANT_THREESTEP, 5, 4),
+                                 (dp.VARIANT_FOURSTEP, 0, 0), (dp.VARIANT_FOURSTEP, 1, 1),
+                                 (dp.VARIANT_FOURSTEP, 6, 4)]:
         sim = dp.MultiSimulation(probs, dtype=dtype)
         sim.set_state([w.U0 for w in probs])
         sim.step(10, graph=True)
@@ -146,11 +148,11 @@ def test_multi_tuner_picks_a_candidate_and_keeps_the_state(tmp_path):
     sim.close()
 
 
-@pytest.mark.parametrize("variant", [dp.VARIANT_TWOSTEP, dp.VARIANT_THREESTEP])
+@pytest.mark.parametrize("variant", [dp.VARIANT_TWOSTEP, dp.VARIANT_THREESTEP, dp.VARIANT_FOURSTEP])
 @pytest.mark.parametrize("dtype,sides", [(torch.float64, [64, 130, 257, 96, 300]),
                                          (torch.float32, [64, 131, 256, 97, 300])])
 def test_multi_twostep_matches_oracle_and_graph(dtype, sides, variant):
-    """Two- and three-step passes over all problems (cores in one launch,
+    """Two-, three- and four-step passes over all problems (cores in one launch,
     frames on a second stream) against the oracle per problem, eagerly and as
     graph replays with step counts of every remainder in between."""
     ms = [8, 13, 16, 9, 20]

@@ -301,17 +301,17 @@ def test_graph_replay_matches_eager(dtype):
 
 
 
-@pytest.mark.parametrize("multi", ["two", "three"])
+@pytest.mark.parametrize("multi", ["two", "three", "four"])
 @pytest.mark.parametrize("rows", [0, 5])
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
 @pytest.mark.parametrize("case", ["bump", "ragged", "onesided", "c2", "batch", "nolayer"])
 def test_twostep_matches_single_steps_and_oracle(dtype, case, rows, multi):
-    """Two (three) steps per pass over the layer-free core (temporal blocking)
-    plus single steps on the frame: bit-identical to single steps, and the
-    oracle agrees; step counts that are not a multiple end with a two-step
-    pass and/or a single step.  rows = 5 makes the kernel's tiles end in a
+    """Two (three, four) steps per pass over the layer-free core (temporal
+    blocking) plus single steps on the frame: bit-identical to single steps,
+    and the oracle agrees; step counts that are not a multiple end with a
+    shorter pass and/or a single step.  rows = 5 makes the kernel's tiles end in a
     remainder of rows."""
-    MULTI = dp.VARIANT_TWOSTEP if multi == "two" else dp.VARIANT_THREESTEP
+    MULTI = {"two": dp.VARIANT_TWOSTEP, "three": dp.VARIANT_THREESTEP, "four": dp.VARIANT_FOURSTEP}[multi]
     rng = np.random.default_rng(17)
     c2 = None
     batch = 1
@@ -368,11 +368,11 @@ def test_twostep_matches_single_steps_and_oracle(dtype, case, rows, multi):
 
 
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
-@pytest.mark.parametrize("variant", [dp.VARIANT_TWOSTEP, dp.VARIANT_THREESTEP])
+@pytest.mark.parametrize("variant", [dp.VARIANT_TWOSTEP, dp.VARIANT_THREESTEP, dp.VARIANT_FOURSTEP])
 @pytest.mark.parametrize("group,rows", [(1, 3), (4, 7), (4, 4), (2, 1), (1 << 4 | 4, 8), (3 << 4 | 2, 5),
                                         (5 << 4 | 4, 6)])
 def test_multistep_launch_shapes_bit_identical(dtype, variant, group, rows):
-    """Every load-group size and tile height of the two- and three-step
+    """Every load-group size and tile height of the two-, three- and four-step
     kernels (tiles shorter than a group, one-row tiles), and the frame's
     steps one thread per cell or as wave marches over spans of 1, 3 or 5
     rows (group's high bits), give the single-step result bit for bit, with
@@ -399,7 +399,7 @@ def test_multistep_launch_shapes_bit_identical(dtype, variant, group, rows):
 
 
 @pytest.mark.parametrize("tile_rows", [0, (3 << 16) | (4 << 12) | 8])
-@pytest.mark.parametrize("variant", [dp.VARIANT_TWOSTEP, dp.VARIANT_THREESTEP])
+@pytest.mark.parametrize("variant", [dp.VARIANT_TWOSTEP, dp.VARIANT_THREESTEP, dp.VARIANT_FOURSTEP])
 def test_twostep_graph_replay_matches_eager(variant, tile_rows):
     w = synthetic.bump2d(200, 20, 0)
     a = dp.Simulation(w.n, w.lo, w.hi, w.h, w.dt, w.sigma, dtype=torch.float32)
@@ -448,6 +448,14 @@ def test_launch_timing_counts_and_bytes(dtype):
     t = sim.get_timing()
     assert t["pair"]["launches"] == 3 and t["frame"]["launches"] == 2 * 3 + 2 and "step" not in t
     assert t["pair"]["bytes"] + t["frame"]["bytes"] == 8 * step_bytes
+    sim.set_variant(dp.VARIANT_FOURSTEP, 0)
+    sim.step(11)                                  # two quadruples and one triple
+    t = sim.get_timing()
+    assert t["pair"]["launches"] == 3 and t["frame"]["launches"] == 2 * 4 + 3 and "step" not in t
+    assert t["pair"]["bytes"] + t["frame"]["bytes"] == 11 * step_bytes
+    sim.step(6)                                   # one quadruple and one pair
+    t = sim.get_timing()
+    assert t["pair"]["launches"] == 2 and t["frame"]["launches"] == 4 + 2 and "step" not in t
     sim.step_graph(4)
     sim.sync()
     assert sim.get_timing() == {}
@@ -463,6 +471,8 @@ def test_launch_timing_counts_and_bytes(dtype):
     (2, dp.VARIANT_THREESTEP, 0, (True, False), [0, 12], [10, 5]),
     (2, dp.VARIANT_THREESTEP, (3 << 16) | (4 << 12) | 8, (False, True), [7, 12], [10, 1]),
     (2, dp.VARIANT_THREESTEP, 0, (True, True), [7, 12], [10, 0]),       # no layer cell above: single steps
+    (2, dp.VARIANT_FOURSTEP, 0, (True, True), [7, 12], [10, 5]),
+    (2, dp.VARIANT_FOURSTEP, (2 << 16) | (2 << 12) | 6, (False, True), [7, 12], [10, 1]),
     (3, dp.VARIANT_TWOSTEP, 0, (True, False, True), [5, 3, 6], [4, 7, 5]),
     (3, dp.VARIANT_TWOSTEP, 0, (True, True, True), [0, 3, 6], [4, 7, 1]),
 ])
