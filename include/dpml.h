@@ -125,6 +125,15 @@ extern "C" {
                                   registers, U^{n+3} is stored off the core's
                                   boundary ring); remaining steps take the three-
                                   or two-step pass.  3D: as TWOSTEP               */
+#define DPML_VARIANT_DEEP 7      /* 2D: as FOURSTEP with D steps per pass, D in
+                                  bits 20-23 of tile_rows (2 .. 8; 0 = 6): the
+                                  core keeps U^{n+1} .. U^{n+D-2} in registers and
+                                  stores U^{n+D-1} off its boundary ring and
+                                  U^{n+D} on it (4 words per core cell per D
+                                  steps) over a core [lo+D, lo+n+1-D) per axis;
+                                  the frame takes D single steps beside it; the
+                                  last steps of a run take a shorter pass.  The
+                                  lower bits as for TWOSTEP.  3D: as TWOSTEP     */
 
 typedef struct dpml_grid {
     int32_t ndim;    /* 2 or 3 */
@@ -210,7 +219,7 @@ int dpml_record_plane(dpml_t *h, int32_t axis, int64_t index, void *planes,
  * tile_rows (meaning per variant above; 0 = default).  All variants
  * evaluate the scheme in the same operation order, so results do not
  * depend on the choice.  DPML_EINVAL for an unknown variant or tile_rows
- * outside [0, 2^20). */
+ * outside [0, 2^20) ([0, 2^24) for DEEP, whose depth may not be 1). */
 int dpml_set_variant(dpml_t *h, int32_t variant, int32_t tile_rows);
 
 /* Enqueue nsteps fused steps (U, Phi, Psi, sources, receivers).  Returns
@@ -369,6 +378,8 @@ int64_t dpml_multi_tiles(const dpml_multi_t *h);
  *   DPML_VARIANT_FOURSTEP: four steps per pass over cores one cell smaller
  *     again (U^{n+1} and U^{n+2} kept in registers), four frame steps, and
  *     a three- or two-step pass for the remaining steps.
+ *   DPML_VARIANT_DEEP: passes of D levels, D in bits 20-23 of tile_rows
+ *     (2 .. 8; 0 = 6), tile_rows' low 20 bits as for TWOSTEP.
  * Results do not depend on the choice.  Drops a captured graph.
  * DPML_EINVAL for another variant or a shape out of range. */
 int dpml_multi_set_variant(dpml_multi_t *h, int32_t variant, int32_t tile_rows, int32_t group);

@@ -26,7 +26,7 @@ LIB_PATH = os.path.join(_HERE, "libdpml.so")
 DPML_OK, DPML_EINVAL, DPML_ENOMEM, DPML_EHIP, DPML_ESTATE, DPML_ENONFINITE = 0, -1, -2, -3, -4, -5
 DPML_F32, DPML_F64 = 0, 1
 (VARIANT_AUTO, VARIANT_CELL, VARIANT_MARCH, VARIANT_MARCH1, VARIANT_TWOSTEP, VARIANT_THREESTEP,
- VARIANT_FOURSTEP) = 0, 1, 2, 3, 4, 5, 6
+ VARIANT_FOURSTEP, VARIANT_DEEP) = 0, 1, 2, 3, 4, 5, 6, 7
 FIELD_U, FIELD_UPREV = 0, 1
 
 
@@ -475,7 +475,8 @@ class MultiSimulation:
 
     def set_variant(self, variant: int = 0, tile_rows: int = 0, group: int = 0):
         """Stepping scheme (VARIANT_MARCH single steps, VARIANT_TWOSTEP,
-        THREESTEP or FOURSTEP multi-step passes) and its tile height and
+        THREESTEP, FOURSTEP or DEEP multi-step passes; DEEP takes its depth
+        in bits 20-23 of tile_rows) and its tile height and
         row-load group (0: defaults); results do not depend on them."""
         self._check(self.lib.dpml_multi_set_variant(self.handle, int(variant), int(tile_rows), int(group)))
         self.tiles = int(self.lib.dpml_multi_tiles(self.handle))

@@ -2,12 +2,12 @@
 
 For a given grid (dimension, extents, dtype, batch, walls) it times the
 candidate (variant, tile_rows) pairs -- one thread per cell, the marching
-single-step kernels with several tile heights, and the two-, three- and
-four-step passes with several wave heights, load groups and frame forms -- on the GPU
+single-step kernels with several tile heights, and the multi-step passes of
+2 to 8 levels with several wave heights, load groups and frame forms -- on the GPU
 with HIP events, keeps the fastest, and caches the choice in a JSON file
 keyed by the grid so later runs reuse it without timing.  ``tune_multi`` does
-the same for a set of problems (single steps, two-, three- or four-step
-passes).
+the same for a set of problems (single steps, or multi-step passes of 2 to 8
+levels).
 Every candidate computes the same result (the kernels evaluate the scheme in
 the same operation order), so tuning never changes numerics.
 """
@@ -17,13 +17,17 @@ import json
 import os
 from typing import Dict, List, Optional, Sequence, Tuple
 
-from . import VARIANT_CELL, VARIANT_FOURSTEP, VARIANT_MARCH, VARIANT_MARCH1, VARIANT_THREESTEP, VARIANT_TWOSTEP
+from . import (VARIANT_CELL, VARIANT_DEEP, VARIANT_FOURSTEP, VARIANT_MARCH, VARIANT_MARCH1, VARIANT_THREESTEP,
+               VARIANT_TWOSTEP)
 
 DEFAULT_CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "autotune_cache.json")
 
 # multi-step variants: rows per wave in the low 12 bits, load group size above
-# (frame span rows above bit 16: the frame's steps as wave marches)
-CANDIDATES_2D: List[Tuple[int, int]] = ([(VARIANT_FOURSTEP, (g << 12) | r) for g in (2, 4) for r in (4, 6, 8, 12, 16)]
+# (frame span rows above bit 16: the frame's steps as wave marches; DEEP:
+# levels per pass above bit 20)
+CANDIDATES_2D: List[Tuple[int, int]] = ([(VARIANT_DEEP, (d << 20) | (g << 12) | r) for d in (6, 7, 8) for g in (2, 4)
+                                         for r in (12, 16, 24, 32, 48)]
+                                        + [(VARIANT_FOURSTEP, (g << 12) | r) for g in (2, 4) for r in (4, 6, 8, 12, 16)]
                                         + [(VARIANT_THREESTEP, (g << 12) | r) for g in (2, 4) for r in (4, 6, 8, 12, 16)]
                                         + [(VARIANT_THREESTEP, (f << 16) | (4 << 12) | r) for f in (2, 3, 4)
                                            for r in (6, 8)]
@@ -104,7 +108,9 @@ def tune(sim, steps: int = 50, candidates: Optional[Sequence[Tuple[int, int]]] =
 # many-problem path: (variant, tile rows, rows loaded together)
 CANDIDATES_MULTI: List[Tuple[int, int, int]] = ([(VARIANT_MARCH, r, g) for r in (8, 16, 32, 64) for g in (1, 2, 4)]
                                               + [(v, r, g) for v in (VARIANT_TWOSTEP, VARIANT_THREESTEP, VARIANT_FOURSTEP)
-                                                 for r in (4, 8, 16) for g in (2, 4)])
+                                                 for r in (4, 8, 16) for g in (2, 4)]
+                                              + [(VARIANT_DEEP, (d << 20) | r, g) for d in (5, 6, 8) for r in (8, 16, 32)
+                                                 for g in (2, 4)])
 
 
 def multi_key(multi) -> str:

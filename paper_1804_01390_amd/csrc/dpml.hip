@@ -12,6 +12,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -42,7 +43,7 @@ struct Layout {
     int64_t aux_elems[3] = {0, 0, 0};   // elements of one compact aux array (one problem)
     // byte offsets into the workspace
     int n_ubuf = 2;                     // U buffers: U^n, U^{n-1} (+ spares of the multi-step variants)
-    size_t off_u[6] = {0, 0, 0, 0, 0, 0};
+    size_t off_u[10] = {};
     size_t off_c2 = 0;
     size_t off_phi[3][2] = {{0, 0}, {0, 0}, {0, 0}};
     size_t off_psi[3][2] = {{0, 0}, {0, 0}, {0, 0}};
@@ -53,10 +54,37 @@ struct Layout {
 
 constexpr int kFlagBlocks = 1024;
 
-// U buffers of a single-grid handle: 2D grids carry four spares for the
-// multi-step variants (which write U^{n+1} .. U^{n+4} beside U^n and
-// U^{n-1}); 3D grids two (U^{n+1}, U^{n+2} of the two-step pass).
-int handle_ubufs(const dpml_grid_t *g) { return g && g->ndim == 2 ? 6 : 4; }
+// Deepest multi-step pass (levels per pass) of the 2D variants.
+constexpr int kMaxLevels = 8;
+
+// Levels per pass a variant asks for: TWOSTEP 2, THREESTEP 3, FOURSTEP 4,
+// DEEP bits 20-23 of tile_rows (0: 6); 1 for the single-step variants.
+int pass_depth(int variant, int tile_rows)
+{
+    switch (variant) {
+    case DPML_VARIANT_TWOSTEP: return 2;
+    case DPML_VARIANT_THREESTEP: return 3;
+    case DPML_VARIANT_FOURSTEP: return 4;
+    case DPML_VARIANT_DEEP: return ((tile_rows >> 20) & 0xF) ? ((tile_rows >> 20) & 0xF) : 6;
+    default: return 1;
+    }
+}
+
+template <typename V, int A, int B>
+using Table2 = std::array<std::array<V, B>, A>;
+
+template <typename V, int A, int B>
+Table2<V, A, B> filled(V v)
+{
+    Table2<V, A, B> t;
+    for (auto &r : t) r.fill(v);
+    return t;
+}
+
+// U buffers of a single-grid handle: 2D grids carry kMaxLevels spares for
+// the multi-step variants (which write U^{n+1} .. U^{n+levels} beside U^n
+// and U^{n-1}); 3D grids two (U^{n+1}, U^{n+2} of the two-step pass).
+int handle_ubufs(const dpml_grid_t *g) { return g && g->ndim == 2 ? 2 + kMaxLevels : 4; }
 
 // Validate the grid and compute the workspace layout.  Returns "" or an error.
 std::string make_layout(const dpml_grid_t *g, bool c2_field, Layout &L, int n_ubuf)
@@ -125,11 +153,11 @@ struct dpml {
     int tile_rows = 0;
     // frame tiles of the multi-step variants: [levels - 2][s] covers
     // everything outside the core shrunk by s cells (-1: not built yet)
-    dpmlk::TileRef *d_frame[3][4] = {};
-    int64_t n_frame[3][4] = {{-1, -1, -1, -1}, {-1, -1, -1, -1}, {-1, -1, -1, -1}};
+    dpmlk::TileRef *d_frame[kMaxLevels - 1][kMaxLevels] = {};
+    Table2<int64_t, kMaxLevels - 1, kMaxLevels> n_frame = filled<int64_t, kMaxLevels - 1, kMaxLevels>(-1);
     // the same frames as spans for the marching frame kernel (span rows fspan_rows)
-    dpmlk::Span2 *d_fspan[3][4] = {};
-    int64_t n_fspan[3][4] = {{-1, -1, -1, -1}, {-1, -1, -1, -1}, {-1, -1, -1, -1}};
+    dpmlk::Span2 *d_fspan[kMaxLevels - 1][kMaxLevels] = {};
+    Table2<int64_t, kMaxLevels - 1, kMaxLevels> n_fspan = filled<int64_t, kMaxLevels - 1, kMaxLevels>(-1);
     int fspan_rows = 0;
     // the frame's steps run on a second stream beside the core kernel
     hipStream_t side = nullptr;
@@ -478,8 +506,7 @@ int launch_step(dpml *H, T *hist = nullptr, T *uout = nullptr)
     p.hist = hist;
     p.uout = uout;
     const unsigned B = (unsigned)L.batch;
-    const bool multi = H->variant == DPML_VARIANT_TWOSTEP || H->variant == DPML_VARIANT_THREESTEP ||
-                       H->variant == DPML_VARIANT_FOURSTEP;
+    const bool multi = pass_depth(H->variant, H->tile_rows) >= 2;
     int variant = (H->variant == DPML_VARIANT_AUTO || multi) ? DPML_VARIANT_CELL : H->variant;
     // 3D single steps of the multi-step variants march like MARCH
     if (L.ndim == 3 && multi) variant = DPML_VARIANT_MARCH;
@@ -640,9 +667,7 @@ dpmlk::Box3 core_box3d(const Layout &L, int shrink)
 int multistep_levels3d(const dpml *H, int64_t nsteps)
 {
     const Layout &L = H->L;
-    if (H->variant != DPML_VARIANT_TWOSTEP && H->variant != DPML_VARIANT_THREESTEP &&
-        H->variant != DPML_VARIANT_FOURSTEP)
-        return 1;
+    if (pass_depth(H->variant, H->tile_rows) < 2) return 1;
     if (nsteps < 2 || L.batch != 1 || H->c2_field || !walls_allow_multistep(L)) return 1;
     if (L.N[0] < 8 || L.N[1] < 8 || L.N[2] < 8 || H->ns > 32) return 1;
     const dpmlk::Box3 c = core_box3d(L, 0), in1 = core_box3d(L, 1);
@@ -655,18 +680,15 @@ int multistep_levels3d(const dpml *H, int64_t nsteps)
     return 2;
 }
 
-// Levels per pass this handle may take right now: 4 (VARIANT_FOURSTEP), 3
-// (VARIANT_THREESTEP, or FOURSTEP for a last three), 2 (VARIANT_TWOSTEP, or
-// the deeper variants for a last pair), or 1.
+// Levels per pass this handle may take right now: the variant's depth, fewer
+// for the last steps of a run or where the core of that depth is empty, or 1.
 int multistep_levels(const dpml *H, int64_t nsteps)
 {
     const Layout &L = H->L;
     if (L.ndim == 3) return multistep_levels3d(H, nsteps);
     if (!walls_allow_multistep(L)) return 1;
     if (H->ns > 0 || (H->recording && (H->nr > 0 || H->plane_axis >= 0))) return 1;
-    int want = H->variant == DPML_VARIANT_FOURSTEP ? 4
-               : H->variant == DPML_VARIANT_THREESTEP ? 3
-               : H->variant == DPML_VARIANT_TWOSTEP ? 2 : 1;
+    int want = pass_depth(H->variant, H->tile_rows);
     if (want > nsteps) want = (int)nsteps;
     // the core kernels wrap halo rows once: each extent must hold its halos
     if (L.N[0] < 8 || L.N[1] < 8) return 1;
@@ -721,8 +743,8 @@ int ensure_frame(dpml *H, int levels, int shrink)
     const int fr = frame_span_rows(H);
     if (fr > 0) {
         if (H->fspan_rows != fr) {                    // span lists of another height
-            for (int a = 0; a < 3; ++a)
-                for (int b = 0; b < 4; ++b) {
+            for (int a = 0; a < kMaxLevels - 1; ++a)
+                for (int b = 0; b < kMaxLevels; ++b) {
                     if (H->d_fspan[a][b]) HIP_TRY(H, hipFree(H->d_fspan[a][b]));
                     H->d_fspan[a][b] = nullptr;
                     H->n_fspan[a][b] = -1;
@@ -769,7 +791,26 @@ int ensure_multistep(dpml *H, int levels)
     return ensure_side(H);
 }
 
-// `levels` (2, 3 or 4) steps.  The core kernel runs on the handle's stream;
+// The core kernel of a pass of 4 .. kMaxLevels levels.
+template <typename T, int VX, int G, bool C2>
+void launch_coreN(int levels, dim3 grid, hipStream_t st, const dpmlk::StepArgs<T> &p, T *pen, T *fin,
+                  const int r[4], int strips, int n_waves)
+{
+    const dim3 block(256);
+#define DPML_CORE_N(NL)                                                                                   \
+    hipLaunchKernelGGL((dpmlk::k_stepN_march<T, VX, G, C2, NL>), grid, block, 0, st, p, pen, fin, r[0], r[1], \
+                       r[2], r[3], strips, n_waves)
+    switch (levels) {
+    case 4: DPML_CORE_N(4); break;
+    case 5: DPML_CORE_N(5); break;
+    case 6: DPML_CORE_N(6); break;
+    case 7: DPML_CORE_N(7); break;
+    default: DPML_CORE_N(8); break;
+    }
+#undef DPML_CORE_N
+}
+
+// `levels` (2 .. kMaxLevels) steps.  The core kernel runs on the handle's stream;
 // the frame takes `levels` ordinary steps on the side stream at the same
 // time, step j (1-based) over everything outside the core shrunk by
 // levels - j cells, which is where the later frame steps need level j.  The
@@ -784,7 +825,7 @@ int launch_multistep(dpml *H, int levels)
     const int q = levels - 2;
     // buffers: A = U^n, Bv = U^{n-1}, then U^{n+1} .. U^{n+levels} in the spares
     T *A = (T *)H->u_now, *Bv = (T *)H->u_old;
-    T *nxt[4] = {nullptr, nullptr, nullptr, nullptr};
+    T *nxt[kMaxLevels] = {};
     int k = 0;
     for (int i = 0; i < L.n_ubuf && k < levels; ++i) {
         void *b = H->at(L.off_u[i]);
@@ -798,7 +839,7 @@ int launch_multistep(dpml *H, int levels)
     // tile_rows: rows per wave in the low 12 bits (0: 8), loads issued G rows at a
     // time with G in the bits above (0: 2)
     const int rows = (H->tile_rows & 0xFFF) > 0 ? (H->tile_rows & 0xFFF) : 8;
-    const int G = (H->tile_rows >> 12) > 0 ? (H->tile_rows >> 12) : 2;
+    const int G = ((H->tile_rows >> 12) & 0xF) > 0 ? ((H->tile_rows >> 12) & 0xF) : 2;
     const int strips = (r[1] - r[0] + (64 - 2 * HL) * VX - 1) / ((64 - 2 * HL) * VX);
     const int n_waves = strips * ((r[3] - r[2] + rows - 1) / rows);
     const dim3 block(256);
@@ -820,8 +861,8 @@ int launch_multistep(dpml *H, int levels)
             hipLaunchKernelGGL((dpmlk::k_step3_march<T, VX, GG, C2>), grid, block, 0, H->stream, p, nxt[1],     \
                                nxt[2], r[0], r[1], r[2], r[3], strips, n_waves);                            \
         else                                                                                                \
-            hipLaunchKernelGGL((dpmlk::k_step4_march<T, VX, GG, C2>), grid, block, 0, H->stream, p, nxt[2],     \
-                               nxt[3], r[0], r[1], r[2], r[3], strips, n_waves);
+            launch_coreN<T, VX, GG, C2>(levels, grid, H->stream, p, nxt[levels - 2], nxt[levels - 1], r, strips,  \
+                                        n_waves);
         if (G == 4) {
             if (p.c2) { DPML_MULTI_LAUNCH(4, true) } else { DPML_MULTI_LAUNCH(4, false) }
         } else if (G == 1) {
@@ -1269,8 +1310,11 @@ int dpml_record_plane(dpml_t *H, int32_t axis, int64_t index, void *planes, int6
 int dpml_set_variant(dpml_t *H, int32_t variant, int32_t tile_rows)
 {
     if (!H) return DPML_EINVAL;
-    if (variant < DPML_VARIANT_AUTO || variant > DPML_VARIANT_FOURSTEP || tile_rows < 0 || tile_rows >= (1 << 20))
+    if (variant < DPML_VARIANT_AUTO || variant > DPML_VARIANT_DEEP || tile_rows < 0 ||
+        tile_rows >= (1 << (variant == DPML_VARIANT_DEEP ? 24 : 20)))
         return H->fail(DPML_EINVAL, "bad variant");
+    if (variant == DPML_VARIANT_DEEP && (pass_depth(variant, tile_rows) < 2 || pass_depth(variant, tile_rows) > kMaxLevels))
+        return H->fail(DPML_EINVAL, "DEEP passes take 2 .. 8 levels");
     H->variant = variant;
     H->tile_rows = tile_rows;
     return DPML_OK;
@@ -1432,8 +1476,8 @@ void dpml_destroy(dpml_t *H)
     if (H->d_src_cells) (void)hipFree(H->d_src_cells);
     if (H->d_src_order) (void)hipFree(H->d_src_order);
     if (H->d_rec_cells) (void)hipFree(H->d_rec_cells);
-    for (int k = 0; k < 3; ++k)
-        for (int j = 0; j < 4; ++j) {
+    for (int k = 0; k < kMaxLevels - 1; ++k)
+        for (int j = 0; j < kMaxLevels; ++j) {
             if (H->d_frame[k][j]) (void)hipFree(H->d_frame[k][j]);
             if (H->d_fspan[k][j]) (void)hipFree(H->d_fspan[k][j]);
         }
@@ -1782,7 +1826,8 @@ struct dpml_multi {
     size_t off_tiles = 0;            // single-step tile list (workspace)
     int64_t ntiles = 0;
     int vx = 1;
-    int variant = DPML_VARIANT_MARCH;  // MARCH: single steps; TWOSTEP .. FOURSTEP: multi-step passes
+    int variant = DPML_VARIANT_MARCH;  // MARCH: single steps; TWOSTEP .. DEEP: multi-step passes
+    int depth = 1;                   // levels per multi-step pass
     int tile_rows = 32;              // single steps: rows per marching tile
     int group = 4;                   // single steps: rows whose loads are issued together
     int pass_rows = 8;               // multi-step passes: rows per core wave
@@ -1794,11 +1839,11 @@ struct dpml_multi {
     // library-owned tables: step arguments per rotation state and role, and
     // the work lists of the multi-step passes ([levels - 2])
     std::vector<void *> d_args;      // [state * kRoles + role]
-    dpmlk::TileRef *d_core_waves[3] = {nullptr, nullptr, nullptr};
-    int64_t n_core_waves[3] = {-1, -1, -1};   // -1: not built for pass_rows yet
-    dpmlk::Span2 *d_frame[3][4] = {};
-    int64_t n_frame[3][4] = {};
-    int pass_ok[3] = {-1, -1, -1};   // every problem has a core for the pass (-1: not checked)
+    dpmlk::TileRef *d_core_waves[kMaxLevels - 1] = {};
+    int64_t n_core_waves[kMaxLevels - 1] = {-1, -1, -1, -1, -1, -1, -1};   // -1: not built for pass_rows yet
+    dpmlk::Span2 *d_frame[kMaxLevels - 1][kMaxLevels] = {};
+    int64_t n_frame[kMaxLevels - 1][kMaxLevels] = {};
+    int pass_ok[kMaxLevels - 1] = {-1, -1, -1, -1, -1, -1, -1};   // every problem has a core (-1: not checked)
     hipStream_t side = nullptr;
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -1823,23 +1868,27 @@ struct MultiLayout {
 
 // The single-step tile list is sized for the shortest tiles allowed
 // (kMultiMinRows rows); the default tiles are 256 VX columns x 32 rows,
-// marched 4 rows at a time.  Each problem holds six U buffers (a
-// four-step pass writes U^{n+1} .. U^{n+4} while other waves still read U^n
-// and U^{n-1}).
+// marched 4 rows at a time.  Each problem holds 2 + kMaxLevels U buffers (a
+// pass of L levels writes U^{n+1} .. U^{n+L} while other waves still read
+// U^n and U^{n-1}).
 constexpr int kMultiMinRows = 4;
 constexpr int kMultiTileRows = 32;
 constexpr int kMultiGroup = 4;
 constexpr int kMultiPassRows = 8;
 constexpr int kMultiPassGroup = 2;
-constexpr int kMultiUbufs = 6;
+constexpr int kMultiUbufs = 2 + kMaxLevels;
 
-// roles of the argument tables of one rotation state: a single step; then
-// for passes of 2, 3 and 4 levels the core and the pass's frame steps
-enum { kRoleStep = 0, kRoleCore2 = 1, kRoleCore3 = 4, kRoleCore4 = 8, kRoles = 13 };
+// roles of the argument tables of one rotation state: a single step (role
+// 0); then for passes of 2 .. kMaxLevels levels, in that order, the core
+// and the pass's frame steps (levels + 1 roles each)
+constexpr int kRoleStep = 0;
+constexpr int kRoles = 1 + (kMaxLevels + 4) * (kMaxLevels - 1) / 2;
 
 int role_base(int levels)
 {
-    return levels == 1 ? kRoleStep : levels == 2 ? kRoleCore2 : levels == 3 ? kRoleCore3 : kRoleCore4;
+    int b = 1;
+    for (int l = 2; l < levels; ++l) b += l + 1;
+    return levels == 1 ? kRoleStep : b;
 }
 
 int state_key(int now, int old, int cur) { return (now * kMultiUbufs + old) * 2 + cur; }
@@ -1894,11 +1943,11 @@ dpml problem_view(const dpml_multi *H, int64_t p, int now, int old, int cur)
     return v;
 }
 
-// The four spare U buffers of a rotation state, in ascending order.
-void spares(int now, int old, int s[4])
+// The kMaxLevels spare U buffers of a rotation state, in ascending order.
+void spares(int now, int old, int s[kMaxLevels])
 {
     int k = 0;
-    for (int i = 0; i < kMultiUbufs && k < 4; ++i)
+    for (int i = 0; i < kMultiUbufs && k < kMaxLevels; ++i)
         if (i != now && i != old) s[k++] = i;
 }
 
@@ -1991,7 +2040,7 @@ int ensure_state(dpml_multi *H, int now, int old, int cur, int levels)
     }
     std::vector<dpmlk::MultiCore<T>> core(c);
     std::vector<std::vector<dpmlk::StepArgs<T>>> fr((size_t)levels, std::vector<dpmlk::StepArgs<T>>(c));
-    int sp[4];
+    int sp[kMaxLevels];
     spares(now, old, sp);
     // levels: U^n = now, U^{n-1} = old, U^{n+j} = spare j-1
     auto level_buf = [&](int j) { return j == 0 ? now : (j == -1 ? old : sp[j - 1]); };
@@ -2004,8 +2053,9 @@ int ensure_state(dpml_multi *H, int now, int old, int cur, int levels)
         core[p].p.tile_rows = H->pass_rows;
         for (int k = 0; k < 4; ++k) core[p].p.skip[k] = r[k];
         core[p].next2 = (T *)v.at(v.L.off_u[sp[1]]);
-        core[p].next3 = levels >= 3 ? (T *)v.at(v.L.off_u[sp[2]]) : nullptr;
-        core[p].next4 = levels == 4 ? (T *)v.at(v.L.off_u[sp[3]]) : nullptr;
+        core[p].next3 = levels == 3 ? (T *)v.at(v.L.off_u[sp[2]]) : nullptr;
+        core[p].pen = (T *)v.at(v.L.off_u[sp[levels - 2]]);
+        core[p].fin = (T *)v.at(v.L.off_u[sp[levels - 1]]);
         for (int j = 1; j <= levels; ++j) {
             const int sh = levels - j;
             dpml w = problem_view(H, p, level_buf(j - 1), level_buf(j - 2), (j % 2 == 0) ? 1 - cur : cur);
@@ -2046,7 +2096,7 @@ int ensure_pass_lists(dpml_multi *H, int levels)
     const int q = levels - 2;
     if (H->n_core_waves[q] >= 0) return DPML_OK;
     std::vector<dpmlk::TileRef> waves;
-    std::vector<dpmlk::Span2> fr[4];
+    std::vector<dpmlk::Span2> fr[kMaxLevels];
     for (int64_t p = 0; p < H->count; ++p) {
         const Layout &L = H->L[p];
         int r[4];
@@ -2083,9 +2133,9 @@ int ensure_pass_lists(dpml_multi *H, int levels)
 // Drop the work lists (after a change of pass_rows).
 void drop_pass_lists(dpml_multi *H)
 {
-    for (int q = 0; q < 3; ++q) {
+    for (int q = 0; q < kMaxLevels - 1; ++q) {
         if (H->d_core_waves[q]) { (void)hipFree(H->d_core_waves[q]); H->d_core_waves[q] = nullptr; }
-        for (int j = 0; j < 4; ++j)
+        for (int j = 0; j < kMaxLevels; ++j)
             if (H->d_frame[q][j]) { (void)hipFree(H->d_frame[q][j]); H->d_frame[q][j] = nullptr; }
         H->n_core_waves[q] = -1;
     }
@@ -2132,10 +2182,21 @@ int multi_launch_pass(dpml_multi *H, hipStream_t s, int key, int levels)
     if (H->pass_group == 4) hipLaunchKernelGGL((dpmlk::KER<T, VX, 4>), grid, block, 0, s, cores, wl, nw); \
     else if (H->pass_group == 1) hipLaunchKernelGGL((dpmlk::KER<T, VX, 1>), grid, block, 0, s, cores, wl, nw); \
     else hipLaunchKernelGGL((dpmlk::KER<T, VX, 2>), grid, block, 0, s, cores, wl, nw);
-    if (levels == 4) { DPML_MULTI_PASS(k_multi_step4_march) }
-    else if (levels == 3) { DPML_MULTI_PASS(k_multi_step3_march) }
-    else { DPML_MULTI_PASS(k_multi_step2_march) }
+#define DPML_MULTI_PASS_N(NL)                                                                               \
+    if (H->pass_group == 4) hipLaunchKernelGGL((dpmlk::k_multi_stepN_march<T, VX, 4, NL>), grid, block, 0, s, cores, wl, nw); \
+    else if (H->pass_group == 1) hipLaunchKernelGGL((dpmlk::k_multi_stepN_march<T, VX, 1, NL>), grid, block, 0, s, cores, wl, nw); \
+    else hipLaunchKernelGGL((dpmlk::k_multi_stepN_march<T, VX, 2, NL>), grid, block, 0, s, cores, wl, nw);
+    switch (levels) {
+    case 2: { DPML_MULTI_PASS(k_multi_step2_march) } break;
+    case 3: { DPML_MULTI_PASS(k_multi_step3_march) } break;
+    case 4: { DPML_MULTI_PASS_N(4) } break;
+    case 5: { DPML_MULTI_PASS_N(5) } break;
+    case 6: { DPML_MULTI_PASS_N(6) } break;
+    case 7: { DPML_MULTI_PASS_N(7) } break;
+    default: { DPML_MULTI_PASS_N(8) } break;
+    }
 #undef DPML_MULTI_PASS
+#undef DPML_MULTI_PASS_N
     for (int j = 1; j <= levels; ++j) {
         const int nf = (int)H->n_frame[q][j - 1];
         const auto *fa = (const dpmlk::StepArgs<T> *)H->d_args[(size_t)key * kRoles + rb + j];
@@ -2149,9 +2210,9 @@ int multi_launch_pass(dpml_multi *H, hipStream_t s, int key, int levels)
     return DPML_OK;
 }
 
-// nsteps steps from the handle's rotation state: passes of four (variant
-// FOURSTEP), three (THREESTEP) or two (TWOSTEP) levels, shorter ones for the
-// last steps, while every problem has a core for them, then single steps.  kPrepare only
+// nsteps steps from the handle's rotation state: passes of the variant's
+// depth (2 .. kMaxLevels levels), shorter ones for the last steps or where
+// a problem has no core that deep, and single steps where none has.  kPrepare only
 // builds the tables the run needs (before a capture); kLaunch enqueues the
 // run on stream s and advances the rotation state; kAdvance only advances
 // it (after a graph replay).
@@ -2160,9 +2221,7 @@ enum { kPrepare = 0, kLaunch = 1, kAdvance = 2 };
 template <typename T>
 int multi_run(dpml_multi *H, hipStream_t s, int64_t nsteps, int mode)
 {
-    const int want = H->variant == DPML_VARIANT_FOURSTEP ? 4
-                     : H->variant == DPML_VARIANT_THREESTEP ? 3
-                     : H->variant == DPML_VARIANT_TWOSTEP ? 2 : 1;
+    const int want = H->variant == DPML_VARIANT_MARCH ? 1 : H->depth;
     int now = H->now, old = H->old, cur = H->cur;
     int64_t k = 0;
     while (k < nsteps) {
@@ -2180,7 +2239,7 @@ int multi_run(dpml_multi *H, hipStream_t s, int64_t nsteps, int mode)
         if (lv == 1) {
             std::swap(now, old);
         } else {
-            int sp[4];
+            int sp[kMaxLevels];
             spares(now, old, sp);
             now = sp[lv - 1];
             old = sp[lv - 2];
@@ -2356,9 +2415,15 @@ int dpml_multi_set_variant(dpml_multi_t *H, int32_t variant, int32_t tile_rows, 
     if (!H) return DPML_EINVAL;
     if (variant == DPML_VARIANT_AUTO) variant = DPML_VARIANT_MARCH;
     if (variant != DPML_VARIANT_MARCH && variant != DPML_VARIANT_TWOSTEP && variant != DPML_VARIANT_THREESTEP &&
-        variant != DPML_VARIANT_FOURSTEP)
-        return H->fail(DPML_EINVAL, "variant must be DPML_VARIANT_MARCH, TWOSTEP, THREESTEP or FOURSTEP");
+        variant != DPML_VARIANT_FOURSTEP && variant != DPML_VARIANT_DEEP)
+        return H->fail(DPML_EINVAL, "variant must be DPML_VARIANT_MARCH, TWOSTEP, THREESTEP, FOURSTEP or DEEP");
     const bool pass = variant != DPML_VARIANT_MARCH;
+    const int depth = pass_depth(variant, tile_rows);
+    if (variant == DPML_VARIANT_DEEP) {
+        if (tile_rows < 0 || tile_rows >= (1 << 24) || depth < 2 || depth > kMaxLevels)
+            return H->fail(DPML_EINVAL, "DEEP passes take 2 .. 8 levels (tile_rows bits 20-23)");
+        tile_rows &= 0xFFFFF;
+    }
     if (tile_rows == 0) tile_rows = pass ? kMultiPassRows : kMultiTileRows;
     if (group == 0) group = pass ? kMultiPassGroup : kMultiGroup;
     if (tile_rows < (pass ? 1 : kMultiMinRows) || tile_rows > 4096 || (group != 1 && group != 2 && group != 4))
@@ -2369,6 +2434,7 @@ int dpml_multi_set_variant(dpml_multi_t *H, int32_t variant, int32_t tile_rows, 
     if (H->graph) { (void)hipGraphDestroy(H->graph); H->graph = nullptr; }
     H->graph_steps = -1;
     H->variant = variant;
+    H->depth = depth;
     if (pass) {
         if (tile_rows != H->pass_rows) drop_pass_lists(H);
         H->pass_rows = tile_rows;
@@ -2578,7 +2644,7 @@ int step_graph_impl(dpml *H, int64_t nsteps)
         for (int lv = 2; lv <= top; ++lv) {    // frame tables, side stream, events before capture
             int rcf = ensure_multistep(H, lv);
             if (rcf) return rcf;
-            for (int sh = 0; sh < 4; ++sh) {
+            for (int sh = 0; sh < kMaxLevels; ++sh) {
                 view.d_frame[lv - 2][sh] = H->d_frame[lv - 2][sh];
                 view.n_frame[lv - 2][sh] = H->n_frame[lv - 2][sh];
                 view.d_fspan[lv - 2][sh] = H->d_fspan[lv - 2][sh];
@@ -2599,8 +2665,8 @@ int step_graph_impl(dpml *H, int64_t nsteps)
         hipError_t e = hipStreamEndCapture(H->cap, &g);
         view.cap = nullptr; view.graph = nullptr; view.exec = nullptr;   // not owned by the view
         view.d_src_cells = view.d_src_order = view.d_rec_cells = view.d_rec_sorted = view.d_rec_order = nullptr;
-        for (int lv = 0; lv < 3; ++lv)
-            for (int sh = 0; sh < 4; ++sh) {
+        for (int lv = 0; lv < kMaxLevels - 1; ++lv)
+            for (int sh = 0; sh < kMaxLevels; ++sh) {
                 view.d_frame[lv][sh] = nullptr;
                 view.d_fspan[lv][sh] = nullptr;
             }

@@ -823,8 +823,8 @@ template <typename T>
 struct MultiCore {
     StepArgs<T> p;
     T *next2;
-    T *next3;         // U^{n+3} (three- and four-step passes)
-    T *next4;         // U^{n+4} (four-step passes)
+    T *next3;         // U^{n+3} (three-step passes)
+    T *pen, *fin;     // U^{n+NL-1}, U^{n+NL} (passes of NL >= 4 levels)
 };
 
 template <typename T, int VX, int G>
@@ -1008,135 +1008,132 @@ __global__ void __launch_bounds__(256) k_step3_march(StepArgs<T> p, T *__restric
 }
 
 // ---------------------------------------------------------------------------
-// Four steps per launch, 2D grids: the marching scheme one level deeper
-// again.  For march index k a wave reads U^n(k+1) and U^{n-1}(k) and
-// computes U^{n+1}(k), U^{n+2}(k-1), U^{n+3}(k-2) and U^{n+4}(k-3) from rows
-// held in registers.  It writes U^{n+4} of its tile and U^{n+3} off the
-// core's boundary ring; U^{n+1} and U^{n+2} stay in registers (the frame's
-// first steps write them where the later frame steps read them): 4 words
-// per core cell per four steps.  Each side of a strip carries
-// HL = ceil(4/VX) halo lanes.
+// NL steps per launch (NL >= 4), 2D grids: the marching scheme carried to any
+// depth.  Level 0 is U^n, level l is U^{n+l}.  For march index k a wave reads
+// U^n(k+1) and U^{n-1}(k) and forms level l on row k-l+1 (l = 1 .. NL) from
+// level l-1 on rows k-l .. k-l+2 and level l-2 on row k-l+1, all held in
+// registers.  It writes level NL on its tile and level NL-1 off the core's
+// boundary ring; the levels below stay in registers (the frame's first steps
+// write them where the later frame steps read them): 4 words per core cell
+// per NL steps.  Level l is formed on rows [-(NL-l), L+NL-l) of a tile of L
+// rows, so each side of a strip carries HL = ceil(NL/VX) halo lanes and a
+// tile reads NL rows beyond each end.
 // ---------------------------------------------------------------------------
-template <typename T, int VX, bool C2F>
-struct March4Ctx : March2Ctx<T, VX, C2F> {
+template <typename T, int VX, bool C2F, int NL>
+struct MarchNCtx : March2Ctx<T, VX, C2F> {
     using R = Row<T, VX>;
-    T *o3, *o4;                    // U^{n+3}, U^{n+4}
+    T *open, *ofin;                // U^{n+NL-1}, U^{n+NL}
 
-    // rolling state at march index k: U^n at k-1, k; U^{n+1} at k-2, k-1;
-    // U^{n+2} at k-3, k-2; U^{n+3} at k-4, k-3; c^2 at k-3, k-2, k-1
+    // rolling state at march index k: w[m] = level m on rows k-m-1, k-m
+    // (m < NL); c[i] = c^2 on row k-NL+1+i (i < NL-1)
     struct State {
-        R n0, n1, a0, a1, b0, b1, d0, d1, c0, c1, c2;
+        R w[NL][2];
+        R c[NL - 1];
     };
 
-    // one march index k, every level guarded (prologue and tail): level l is
-    // formed at row k-l+1 and needed on rows [-(4-l), L+4-l)
+    // one march index k, every level guarded (prologue and tail)
     template <int DIR>
     __device__ __forceinline__ void one(State &s, int base, int k, int L) const
     {
-        const R nn = this->load(this->u, this->wrapy(base + DIR * (k + 1)));
+        R cur[NL + 1];                                  // level l formed on row k-l+1
+        cur[0] = this->load(this->u, this->wrapy(base + DIR * (k + 1)));
         const R pm = this->load(this->up, this->wrapy(base + DIR * k));
         R cn{};
         if (C2F) cn = this->load(this->c2, this->wrapy(base + DIR * k));
-        const R v1 = this->template lev<DIR>(s.n0, s.n1, nn, pm, cn);           // U^{n+1}(k)
-        R v2{}, v3{};
-        if (k - 1 >= -2) v2 = this->template lev<DIR>(s.a0, s.a1, v1, s.n0, s.c2);   // U^{n+2}(k-1)
-        if (k - 2 >= -1) {
-            v3 = this->template lev<DIR>(s.b0, s.b1, v2, s.a0, s.c1);           // U^{n+3}(k-2)
-            if (k - 2 >= 0 && k - 2 < L) this->store_inner(o3, base + DIR * (k - 2), v3);
+#pragma unroll
+        for (int l = 1; l <= NL; ++l) {
+            const int r = k - l + 1;
+            cur[l] = R{};
+            if (r < l - NL) continue;                   // below the rows level l is needed on
+            const R &old = l == 1 ? pm : s.w[l >= 2 ? l - 2 : 0][0];
+            const R &cl = l == 1 ? cn : s.c[l >= 2 ? NL - l : 0];
+            cur[l] = this->template lev<DIR>(s.w[l - 1][0], s.w[l - 1][1], cur[l - 1], old, cl);
+            if (l == NL - 1 && r >= 0 && r < L) this->store_inner(open, base + DIR * r, cur[l]);
+            if (l == NL && r >= 0 && r < L) this->store(ofin, base + DIR * r, cur[l]);
         }
-        if (k - 3 >= 0 && k - 3 < L)
-            this->store(o4, base + DIR * (k - 3), this->template lev<DIR>(s.d0, s.d1, v3, s.b0, s.c0));
-        s.n0 = s.n1;
-        s.n1 = nn;
-        s.a0 = s.a1;
-        s.a1 = v1;
-        s.b0 = s.b1;
-        s.b1 = v2;
-        s.d0 = s.d1;
-        s.d1 = v3;
-        s.c0 = s.c1;
-        s.c1 = s.c2;
-        s.c2 = cn;
+#pragma unroll
+        for (int m = 0; m < NL; ++m) {
+            s.w[m][0] = s.w[m][1];
+            s.w[m][1] = cur[m];
+        }
+#pragma unroll
+        for (int i = 0; i + 1 < NL - 1; ++i) s.c[i] = s.c[i + 1];
+        s.c[NL - 2] = cn;
     }
 
-    // G march indices k .. k+G-1 in the steady state (every level inside the
-    // tile's range), all loads of the group issued first
+    // G march indices k .. k+G-1 in the steady state (every level's row inside
+    // the tile), all loads of the group issued first
     template <int G, int DIR>
     __device__ __forceinline__ void group(State &s, int base, int k) const
     {
-        R wn[G + 2], pm[G], v1[G + 2], v2[G + 2], v3[G + 2], cw[G + 3];
-        wn[0] = s.n0;
-        wn[1] = s.n1;
-        v1[0] = s.a0;
-        v1[1] = s.a1;
-        v2[0] = s.b0;
-        v2[1] = s.b1;
-        v3[0] = s.d0;
-        v3[1] = s.d1;
-        cw[0] = s.c0;
-        cw[1] = s.c1;
-        cw[2] = s.c2;
+        R w[NL][G + 2], pm[G], cw[NL - 1 + G];         // w[m][i]: level m on row k-m-1+i
+#pragma unroll
+        for (int m = 0; m < NL; ++m) {
+            w[m][0] = s.w[m][0];
+            w[m][1] = s.w[m][1];
+        }
+#pragma unroll
+        for (int i = 0; i < NL - 1; ++i) cw[i] = s.c[i];
 #pragma unroll
         for (int g = 0; g < G; ++g) {
-            wn[2 + g] = this->load(this->u, this->wrapy(base + DIR * (k + 1 + g)));
+            w[0][2 + g] = this->load(this->u, this->wrapy(base + DIR * (k + 1 + g)));
             pm[g] = this->load(this->up, this->wrapy(base + DIR * (k + g)));
-            if (C2F) cw[3 + g] = this->load(this->c2, this->wrapy(base + DIR * (k + g)));
+            if (C2F) cw[NL - 1 + g] = this->load(this->c2, this->wrapy(base + DIR * (k + g)));
         }
 #pragma unroll
         for (int g = 0; g < G; ++g) {
-            v1[2 + g] = this->template lev<DIR>(wn[g], wn[g + 1], wn[g + 2], pm[g], cw[3 + g]);
-            v2[2 + g] = this->template lev<DIR>(v1[g], v1[g + 1], v1[g + 2], wn[g], cw[2 + g]);
-            v3[2 + g] = this->template lev<DIR>(v2[g], v2[g + 1], v2[g + 2], v1[g], cw[1 + g]);
-            this->store_inner(o3, base + DIR * (k - 2 + g), v3[2 + g]);
-            this->store(o4, base + DIR * (k - 3 + g), this->template lev<DIR>(v3[g], v3[g + 1], v3[g + 2], v2[g], cw[g]));
+#pragma unroll
+            for (int l = 1; l <= NL; ++l) {
+                const R v = this->template lev<DIR>(w[l - 1][g], w[l - 1][g + 1], w[l - 1][g + 2],
+                                                    l == 1 ? pm[g] : w[l >= 2 ? l - 2 : 0][g], cw[NL - l + g]);
+                if (l < NL) w[l][2 + g] = v;
+                if (l == NL - 1) this->store_inner(open, base + DIR * (k - l + 1 + g), v);
+                if (l == NL) this->store(ofin, base + DIR * (k - l + 1 + g), v);
+            }
         }
-        s.n0 = wn[G];
-        s.n1 = wn[G + 1];
-        s.a0 = v1[G];
-        s.a1 = v1[G + 1];
-        s.b0 = v2[G];
-        s.b1 = v2[G + 1];
-        s.d0 = v3[G];
-        s.d1 = v3[G + 1];
-        s.c0 = cw[G];
-        s.c1 = cw[G + 1];
-        s.c2 = cw[G + 2];
+#pragma unroll
+        for (int m = 0; m < NL; ++m) {
+            s.w[m][0] = w[m][G];
+            s.w[m][1] = w[m][G + 1];
+        }
+#pragma unroll
+        for (int i = 0; i < NL - 1; ++i) s.c[i] = cw[G + i];
     }
 
     template <int G, int DIR>
     __device__ __forceinline__ void march(int base, int L) const
     {
         State s;
-        s.n0 = this->load(this->u, this->wrapy(base - 4 * DIR));
-        s.n1 = this->load(this->u, this->wrapy(base - 3 * DIR));
-        s.a0 = s.a1 = s.b0 = s.b1 = s.d0 = s.d1 = s.c0 = s.c1 = s.c2 = R{};
-        // march indices -3 .. 2: the levels fill up
-        int k = -3;
-        for (; k <= 2 && k <= L + 2; ++k) one<DIR>(s, base, k, L);
+#pragma unroll
+        for (int m = 0; m < NL; ++m) s.w[m][0] = s.w[m][1] = R{};
+#pragma unroll
+        for (int i = 0; i < NL - 1; ++i) s.c[i] = R{};
+        s.w[0][0] = this->load(this->u, this->wrapy(base - NL * DIR));
+        s.w[0][1] = this->load(this->u, this->wrapy(base - (NL - 1) * DIR));
+        // march indices -(NL-1) .. NL-2: the levels fill up
+        int k = -(NL - 1);
+        for (; k <= NL - 2 && k <= L + NL - 2; ++k) one<DIR>(s, base, k, L);
         // steady state: every level's rows inside the tile (no guards needed)
         for (; k + G - 1 <= L - 1; k += G) group<G, DIR>(s, base, k);
-        for (; k <= L + 2; ++k) one<DIR>(s, base, k, L);
+        for (; k <= L + NL - 2; ++k) one<DIR>(s, base, k, L);
     }
 };
 
-template <typename T, int VX, int G, bool C2F>
-__global__ void __launch_bounds__(256) k_step4_march(StepArgs<T> p, T *__restrict__ u_next3, T *__restrict__ u_next4,
-                                                     int cx0, int cx1, int cy0, int cy1, int strips, int n_waves)
+// Set up a march context for strip `strip`, tile row `ty` of the core
+// [cx0, cx1) x [cy0, cy1) and run it.
+template <typename T, int VX, int G, bool C2F, int NL>
+__device__ __forceinline__ void run_marchN(const StepArgs<T> &p, const T *u, const T *uo, T *u_pen, T *u_fin,
+                                           int cx0, int cx1, int cy0, int cy1, int strip, int ty, int lane)
 {
-    constexpr int HL = (4 + VX - 1) / VX;                    // halo lanes per side
-    const int w = __builtin_amdgcn_readfirstlane(xcd_tile(blockIdx.x, gridDim.x) * 4 + (int)(threadIdx.x >> 6));
-    if (w >= n_waves) return;                                // whole waves; no barriers below
-    const int lane = (int)(threadIdx.x & 63);
-    const int strip = w % strips, ty = w / strips;
-    const int64_t boff = (int64_t)blockIdx.y * p.bstride;
-    March4Ctx<T, VX, C2F> c;
-    c.u = p.u + boff;
-    c.up = p.uo + boff;
+    constexpr int HL = (NL + VX - 1) / VX;                   // halo lanes per side
+    MarchNCtx<T, VX, C2F, NL> c;
+    c.u = u;
+    c.up = uo;
     c.c2 = C2F ? p.c2 : nullptr;
-    c.o1 = p.uout + boff;
+    c.o1 = nullptr;
     c.o2 = nullptr;
-    c.o3 = u_next3 + boff;
-    c.o4 = u_next4 + boff;
+    c.open = u_pen;
+    c.ofin = u_fin;
     c.inv_h2 = p.inv_h2;
     c.dt2 = p.dt2;
     c.c2c = p.c2_const;
@@ -1158,6 +1155,17 @@ __global__ void __launch_bounds__(256) k_step4_march(StepArgs<T> p, T *__restric
         c.template march<G, -1>(yb - 1, yb - ya);
     else
         c.template march<G, 1>(ya, yb - ya);
+}
+
+template <typename T, int VX, int G, bool C2F, int NL>
+__global__ void __launch_bounds__(256) k_stepN_march(StepArgs<T> p, T *__restrict__ u_pen, T *__restrict__ u_fin,
+                                                     int cx0, int cx1, int cy0, int cy1, int strips, int n_waves)
+{
+    const int w = __builtin_amdgcn_readfirstlane(xcd_tile(blockIdx.x, gridDim.x) * 4 + (int)(threadIdx.x >> 6));
+    if (w >= n_waves) return;                                // whole waves; no barriers below
+    const int64_t boff = (int64_t)blockIdx.y * p.bstride;
+    run_marchN<T, VX, G, C2F, NL>(p, p.u + boff, p.uo + boff, u_pen + boff, u_fin + boff, cx0, cx1, cy0, cy1,
+                                  w % strips, w / strips, (int)(threadIdx.x & 63));
 }
 
 template <typename T, int VX, int G>
@@ -1200,45 +1208,16 @@ __global__ void __launch_bounds__(256) k_multi_step3_march(const MultiCore<T> *_
         c.template march<G, 1>(ya, yb - ya);
 }
 
-template <typename T, int VX, int G>
-__global__ void __launch_bounds__(256) k_multi_step4_march(const MultiCore<T> *__restrict__ cores,
+template <typename T, int VX, int G, int NL>
+__global__ void __launch_bounds__(256) k_multi_stepN_march(const MultiCore<T> *__restrict__ cores,
                                                            const TileRef *__restrict__ waves, int n_waves)
 {
-    constexpr int HL = (4 + VX - 1) / VX;                    // halo lanes per side
     const int w = __builtin_amdgcn_readfirstlane(xcd_tile(blockIdx.x, gridDim.x) * 4 + (int)(threadIdx.x >> 6));
     if (w >= n_waves) return;                                // whole waves; no barriers below
-    const int lane = (int)(threadIdx.x & 63);
     const TileRef t = waves[w];
-    const StepArgs<T> &p = cores[t.prob].p;
-    March4Ctx<T, VX, false> c;
-    c.u = p.u;
-    c.up = p.uo;
-    c.c2 = nullptr;
-    c.o1 = p.uout;
-    c.o2 = cores[t.prob].next2;
-    c.o3 = cores[t.prob].next3;
-    c.o4 = cores[t.prob].next4;
-    c.inv_h2 = p.inv_h2;
-    c.dt2 = p.dt2;
-    c.c2c = p.c2_const;
-    c.nx = p.nx;
-    c.ny = p.ny;
-    c.cx0 = p.skip[0];
-    c.cx1 = p.skip[1];
-    c.cy0 = p.skip[2];
-    c.cy1 = p.skip[3];
-    c.xs = c.cx0 + (t.tx * (64 - 2 * HL) + lane - HL) * VX;
-    c.need = c.xs < c.cx1 + HL * VX;
-    c.xw = c.xs % c.nx;
-    if (c.xw < 0) c.xw += c.nx;
-    c.vec = c.xw % VX == 0 && c.xw + VX <= c.nx;
-    c.out = lane >= HL && lane < 64 - HL && c.xs < c.cx1;
-    const int rows = p.tile_rows;
-    const int ya = c.cy0 + t.ty * rows, yb = min(ya + rows, c.cy1);
-    if (t.ty & 1)
-        c.template march<G, -1>(yb - 1, yb - ya);
-    else
-        c.template march<G, 1>(ya, yb - ya);
+    const MultiCore<T> &mc = cores[t.prob];
+    run_marchN<T, VX, G, false, NL>(mc.p, mc.p.u, mc.p.uo, mc.pen, mc.fin, mc.p.skip[0], mc.p.skip[1],
+                                    mc.p.skip[2], mc.p.skip[3], t.tx, t.ty, (int)(threadIdx.x & 63));
 }
 
 // One ordinary step over a list of 64 x 4 cell tiles (the frame around the

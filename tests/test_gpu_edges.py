@@ -15,8 +15,9 @@ dp = pytest.importorskip("paper_1804_01390_amd")
 
 pytestmark = pytest.mark.gpu
 
-VARIANTS = [dp.VARIANT_CELL, dp.VARIANT_MARCH, dp.VARIANT_MARCH1, dp.VARIANT_TWOSTEP, dp.VARIANT_THREESTEP,
-            dp.VARIANT_FOURSTEP]
+# (variant, tile_rows)
+VARIANTS = [(dp.VARIANT_CELL, 0), (dp.VARIANT_MARCH, 0), (dp.VARIANT_MARCH1, 0), (dp.VARIANT_TWOSTEP, 0),
+            (dp.VARIANT_THREESTEP, 0), (dp.VARIANT_FOURSTEP, 0), (dp.VARIANT_DEEP, 0), (dp.VARIANT_DEEP, 8 << 20)]
 
 
 def _fields(sim, ndim):
@@ -25,11 +26,11 @@ def _fields(sim, ndim):
                if sim.lo[a] + sim.hi[a] > 0])
 
 
-@pytest.mark.parametrize("variant", VARIANTS)
-def test_zero_steps_change_nothing(variant):
+@pytest.mark.parametrize("variant,tile_rows", VARIANTS)
+def test_zero_steps_change_nothing(variant, tile_rows):
     w = synthetic.bump2d(40, 6, 0)
     sim = dp.Simulation(w.n, w.lo, w.hi, w.h, w.dt, w.sigma, dtype=torch.float64)
-    sim.set_variant(variant, 0)
+    sim.set_variant(variant, tile_rows)
     sim.set_state(torch.from_numpy(w.U0))
     sim.step(7)
     sim.sync()
@@ -61,9 +62,9 @@ def test_small_grids_and_thin_layers(dtype, ndim, n, lo, hi):
     steps = 37
     print("case small %dD n=%s lo=%s hi=%s %s" % (ndim, n, lo, hi, dtype), flush=True)
     outs = []
-    for v in VARIANTS:
+    for v, tr in VARIANTS:
         sim = dp.Simulation(n, lo, hi, 1.0, dt, sig, dtype=dtype)
-        sim.set_variant(v, 0)
+        sim.set_variant(v, tr)
         sim.set_state(torch.from_numpy(U0))
         sim.step(steps)
         sim.sync()
@@ -81,15 +82,16 @@ def test_small_grids_and_thin_layers(dtype, ndim, n, lo, hi):
     assert max(errs.values()) <= tol, errs
 
 
-@pytest.mark.parametrize("variant", [dp.VARIANT_TWOSTEP, dp.VARIANT_THREESTEP, dp.VARIANT_FOURSTEP])
-def test_problem_set_with_a_problem_too_small_for_passes(variant):
+@pytest.mark.parametrize("variant,rows", [(dp.VARIANT_TWOSTEP, 0), (dp.VARIANT_THREESTEP, 0),
+                                          (dp.VARIANT_FOURSTEP, 0), (dp.VARIANT_DEEP, 8 << 20)])
+def test_problem_set_with_a_problem_too_small_for_passes(variant, rows):
     """One problem too small for a multi-step core makes the whole set take
     single steps (or two-step passes); the result does not change."""
     probs = [synthetic.bump2d(s, m, 0, 2.0, 2.0, 1.0, 0.5) for s, m in [(64, 8), (3, 2), (100, 12)]]
     outs = []
     for v in (variant, dp.VARIANT_MARCH):
         sim = dp.MultiSimulation(probs, dtype=torch.float64)
-        sim.set_variant(v, 0, 0)
+        sim.set_variant(v, rows if v == variant else 0, 0)
         sim.set_state([w.U0 for w in probs])
         sim.step(23, graph=True)
         sim.step(10)
@@ -119,9 +121,9 @@ def test_layer_without_damping_is_the_plain_wave_equation():
     plain, _ = oracle.run(g0, oracle.start(g0, U0), 40)
     g = oracle.Grid(N, 1.0, 0.5, sig)
     ref, _ = oracle.run(g, oracle.start(g, U0), 40)
-    for v in VARIANTS:
+    for v, tr in VARIANTS:
         sim = dp.Simulation(n, lo, hi, 1.0, 0.5, sig, dtype=torch.float64)
-        sim.set_variant(v, 0)
+        sim.set_variant(v, tr)
         sim.set_state(torch.from_numpy(U0))
         sim.step(40)
         sim.sync()

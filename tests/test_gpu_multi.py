@@ -107,7 +107,8 @@ def test_multi_launch_shapes_bit_identical(dtype, sides):
                                  (dp.VARIANT_TWOSTEP, 64, 2), (dp.VARIANT_THREESTEP, 0, 0),
                                  (dp.VARIANT_THREESTEP, 1, 1), (dp.VARIANT_THREESTEP, 5, 4),
                                  (dp.VARIANT_FOURSTEP, 0, 0), (dp.VARIANT_FOURSTEP, 1, 1),
-                                 (dp.VARIANT_FOURSTEP, 6, 4)]:
+                                 (dp.VARIANT_FOURSTEP, 6, 4), (dp.VARIANT_DEEP, 5 << 20, 0),
+                                 (dp.VARIANT_DEEP, (8 << 20) | 3, 4)]:
         sim = dp.MultiSimulation(probs, dtype=dtype)
         sim.set_state([w.U0 for w in probs])
         sim.step(10, graph=True)
@@ -127,7 +128,8 @@ def test_multi_set_variant_rejects_bad_shapes():
     probs = _problems([64, 96], [8, 9])
     sim = dp.MultiSimulation(probs, dtype=torch.float32)
     for variant, rows, group in [(dp.VARIANT_MARCH, 3, 4), (dp.VARIANT_MARCH, 5000, 4), (dp.VARIANT_MARCH, 32, 3),
-                                 (dp.VARIANT_TWOSTEP, 5000, 2), (dp.VARIANT_CELL, 8, 2)]:
+                                 (dp.VARIANT_TWOSTEP, 5000, 2), (dp.VARIANT_CELL, 8, 2),
+                                 (dp.VARIANT_DEEP, 1 << 20, 2), (dp.VARIANT_DEEP, 9 << 20, 2)]:
         with pytest.raises(dp.DpmlError):
             sim.set_variant(variant, rows, group)
     sim.close()
@@ -148,18 +150,20 @@ def test_multi_tuner_picks_a_candidate_and_keeps_the_state(tmp_path):
     sim.close()
 
 
-@pytest.mark.parametrize("variant", [dp.VARIANT_TWOSTEP, dp.VARIANT_THREESTEP, dp.VARIANT_FOURSTEP])
+@pytest.mark.parametrize("variant,rows", [(dp.VARIANT_TWOSTEP, 0), (dp.VARIANT_THREESTEP, 0),
+                                          (dp.VARIANT_FOURSTEP, 0), (dp.VARIANT_DEEP, 6 << 20),
+                                          (dp.VARIANT_DEEP, 8 << 20)])
 @pytest.mark.parametrize("dtype,sides", [(torch.float64, [64, 130, 257, 96, 300]),
                                          (torch.float32, [64, 131, 256, 97, 300])])
-def test_multi_twostep_matches_oracle_and_graph(dtype, sides, variant):
-    """Two-, three- and four-step passes over all problems (cores in one launch,
+def test_multi_twostep_matches_oracle_and_graph(dtype, sides, variant, rows):
+    """Passes of 2, 3, 4, 6 and 8 levels over all problems (cores in one launch,
     frames on a second stream) against the oracle per problem, eagerly and as
     graph replays with step counts of every remainder in between."""
     ms = [8, 13, 16, 9, 20]
     probs = _problems(sides, ms)
     print("case multi passes %d %s sides=%s" % (variant, dtype, sides), flush=True)
     sim = dp.MultiSimulation(probs, dtype=dtype)
-    sim.set_variant(variant, 0, 0)
+    sim.set_variant(variant, rows, 0)
     sim.set_state([w.U0 for w in probs])
     for k, graph in [(20, True), (7, False), (20, True), (20, True), (13, True), (10, False)]:
         sim.step(k, graph=graph)

@@ -237,6 +237,18 @@ def test_step_checked_reports_nonfinite():
     sim.close()
 
 
+def test_set_variant_rejects_bad_shapes():
+    w = synthetic.bump2d(32, 4, 0)
+    sim = dp.Simulation(w.n, w.lo, w.hi, w.h, w.dt, w.sigma, dtype=torch.float32)
+    for variant, tile_rows in [(8, 0), (-1, 0), (dp.VARIANT_TWOSTEP, 1 << 20), (dp.VARIANT_DEEP, 1 << 20),
+                               (dp.VARIANT_DEEP, 9 << 20), (dp.VARIANT_DEEP, 1 << 24), (dp.VARIANT_CELL, -1)]:
+        with pytest.raises(dp.DpmlError) as ei:
+            sim.set_variant(variant, tile_rows)
+        assert ei.value.code == dp.DPML_EINVAL
+    sim.set_variant(dp.VARIANT_DEEP, (8 << 20) | (4 << 12) | 16)
+    sim.close()
+
+
 def test_step_before_state_is_an_error():
     w = synthetic.bump2d(32, 4, 0)
     sim = dp.Simulation(w.n, w.lo, w.hi, w.h, w.dt, w.sigma, dtype=torch.float32)
@@ -301,7 +313,7 @@ def test_graph_replay_matches_eager(dtype):
 
 
 
-@pytest.mark.parametrize("multi", ["two", "three", "four"])
+@pytest.mark.parametrize("multi", ["two", "three", "four", "five", "eight"])
 @pytest.mark.parametrize("rows", [0, 5])
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
 @pytest.mark.parametrize("case", ["bump", "ragged", "onesided", "c2", "batch", "nolayer"])
@@ -311,7 +323,8 @@ def test_twostep_matches_single_steps_and_oracle(dtype, case, rows, multi):
     and the oracle agrees; step counts that are not a multiple end with a
     shorter pass and/or a single step.  rows = 5 makes the kernel's tiles end in a
     remainder of rows."""
-    MULTI = {"two": dp.VARIANT_TWOSTEP, "three": dp.VARIANT_THREESTEP, "four": dp.VARIANT_FOURSTEP}[multi]
+    MULTI, depth = {"two": (dp.VARIANT_TWOSTEP, 0), "three": (dp.VARIANT_THREESTEP, 0),
+                    "four": (dp.VARIANT_FOURSTEP, 0), "five": (dp.VARIANT_DEEP, 5), "eight": (dp.VARIANT_DEEP, 8)}[multi]
     rng = np.random.default_rng(17)
     c2 = None
     batch = 1
@@ -346,7 +359,7 @@ def test_twostep_matches_single_steps_and_oracle(dtype, case, rows, multi):
     outs = []
     for variant in (MULTI, dp.VARIANT_CELL):
         sim = dp.Simulation(n, lo, hi, 1.0, dt, sig, c2=1.0 if c2 is None else c2, dtype=_dtype(dtype), batch=batch)
-        sim.set_variant(variant, rows if variant == MULTI else 0)
+        sim.set_variant(variant, (depth << 20) | rows if variant == MULTI else 0)
         sim.set_state(torch.from_numpy(U0))
         sim.step(steps)
         sim.sync()
@@ -368,12 +381,13 @@ def test_twostep_matches_single_steps_and_oracle(dtype, case, rows, multi):
 
 
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
-@pytest.mark.parametrize("variant", [dp.VARIANT_TWOSTEP, dp.VARIANT_THREESTEP, dp.VARIANT_FOURSTEP])
+@pytest.mark.parametrize("variant", [dp.VARIANT_TWOSTEP, dp.VARIANT_THREESTEP, dp.VARIANT_FOURSTEP,
+                                     (dp.VARIANT_DEEP, 5), (dp.VARIANT_DEEP, 7)])
 @pytest.mark.parametrize("group,rows", [(1, 3), (4, 7), (4, 4), (2, 1), (1 << 4 | 4, 8), (3 << 4 | 2, 5),
                                         (5 << 4 | 4, 6)])
 def test_multistep_launch_shapes_bit_identical(dtype, variant, group, rows):
-    """Every load-group size and tile height of the two-, three- and four-step
-    kernels (tiles shorter than a group, one-row tiles), and the frame's
+    """Every load-group size and tile height of the multi-step core kernels
+    (2, 3, 4, 5 and 7 levels) (tiles shorter than a group, one-row tiles), and the frame's
     steps one thread per cell or as wave marches over spans of 1, 3 or 5
     rows (group's high bits), give the single-step result bit for bit, with
     a c^2 field and a ragged grid."""
@@ -383,8 +397,11 @@ def test_multistep_launch_shapes_bit_identical(dtype, variant, group, rows):
     c2 = synthetic.smooth_c2(n, lo, hi, 6, 10.0, 30.0, 0.5, 8, rng)
     U0 = synthetic.gaussian_sum(n, lo, hi, 8, 2.0, 6.0, rng)
     dt = 0.5 / math.sqrt(float(np.max(c2)))
+    depth = 0
+    if isinstance(variant, tuple):
+        variant, depth = variant
     outs = []
-    for v, tr in ((variant, (group << 12) | rows), (dp.VARIANT_CELL, 0)):
+    for v, tr in ((variant, (depth << 20) | (group << 12) | rows), (dp.VARIANT_CELL, 0)):
         sim = dp.Simulation(n, lo, hi, 1.0, dt, sig, c2=c2, dtype=_dtype(dtype))
         sim.set_variant(v, tr)
         sim.set_state(torch.from_numpy(U0))
@@ -399,8 +416,12 @@ def test_multistep_launch_shapes_bit_identical(dtype, variant, group, rows):
 
 
 @pytest.mark.parametrize("tile_rows", [0, (3 << 16) | (4 << 12) | 8])
-@pytest.mark.parametrize("variant", [dp.VARIANT_TWOSTEP, dp.VARIANT_THREESTEP, dp.VARIANT_FOURSTEP])
+@pytest.mark.parametrize("variant", [dp.VARIANT_TWOSTEP, dp.VARIANT_THREESTEP, dp.VARIANT_FOURSTEP,
+                                     (dp.VARIANT_DEEP, 6), (dp.VARIANT_DEEP, 8)])
 def test_twostep_graph_replay_matches_eager(variant, tile_rows):
+    if isinstance(variant, tuple):
+        variant, depth = variant
+        tile_rows |= depth << 20
     w = synthetic.bump2d(200, 20, 0)
     a = dp.Simulation(w.n, w.lo, w.hi, w.h, w.dt, w.sigma, dtype=torch.float32)
     b = dp.Simulation(w.n, w.lo, w.hi, w.h, w.dt, w.sigma, dtype=torch.float32)
@@ -456,6 +477,11 @@ def test_launch_timing_counts_and_bytes(dtype):
     sim.step(6)                                   # one quadruple and one pair
     t = sim.get_timing()
     assert t["pair"]["launches"] == 2 and t["frame"]["launches"] == 4 + 2 and "step" not in t
+    sim.set_variant(dp.VARIANT_DEEP, 6 << 20)
+    sim.step(15)                                  # two passes of six levels and one of three
+    t = sim.get_timing()
+    assert t["pair"]["launches"] == 3 and t["frame"]["launches"] == 6 + 6 + 3 and "step" not in t
+    assert t["pair"]["bytes"] + t["frame"]["bytes"] == 15 * step_bytes
     sim.step_graph(4)
     sim.sync()
     assert sim.get_timing() == {}
@@ -473,6 +499,7 @@ def test_launch_timing_counts_and_bytes(dtype):
     (2, dp.VARIANT_THREESTEP, 0, (True, True), [7, 12], [10, 0]),       # no layer cell above: single steps
     (2, dp.VARIANT_FOURSTEP, 0, (True, True), [7, 12], [10, 5]),
     (2, dp.VARIANT_FOURSTEP, (2 << 16) | (2 << 12) | 6, (False, True), [7, 12], [10, 1]),
+    (2, dp.VARIANT_DEEP, (8 << 20) | (4 << 12) | 12, (True, True), [9, 12], [10, 1]),
     (3, dp.VARIANT_TWOSTEP, 0, (True, False, True), [5, 3, 6], [4, 7, 5]),
     (3, dp.VARIANT_TWOSTEP, 0, (True, True, True), [0, 3, 6], [4, 7, 1]),
 ])
