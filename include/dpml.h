@@ -132,8 +132,13 @@ extern "C" {
                                   U^{n+D} on it (4 words per core cell per D
                                   steps) over a core [lo+D, lo+n+1-D) per axis;
                                   the frame takes D single steps beside it; the
-                                  last steps of a run take a shorter pass.  The
-                                  lower bits as for TWOSTEP.  3D: as TWOSTEP     */
+                                  last steps of a run take a shorter pass.  Bit
+                                  24: depths 4 .. 8 issue each group's loads one
+                                  group ahead.  The lower bits as for TWOSTEP,
+                                  and frame form 15 in bits 16-19 (any multi-step
+                                  variant) takes all the frame's steps of a pass
+                                  in one launch over tiles held in LDS with a
+                                  halo of D cells.  3D: as TWOSTEP                */
 
 typedef struct dpml_grid {
     int32_t ndim;    /* 2 or 3 */
@@ -219,7 +224,7 @@ int dpml_record_plane(dpml_t *h, int32_t axis, int64_t index, void *planes,
  * tile_rows (meaning per variant above; 0 = default).  All variants
  * evaluate the scheme in the same operation order, so results do not
  * depend on the choice.  DPML_EINVAL for an unknown variant or tile_rows
- * outside [0, 2^20) ([0, 2^24) for DEEP, whose depth may not be 1). */
+ * outside [0, 2^20) ([0, 2^25) for DEEP, whose depth may not be 1). */
 int dpml_set_variant(dpml_t *h, int32_t variant, int32_t tile_rows);
 
 /* Enqueue nsteps fused steps (U, Phi, Psi, sources, receivers).  Returns

@@ -23,14 +23,17 @@ from . import (VARIANT_CELL, VARIANT_DEEP, VARIANT_FOURSTEP, VARIANT_MARCH, VARI
 DEFAULT_CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "autotune_cache.json")
 
 # multi-step variants: rows per wave in the low 12 bits, load group size above
-# (frame span rows above bit 16: the frame's steps as wave marches; DEEP:
-# levels per pass above bit 20)
-CANDIDATES_2D: List[Tuple[int, int]] = ([(VARIANT_DEEP, (d << 20) | (g << 12) | r) for d in (6, 7, 8) for g in (2, 4)
-                                         for r in (12, 16, 24, 32, 48)]
-                                        + [(VARIANT_FOURSTEP, (g << 12) | r) for g in (2, 4) for r in (4, 6, 8, 12, 16)]
-                                        + [(VARIANT_THREESTEP, (g << 12) | r) for g in (2, 4) for r in (4, 6, 8, 12, 16)]
-                                        + [(VARIANT_THREESTEP, (f << 16) | (4 << 12) | r) for f in (2, 3, 4)
-                                           for r in (6, 8)]
+# (frame form in bits 16-19: spans of that many rows for the frame's steps as
+# wave marches, 15 all of them fused in one launch; DEEP: levels per pass in
+# bits 20-23, bit 24 loads issued a group ahead)
+CANDIDATES_2D: List[Tuple[int, int]] = ([(VARIANT_DEEP, (pf << 24) | (d << 20) | (g << 12) | r)
+                                         for d in (6, 8) for pf in (0, 1) for g in (2, 4) for r in (16, 24, 32, 48)]
+                                        + [(VARIANT_DEEP, (pf << 24) | (7 << 20) | (2 << 12) | r)
+                                           for pf in (0, 1) for r in (24, 32)]
+                                        + [(VARIANT_DEEP, (d << 20) | (15 << 16) | (2 << 12) | 24) for d in (4, 6)]
+                                        + [(VARIANT_FOURSTEP, (g << 12) | r) for g in (2, 4) for r in (8, 16)]
+                                        + [(VARIANT_THREESTEP, (g << 12) | r) for g in (2, 4) for r in (6, 8, 12)]
+                                        + [(VARIANT_THREESTEP, (f << 16) | (4 << 12) | 8) for f in (2, 3)]
                                         + [(VARIANT_TWOSTEP, (g << 12) | r) for g in (2, 4) for r in (8, 16)]
                                         + [(VARIANT_CELL, th) for th in (1, 2, 4, 8)]
                                         + [(VARIANT_MARCH, r) for r in (4, 8, 16)]

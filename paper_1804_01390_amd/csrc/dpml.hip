@@ -158,6 +158,9 @@ struct dpml {
     // the same frames as spans for the marching frame kernel (span rows fspan_rows)
     dpmlk::Span2 *d_fspan[kMaxLevels - 1][kMaxLevels] = {};
     Table2<int64_t, kMaxLevels - 1, kMaxLevels> n_fspan = filled<int64_t, kMaxLevels - 1, kMaxLevels>(-1);
+    // tiles of the fused frame launch per depth ([levels - 2]; -1: not built yet)
+    dpmlk::TileRef *d_ffused[kMaxLevels - 1] = {};
+    int64_t n_ffused[kMaxLevels - 1] = {-1, -1, -1, -1, -1, -1, -1};
     int fspan_rows = 0;
     // the frame's steps run on a second stream beside the core kernel
     hipStream_t side = nullptr;
@@ -722,12 +725,50 @@ void frame_spans(const Layout &L, const int S[4], int prob, std::vector<dpmlk::S
     if (S[1] - S[0] < NX) rect(S[1], S[0] + NX, S[2], S[3]);
 }
 
-// Frame span rows of the two- and three-step variants: bits 16-19 of
-// tile_rows (0: the frame one thread per cell, as always with walls: the
-// marching frame assumes the periodic wrap).
+// Frame form of the multi-step variants, bits 16-19 of tile_rows: 0 the
+// frame's steps one thread per cell; 1 .. 14 wave marches over spans of that
+// many rows (periodic grids only: with walls the frame is one thread per
+// cell); kFrameFused all of a pass's frame steps in one launch.
+constexpr int kFrameFused = 15;
+
+bool frame_fused(const dpml *H) { return ((H->tile_rows >> 16) & 0xF) == kFrameFused; }
+
 int frame_span_rows(const dpml *H)
 {
-    return (H->L.wall[0] || H->L.wall[1]) ? 0 : (H->tile_rows >> 16) & 0xF;
+    const int f = (H->tile_rows >> 16) & 0xF;
+    return (H->L.wall[0] || H->L.wall[1] || f == kFrameFused) ? 0 : f;
+}
+
+// Tile shape of the fused frame kernel per element type.
+template <typename T>
+struct FusedTile {
+    static constexpr int TX = 64, TY = 8;
+};
+
+// The fused frame's tiles for passes of `levels` levels: the TX x TY tiles of
+// a fixed grid that meet everything outside the core shrunk by one.
+int ensure_fused(dpml *H, int levels, int TX, int TY)
+{
+    const int q = levels - 2;
+    if (H->n_ffused[q] >= 0) return DPML_OK;
+    const Layout &L = H->L;
+    int r[4];
+    core_rect(L, levels, r);
+    const int in[4] = {r[0] + 1, r[1] - 1, r[2] + 1, r[3] - 1};
+    const int tx = (int)((L.N[0] + TX - 1) / TX), ty = (int)((L.N[1] + TY - 1) / TY);
+    std::vector<dpmlk::TileRef> t;
+    for (int y = 0; y < ty; ++y)
+        for (int x = 0; x < tx; ++x) {
+            const int xa = x * TX, xb = std::min<int>(xa + TX, (int)L.N[0]);
+            const int ya = y * TY, yb = std::min<int>(ya + TY, (int)L.N[1]);
+            const bool inside = xa >= in[0] && xb <= in[1] && ya >= in[2] && yb <= in[3];
+            if (!inside) t.push_back({0, x, y, 0});
+        }
+    H->n_ffused[q] = (int64_t)t.size();
+    if (t.empty()) return DPML_OK;
+    HIP_TRY(H, hipMalloc((void **)&H->d_ffused[q], t.size() * sizeof(dpmlk::TileRef)));
+    HIP_TRY(H, hipMemcpy(H->d_ffused[q], t.data(), t.size() * sizeof(dpmlk::TileRef), hipMemcpyHostToDevice));
+    return DPML_OK;
 }
 
 int ensure_frame(dpml *H, int levels, int shrink)
@@ -784,6 +825,12 @@ int ensure_frame(dpml *H, int levels, int shrink)
 int ensure_multistep(dpml *H, int levels)
 {
     if (H->L.ndim == 3) return ensure_side(H);
+    if (frame_fused(H)) {
+        const bool f32 = H->L.dtype == DPML_F32;
+        int rc = ensure_fused(H, levels, f32 ? FusedTile<float>::TX : FusedTile<double>::TX,
+                              f32 ? FusedTile<float>::TY : FusedTile<double>::TY);
+        return rc ? rc : ensure_side(H);
+    }
     for (int sh = 0; sh < levels; ++sh) {
         int rc = ensure_frame(H, levels, sh);
         if (rc) return rc;
@@ -791,15 +838,41 @@ int ensure_multistep(dpml *H, int levels)
     return ensure_side(H);
 }
 
-// The core kernel of a pass of 4 .. kMaxLevels levels.
+// The fused frame kernel of a pass of 2 .. kMaxLevels levels.
+template <typename T>
+void launch_fused(int levels, dim3 grid, hipStream_t st, const dpmlk::StepArgs<T> &p, T *pen, T *fin,
+                  const dpmlk::TileRef *tiles, int n)
+{
+    constexpr int TX = FusedTile<T>::TX, TY = FusedTile<T>::TY;
+    const dim3 block(256);
+#define DPML_FUSED(D_) \
+    hipLaunchKernelGGL((dpmlk::k_frame_fused2d<T, D_, TX, TY>), grid, block, 0, st, p, pen, fin, tiles, n)
+    switch (levels) {
+    case 2: DPML_FUSED(2); break;
+    case 3: DPML_FUSED(3); break;
+    case 4: DPML_FUSED(4); break;
+    case 5: DPML_FUSED(5); break;
+    case 6: DPML_FUSED(6); break;
+    case 7: DPML_FUSED(7); break;
+    default: DPML_FUSED(8); break;
+    }
+#undef DPML_FUSED
+}
+
+// The core kernel of a pass of 4 .. kMaxLevels levels (pf: the next load
+// group issued ahead).
 template <typename T, int VX, int G, bool C2>
-void launch_coreN(int levels, dim3 grid, hipStream_t st, const dpmlk::StepArgs<T> &p, T *pen, T *fin,
+void launch_coreN(int levels, bool pf, dim3 grid, hipStream_t st, const dpmlk::StepArgs<T> &p, T *pen, T *fin,
                   const int r[4], int strips, int n_waves)
 {
     const dim3 block(256);
-#define DPML_CORE_N(NL)                                                                                   \
-    hipLaunchKernelGGL((dpmlk::k_stepN_march<T, VX, G, C2, NL>), grid, block, 0, st, p, pen, fin, r[0], r[1], \
-                       r[2], r[3], strips, n_waves)
+#define DPML_CORE_N(NL)                                                                                        \
+    if (pf)                                                                                                    \
+        hipLaunchKernelGGL((dpmlk::k_stepN_march<T, VX, G, C2, NL, true>), grid, block, 0, st, p, pen, fin, r[0], \
+                           r[1], r[2], r[3], strips, n_waves);                                                 \
+    else                                                                                                       \
+        hipLaunchKernelGGL((dpmlk::k_stepN_march<T, VX, G, C2, NL, false>), grid, block, 0, st, p, pen, fin, r[0], \
+                           r[1], r[2], r[3], strips, n_waves)
     switch (levels) {
     case 4: DPML_CORE_N(4); break;
     case 5: DPML_CORE_N(5); break;
@@ -861,8 +934,8 @@ int launch_multistep(dpml *H, int levels)
             hipLaunchKernelGGL((dpmlk::k_step3_march<T, VX, GG, C2>), grid, block, 0, H->stream, p, nxt[1],     \
                                nxt[2], r[0], r[1], r[2], r[3], strips, n_waves);                            \
         else                                                                                                \
-            launch_coreN<T, VX, GG, C2>(levels, grid, H->stream, p, nxt[levels - 2], nxt[levels - 1], r, strips,  \
-                                        n_waves);
+            launch_coreN<T, VX, GG, C2>(levels, (H->tile_rows >> 24) & 1, grid, H->stream, p, nxt[levels - 2],    \
+                                        nxt[levels - 1], r, strips, n_waves);
         if (G == 4) {
             if (p.c2) { DPML_MULTI_LAUNCH(4, true) } else { DPML_MULTI_LAUNCH(4, false) }
         } else if (G == 1) {
@@ -872,6 +945,30 @@ int launch_multistep(dpml *H, int levels)
         }
 #undef DPML_MULTI_LAUNCH
         timed_end(H, slot);
+    }
+    if (frame_fused(H)) {
+        // all the frame's steps in one launch on the side stream; it reads the
+        // aux buffer of level n and writes level n+levels to the other one
+        const int nf = (int)H->n_ffused[q];
+        if (nf > 0) {
+            dpmlk::StepArgs<T> pj = make_args<T>(H);
+            pj.u = A;
+            pj.uo = Bv;
+            for (int a = 0; a < 4; ++a) pj.skip[a] = r[a];
+            const int slot = timed_begin(H, DPML_KERNEL_FRAME, levels * step_bytes(H, (double)L.ncell - core, aux_cells(L)),
+                                         H->side);
+            launch_fused<T>(levels, dim3((unsigned)round8(nf), B), H->side, pj, nxt[levels - 2], nxt[levels - 1],
+                            H->d_ffused[q], nf);
+            timed_end(H, slot, H->side);
+        }
+        HIP_TRY(H, hipEventRecord(H->ev_join, H->side));
+        HIP_TRY(H, hipStreamWaitEvent(H->stream, H->ev_join, 0));
+        HIP_TRY(H, hipGetLastError());
+        H->u_now = nxt[levels - 1];
+        H->u_old = nxt[levels - 2];
+        H->cur = 1 - H->cur;
+        H->n += levels;
+        return DPML_OK;
     }
     // the frame's steps on the side stream: level j from level j-1 (U^n at
     // j = 1) and the level before it, aux buffers alternating
@@ -1311,7 +1408,7 @@ int dpml_set_variant(dpml_t *H, int32_t variant, int32_t tile_rows)
 {
     if (!H) return DPML_EINVAL;
     if (variant < DPML_VARIANT_AUTO || variant > DPML_VARIANT_DEEP || tile_rows < 0 ||
-        tile_rows >= (1 << (variant == DPML_VARIANT_DEEP ? 24 : 20)))
+        tile_rows >= (1 << (variant == DPML_VARIANT_DEEP ? 25 : 20)))
         return H->fail(DPML_EINVAL, "bad variant");
     if (variant == DPML_VARIANT_DEEP && (pass_depth(variant, tile_rows) < 2 || pass_depth(variant, tile_rows) > kMaxLevels))
         return H->fail(DPML_EINVAL, "DEEP passes take 2 .. 8 levels");
@@ -1481,6 +1578,8 @@ void dpml_destroy(dpml_t *H)
             if (H->d_frame[k][j]) (void)hipFree(H->d_frame[k][j]);
             if (H->d_fspan[k][j]) (void)hipFree(H->d_fspan[k][j]);
         }
+    for (int k = 0; k < kMaxLevels - 1; ++k)
+        if (H->d_ffused[k]) (void)hipFree(H->d_ffused[k]);
     if (H->ev_fork) (void)hipEventDestroy(H->ev_fork);
     if (H->ev_join) (void)hipEventDestroy(H->ev_join);
     if (H->side) (void)hipStreamDestroy(H->side);
@@ -2644,6 +2743,8 @@ int step_graph_impl(dpml *H, int64_t nsteps)
         for (int lv = 2; lv <= top; ++lv) {    // frame tables, side stream, events before capture
             int rcf = ensure_multistep(H, lv);
             if (rcf) return rcf;
+            view.d_ffused[lv - 2] = H->d_ffused[lv - 2];
+            view.n_ffused[lv - 2] = H->n_ffused[lv - 2];
             for (int sh = 0; sh < kMaxLevels; ++sh) {
                 view.d_frame[lv - 2][sh] = H->d_frame[lv - 2][sh];
                 view.n_frame[lv - 2][sh] = H->n_frame[lv - 2][sh];
@@ -2665,6 +2766,7 @@ int step_graph_impl(dpml *H, int64_t nsteps)
         hipError_t e = hipStreamEndCapture(H->cap, &g);
         view.cap = nullptr; view.graph = nullptr; view.exec = nullptr;   // not owned by the view
         view.d_src_cells = view.d_src_order = view.d_rec_cells = view.d_rec_sorted = view.d_rec_order = nullptr;
+        for (int lv = 0; lv < kMaxLevels - 1; ++lv) view.d_ffused[lv] = nullptr;
         for (int lv = 0; lv < kMaxLevels - 1; ++lv)
             for (int sh = 0; sh < kMaxLevels; ++sh) {
                 view.d_frame[lv][sh] = nullptr;

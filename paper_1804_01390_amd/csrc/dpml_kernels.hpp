@@ -1061,10 +1061,36 @@ struct MarchNCtx : March2Ctx<T, VX, C2F> {
         s.c[NL - 2] = cn;
     }
 
+    // the loads of the group at march index k: U^n rows k+1 .. k+G, U^{n-1}
+    // and c^2 rows k .. k+G-1
+    template <int G>
+    struct Loads {
+        R un[G], pm[G], c[G];
+    };
+
+    template <int G, int DIR>
+    __device__ __forceinline__ void issue(Loads<G> &ld, int base, int k) const
+    {
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+            ld.un[g] = this->load(this->u, this->wrapy(base + DIR * (k + 1 + g)));
+            ld.pm[g] = this->load(this->up, this->wrapy(base + DIR * (k + g)));
+            if (C2F) ld.c[g] = this->load(this->c2, this->wrapy(base + DIR * (k + g)));
+        }
+    }
+
     // G march indices k .. k+G-1 in the steady state (every level's row inside
     // the tile), all loads of the group issued first
     template <int G, int DIR>
     __device__ __forceinline__ void group(State &s, int base, int k) const
+    {
+        Loads<G> ld;
+        issue<G, DIR>(ld, base, k);
+        compute<G, DIR>(s, base, k, ld);
+    }
+
+    template <int G, int DIR>
+    __device__ __forceinline__ void compute(State &s, int base, int k, const Loads<G> &ld) const
     {
         R w[NL][G + 2], pm[G], cw[NL - 1 + G];         // w[m][i]: level m on row k-m-1+i
 #pragma unroll
@@ -1076,9 +1102,9 @@ struct MarchNCtx : March2Ctx<T, VX, C2F> {
         for (int i = 0; i < NL - 1; ++i) cw[i] = s.c[i];
 #pragma unroll
         for (int g = 0; g < G; ++g) {
-            w[0][2 + g] = this->load(this->u, this->wrapy(base + DIR * (k + 1 + g)));
-            pm[g] = this->load(this->up, this->wrapy(base + DIR * (k + g)));
-            if (C2F) cw[NL - 1 + g] = this->load(this->c2, this->wrapy(base + DIR * (k + g)));
+            w[0][2 + g] = ld.un[g];
+            pm[g] = ld.pm[g];
+            if (C2F) cw[NL - 1 + g] = ld.c[g];
         }
 #pragma unroll
         for (int g = 0; g < G; ++g) {
@@ -1100,7 +1126,9 @@ struct MarchNCtx : March2Ctx<T, VX, C2F> {
         for (int i = 0; i < NL - 1; ++i) s.c[i] = cw[G + i];
     }
 
-    template <int G, int DIR>
+    // PF: in the steady state the loads of the next group are issued before
+    // the current group's arithmetic (one group of rows in flight ahead)
+    template <int G, int DIR, bool PF = false>
     __device__ __forceinline__ void march(int base, int L) const
     {
         State s;
@@ -1114,14 +1142,29 @@ struct MarchNCtx : March2Ctx<T, VX, C2F> {
         int k = -(NL - 1);
         for (; k <= NL - 2 && k <= L + NL - 2; ++k) one<DIR>(s, base, k, L);
         // steady state: every level's rows inside the tile (no guards needed)
-        for (; k + G - 1 <= L - 1; k += G) group<G, DIR>(s, base, k);
+        if (PF) {
+            if (k + G - 1 <= L - 1) {
+                Loads<G> ld;
+                issue<G, DIR>(ld, base, k);
+                for (;;) {
+                    const Loads<G> cur = ld;
+                    const bool more = k + 2 * G - 1 <= L - 1;
+                    if (more) issue<G, DIR>(ld, base, k + G);
+                    compute<G, DIR>(s, base, k, cur);
+                    k += G;
+                    if (!more) break;
+                }
+            }
+        } else {
+            for (; k + G - 1 <= L - 1; k += G) group<G, DIR>(s, base, k);
+        }
         for (; k <= L + NL - 2; ++k) one<DIR>(s, base, k, L);
     }
 };
 
 // Set up a march context for strip `strip`, tile row `ty` of the core
 // [cx0, cx1) x [cy0, cy1) and run it.
-template <typename T, int VX, int G, bool C2F, int NL>
+template <typename T, int VX, int G, bool C2F, int NL, bool PF>
 __device__ __forceinline__ void run_marchN(const StepArgs<T> &p, const T *u, const T *uo, T *u_pen, T *u_fin,
                                            int cx0, int cx1, int cy0, int cy1, int strip, int ty, int lane)
 {
@@ -1152,20 +1195,20 @@ __device__ __forceinline__ void run_marchN(const StepArgs<T> &p, const T *u, con
     const int rows = p.tile_rows;
     const int ya = cy0 + ty * rows, yb = min(ya + rows, cy1);
     if (ty & 1)
-        c.template march<G, -1>(yb - 1, yb - ya);
+        c.template march<G, -1, PF>(yb - 1, yb - ya);
     else
-        c.template march<G, 1>(ya, yb - ya);
+        c.template march<G, 1, PF>(ya, yb - ya);
 }
 
-template <typename T, int VX, int G, bool C2F, int NL>
+template <typename T, int VX, int G, bool C2F, int NL, bool PF>
 __global__ void __launch_bounds__(256) k_stepN_march(StepArgs<T> p, T *__restrict__ u_pen, T *__restrict__ u_fin,
                                                      int cx0, int cx1, int cy0, int cy1, int strips, int n_waves)
 {
     const int w = __builtin_amdgcn_readfirstlane(xcd_tile(blockIdx.x, gridDim.x) * 4 + (int)(threadIdx.x >> 6));
     if (w >= n_waves) return;                                // whole waves; no barriers below
     const int64_t boff = (int64_t)blockIdx.y * p.bstride;
-    run_marchN<T, VX, G, C2F, NL>(p, p.u + boff, p.uo + boff, u_pen + boff, u_fin + boff, cx0, cx1, cy0, cy1,
-                                  w % strips, w / strips, (int)(threadIdx.x & 63));
+    run_marchN<T, VX, G, C2F, NL, PF>(p, p.u + boff, p.uo + boff, u_pen + boff, u_fin + boff, cx0, cx1, cy0, cy1,
+                                      w % strips, w / strips, (int)(threadIdx.x & 63));
 }
 
 template <typename T, int VX, int G>
@@ -1216,8 +1259,222 @@ __global__ void __launch_bounds__(256) k_multi_stepN_march(const MultiCore<T> *_
     if (w >= n_waves) return;                                // whole waves; no barriers below
     const TileRef t = waves[w];
     const MultiCore<T> &mc = cores[t.prob];
-    run_marchN<T, VX, G, false, NL>(mc.p, mc.p.u, mc.p.uo, mc.pen, mc.fin, mc.p.skip[0], mc.p.skip[1],
-                                    mc.p.skip[2], mc.p.skip[3], t.tx, t.ty, (int)(threadIdx.x & 63));
+    run_marchN<T, VX, G, false, NL, false>(mc.p, mc.p.u, mc.p.uo, mc.pen, mc.fin, mc.p.skip[0], mc.p.skip[1],
+                                           mc.p.skip[2], mc.p.skip[3], t.tx, t.ty, (int)(threadIdx.x & 63));
+}
+
+// All D frame steps of a 2D pass in one launch (overlapped tiling).  Each
+// block owns a TX x TY tile of the frame (tiles on a fixed grid, listed where
+// they meet everything outside the core shrunk by one) and loads the tile
+// with a halo of D cells into LDS: U^n, U^{n-1} and the four compact layer
+// arrays (Phi_x, Psi_x, Phi_y, Psi_y) of the cells on their bands.  Step j
+// updates the extended region shrunk by j cells, so after D steps the tile
+// holds levels D-1 and D exactly; halo cells are recomputed by every tile
+// that needs them.  U of level j overwrites level j-2 in place (a cell reads
+// its own old value only); the layer arrays are updated through registers
+// between two barriers (a cell reads its neighbours' old values).  The block
+// writes U^{n+D-1} outside the core shrunk by one, U^{n+D} outside the core
+// and the layer arrays of level n+D (to the aux buffer it did not read).
+// Cells beyond a reflecting wall are ghosts holding 0.  Every cell is
+// updated in cell_update's operation order.
+template <typename T, int D, int TX, int TY>
+__global__ void __launch_bounds__(256) k_frame_fused2d(StepArgs<T> p, T *__restrict__ u_pen, T *__restrict__ u_fin,
+                                                       const TileRef *__restrict__ tiles, int ntiles)
+{
+    constexpr int W = TX + 2 * D, HH = TY + 2 * D, E = W * HH;
+    constexpr int K = (E + 255) / 256;                       // extended cells per thread
+    constexpr int MAXM = 255;                                // sigma slots kept in LDS per axis
+    __shared__ T su[2][E];                                   // two U levels, alternating
+    __shared__ T sx[2][E];                                   // Phi_x, Psi_x
+    __shared__ T sy[2][E];                                   // Phi_y, Psi_y
+    __shared__ T ssig[2][MAXM + 1];                          // sigma_x, sigma_y by band slot
+    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+    if (tile >= ntiles) return;                              // whole blocks, before any barrier
+    select_member(p, (int)blockIdx.y);
+    const int64_t boff = (int64_t)blockIdx.y * p.bstride;
+    u_pen += boff;
+    u_fin += boff;
+    const TileRef t = tiles[tile];
+    const int nx = p.nx, ny = p.ny;
+    const int ox = t.tx * TX - D, oy = t.ty * TY - D;        // extended origin, unwrapped
+    const Axis<T> &A0 = p.ax[0];
+    const Axis<T> &A1 = p.ax[1];
+    const int tid = (int)threadIdx.x;
+    // (an axis without a layer has no sigma table: sig is null there)
+    if (A0.M > 0)
+        for (int k = tid; k <= A0.M && k <= MAXM; k += 256) ssig[0][k] = A0.sig[k];
+    if (A1.M > 0)
+        for (int k = tid; k <= A1.M && k <= MAXM; k += 256) ssig[1][k] = A1.sig[k];
+    // grid coordinate of an extended coordinate, or -1 past a reflecting wall
+    auto gco = [](int v, int n, int wall) {
+        if (v >= 0 && v < n) return v;
+        if (wall) return -1;
+        const int m = v % n;
+        return m < 0 ? m + n : m;
+    };
+    // per owned extended cell: grid coordinates (-1: ghost or past the end)
+    int gxs[K], gys[K];
+#pragma unroll
+    for (int i = 0; i < K; ++i) {
+        const int e = tid + 256 * i;
+        gxs[i] = gys[i] = -1;
+        if (e >= E) continue;
+        const int gx = gco(ox + e % W, nx, A0.wall), gy = gco(oy + e / W, ny, A1.wall);
+        if (gx < 0 || gy < 0) continue;
+        gxs[i] = gx;
+        gys[i] = gy;
+    }
+    // load U^n, U^{n-1} and the layer arrays of the extended region
+#pragma unroll
+    for (int i = 0; i < K; ++i) {
+        const int e = tid + 256 * i;
+        if (e >= E) break;
+        const int gx = gxs[i], gy = gys[i];
+        T a = T(0), b = T(0), px = T(0), qx = T(0), py = T(0), qy = T(0);
+        if (gx >= 0) {
+            const int64_t idx = (int64_t)gy * nx + gx;
+            a = p.u[idx];
+            b = p.uo[idx];
+            if (A0.M > 0) {
+                const int j = band_coord(A0, gx);
+                if (j <= A0.M) {
+                    const int64_t c = layer_base<0>(A0.M, nx, ny, gx, gy, 0) + j;
+                    if (j < A0.M) px = A0.phi[c];
+                    if (j > 0) qx = A0.psi[c];
+                }
+            }
+            if (A1.M > 0) {
+                const int j = band_coord(A1, gy);
+                if (j <= A1.M) {
+                    const int64_t c = layer_base<1>(A1.M, nx, ny, gx, gy, 0) + (int64_t)j * nx;
+                    if (j < A1.M) py = A1.phi[c];
+                    if (j > 0) qy = A1.psi[c];
+                }
+            }
+        }
+        su[0][e] = a;
+        su[1][e] = b;
+        sx[0][e] = px;
+        sx[1][e] = qx;
+        sy[0][e] = py;
+        sy[1][e] = qy;
+    }
+    __syncthreads();
+    int cur = 0;                                             // su[cur]: level j-1; su[1-cur]: level j-2
+    for (int lv = 1; lv <= D; ++lv) {
+        T npx[K], nqx[K], npy[K], nqy[K];
+#pragma unroll
+        for (int i = 0; i < K; ++i) {
+            const int e = tid + 256 * i;
+            npx[i] = nqx[i] = npy[i] = nqy[i] = T(0);
+            const int gx = gxs[i], gy = gys[i];
+            if (gx < 0) continue;                            // ghosts stay 0
+            const int ex = e % W, ey = e / W;
+            if (ex < lv || ex >= W - lv || ey < lv || ey >= HH - lv) continue;
+            const T *uc_ = su[cur];
+            const T uc = uc_[e], uxm = uc_[e - 1], uxp = uc_[e + 1], uym = uc_[e - W], uyp = uc_[e + W];
+            const T uold = su[1 - cur][e];
+            T lap = ((uxm - T(2) * uc) + uxp) * p.inv_h2;
+            lap += ((uym - T(2) * uc) + uyp) * p.inv_h2;
+            const T c2 = p.c2 ? p.c2[(int64_t)gy * nx + gx] : p.c2_const;
+            T damp = T(0);
+            if (A0.M > 0) {
+                const int j = band_coord(A0, gx);
+                if (j <= A0.M) {
+                    const bool lg = A0.wall && j == A0.hi, rg = A0.wall && j == A0.hi - 1;
+                    const T s = j <= MAXM ? ssig[0][j] : A0.sig[j];
+                    const T sl = (j > 0 && !lg) ? (j - 1 <= MAXM ? ssig[0][j - 1] : A0.sig[j - 1]) : T(0);
+                    const T phi_l = (j > 0 && !lg) ? sx[0][e - 1] : T(0);
+                    const T psi_r = (j < A0.M && !rg) ? sx[1][e + 1] : T(0);
+                    const T grad = (uxp - uxm) * p.inv_2h;
+                    if (j < A0.M) {
+                        const T phi_c = sx[0][e];
+                        npx[i] = phi_c + p.dt * (T(-0.5) * (sl * phi_l + s * phi_c) - grad);
+                    }
+                    if (j > 0) {
+                        const T psi_c = sx[1][e];
+                        nqx[i] = psi_c + p.dt * (T(-0.5) * (sl * psi_c + s * psi_r) - grad);
+                    }
+                    damp += (s * psi_r - sl * phi_l) * p.inv_h;
+                }
+            }
+            if (A1.M > 0) {
+                const int j = band_coord(A1, gy);
+                if (j <= A1.M) {
+                    const bool lg = A1.wall && j == A1.hi, rg = A1.wall && j == A1.hi - 1;
+                    const T s = j <= MAXM ? ssig[1][j] : A1.sig[j];
+                    const T sl = (j > 0 && !lg) ? (j - 1 <= MAXM ? ssig[1][j - 1] : A1.sig[j - 1]) : T(0);
+                    const T phi_l = (j > 0 && !lg) ? sy[0][e - W] : T(0);
+                    const T psi_r = (j < A1.M && !rg) ? sy[1][e + W] : T(0);
+                    const T grad = (uyp - uym) * p.inv_2h;
+                    if (j < A1.M) {
+                        const T phi_c = sy[0][e];
+                        npy[i] = phi_c + p.dt * (T(-0.5) * (sl * phi_l + s * phi_c) - grad);
+                    }
+                    if (j > 0) {
+                        const T psi_c = sy[1][e];
+                        nqy[i] = psi_c + p.dt * (T(-0.5) * (sl * psi_c + s * psi_r) - grad);
+                    }
+                    damp += (s * psi_r - sl * phi_l) * p.inv_h;
+                }
+            }
+            const T rhs = c2 * lap + damp;
+            su[1 - cur][e] = (T(2) * uc - uold) + p.dt2 * rhs;
+        }
+        __syncthreads();                                     // every old layer value has been read
+#pragma unroll
+        for (int i = 0; i < K; ++i) {
+            const int e = tid + 256 * i;
+            const int gx = gxs[i], gy = gys[i];
+            if (gx < 0) continue;
+            const int ex = e % W, ey = e / W;
+            if (ex < lv || ex >= W - lv || ey < lv || ey >= HH - lv) continue;
+            if (A0.M > 0) {
+                const int j = band_coord(A0, gx);
+                if (j <= A0.M) {
+                    if (j < A0.M) sx[0][e] = npx[i];
+                    if (j > 0) sx[1][e] = nqx[i];
+                }
+            }
+            if (A1.M > 0) {
+                const int j = band_coord(A1, gy);
+                if (j <= A1.M) {
+                    if (j < A1.M) sy[0][e] = npy[i];
+                    if (j > 0) sy[1][e] = nqy[i];
+                }
+            }
+        }
+        __syncthreads();
+        cur = 1 - cur;
+    }
+    // the tile's own cells: su[cur] = level D, su[1-cur] = level D-1
+    for (int e2 = tid; e2 < TX * TY; e2 += 256) {
+        const int tx = e2 % TX, ty = e2 / TX;
+        const int gx = t.tx * TX + tx, gy = t.ty * TY + ty;
+        if (gx >= nx || gy >= ny) continue;
+        const int e = (ty + D) * W + tx + D;
+        const int64_t idx = (int64_t)gy * nx + gx;
+        const bool core0 = gx >= p.skip[0] && gx < p.skip[1] && gy >= p.skip[2] && gy < p.skip[3];
+        const bool core1 = gx > p.skip[0] && gx < p.skip[1] - 1 && gy > p.skip[2] && gy < p.skip[3] - 1;
+        if (!core0) u_fin[idx] = su[cur][e];
+        if (!core1) u_pen[idx] = su[1 - cur][e];
+        if (A0.M > 0) {
+            const int j = band_coord(A0, gx);
+            if (j <= A0.M) {
+                const int64_t c = layer_base<0>(A0.M, nx, ny, gx, gy, 0) + j;
+                if (j < A0.M) A0.phi_o[c] = sx[0][e];
+                if (j > 0) A0.psi_o[c] = sx[1][e];
+            }
+        }
+        if (A1.M > 0) {
+            const int j = band_coord(A1, gy);
+            if (j <= A1.M) {
+                const int64_t c = layer_base<1>(A1.M, nx, ny, gx, gy, 0) + (int64_t)j * nx;
+                if (j < A1.M) A1.phi_o[c] = sy[0][e];
+                if (j > 0) A1.psi_o[c] = sy[1][e];
+            }
+        }
+    }
 }
 
 // One ordinary step over a list of 64 x 4 cell tiles (the frame around the

@@ -17,7 +17,8 @@ pytestmark = pytest.mark.gpu
 
 # (variant, tile_rows)
 VARIANTS = [(dp.VARIANT_CELL, 0), (dp.VARIANT_MARCH, 0), (dp.VARIANT_MARCH1, 0), (dp.VARIANT_TWOSTEP, 0),
-            (dp.VARIANT_THREESTEP, 0), (dp.VARIANT_FOURSTEP, 0), (dp.VARIANT_DEEP, 0), (dp.VARIANT_DEEP, 8 << 20)]
+            (dp.VARIANT_THREESTEP, 0), (dp.VARIANT_FOURSTEP, 0), (dp.VARIANT_DEEP, 0), (dp.VARIANT_DEEP, 8 << 20),
+            (dp.VARIANT_TWOSTEP, 15 << 16), (dp.VARIANT_DEEP, (8 << 20) | (15 << 16))]
 
 
 def _fields(sim, ndim):

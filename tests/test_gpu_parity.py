@@ -241,7 +241,7 @@ def test_set_variant_rejects_bad_shapes():
     w = synthetic.bump2d(32, 4, 0)
     sim = dp.Simulation(w.n, w.lo, w.hi, w.h, w.dt, w.sigma, dtype=torch.float32)
     for variant, tile_rows in [(8, 0), (-1, 0), (dp.VARIANT_TWOSTEP, 1 << 20), (dp.VARIANT_DEEP, 1 << 20),
-                               (dp.VARIANT_DEEP, 9 << 20), (dp.VARIANT_DEEP, 1 << 24), (dp.VARIANT_CELL, -1)]:
+                               (dp.VARIANT_DEEP, 9 << 20), (dp.VARIANT_DEEP, 1 << 25), (dp.VARIANT_CELL, -1)]:
         with pytest.raises(dp.DpmlError) as ei:
             sim.set_variant(variant, tile_rows)
         assert ei.value.code == dp.DPML_EINVAL
@@ -313,18 +313,20 @@ def test_graph_replay_matches_eager(dtype):
 
 
 
-@pytest.mark.parametrize("multi", ["two", "three", "four", "five", "eight"])
-@pytest.mark.parametrize("rows", [0, 5])
+@pytest.mark.parametrize("multi", ["two", "three", "four", "five", "eight", "eight-ahead"])
+@pytest.mark.parametrize("rows", [0, 5, (15 << 16) | 6])
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
 @pytest.mark.parametrize("case", ["bump", "ragged", "onesided", "c2", "batch", "nolayer"])
 def test_twostep_matches_single_steps_and_oracle(dtype, case, rows, multi):
     """Two (three, four) steps per pass over the layer-free core (temporal
     blocking) plus single steps on the frame: bit-identical to single steps,
     and the oracle agrees; step counts that are not a multiple end with a
-    shorter pass and/or a single step.  rows = 5 makes the kernel's tiles end in a
-    remainder of rows."""
+    shorter pass and/or a single step.  rows = 5 makes the kernel's tiles end
+    in a remainder of rows; frame form 15 takes the frame's steps in one
+    fused launch."""
     MULTI, depth = {"two": (dp.VARIANT_TWOSTEP, 0), "three": (dp.VARIANT_THREESTEP, 0),
-                    "four": (dp.VARIANT_FOURSTEP, 0), "five": (dp.VARIANT_DEEP, 5), "eight": (dp.VARIANT_DEEP, 8)}[multi]
+                    "four": (dp.VARIANT_FOURSTEP, 0), "five": (dp.VARIANT_DEEP, 5), "eight": (dp.VARIANT_DEEP, 8),
+                    "eight-ahead": (dp.VARIANT_DEEP, 16 | 8)}[multi]
     rng = np.random.default_rng(17)
     c2 = None
     batch = 1
@@ -382,15 +384,15 @@ def test_twostep_matches_single_steps_and_oracle(dtype, case, rows, multi):
 
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
 @pytest.mark.parametrize("variant", [dp.VARIANT_TWOSTEP, dp.VARIANT_THREESTEP, dp.VARIANT_FOURSTEP,
-                                     (dp.VARIANT_DEEP, 5), (dp.VARIANT_DEEP, 7)])
+                                     (dp.VARIANT_DEEP, 5), (dp.VARIANT_DEEP, 7), (dp.VARIANT_DEEP, 16 | 6)])
 @pytest.mark.parametrize("group,rows", [(1, 3), (4, 7), (4, 4), (2, 1), (1 << 4 | 4, 8), (3 << 4 | 2, 5),
-                                        (5 << 4 | 4, 6)])
+                                        (5 << 4 | 4, 6), (15 << 4 | 2, 6), (15 << 4 | 4, 17)])
 def test_multistep_launch_shapes_bit_identical(dtype, variant, group, rows):
     """Every load-group size and tile height of the multi-step core kernels
-    (2, 3, 4, 5 and 7 levels) (tiles shorter than a group, one-row tiles), and the frame's
-    steps one thread per cell or as wave marches over spans of 1, 3 or 5
-    rows (group's high bits), give the single-step result bit for bit, with
-    a c^2 field and a ragged grid."""
+    (2, 3, 4, 5 and 7 levels, and 6 with the loads issued a group ahead) (tiles shorter than a group, one-row tiles), and the frame's
+    steps one thread per cell, as wave marches over spans of 1, 3 or 5 rows,
+    or fused into one launch (group's high bits), give the single-step
+    result bit for bit, with a c^2 field and a ragged grid."""
     rng = np.random.default_rng(5)
     n, lo, hi = [333, 157], [7, 11], [9, 4]
     sig = [synthetic.sigma_random(n[a], lo[a], hi[a], 2.0, rng) for a in range(2)]
@@ -415,7 +417,7 @@ def test_multistep_launch_shapes_bit_identical(dtype, variant, group, rows):
         assert np.array_equal(x, y)
 
 
-@pytest.mark.parametrize("tile_rows", [0, (3 << 16) | (4 << 12) | 8])
+@pytest.mark.parametrize("tile_rows", [0, (3 << 16) | (4 << 12) | 8, (15 << 16) | (4 << 12) | 8])
 @pytest.mark.parametrize("variant", [dp.VARIANT_TWOSTEP, dp.VARIANT_THREESTEP, dp.VARIANT_FOURSTEP,
                                      (dp.VARIANT_DEEP, 6), (dp.VARIANT_DEEP, 8)])
 def test_twostep_graph_replay_matches_eager(variant, tile_rows):
@@ -482,6 +484,11 @@ def test_launch_timing_counts_and_bytes(dtype):
     t = sim.get_timing()
     assert t["pair"]["launches"] == 3 and t["frame"]["launches"] == 6 + 6 + 3 and "step" not in t
     assert t["pair"]["bytes"] + t["frame"]["bytes"] == 15 * step_bytes
+    sim.set_variant(dp.VARIANT_DEEP, (6 << 20) | (15 << 16))
+    sim.step(14)                                  # two fused passes of six levels and one pair
+    t = sim.get_timing()
+    assert t["pair"]["launches"] == 3 and t["frame"]["launches"] == 3 and "step" not in t
+    assert t["pair"]["bytes"] + t["frame"]["bytes"] == 14 * step_bytes
     sim.step_graph(4)
     sim.sync()
     assert sim.get_timing() == {}
@@ -500,6 +507,8 @@ def test_launch_timing_counts_and_bytes(dtype):
     (2, dp.VARIANT_FOURSTEP, 0, (True, True), [7, 12], [10, 5]),
     (2, dp.VARIANT_FOURSTEP, (2 << 16) | (2 << 12) | 6, (False, True), [7, 12], [10, 1]),
     (2, dp.VARIANT_DEEP, (8 << 20) | (4 << 12) | 12, (True, True), [9, 12], [10, 1]),
+    (2, dp.VARIANT_DEEP, (8 << 20) | (15 << 16) | (4 << 12) | 12, (True, True), [9, 12], [10, 1]),
+    (2, dp.VARIANT_THREESTEP, (15 << 16) | 8, (True, False), [0, 12], [10, 5]),
     (3, dp.VARIANT_TWOSTEP, 0, (True, False, True), [5, 3, 6], [4, 7, 5]),
     (3, dp.VARIANT_TWOSTEP, 0, (True, True, True), [0, 3, 6], [4, 7, 1]),
 ])
