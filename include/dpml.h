@@ -133,8 +133,8 @@ extern "C" {
                                   steps) over a core [lo+D, lo+n+1-D) per axis;
                                   the frame takes D single steps beside it; the
                                   last steps of a run take a shorter pass.  Bit
-                                  24: depths 4 .. 8 issue each group's loads one
-                                  group ahead.  The lower bits as for TWOSTEP,
+                                  24: depths 4 .. 8 take every march index's
+                                  loads from a ring issued four indices ahead.  The lower bits as for TWOSTEP,
                                   and frame form 15 in bits 16-19 (any multi-step
                                   variant) takes all the frame's steps of a pass
                                   in one launch over tiles held in LDS with a

@@ -1035,11 +1035,20 @@ struct MarchNCtx : March2Ctx<T, VX, C2F> {
     template <int DIR>
     __device__ __forceinline__ void one(State &s, int base, int k, int L) const
     {
-        R cur[NL + 1];                                  // level l formed on row k-l+1
-        cur[0] = this->load(this->u, this->wrapy(base + DIR * (k + 1)));
+        const R nn = this->load(this->u, this->wrapy(base + DIR * (k + 1)));
         const R pm = this->load(this->up, this->wrapy(base + DIR * k));
         R cn{};
         if (C2F) cn = this->load(this->c2, this->wrapy(base + DIR * k));
+        advance<DIR>(s, base, k, L, nn, pm, cn);
+    }
+
+    // march index k from its loads: U^n(k+1), U^{n-1}(k), c^2(k)
+    template <int DIR>
+    __device__ __forceinline__ void advance(State &s, int base, int k, int L, const R &nn, const R &pm,
+                                            const R &cn) const
+    {
+        R cur[NL + 1];                                  // level l formed on row k-l+1
+        cur[0] = nn;
 #pragma unroll
         for (int l = 1; l <= NL; ++l) {
             const int r = k - l + 1;
@@ -1126,8 +1135,11 @@ struct MarchNCtx : March2Ctx<T, VX, C2F> {
         for (int i = 0; i < NL - 1; ++i) s.c[i] = cw[G + i];
     }
 
-    // PF: in the steady state the loads of the next group are issued before
-    // the current group's arithmetic (one group of rows in flight ahead)
+    // PF: every march index, prologue and tail included, takes loads issued
+    // kAhead indices earlier (a ring of kAhead rows of each input in
+    // registers) instead of the group scheme
+    static constexpr int kAhead = 4;
+
     template <int G, int DIR, bool PF = false>
     __device__ __forceinline__ void march(int base, int L) const
     {
@@ -1138,26 +1150,38 @@ struct MarchNCtx : March2Ctx<T, VX, C2F> {
         for (int i = 0; i < NL - 1; ++i) s.c[i] = R{};
         s.w[0][0] = this->load(this->u, this->wrapy(base - NL * DIR));
         s.w[0][1] = this->load(this->u, this->wrapy(base - (NL - 1) * DIR));
-        // march indices -(NL-1) .. NL-2: the levels fill up
         int k = -(NL - 1);
-        for (; k <= NL - 2 && k <= L + NL - 2; ++k) one<DIR>(s, base, k, L);
-        // steady state: every level's rows inside the tile (no guards needed)
         if (PF) {
-            if (k + G - 1 <= L - 1) {
-                Loads<G> ld;
-                issue<G, DIR>(ld, base, k);
-                for (;;) {
-                    const Loads<G> cur = ld;
-                    const bool more = k + 2 * G - 1 <= L - 1;
-                    if (more) issue<G, DIR>(ld, base, k + G);
-                    compute<G, DIR>(s, base, k, cur);
-                    k += G;
-                    if (!more) break;
+            const int kend = L + NL - 2;
+            R ru[kAhead], rp[kAhead], rc[kAhead];
+#pragma unroll
+            for (int q = 0; q < kAhead; ++q) {
+                ru[q] = rp[q] = rc[q] = R{};
+                if (k + q > kend) continue;
+                ru[q] = this->load(this->u, this->wrapy(base + DIR * (k + q + 1)));
+                rp[q] = this->load(this->up, this->wrapy(base + DIR * (k + q)));
+                if (C2F) rc[q] = this->load(this->c2, this->wrapy(base + DIR * (k + q)));
+            }
+            for (; k <= kend; k += kAhead) {
+#pragma unroll
+                for (int q = 0; q < kAhead; ++q) {
+                    const int kq = k + q;
+                    if (kq > kend) break;
+                    const R nn = ru[q], pm = rp[q], cn = rc[q];
+                    if (kq + kAhead <= kend) {
+                        ru[q] = this->load(this->u, this->wrapy(base + DIR * (kq + kAhead + 1)));
+                        rp[q] = this->load(this->up, this->wrapy(base + DIR * (kq + kAhead)));
+                        if (C2F) rc[q] = this->load(this->c2, this->wrapy(base + DIR * (kq + kAhead)));
+                    }
+                    advance<DIR>(s, base, kq, L, nn, pm, cn);
                 }
             }
-        } else {
-            for (; k + G - 1 <= L - 1; k += G) group<G, DIR>(s, base, k);
+            return;
         }
+        // march indices -(NL-1) .. NL-2: the levels fill up
+        for (; k <= NL - 2 && k <= L + NL - 2; ++k) one<DIR>(s, base, k, L);
+        // steady state: every level's rows inside the tile (no guards needed)
+        for (; k + G - 1 <= L - 1; k += G) group<G, DIR>(s, base, k);
         for (; k <= L + NL - 2; ++k) one<DIR>(s, base, k, L);
     }
 };
