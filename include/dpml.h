@@ -399,14 +399,18 @@ const char *dpml_multi_last_error(const dpml_multi_t *h);
  * the launch count, the summed launch durations and the summed algorithmic
  * bytes of those launches (the byte model of the roofline: 3 words per cell
  * per step, 4 words per layer axis-cell per step, 1 word per cell per step
- * of a c^2 field; a two-step core launch counts its cells twice).  Launches
+ * of a c^2 field; the core launch of a multi-step pass of D levels counts
+ * its cells D times, a fused frame launch its cells D times).  Launches
  * inside a HIP-graph capture are not timed; at most 4096 launches are kept
- * between two reads.  The events slightly delay back-to-back launches, so
- * throughput should be timed with timing off. */
+ * between two reads.  Frame launches run on a second stream beside the core
+ * launch, so their durations include time shared with it.  The events
+ * slightly delay back-to-back launches, so throughput should be timed with
+ * timing off. */
 #define DPML_KERNEL_STEP 0   /* one step over all cells (any variant)                */
-#define DPML_KERNEL_PAIR 1   /* two-step core kernel with the frame's first step     */
-#define DPML_KERNEL_FRAME 2  /* the frame's second step (two-step variant); the
-                                layer slabs of a split 3D marching step             */
+#define DPML_KERNEL_PAIR 1   /* the core kernel of a multi-step pass (any depth)     */
+#define DPML_KERNEL_FRAME 2  /* the frame's steps of a multi-step pass (one launch
+                                per step, or one fused launch per pass); the layer
+                                slabs of a split 3D marching step                   */
 #define DPML_KERNEL_CORE 3   /* the marching box of a split 3D marching step        */
 
 typedef struct dpml_timing {

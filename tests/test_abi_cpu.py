@@ -36,6 +36,58 @@ def test_header_parses_as_c():
     assert r.returncode == 0, r.stderr
 
 
+def _defines():
+    src = open(os.path.join(ROOT, "include", "dpml.h")).read()
+    return {m.group(1): int(m.group(2)) for m in
+            re.finditer(r"#define (DPML_[A-Z0-9_]+) \(?(-?\d+)\)?", src)}
+
+
+def test_binding_constants_match_the_header():
+    d = _defines()
+    assert len(d) >= 20
+    for name, value in d.items():
+        py = name[len("DPML_"):] if name.startswith(("DPML_VARIANT_", "DPML_KERNEL_", "DPML_FIELD_")) else name
+        assert getattr(dp, py) == value, name
+    for a in range(3):
+        assert dp.FIELD_PHI(a) == 2 + 2 * a and dp.FIELD_PSI(a) == 3 + 2 * a
+
+
+def test_tuner_candidates_are_valid_launch_shapes():
+    """Every shape the tuner may apply lies inside the ranges dpml_set_variant
+    and dpml_multi_set_variant accept (depth 2..8 for DEEP, load group 1, 2
+    or 4, frame form 0..15, rows within the kernels' limits)."""
+    from paper_1804_01390_amd import autotune
+    multi_variants = (dp.VARIANT_TWOSTEP, dp.VARIANT_THREESTEP, dp.VARIANT_FOURSTEP, dp.VARIANT_DEEP)
+    for variant, tr in autotune.CANDIDATES_2D + autotune.CANDIDATES_3D:
+        assert dp.VARIANT_AUTO <= variant <= dp.VARIANT_DEEP
+        assert 0 <= tr < (1 << (25 if variant == dp.VARIANT_DEEP else 20))
+        if variant == dp.VARIANT_DEEP:
+            assert ((tr >> 20) & 0xF) in (0, 2, 3, 4, 5, 6, 7, 8)
+    for variant, tr in autotune.CANDIDATES_2D:
+        if variant in multi_variants:
+            assert ((tr >> 12) & 0xF) in (0, 1, 2, 4) and 0 < (tr & 0xFFF) <= 4095
+    for variant, tr in autotune.CANDIDATES_3D:
+        if variant in multi_variants:          # 3D passes: rows per wave in bits 12-19, planes per chunk below
+            assert ((tr >> 12) & 0xFF) in (4, 8, 16) and 0 < (tr & 0xFFF) <= 4095
+    for variant, rows, group in autotune.CANDIDATES_MULTI:
+        assert variant in (dp.VARIANT_MARCH,) + multi_variants
+        assert group in (1, 2, 4)
+        if variant == dp.VARIANT_DEEP:
+            assert ((rows >> 20) & 0xF) in (2, 3, 4, 5, 6, 7, 8) and 1 <= (rows & 0xFFFFF) <= 4096
+        else:
+            assert (4 if variant == dp.VARIANT_MARCH else 1) <= rows <= 4096
+
+
+def test_workspace_holds_the_multistep_buffers():
+    """2D handles carry U^n, U^{n-1} and eight more U arrays (passes of up to
+    eight levels write U^{n+1} .. U^{n+8}); 3D handles two more."""
+    lib = dp.load_library()
+    for ndim, n, esize, ubufs in [(2, [100, 80], 4, 10), (3, [20, 18, 16], 8, 4)]:
+        g = dp._grid(n, [0] * ndim, [0] * ndim, dp.DPML_F32 if esize == 4 else dp.DPML_F64)
+        cells = int(np.prod(n))
+        assert lib.dpml_workspace_bytes(ctypes.byref(g), 0) >= ubufs * cells * esize
+
+
 def _create(n, lo, hi, h=1.0, dt=0.5, sigma=None, c2=(1.0,), dtype=dp.DPML_F64, ws_bytes=None,
             ws_ptr=4096):
     lib = dp.load_library()
