@@ -30,6 +30,18 @@ DPML_F32, DPML_F64 = 0, 1
 FIELD_U, FIELD_UPREV = 0, 1
 
 
+def pass_shape(rows: int = 0, group: int = 0, frame: int = 0, depth: int = 0, ahead: bool = False) -> int:
+    """The tile_rows value of a 2D multi-step launch shape: rows per core wave
+    (0: 8), rows whose loads a wave issues together (1, 2 or 4; 0: 2), the
+    frame form (0 one thread per cell, 1-14 wave marches over spans of that
+    many rows, 15 all frame steps of a pass in one launch), the levels per
+    pass of VARIANT_DEEP (2-8; 0: 6) and loads issued ahead in cores of four
+    or more levels."""
+    if not (0 <= rows < 4096 and group in (0, 1, 2, 4) and 0 <= frame <= 15 and depth in (0, 2, 3, 4, 5, 6, 7, 8)):
+        raise ValueError("launch shape out of range")
+    return rows | (group << 12) | (frame << 16) | (depth << 20) | (int(bool(ahead)) << 24)
+
+
 def FIELD_PHI(a: int) -> int:
     return 2 + 2 * a
 
@@ -235,6 +247,9 @@ class Simulation:
 
     # -- API ----------------------------------------------------------------
     def set_variant(self, variant: int, tile_rows: int = 0):
+        """Kernel variant (VARIANT_*) and its launch shape (0: defaults; for
+        the multi-step variants see ``pass_shape``).  Results do not depend on
+        the choice; ``autotune.tune`` picks the fastest."""
         self._check(self.lib.dpml_set_variant(self.handle, variant, tile_rows))
 
     def set_state(self, U0, V0=None):

@@ -78,6 +78,15 @@ def test_tuner_candidates_are_valid_launch_shapes():
             assert (4 if variant == dp.VARIANT_MARCH else 1) <= rows <= 4096
 
 
+def test_pass_shape_packs_the_documented_bits():
+    assert dp.pass_shape() == 0
+    assert dp.pass_shape(rows=32, group=4, depth=8, ahead=True) == (1 << 24) | (8 << 20) | (4 << 12) | 32
+    assert dp.pass_shape(rows=6, frame=15, depth=6) == (6 << 20) | (15 << 16) | 6
+    for bad in (dict(rows=4096), dict(group=3), dict(frame=16), dict(depth=1), dict(depth=9)):
+        with pytest.raises(ValueError):
+            dp.pass_shape(**bad)
+
+
 def test_workspace_holds_the_multistep_buffers():
     """2D handles carry U^n, U^{n-1} and eight more U arrays (passes of up to
     eight levels write U^{n+1} .. U^{n+8}); 3D handles two more."""
