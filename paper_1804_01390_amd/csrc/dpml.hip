@@ -1066,7 +1066,7 @@ int launch_multistep3d(dpml *H)
     // tile_rows: planes per chunk in the low 12 bits (0: 32), rows per wave
     // in the bits above (4, 8 or 16; 0: 8)
     const int chunk = (H->tile_rows & 0xFFF) > 0 ? (H->tile_rows & 0xFFF) : 32;
-    const int ryb = H->tile_rows >> 12;
+    const int ryb = (H->tile_rows >> 12) & 0xFF;
     const int ry = (ryb == 4 || ryb == 16) ? ryb : 8;
     HIP_TRY(H, hipEventRecord(H->ev_fork, H->stream));
     HIP_TRY(H, hipStreamWaitEvent(H->side, H->ev_fork, 0));

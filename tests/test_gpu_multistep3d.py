@@ -165,3 +165,32 @@ def test_3d_twostep_graph_replay_matches_eager():
         assert np.array_equal(a.field(dp.FIELD_PHI(1)).cpu().numpy(), b.field(dp.FIELD_PHI(1)).cpu().numpy()), rep
     a.close()
     b.close()
+
+
+@pytest.mark.parametrize("variant,tile_rows", [(dp.VARIANT_THREESTEP, 0), (dp.VARIANT_FOURSTEP, (8 << 12) | 32),
+                                               (dp.VARIANT_DEEP, (8 << 20) | (16 << 12) | 16),
+                                               (dp.VARIANT_DEEP, (1 << 24) | (15 << 16))])
+def test_3d_deeper_variants_take_two_step_passes(variant, tile_rows):
+    """On 3D grids the three-, four-step and DEEP variants take the two-step
+    passes (bits that only 2D passes read are ignored): same fields as
+    TWOSTEP with the same 3D shape and as single steps, and one core launch
+    per two steps."""
+    rng = np.random.default_rng(23)
+    n, lo, hi, sig, U0 = _case("ragged", rng)
+    shape3d = tile_rows & 0xFFFFF if variant != dp.VARIANT_DEEP else (tile_rows & 0xFF000) | (tile_rows & 0xFFF)
+    outs = []
+    for v, tr in ((variant, tile_rows), (dp.VARIANT_TWOSTEP, shape3d), (dp.VARIANT_MARCH, 0)):
+        sim = dp.Simulation(n, lo, hi, 1.0, 0.4, sig, dtype=torch.float32)
+        sim.set_variant(v, tr)
+        sim.set_state(torch.from_numpy(U0))
+        sim.set_timing(True)
+        sim.step(10)
+        sim.sync()
+        t = sim.get_timing()
+        if v == variant:
+            assert t["pair"]["launches"] == 5
+        outs.append(_fields(sim, lo, hi))
+        sim.close()
+    for o in outs[1:]:
+        for x, y in zip(outs[0], o):
+            assert np.array_equal(x, y)
