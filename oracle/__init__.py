@@ -12,7 +12,12 @@ arrays in and out.  Arrays are numpy FP64 with shape ``(N2, N1, N0)`` for 3D,
 the LAST (fastest) numpy axis.
 
 Parity status of each function (see the pins in ``tests/test_oracle_pins.py``):
-  start, step, run       -- pinned (exact Fourier modes, Sec. 1.1.1 / Eq.
+  start                  -- pinned: both branches.  Zero velocity: exact
+                            Fourier modes at rest (U^{-1} = cos(theta) U^0).
+                            Given velocity V^0: the exact leapfrog sine/cosine
+                            mode a cos(n theta) + (dt v / sin theta) sin(n theta)
+                            (Sec. 1.1.1, Eq. DiscreteDispersion)
+  step, run              -- pinned (exact Fourier modes, Sec. 1.1.1 / Eq.
                             DiscreteDispersion; exact layer modes of Thm. 1;
                             energy conservation; reflection against free space,
                             Figs. 2/3; 1-D light-cone Green's function)
@@ -81,8 +86,6 @@ def _load():
         lib.orc_start.restype = None
         lib.orc_step.argtypes = [gp, _DP, _DP, _DP3, _DP3, _DP, _DP3, _DP3]
         lib.orc_step.restype = None
-        lib.orc_rhs_u_all.argtypes = [gp, _DP, _DP3, _DP3, _DP]
-        lib.orc_rhs_u_all.restype = None
         lib.orc_run.argtypes = [gp, _DP, _DP, _DP3, _DP3, ctypes.c_int64, ctypes.c_int64,
                                 ctypes.c_int64, _I64P, _DP,
                                 ctypes.c_int64, _I64P, _DP, ctypes.c_int64]
@@ -204,21 +207,6 @@ def step(g: Grid, s: State) -> State:
     lib.orc_step(ctypes.byref(gs), _dp(_f64(s.U)), _dp(_f64(s.Uprev)), _aux3(Phi), _aux3(Psi),
                  _dp(Un), _aux3(PhiN), _aux3(PsiN))
     return State(Un, s.U.copy(), PhiN, PsiN, s.n + 1)
-
-
-def rhs_u(g: Grid, U, Phi=None, Psi=None) -> np.ndarray:
-    """A(U, Phi, Psi), the right-hand side of Eq. (DiscretePML a)."""
-    lib = _load()
-    gs, keep = g._struct()
-    U = _f64(U)
-    out = np.empty_like(U)
-    if Phi is None:
-        Phi = [np.zeros_like(U) for _ in range(g.ndim)]
-        Psi = [np.zeros_like(U) for _ in range(g.ndim)]
-    Phi = [_f64(p) for p in Phi]
-    Psi = [_f64(p) for p in Psi]
-    lib.orc_rhs_u_all(ctypes.byref(gs), _dp(U), _aux3(Phi), _aux3(Psi), _dp(out))
-    return out
 
 
 def run(g: Grid, s: State, nsteps: int, sources=None, wavelets=None,

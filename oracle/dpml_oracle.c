@@ -183,16 +183,6 @@ static double orc_rhs_psi(const orc_grid *g, const double *U, const double *Psi_
            - (orc_at(U, cp) - orc_at(U, cm)) / (2.0 * g->h);
 }
 
-/* Evaluate A(U, Phi, Psi) of Eq. (DiscretePML a) on the whole grid. */
-void orc_rhs_u_all(const orc_grid *g, const double *U,
-                   double *const Phi[3], double *const Psi[3], double *out)
-{
-    int64_t n = orc_ncells(g);
-    #pragma omp parallel for schedule(static)
-    for (int64_t c = 0; c < n; ++c)
-        out[c] = orc_rhs_u(g, U, Phi, Psi, c);
-}
-
 /* Start: U^{-1} = U^0 - dt V^0 + dt^2/2 A(U^0, 0, 0).  V0 may be NULL. */
 void orc_start(const orc_grid *g, const double *U0, const double *V0, double *Um1)
 {

@@ -125,6 +125,38 @@ def test_fourier_mode_exact(oracle_lib, ndim, dt):
     assert np.max(np.abs(Uw - math.cos(steps * theta) * U0)) < 5e-13
 
 
+@pytest.mark.parametrize("ndim,dt,amp,vel", [(1, 0.9, 1.0, 0.7), (1, 0.6, 0.0, 1.0),
+                                             (2, 0.5, 0.8, -1.3), (2, 0.5, 0.0, 0.5),
+                                             (3, 0.4, 1.0, 0.9), (3, 0.4, 0.0, -2.0)])
+def test_fourier_mode_with_initial_velocity_exact(oracle_lib, ndim, dt, amp, vel):
+    """The start with a given velocity.  With sigma = 0 the leapfrog
+    recurrence U^{n+1} = (2 - 4 sin^2(theta/2)) U^n - U^{n-1} on a periodic
+    Fourier mode (Sec. 1.1.1, Eq. DiscreteDispersion: sin(theta/2) =
+    (c dt/h) sqrt(sum sin^2(k h/2))) has the general solution
+    A cos(n theta) + B sin(n theta).  U^0 = a cos(k.x) gives A = a; a start
+    U^{-1} = U^0 - dt V^0 + dt^2/2 A(U^0) with V^0 = v cos(k.x) gives
+    U^{-1} = a cos(theta) - dt v, hence B = dt v / sin(theta).  A flipped sign
+    or a dropped dt on the velocity term changes B and fails this."""
+    oracle = oracle_lib
+    N = [24, 20, 16][:ndim]
+    m = [3, 2, 5][:ndim]
+    k = [2 * math.pi * m[a] / N[a] for a in range(ndim)]
+    X = np.meshgrid(*[np.arange(n) for n in reversed(N)], indexing="ij")[::-1]
+    mode = np.cos(sum(k[a] * X[a] for a in range(ndim)))
+    g = oracle.Grid(N, 1.0, dt, [np.zeros(n) for n in N])
+    theta = cf.leapfrog_theta(k, 1.0, dt)
+    B = dt * vel / math.sin(theta)
+    s = oracle.start(g, amp * mode, vel * mode)
+    # level -1 of the closed form: a cos(theta) - B sin(theta)
+    assert np.max(np.abs(s.Uprev - (amp * math.cos(theta) - B * math.sin(theta)) * mode)) < 1e-14
+    steps = 300
+    fin, _ = oracle.run(g, s, steps)
+    want = (amp * math.cos(steps * theta) + B * math.sin(steps * theta)) * mode
+    assert np.max(np.abs(fin.U - want)) < 5e-13
+    want_prev = (amp * math.cos((steps - 1) * theta) + B * math.sin((steps - 1) * theta)) * mode
+    assert np.max(np.abs(fin.Uprev - want_prev)) < 5e-13
+
+
 def test_fourier_mode_exact_with_constant_c2(oracle_lib):
     """c^2 multiplies the Laplacian: a constant c0^2 rescales the phase
     advance to sin(theta/2) = (c0 dt/h) sqrt(sum sin^2(k h/2))."""
