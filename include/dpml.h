@@ -427,6 +427,32 @@ int dpml_set_timing(dpml_t *h, int32_t enable);
  * clear the records.  Returns DPML_EHIP if an event query fails. */
 int dpml_get_timing(dpml_t *h, dpml_timing_t *out);
 
+/* ---- streaming bandwidth probe (measurement) -------------------------------
+ * Not part of the paper: a plain streaming kernel over one device buffer,
+ * timed with HIP events, that states the HBM bandwidth the stencil kernels
+ * can reach and calibrates the hardware traffic counters against a kernel
+ * of known size.
+ *   kind    DPML_PROBE_READ (read `bytes` of src; one 16-byte XOR fold per
+ *           block is written to dst, which must hold DPML_PROBE_MAX_BLOCKS
+ *           x 16 bytes), DPML_PROBE_WRITE (write `bytes` of dst; src unused)
+ *           or DPML_PROBE_COPY (dst = src, `bytes` each way), optionally or-ed
+ *           with DPML_PROBE_NONTEMPORAL (non-temporal loads and stores).
+ *   bytes   a positive multiple of 16; src and dst 16-byte aligned device
+ *           pointers (borrowed for the call).
+ *   blocks_per_cu  256-thread blocks per compute unit (1 .. 64); the grid
+ *           never exceeds one block per 256 elements.
+ *   reps    launches timed back to back on `stream` (hipStream_t).
+ * Waits for the launches; *ms_per_rep = elapsed milliseconds / reps.
+ * DPML_EINVAL for bad arguments, DPML_EHIP on a runtime failure. */
+#define DPML_PROBE_READ 0
+#define DPML_PROBE_WRITE 1
+#define DPML_PROBE_COPY 2
+#define DPML_PROBE_NONTEMPORAL 4
+#define DPML_PROBE_MAX_BLOCKS 16384
+
+int dpml_bandwidth_probe(int32_t kind, void *dst, const void *src, size_t bytes, int32_t blocks_per_cu,
+                         int32_t reps, void *stream, double *ms_per_rep);
+
 /* Release the handle (not the caller's workspace or buffers). */
 void dpml_destroy(dpml_t *h);
 

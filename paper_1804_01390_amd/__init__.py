@@ -60,8 +60,10 @@ EXPORTED = [
     "dpml_multi_field", "dpml_multi_tiles", "dpml_multi_set_variant", "dpml_multi_sync", "dpml_multi_destroy",
     "dpml_multi_last_error",
     "dpml_rk4_workspace_bytes", "dpml_rk4_set_state", "dpml_rk4_step", "dpml_rk4_field",
-    "dpml_rk4_time_index", "dpml_set_timing", "dpml_get_timing",
+    "dpml_rk4_time_index", "dpml_set_timing", "dpml_get_timing", "dpml_bandwidth_probe",
 ]
+
+PROBE_READ, PROBE_WRITE, PROBE_COPY, PROBE_NONTEMPORAL, PROBE_MAX_BLOCKS = 0, 1, 2, 4, 16384
 
 KERNEL_STEP, KERNEL_PAIR, KERNEL_FRAME, KERNEL_CORE = 0, 1, 2, 3
 KERNEL_NAMES = {KERNEL_STEP: "step", KERNEL_PAIR: "pair", KERNEL_FRAME: "frame", KERNEL_CORE: "core"}
@@ -141,6 +143,8 @@ def load_library():
         "dpml_rk4_time_index": (ctypes.c_int64, [_VP]),
         "dpml_set_timing": (ctypes.c_int, [_VP, ctypes.c_int32]),
         "dpml_get_timing": (ctypes.c_int, [_VP, ctypes.POINTER(TimingT)]),
+        "dpml_bandwidth_probe": (ctypes.c_int, [ctypes.c_int32, _VP, _VP, ctypes.c_size_t, ctypes.c_int32,
+                                                ctypes.c_int32, _VP, _DP]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -167,6 +171,28 @@ def _grid(n, lo, hi, dtype_code, batch: int = 1, walls=()) -> GridT:
 def workspace_bytes(n, lo, hi, dtype_code: int, c2_field: bool, batch: int = 1) -> int:
     return int(load_library().dpml_workspace_bytes(ctypes.byref(_grid(n, lo, hi, dtype_code, batch)),
                                                    1 if c2_field else 0))
+
+
+def bandwidth_probe(kind: int, nbytes: int, reps: int = 10, blocks_per_cu: int = 8, buffers=None) -> float:
+    """Time the library's streaming probe (PROBE_READ / PROBE_WRITE /
+    PROBE_COPY, optionally | PROBE_NONTEMPORAL) over ``nbytes`` bytes on the
+    current stream; returns milliseconds per launch.  ``buffers`` = (dst,
+    src) device tensors to reuse, else they are allocated here."""
+    import torch
+    lib = load_library()
+    if buffers is None:
+        src = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+        src.random_(0, 255)
+        dst = torch.empty(max(nbytes, PROBE_MAX_BLOCKS * 16), dtype=torch.uint8, device="cuda")
+    else:
+        dst, src = buffers
+    ms = ctypes.c_double(0.0)
+    rc = lib.dpml_bandwidth_probe(int(kind), dst.data_ptr(), src.data_ptr(), int(nbytes), int(blocks_per_cu),
+                                  int(reps), ctypes.c_void_p(torch.cuda.current_stream().cuda_stream),
+                                  ctypes.byref(ms))
+    if rc != DPML_OK:
+        raise DpmlError(rc, lib.dpml_strerror(rc).decode())
+    return ms.value
 
 
 class Simulation:

@@ -20,486 +20,20 @@
 #include <string>
 #include <vector>
 
-namespace {
+#include "dpml_host.hpp"
 
-thread_local std::string g_create_error;
-
-constexpr size_t kAlign = 256;
-
-size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
-
-struct Layout {
-    int ndim = 0;
-    int dtype = 0;
-    size_t esize = 0;
-    int64_t N[3] = {1, 1, 1};
-    int64_t n[3] = {1, 1, 1};
-    int32_t lo[3] = {0, 0, 0};
-    int32_t hi[3] = {0, 0, 0};
-    int32_t M[3] = {0, 0, 0};
-    int32_t wall[3] = {0, 0, 0};        // reflecting walls instead of periodic wrap
-    int64_t ncell = 0;                  // cells of one problem
-    int64_t batch = 1;                  // independent problems sharing c^2 and sigma
-    int64_t aux_elems[3] = {0, 0, 0};   // elements of one compact aux array (one problem)
-    // byte offsets into the workspace
-    int n_ubuf = 2;                     // U buffers: U^n, U^{n-1} (+ spares of the multi-step variants)
-    size_t off_u[10] = {};
-    size_t off_c2 = 0;
-    size_t off_phi[3][2] = {{0, 0}, {0, 0}, {0, 0}};
-    size_t off_psi[3][2] = {{0, 0}, {0, 0}, {0, 0}};
-    size_t off_sig[3] = {0, 0, 0};
-    size_t off_flags = 0;
-    size_t total = 0;
-};
-
-constexpr int kFlagBlocks = 1024;
-
-// Deepest multi-step pass (levels per pass) of the 2D variants.
-constexpr int kMaxLevels = 8;
-
-// Levels per pass a variant asks for: TWOSTEP 2, THREESTEP 3, FOURSTEP 4,
-// DEEP bits 20-23 of tile_rows (0: 6); 1 for the single-step variants.
-int pass_depth(int variant, int tile_rows)
-{
-    switch (variant) {
-    case DPML_VARIANT_TWOSTEP: return 2;
-    case DPML_VARIANT_THREESTEP: return 3;
-    case DPML_VARIANT_FOURSTEP: return 4;
-    case DPML_VARIANT_DEEP: return ((tile_rows >> 20) & 0xF) ? ((tile_rows >> 20) & 0xF) : 6;
-    default: return 1;
-    }
-}
-
-template <typename V, int A, int B>
-using Table2 = std::array<std::array<V, B>, A>;
-
-template <typename V, int A, int B>
-Table2<V, A, B> filled(V v)
-{
-    Table2<V, A, B> t;
-    for (auto &r : t) r.fill(v);
-    return t;
-}
-
-// U buffers of a single-grid handle: 2D grids carry kMaxLevels spares for
-// the multi-step variants (which write U^{n+1} .. U^{n+levels} beside U^n
-// and U^{n-1}); 3D grids two (U^{n+1}, U^{n+2} of the two-step pass).
-int handle_ubufs(const dpml_grid_t *g) { return g && g->ndim == 2 ? 2 + kMaxLevels : 4; }
-
-// Validate the grid and compute the workspace layout.  Returns "" or an error.
-std::string make_layout(const dpml_grid_t *g, bool c2_field, Layout &L, int n_ubuf)
-{
-    if (!g) return "grid is NULL";
-    if (g->ndim != 2 && g->ndim != 3) return "ndim must be 2 or 3";
-    if (g->dtype != DPML_F32 && g->dtype != DPML_F64) return "dtype must be DPML_F32 or DPML_F64";
-    L.ndim = g->ndim;
-    L.dtype = g->dtype;
-    L.esize = g->dtype == DPML_F32 ? 4 : 8;
-    L.ncell = 1;
-    for (int a = 0; a < 3; ++a) {
-        if (a < g->ndim) {
-            if (g->n[a] < 1 || g->lo[a] < 0 || g->hi[a] < 0) return "extents must be n >= 1, lo, hi >= 0";
-            L.n[a] = g->n[a];
-            L.lo[a] = g->lo[a];
-            L.hi[a] = g->hi[a];
-            L.N[a] = g->n[a] + g->lo[a] + g->hi[a];
-            if (L.N[a] < 3) return "each axis needs at least 3 cells";
-            if (L.N[a] > (int64_t)1 << 30) return "axis too long";
-            L.M[a] = g->lo[a] + g->hi[a];
-            if (g->walls[a] != 0 && g->walls[a] != 1) return "walls[a] must be 0 or 1";
-            L.wall[a] = g->walls[a];
-        }
-        L.ncell *= L.N[a];
-    }
-    L.batch = g->batch > 1 ? g->batch : 1;
-    if (L.batch > 65535) return "batch too large";
-    if (L.ncell * L.batch > ((int64_t)1 << 40)) return "grid too large";
-    size_t off = 0;
-    const size_t ubytes = align_up((size_t)(L.ncell * L.batch) * L.esize);
-    L.n_ubuf = n_ubuf;
-    for (int k = 0; k < n_ubuf; ++k) { L.off_u[k] = off; off += ubytes; }
-    if (c2_field) { L.off_c2 = off; off += align_up((size_t)L.ncell * L.esize); }
-    for (int a = 0; a < L.ndim; ++a) {
-        if (L.M[a] == 0) continue;
-        L.aux_elems[a] = L.ncell / L.N[a] * (L.M[a] + 1);
-        const size_t ab = align_up((size_t)(L.aux_elems[a] * L.batch) * L.esize);
-        for (int k = 0; k < 2; ++k) {
-            L.off_phi[a][k] = off; off += ab;
-            L.off_psi[a][k] = off; off += ab;
-        }
-        L.off_sig[a] = off; off += align_up((size_t)(L.M[a] + 1) * L.esize);
-    }
-    L.off_flags = off; off += align_up(kFlagBlocks * sizeof(int32_t));
-    L.total = off;
-    return "";
-}
-
-using TileRefVec = std::vector<dpmlk::TileRef>;
-
-}  // namespace
-
-struct dpml {
-    Layout L;
-    char *ws = nullptr;
-    hipStream_t stream = nullptr;
-    double h = 1, dt = 1;
-    double c2_const = 1;     // used when c2 is not a field
-    bool c2_field = false;
-    void *u_now = nullptr, *u_old = nullptr;
-    int cur = 0;             // aux buffer index holding time level n
-    int64_t n = 0;
-    bool state_set = false;
-    int variant = DPML_VARIANT_AUTO;
-    int tile_rows = 0;
-    // frame tiles of the multi-step variants: [levels - 2][s] covers
-    // everything outside the core shrunk by s cells (-1: not built yet)
-    dpmlk::TileRef *d_frame[kMaxLevels - 1][kMaxLevels] = {};
-    Table2<int64_t, kMaxLevels - 1, kMaxLevels> n_frame = filled<int64_t, kMaxLevels - 1, kMaxLevels>(-1);
-    // the same frames as spans for the marching frame kernel (span rows fspan_rows)
-    dpmlk::Span2 *d_fspan[kMaxLevels - 1][kMaxLevels] = {};
-    Table2<int64_t, kMaxLevels - 1, kMaxLevels> n_fspan = filled<int64_t, kMaxLevels - 1, kMaxLevels>(-1);
-    // tiles of the fused frame launch per depth ([levels - 2]; -1: not built yet)
-    dpmlk::TileRef *d_ffused[kMaxLevels - 1] = {};
-    int64_t n_ffused[kMaxLevels - 1] = {-1, -1, -1, -1, -1, -1, -1};
-    int fspan_rows = 0;
-    // the frame's steps run on a second stream beside the core kernel
-    hipStream_t side = nullptr;
-    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
-    dpmlk::TileRef *d_adj_frame = nullptr;  // 2D adjoint: tiles outside the marching core
-    int64_t n_adj_frame = -1;               // -1: not built yet
-    // sources
-    int64_t ns = 0, nt_src = 0;
-    int64_t *d_src_cells = nullptr, *d_src_order = nullptr;
-    std::vector<int64_t> src_sorted;      // host copy of d_src_cells
-    const void *wavelets = nullptr;
-    // receivers
-    int64_t nr = 0, nt_rec = 0;
-    int64_t *d_rec_cells = nullptr;
-    int64_t *d_rec_sorted = nullptr, *d_rec_order = nullptr;
-    void *traces = nullptr;
-    bool recording = true;   // off while the adjoint recomputes segments
-    // checkpointed forward / adjoint
-    char *adj_ws = nullptr;
-    size_t adj_bytes = 0;
-    int64_t adj_nsteps = 0, adj_every = 0;
-    bool adj_ready = false;
-    // cached HIP graph of a run of steps (no sources/receivers/planes)
-    hipStream_t cap = nullptr;
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t exec = nullptr;
-    int64_t graph_steps = -1;
-    int graph_cur = -1;
-    void *graph_unow = nullptr, *graph_uold = nullptr;
-    int graph_variant = -1, graph_rows = -1;
-    void *graph_end_unow = nullptr, *graph_end_uold = nullptr;
-    int graph_end_cur = 0;
-    // RK4 integrator state (caller-owned workspace)
-    char *rk_ws = nullptr;
-    int rk_role[4] = {0, 1, 2, 3};   // buffer sets holding Y0, YS0, YS1, S
-    int64_t rk_n = 0;
-    bool rk_set = false;
-    // plane recorder
-    int plane_axis = -1;
-    int64_t plane_index = 0, nt_plane = 0;
-    void *planes = nullptr;
-    // optional per-launch timing of the step kernels (event pairs on `stream`)
-    struct Timed {
-        int kind;
-        hipEvent_t e0, e1;
-        double bytes;
-    };
-    bool timing = false;
-    std::vector<Timed> timed;
-    std::vector<hipEvent_t> events;      // pool, reused after each dpml_get_timing
-    size_t events_used = 0;
-    std::string err;
-
-    void *at(size_t off) { return ws + off; }
-    int fail(int code, const std::string &msg) { err = msg; return code; }
-};
+using namespace dpmlh;
 
 namespace {
 
-int hip_fail(dpml *h, hipError_t e, const char *what)
-{
-    std::string m = std::string(what) + ": " + hipGetErrorString(e);
-    if (h) h->err = m; else g_create_error = m;
-    return DPML_EHIP;
-}
 
-#define HIP_TRY(h, call)                                   \
-    do {                                                   \
-        hipError_t e_ = (call);                            \
-        if (e_ != hipSuccess) return hip_fail(h, e_, #call); \
-    } while (0)
 
-constexpr size_t kMaxTimed = 4096;    // launches recorded between two dpml_get_timing calls
 
-// Layer axis-cells per member: M_a cells on every line along each axis a.
-double aux_cells(const Layout &L)
-{
-    double aux = 0;
-    for (int a = 0; a < L.ndim; ++a) aux += (double)L.M[a] * (double)(L.ncell / L.N[a]);
-    return aux;
-}
 
-// Algorithmic bytes of one step over `cells` cells and `aux` layer
-// axis-cells per member: 3 words per cell, 4 words per layer axis-cell and 1
-// word per cell of a c^2 field.
-double step_bytes(const dpml *H, double cells, double aux)
-{
-    const Layout &L = H->L;
-    const double words = (3.0 * cells + 4.0 * aux) * (double)L.batch + (H->c2_field ? cells : 0.0);
-    return words * (double)L.esize;
-}
 
-hipEvent_t take_event(dpml *H)
-{
-    if (H->events_used == H->events.size()) {
-        hipEvent_t e = nullptr;
-        if (hipEventCreate(&e) != hipSuccess) return nullptr;
-        H->events.push_back(e);
-    }
-    return H->events[H->events_used++];
-}
 
-// Record the start of a timed launch of class `kind` on stream s (default:
-// the handle's); returns its slot or -1.
-int timed_begin(dpml *H, int kind, double bytes, hipStream_t s = nullptr)
-{
-    if (!H->timing || H->timed.size() >= kMaxTimed) return -1;
-    if (!s) s = H->stream;
-    hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
-    if (hipStreamIsCapturing(H->stream, &st) != hipSuccess || st != hipStreamCaptureStatusNone) return -1;
-    dpml::Timed t{kind, take_event(H), take_event(H), bytes};
-    if (!t.e0 || !t.e1 || hipEventRecord(t.e0, s) != hipSuccess) return -1;
-    H->timed.push_back(t);
-    return (int)H->timed.size() - 1;
-}
 
-void timed_end(dpml *H, int slot, hipStream_t s = nullptr)
-{
-    if (slot >= 0) (void)hipEventRecord(H->timed[(size_t)slot].e1, s ? s : H->stream);
-}
 
-template <typename T>
-dpmlk::Axis<T> make_axis(dpml *H, int a, bool next)
-{
-    dpmlk::Axis<T> A{};
-    const Layout &L = H->L;
-    A.N = (int32_t)L.N[a];
-    A.b = (int32_t)(L.lo[a] + L.n[a]);
-    A.M = a < L.ndim ? L.M[a] : 0;
-    A.hi = L.hi[a];
-    A.wall = a < L.ndim ? L.wall[a] : 0;
-    if (A.M > 0) {
-        const int in = H->cur, out = 1 - H->cur;
-        A.sig = (const T *)H->at(L.off_sig[a]);
-        A.phi = (const T *)H->at(L.off_phi[a][in]);
-        A.psi = (const T *)H->at(L.off_psi[a][in]);
-        A.phi_o = (T *)H->at(L.off_phi[a][out]);
-        A.psi_o = (T *)H->at(L.off_psi[a][out]);
-    }
-    (void)next;
-    return A;
-}
-
-template <typename T>
-dpmlk::StepArgs<T> make_args(dpml *H)
-{
-    dpmlk::StepArgs<T> p{};
-    const Layout &L = H->L;
-    for (int a = 0; a < 3; ++a) p.ax[a] = make_axis<T>(H, a, true);
-    p.u = (const T *)H->u_now;
-    p.uo = (T *)H->u_old;
-    p.c2 = H->c2_field ? (const T *)H->at(L.off_c2) : nullptr;
-    p.c2_const = (T)H->c2_const;
-    p.inv_h2 = (T)(1.0 / (H->h * H->h));
-    p.inv_h = (T)(1.0 / H->h);
-    p.inv_2h = (T)(1.0 / (2.0 * H->h));
-    p.dt = (T)H->dt;
-    p.dt2 = (T)(H->dt * H->dt);
-    p.nx = (int32_t)L.N[0];
-    p.ny = (int32_t)L.N[1];
-    p.nz = (int32_t)L.N[2];
-    p.bstride = L.ncell;
-    for (int a = 0; a < 3; ++a) p.bstride_aux[a] = L.aux_elems[a];
-    p.hist = nullptr;
-    p.uout = nullptr;
-    p.skip[0] = p.skip[1] = p.skip[2] = p.skip[3] = 0;
-    return p;
-}
-
-int round8(int v) { return (v + 7) / 8 * 8; }
-
-// Box of a 3D step where no y or z damping term acts: [lo+1, lo+n) on an
-// axis with a layer (cell lo still meets sigma(lo-1)), the whole axis
-// without one.  Returns {y0, y1, z0, z1}.
-void march_box3d(const Layout &L, int b[4])
-{
-    for (int a = 1; a < 3; ++a) {
-        const int k = 2 * (a - 1);
-        if (L.M[a] == 0) {
-            b[k] = 0;
-            b[k + 1] = (int)L.N[a];
-        } else {
-            b[k] = L.lo[a] + 1;
-            b[k + 1] = (int)(L.lo[a] + L.n[a]);
-        }
-    }
-}
-
-// The second stream (and its fork/join events) on which the layer parts of a
-// split step run beside the main kernel.
-int ensure_side(dpml *H)
-{
-    if (!H->side) HIP_TRY(H, hipStreamCreateWithFlags(&H->side, hipStreamNonBlocking));
-    if (!H->ev_fork) HIP_TRY(H, hipEventCreateWithFlags(&H->ev_fork, hipEventDisableTiming));
-    if (!H->ev_join) HIP_TRY(H, hipEventCreateWithFlags(&H->ev_join, hipEventDisableTiming));
-    return DPML_OK;
-}
-
-// Algorithmic layer axis-cells of a 3D box: per axis, the weight of each band
-// slot in the box's range along it (a half word pair for each of Phi and Psi
-// the slot holds, so a whole band counts M) times the box's other extents.
-double box_aux(const Layout &L, const dpmlk::Box3 &bx)
-{
-    const int r0[3] = {bx.xs, bx.ys, bx.zs}, r1[3] = {bx.xe, bx.ye, bx.ze};
-    double aux = 0;
-    for (int a = 0; a < 3; ++a) {
-        if (L.M[a] == 0) continue;
-        const int64_t b = L.lo[a] + L.n[a], N = L.N[a];
-        double w = 0;
-        for (int i = r0[a]; i < r1[a]; ++i) {
-            const int64_t ic = i % N;
-            const int64_t j = ic >= b ? ic - b : ic + (N - b);
-            if (j <= L.M[a]) w += 0.5 * ((j < L.M[a]) + (j > 0));
-        }
-        double other = 1;
-        for (int c = 0; c < 3; ++c)
-            if (c != a) other *= (double)(r1[c] - r0[c]);
-        aux += w * other;
-    }
-    return aux;
-}
-
-double box_cells(const dpmlk::Box3 &bx)
-{
-    return (double)(bx.xe - bx.xs) * (double)(bx.ye - bx.ys) * (double)(bx.ze - bx.zs);
-}
-
-// One thread-per-cell launch over a box with the layer code of the axes in
-// `ax` (x and z, or all).
-template <typename T>
-int launch_box(dpml *H, dpmlk::StepArgs<T> p, const dpmlk::Box3 &bx, int ax, hipStream_t st, int kind,
-               double bytes = -1)
-{
-    if (bx.xe <= bx.xs || bx.ye <= bx.ys || bx.ze <= bx.zs) return DPML_OK;
-    p.tiles_x = (bx.xe - bx.xs + 63) / 64;
-    p.tiles_y = (bx.ye - bx.ys + 3) / 4;
-    p.n_tiles = p.tiles_x * p.tiles_y * (bx.ze - bx.zs);
-    if (H->timing && bytes < 0) bytes = step_bytes(H, box_cells(bx), box_aux(H->L, bx));
-    const int slot = H->timing ? timed_begin(H, kind, bytes, st) : -1;
-    const dim3 grid((unsigned)round8(p.n_tiles), (unsigned)H->L.batch), block(256);
-    if (ax == 5) hipLaunchKernelGGL((dpmlk::k_step_box3d<T, 5>), grid, block, 0, st, p, bx);
-    else hipLaunchKernelGGL((dpmlk::k_step_box3d<T, 7>), grid, block, 0, st, p, bx);
-    if (slot >= 0) timed_end(H, slot, st);
-    return DPML_OK;
-}
-
-// One z-march launch over a box with the layer code of the axes in `ax`
-// (none or x alone), `ry` register rows per wave and `zchunk` planes per
-// tile.
-template <typename T>
-int launch_zmarch(dpml *H, dpmlk::StepArgs<T> p, const dpmlk::Box3 &bx, int ry, int ax, int zchunk,
-                  hipStream_t st, int kind, double bytes = -1)
-{
-    if (bx.xe <= bx.xs || bx.ye <= bx.ys || bx.ze <= bx.zs) return DPML_OK;
-    p.tile_rows = zchunk;
-    p.tiles_x = (bx.xe - bx.xs + 63) / 64;
-    p.tiles_y = (bx.ye - bx.ys + 4 * ry - 1) / (4 * ry);
-    const int tz = (bx.ze - bx.zs + zchunk - 1) / zchunk;
-    p.n_tiles = p.tiles_x * p.tiles_y * tz;
-    if (H->timing && bytes < 0) bytes = step_bytes(H, box_cells(bx), box_aux(H->L, bx));
-    const int slot = H->timing ? timed_begin(H, kind, bytes, st) : -1;
-    const dim3 grid((unsigned)round8(p.n_tiles), (unsigned)H->L.batch), block(256);
-#define DPML_ZMARCH(RY_, AX_) hipLaunchKernelGGL((dpmlk::k_step_zmarch3d<T, RY_, AX_>), grid, block, 0, st, p, bx)
-    if (ry == 4) {
-        if (ax == 0) DPML_ZMARCH(4, 0);
-        else DPML_ZMARCH(4, 1);
-    } else {
-        if (ax == 0) DPML_ZMARCH(2, 0);
-        else DPML_ZMARCH(2, 1);
-    }
-#undef DPML_ZMARCH
-    if (slot >= 0) timed_end(H, slot, st);
-    return DPML_OK;
-}
-
-// 3D marching step as boxes:
-//   core    x strips [64 s0, 64 s1) that no x damping term reaches, rows and
-//           planes [lo+1, lo+n) (the box of march_box3d): no layer code;
-//   x band  the remaining columns [64 s1, 64 s0 + N) of the same rows and
-//           planes (one box across the periodic wrap): x-layer code;
-//   y band  every column and plane of the rows [lo+n, lo+n+M] (wrapped):
-//           all layer code, one thread per cell;
-//   z band  every column of the box's rows, planes [lo+n, lo+n+M]: x and z
-//           layer code, one thread per cell.
-// The boxes partition the grid.  The layer boxes run on the side stream
-// while the core runs on the handle's stream; they write disjoint cells and
-// the step ends with the handle's stream waiting for the side stream.
-template <typename T>
-int launch_march3d(dpml *H, dpmlk::StepArgs<T> p, int ry)
-{
-    const Layout &L = H->L;
-    int b[4];
-    march_box3d(L, b);
-    const int NX = (int)L.N[0], NZ = (int)L.N[2];
-    const bool layers = L.M[0] > 0 || L.M[1] > 0 || L.M[2] > 0;
-    if (layers) {
-        int rc = ensure_side(H);
-        if (rc) return rc;
-        HIP_TRY(H, hipEventRecord(H->ev_fork, H->stream));
-        HIP_TRY(H, hipStreamWaitEvent(H->side, H->ev_fork, 0));
-    }
-    hipStream_t ls = layers ? H->side : H->stream;     // stream of the layer parts
-    int x0 = 0, x1 = NX;
-    if (L.M[0] > 0) {
-        const int s0 = (L.lo[0] + 1 + 63) / 64;
-        int s1 = (int)((L.lo[0] + L.n[0]) / 64);
-        if (s1 < s0) s1 = s0;
-        x0 = 64 * s0;
-        x1 = std::min(64 * s1, NX);
-    }
-    const int zc = (H->tile_rows & 0xFFF) > 0 ? (H->tile_rows & 0xFFF) : 32;
-    const int zl = std::max(8, zc / 4);               // layer boxes: few tiles, shorter chunks
-    int rc;
-    if (L.M[1] > 0) {
-        const int yb = L.lo[1] + (int)L.n[1];
-        rc = launch_box<T>(H, p, dpmlk::Box3{0, NX, yb, yb + L.M[1] + 1, 0, NZ}, 7, ls, DPML_KERNEL_FRAME);
-        if (rc) return rc;
-    }
-    if (L.M[2] > 0) {
-        const int zb = L.lo[2] + (int)L.n[2];
-        rc = launch_box<T>(H, p, dpmlk::Box3{0, NX, b[0], b[1], zb, zb + L.M[2] + 1}, 5, ls, DPML_KERNEL_FRAME);
-        if (rc) return rc;
-    }
-    const bool whole = !layers;
-    rc = launch_zmarch<T>(H, p, dpmlk::Box3{x0, x1, b[0], b[1], b[2], b[3]}, ry, 0, zc, H->stream,
-                          whole ? DPML_KERNEL_STEP : DPML_KERNEL_CORE);
-    if (rc) return rc;
-    if (L.M[0] > 0) {
-        rc = launch_zmarch<T>(H, p, dpmlk::Box3{x1, x0 + NX, b[0], b[1], b[2], b[3]}, ry, 1, zl, ls,
-                              DPML_KERNEL_FRAME);
-        if (rc) return rc;
-    }
-    if (layers) {
-        HIP_TRY(H, hipEventRecord(H->ev_join, H->side));
-        HIP_TRY(H, hipStreamWaitEvent(H->stream, H->ev_join, 0));
-    }
-    HIP_TRY(H, hipGetLastError());
-    return DPML_OK;
-}
 
 template <typename T>
 int launch_step(dpml *H, T *hist = nullptr, T *uout = nullptr)
@@ -556,54 +90,8 @@ int launch_step(dpml *H, T *hist = nullptr, T *uout = nullptr)
     return DPML_OK;
 }
 
-template <typename T>
-int launch_record(dpml *H, const T *unew, int64_t n);
 
-template <typename T>
-int launch_epilogue(dpml *H)
-{
-    // U^{n+1} now sits in u_old (before the rotation)
-    T *unew = (T *)H->u_old;
-    const Layout &L = H->L;
-    if (H->ns > 0 && H->n < H->nt_src) {
-        double hd = 1;
-        for (int a = 0; a < L.ndim; ++a) hd *= H->h;
-        const T amp = (T)(H->dt * H->dt / hd);
-        dim3 grid((unsigned)((H->ns + 255) / 256)), block(256);
-        hipLaunchKernelGGL((dpmlk::k_inject<T>), grid, block, 0, H->stream, unew, H->d_src_cells,
-                           H->d_src_order, (const T *)H->wavelets, H->ns, H->nt_src, H->n, amp);
-    }
-    return launch_record<T>(H, unew, H->n);
-}
 
-// Receivers and the recorded plane of time index n from the field `unew`.
-template <typename T>
-int launch_record(dpml *H, const T *unew, int64_t n)
-{
-    const Layout &L = H->L;
-    if (H->recording && H->nr > 0 && n < H->nt_rec) {
-        dim3 grid((unsigned)((H->nr + 255) / 256)), block(256);
-        hipLaunchKernelGGL((dpmlk::k_record<T>), grid, block, 0, H->stream, unew,
-                           H->d_rec_cells, (T *)H->traces, H->nr, H->nt_rec, n);
-    }
-    if (H->recording && H->plane_axis >= 0 && n < H->nt_plane) {
-        int a0 = -1, a1 = -1;
-        for (int a = 0; a < L.ndim; ++a) {
-            if (a == H->plane_axis) continue;
-            if (a0 < 0) a0 = a; else a1 = a;
-        }
-        const int64_t stride[3] = {1, L.N[0], L.N[0] * L.N[1]};
-        const int64_t e0 = L.N[a0], e1 = a1 >= 0 ? L.N[a1] : 1;
-        const int64_t s0 = stride[a0], s1 = a1 >= 0 ? stride[a1] : 0;
-        const int64_t cells = e0 * e1;
-        T *out = (T *)H->planes + n * cells;
-        dim3 grid((unsigned)((cells + 255) / 256)), block(256);
-        hipLaunchKernelGGL((dpmlk::k_record_plane<T>), grid, block, 0, H->stream, unew, out,
-                           e0, e1, s0, s1, H->plane_index * stride[H->plane_axis]);
-    }
-    HIP_TRY(H, hipGetLastError());
-    return DPML_OK;
-}
 
 // Columns per lane of the multi-step core kernels.
 int multistep_vx(const Layout &L) { return L.dtype == DPML_F32 ? 4 : 2; }
@@ -632,56 +120,8 @@ void core_rect(const Layout &L, int levels, int r[4])
     }
 }
 
-// Multi-step passes with reflecting walls: the core kernels read `levels`
-// cells beyond their outputs, which stays inside the grid (the ghost cells
-// past a wall are never read) when every walled axis has a layer with at
-// least one cell above the interior; an axis without a layer is core over its
-// whole extent and wraps, so it must be periodic.
-bool walls_allow_multistep(const Layout &L)
-{
-    for (int a = 0; a < L.ndim; ++a)
-        if (L.wall[a] && (L.M[a] == 0 || L.N[a] - L.lo[a] - L.n[a] < 1)) return false;
-    return true;
-}
 
-// Core box of a 3D two-step pass shrunk by `shrink` cells: [lo+2+shrink,
-// lo+n-1-shrink) along an axis with a layer (the cells whose one-cell halo is
-// free of damping terms), the whole periodic axis without one.
-dpmlk::Box3 core_box3d(const Layout &L, int shrink)
-{
-    int r[6];
-    for (int a = 0; a < 3; ++a) {
-        if (L.M[a] == 0) {
-            r[2 * a] = 0;
-            r[2 * a + 1] = (int)L.N[a];
-            continue;
-        }
-        const int b0 = L.lo[a] + 2 + shrink, b1 = (int)(L.lo[a] + L.n[a]) - 1 - shrink;
-        r[2 * a] = b0;
-        r[2 * a + 1] = std::max(b0, b1);
-    }
-    return dpmlk::Box3{r[0], r[1], r[2], r[3], r[4], r[5]};
-}
 
-// 3D: two levels per pass for the multi-step variants on
-// single-member grids with a constant c^2 (walls as walls_allow_multistep
-// admits), at most 32 sources, all inside the core shrunk by one (the frame's
-// steps then add none); otherwise 1.
-int multistep_levels3d(const dpml *H, int64_t nsteps)
-{
-    const Layout &L = H->L;
-    if (pass_depth(H->variant, H->tile_rows) < 2) return 1;
-    if (nsteps < 2 || L.batch != 1 || H->c2_field || !walls_allow_multistep(L)) return 1;
-    if (L.N[0] < 8 || L.N[1] < 8 || L.N[2] < 8 || H->ns > 32) return 1;
-    const dpmlk::Box3 c = core_box3d(L, 0), in1 = core_box3d(L, 1);
-    if (in1.xe <= in1.xs || in1.ye <= in1.ys || in1.ze <= in1.zs) return 1;
-    (void)c;
-    for (int64_t cell : H->src_sorted) {
-        const int x = (int)(cell % L.N[0]), y = (int)((cell / L.N[0]) % L.N[1]), z = (int)(cell / (L.N[0] * L.N[1]));
-        if (x < in1.xs || x >= in1.xe || y < in1.ys || y >= in1.ye || z < in1.zs || z >= in1.ze) return 1;
-    }
-    return 2;
-}
 
 // Levels per pass this handle may take right now: the variant's depth, fewer
 // for the last steps of a run or where the core of that depth is empty, or 1.
@@ -1009,119 +449,7 @@ int launch_multistep(dpml *H, int levels)
     return DPML_OK;
 }
 
-// One step over everything outside the box S (a frame step of a 3D pass):
-// the rows outside S (every column and plane; all layer code), S's rows on
-// the planes outside S (every column; x and z layer code) and S's rows and
-// planes on the columns outside S (the x-band march).  `share` is the
-// algorithmic byte count the three launches report together.
-template <typename T>
-int launch_outside3d(dpml *H, const dpmlk::StepArgs<T> &p, const dpmlk::Box3 &S, double share, hipStream_t st)
-{
-    const Layout &L = H->L;
-    const int NX = (int)L.N[0], NY = (int)L.N[1], NZ = (int)L.N[2];
-    const dpmlk::Box3 by{0, NX, S.ye, S.ys + NY, 0, NZ};
-    const dpmlk::Box3 bz{0, NX, S.ys, S.ye, S.ze, S.zs + NZ};
-    const dpmlk::Box3 bx{S.xe, S.xs + NX, S.ys, S.ye, S.zs, S.ze};
-    const bool hy = S.ye - S.ys < NY, hz = S.ze - S.zs < NZ, hx = S.xe - S.xs < NX;
-    // each launch reports its part of the share, by its own algorithmic bytes
-    double w[3] = {0, 0, 0};
-    if (H->timing) {
-        if (hy) w[0] = step_bytes(H, box_cells(by), box_aux(L, by));
-        if (hz) w[1] = step_bytes(H, box_cells(bz), box_aux(L, bz));
-        if (hx) w[2] = step_bytes(H, box_cells(bx), box_aux(L, bx));
-        const double sum = w[0] + w[1] + w[2];
-        for (double &v : w) v = sum > 0 ? share * v / sum : 0;
-    }
-    int rc = DPML_OK;
-    if (hy) rc = launch_box<T>(H, p, by, 7, st, DPML_KERNEL_FRAME, w[0]);
-    if (rc) return rc;
-    if (hz) rc = launch_box<T>(H, p, bz, 5, st, DPML_KERNEL_FRAME, w[1]);
-    if (rc) return rc;
-    if (hx) {
-        const int zc = (H->tile_rows & 0xFFF) > 0 ? (H->tile_rows & 0xFFF) : 32;
-        rc = launch_zmarch<T>(H, p, bx, 4, 1, std::max(8, zc / 4), st, DPML_KERNEL_FRAME, w[2]);
-    }
-    return rc;
-}
 
-// Two steps of a 3D grid.  The core kernel runs on the handle's stream; the
-// frame takes two ordinary steps on the side stream at the same time, step
-// j over everything outside the core shrunk by 2 - j cells.  The core writes
-// U^{n+1} only on the core shrunk by one, so every cell of every buffer has
-// one writer.  Receivers and the plane record both levels once the side
-// stream has joined.
-template <typename T>
-int launch_multistep3d(dpml *H)
-{
-    const Layout &L = H->L;
-    T *A = (T *)H->u_now, *Bv = (T *)H->u_old;
-    T *nxt[2] = {nullptr, nullptr};
-    int k = 0;
-    for (int i = 0; i < L.n_ubuf && k < 2; ++i) {
-        void *b = H->at(L.off_u[i]);
-        if (b != H->u_now && b != H->u_old) nxt[k++] = (T *)b;
-    }
-    if (k < 2) return H->fail(DPML_EINVAL, "not enough field buffers for a multi-step pass");
-    const dpmlk::Box3 c = core_box3d(L, 0), in1 = core_box3d(L, 1);
-    // tile_rows: planes per chunk in the low 12 bits (0: 32), rows per wave
-    // in the bits above (4, 8 or 16; 0: 8)
-    const int chunk = (H->tile_rows & 0xFFF) > 0 ? (H->tile_rows & 0xFFF) : 32;
-    const int ryb = (H->tile_rows >> 12) & 0xFF;
-    const int ry = (ryb == 4 || ryb == 16) ? ryb : 8;
-    HIP_TRY(H, hipEventRecord(H->ev_fork, H->stream));
-    HIP_TRY(H, hipStreamWaitEvent(H->side, H->ev_fork, 0));
-    {
-        dpmlk::StepArgs<T> p = make_args<T>(H);
-        p.uout = nxt[0];
-        p.tile_rows = chunk;
-        p.tiles_x = (c.xe - c.xs + 59) / 60;
-        p.tiles_y = (c.ye - c.ys + 4 * ry - 1) / (4 * ry);
-        p.n_tiles = p.tiles_x * p.tiles_y * ((c.ze - c.zs + chunk - 1) / chunk);
-        dpmlk::Src3<T> src{};
-        src.cells = H->d_src_cells;
-        src.order = H->d_src_order;
-        src.wav = (const T *)H->wavelets;
-        src.ns = H->ns;
-        src.nt = H->nt_src;
-        src.n = H->n;
-        src.amp = (T)(H->dt * H->dt / (H->h * H->h * H->h));
-        const double core = box_cells(c);
-        const int slot = timed_begin(H, DPML_KERNEL_PAIR, step_bytes(H, 2 * core, 0.0));
-        const dim3 grid((unsigned)round8(p.n_tiles)), block(256);
-        if (ry == 4)
-            hipLaunchKernelGGL((dpmlk::k_step2_zmarch3d<T, 4>), grid, block, 0, H->stream, p, nxt[1], c, in1, src);
-        else if (ry == 16)
-            hipLaunchKernelGGL((dpmlk::k_step2_zmarch3d<T, 16>), grid, block, 0, H->stream, p, nxt[1], c, in1, src);
-        else
-            hipLaunchKernelGGL((dpmlk::k_step2_zmarch3d<T, 8>), grid, block, 0, H->stream, p, nxt[1], c, in1, src);
-        timed_end(H, slot);
-    }
-    // the frame's steps on the side stream, aux buffers alternating
-    for (int j = 1; j <= 2; ++j) {
-        if (j == 2) H->cur = 1 - H->cur;
-        dpmlk::StepArgs<T> pj = make_args<T>(H);
-        if (j == 2) H->cur = 1 - H->cur;
-        pj.u = j == 1 ? A : nxt[0];
-        pj.uo = j == 1 ? Bv : A;
-        pj.uout = nxt[j - 1];
-        // algorithmic share: the frame's own cells (the ring cells it recomputes
-        // are the core's, counted there)
-        const double share = step_bytes(H, (double)L.ncell - box_cells(c), aux_cells(L));
-        int rc = launch_outside3d<T>(H, pj, core_box3d(L, 2 - j), share, H->side);
-        if (rc) return rc;
-    }
-    HIP_TRY(H, hipEventRecord(H->ev_join, H->side));
-    HIP_TRY(H, hipStreamWaitEvent(H->stream, H->ev_join, 0));
-    HIP_TRY(H, hipGetLastError());
-    int rc = launch_record<T>(H, nxt[0], H->n);
-    if (rc) return rc;
-    rc = launch_record<T>(H, nxt[1], H->n + 1);
-    if (rc) return rc;
-    H->u_now = nxt[1];
-    H->u_old = nxt[0];
-    H->n += 2;
-    return DPML_OK;
-}
 
 template <typename T>
 int step_impl(dpml *H, int64_t nsteps)

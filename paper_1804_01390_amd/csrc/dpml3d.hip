@@ -1,0 +1,328 @@
+// dpml3d.hip -- 3D stepping paths of the discrete-PML wave stepper: the
+// marching single steps split into boxes (layer-free core, x-band strip, y and
+// z layer slabs) and the multi-step passes (a temporally blocked core beside
+// the frame's single steps), their launch shapes and algorithmic byte counts.
+// The per-cell arithmetic is Eq. (DiscretePML a-c) of Chern, "A Reflectionless
+// Discrete Perfectly Matched Layer", as in dpml_kernels.hpp.
+#include "dpml_host.hpp"
+
+namespace dpmlh {
+
+// Box of a 3D step where no y or z damping term acts: [lo+1, lo+n) on an
+// axis with a layer (cell lo still meets sigma(lo-1)), the whole axis
+// without one.  Returns {y0, y1, z0, z1}.
+static void march_box3d(const Layout &L, int b[4])
+{
+    for (int a = 1; a < 3; ++a) {
+        const int k = 2 * (a - 1);
+        if (L.M[a] == 0) {
+            b[k] = 0;
+            b[k + 1] = (int)L.N[a];
+        } else {
+            b[k] = L.lo[a] + 1;
+            b[k + 1] = (int)(L.lo[a] + L.n[a]);
+        }
+    }
+}
+
+// Algorithmic layer axis-cells of a 3D box: per axis, the weight of each band
+// slot in the box's range along it (a half word pair for each of Phi and Psi
+// the slot holds, so a whole band counts M) times the box's other extents.
+static double box_aux(const Layout &L, const dpmlk::Box3 &bx)
+{
+    const int r0[3] = {bx.xs, bx.ys, bx.zs}, r1[3] = {bx.xe, bx.ye, bx.ze};
+    double aux = 0;
+    for (int a = 0; a < 3; ++a) {
+        if (L.M[a] == 0) continue;
+        const int64_t b = L.lo[a] + L.n[a], N = L.N[a];
+        double w = 0;
+        for (int i = r0[a]; i < r1[a]; ++i) {
+            const int64_t ic = i % N;
+            const int64_t j = ic >= b ? ic - b : ic + (N - b);
+            if (j <= L.M[a]) w += 0.5 * ((j < L.M[a]) + (j > 0));
+        }
+        double other = 1;
+        for (int c = 0; c < 3; ++c)
+            if (c != a) other *= (double)(r1[c] - r0[c]);
+        aux += w * other;
+    }
+    return aux;
+}
+
+static double box_cells(const dpmlk::Box3 &bx)
+{
+    return (double)(bx.xe - bx.xs) * (double)(bx.ye - bx.ys) * (double)(bx.ze - bx.zs);
+}
+
+// One thread-per-cell launch over a box with the layer code of the axes in
+// `ax` (x and z, or all).
+template <typename T>
+int launch_box(dpml *H, dpmlk::StepArgs<T> p, const dpmlk::Box3 &bx, int ax, hipStream_t st, int kind,
+               double bytes = -1)
+{
+    if (bx.xe <= bx.xs || bx.ye <= bx.ys || bx.ze <= bx.zs) return DPML_OK;
+    p.tiles_x = (bx.xe - bx.xs + 63) / 64;
+    p.tiles_y = (bx.ye - bx.ys + 3) / 4;
+    p.n_tiles = p.tiles_x * p.tiles_y * (bx.ze - bx.zs);
+    if (H->timing && bytes < 0) bytes = step_bytes(H, box_cells(bx), box_aux(H->L, bx));
+    const int slot = H->timing ? timed_begin(H, kind, bytes, st) : -1;
+    const dim3 grid((unsigned)round8(p.n_tiles), (unsigned)H->L.batch), block(256);
+    if (ax == 5) hipLaunchKernelGGL((dpmlk::k_step_box3d<T, 5>), grid, block, 0, st, p, bx);
+    else hipLaunchKernelGGL((dpmlk::k_step_box3d<T, 7>), grid, block, 0, st, p, bx);
+    if (slot >= 0) timed_end(H, slot, st);
+    return DPML_OK;
+}
+
+// One z-march launch over a box with the layer code of the axes in `ax`
+// (none or x alone), `ry` register rows per wave and `zchunk` planes per
+// tile.
+template <typename T>
+int launch_zmarch(dpml *H, dpmlk::StepArgs<T> p, const dpmlk::Box3 &bx, int ry, int ax, int zchunk,
+                  hipStream_t st, int kind, double bytes = -1)
+{
+    if (bx.xe <= bx.xs || bx.ye <= bx.ys || bx.ze <= bx.zs) return DPML_OK;
+    p.tile_rows = zchunk;
+    p.tiles_x = (bx.xe - bx.xs + 63) / 64;
+    p.tiles_y = (bx.ye - bx.ys + 4 * ry - 1) / (4 * ry);
+    const int tz = (bx.ze - bx.zs + zchunk - 1) / zchunk;
+    p.n_tiles = p.tiles_x * p.tiles_y * tz;
+    if (H->timing && bytes < 0) bytes = step_bytes(H, box_cells(bx), box_aux(H->L, bx));
+    const int slot = H->timing ? timed_begin(H, kind, bytes, st) : -1;
+    const dim3 grid((unsigned)round8(p.n_tiles), (unsigned)H->L.batch), block(256);
+#define DPML_ZMARCH(RY_, AX_) hipLaunchKernelGGL((dpmlk::k_step_zmarch3d<T, RY_, AX_>), grid, block, 0, st, p, bx)
+    if (ry == 4) {
+        if (ax == 0) DPML_ZMARCH(4, 0);
+        else DPML_ZMARCH(4, 1);
+    } else {
+        if (ax == 0) DPML_ZMARCH(2, 0);
+        else DPML_ZMARCH(2, 1);
+    }
+#undef DPML_ZMARCH
+    if (slot >= 0) timed_end(H, slot, st);
+    return DPML_OK;
+}
+
+// 3D marching step as boxes:
+//   core    x strips [64 s0, 64 s1) that no x damping term reaches, rows and
+//           planes [lo+1, lo+n) (the box of march_box3d): no layer code;
+//   x band  the remaining columns [64 s1, 64 s0 + N) of the same rows and
+//           planes (one box across the periodic wrap): x-layer code;
+//   y band  every column and plane of the rows [lo+n, lo+n+M] (wrapped):
+//           all layer code, one thread per cell;
+//   z band  every column of the box's rows, planes [lo+n, lo+n+M]: x and z
+//           layer code, one thread per cell.
+// The boxes partition the grid.  The layer boxes run on the side stream
+// while the core runs on the handle's stream; they write disjoint cells and
+// the step ends with the handle's stream waiting for the side stream.
+template <typename T>
+int launch_march3d(dpml *H, dpmlk::StepArgs<T> p, int ry)
+{
+    const Layout &L = H->L;
+    int b[4];
+    march_box3d(L, b);
+    const int NX = (int)L.N[0], NZ = (int)L.N[2];
+    const bool layers = L.M[0] > 0 || L.M[1] > 0 || L.M[2] > 0;
+    if (layers) {
+        int rc = ensure_side(H);
+        if (rc) return rc;
+        HIP_TRY(H, hipEventRecord(H->ev_fork, H->stream));
+        HIP_TRY(H, hipStreamWaitEvent(H->side, H->ev_fork, 0));
+    }
+    hipStream_t ls = layers ? H->side : H->stream;     // stream of the layer parts
+    int x0 = 0, x1 = NX;
+    if (L.M[0] > 0) {
+        const int s0 = (L.lo[0] + 1 + 63) / 64;
+        int s1 = (int)((L.lo[0] + L.n[0]) / 64);
+        if (s1 < s0) s1 = s0;
+        x0 = 64 * s0;
+        x1 = std::min(64 * s1, NX);
+    }
+    const int zc = (H->tile_rows & 0xFFF) > 0 ? (H->tile_rows & 0xFFF) : 32;
+    const int zl = std::max(8, zc / 4);               // layer boxes: few tiles, shorter chunks
+    int rc;
+    if (L.M[1] > 0) {
+        const int yb = L.lo[1] + (int)L.n[1];
+        rc = launch_box<T>(H, p, dpmlk::Box3{0, NX, yb, yb + L.M[1] + 1, 0, NZ}, 7, ls, DPML_KERNEL_FRAME);
+        if (rc) return rc;
+    }
+    if (L.M[2] > 0) {
+        const int zb = L.lo[2] + (int)L.n[2];
+        rc = launch_box<T>(H, p, dpmlk::Box3{0, NX, b[0], b[1], zb, zb + L.M[2] + 1}, 5, ls, DPML_KERNEL_FRAME);
+        if (rc) return rc;
+    }
+    const bool whole = !layers;
+    rc = launch_zmarch<T>(H, p, dpmlk::Box3{x0, x1, b[0], b[1], b[2], b[3]}, ry, 0, zc, H->stream,
+                          whole ? DPML_KERNEL_STEP : DPML_KERNEL_CORE);
+    if (rc) return rc;
+    if (L.M[0] > 0) {
+        rc = launch_zmarch<T>(H, p, dpmlk::Box3{x1, x0 + NX, b[0], b[1], b[2], b[3]}, ry, 1, zl, ls,
+                              DPML_KERNEL_FRAME);
+        if (rc) return rc;
+    }
+    if (layers) {
+        HIP_TRY(H, hipEventRecord(H->ev_join, H->side));
+        HIP_TRY(H, hipStreamWaitEvent(H->stream, H->ev_join, 0));
+    }
+    HIP_TRY(H, hipGetLastError());
+    return DPML_OK;
+}
+
+// Core box of a 3D two-step pass shrunk by `shrink` cells: [lo+2+shrink,
+// lo+n-1-shrink) along an axis with a layer (the cells whose one-cell halo is
+// free of damping terms), the whole periodic axis without one.
+static dpmlk::Box3 core_box3d(const Layout &L, int shrink)
+{
+    int r[6];
+    for (int a = 0; a < 3; ++a) {
+        if (L.M[a] == 0) {
+            r[2 * a] = 0;
+            r[2 * a + 1] = (int)L.N[a];
+            continue;
+        }
+        const int b0 = L.lo[a] + 2 + shrink, b1 = (int)(L.lo[a] + L.n[a]) - 1 - shrink;
+        r[2 * a] = b0;
+        r[2 * a + 1] = std::max(b0, b1);
+    }
+    return dpmlk::Box3{r[0], r[1], r[2], r[3], r[4], r[5]};
+}
+
+// 3D: two levels per pass for the multi-step variants on
+// single-member grids with a constant c^2 (walls as walls_allow_multistep
+// admits), at most 32 sources, all inside the core shrunk by one (the frame's
+// steps then add none); otherwise 1.
+int multistep_levels3d(const dpml *H, int64_t nsteps)
+{
+    const Layout &L = H->L;
+    if (pass_depth(H->variant, H->tile_rows) < 2) return 1;
+    if (nsteps < 2 || L.batch != 1 || H->c2_field || !walls_allow_multistep(L)) return 1;
+    if (L.N[0] < 8 || L.N[1] < 8 || L.N[2] < 8 || H->ns > 32) return 1;
+    const dpmlk::Box3 c = core_box3d(L, 0), in1 = core_box3d(L, 1);
+    if (in1.xe <= in1.xs || in1.ye <= in1.ys || in1.ze <= in1.zs) return 1;
+    (void)c;
+    for (int64_t cell : H->src_sorted) {
+        const int x = (int)(cell % L.N[0]), y = (int)((cell / L.N[0]) % L.N[1]), z = (int)(cell / (L.N[0] * L.N[1]));
+        if (x < in1.xs || x >= in1.xe || y < in1.ys || y >= in1.ye || z < in1.zs || z >= in1.ze) return 1;
+    }
+    return 2;
+}
+
+// One step over everything outside the box S (a frame step of a 3D pass):
+// the rows outside S (every column and plane; all layer code), S's rows on
+// the planes outside S (every column; x and z layer code) and S's rows and
+// planes on the columns outside S (the x-band march).  `share` is the
+// algorithmic byte count the three launches report together.
+template <typename T>
+int launch_outside3d(dpml *H, const dpmlk::StepArgs<T> &p, const dpmlk::Box3 &S, double share, hipStream_t st)
+{
+    const Layout &L = H->L;
+    const int NX = (int)L.N[0], NY = (int)L.N[1], NZ = (int)L.N[2];
+    const dpmlk::Box3 by{0, NX, S.ye, S.ys + NY, 0, NZ};
+    const dpmlk::Box3 bz{0, NX, S.ys, S.ye, S.ze, S.zs + NZ};
+    const dpmlk::Box3 bx{S.xe, S.xs + NX, S.ys, S.ye, S.zs, S.ze};
+    const bool hy = S.ye - S.ys < NY, hz = S.ze - S.zs < NZ, hx = S.xe - S.xs < NX;
+    // each launch reports its part of the share, by its own algorithmic bytes
+    double w[3] = {0, 0, 0};
+    if (H->timing) {
+        if (hy) w[0] = step_bytes(H, box_cells(by), box_aux(L, by));
+        if (hz) w[1] = step_bytes(H, box_cells(bz), box_aux(L, bz));
+        if (hx) w[2] = step_bytes(H, box_cells(bx), box_aux(L, bx));
+        const double sum = w[0] + w[1] + w[2];
+        for (double &v : w) v = sum > 0 ? share * v / sum : 0;
+    }
+    int rc = DPML_OK;
+    if (hy) rc = launch_box<T>(H, p, by, 7, st, DPML_KERNEL_FRAME, w[0]);
+    if (rc) return rc;
+    if (hz) rc = launch_box<T>(H, p, bz, 5, st, DPML_KERNEL_FRAME, w[1]);
+    if (rc) return rc;
+    if (hx) {
+        const int zc = (H->tile_rows & 0xFFF) > 0 ? (H->tile_rows & 0xFFF) : 32;
+        rc = launch_zmarch<T>(H, p, bx, 4, 1, std::max(8, zc / 4), st, DPML_KERNEL_FRAME, w[2]);
+    }
+    return rc;
+}
+
+// Two steps of a 3D grid.  The core kernel runs on the handle's stream; the
+// frame takes two ordinary steps on the side stream at the same time, step
+// j over everything outside the core shrunk by 2 - j cells.  The core writes
+// U^{n+1} only on the core shrunk by one, so every cell of every buffer has
+// one writer.  Receivers and the plane record both levels once the side
+// stream has joined.
+template <typename T>
+int launch_multistep3d(dpml *H)
+{
+    const Layout &L = H->L;
+    T *A = (T *)H->u_now, *Bv = (T *)H->u_old;
+    T *nxt[2] = {nullptr, nullptr};
+    int k = 0;
+    for (int i = 0; i < L.n_ubuf && k < 2; ++i) {
+        void *b = H->at(L.off_u[i]);
+        if (b != H->u_now && b != H->u_old) nxt[k++] = (T *)b;
+    }
+    if (k < 2) return H->fail(DPML_EINVAL, "not enough field buffers for a multi-step pass");
+    const dpmlk::Box3 c = core_box3d(L, 0), in1 = core_box3d(L, 1);
+    // tile_rows: planes per chunk in the low 12 bits (0: 32), rows per wave
+    // in the bits above (4, 8 or 16; 0: 8)
+    const int chunk = (H->tile_rows & 0xFFF) > 0 ? (H->tile_rows & 0xFFF) : 32;
+    const int ryb = (H->tile_rows >> 12) & 0xFF;
+    const int ry = (ryb == 4 || ryb == 16) ? ryb : 8;
+    HIP_TRY(H, hipEventRecord(H->ev_fork, H->stream));
+    HIP_TRY(H, hipStreamWaitEvent(H->side, H->ev_fork, 0));
+    {
+        dpmlk::StepArgs<T> p = make_args<T>(H);
+        p.uout = nxt[0];
+        p.tile_rows = chunk;
+        p.tiles_x = (c.xe - c.xs + 59) / 60;
+        p.tiles_y = (c.ye - c.ys + 4 * ry - 1) / (4 * ry);
+        p.n_tiles = p.tiles_x * p.tiles_y * ((c.ze - c.zs + chunk - 1) / chunk);
+        dpmlk::Src3<T> src{};
+        src.cells = H->d_src_cells;
+        src.order = H->d_src_order;
+        src.wav = (const T *)H->wavelets;
+        src.ns = H->ns;
+        src.nt = H->nt_src;
+        src.n = H->n;
+        src.amp = (T)(H->dt * H->dt / (H->h * H->h * H->h));
+        const double core = box_cells(c);
+        const int slot = timed_begin(H, DPML_KERNEL_PAIR, step_bytes(H, 2 * core, 0.0));
+        const dim3 grid((unsigned)round8(p.n_tiles)), block(256);
+        if (ry == 4)
+            hipLaunchKernelGGL((dpmlk::k_step2_zmarch3d<T, 4>), grid, block, 0, H->stream, p, nxt[1], c, in1, src);
+        else if (ry == 16)
+            hipLaunchKernelGGL((dpmlk::k_step2_zmarch3d<T, 16>), grid, block, 0, H->stream, p, nxt[1], c, in1, src);
+        else
+            hipLaunchKernelGGL((dpmlk::k_step2_zmarch3d<T, 8>), grid, block, 0, H->stream, p, nxt[1], c, in1, src);
+        timed_end(H, slot);
+    }
+    // the frame's steps on the side stream, aux buffers alternating
+    for (int j = 1; j <= 2; ++j) {
+        if (j == 2) H->cur = 1 - H->cur;
+        dpmlk::StepArgs<T> pj = make_args<T>(H);
+        if (j == 2) H->cur = 1 - H->cur;
+        pj.u = j == 1 ? A : nxt[0];
+        pj.uo = j == 1 ? Bv : A;
+        pj.uout = nxt[j - 1];
+        // algorithmic share: the frame's own cells (the ring cells it recomputes
+        // are the core's, counted there)
+        const double share = step_bytes(H, (double)L.ncell - box_cells(c), aux_cells(L));
+        int rc = launch_outside3d<T>(H, pj, core_box3d(L, 2 - j), share, H->side);
+        if (rc) return rc;
+    }
+    HIP_TRY(H, hipEventRecord(H->ev_join, H->side));
+    HIP_TRY(H, hipStreamWaitEvent(H->stream, H->ev_join, 0));
+    HIP_TRY(H, hipGetLastError());
+    int rc = launch_record<T>(H, nxt[0], H->n);
+    if (rc) return rc;
+    rc = launch_record<T>(H, nxt[1], H->n + 1);
+    if (rc) return rc;
+    H->u_now = nxt[1];
+    H->u_old = nxt[0];
+    H->n += 2;
+    return DPML_OK;
+}
+
+template int launch_march3d<float>(dpml *, dpmlk::StepArgs<float>, int);
+template int launch_march3d<double>(dpml *, dpmlk::StepArgs<double>, int);
+template int launch_multistep3d<float>(dpml *);
+template int launch_multistep3d<double>(dpml *);
+
+}  // namespace dpmlh

@@ -46,7 +46,7 @@ def test_binding_constants_match_the_header():
     d = _defines()
     assert len(d) >= 20
     for name, value in d.items():
-        py = name[len("DPML_"):] if name.startswith(("DPML_VARIANT_", "DPML_KERNEL_", "DPML_FIELD_")) else name
+        py = name[len("DPML_"):] if name.startswith(("DPML_VARIANT_", "DPML_KERNEL_", "DPML_FIELD_", "DPML_PROBE_")) else name
         assert getattr(dp, py) == value, name
     for a in range(3):
         assert dp.FIELD_PHI(a) == 2 + 2 * a and dp.FIELD_PSI(a) == 3 + 2 * a
