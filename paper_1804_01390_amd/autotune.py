@@ -38,12 +38,18 @@ CANDIDATES_2D: List[Tuple[int, int]] = ([(VARIANT_DEEP, (pf << 24) | (d << 20) |
                                         + [(VARIANT_CELL, th) for th in (1, 2, 4, 8)]
                                         + [(VARIANT_MARCH, r) for r in (4, 8, 16)]
                                         + [(VARIANT_MARCH1, r) for r in (4, 8, 16)])
-# 3D two-step passes: rows per wave above bit 12, planes per chunk below
-CANDIDATES_3D: List[Tuple[int, int]] = ([(VARIANT_CELL, th) for th in (2, 4, 8)]
-                                        + [(VARIANT_MARCH, r) for r in (16, 32, 64, 128)]
-                                        + [(VARIANT_MARCH1, r) for r in (16, 32, 64, 128)]
-                                        + [(VARIANT_TWOSTEP, (ry << 12) | ch) for ry in (4, 8, 16)
-                                           for ch in (32, 64, 128)])
+# 3D: marching single steps (k_march3d_plan: planes per core chunk in bits
+# 0-11, rows per core wave in bits 12-15, planes of loads in flight in 16-17,
+# planes per layer chunk in 20-27, launch-order tiles bit 28) and two-step
+# passes (planes per chunk in bits 0-11, rows per wave in 12-17; bit 19 the
+# marching frame with its layer chunk in 20-27; bit 28 launch-order tiles)
+CANDIDATES_3D: List[Tuple[int, int]] = ([(VARIANT_CELL, 4)]
+                                        + [(VARIANT_MARCH, (1 << 28) | (lc << 20) | (1 << 16) | (ry << 12) | ch)
+                                           for ry, ch, lc in ((2, 16, 8), (4, 16, 8), (2, 16, 32), (8, 16, 8),
+                                                              (4, 32, 8))]
+                                        + [(VARIANT_TWOSTEP, (ry << 12) | ch) for ry in (8, 16) for ch in (32, 64)]
+                                        + [(VARIANT_TWOSTEP, (1 << 28) | (1 << 19) | (lc << 20) | (ry << 12) | ch)
+                                           for ry, ch, lc in ((4, 64, 8), (8, 64, 8), (4, 32, 16))])
 
 
 def grid_key(sim) -> str:

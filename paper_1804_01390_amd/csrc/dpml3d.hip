@@ -5,6 +5,7 @@
 // The per-cell arithmetic is Eq. (DiscretePML a-c) of Chern, "A Reflectionless
 // Discrete Perfectly Matched Layer", as in dpml_kernels.hpp.
 #include "dpml_host.hpp"
+#include "dpml_kernels3d.hpp"
 
 namespace dpmlh {
 
@@ -114,10 +115,164 @@ int launch_zmarch(dpml *H, dpmlk::StepArgs<T> p, const dpmlk::Box3 &bx, int ry, 
 // The boxes partition the grid.  The layer boxes run on the side stream
 // while the core runs on the handle's stream; they write disjoint cells and
 // the step ends with the handle's stream waiting for the side stream.
+// Launch shape of the register-neighbour marching step (k_march3d_plan):
+// bits 0-11 of tile_rows planes per chunk of the core's waves (0: 64), bits
+// 12-15 rows per core wave (1, 2, 4 or 8; 0: 4), bits 16-17 planes of loads in
+// flight (1 or 2; 0: 1), bit 18 non-temporal U^{n-1} loads and U^{n+1}
+// stores, bit 19 the core and the layer boxes as two launches on two streams
+// (else one launch), bits 20-27 planes per chunk of the layer waves (0: 16),
+// bit 28 blocks in launch order (else XCD-grouped tiles).
+struct MShape {
+    int chunk, ry, pf, nt, split, lchunk, ord;
+};
+
+static MShape mshape(int tile_rows)
+{
+    MShape s;
+    s.chunk = (tile_rows & 0xFFF) ? (tile_rows & 0xFFF) : 64;
+    const int ry = (tile_rows >> 12) & 0xF;
+    s.ry = (ry == 1 || ry == 2 || ry == 8) ? ry : 4;
+    s.pf = ((tile_rows >> 16) & 3) == 2 ? 2 : 1;
+    s.nt = (tile_rows >> 18) & 1;
+    s.split = (tile_rows >> 19) & 1;
+    s.lchunk = ((tile_rows >> 20) & 0xFF) ? ((tile_rows >> 20) & 0xFF) : 16;
+    s.ord = (tile_rows >> 28) & 1;
+    return s;
+}
+
+static dpmlk::MBox make_mbox(const dpmlk::Box3 &bx, int ry, int chunk)
+{
+    dpmlk::MBox m{bx.xs, bx.xe, bx.ys, bx.ye, bx.zs, bx.ze, 0, 0, 1, 0};
+    if (bx.xe <= bx.xs || bx.ye <= bx.ys || bx.ze <= bx.zs) return m;   // no waves
+    m.strips = (bx.xe - bx.xs + 61) / 62;
+    m.groups = (bx.ye - bx.ys + ry - 1) / ry;
+    m.chunk = std::min(chunk, bx.ze - bx.zs);
+    m.chunks = (bx.ze - bx.zs + m.chunk - 1) / m.chunk;
+    return m;
+}
+
+static int64_t mbox_waves(const dpmlk::MBox &m) { return (int64_t)m.strips * m.groups * m.chunks; }
+
+template <typename T, int RYC, int PF>
+static void plan_launch(bool nt, int ord, dim3 g, hipStream_t st, const dpmlk::StepArgs<T> &p,
+                        const dpmlk::MPlan &pl)
+{
+    if (ord) {
+        if (nt) hipLaunchKernelGGL((dpmlk::k_march3d_plan<T, RYC, PF, true, 1>), g, dim3(256), 0, st, p, pl);
+        else hipLaunchKernelGGL((dpmlk::k_march3d_plan<T, RYC, PF, false, 1>), g, dim3(256), 0, st, p, pl);
+    } else {
+        if (nt) hipLaunchKernelGGL((dpmlk::k_march3d_plan<T, RYC, PF, true, 0>), g, dim3(256), 0, st, p, pl);
+        else hipLaunchKernelGGL((dpmlk::k_march3d_plan<T, RYC, PF, false, 0>), g, dim3(256), 0, st, p, pl);
+    }
+}
+
+// One k_march3d_plan launch over the boxes of `pl` (wave offsets filled in
+// here); `bytes` is the algorithmic byte count it reports when timed.
+template <typename T>
+static int launch_plan(dpml *H, const dpmlk::StepArgs<T> &p, dpmlk::MPlan pl, const MShape &s, hipStream_t st,
+                       int kind, double bytes)
+{
+    int64_t w = 0;
+    for (int i = 0; i < 4; ++i) {
+        w += mbox_waves(pl.b[i]);
+        pl.w[i] = (int32_t)w;
+    }
+    if (w == 0) return DPML_OK;
+    if (w > ((int64_t)1 << 30)) return H->fail(DPML_EINVAL, "3D grid too large for one marching launch");
+    const dim3 g((unsigned)round8((int)((w + 3) / 4)), (unsigned)H->L.batch);
+    const int slot = H->timing ? timed_begin(H, kind, bytes, st) : -1;
+    if (s.ry == 8) {
+        if (s.pf == 2) plan_launch<T, 8, 2>(s.nt, s.ord, g, st, p, pl);
+        else plan_launch<T, 8, 1>(s.nt, s.ord, g, st, p, pl);
+    } else if (s.ry == 2) {
+        if (s.pf == 2) plan_launch<T, 2, 2>(s.nt, s.ord, g, st, p, pl);
+        else plan_launch<T, 2, 1>(s.nt, s.ord, g, st, p, pl);
+    } else if (s.ry == 1) {
+        if (s.pf == 2) plan_launch<T, 1, 2>(s.nt, s.ord, g, st, p, pl);
+        else plan_launch<T, 1, 1>(s.nt, s.ord, g, st, p, pl);
+    } else {
+        if (s.pf == 2) plan_launch<T, 4, 2>(s.nt, s.ord, g, st, p, pl);
+        else plan_launch<T, 4, 1>(s.nt, s.ord, g, st, p, pl);
+    }
+    if (slot >= 0) timed_end(H, slot, st);
+    return DPML_OK;
+}
+
+// 3D marching step of periodic grids by k_march3d_plan, as boxes that
+// partition the grid (per axis a with a layer, "inner" = [lo+1, lo+n), the
+// cells no a damping term reaches; an axis without a layer is inner over
+// its whole extent):
+//   y band  rows [lo+n, lo+n+M] (wrapped), every column and plane: all layer code;
+//   z band  inner rows, planes [lo+n, lo+n+M], every column: x and z layer code;
+//   x band  columns [lo+n, lo+n+M], inner rows and planes: x layer code;
+//   core    inner columns, rows and planes: no layer code.
+// By default all four boxes are one launch (the layer boxes' waves first);
+// split shapes run the core on the handle's stream and the layer boxes as a
+// second launch on the side stream beside it.
+template <typename T>
+static int launch_mstep3d(dpml *H, const dpmlk::StepArgs<T> &p, const MShape &s)
+{
+    const Layout &L = H->L;
+    int in0[3], in1[3], bb[3];
+    for (int a = 0; a < 3; ++a) {
+        bb[a] = L.lo[a] + (int)L.n[a];
+        if (L.M[a] == 0) {
+            in0[a] = 0;
+            in1[a] = (int)L.N[a];
+        } else {
+            in0[a] = L.lo[a] + 1;
+            in1[a] = L.lo[a] + (int)L.n[a];
+        }
+    }
+    const int NX = (int)L.N[0], NZ = (int)L.N[2];
+    const dpmlk::Box3 by{0, NX, bb[1], bb[1] + L.M[1] + 1, 0, NZ};
+    const dpmlk::Box3 bz{0, NX, in0[1], in1[1], bb[2], bb[2] + L.M[2] + 1};
+    const dpmlk::Box3 bx{bb[0], bb[0] + L.M[0] + 1, in0[1], in1[1], in0[2], in1[2]};
+    const dpmlk::Box3 bc{in0[0], in1[0], in0[1], in1[1], in0[2], in1[2]};
+    const dpmlk::Box3 none{0, 0, 0, 0, 0, 0};
+    dpmlk::MPlan frame{}, core{};
+    frame.b[0] = make_mbox(L.M[1] > 0 ? by : none, 1, s.lchunk);
+    frame.b[1] = make_mbox(L.M[2] > 0 ? bz : none, 1, s.lchunk);
+    frame.b[2] = make_mbox(L.M[0] > 0 ? bx : none, 1, s.lchunk);
+    frame.b[3] = make_mbox(none, s.ry, s.chunk);
+    const bool layers = L.M[0] > 0 || L.M[1] > 0 || L.M[2] > 0;
+    // algorithmic bytes: the core's cells carry no layer terms, the layer
+    // boxes hold every other cell and all layer axis-cells
+    double fbytes = 0, cbytes = 0;
+    if (H->timing) {
+        cbytes = step_bytes(H, box_cells(bc), 0.0);
+        fbytes = step_bytes(H, (double)L.ncell, aux_cells(L)) - cbytes;
+    }
+    if (!s.split || !layers) {
+        dpmlk::MPlan all = frame;
+        all.b[3] = make_mbox(bc, s.ry, s.chunk);
+        const int rc = launch_plan<T>(H, p, all, s, H->stream, DPML_KERNEL_STEP, fbytes + cbytes);
+        if (rc) return rc;
+        HIP_TRY(H, hipGetLastError());
+        return DPML_OK;
+    }
+    core.b[0] = core.b[1] = core.b[2] = make_mbox(none, 1, 1);
+    core.b[3] = make_mbox(bc, s.ry, s.chunk);
+    int rc = ensure_side(H);
+    if (rc) return rc;
+    HIP_TRY(H, hipEventRecord(H->ev_fork, H->stream));
+    HIP_TRY(H, hipStreamWaitEvent(H->side, H->ev_fork, 0));
+    rc = launch_plan<T>(H, p, frame, s, H->side, DPML_KERNEL_FRAME, fbytes);
+    if (!rc) rc = launch_plan<T>(H, p, core, s, H->stream, DPML_KERNEL_CORE, cbytes);
+    if (rc) return rc;
+    HIP_TRY(H, hipEventRecord(H->ev_join, H->side));
+    HIP_TRY(H, hipStreamWaitEvent(H->stream, H->ev_join, 0));
+    HIP_TRY(H, hipGetLastError());
+    return DPML_OK;
+}
+
 template <typename T>
 int launch_march3d(dpml *H, dpmlk::StepArgs<T> p, int ry)
 {
     const Layout &L = H->L;
+    // periodic grids: the register-neighbour march (MARCH); walls and MARCH1
+    // take the box kernels below
+    if (ry != 2 && !L.wall[0] && !L.wall[1] && !L.wall[2]) return launch_mstep3d<T>(H, p, mshape(H->tile_rows));
     int b[4];
     march_box3d(L, b);
     const int NX = (int)L.N[0], NZ = (int)L.N[2];
@@ -206,13 +361,40 @@ int multistep_levels3d(const dpml *H, int64_t nsteps)
     return 2;
 }
 
-// One step over everything outside the box S (a frame step of a 3D pass):
+// One step over everything outside the box S (a frame step of a 3D pass)
+// as one k_march3d_plan launch of three boxes: the rows outside S (every
+// column and plane; all layer code), S's rows on the planes outside S (every
+// column; x and z layer code) and S's rows and planes on the columns outside
+// S (x layer code).  `bytes` is the algorithmic byte count it reports.
+template <typename T>
+static int launch_outside3d(dpml *H, const dpmlk::StepArgs<T> &p, const dpmlk::Box3 &S, double bytes,
+                            hipStream_t st, const MShape &sh)
+{
+    const Layout &L = H->L;
+    const int NX = (int)L.N[0], NY = (int)L.N[1], NZ = (int)L.N[2];
+    const dpmlk::Box3 by{0, NX, S.ye, S.ys + NY, 0, NZ};
+    const dpmlk::Box3 bz{0, NX, S.ys, S.ye, S.ze, S.zs + NZ};
+    const dpmlk::Box3 bx{S.xe, S.xs + NX, S.ys, S.ye, S.zs, S.ze};
+    const dpmlk::Box3 none{0, 0, 0, 0, 0, 0};
+    dpmlk::MPlan pl{};
+    pl.b[0] = make_mbox(S.ye - S.ys < NY ? by : none, 1, sh.lchunk);
+    pl.b[1] = make_mbox(S.ze - S.zs < NZ ? bz : none, 1, sh.lchunk);
+    pl.b[2] = make_mbox(S.xe - S.xs < NX ? bx : none, 1, sh.lchunk);
+    pl.b[3] = make_mbox(none, 4, 1);
+    MShape fs = sh;
+    fs.ry = 4;
+    return launch_plan<T>(H, p, pl, fs, st, DPML_KERNEL_FRAME, bytes);
+}
+
+// One step over everything outside the box S (a frame step of a 3D pass) by
+// the box kernels:
 // the rows outside S (every column and plane; all layer code), S's rows on
 // the planes outside S (every column; x and z layer code) and S's rows and
 // planes on the columns outside S (the x-band march).  `share` is the
 // algorithmic byte count the three launches report together.
 template <typename T>
-int launch_outside3d(dpml *H, const dpmlk::StepArgs<T> &p, const dpmlk::Box3 &S, double share, hipStream_t st)
+static int launch_outside3d_boxes(dpml *H, const dpmlk::StepArgs<T> &p, const dpmlk::Box3 &S, double share,
+                                  hipStream_t st)
 {
     const Layout &L = H->L;
     const int NX = (int)L.N[0], NY = (int)L.N[1], NZ = (int)L.N[2];
@@ -261,10 +443,16 @@ int launch_multistep3d(dpml *H)
     if (k < 2) return H->fail(DPML_EINVAL, "not enough field buffers for a multi-step pass");
     const dpmlk::Box3 c = core_box3d(L, 0), in1 = core_box3d(L, 1);
     // tile_rows: planes per chunk in the low 12 bits (0: 32), rows per wave
-    // in the bits above (4, 8 or 16; 0: 8)
+    // in bits 12-17 (4, 8 or 16; 0: 8); the frame's steps as in mshape (bits
+    // 20-27 planes per layer chunk, bit 18 non-temporal streaming) when bit
+    // 19 selects the register-neighbour march for them (else the box
+    // kernels); bit 28 tiles in launch order for both
     const int chunk = (H->tile_rows & 0xFFF) > 0 ? (H->tile_rows & 0xFFF) : 32;
-    const int ryb = (H->tile_rows >> 12) & 0xFF;
+    const int ryb = (H->tile_rows >> 12) & 0x3F;
     const int ry = (ryb == 4 || ryb == 16) ? ryb : 8;
+    const MShape fsh = mshape(H->tile_rows & ~0xFFFF);
+    const int ord = (H->tile_rows >> 28) & 1;
+    const bool frame_plan = (H->tile_rows >> 19) & 1;
     HIP_TRY(H, hipEventRecord(H->ev_fork, H->stream));
     HIP_TRY(H, hipStreamWaitEvent(H->side, H->ev_fork, 0));
     {
@@ -285,12 +473,16 @@ int launch_multistep3d(dpml *H)
         const double core = box_cells(c);
         const int slot = timed_begin(H, DPML_KERNEL_PAIR, step_bytes(H, 2 * core, 0.0));
         const dim3 grid((unsigned)round8(p.n_tiles)), block(256);
-        if (ry == 4)
-            hipLaunchKernelGGL((dpmlk::k_step2_zmarch3d<T, 4>), grid, block, 0, H->stream, p, nxt[1], c, in1, src);
-        else if (ry == 16)
-            hipLaunchKernelGGL((dpmlk::k_step2_zmarch3d<T, 16>), grid, block, 0, H->stream, p, nxt[1], c, in1, src);
-        else
-            hipLaunchKernelGGL((dpmlk::k_step2_zmarch3d<T, 8>), grid, block, 0, H->stream, p, nxt[1], c, in1, src);
+#define DPML_TWO3D(RY_, O_) \
+    hipLaunchKernelGGL((dpmlk::k_step2_zmarch3d<T, RY_, O_>), grid, block, 0, H->stream, p, nxt[1], c, in1, src)
+        if (ry == 4) {
+            if (ord) DPML_TWO3D(4, 1); else DPML_TWO3D(4, 0);
+        } else if (ry == 16) {
+            if (ord) DPML_TWO3D(16, 1); else DPML_TWO3D(16, 0);
+        } else {
+            if (ord) DPML_TWO3D(8, 1); else DPML_TWO3D(8, 0);
+        }
+#undef DPML_TWO3D
         timed_end(H, slot);
     }
     // the frame's steps on the side stream, aux buffers alternating
@@ -304,7 +496,8 @@ int launch_multistep3d(dpml *H)
         // algorithmic share: the frame's own cells (the ring cells it recomputes
         // are the core's, counted there)
         const double share = step_bytes(H, (double)L.ncell - box_cells(c), aux_cells(L));
-        int rc = launch_outside3d<T>(H, pj, core_box3d(L, 2 - j), share, H->side);
+        int rc = frame_plan ? launch_outside3d<T>(H, pj, core_box3d(L, 2 - j), share, H->side, fsh)
+                            : launch_outside3d_boxes<T>(H, pj, core_box3d(L, 2 - j), share, H->side);
         if (rc) return rc;
     }
     HIP_TRY(H, hipEventRecord(H->ev_join, H->side));

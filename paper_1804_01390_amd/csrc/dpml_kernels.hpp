@@ -1776,12 +1776,15 @@ __device__ __forceinline__ bool in_window(int s, int start, int len, int n)
     return len >= n || d < len;
 }
 
-template <typename T, int RY>
+// ORD = 1 takes tiles in launch order (the XCDs interleaved, so the whole
+// GPU marches through the same chunk of planes at a time); ORD = 0 gives
+// each XCD a consecutive run of tiles.
+template <typename T, int RY, int ORD = 0>
 __global__ void __launch_bounds__(256) k_step2_zmarch3d(StepArgs<T> p, T *__restrict__ u_next2, Box3 c, Box3 in1,
                                                         Src3<T> src)
 {
     constexpr int NR = RY + 2;                               // rows of the first level: -1 .. RY
-    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+    const int tile = ORD ? (int)blockIdx.x : xcd_tile(blockIdx.x, gridDim.x);
     if (tile >= p.n_tiles) return;
     const int per_plane = p.tiles_x * p.tiles_y;
     const int tz = tile / per_plane;

@@ -58,17 +58,22 @@ def test_tuner_candidates_are_valid_launch_shapes():
     or 4, frame form 0..15, rows within the kernels' limits)."""
     from paper_1804_01390_amd import autotune
     multi_variants = (dp.VARIANT_TWOSTEP, dp.VARIANT_THREESTEP, dp.VARIANT_FOURSTEP, dp.VARIANT_DEEP)
-    for variant, tr in autotune.CANDIDATES_2D + autotune.CANDIDATES_3D:
+    for variant, tr in autotune.CANDIDATES_2D:
         assert dp.VARIANT_AUTO <= variant <= dp.VARIANT_DEEP
         assert 0 <= tr < (1 << (25 if variant == dp.VARIANT_DEEP else 20))
+    for variant, tr in autotune.CANDIDATES_3D:       # 3D shapes take bits up to 28
+        assert dp.VARIANT_AUTO <= variant <= dp.VARIANT_DEEP
+        assert 0 <= tr < (1 << (29 if variant >= dp.VARIANT_MARCH and variant != dp.VARIANT_MARCH1 else 20))
         if variant == dp.VARIANT_DEEP:
             assert ((tr >> 20) & 0xF) in (0, 2, 3, 4, 5, 6, 7, 8)
     for variant, tr in autotune.CANDIDATES_2D:
         if variant in multi_variants:
             assert ((tr >> 12) & 0xF) in (0, 1, 2, 4) and 0 < (tr & 0xFFF) <= 4095
     for variant, tr in autotune.CANDIDATES_3D:
-        if variant in multi_variants:          # 3D passes: rows per wave in bits 12-19, planes per chunk below
-            assert ((tr >> 12) & 0xFF) in (4, 8, 16) and 0 < (tr & 0xFFF) <= 4095
+        if variant in multi_variants:          # 3D passes: rows per wave in bits 12-17, planes per chunk below
+            assert ((tr >> 12) & 0x3F) in (4, 8, 16) and 0 < (tr & 0xFFF) <= 4095
+        if variant == dp.VARIANT_MARCH:        # marching steps: rows per core wave in bits 12-15
+            assert ((tr >> 12) & 0xF) in (1, 2, 4, 8) and ((tr >> 16) & 3) in (0, 1, 2)
     for variant, rows, group in autotune.CANDIDATES_MULTI:
         assert variant in (dp.VARIANT_MARCH,) + multi_variants
         assert group in (1, 2, 4)

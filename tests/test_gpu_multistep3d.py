@@ -44,7 +44,11 @@ def _case(name, rng):
 
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
 @pytest.mark.parametrize("case", ["ragged", "z_periodic", "x_periodic"])
-@pytest.mark.parametrize("tile_rows", [0, (4 << 12) | 5, (16 << 12) | 7, (8 << 12) | 64])
+@pytest.mark.parametrize("tile_rows", [0, (4 << 12) | 5, (16 << 12) | 7, (8 << 12) | 64,
+                                       # launch-order tiles; the marching frame (bit 19) with layer
+                                       # chunks (bits 20-27) and non-temporal streaming (bit 18)
+                                       (1 << 28) | (16 << 12) | 32, (1 << 28) | (1 << 19) | (8 << 20) | (4 << 12) | 16,
+                                       (1 << 19) | (1 << 18) | (3 << 20) | (8 << 12) | 9])
 def test_3d_twostep_bit_identical_and_oracle(dtype, case, tile_rows):
     rng = np.random.default_rng(17)
     n, lo, hi, sig, U0 = _case(case, rng)
@@ -121,25 +125,29 @@ def test_3d_twostep_sources_receivers_plane(dtype, where):
 def test_3d_twostep_timing_counts_and_bytes():
     """Per-launch timing of a 3D two-step run: one core launch per pass
     counting both levels of the core's cells, three frame launches per frame
-    step, and the frame's share of the byte model per pass."""
+    step (box kernels) or one (the marching frame, bit 19), and the frame's
+    share of the byte model per pass."""
     rng = np.random.default_rng(4)
     n, lo, hi, sig, U0 = _case("ragged", rng)
     N = [lo[a] + n[a] + hi[a] for a in range(3)]
     sim = dp.Simulation(n, lo, hi, 1.0, 0.4, sig, dtype=torch.float32)
-    sim.set_variant(dp.VARIANT_TWOSTEP, 0)
-    sim.set_state(torch.from_numpy(U0))
-    sim.set_timing(True)
-    sim.step(8)
-    t = sim.get_timing()
+    t = {}
+    for form in (0, 1 << 19):
+        sim.set_variant(dp.VARIANT_TWOSTEP, form)
+        sim.set_state(torch.from_numpy(U0))
+        sim.set_timing(True)
+        sim.step(8)
+        t[form] = sim.get_timing()
     sim.close()
     core = [n[a] - 3 for a in range(3)]                  # [lo+2, lo+n-1) per axis
     core_cells = core[0] * core[1] * core[2]
     cells = N[0] * N[1] * N[2]
     aux = sum((lo[a] + hi[a]) * cells // N[a] for a in range(3))
-    assert t["pair"]["launches"] == 4
-    assert t["pair"]["bytes"] == pytest.approx(4 * 2 * 3 * core_cells * 4, rel=1e-12)
-    assert t["frame"]["launches"] == 4 * 2 * 3
-    assert t["frame"]["bytes"] == pytest.approx(4 * 2 * (3 * (cells - core_cells) + 4 * aux) * 4, rel=1e-9)
+    for form, per_step in ((0, 3), (1 << 19, 1)):
+        assert t[form]["pair"]["launches"] == 4
+        assert t[form]["pair"]["bytes"] == pytest.approx(4 * 2 * 3 * core_cells * 4, rel=1e-12)
+        assert t[form]["frame"]["launches"] == 4 * 2 * per_step
+        assert t[form]["frame"]["bytes"] == pytest.approx(4 * 2 * (3 * (cells - core_cells) + 4 * aux) * 4, rel=1e-9)
 
 
 def test_3d_twostep_graph_replay_matches_eager():
