@@ -306,20 +306,40 @@ int orc_wave_run(const orc_grid *g, double *U, double *Uprev, int64_t nsteps)
     memcpy(u[0], U, bytes);
     memcpy(u[1], Uprev, bytes);
     int inow = 0, iold = 1, inew = 2;
+    const int64_t rows = g->N[1] * g->N[2];
     for (int64_t k = 0; k < nsteps; ++k) {
         const double *un = u[inow], *uo = u[iold];
         double *uw = u[inew];
+        /* one row of cells (fixed y, z) per iteration: the same per-cell
+         * expression, without recovering the coordinates by division */
         #pragma omp parallel for schedule(static)
-        for (int64_t c = 0; c < n; ++c) {
-            int64_t ii[3];
-            double lap = 0.0;
-            orc_coords(g, c, ii);
-            for (int a = 0; a < g->ndim; ++a) {
-                int64_t cp = orc_shift(g, c, ii, a, +1);
-                int64_t cm = orc_shift(g, c, ii, a, -1);
-                lap += (orc_at(un, cm) - 2.0 * un[c] + orc_at(un, cp)) / (g->h * g->h);
+        for (int64_t r = 0; r < rows; ++r) {
+            const int64_t N0 = g->N[0], base = r * N0;
+            int64_t ii[3] = {0, r % g->N[1], r / g->N[1]};
+            /* the rows above/below and the planes before/after (index of the
+             * row's first cell; -1 for a ghost row past a wall) */
+            int64_t nb[3][2] = {{0, 0}, {0, 0}, {0, 0}};
+            for (int a = 1; a < g->ndim; ++a) {
+                nb[a][0] = orc_shift(g, base, ii, a, -1);
+                nb[a][1] = orc_shift(g, base, ii, a, +1);
             }
-            uw[c] = 2.0 * un[c] - uo[c] + dt2 * (g->c2 ? g->c2[c] : 1.0) * lap;
+            const double h2 = g->h * g->h;
+            for (int64_t x = 0; x < N0; ++x) {
+                const int64_t c = base + x;
+                double lap = 0.0;
+                ii[0] = x;
+                {
+                    int64_t cp = orc_shift(g, c, ii, 0, +1);
+                    int64_t cm = orc_shift(g, c, ii, 0, -1);
+                    lap += (orc_at(un, cm) - 2.0 * un[c] + orc_at(un, cp)) / h2;
+                }
+                for (int a = 1; a < g->ndim; ++a) {
+                    double um = nb[a][0] < 0 ? 0.0 : un[nb[a][0] + x];
+                    double up = nb[a][1] < 0 ? 0.0 : un[nb[a][1] + x];
+                    lap += (um - 2.0 * un[c] + up) / h2;
+                }
+                uw[c] = 2.0 * un[c] - uo[c] + dt2 * (g->c2 ? g->c2[c] : 1.0) * lap;
+            }
         }
         int t = iold; iold = inow; inow = inew; inew = t;
     }

@@ -207,26 +207,36 @@ class Workload:
         return int(np.prod(self.N))
 
 
-def bump2d(n: int = 128, m: int = 16, steps: int = 500, smax: float = 2.0,
+def bump2d(n=128, m=16, steps: int = 500, smax: float = 2.0,
            width: float = 4.0, h: float = 1.0, courant: float = 0.5) -> Workload:
     """2D, n x n interior + m-cell layer on each side, h = 1, c = 1,
     dt = courant * h, quadratic ramp to smax, centred Gaussian bump (zero
-    velocity).  Defaults: the 128^2 + 16-cell, 500-step parity case."""
-    sig = sigma_ramp(n, m, m, smax)
-    U0 = gaussian_bump([n, n], [m, m], [m, m], width)
-    return Workload("bump2d_%d_m%d" % (n, m), [n, n], [m, m], [m, m], h, courant * h,
-                    steps, [sig, sig.copy()], U0)
+    velocity).  ``n`` may be a pair (nx, ny) for a rectangular interior.
+    Defaults: the 128^2 + 16-cell, 500-step parity case."""
+    nx, ny = (n, n) if np.isscalar(n) else (int(n[0]), int(n[1]))
+    sx = sigma_ramp(nx, m, m, smax)
+    sy = sigma_ramp(ny, m, m, smax)
+    U0 = gaussian_bump([nx, ny], [m, m], [m, m], width)
+    name = "bump2d_%d_m%d" % (nx, m) if nx == ny else "bump2d_%dx%d_m%d" % (nx, ny, m)
+    return Workload(name, [nx, ny], [m, m], [m, m], h, courant * h, steps, [sx, sy], U0)
 
 
 def bumps2d(n: int = 4096, m: int = 32, steps: int = 2000, seed: int = 0,
-            count: int = 64, courant: float = 0.5, h: float = 1.0) -> Workload:
+            count: int = 64, courant: float = 0.5, h: float = 1.0, margin: int = 0) -> Workload:
     """2D, n x n interior + m-cell layer per side, c = 1, dt = courant * h,
     quadratic ramp to 2/h, U0 = sum of ``count`` Gaussians (widths U(2,8) h,
     amplitudes N(0,1), uniform centres) from ``seed``.  Defaults: the
-    4096^2 + 32-cell, 2000-step throughput case."""
+    4096^2 + 32-cell, 2000-step throughput case.  ``margin`` > 0 also zeroes
+    U0 on the ``margin`` interior cells next to every layer interface (data
+    that starts in the physical domain, away from the layer: the setting of
+    the free-space reflection measurement)."""
     rng = np.random.default_rng(seed)
     sig = sigma_ramp(n, m, m, 2.0 / h)
     U0 = gaussian_sum([n, n], [m, m], [m, m], count, 2.0, 8.0, rng)
+    if margin > 0:
+        keep = np.zeros_like(U0, dtype=bool)
+        keep[m + margin:m + n - margin, m + margin:m + n - margin] = True
+        U0[~keep] = 0.0
     return Workload("bumps2d_%d_m%d" % (n, m), [n, n], [m, m], [m, m], h, courant * h,
                     steps, [sig, sig.copy()], U0)
 
@@ -253,16 +263,18 @@ def ricker3d(n: int = 512, m: int = 24, steps: int = 1000, courant: float = 0.4,
 def batch2d(count: int = 256, seed: int = 0, steps: int = 1500, smin: int = 256,
             smax_side: int = 1536, mmin: int = 16, mmax: int = 32,
             courant: float = 0.5) -> List[Workload]:
-    """``count`` independent 2D problems: side round(exp(U(ln smin, ln smax))),
-    layer width uniform in {mmin..mmax}, quadratic ramp to 2/h, one centred
-    Gaussian (width 4) each."""
+    """``count`` independent 2D problems: each of the two interior sides
+    round(exp(U(ln smin, ln smax))) drawn independently (x sides first, then
+    y sides), layer width uniform in {mmin..mmax}, quadratic ramp to 2/h, one
+    centred Gaussian (width 4) each."""
     rng = np.random.default_rng(seed)
-    sides = np.round(np.exp(rng.uniform(math.log(smin), math.log(smax_side), size=count))).astype(int)
+    sx = np.round(np.exp(rng.uniform(math.log(smin), math.log(smax_side), size=count))).astype(int)
+    sy = np.round(np.exp(rng.uniform(math.log(smin), math.log(smax_side), size=count))).astype(int)
     ms = rng.integers(mmin, mmax + 1, size=count)
     out = []
     for b in range(count):
-        w = bump2d(int(sides[b]), int(ms[b]), steps, 2.0, 4.0, 1.0, courant)
-        w.name = "batch%d_%d_m%d" % (b, sides[b], ms[b])
+        w = bump2d((int(sx[b]), int(sy[b])), int(ms[b]), steps, 2.0, 4.0, 1.0, courant)
+        w.name = "batch%d_%dx%d_m%d" % (b, sx[b], sy[b], ms[b])
         out.append(w)
     return out
 

@@ -6,7 +6,7 @@ import pytest
 
 import oracle
 import synthetic
-from helpers import rel_err
+from helpers import compare_states, multi_state, rel_err, run_with_peaks
 
 torch = pytest.importorskip("torch")
 dp = pytest.importorskip("paper_1804_01390_amd")
@@ -15,6 +15,7 @@ pytestmark = pytest.mark.gpu
 
 
 def _problems(sides, ms, seed=0):
+    """One centred bump per problem; a side given as a pair is (nx, ny)."""
     out = []
     for b, (s, m) in enumerate(zip(sides, ms)):
         w = synthetic.bump2d(s, m, 0, 2.0, 4.0, 1.0, 0.5)
@@ -22,9 +23,23 @@ def _problems(sides, ms, seed=0):
     return out
 
 
+def _check_problems(sim, probs, steps, dtype):
+    """Every problem's U, U^{n-1} and Phi_a/Psi_a (on their supports) against
+    its own oracle run; FP32 normalised by each field's peak over the run."""
+    f64 = dtype == torch.float64
+    tol = 1e-12 if f64 else 2e-5
+    for i, w in enumerate(probs):
+        g = oracle.Grid(w.N, w.h, w.dt, w.sigma)
+        ref, _, peaks = run_with_peaks(g, oracle.start(g, w.U0), steps, w.n, w.lo, w.hi)
+        errs = compare_states(multi_state(sim, i, w), ref, w.n, w.lo, w.hi, None if f64 else peaks)
+        print("problem", i, w.N, {k: "%.2e" % v for k, v in errs.items()}, flush=True)
+        for k, v in errs.items():
+            assert v <= tol, (i, k, v)
+
+
 @pytest.mark.parametrize("dtype,sides", [
-    (torch.float64, [64, 130, 257, 96, 300]),      # one odd extent: vector width 1
-    (torch.float32, [64, 130, 256, 96, 300]),      # all even: 8-byte vectors
+    (torch.float64, [64, (130, 77), 257, (96, 180), 300]),      # odd extents: vector width 1
+    (torch.float32, [64, (130, 76), 256, (96, 180), (300, 120)]),  # all even: 8-byte vectors
 ])
 def test_multi_matches_oracle(dtype, sides):
     ms = [8, 13, 16, 9, 20]
@@ -35,14 +50,7 @@ def test_multi_matches_oracle(dtype, sides):
     steps = 90
     sim.step(steps)
     sim.sync()
-    tol = 1e-12 if dtype == torch.float64 else 2e-5
-    for i, w in enumerate(probs):
-        g = oracle.Grid(w.N, w.h, w.dt, w.sigma)
-        ref, _ = oracle.run(g, oracle.start(g, w.U0), steps)
-        got = sim.field(i, dp.FIELD_U).double().cpu().numpy()
-        err = rel_err(got, ref.U)
-        print("problem", i, "err %.2e" % err, flush=True)
-        assert err <= tol
+    _check_problems(sim, probs, steps, dtype)
     sim.close()
 
 
@@ -153,8 +161,8 @@ def test_multi_tuner_picks_a_candidate_and_keeps_the_state(tmp_path):
 @pytest.mark.parametrize("variant,rows", [(dp.VARIANT_TWOSTEP, 0), (dp.VARIANT_THREESTEP, 0),
                                           (dp.VARIANT_FOURSTEP, 0), (dp.VARIANT_DEEP, 6 << 20),
                                           (dp.VARIANT_DEEP, 8 << 20)])
-@pytest.mark.parametrize("dtype,sides", [(torch.float64, [64, 130, 257, 96, 300]),
-                                         (torch.float32, [64, 131, 256, 97, 300])])
+@pytest.mark.parametrize("dtype,sides", [(torch.float64, [64, (130, 211), 257, 96, (300, 71)]),
+                                         (torch.float32, [(64, 150), 131, 256, (97, 40), 300])])
 def test_multi_twostep_matches_oracle_and_graph(dtype, sides, variant, rows):
     """Passes of 2, 3, 4, 6 and 8 levels over all problems (cores in one launch,
     frames on a second stream) against the oracle per problem, eagerly and as
@@ -170,12 +178,5 @@ def test_multi_twostep_matches_oracle_and_graph(dtype, sides, variant, rows):
         _ = torch.ones(1000, device="cuda").sum().item()
     steps = 90
     sim.sync()
-    tol = 1e-12 if dtype == torch.float64 else 2e-5
-    for i, w in enumerate(probs):
-        g = oracle.Grid(w.N, w.h, w.dt, w.sigma)
-        ref, _ = oracle.run(g, oracle.start(g, w.U0), steps)
-        got = sim.field(i, dp.FIELD_U).double().cpu().numpy()
-        err = rel_err(got, ref.U)
-        print("problem", i, "err %.2e" % err, flush=True)
-        assert err <= tol
+    _check_problems(sim, probs, steps, dtype)
     sim.close()
