@@ -1,20 +1,28 @@
 """Throughput benchmark of the fused discrete-PML step on one MI355X.
 
-Workload: 2D, 4096 x 4096 interior + 32-cell layer on every side (4160^2
-cells), c = 1, dt = h/2, damping ramping quadratically to 2/h, initial field
-a seeded sum of 64 Gaussians (widths 2-8 h) at rest.  A step is one full
-pass of the method over the grid: U by leapfrog with the layer terms, and
-Phi_a, Psi_a of both axes, fused in one kernel.  The default run times the
-workload's 2000 steps in FP32 (the reported value) and in FP64.
+Headline workload: 3D, 512^3 interior + 24-cell layer on all six faces
+(560^3 cells), FP64 (the precision of the paper's runs), c = 1, dt = 0.4 h,
+damping ramping quadratically to 2/h, a Ricker point source at the centre
+(15 points per wavelength) and the z plane through it recorded every step.
+A step is one full pass of the method over the grid: U by leapfrog with the
+layer terms, Phi_a and Psi_a of all three axes, the source and the plane.
+The timed region is exactly --steps steps of the workload from rest (steps
+0 .. K-1 of its 1000), launched as the tuned launch shape.
 
 Prints ONE JSON line:
-  value         Gcell-updates/s (all 4160^2 cells per step, layer included)
-  roofline      the dominant step kernel: algorithmic bytes per launch over its
-                mean launch duration (HIP events around each launch, on the
-                library's stream) vs 8 TB/s
+  value         Gcell-updates/s (all 560^3 cells per step, layer included)
+  roofline      the dominant step kernel of the headline: its algorithmic
+                bytes per launch (a single step: 3 words per cell + 4 per layer
+                axis-cell; a multi-step pass's core: 4 words per core cell)
+                over its mean launch duration (HIP events around each launch,
+                on the stream it runs on) vs 8 TB/s, with the HBM bytes the
+                rocprofv3 counters measured for that kernel when a summary for
+                the current sources is committed under profiles/
   cpu_baseline  the FP64 CPU oracle on a bounded sample of the same workload
+  runs          the headline and the secondary single-grid records (3D FP32,
+                the 2D 4160^2 workload in FP32 and FP64)
 
-    python bench.py [--gpus 1] [--steps 2000] [--warmup 50]
+    python bench.py [--gpus 1] [--steps 1000] [--warmup 20]
 """
 import argparse
 import json
@@ -104,38 +112,61 @@ def time_gpu(w, dtype_name, steps, warmup, variant=0, tile_rows=0):
             "finite": ok, "launch": launch}
 
 
-def roofline_from_timing(kernels, timed_steps):
+def roofline_from_timing(kernels, timed_steps, workload=None, dtype_name=None):
     """Roofline of the dominant step kernel from the library's per-launch
     timing: its algorithmic bytes per launch over its mean launch duration.
     The dominant kernel is the class that moves the most algorithmic bytes:
     frame launches run on a second stream beside the core, so their event
     durations include time spent sharing the GPU and are no measure of which
-    kernel carries the step."""
+    kernel carries the step.  With a committed counter summary for this
+    workload, dtype and kernel class (and the current sources), ``traffic`` is
+    the HBM bytes per launch it measured and ``hbm_GBps``/``hbm_frac`` that
+    traffic over the same mean duration."""
     name, k = max(((n, v) for n, v in kernels.items() if v["launches"]), key=lambda kv: kv[1]["bytes"])
     ms = k["ms"] / k["launches"]
     bpl = k["bytes"] / k["launches"]
     achieved = bpl / (ms * 1e-3) / 1e9
-    return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "kernel": name,
-            "alg_bytes_per_launch": int(round(bpl)), "kernel_ms_mean": round(ms, 5),
-            "launches": k["launches"], "timed_steps": timed_steps}
+    out = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+           "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": name,
+           "alg_bytes_per_launch": int(round(bpl)), "kernel_ms_mean": round(ms, 5),
+           "launches": k["launches"], "timed_steps": timed_steps}
+    if workload:
+        t = traffic_from_profile(workload, dtype_name, name)
+        if t:
+            out["traffic"] = int(t)
+            out["hbm_GBps"] = round(t / (ms * 1e-3) / 1e9, 1)
+            out["hbm_frac"] = round(t / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
+    return out
 
 
-def cpu_baseline(w, sample_steps: int):
-    """The FP64 oracle on the same workload for `sample_steps` steps."""
+def cpu_baseline(w, sample_steps: int, U0=None):
+    """The FP64 oracle on the same workload (its sources included) for
+    `sample_steps` steps from rest."""
     import oracle
     threads = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or os.cpu_count()
     os.environ["OMP_NUM_THREADS"] = str(threads)
     g = oracle.Grid(w.N, w.h, w.dt, w.sigma)
-    s = oracle.start(g, w.U0)
-    oracle.run(g, s, 1)            # page in, spin up threads
+    U0 = w.U0 if w.U0 is not None else np.zeros(tuple(reversed(w.N)))
+    s = oracle.start(g, U0)
+    kw = {}
+    if w.sources:
+        kw = {"sources": w.sources, "wavelets": w.wavelets, "nt": w.wavelets.shape[1]}
+    # a run copies the state in and out of private buffers; the time of a
+    # run of no steps (the same copies) is taken off a run of sample_steps
+    oracle.run(g, s, 0, **kw)
     t = time.perf_counter()
-    oracle.run(g, s, sample_steps)
-    dt = time.perf_counter() - t
+    oracle.run(g, s, 0, **kw)
+    t0 = time.perf_counter() - t
+    t = time.perf_counter()
+    oracle.run(g, s, sample_steps, **kw)
+    t1 = time.perf_counter() - t
+    dt = t1 - t0
+    shape = "x".join(str(n) for n in w.N)
     return {"value": round(sample_steps * w.cells / dt / 1e9, 5), "unit": "Gcell/s", "cores": threads,
             "kind": "oracle",
-            "sample": "%d steps of the same %dx%d-cell workload, FP64, OpenMP over cells"
-                      % (sample_steps, w.N[0], w.N[1]),
+            "sample": "%d steps (from rest, source included) of the same %s-cell workload, FP64, OpenMP over "
+                      "cells; a %d-step run (%.1f s) minus a run of no steps (%.1f s: the state copies)"
+                      % (sample_steps, shape, sample_steps, t1, t0),
             "seconds": round(dt, 3)}
 
 
@@ -158,27 +189,28 @@ def traffic_from_profile(workload: str, dtype_name: str, kernel: str):
 
 
 def copy_probe(mib: int = 1024, reps: int = 20):
-    """A plain device copy of known size (torch's copy kernel): the achievable
-    read+write bandwidth on this GPU and the reference for scaling the HBM
-    counters of rocprofv3 (FETCH_SIZE / WRITE_SIZE) to bytes."""
+    """The library's streaming probe (read-only, write-only, copy; plain and
+    non-temporal) over a buffer of known size: the bandwidth HBM gives a
+    plain streaming kernel on this GPU, and the reference for scaling the
+    rocprofv3 counters FETCH_SIZE / WRITE_SIZE to bytes."""
     import torch
-    n = mib * (1 << 20) // 4
-    a = torch.ones(n, dtype=torch.float32, device="cuda")
-    b = torch.empty_like(a)
-    for _ in range(3):
-        b.copy_(a)
-    torch.cuda.synchronize()
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    e0.record()
-    for _ in range(reps):
-        b.copy_(a)
-    e1.record()
-    torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1) / reps
-    gbs = 2 * n * 4 / (ms * 1e-3) / 1e9
-    print(json.dumps({"copy_probe_bytes_read": n * 4, "copy_probe_bytes_written": n * 4,
-                      "ms": round(ms, 4), "GB_per_s": round(gbs, 1)}), flush=True)
+    import paper_1804_01390_amd as dp
+    nb = mib << 20
+    src = torch.empty(nb, dtype=torch.uint8, device="cuda")
+    src.random_(0, 255)
+    dst = torch.empty(nb, dtype=torch.uint8, device="cuda")
+    out = {"probe_bytes": nb}
+    for kind, name in ((dp.PROBE_READ, "read"), (dp.PROBE_WRITE, "write"), (dp.PROBE_COPY, "copy")):
+        for nt in (0, dp.PROBE_NONTEMPORAL):
+            best = 0.0
+            for bpc in (1, 2, 4, 8):
+                dp.bandwidth_probe(kind | nt, nb, reps=2, blocks_per_cu=bpc, buffers=(dst, src))
+                ms = dp.bandwidth_probe(kind | nt, nb, reps=reps, blocks_per_cu=bpc, buffers=(dst, src))
+                gbs = nb * (2 if kind == dp.PROBE_COPY else 1) / (ms * 1e-3) / 1e9
+                out["%s%s_b%d_GBps" % (name, "_nt" if nt else "", bpc)] = round(gbs, 1)
+                best = max(best, gbs)
+            out["%s%s_best_GBps" % (name, "_nt" if nt else "")] = round(best, 1)
+    print(json.dumps(out), flush=True)
 
 
 def _events():
@@ -186,52 +218,67 @@ def _events():
     return torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
 
 
-def bench_ricker3d(steps: int):
-    """3D, 512^3 interior + 24-cell layer on all faces (560^3 cells), FP32,
+def bench_ricker3d(steps: int, warmup: int, dtype_name: str = "f64"):
+    """3D, 512^3 interior + 24-cell layer on all faces (560^3 cells),
     dt = 0.4 h, Ricker point source at the centre, the z plane through it
-    recorded every step."""
+    recorded every step: `steps` steps of the workload from rest, after
+    `warmup` untimed steps, in the tuned launch."""
     import torch
     import paper_1804_01390_amd as dp
     import synthetic
     from paper_1804_01390_amd import autotune
-    w = synthetic.ricker3d(n=512, m=24, steps=steps)
-    sim = dp.Simulation(w.n, w.lo, w.hi, w.h, w.dt, w.sigma, dtype=torch.float32)
-    sim.set_state(torch.zeros(tuple(reversed(w.N)), dtype=torch.float32, device="cuda"))
-    sim.inject(w.sources, torch.from_numpy(w.wavelets))
+    w = synthetic.ricker3d(n=512, m=24, steps=1000)
+    dtype = torch.float32 if dtype_name == "f32" else torch.float64
+    esize = 4 if dtype_name == "f32" else 8
+    if steps > w.steps:
+        raise SystemExit("the 3D workload has %d steps" % w.steps)
+    sim = dp.Simulation(w.n, w.lo, w.hi, w.h, w.dt, w.sigma, dtype=dtype)
+    rest = lambda: torch.zeros(tuple(reversed(w.N)), dtype=dtype, device="cuda")
+    sim.set_state(rest())
+    sim.inject(w.sources, torch.from_numpy(w.wavelets).to(dtype))
     axis, index = w.plane
     sim.record_plane(axis, index, w.steps)
     choice = autotune.tune(sim, steps=10)
-    sim.step(5)
+    sim.set_state(rest())
+    sim.step(warmup)
     sim.sync()
+    # restart from rest so the timed run is the workload's steps 0 .. steps-1
+    sim.set_state(rest())
+    sim.sync()
+    torch.cuda.synchronize()
     e0, e1 = _events()
-    # restart from rest so the timed run is the workload's steps 0..steps-1
-    sim.set_state(torch.zeros(tuple(reversed(w.N)), dtype=torch.float32, device="cuda"))
-    sim.sync()
     e0.record()
-    sim.step(w.steps)
+    sim.step(steps)
     e1.record()
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1)
     plane_cells = w.N[0] * w.N[1]
-    ab = alg_bytes_per_step(w, 4) + plane_cells * 4
-    peak = float(sim._keep["planes"][-1].abs().max().item())
-    # the step kernel alone (library launch timing), on a restarted run
-    sim.set_state(torch.zeros(tuple(reversed(w.N)), dtype=torch.float32, device="cuda"))
+    ab = alg_bytes_per_step(w, esize) + plane_cells * esize
+    peak = float(sim._keep["planes"][steps - 1].abs().max().item())
+    # per-launch durations of the step kernels on a restarted run (library
+    # events on each launch's stream; timing is off in the timed region)
+    k = max(2, min(steps, 50) // 2 * 2)
+    sim.set_state(rest())
     sim.set_timing(True)
-    sim.step(50)
-    roof = roofline_from_timing(sim.get_timing(), 50)
+    sim.step(k)
+    kernels = sim.get_timing()
     sim.set_timing(False)
-    roof["traffic"] = traffic_from_profile("ricker3d_512_m24", "f32", roof["kernel"])
-    roof["path_alg_GBps"] = round(ab * w.steps / (ms * 1e-3) / 1e9, 1)
+    roof = roofline_from_timing(kernels, k, "ricker3d_512_m24", dtype_name)
+    roof["path_alg_GBps"] = round(ab * steps / (ms * 1e-3) / 1e9, 1)
     sim.close()
-    return {"workload": "3D 512^3 interior + 24-cell layer (560^3 cells), FP32, Ricker source, "
-                        "plane recorded every step, %d steps" % w.steps,
-            "value": round(w.cells * w.steps / (ms * 1e-3) / 1e9, 3), "unit": "Gcell/s",
-            "ms_per_step": round(ms / w.steps, 5),
-            "alg_GBps": round(ab * w.steps / (ms * 1e-3) / 1e9, 1),
-            "frac_of_8TBps": round(ab * w.steps / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
-            "last_plane_peak": peak, "roofline": roof,
-            "launch": {"variant": choice["variant"], "tile_rows": choice["tile_rows"], "autotuned": True}}
+    return {"dtype": dtype_name,
+            "workload": "3D 512^3 interior + 24-cell layer on all six faces (560^3 cells), %s, c=1, dt=0.4h, "
+                        "quadratic damping ramp to 2/h, Ricker point source at the centre (15 points per "
+                        "wavelength), the z plane through it recorded every step; steps 0..%d of the workload's "
+                        "%d timed after %d warmup steps" % (dtype_name.upper(), steps - 1, w.steps, warmup),
+            "cells": w.cells, "steps": steps,
+            "value": round(w.cells * steps / (ms * 1e-3) / 1e9, 3), "unit": "Gcell/s",
+            "ms_per_step": round(ms / steps, 5),
+            "alg_bytes_per_step": ab,
+            "alg_GBps": round(ab * steps / (ms * 1e-3) / 1e9, 1),
+            "plane_peak": peak, "roofline": roof, "kernels": kernels,
+            "launch": {"variant": choice["variant"], "tile_rows": choice["tile_rows"], "autotuned": True,
+                       "cached": choice["cached"]}}
 
 
 def bench_rk4(steps: int = 200):
@@ -441,26 +488,46 @@ def bench_adjoint(steps: int, shots: int):
             "launch": {"variant": choice["variant"], "tile_rows": choice["tile_rows"], "autotuned": True}}
 
 
+def bench_2d(dn: str, steps: int, warmup: int, variant: int = 0, tile_rows: int = 0):
+    """The 2D 4096^2 + 32-cell workload (64 seeded Gaussians), `steps` of its
+    2000 steps, tuned launch, eager or as one graph replay (the faster)."""
+    import synthetic
+    w = synthetic.bumps2d(n=4096, m=32, steps=2000, seed=0)
+    r = time_gpu(w, dn, steps, warmup, variant, tile_rows)
+    roof = roofline_from_timing(r["kernels"], r["timed_steps"], w.name, dn)
+    # the whole path: algorithmic bytes per step over the measured time per step
+    # (kernels of a step may overlap on two streams, so this is not their sum)
+    roof["path_alg_GBps"] = round(alg_bytes_per_step(w, 4 if dn == "f32" else 8) / (r["ms_per_step"] * 1e-3) / 1e9, 1)
+    return {"dtype": dn,
+            "workload": "2D 4096^2 interior + 32-cell layer per side (4160^2 cells), 64 seeded Gaussians, "
+                        "%s, c=1, dt=h/2, quadratic damping ramp to 2/h; %d of the workload's 2000 steps timed "
+                        "after %d warmup steps" % (dn.upper(), steps, warmup),
+            "cells": w.cells, "steps": steps,
+            "value": round(w.cells * steps / (r["total_ms"] * 1e-3) / 1e9, 3),
+            "ms_per_step": round(r["ms_per_step"], 5), "roofline": roof, "kernels": r["kernels"],
+            "finite": r["finite"], "launch": r["launch"]}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=2000)
-    ap.add_argument("--warmup", type=int, default=50)
-    ap.add_argument("--cpu-steps", type=int, default=160)   # ~10 s of the oracle on 16 host cores
+    ap.add_argument("--steps", type=int, default=1000,
+                    help="steps timed of each single-grid workload (the 3D headline has 1000)")
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--cpu-steps", type=int, default=2)     # ~15 s of the oracle on 16 host cores
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--dtypes", default="f32,f64")
-    ap.add_argument("--variant", type=int, default=0)
+    ap.add_argument("--variant", type=int, default=0, help="2D records: fixed variant instead of the tuner")
     ap.add_argument("--tile-rows", type=int, default=0)
     ap.add_argument("--copy-probe", action="store_true",
-                    help="only time a plain 1 GiB device copy and exit")
+                    help="only run the streaming bandwidth probe and exit")
     ap.add_argument("--quick", action="store_true",
-                    help="only the 4160^2 workload (skip the 3D, batched and adjoint workloads)")
+                    help="only the single-grid records (skip the batched, adjoint, RK4, walls and small workloads)")
     ap.add_argument("--adjoint-steps", type=int, default=3000)
     ap.add_argument("--batch-steps", type=int, default=1500)
     ap.add_argument("--batch-count", type=int, default=256)
-    ap.add_argument("--steps-3d", type=int, default=1000)
     ap.add_argument("--only", default="",
-                    help="run a single section: ricker3d, batch, adjoint, small, rk4 or walls")
+                    help="run a single section: ricker3d, ricker3d32, bumps2d, bumps2d64, batch, adjoint, "
+                         "small, rk4 or walls")
     args = ap.parse_args()
     if args.copy_probe:
         copy_probe()
@@ -469,66 +536,55 @@ def main():
         print("bench.py: this build runs on one GPU only (the stencil would shard by slabs "
               "with halo exchange; that path is not built); use --gpus 1", file=sys.stderr)
         sys.exit(2)
-
+    steps3d = min(args.steps, 1000)
     if args.only:
-        fn = {"ricker3d": lambda: bench_ricker3d(args.steps_3d),
+        fn = {"ricker3d": lambda: bench_ricker3d(steps3d, args.warmup, "f64"),
+              "ricker3d32": lambda: bench_ricker3d(steps3d, args.warmup, "f32"),
+              "bumps2d": lambda: bench_2d("f32", args.steps, args.warmup, args.variant, args.tile_rows),
+              "bumps2d64": lambda: bench_2d("f64", args.steps, args.warmup, args.variant, args.tile_rows),
               "batch": lambda: bench_batch(args.batch_steps, args.batch_count),
               "adjoint": lambda: bench_adjoint(args.adjoint_steps, 32),
               "small": bench_small, "rk4": bench_rk4, "walls": bench_walls}[args.only]
         print(json.dumps({args.only: fn()}), flush=True)
         return
     import synthetic
-    w = synthetic.bumps2d(n=4096, m=32, steps=2000, seed=0)
-    runs = []
-    for dn in args.dtypes.split(","):
-        log("timing %s %s: %d warmup + %d steps" % (w.name, dn, args.warmup, args.steps))
-        r = time_gpu(w, dn, args.steps, args.warmup, args.variant, args.tile_rows)
-        roof = roofline_from_timing(r["kernels"], r["timed_steps"])
-        roof["traffic"] = traffic_from_profile(w.name, dn, roof["kernel"])
-        # the whole path: algorithmic bytes per step over the measured time per step
-        # (kernels of a step may overlap on two streams, so this is not their sum)
-        roof["path_alg_GBps"] = round(alg_bytes_per_step(w, 4 if dn == "f32" else 8) / (r["ms_per_step"] * 1e-3) / 1e9, 1)
-        runs.append({
-            "dtype": dn,
-            "value": round(w.cells * args.steps / (r["total_ms"] * 1e-3) / 1e9, 3),
-            "ms_per_step": round(r["ms_per_step"], 5),
-            "roofline": roof,
-            "kernels": r["kernels"],
-            "finite": r["finite"],
-            "launch": r["launch"],
-        })
-        log("  %s: %.1f Gcell/s, %.4f ms/step; %s kernel %.4f ms/launch, %.0f GB/s algorithmic (path %.0f GB/s)" % (
-            dn, runs[-1]["value"], r["ms_per_step"], roof["kernel"], roof["kernel_ms_mean"], roof["achieved"],
-            roof["path_alg_GBps"]))
-        log("  launch %s" % r["launch"])
-    main_run = runs[0]
+    log("headline: 3D 560^3 FP64, %d warmup + %d steps" % (args.warmup, steps3d))
+    head = bench_ricker3d(steps3d, args.warmup, "f64")
+    log("  %.1f Gcell/s, %.4f ms/step; %s kernel %.4f ms/launch, %.0f GB/s algorithmic; launch %s" % (
+        head["value"], head["ms_per_step"], head["roofline"]["kernel"], head["roofline"]["kernel_ms_mean"],
+        head["roofline"]["achieved"], head["launch"]))
+    runs = [head]
+    log("3D 560^3 FP32")
+    runs.append(bench_ricker3d(steps3d, args.warmup, "f32"))
+    log("  %.1f Gcell/s, %.4f ms/step" % (runs[-1]["value"], runs[-1]["ms_per_step"]))
+    for dn in ("f32", "f64"):
+        steps2d = min(args.steps, 2000)
+        log("2D 4160^2 %s: %d warmup + %d steps" % (dn, args.warmup, steps2d))
+        runs.append(bench_2d(dn, steps2d, args.warmup, args.variant, args.tile_rows))
+        log("  %.1f Gcell/s, %.4f ms/step; launch %s" % (runs[-1]["value"], runs[-1]["ms_per_step"],
+                                                        runs[-1]["launch"]))
     out = {
         "metric": METRIC,
-        "value": main_run["value"],
+        "value": head["value"],
         "unit": "Gcell/s",
         "n_gpus": 1,
-        "steps": args.steps,
+        "steps": steps3d,
         "warmup": args.warmup,
-        "ms_per_step": main_run["ms_per_step"],
+        "ms_per_step": head["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": main_run["dtype"],
+        "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": "2D 4096^2 interior + 32-cell layer per side (4160^2 cells), "
-                               "64 seeded Gaussians, c=1, dt=h/2, quadratic damping ramp to 2/h, "
-                               "2000 steps",
-                   "cells": w.cells, "global_batch": 1, "parallelism": "single-gpu"},
-        "roofline": main_run["roofline"],
+        "config": {"workload": head["workload"], "cells": head["cells"], "steps_timed": steps3d,
+                   "global_batch": 1, "parallelism": "single-gpu"},
+        "roofline": head["roofline"],
         "runs": runs,
     }
     if not args.quick:
         log("small: 160^2 FP64 x 500 steps, eager vs graph")
         out["small"] = bench_small()
         log("  %s" % out["small"])
-        log("ricker3d: %d steps" % args.steps_3d)
-        out["ricker3d"] = bench_ricker3d(args.steps_3d)
-        log("  %s" % out["ricker3d"])
         log("batch: %d problems x %d steps" % (args.batch_count, args.batch_steps))
         out["batch"] = bench_batch(args.batch_steps, args.batch_count)
         log("  %s" % out["batch"])
@@ -542,8 +598,9 @@ def main():
         out["adjoint"] = bench_adjoint(args.adjoint_steps, 32)
         log("  %s" % out["adjoint"])
     if not args.no_cpu:
-        log("cpu baseline: oracle, %d steps" % args.cpu_steps)
-        out["cpu_baseline"] = cpu_baseline(w, args.cpu_steps)
+        log("cpu baseline: oracle, %d steps of the 3D workload" % args.cpu_steps)
+        out["cpu_baseline"] = cpu_baseline(synthetic.ricker3d(n=512, m=24, steps=1000), args.cpu_steps)
+        log("  %s" % out["cpu_baseline"])
     print(json.dumps(out), flush=True)
 
 

@@ -82,12 +82,27 @@ extern "C" {
 #define DPML_VARIANT_AUTO 0   /* library default (CELL)                               */
 #define DPML_VARIANT_CELL 1   /* one thread per cell; tile_rows = block rows TH in
                                  {1, 2, 4, 8} (block of 256/TH x TH cells)            */
-#define DPML_VARIANT_MARCH 2  /* tiles marching along the slowest axis; tile_rows =
-                                 rows (2D) or planes (3D) per tile.  2D: the loads
-                                 of 4 rows issued together.  3D: each wave holds
-                                 64 columns x 4 rows of three planes in registers  */
-#define DPML_VARIANT_MARCH1 3 /* as MARCH; 2D: one row at a time; 3D: waves of 64
-                                 columns x 2 rows                                    */
+#define DPML_VARIANT_MARCH 2  /* tiles marching along the slowest axis.  2D:
+                                 tile_rows = rows per tile, the loads of 4 rows
+                                 issued together.  3D periodic grids: one launch
+                                 per step over the layer-free core and the three
+                                 layer boxes, each wave holding 64 columns x RY
+                                 rows of two planes in registers and taking every
+                                 neighbour -- of U and of the layer fields -- from
+                                 lanes, register rows or the previous plane
+                                 (tile_rows: planes per core chunk in bits 0-11
+                                 (0 = 64), RY of the core in bits 12-15 (1, 2, 4
+                                 or 8; 0 = 4), RY of the z- and x-band boxes in
+                                 bits 16-17 (0: 1, 1: 2, 2: 4; the y band takes
+                                 1), the core's waves first bit 18, the core and
+                                 the layer boxes as two launches on two streams
+                                 bit 19, planes per layer chunk in bits 20-27
+                                 (0 = 16); values below 2^29).  3D with walls:
+                                 as MARCH1 with RY 4                              */
+#define DPML_VARIANT_MARCH1 3 /* as MARCH; 2D: one row at a time; 3D: one z-march
+                                 launch over the layer-free core (waves of 64
+                                 columns x 2 rows, tile_rows planes per tile) and
+                                 one thread per cell over the layer slabs         */
 #define DPML_VARIANT_TWOSTEP 4 /* 2D runs without sources/receivers/planes (with
                                   reflecting walls when every walled axis has a
                                   layer with a cell above the interior):
@@ -107,9 +122,14 @@ extern "C" {
                                   same
                                   with each wave marching in z over 64 columns x
                                   RY rows (tile_rows: planes per chunk in bits
-                                  0-11 (0 = 32), RY in bits 12-19 (4, 8 or 16;
-                                  0 = 8)); sources are added inside the pass,
-                                  receivers and planes recorded after it.
+                                  0-11 (0 = 32), RY in bits 12-17 (4, 8 or 16;
+                                  0 = 8); the frame's steps by the box kernels,
+                                  or with bit 19 by the register-neighbour march
+                                  of MARCH (its planes per layer chunk in bits
+                                  20-27); the core's tiles in launch order bit
+                                  28; values below 2^29);
+                                  sources are added inside the pass, receivers
+                                  and planes recorded after it.
                                   Otherwise single steps as CELL (2D) or MARCH
                                   (3D)                                                */
 #define DPML_VARIANT_THREESTEP 5 /* 2D: as TWOSTEP with three steps per pass over a
@@ -224,7 +244,8 @@ int dpml_record_plane(dpml_t *h, int32_t axis, int64_t index, void *planes,
  * tile_rows (meaning per variant above; 0 = default).  All variants
  * evaluate the scheme in the same operation order, so results do not
  * depend on the choice.  DPML_EINVAL for an unknown variant or tile_rows
- * outside [0, 2^20) ([0, 2^25) for DEEP, whose depth may not be 1). */
+ * outside [0, 2^20) ([0, 2^25) for DEEP, whose depth may not be 1; [0, 2^29)
+ * for MARCH and the multi-step variants on a 3D grid). */
 int dpml_set_variant(dpml_t *h, int32_t variant, int32_t tile_rows);
 
 /* Enqueue nsteps fused steps (U, Phi, Psi, sources, receivers).  Returns
@@ -399,8 +420,10 @@ const char *dpml_multi_last_error(const dpml_multi_t *h);
  * the launch count, the summed launch durations and the summed algorithmic
  * bytes of those launches (the byte model of the roofline: 3 words per cell
  * per step, 4 words per layer axis-cell per step, 1 word per cell per step
- * of a c^2 field; the core launch of a multi-step pass of D levels counts
- * its cells D times, a fused frame launch its cells D times).  Launches
+ * of a c^2 field; the core launch of a multi-step pass counts what the pass
+ * must move whatever its depth -- 4 words per core cell (U^n, U^{n-1} read,
+ * the pass's last two levels written) plus 1 word per cell of a c^2 field --
+ * and a fused frame launch counts its cells once per level it advances).  Launches
  * inside a HIP-graph capture are not timed; at most 4096 launches are kept
  * between two reads.  Frame launches run on a second stream beside the core
  * launch, so their durations include time shared with it.  The events

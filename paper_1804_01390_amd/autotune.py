@@ -39,17 +39,20 @@ CANDIDATES_2D: List[Tuple[int, int]] = ([(VARIANT_DEEP, (pf << 24) | (d << 20) |
                                         + [(VARIANT_MARCH, r) for r in (4, 8, 16)]
                                         + [(VARIANT_MARCH1, r) for r in (4, 8, 16)])
 # 3D: marching single steps (k_march3d_plan: planes per core chunk in bits
-# 0-11, rows per core wave in bits 12-15, planes of loads in flight in 16-17,
-# planes per layer chunk in 20-27, launch-order tiles bit 28) and two-step
-# passes (planes per chunk in bits 0-11, rows per wave in 12-17; bit 19 the
-# marching frame with its layer chunk in 20-27; bit 28 launch-order tiles)
+# 0-11, rows per core wave in bits 12-15, rows per z/x-band wave in 16-17
+# (0: 1, 1: 2, 2: 4), the core's waves first bit 18, planes per layer chunk
+# in 20-27) and two-step passes (planes per chunk in bits 0-11, rows per wave
+# in 12-17; bit 19 the marching frame with its layer chunk in 20-27; bit 28
+# the core's tiles in launch order)
 CANDIDATES_3D: List[Tuple[int, int]] = ([(VARIANT_CELL, 4)]
-                                        + [(VARIANT_MARCH, (1 << 28) | (lc << 20) | (1 << 16) | (ry << 12) | ch)
-                                           for ry, ch, lc in ((2, 16, 8), (4, 16, 8), (2, 16, 32), (8, 16, 8),
-                                                              (4, 32, 8))]
+                                        + [(VARIANT_MARCH, (lc << 20) | (cf << 18) | (yl << 16) | (ry << 12) | ch)
+                                           for ry, ch, lc, yl, cf in ((2, 16, 8, 0, 0), (4, 16, 8, 0, 0),
+                                                                      (2, 16, 8, 1, 0), (2, 16, 8, 2, 0),
+                                                                      (4, 16, 8, 2, 1), (2, 16, 8, 1, 1),
+                                                                      (4, 32, 16, 2, 0))]
                                         + [(VARIANT_TWOSTEP, (ry << 12) | ch) for ry in (8, 16) for ch in (32, 64)]
                                         + [(VARIANT_TWOSTEP, (1 << 28) | (1 << 19) | (lc << 20) | (ry << 12) | ch)
-                                           for ry, ch, lc in ((4, 64, 8), (8, 64, 8), (4, 32, 16))])
+                                           for ry, ch, lc in ((4, 64, 8), (8, 64, 8))])
 
 
 def grid_key(sim) -> str:

@@ -365,7 +365,7 @@ int launch_multistep(dpml *H, int levels)
         p.uout = nxt[0];
         p.tile_rows = rows;
         const dim3 grid((unsigned)round8((n_waves + 3) / 4), B);
-        const int slot = timed_begin(H, DPML_KERNEL_PAIR, step_bytes(H, levels * core, 0.0));
+        const int slot = timed_begin(H, DPML_KERNEL_PAIR, pass_bytes(H, core));
 #define DPML_MULTI_LAUNCH(GG, C2)                                                                           \
         if (levels == 2)                                                                                    \
             hipLaunchKernelGGL((dpmlk::k_step2_march<T, VX, GG, C2>), grid, block, 0, H->stream, p, nxt[1],     \

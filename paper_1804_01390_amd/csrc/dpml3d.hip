@@ -117,13 +117,13 @@ int launch_zmarch(dpml *H, dpmlk::StepArgs<T> p, const dpmlk::Box3 &bx, int ry, 
 // the step ends with the handle's stream waiting for the side stream.
 // Launch shape of the register-neighbour marching step (k_march3d_plan):
 // bits 0-11 of tile_rows planes per chunk of the core's waves (0: 64), bits
-// 12-15 rows per core wave (1, 2, 4 or 8; 0: 4), bits 16-17 planes of loads in
-// flight (1 or 2; 0: 1), bit 18 non-temporal U^{n-1} loads and U^{n+1}
-// stores, bit 19 the core and the layer boxes as two launches on two streams
-// (else one launch), bits 20-27 planes per chunk of the layer waves (0: 16),
-// bit 28 blocks in launch order (else XCD-grouped tiles).
+// 12-15 rows per core wave (1, 2, 4 or 8; 0: 4), bits 16-17 rows per wave of
+// the z-band and x-band boxes (0: 1, 1: 2, 2: 4), bit 18 the core's waves
+// first in launch order (else the layer boxes'), bit 19 the core and the
+// layer boxes as two launches on two streams (else one launch), bits 20-27
+// planes per chunk of the layer waves (0: 16).
 struct MShape {
-    int chunk, ry, pf, nt, split, lchunk, ord;
+    int chunk, ry, ryl, cf, split, lchunk;
 };
 
 static MShape mshape(int tile_rows)
@@ -132,11 +132,11 @@ static MShape mshape(int tile_rows)
     s.chunk = (tile_rows & 0xFFF) ? (tile_rows & 0xFFF) : 64;
     const int ry = (tile_rows >> 12) & 0xF;
     s.ry = (ry == 1 || ry == 2 || ry == 8) ? ry : 4;
-    s.pf = ((tile_rows >> 16) & 3) == 2 ? 2 : 1;
-    s.nt = (tile_rows >> 18) & 1;
+    const int yl = (tile_rows >> 16) & 3;
+    s.ryl = yl == 1 ? 2 : (yl == 2 ? 4 : 1);
+    s.cf = (tile_rows >> 18) & 1;
     s.split = (tile_rows >> 19) & 1;
     s.lchunk = ((tile_rows >> 20) & 0xFF) ? ((tile_rows >> 20) & 0xFF) : 16;
-    s.ord = (tile_rows >> 28) & 1;
     return s;
 }
 
@@ -153,17 +153,20 @@ static dpmlk::MBox make_mbox(const dpmlk::Box3 &bx, int ry, int chunk)
 
 static int64_t mbox_waves(const dpmlk::MBox &m) { return (int64_t)m.strips * m.groups * m.chunks; }
 
-template <typename T, int RYC, int PF>
-static void plan_launch(bool nt, int ord, dim3 g, hipStream_t st, const dpmlk::StepArgs<T> &p,
-                        const dpmlk::MPlan &pl)
+template <typename T, int RYC, int RYL>
+static void plan_launch(bool cf, dim3 g, hipStream_t st, const dpmlk::StepArgs<T> &p, const dpmlk::MPlan &pl)
 {
-    if (ord) {
-        if (nt) hipLaunchKernelGGL((dpmlk::k_march3d_plan<T, RYC, PF, true, 1>), g, dim3(256), 0, st, p, pl);
-        else hipLaunchKernelGGL((dpmlk::k_march3d_plan<T, RYC, PF, false, 1>), g, dim3(256), 0, st, p, pl);
-    } else {
-        if (nt) hipLaunchKernelGGL((dpmlk::k_march3d_plan<T, RYC, PF, true, 0>), g, dim3(256), 0, st, p, pl);
-        else hipLaunchKernelGGL((dpmlk::k_march3d_plan<T, RYC, PF, false, 0>), g, dim3(256), 0, st, p, pl);
-    }
+    if (cf) hipLaunchKernelGGL((dpmlk::k_march3d_plan<T, RYC, RYL, true>), g, dim3(256), 0, st, p, pl);
+    else hipLaunchKernelGGL((dpmlk::k_march3d_plan<T, RYC, RYL, false>), g, dim3(256), 0, st, p, pl);
+}
+
+template <typename T, int RYC>
+static void plan_launch_ryl(int ryl, bool cf, dim3 g, hipStream_t st, const dpmlk::StepArgs<T> &p,
+                            const dpmlk::MPlan &pl)
+{
+    if (ryl == 4) plan_launch<T, RYC, 4>(cf, g, st, p, pl);
+    else if (ryl == 2) plan_launch<T, RYC, 2>(cf, g, st, p, pl);
+    else plan_launch<T, RYC, 1>(cf, g, st, p, pl);
 }
 
 // One k_march3d_plan launch over the boxes of `pl` (wave offsets filled in
@@ -179,21 +182,12 @@ static int launch_plan(dpml *H, const dpmlk::StepArgs<T> &p, dpmlk::MPlan pl, co
     }
     if (w == 0) return DPML_OK;
     if (w > ((int64_t)1 << 30)) return H->fail(DPML_EINVAL, "3D grid too large for one marching launch");
-    const dim3 g((unsigned)round8((int)((w + 3) / 4)), (unsigned)H->L.batch);
+    const dim3 g((unsigned)((w + 3) / 4), (unsigned)H->L.batch);
     const int slot = H->timing ? timed_begin(H, kind, bytes, st) : -1;
-    if (s.ry == 8) {
-        if (s.pf == 2) plan_launch<T, 8, 2>(s.nt, s.ord, g, st, p, pl);
-        else plan_launch<T, 8, 1>(s.nt, s.ord, g, st, p, pl);
-    } else if (s.ry == 2) {
-        if (s.pf == 2) plan_launch<T, 2, 2>(s.nt, s.ord, g, st, p, pl);
-        else plan_launch<T, 2, 1>(s.nt, s.ord, g, st, p, pl);
-    } else if (s.ry == 1) {
-        if (s.pf == 2) plan_launch<T, 1, 2>(s.nt, s.ord, g, st, p, pl);
-        else plan_launch<T, 1, 1>(s.nt, s.ord, g, st, p, pl);
-    } else {
-        if (s.pf == 2) plan_launch<T, 4, 2>(s.nt, s.ord, g, st, p, pl);
-        else plan_launch<T, 4, 1>(s.nt, s.ord, g, st, p, pl);
-    }
+    if (s.ry == 8) plan_launch_ryl<T, 8>(s.ryl, s.cf, g, st, p, pl);
+    else if (s.ry == 2) plan_launch_ryl<T, 2>(s.ryl, s.cf, g, st, p, pl);
+    else if (s.ry == 1) plan_launch_ryl<T, 1>(s.ryl, s.cf, g, st, p, pl);
+    else plan_launch_ryl<T, 4>(s.ryl, s.cf, g, st, p, pl);
     if (slot >= 0) timed_end(H, slot, st);
     return DPML_OK;
 }
@@ -232,8 +226,8 @@ static int launch_mstep3d(dpml *H, const dpmlk::StepArgs<T> &p, const MShape &s)
     const dpmlk::Box3 none{0, 0, 0, 0, 0, 0};
     dpmlk::MPlan frame{}, core{};
     frame.b[0] = make_mbox(L.M[1] > 0 ? by : none, 1, s.lchunk);
-    frame.b[1] = make_mbox(L.M[2] > 0 ? bz : none, 1, s.lchunk);
-    frame.b[2] = make_mbox(L.M[0] > 0 ? bx : none, 1, s.lchunk);
+    frame.b[1] = make_mbox(L.M[2] > 0 ? bz : none, s.ryl, s.lchunk);
+    frame.b[2] = make_mbox(L.M[0] > 0 ? bx : none, s.ryl, s.lchunk);
     frame.b[3] = make_mbox(none, s.ry, s.chunk);
     const bool layers = L.M[0] > 0 || L.M[1] > 0 || L.M[2] > 0;
     // algorithmic bytes: the core's cells carry no layer terms, the layer
@@ -378,8 +372,8 @@ static int launch_outside3d(dpml *H, const dpmlk::StepArgs<T> &p, const dpmlk::B
     const dpmlk::Box3 none{0, 0, 0, 0, 0, 0};
     dpmlk::MPlan pl{};
     pl.b[0] = make_mbox(S.ye - S.ys < NY ? by : none, 1, sh.lchunk);
-    pl.b[1] = make_mbox(S.ze - S.zs < NZ ? bz : none, 1, sh.lchunk);
-    pl.b[2] = make_mbox(S.xe - S.xs < NX ? bx : none, 1, sh.lchunk);
+    pl.b[1] = make_mbox(S.ze - S.zs < NZ ? bz : none, sh.ryl, sh.lchunk);
+    pl.b[2] = make_mbox(S.xe - S.xs < NX ? bx : none, sh.ryl, sh.lchunk);
     pl.b[3] = make_mbox(none, 4, 1);
     MShape fs = sh;
     fs.ry = 4;
@@ -443,10 +437,10 @@ int launch_multistep3d(dpml *H)
     if (k < 2) return H->fail(DPML_EINVAL, "not enough field buffers for a multi-step pass");
     const dpmlk::Box3 c = core_box3d(L, 0), in1 = core_box3d(L, 1);
     // tile_rows: planes per chunk in the low 12 bits (0: 32), rows per wave
-    // in bits 12-17 (4, 8 or 16; 0: 8); the frame's steps as in mshape (bits
-    // 20-27 planes per layer chunk, bit 18 non-temporal streaming) when bit
-    // 19 selects the register-neighbour march for them (else the box
-    // kernels); bit 28 tiles in launch order for both
+    // in bits 12-17 (4, 8 or 16; 0: 8); the frame's steps by the
+    // register-neighbour march when bit 19 is set (planes per layer chunk in
+    // bits 20-27, as in mshape), else by the box kernels; bit 28 the core's
+    // tiles in launch order
     const int chunk = (H->tile_rows & 0xFFF) > 0 ? (H->tile_rows & 0xFFF) : 32;
     const int ryb = (H->tile_rows >> 12) & 0x3F;
     const int ry = (ryb == 4 || ryb == 16) ? ryb : 8;
@@ -471,7 +465,7 @@ int launch_multistep3d(dpml *H)
         src.n = H->n;
         src.amp = (T)(H->dt * H->dt / (H->h * H->h * H->h));
         const double core = box_cells(c);
-        const int slot = timed_begin(H, DPML_KERNEL_PAIR, step_bytes(H, 2 * core, 0.0));
+        const int slot = timed_begin(H, DPML_KERNEL_PAIR, pass_bytes(H, core));
         const dim3 grid((unsigned)round8(p.n_tiles)), block(256);
 #define DPML_TWO3D(RY_, O_) \
     hipLaunchKernelGGL((dpmlk::k_step2_zmarch3d<T, RY_, O_>), grid, block, 0, H->stream, p, nxt[1], c, in1, src)

@@ -256,6 +256,17 @@ inline double step_bytes(const dpml *H, double cells, double aux)
     return words * (double)L.esize;
 }
 
+// Algorithmic bytes of the core launch of a multi-step pass over `cells`
+// core cells per member: what the pass must move whatever its depth -- read
+// U^n and U^{n-1}, write the pass's last two levels (4 words per cell), and
+// 1 word per cell of a c^2 field.
+inline double pass_bytes(const dpml *H, double cells)
+{
+    const Layout &L = H->L;
+    const double words = 4.0 * cells * (double)L.batch + (H->c2_field ? cells : 0.0);
+    return words * (double)L.esize;
+}
+
 inline hipEvent_t take_event(dpml *H)
 {
     if (H->events_used == H->events.size()) {

@@ -330,28 +330,35 @@ __global__ void __launch_bounds__(256) k_march3d(StepArgs<T> p, MBox bx)
     march_box<T, RY, PF, AX, NT>(p, bx, xcd_tile(blockIdx.x, gridDim.x) * 4 + wv);
 }
 
-// A whole step in one launch: the y-band, z-band and x-band boxes (rows of
-// one wave each, all layer code) and the layer-free core (RYC rows per wave,
-// no layer code); each wave finds its box from the wave offsets.  Layer
-// waves come first in launch order.
+// A whole step in one launch: the y-band box (rows of one wave each, all
+// layer code), the z-band and x-band boxes (RYL rows per wave; x and z, or x
+// layer code) and the layer-free core (RYC rows per wave, no layer code);
+// each wave finds its box from the wave offsets.  Tiles go in launch order
+// (the XCDs interleaved), so at any time the whole GPU marches through one
+// stretch of the wave order: the same chunk of planes.  CF = 0 puts the
+// layer boxes' waves first, CF = 1 the core's.
 struct MPlan {
     MBox b[4];         // y band, z band, x band, core (empty boxes have no waves)
-    int32_t w[4];      // first wave of boxes 1, 2, 3 and the total
+    int32_t w[4];      // cumulative wave counts in launch order
 };
 
-// ORD = 0: blocks congruent mod 8 (one XCD) take consecutive tiles (halo
-// rows shared in that XCD's L2); ORD = 1: launch order (the XCDs take
-// interleaved tiles, so at any time the whole GPU works on one stretch of
-// the wave order: the same chunk of planes).
-template <typename T, int RYC, int PF, bool NT, int ORD>
+template <typename T, int RYC, int RYL, bool CF>
 __global__ void __launch_bounds__(256) k_march3d_plan(StepArgs<T> p, MPlan pl)
 {
     const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
-    const int wave = (ORD == 0 ? xcd_tile(blockIdx.x, gridDim.x) : (int)blockIdx.x) * 4 + wv;
-    if (wave < pl.w[0]) march_box<T, 1, PF, 7, NT>(p, pl.b[0], wave);
-    else if (wave < pl.w[1]) march_box<T, 1, PF, 5, NT>(p, pl.b[1], wave - pl.w[0]);
-    else if (wave < pl.w[2]) march_box<T, 1, PF, 1, NT>(p, pl.b[2], wave - pl.w[1]);
-    else if (wave < pl.w[3]) march_box<T, RYC, PF, 0, NT>(p, pl.b[3], wave - pl.w[2]);
+    int wave = (int)blockIdx.x * 4 + wv;
+    if constexpr (CF) {
+        const int nc = pl.w[3] - pl.w[2];
+        if (wave < nc) {
+            march_box<T, RYC, 1, 0, false>(p, pl.b[3], wave);
+            return;
+        }
+        wave -= nc;
+    }
+    if (wave < pl.w[0]) march_box<T, 1, 1, 7, false>(p, pl.b[0], wave);
+    else if (wave < pl.w[1]) march_box<T, RYL, 1, 5, false>(p, pl.b[1], wave - pl.w[0]);
+    else if (wave < pl.w[2]) march_box<T, RYL, 1, 1, false>(p, pl.b[2], wave - pl.w[1]);
+    else if (!CF && wave < pl.w[3]) march_box<T, RYC, 1, 0, false>(p, pl.b[3], wave - pl.w[2]);
 }
 
 }  // namespace dpmlk

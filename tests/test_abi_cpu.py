@@ -74,6 +74,7 @@ def test_tuner_candidates_are_valid_launch_shapes():
             assert ((tr >> 12) & 0x3F) in (4, 8, 16) and 0 < (tr & 0xFFF) <= 4095
         if variant == dp.VARIANT_MARCH:        # marching steps: rows per core wave in bits 12-15
             assert ((tr >> 12) & 0xF) in (1, 2, 4, 8) and ((tr >> 16) & 3) in (0, 1, 2)
+            assert (tr & 0xFFF) > 0 and ((tr >> 20) & 0xFF) > 0
     for variant, rows, group in autotune.CANDIDATES_MULTI:
         assert variant in (dp.VARIANT_MARCH,) + multi_variants
         assert group in (1, 2, 4)

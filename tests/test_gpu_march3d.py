@@ -23,16 +23,19 @@ pytestmark = pytest.mark.gpu
 TOL = {"f64": 1e-12, "f32": 2e-5}
 
 
-def march_shape(chunk=0, ry=0, pf=0, nt=False, split=False, lchunk=0):
+def march_shape(chunk=0, ry=0, ryl=1, core_first=False, split=False, lchunk=0):
     """tile_rows of a 3D MARCH launch: planes per core chunk (bits 0-11), rows
-    per core wave (bits 12-15: 2, 4 or 8), planes of loads in flight (bits
-    16-17: 1, 2), non-temporal streaming (bit 18), core and layer boxes as
-    two launches (bit 19), planes per layer chunk (bits 20-27)."""
-    return chunk | (ry << 12) | (pf << 16) | (int(nt) << 18) | (int(split) << 19) | (lchunk << 20)
+    per core wave (bits 12-15: 1, 2, 4 or 8), rows per wave of the z- and
+    x-band boxes (bits 16-17: 1, 2 or 4), the core's waves first (bit 18),
+    core and layer boxes as two launches (bit 19), planes per layer chunk
+    (bits 20-27)."""
+    return (chunk | (ry << 12) | ({1: 0, 2: 1, 4: 2}[ryl] << 16) | (int(core_first) << 18) | (int(split) << 19)
+            | (lchunk << 20))
 
 
-SHAPES = [march_shape(), march_shape(5, 4, 1, lchunk=3), march_shape(7, 8, 2, nt=True), march_shape(64, 2, 1, split=True),
-          march_shape(3, 4, 2, nt=True, split=True, lchunk=200)]
+SHAPES = [march_shape(), march_shape(5, 4, 2, lchunk=3), march_shape(7, 8, 4, core_first=True),
+          march_shape(64, 2, 1, split=True), march_shape(3, 1, 2, core_first=True, split=True, lchunk=200),
+          march_shape(9, 2, 4, lchunk=5)]
 
 
 def _case(name, rng):
@@ -114,7 +117,7 @@ def test_march3d_batch_and_c2_field(dtype):
                               "dt": 0.4 / math.sqrt(1.4)}):
         outs = []
         for variant, tr in ((dp.VARIANT_CELL, 0), (dp.VARIANT_MARCH, march_shape(9, 8, 2)),
-                            (dp.VARIANT_MARCH, march_shape(0, 4, 1))):
+                            (dp.VARIANT_MARCH, march_shape(0, 4, 4, core_first=True))):
             sim = _run(n, lo, hi, sig, U0, 17, td, variant, tr, **kw)
             outs.append(_state_arrays(sim))
             sim.close()

@@ -45,10 +45,10 @@ def _case(name, rng):
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
 @pytest.mark.parametrize("case", ["ragged", "z_periodic", "x_periodic"])
 @pytest.mark.parametrize("tile_rows", [0, (4 << 12) | 5, (16 << 12) | 7, (8 << 12) | 64,
-                                       # launch-order tiles; the marching frame (bit 19) with layer
-                                       # chunks (bits 20-27) and non-temporal streaming (bit 18)
+                                       # launch-order core tiles; the marching frame (bit 19) with
+                                       # layer chunks (bits 20-27)
                                        (1 << 28) | (16 << 12) | 32, (1 << 28) | (1 << 19) | (8 << 20) | (4 << 12) | 16,
-                                       (1 << 19) | (1 << 18) | (3 << 20) | (8 << 12) | 9])
+                                       (1 << 19) | (3 << 20) | (8 << 12) | 9])
 def test_3d_twostep_bit_identical_and_oracle(dtype, case, tile_rows):
     rng = np.random.default_rng(17)
     n, lo, hi, sig, U0 = _case(case, rng)
@@ -145,7 +145,7 @@ def test_3d_twostep_timing_counts_and_bytes():
     aux = sum((lo[a] + hi[a]) * cells // N[a] for a in range(3))
     for form, per_step in ((0, 3), (1 << 19, 1)):
         assert t[form]["pair"]["launches"] == 4
-        assert t[form]["pair"]["bytes"] == pytest.approx(4 * 2 * 3 * core_cells * 4, rel=1e-12)
+        assert t[form]["pair"]["bytes"] == pytest.approx(4 * 4 * core_cells * 4, rel=1e-12)   # 4 words per pass
         assert t[form]["frame"]["launches"] == 4 * 2 * per_step
         assert t[form]["frame"]["bytes"] == pytest.approx(4 * 2 * (3 * (cells - core_cells) + 4 * aux) * 4, rel=1e-9)
 

@@ -445,8 +445,9 @@ def test_twostep_graph_replay_matches_eager(variant, tile_rows):
 def test_launch_timing_counts_and_bytes(dtype):
     """The library's per-launch timing: one record per step-kernel launch,
     the algorithmic byte model per launch (3 words per cell, 4 per layer
-    axis-cell), and a two-step pass (core + frame) that carries exactly the
-    bytes of two single steps; graph replays are not timed."""
+    axis-cell; a pass's core launch 4 words per core cell), so that a pass of
+    D levels stands for the bytes of D single steps; graph replays are not
+    timed."""
     w = synthetic.bump2d(200, 20, 0)
     esize = 4 if dtype == "f32" else 8
     cells = w.N[0] * w.N[1]
@@ -460,35 +461,27 @@ def test_launch_timing_counts_and_bytes(dtype):
     t = sim.get_timing()
     assert set(t) == {"step"} and t["step"]["launches"] == 6
     assert t["step"]["bytes"] == 6 * step_bytes and t["step"]["ms"] > 0
+    # a pass of D levels: the core launch counts what it must move (4 words
+    # per core cell), the frame's launches their steps' share; together they
+    # stand for D steps: frame + (3 D / 4) core = D single steps
     sim.set_variant(dp.VARIANT_TWOSTEP, 0)
     sim.step(7)                                   # three pairs and one single step
     t = sim.get_timing()
     assert t["pair"]["launches"] == 3 and t["frame"]["launches"] == 3 * 2 and t["step"]["launches"] == 1
-    assert t["pair"]["bytes"] + t["frame"]["bytes"] == 3 * 2 * step_bytes
+    assert t["frame"]["bytes"] + 1.5 * t["pair"]["bytes"] == pytest.approx(3 * 2 * step_bytes, rel=1e-12)
     assert t["step"]["bytes"] == step_bytes
-    sim.set_variant(dp.VARIANT_THREESTEP, 0)
-    sim.step(8)                                   # two triples and one pair
-    t = sim.get_timing()
-    assert t["pair"]["launches"] == 3 and t["frame"]["launches"] == 2 * 3 + 2 and "step" not in t
-    assert t["pair"]["bytes"] + t["frame"]["bytes"] == 8 * step_bytes
+    for variant, rows, steps, depth, frames in ((dp.VARIANT_THREESTEP, 0, 9, 3, 9), (dp.VARIANT_FOURSTEP, 0, 8, 4, 8),
+                                                (dp.VARIANT_DEEP, 6 << 20, 12, 6, 12),
+                                                (dp.VARIANT_DEEP, (6 << 20) | (15 << 16), 12, 6, 2)):
+        sim.set_variant(variant, rows)
+        sim.step(steps)
+        t = sim.get_timing()
+        assert t["pair"]["launches"] == steps // depth and t["frame"]["launches"] == frames and "step" not in t
+        assert t["frame"]["bytes"] + 0.75 * depth * t["pair"]["bytes"] == pytest.approx(steps * step_bytes, rel=1e-12)
     sim.set_variant(dp.VARIANT_FOURSTEP, 0)
     sim.step(11)                                  # two quadruples and one triple
     t = sim.get_timing()
     assert t["pair"]["launches"] == 3 and t["frame"]["launches"] == 2 * 4 + 3 and "step" not in t
-    assert t["pair"]["bytes"] + t["frame"]["bytes"] == 11 * step_bytes
-    sim.step(6)                                   # one quadruple and one pair
-    t = sim.get_timing()
-    assert t["pair"]["launches"] == 2 and t["frame"]["launches"] == 4 + 2 and "step" not in t
-    sim.set_variant(dp.VARIANT_DEEP, 6 << 20)
-    sim.step(15)                                  # two passes of six levels and one of three
-    t = sim.get_timing()
-    assert t["pair"]["launches"] == 3 and t["frame"]["launches"] == 6 + 6 + 3 and "step" not in t
-    assert t["pair"]["bytes"] + t["frame"]["bytes"] == 15 * step_bytes
-    sim.set_variant(dp.VARIANT_DEEP, (6 << 20) | (15 << 16))
-    sim.step(14)                                  # two fused passes of six levels and one pair
-    t = sim.get_timing()
-    assert t["pair"]["launches"] == 3 and t["frame"]["launches"] == 3 and "step" not in t
-    assert t["pair"]["bytes"] + t["frame"]["bytes"] == 14 * step_bytes
     sim.step_graph(4)
     sim.sync()
     assert sim.get_timing() == {}
