@@ -218,11 +218,12 @@ def _events():
     return torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
 
 
-def bench_ricker3d(steps: int, warmup: int, dtype_name: str = "f64"):
+def bench_ricker3d(steps: int, warmup: int, dtype_name: str = "f64", variant: int = 0, tile_rows: int = 0):
     """3D, 512^3 interior + 24-cell layer on all faces (560^3 cells),
     dt = 0.4 h, Ricker point source at the centre, the z plane through it
     recorded every step: `steps` steps of the workload from rest, after
-    `warmup` untimed steps, in the tuned launch."""
+    `warmup` untimed steps, in the tuned launch (or the given variant and
+    launch shape)."""
     import torch
     import paper_1804_01390_amd as dp
     import synthetic
@@ -238,7 +239,11 @@ def bench_ricker3d(steps: int, warmup: int, dtype_name: str = "f64"):
     sim.inject(w.sources, torch.from_numpy(w.wavelets).to(dtype))
     axis, index = w.plane
     sim.record_plane(axis, index, w.steps)
-    choice = autotune.tune(sim, steps=10)
+    if variant:
+        sim.set_variant(variant, tile_rows)
+        choice = {"variant": variant, "tile_rows": tile_rows, "cached": False}
+    else:
+        choice = autotune.tune(sim, steps=10)
     sim.set_state(rest())
     sim.step(warmup)
     sim.sync()
@@ -277,7 +282,7 @@ def bench_ricker3d(steps: int, warmup: int, dtype_name: str = "f64"):
             "alg_bytes_per_step": ab,
             "alg_GBps": round(ab * steps / (ms * 1e-3) / 1e9, 1),
             "plane_peak": peak, "roofline": roof, "kernels": kernels,
-            "launch": {"variant": choice["variant"], "tile_rows": choice["tile_rows"], "autotuned": True,
+            "launch": {"variant": choice["variant"], "tile_rows": choice["tile_rows"], "autotuned": not variant,
                        "cached": choice["cached"]}}
 
 
@@ -516,8 +521,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--cpu-steps", type=int, default=2)     # ~15 s of the oracle on 16 host cores
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--variant", type=int, default=0, help="2D records: fixed variant instead of the tuner")
-    ap.add_argument("--tile-rows", type=int, default=0)
+    ap.add_argument("--variant", type=int, default=0,
+                    help="a fixed variant instead of the tuner (with --only: that record)")
+    ap.add_argument("--tile-rows", type=lambda v: int(v, 0), default=0)
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run the streaming bandwidth probe and exit")
     ap.add_argument("--quick", action="store_true",
@@ -538,8 +544,8 @@ def main():
         sys.exit(2)
     steps3d = min(args.steps, 1000)
     if args.only:
-        fn = {"ricker3d": lambda: bench_ricker3d(steps3d, args.warmup, "f64"),
-              "ricker3d32": lambda: bench_ricker3d(steps3d, args.warmup, "f32"),
+        fn = {"ricker3d": lambda: bench_ricker3d(steps3d, args.warmup, "f64", args.variant, args.tile_rows),
+              "ricker3d32": lambda: bench_ricker3d(steps3d, args.warmup, "f32", args.variant, args.tile_rows),
               "bumps2d": lambda: bench_2d("f32", args.steps, args.warmup, args.variant, args.tile_rows),
               "bumps2d64": lambda: bench_2d("f64", args.steps, args.warmup, args.variant, args.tile_rows),
               "batch": lambda: bench_batch(args.batch_steps, args.batch_count),
@@ -560,7 +566,7 @@ def main():
     for dn in ("f32", "f64"):
         steps2d = min(args.steps, 2000)
         log("2D 4160^2 %s: %d warmup + %d steps" % (dn, args.warmup, steps2d))
-        runs.append(bench_2d(dn, steps2d, args.warmup, args.variant, args.tile_rows))
+        runs.append(bench_2d(dn, steps2d, args.warmup))
         log("  %.1f Gcell/s, %.4f ms/step; launch %s" % (runs[-1]["value"], runs[-1]["ms_per_step"],
                                                         runs[-1]["launch"]))
     out = {

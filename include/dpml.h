@@ -97,7 +97,7 @@ extern "C" {
                                  1), the core's waves first bit 18, the core and
                                  the layer boxes as two launches on two streams
                                  bit 19, planes per layer chunk in bits 20-27
-                                 (0 = 16); values below 2^29).  3D with walls:
+                                 (0 = 16); values below 2^30).  3D with walls:
                                  as MARCH1 with RY 4                              */
 #define DPML_VARIANT_MARCH1 3 /* as MARCH; 2D: one row at a time; 3D: one z-march
                                  launch over the layer-free core (waves of 64
@@ -127,7 +127,9 @@ extern "C" {
                                   or with bit 19 by the register-neighbour march
                                   of MARCH (its planes per layer chunk in bits
                                   20-27); the core's tiles in launch order bit
-                                  28; values below 2^29);
+                                  28; bit 29: the frame's first step alone
+                                  before the core, which then runs beside the
+                                  frame's second step; values below 2^30);
                                   sources are added inside the pass, receivers
                                   and planes recorded after it.
                                   Otherwise single steps as CELL (2D) or MARCH
@@ -244,7 +246,7 @@ int dpml_record_plane(dpml_t *h, int32_t axis, int64_t index, void *planes,
  * tile_rows (meaning per variant above; 0 = default).  All variants
  * evaluate the scheme in the same operation order, so results do not
  * depend on the choice.  DPML_EINVAL for an unknown variant or tile_rows
- * outside [0, 2^20) ([0, 2^25) for DEEP, whose depth may not be 1; [0, 2^29)
+ * outside [0, 2^20) ([0, 2^25) for DEEP, whose depth may not be 1; [0, 2^30)
  * for MARCH and the multi-step variants on a 3D grid). */
 int dpml_set_variant(dpml_t *h, int32_t variant, int32_t tile_rows);
 

@@ -736,7 +736,7 @@ int dpml_set_variant(dpml_t *H, int32_t variant, int32_t tile_rows)
 {
     if (!H) return DPML_EINVAL;
     if (variant < DPML_VARIANT_AUTO || variant > DPML_VARIANT_DEEP || tile_rows < 0 ||
-        tile_rows >= (1 << (variant == DPML_VARIANT_DEEP ? 25 : (H->L.ndim == 3 && variant >= DPML_VARIANT_MARCH && variant != DPML_VARIANT_MARCH1) ? 29 : 20)))
+        tile_rows >= (1 << (variant == DPML_VARIANT_DEEP ? 25 : (H->L.ndim == 3 && variant >= DPML_VARIANT_MARCH && variant != DPML_VARIANT_MARCH1) ? 30 : 20)))
         return H->fail(DPML_EINVAL, "bad variant");
     if (variant == DPML_VARIANT_DEEP && (pass_depth(variant, tile_rows) < 2 || pass_depth(variant, tile_rows) > kMaxLevels))
         return H->fail(DPML_EINVAL, "DEEP passes take 2 .. 8 levels");

@@ -440,13 +440,34 @@ int launch_multistep3d(dpml *H)
     // in bits 12-17 (4, 8 or 16; 0: 8); the frame's steps by the
     // register-neighbour march when bit 19 is set (planes per layer chunk in
     // bits 20-27, as in mshape), else by the box kernels; bit 28 the core's
-    // tiles in launch order
+    // tiles in launch order; bit 29 below
     const int chunk = (H->tile_rows & 0xFFF) > 0 ? (H->tile_rows & 0xFFF) : 32;
     const int ryb = (H->tile_rows >> 12) & 0x3F;
     const int ry = (ryb == 4 || ryb == 16) ? ryb : 8;
     const MShape fsh = mshape(H->tile_rows & ~0xFFFF);
     const int ord = (H->tile_rows >> 28) & 1;
     const bool frame_plan = (H->tile_rows >> 19) & 1;
+    // bit 29: the frame's first step alone on the handle's stream first, then
+    // the core beside the frame's second step (else the core beside both)
+    const bool frame_first = (H->tile_rows >> 29) & 1;
+    // the frame's step j (1 or 2) on stream st, aux buffers alternating
+    auto frame_step = [&](int j, hipStream_t st) -> int {
+        if (j == 2) H->cur = 1 - H->cur;
+        dpmlk::StepArgs<T> pj = make_args<T>(H);
+        if (j == 2) H->cur = 1 - H->cur;
+        pj.u = j == 1 ? A : nxt[0];
+        pj.uo = j == 1 ? Bv : A;
+        pj.uout = nxt[j - 1];
+        // algorithmic share: the frame's own cells (the ring cells it recomputes
+        // are the core's, counted there)
+        const double share = step_bytes(H, (double)L.ncell - box_cells(c), aux_cells(L));
+        return frame_plan ? launch_outside3d<T>(H, pj, core_box3d(L, 2 - j), share, st, fsh)
+                          : launch_outside3d_boxes<T>(H, pj, core_box3d(L, 2 - j), share, st);
+    };
+    if (frame_first) {
+        int rc = frame_step(1, H->stream);
+        if (rc) return rc;
+    }
     HIP_TRY(H, hipEventRecord(H->ev_fork, H->stream));
     HIP_TRY(H, hipStreamWaitEvent(H->side, H->ev_fork, 0));
     {
@@ -479,19 +500,9 @@ int launch_multistep3d(dpml *H)
 #undef DPML_TWO3D
         timed_end(H, slot);
     }
-    // the frame's steps on the side stream, aux buffers alternating
-    for (int j = 1; j <= 2; ++j) {
-        if (j == 2) H->cur = 1 - H->cur;
-        dpmlk::StepArgs<T> pj = make_args<T>(H);
-        if (j == 2) H->cur = 1 - H->cur;
-        pj.u = j == 1 ? A : nxt[0];
-        pj.uo = j == 1 ? Bv : A;
-        pj.uout = nxt[j - 1];
-        // algorithmic share: the frame's own cells (the ring cells it recomputes
-        // are the core's, counted there)
-        const double share = step_bytes(H, (double)L.ncell - box_cells(c), aux_cells(L));
-        int rc = frame_plan ? launch_outside3d<T>(H, pj, core_box3d(L, 2 - j), share, H->side, fsh)
-                            : launch_outside3d_boxes<T>(H, pj, core_box3d(L, 2 - j), share, H->side);
+    // the frame's (remaining) steps on the side stream beside the core
+    for (int j = frame_first ? 2 : 1; j <= 2; ++j) {
+        int rc = frame_step(j, H->side);
         if (rc) return rc;
     }
     HIP_TRY(H, hipEventRecord(H->ev_join, H->side));

@@ -63,7 +63,7 @@ def test_tuner_candidates_are_valid_launch_shapes():
         assert 0 <= tr < (1 << (25 if variant == dp.VARIANT_DEEP else 20))
     for variant, tr in autotune.CANDIDATES_3D:       # 3D shapes take bits up to 28
         assert dp.VARIANT_AUTO <= variant <= dp.VARIANT_DEEP
-        assert 0 <= tr < (1 << (29 if variant >= dp.VARIANT_MARCH and variant != dp.VARIANT_MARCH1 else 20))
+        assert 0 <= tr < (1 << (30 if variant >= dp.VARIANT_MARCH and variant != dp.VARIANT_MARCH1 else 20))
         if variant == dp.VARIANT_DEEP:
             assert ((tr >> 20) & 0xF) in (0, 2, 3, 4, 5, 6, 7, 8)
     for variant, tr in autotune.CANDIDATES_2D:

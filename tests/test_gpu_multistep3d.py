@@ -48,7 +48,9 @@ def _case(name, rng):
                                        # launch-order core tiles; the marching frame (bit 19) with
                                        # layer chunks (bits 20-27)
                                        (1 << 28) | (16 << 12) | 32, (1 << 28) | (1 << 19) | (8 << 20) | (4 << 12) | 16,
-                                       (1 << 19) | (3 << 20) | (8 << 12) | 9])
+                                       (1 << 19) | (3 << 20) | (8 << 12) | 9,
+                                       # the frame's first step alone before the core (bit 29)
+                                       (1 << 29) | (16 << 12) | 32, (1 << 29) | (1 << 19) | (4 << 12) | 11])
 def test_3d_twostep_bit_identical_and_oracle(dtype, case, tile_rows):
     rng = np.random.default_rng(17)
     n, lo, hi, sig, U0 = _case(case, rng)
@@ -150,17 +152,19 @@ def test_3d_twostep_timing_counts_and_bytes():
         assert t[form]["frame"]["bytes"] == pytest.approx(4 * 2 * (3 * (cells - core_cells) + 4 * aux) * 4, rel=1e-9)
 
 
-def test_3d_twostep_graph_replay_matches_eager():
+@pytest.mark.parametrize("tile_rows", [0, (1 << 29) | (1 << 19) | (8 << 12) | 16])
+def test_3d_twostep_graph_replay_matches_eager(tile_rows):
     """The 3D two-step pass captured into a HIP graph (core on the captured
-    stream, frame steps on the side stream joined by events): every replay,
-    with eager work and synchronisations between replays, equals eager
-    stepping bit for bit."""
+    stream, frame steps on the side stream joined by events; or the frame's
+    first step on the captured stream before the fork): every replay, with
+    eager work and synchronisations between replays, equals eager stepping
+    bit for bit."""
     rng = np.random.default_rng(23)
     n, lo, hi, sig, U0 = _case("ragged", rng)
     a = dp.Simulation(n, lo, hi, 1.0, 0.4, sig, dtype=torch.float32)
     b = dp.Simulation(n, lo, hi, 1.0, 0.4, sig, dtype=torch.float32)
-    a.set_variant(dp.VARIANT_TWOSTEP, 0)
-    b.set_variant(dp.VARIANT_TWOSTEP, 0)
+    a.set_variant(dp.VARIANT_TWOSTEP, tile_rows)
+    b.set_variant(dp.VARIANT_TWOSTEP, tile_rows)
     a.set_state(torch.from_numpy(U0))
     b.set_state(torch.from_numpy(U0))
     for rep, k in enumerate([6, 6, 5, 5, 6]):
