@@ -267,6 +267,20 @@ int dpml_step_graph(dpml_t *h, int64_t nsteps);
  * is left at that step). */
 int dpml_step_checked(dpml_t *h, int64_t nsteps, int64_t every);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): as
+ * dpml_step_checked, but the call allocates nothing -- no hipMalloc, no
+ * stream, event or table created on first use.  Steps are taken one at a
+ * time by the one-thread-per-cell kernel (whatever dpml_set_variant chose;
+ * results are identical), sources and receivers from the tables registered
+ * beforehand, and the non-finite scan keeps its flags (one int32 per scan
+ * block, 1024 of them, 4 KiB) in a static device array of the library that
+ * each GPU holds until the process ends.  Calls that overlap on one GPU (from
+ * several threads or handles) share that array and race.  The scan strides
+ * over the grid, so any grid dpml_create accepts is handled (up to 2^40
+ * cells; larger gives DPML_EINVAL).  Return codes as dpml_step_checked. */
+int dpml_step_checked_noalloc(dpml_t *h, int64_t nsteps, int64_t every);
+
 /* Borrowed device pointer to a field of the current time level (see the
  * DPML_FIELD_* selectors and the auxiliary layout above) and its extents in
  * x, y, z order (unused axes 1).  Valid until the next dpml_step. */

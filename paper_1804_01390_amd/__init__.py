@@ -61,6 +61,7 @@ EXPORTED = [
     "dpml_multi_last_error",
     "dpml_rk4_workspace_bytes", "dpml_rk4_set_state", "dpml_rk4_step", "dpml_rk4_field",
     "dpml_rk4_time_index", "dpml_set_timing", "dpml_get_timing", "dpml_bandwidth_probe",
+    "dpml_step_checked_noalloc",
 ]
 
 PROBE_READ, PROBE_WRITE, PROBE_COPY, PROBE_NONTEMPORAL, PROBE_MAX_BLOCKS = 0, 1, 2, 4, 16384
@@ -111,6 +112,7 @@ def load_library():
         "dpml_set_variant": (ctypes.c_int, [_VP, ctypes.c_int32, ctypes.c_int32]),
         "dpml_step": (ctypes.c_int, [_VP, ctypes.c_int64]),
         "dpml_step_checked": (ctypes.c_int, [_VP, ctypes.c_int64, ctypes.c_int64]),
+        "dpml_step_checked_noalloc": (ctypes.c_int, [_VP, ctypes.c_int64, ctypes.c_int64]),
         "dpml_step_graph": (ctypes.c_int, [_VP, ctypes.c_int64]),
         "dpml_field": (ctypes.c_int, [_VP, ctypes.c_int32, ctypes.POINTER(_VP), ctypes.c_int64 * 3]),
         "dpml_time_index": (ctypes.c_int64, [_VP]),
@@ -325,6 +327,11 @@ class Simulation:
 
     def step_checked(self, nsteps: int, every: int):
         self._check(self.lib.dpml_step_checked(self.handle, int(nsteps), int(every)))
+
+    def step_checked_noalloc(self, nsteps: int, every: int):
+        """As step_checked, through the entry point that allocates nothing
+        (one thread per cell, scan flags in the library's static array)."""
+        self._check(self.lib.dpml_step_checked_noalloc(self.handle, int(nsteps), int(every)))
 
     def field(self, which: int):
         """Borrowed view of a field of the current level (valid until the next step)."""

@@ -18,6 +18,7 @@
 #include <cstring>
 #include <numeric>
 #include <string>
+#include <mutex>
 #include <vector>
 
 #include "dpml_host.hpp"
@@ -550,6 +551,86 @@ bool near_layer(const Layout &L, int a, int64_t i)
     return i >= L.lo[a] + L.n[a] - 1 || i <= L.lo[a];
 }
 
+// ---- allocation-free watchdog (dpml_step_checked_noalloc) ---------------
+// Its scan flags live in this file-scope device array instead of the caller's
+// workspace: one int32 flag per scan block.  Each GPU holds its own copy for
+// the life of the process; host code reaches it only through the address
+// hipGetSymbolAddress returns for the current device (kept per device, looked
+// up once at dpml_create), never through the array's name.
+constexpr int kScratchFlags = 1024;
+constexpr int64_t kMaxNoallocCells = (int64_t)1 << 40;   // the scan's 64-bit grid stride
+static_assert(kScratchFlags >= kFlagBlocks, "the scan's flags must fit the static scratch");
+
+}  // namespace
+
+static __device__ __align__(256) int32_t scratch[kScratchFlags];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mutex;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+// Address of the current device's scratch array (looked up once per device);
+// nullptr with *err set on failure.
+void *scratch_for_current_device(hipError_t *err)
+{
+    int dev = -1;
+    *err = hipGetDevice(&dev);
+    if (*err != hipSuccess) return nullptr;
+    if (dev < 0 || dev >= kMaxDevices) {
+        *err = hipErrorInvalidDevice;
+        return nullptr;
+    }
+    std::lock_guard<std::mutex> lock(g_scratch_mutex);
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        *err = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (*err != hipSuccess) return nullptr;
+        g_scratch_ptr[dev] = ptr;
+    }
+    return g_scratch_ptr[dev];
+}
+
+// The non-finite scan of U^n into the static flags: every scan block writes
+// its flag, so nothing has to be cleared between calls.
+template <typename T>
+int nonfinite_check_noalloc(dpml *H, bool *bad)
+{
+    if (!H->scratch) return H->fail(DPML_EHIP, "no static scratch for this device");
+    int32_t *flags = (int32_t *)H->scratch;
+    hipLaunchKernelGGL((dpmlk::k_nonfinite<T>), dim3(kFlagBlocks), dim3(256), 0, H->stream,
+                       (const T *)H->u_now, H->L.ncell * H->L.batch, flags);
+    HIP_TRY(H, hipGetLastError());
+    int32_t host[kFlagBlocks];
+    HIP_TRY(H, hipMemcpyAsync(host, flags, sizeof(host), hipMemcpyDeviceToHost, H->stream));
+    HIP_TRY(H, hipStreamSynchronize(H->stream));
+    *bad = false;
+    for (int i = 0; i < kFlagBlocks; ++i) *bad |= host[i] != 0;
+    return DPML_OK;
+}
+
+// One step by one thread per cell (no multi-step pass, no second stream, no
+// table built on first use: nothing is allocated), sources and receivers
+// from the tables registered beforehand.
+template <typename T>
+int step_cells_noalloc(dpml *H)
+{
+    const int variant = H->variant, rows = H->tile_rows;
+    H->variant = DPML_VARIANT_CELL;
+    H->tile_rows = 0;
+    int rc = launch_step<T>(H);
+    H->variant = variant;
+    H->tile_rows = rows;
+    if (rc) return rc;
+    rc = launch_epilogue<T>(H);
+    if (rc) return rc;
+    std::swap(H->u_now, H->u_old);
+    H->cur = 1 - H->cur;
+    H->n += 1;
+    return DPML_OK;
+}
+
 template <typename T>
 int nonfinite_check(dpml *H, bool *bad)
 {
@@ -638,8 +719,12 @@ int dpml_create(const dpml_grid_t *g, double h, double dt, const double *c2, int
     }
     if (((uintptr_t)workspace) % kAlign != 0) { g_create_error = "workspace must be 256-byte aligned"; return DPML_ENOMEM; }
 
+    hipError_t serr = hipSuccess;
+    void *sp = scratch_for_current_device(&serr);
+    if (!sp) { g_create_error = std::string("static scratch lookup: ") + hipGetErrorString(serr); return DPML_EHIP; }
     dpml *H = new (std::nothrow) dpml();
     if (!H) { g_create_error = "out of host memory"; return DPML_ENOMEM; }
+    H->scratch = sp;
     H->L = L;
     H->ws = (char *)workspace;
     H->stream = (hipStream_t)stream;
@@ -766,6 +851,30 @@ int dpml_step_checked(dpml_t *H, int64_t nsteps, int64_t every)
         done += k;
         bool bad = false;
         rc = H->L.dtype == DPML_F32 ? nonfinite_check<float>(H, &bad) : nonfinite_check<double>(H, &bad);
+        if (rc) return rc;
+        if (bad) return H->fail(DPML_ENONFINITE, "non-finite value in U at step " + std::to_string(H->n));
+    }
+    return DPML_OK;
+}
+
+int dpml_step_checked_noalloc(dpml_t *H, int64_t nsteps, int64_t every)
+{
+    if (!H) return DPML_EINVAL;
+    if (nsteps < 0 || every < 1) return H->fail(DPML_EINVAL, "nsteps < 0 or every < 1");
+    if (!H->state_set) return H->fail(DPML_ESTATE, "dpml_set_state has not been called");
+    if (H->L.ncell * H->L.batch > kMaxNoallocCells)
+        return H->fail(DPML_EINVAL, "grid larger than the allocation-free scan handles (2^40 cells)");
+    int64_t done = 0;
+    while (done < nsteps) {
+        const int64_t k = std::min(every, nsteps - done);
+        for (int64_t i = 0; i < k; ++i) {
+            int rc = H->L.dtype == DPML_F32 ? step_cells_noalloc<float>(H) : step_cells_noalloc<double>(H);
+            if (rc) return rc;
+        }
+        done += k;
+        bool bad = false;
+        int rc = H->L.dtype == DPML_F32 ? nonfinite_check_noalloc<float>(H, &bad)
+                                        : nonfinite_check_noalloc<double>(H, &bad);
         if (rc) return rc;
         if (bad) return H->fail(DPML_ENONFINITE, "non-finite value in U at step " + std::to_string(H->n));
     }

@@ -215,6 +215,7 @@ struct dpml {
     std::vector<hipEvent_t> events;      // pool, reused after each dpml_get_timing
     size_t events_used = 0;
     std::string err;
+    void *scratch = nullptr;   // this device's static scratch (dpml_step_checked_noalloc)
 
     void *at(size_t off) { return ws + off; }
     int fail(int code, const std::string &msg) { err = msg; return code; }
