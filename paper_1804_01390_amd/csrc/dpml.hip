@@ -126,12 +126,20 @@ void core_rect(const Layout &L, int levels, int r[4])
 
 // Levels per pass this handle may take right now: the variant's depth, fewer
 // for the last steps of a run or where the core of that depth is empty, or 1.
+bool frame_fused(const dpml *H);
+
 int multistep_levels(const dpml *H, int64_t nsteps)
 {
     const Layout &L = H->L;
     if (L.ndim == 3) return multistep_levels3d(H, nsteps);
     if (!walls_allow_multistep(L)) return 1;
-    if (H->ns > 0 || (H->recording && (H->nr > 0 || H->plane_axis >= 0))) return 1;
+    if (H->recording && H->plane_axis >= 0) return 1;
+    // sources and receivers: passes of 4 .. 8 levels (the deep cores form
+    // them; the frame's per-step launches record), at most 32 sources, each
+    // at least levels-1 cells inside the core (the frame's steps then add
+    // none), receivers on distinct cells
+    const bool taps = H->ns > 0 || (H->recording && H->nr > 0);
+    if (taps && (H->ns > 32 || frame_fused(H) || (H->recording && H->rec_dups))) return 1;
     int want = pass_depth(H->variant, H->tile_rows);
     if (want > nsteps) want = (int)nsteps;
     // the core kernels wrap halo rows once: each extent must hold its halos
@@ -139,7 +147,16 @@ int multistep_levels(const dpml *H, int64_t nsteps)
     for (; want >= 2; --want) {
         int r[4];
         core_rect(L, want, r);
-        if (r[1] - r[0] >= 1 && r[3] - r[2] >= 1) return want;
+        if (r[1] - r[0] < 1 || r[3] - r[2] < 1) continue;
+        if (!taps) return want;
+        if (want < 4) return 1;
+        bool inside = true;
+        for (int64_t cell : H->src_sorted) {
+            const int64_t c = cell % L.ncell;
+            const int x = (int)(c % L.N[0]), y = (int)(c / L.N[0]);
+            inside &= x >= r[0] + want - 1 && x < r[1] - (want - 1) && y >= r[2] + want - 1 && y < r[3] - (want - 1);
+        }
+        if (inside) return want;
     }
     return 1;
 }
@@ -279,6 +296,78 @@ int ensure_multistep(dpml *H, int levels)
     return ensure_side(H);
 }
 
+// Receiver tables of the 2D passes with receivers: per (member, row) a
+// column map of receiver indices in a pool (built once per registration),
+// and for passes of `levels` levels over the core r the receivers sorted by
+// how deep they lie in the core (min distance to its edges; negative
+// outside), with the frame's share at level l = those less than levels-l
+// deep (the core records the rest).
+int ensure_taps(dpml *H, int levels, const int r[4])
+{
+    const Layout &L = H->L;
+    const int NX = (int)L.N[0], NY = (int)L.N[1];
+    if (!H->d_rmap) {
+        std::vector<int32_t> rmap((size_t)(L.batch * NY), -1), pool;
+        for (int64_t i = 0; i < (int64_t)H->rec_host.size(); ++i) {
+            const int64_t cell = H->rec_host[i], b = cell / L.ncell, c = cell % L.ncell;
+            const int64_t key = b * NY + c / NX;
+            if (rmap[(size_t)key] < 0) {
+                rmap[(size_t)key] = (int32_t)pool.size();
+                pool.resize(pool.size() + (size_t)NX, -1);
+            }
+            pool[(size_t)rmap[(size_t)key] + (size_t)(c % NX)] = (int32_t)i;
+        }
+        HIP_TRY(H, hipMalloc((void **)&H->d_rmap, rmap.size() * sizeof(int32_t)));
+        HIP_TRY(H, hipMalloc((void **)&H->d_rpool, std::max<size_t>(pool.size(), 1) * sizeof(int32_t)));
+        HIP_TRY(H, hipMemcpy(H->d_rmap, rmap.data(), rmap.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+        if (!pool.empty())
+            HIP_TRY(H, hipMemcpy(H->d_rpool, pool.data(), pool.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+    }
+    const int q = levels - 2;
+    if (!H->d_frec_cells[q]) {
+        const int64_t nr = (int64_t)H->rec_host.size();
+        std::vector<int64_t> order((size_t)nr);
+        std::vector<int> depth((size_t)nr);
+        for (int64_t i = 0; i < nr; ++i) {
+            const int64_t c = H->rec_host[i] % L.ncell;
+            const int x = (int)(c % NX), y = (int)(c / NX);
+            depth[i] = std::min(std::min(x - r[0], r[1] - 1 - x), std::min(y - r[2], r[3] - 1 - y));
+            order[i] = i;
+        }
+        std::stable_sort(order.begin(), order.end(), [&](int64_t a, int64_t b) { return depth[a] < depth[b]; });
+        std::vector<int64_t> cells((size_t)nr);
+        std::vector<int32_t> idx((size_t)nr);
+        for (int64_t k = 0; k < nr; ++k) {
+            cells[k] = H->rec_host[order[k]];
+            idx[k] = (int32_t)order[k];
+        }
+        for (int l = 1; l <= levels; ++l) {
+            int64_t cnt = 0;
+            while (cnt < nr && depth[order[cnt]] < levels - l) ++cnt;
+            H->frec_count[q][l] = cnt;
+        }
+        HIP_TRY(H, hipMalloc((void **)&H->d_frec_cells[q], (size_t)std::max<int64_t>(nr, 1) * sizeof(int64_t)));
+        HIP_TRY(H, hipMalloc((void **)&H->d_frec_idx[q], (size_t)std::max<int64_t>(nr, 1) * sizeof(int32_t)));
+        HIP_TRY(H, hipMemcpy(H->d_frec_cells[q], cells.data(), (size_t)nr * sizeof(int64_t), hipMemcpyHostToDevice));
+        HIP_TRY(H, hipMemcpy(H->d_frec_idx[q], idx.data(), (size_t)nr * sizeof(int32_t), hipMemcpyHostToDevice));
+    }
+    return DPML_OK;
+}
+
+// Release the receiver tables (receivers re-registered, or destroy).
+void free_taps(dpml *H)
+{
+    if (H->d_rmap) (void)hipFree(H->d_rmap);
+    if (H->d_rpool) (void)hipFree(H->d_rpool);
+    H->d_rmap = H->d_rpool = nullptr;
+    for (int q = 0; q < kMaxLevels - 1; ++q) {
+        if (H->d_frec_cells[q]) (void)hipFree(H->d_frec_cells[q]);
+        if (H->d_frec_idx[q]) (void)hipFree(H->d_frec_idx[q]);
+        H->d_frec_cells[q] = nullptr;
+        H->d_frec_idx[q] = nullptr;
+    }
+}
+
 // The fused frame kernel of a pass of 2 .. kMaxLevels levels.
 template <typename T>
 void launch_fused(int levels, dim3 grid, hipStream_t st, const dpmlk::StepArgs<T> &p, T *pen, T *fin,
@@ -304,16 +393,16 @@ void launch_fused(int levels, dim3 grid, hipStream_t st, const dpmlk::StepArgs<T
 // group issued ahead).
 template <typename T, int VX, int G, bool C2>
 void launch_coreN(int levels, bool pf, dim3 grid, hipStream_t st, const dpmlk::StepArgs<T> &p, T *pen, T *fin,
-                  const int r[4], int strips, int n_waves)
+                  const int r[4], int strips, int n_waves, const dpmlk::Taps2<T> &tp)
 {
     const dim3 block(256);
 #define DPML_CORE_N(NL)                                                                                        \
     if (pf)                                                                                                    \
         hipLaunchKernelGGL((dpmlk::k_stepN_march<T, VX, G, C2, NL, true>), grid, block, 0, st, p, pen, fin, r[0], \
-                           r[1], r[2], r[3], strips, n_waves);                                                 \
+                           r[1], r[2], r[3], strips, n_waves, tp);                                             \
     else                                                                                                       \
         hipLaunchKernelGGL((dpmlk::k_stepN_march<T, VX, G, C2, NL, false>), grid, block, 0, st, p, pen, fin, r[0], \
-                           r[1], r[2], r[3], strips, n_waves)
+                           r[1], r[2], r[3], strips, n_waves, tp)
     switch (levels) {
     case 4: DPML_CORE_N(4); break;
     case 5: DPML_CORE_N(5); break;
@@ -358,6 +447,28 @@ int launch_multistep(dpml *H, int levels)
     const int n_waves = strips * ((r[3] - r[2] + rows - 1) / rows);
     const dim3 block(256);
     const double core = (double)(r[1] - r[0]) * (double)(r[3] - r[2]);
+    // sources and receivers of this pass (passes of 4 .. 8 levels only)
+    dpmlk::Taps2<T> tp{};
+    const bool rec = H->recording && H->nr > 0;
+    if (H->ns > 0 || rec) {
+        if (levels < 4) return H->fail(DPML_EINVAL, "sources or receivers in a pass of fewer than 4 levels");
+        if (rec) {
+            int rc = ensure_taps(H, levels, r);
+            if (rc) return rc;
+            tp.nr = (int32_t)H->nr;
+            tp.rmap = H->d_rmap;
+            tp.rpool = H->d_rpool;
+            tp.traces = (T *)H->traces;
+            tp.nt_rec = H->nt_rec;
+        }
+        tp.ns = (int32_t)H->ns;
+        tp.scells = H->d_src_cells;
+        tp.sorder = H->d_src_order;
+        tp.wav = (const T *)H->wavelets;
+        tp.nt_src = H->nt_src;
+        tp.amp = (T)(H->dt * H->dt / (H->h * H->h));
+        tp.n = H->n;
+    }
     // fork: the side stream starts once everything before this pass is done
     HIP_TRY(H, hipEventRecord(H->ev_fork, H->stream));
     HIP_TRY(H, hipStreamWaitEvent(H->side, H->ev_fork, 0));
@@ -376,7 +487,7 @@ int launch_multistep(dpml *H, int levels)
                                nxt[2], r[0], r[1], r[2], r[3], strips, n_waves);                            \
         else                                                                                                \
             launch_coreN<T, VX, GG, C2>(levels, (H->tile_rows >> 24) & 1, grid, H->stream, p, nxt[levels - 2],    \
-                                        nxt[levels - 1], r, strips, n_waves);
+                                        nxt[levels - 1], r, strips, n_waves, tp);
         if (G == 4) {
             if (p.c2) { DPML_MULTI_LAUNCH(4, true) } else { DPML_MULTI_LAUNCH(4, false) }
         } else if (G == 1) {
@@ -438,6 +549,12 @@ int launch_multistep(dpml *H, int levels)
             hipLaunchKernelGGL((dpmlk::k_step_frame<T>), dim3((unsigned)round8(nf), B), block, 0, H->side, pj,
                                H->d_frame[q][sh], nf);
         timed_end(H, slot, H->side);
+        // the receivers less than levels-j cells inside the core, from this step's output
+        const int64_t nrec = rec ? H->frec_count[q][j] : 0;
+        if (nrec > 0 && H->n + j - 1 < H->nt_rec)
+            hipLaunchKernelGGL((dpmlk::k_record_list<T>), dim3((unsigned)((nrec + 255) / 256)), block, 0, H->side,
+                               (const T *)nxt[j - 1], H->d_frec_cells[q], H->d_frec_idx[q], nrec, (T *)H->traces,
+                               H->nt_rec, H->n + j - 1);
     }
     // join
     HIP_TRY(H, hipEventRecord(H->ev_join, H->side));
@@ -785,6 +902,8 @@ int dpml_record(dpml_t *H, int64_t nr, const int64_t *cells, void *traces, int64
     HIP_TRY(H, hipStreamSynchronize(H->stream));
     for (int64_t **pp : {&H->d_rec_cells, &H->d_rec_sorted, &H->d_rec_order})
         if (*pp) { HIP_TRY(H, hipFree(*pp)); *pp = nullptr; }
+    free_taps(H);
+    H->rec_host.assign(cells, cells + nr);
     H->nr = 0;
     if (nr == 0) return DPML_OK;
     std::vector<int64_t> order((size_t)nr);
@@ -792,6 +911,8 @@ int dpml_record(dpml_t *H, int64_t nr, const int64_t *cells, void *traces, int64
     std::stable_sort(order.begin(), order.end(), [&](int64_t a, int64_t b) { return cells[a] < cells[b]; });
     std::vector<int64_t> sorted((size_t)nr);
     for (int64_t q = 0; q < nr; ++q) sorted[q] = cells[order[q]];
+    H->rec_dups = false;
+    for (int64_t q = 1; q < nr; ++q) H->rec_dups |= sorted[q] == sorted[q - 1];
     HIP_TRY(H, hipMalloc((void **)&H->d_rec_cells, (size_t)nr * sizeof(int64_t)));
     HIP_TRY(H, hipMalloc((void **)&H->d_rec_sorted, (size_t)nr * sizeof(int64_t)));
     HIP_TRY(H, hipMalloc((void **)&H->d_rec_order, (size_t)nr * sizeof(int64_t)));
@@ -1021,6 +1142,7 @@ void dpml_destroy(dpml_t *H)
     if (H->ev_join) (void)hipEventDestroy(H->ev_join);
     if (H->side) (void)hipStreamDestroy(H->side);
     if (H->d_adj_frame) (void)hipFree(H->d_adj_frame);
+    free_taps(H);
     if (H->d_rec_sorted) (void)hipFree(H->d_rec_sorted);
     if (H->d_rec_order) (void)hipFree(H->d_rec_order);
     for (hipEvent_t e : H->events) (void)hipEventDestroy(e);
@@ -1088,13 +1210,17 @@ template <typename T>
 int forward_ckpt_impl(dpml *H, int64_t nsteps)
 {
     const AdjLayout A = adj_layout(H, nsteps, H->adj_every);
-    for (int64_t k = 0; k < nsteps; ++k) {
+    // a checkpoint every adj_every steps; the steps between two checkpoints
+    // go as one run (multi-step passes where the variant takes them)
+    for (int64_t k = 0; k < nsteps;) {
         if (k % H->adj_every == 0) {
             int rc = copy_state(H, H->adj_ws + A.off_ckpt + (size_t)(k / H->adj_every) * A.state, true);
             if (rc) return rc;
         }
-        int rc = step_impl<T>(H, 1);
+        const int64_t seg = std::min(H->adj_every - k % H->adj_every, nsteps - k);
+        int rc = step_impl<T>(H, seg);
         if (rc) return rc;
+        k += seg;
     }
     return DPML_OK;
 }

@@ -216,6 +216,16 @@ struct dpml {
     size_t events_used = 0;
     std::string err;
     void *scratch = nullptr;   // this device's static scratch (dpml_step_checked_noalloc)
+    // sources/receivers of the 2D multi-step passes: host copy of the
+    // receivers, whether two share a cell (then no passes), the per-(member,
+    // row) column maps, and per pass depth the receivers sorted by how deep
+    // they lie in the core with the frame's share per level
+    std::vector<int64_t> rec_host;
+    bool rec_dups = false;
+    int32_t *d_rmap = nullptr, *d_rpool = nullptr;
+    int64_t *d_frec_cells[dpmlh::kMaxLevels - 1] = {};
+    int32_t *d_frec_idx[dpmlh::kMaxLevels - 1] = {};
+    std::array<int64_t, dpmlh::kMaxLevels + 1> frec_count[dpmlh::kMaxLevels - 1] = {};
 
     void *at(size_t off) { return ws + off; }
     int fail(int code, const std::string &msg) { err = msg; return code; }

@@ -1019,10 +1019,76 @@ __global__ void __launch_bounds__(256) k_step3_march(StepArgs<T> p, T *__restric
 // rows, so each side of a strip carries HL = ceil(NL/VX) halo lanes and a
 // tile reads NL rows beyond each end.
 // ---------------------------------------------------------------------------
+// Point sources and receivers of a 2D pass (not part of the paper; the
+// workload's shots and traces).  Level l of a pass from time index n is the
+// step n+l-1: its sources add dt^2 w_s[n+l-1] / h^2 to U^{n+l} at their cells
+// (every time a wave forms that cell at that level, halo copies included, so
+// the levels built on it agree), and its receivers take U^{n+l} into trace
+// column n+l-1.  The core records a receiver at level l when it lies at least
+// NL-l cells inside the core (only the wave and lane that own the cell
+// write); the frame's step l records the others from its own output.
+template <typename T>
+struct Taps2 {
+    const int64_t *scells;     // source cells over the batch, ascending (member * cells + cell)
+    const int64_t *sorder;     // caller's index of each sorted source
+    const T *wav;              // wavelets [ns][nt_src]
+    int32_t ns;                // sources (at most 32), 0: none
+    int32_t nr;                // receivers, 0: none recorded
+    int64_t nt_src, nt_rec;
+    T amp;                     // dt^2 / h^2
+    const int32_t *rmap;       // [member * ny + y]: first pool slot of row y's column map, or -1
+    const int32_t *rpool;      // pool[slot + x]: receiver index of column x, or -1
+    T *traces;                 // [nr][nt_rec]
+    int64_t n;                 // time index of the pass's first step
+};
+
 template <typename T, int VX, bool C2F, int NL>
 struct MarchNCtx : March2Ctx<T, VX, C2F> {
     using R = Row<T, VX>;
     T *open, *ofin;                // U^{n+NL-1}, U^{n+NL}
+    Taps2<T> tp;                   // sources and receivers (tp.ns == 0 and tp.nr == 0: none)
+    uint32_t smask = 0;            // sources this wave may form (bit q: the run starting at sorted q)
+    int member = 0;
+    bool taps = false;             // the tile has a source or receiver row: march with tap()
+
+    // level l (1 .. NL) of this lane's cells on array row y: add the sources
+    // there; record the receivers this lane owns (`own`: the row belongs to
+    // the wave's tile)
+    __device__ __forceinline__ void tap(R &v, int l, int y, bool own) const
+    {
+        const int nx = this->nx, ny = this->ny;
+        const int64_t t = tp.n + l - 1;
+        if (smask && t < tp.nt_src) {
+            const int64_t mb = (int64_t)member * nx * ny;
+            for (uint32_t m = smask; m; m &= m - 1) {
+                const int q = __builtin_ctz(m);
+                const int64_t cell = tp.scells[q] - mb;
+                if ((int)(cell / nx) != y) continue;
+                const int sx = (int)(cell % nx);
+                T add = T(0);
+                for (int r = q; r < tp.ns && tp.scells[r] == tp.scells[q]; ++r) add += tp.wav[tp.sorder[r] * tp.nt_src + t];
+#pragma unroll
+                for (int k = 0; k < VX; ++k) {
+                    int x = (this->xs + k) % nx;
+                    if (x < 0) x += nx;
+                    if (x == sx) v.v[k] = v.v[k] + tp.amp * add;
+                }
+            }
+        }
+        if (tp.nr && own && this->out && t < tp.nt_rec) {
+            const int slot = tp.rmap[(int64_t)member * ny + y];
+            if (slot >= 0) {
+#pragma unroll
+                for (int k = 0; k < VX; ++k) {
+                    const int x = this->xs + k;
+                    if (x < this->cx0 || x >= this->cx1) continue;
+                    const int ri = tp.rpool[slot + x];
+                    const int d = min(min(x - this->cx0, this->cx1 - 1 - x), min(y - this->cy0, this->cy1 - 1 - y));
+                    if (ri >= 0 && d >= NL - l) tp.traces[(int64_t)ri * tp.nt_rec + t] = v.v[k];
+                }
+            }
+        }
+    }
 
     // rolling state at march index k: w[m] = level m on rows k-m-1, k-m
     // (m < NL); c[i] = c^2 on row k-NL+1+i (i < NL-1)
@@ -1031,19 +1097,21 @@ struct MarchNCtx : March2Ctx<T, VX, C2F> {
         R c[NL - 1];
     };
 
-    // one march index k, every level guarded (prologue and tail)
-    template <int DIR>
+    // one march index k, every level guarded (prologue and tail; the whole
+    // tile of a wave with sources or receivers, TAP)
+    template <int DIR, bool TAP = false>
     __device__ __forceinline__ void one(State &s, int base, int k, int L) const
     {
         const R nn = this->load(this->u, this->wrapy(base + DIR * (k + 1)));
         const R pm = this->load(this->up, this->wrapy(base + DIR * k));
         R cn{};
         if (C2F) cn = this->load(this->c2, this->wrapy(base + DIR * k));
-        advance<DIR>(s, base, k, L, nn, pm, cn);
+        advance<DIR, TAP>(s, base, k, L, nn, pm, cn);
     }
 
-    // march index k from its loads: U^n(k+1), U^{n-1}(k), c^2(k)
-    template <int DIR>
+    // march index k from its loads: U^n(k+1), U^{n-1}(k), c^2(k); TAP: with
+    // the sources and receivers of the level rows formed
+    template <int DIR, bool TAP = false>
     __device__ __forceinline__ void advance(State &s, int base, int k, int L, const R &nn, const R &pm,
                                             const R &cn) const
     {
@@ -1057,6 +1125,7 @@ struct MarchNCtx : March2Ctx<T, VX, C2F> {
             const R &old = l == 1 ? pm : s.w[l >= 2 ? l - 2 : 0][0];
             const R &cl = l == 1 ? cn : s.c[l >= 2 ? NL - l : 0];
             cur[l] = this->template lev<DIR>(s.w[l - 1][0], s.w[l - 1][1], cur[l - 1], old, cl);
+            if (TAP) tap(cur[l], l, this->wrapy(base + DIR * r), r >= 0 && r < L);
             if (l == NL - 1 && r >= 0 && r < L) this->store_inner(open, base + DIR * r, cur[l]);
             if (l == NL && r >= 0 && r < L) this->store(ofin, base + DIR * r, cur[l]);
         }
@@ -1151,6 +1220,11 @@ struct MarchNCtx : March2Ctx<T, VX, C2F> {
         s.w[0][0] = this->load(this->u, this->wrapy(base - NL * DIR));
         s.w[0][1] = this->load(this->u, this->wrapy(base - (NL - 1) * DIR));
         int k = -(NL - 1);
+        if (taps) {
+            // a tile with sources or receivers: one march index at a time
+            for (; k <= L + NL - 2; ++k) one<DIR, true>(s, base, k, L);
+            return;
+        }
         if (PF) {
             const int kend = L + NL - 2;
             R ru[kAhead], rp[kAhead], rc[kAhead];
@@ -1190,7 +1264,8 @@ struct MarchNCtx : March2Ctx<T, VX, C2F> {
 // [cx0, cx1) x [cy0, cy1) and run it.
 template <typename T, int VX, int G, bool C2F, int NL, bool PF>
 __device__ __forceinline__ void run_marchN(const StepArgs<T> &p, const T *u, const T *uo, T *u_pen, T *u_fin,
-                                           int cx0, int cx1, int cy0, int cy1, int strip, int ty, int lane)
+                                           int cx0, int cx1, int cy0, int cy1, int strip, int ty, int lane,
+                                           const Taps2<T> &tp = Taps2<T>{})
 {
     constexpr int HL = (NL + VX - 1) / VX;                   // halo lanes per side
     MarchNCtx<T, VX, C2F, NL> c;
@@ -1218,6 +1293,23 @@ __device__ __forceinline__ void run_marchN(const StepArgs<T> &p, const T *u, con
     c.out = lane >= HL && lane < 64 - HL && c.xs < cx1;
     const int rows = p.tile_rows;
     const int ya = cy0 + ty * rows, yb = min(ya + rows, cy1);
+    c.tp = tp;
+    c.member = (int)blockIdx.y;
+    if (tp.ns > 0) {
+        // the sources of this member whose row is within the rows the wave
+        // forms at some level ([ya - NL, yb + NL)); columns are tested per lane
+        const int64_t mb = (int64_t)c.member * p.nx * p.ny;
+        for (int q = 0; q < tp.ns && q < 32; ++q) {
+            const int64_t cell = tp.scells[q];
+            if (q > 0 && tp.scells[q - 1] == cell) continue;
+            if (cell < mb || cell >= mb + (int64_t)p.nx * p.ny) continue;
+            const int sy = (int)((cell - mb) / p.nx);
+            if (sy >= ya - NL && sy < yb + NL) c.smask |= 1u << q;
+        }
+    }
+    c.taps = c.smask != 0;
+    if (tp.nr > 0)
+        for (int y = ya; y < yb && !c.taps; ++y) c.taps = tp.rmap[(int64_t)c.member * p.ny + y] >= 0;
     if (ty & 1)
         c.template march<G, -1, PF>(yb - 1, yb - ya);
     else
@@ -1226,13 +1318,26 @@ __device__ __forceinline__ void run_marchN(const StepArgs<T> &p, const T *u, con
 
 template <typename T, int VX, int G, bool C2F, int NL, bool PF>
 __global__ void __launch_bounds__(256) k_stepN_march(StepArgs<T> p, T *__restrict__ u_pen, T *__restrict__ u_fin,
-                                                     int cx0, int cx1, int cy0, int cy1, int strips, int n_waves)
+                                                     int cx0, int cx1, int cy0, int cy1, int strips, int n_waves,
+                                                     Taps2<T> tp)
 {
     const int w = __builtin_amdgcn_readfirstlane(xcd_tile(blockIdx.x, gridDim.x) * 4 + (int)(threadIdx.x >> 6));
     if (w >= n_waves) return;                                // whole waves; no barriers below
     const int64_t boff = (int64_t)blockIdx.y * p.bstride;
     run_marchN<T, VX, G, C2F, NL, PF>(p, p.u + boff, p.uo + boff, u_pen + boff, u_fin + boff, cx0, cx1, cy0, cy1,
-                                      w % strips, w / strips, (int)(threadIdx.x & 63));
+                                      w % strips, w / strips, (int)(threadIdx.x & 63), tp);
+}
+
+// Receivers from a list: traces[idx[i]][t] = U[cells[i]] for i < count (the
+// receivers a frame step owns at its level).
+template <typename T>
+__global__ void __launch_bounds__(256) k_record_list(const T *__restrict__ u, const int64_t *__restrict__ cells,
+                                                     const int32_t *__restrict__ idx, int64_t count,
+                                                     T *__restrict__ traces, int64_t nt, int64_t t)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= count) return;
+    traces[(int64_t)idx[i] * nt + t] = u[cells[i]];
 }
 
 template <typename T, int VX, int G>
