@@ -419,9 +419,12 @@ void launch_coreN(int levels, bool pf, dim3 grid, hipStream_t st, const dpmlk::S
 // levels - j cells, which is where the later frame steps need level j.  The
 // core writes no level-j value on those cells, so every cell of every
 // buffer has one writer.  The pass ends with the handle's stream waiting
-// for the side stream.
+// for the side stream.  With `hist`, level l goes to hist + (l-1) * hstride
+// (whole batch levels; every level kept: passes of 2 or 4 .. kMaxLevels
+// levels, the frame's steps one launch per level) and the fields then point
+// there.
 template <typename T>
-int launch_multistep(dpml *H, int levels)
+int launch_multistep(dpml *H, int levels, T *hist = nullptr, int64_t hstride = 0)
 {
     const Layout &L = H->L;
     const unsigned B = (unsigned)L.batch;
@@ -430,6 +433,10 @@ int launch_multistep(dpml *H, int levels)
     T *A = (T *)H->u_now, *Bv = (T *)H->u_old;
     T *nxt[kMaxLevels] = {};
     int k = 0;
+    if (hist) {
+        if (levels == 3 || frame_fused(H)) return H->fail(DPML_EINVAL, "a history pass of this shape");
+        for (; k < levels; ++k) nxt[k] = hist + (int64_t)k * hstride;
+    }
     for (int i = 0; i < L.n_ubuf && k < levels; ++i) {
         void *b = H->at(L.off_u[i]);
         if (b != H->u_now && b != H->u_old) nxt[k++] = (T *)b;
@@ -485,6 +492,9 @@ int launch_multistep(dpml *H, int levels)
         else if (levels == 3)                                                                               \
             hipLaunchKernelGGL((dpmlk::k_step3_march<T, VX, GG, C2>), grid, block, 0, H->stream, p, nxt[1],     \
                                nxt[2], r[0], r[1], r[2], r[3], strips, n_waves);                            \
+        else if (hist)                                                                                      \
+            launch_coreN_hist<T>(levels, GG, C2, grid, H->stream, p, hist, hstride, nxt[levels - 2],          \
+                                 nxt[levels - 1], r, strips, n_waves, tp);                                  \
         else                                                                                                \
             launch_coreN<T, VX, GG, C2>(levels, (H->tile_rows >> 24) & 1, grid, H->stream, p, nxt[levels - 2],    \
                                         nxt[levels - 1], r, strips, n_waves, tp);
@@ -1227,6 +1237,8 @@ int forward_ckpt_impl(dpml *H, int64_t nsteps)
 
 constexpr int kAdjRows = 4;   // rows per wave of the 2D marching adjoint kernel
 constexpr int kAdjFrameGroups = 8;   // waves (shot groups) per block of the 2D adjoint frame
+template <typename T>
+constexpr int kAdjFrameShots = sizeof(T) == 4 ? 2 : 1;   // shots whose loads a frame wave issues together
 
 // Core of the 2D adjoint: cells whose update, and whose neighbours' band
 // slots, carry no layer term: [lo+2, lo+n-1) on an axis with a layer, the
@@ -1297,7 +1309,13 @@ int adjoint_impl(dpml *H, const void *resid, double *grad, void *grad_w)
     // frame one thread per cell over a tile list
     int core[4] = {0, 0, 0, 0};
     int adj_tiles_x = 0, adj_waves = 0;
-    if (L.ndim == 2) {
+    // the frame kernel addresses a member's field and each axis's compact
+    // auxiliaries by 32-bit byte offsets: larger 2D members take one thread
+    // per cell over the whole grid
+    bool fits32 = (uint64_t)L.ncell * L.esize < (1ull << 32);
+    for (int a = 0; a < L.ndim; ++a) fits32 &= (uint64_t)L.aux_elems[a] * L.esize < (1ull << 32);
+    const bool march2d = L.ndim == 2 && fits32;
+    if (march2d) {
         int rc = ensure_adj_frame(H);
         if (!rc) rc = ensure_side(H);
         if (rc) return rc;
@@ -1318,13 +1336,25 @@ int adjoint_impl(dpml *H, const void *resid, double *grad, void *grad_w)
         if (rc) return rc;
         H->n = t0;
         // U^{t0} goes to history slot 0; each recomputed level is then written
-        // straight into the next slot (reading the two previous slots), so the
-        // recompute moves the same 3 words per cell as a forward step
+        // straight into its slot: the multi-step passes keep every level they
+        // form (the levels the handle's variant takes, 2 or 4 and more), the
+        // rest single steps reading the two previous slots
         HIP_TRY(H, hipMemcpyAsync(ws + A.off_hist, H->u_now, lb, hipMemcpyDeviceToDevice, H->stream));
-        for (int64_t k = t0; k + 1 < t1; ++k) {
+        H->u_now = ws + A.off_hist;
+        const int64_t hstride = (int64_t)(A.level / sizeof(T));
+        for (int64_t k = t0; k + 1 < t1;) {
             T *slot = (T *)(ws + A.off_hist + (size_t)(k - t0 + 1) * A.level);
-            T *cur = (T *)(ws + A.off_hist + (size_t)(k - t0) * A.level);
-            H->u_now = cur;                 // U^k; u_old holds U^{k-1}
+            int lv = L.ndim == 2 ? multistep_levels(H, t1 - 1 - k) : 1;
+            if (lv == 3) lv = 2;
+            if (lv >= 2 && frame_fused(H)) lv = 1;
+            if (lv >= 2) {
+                rc = ensure_multistep(H, lv);
+                if (!rc) rc = launch_multistep<T>(H, lv, slot, hstride);
+                if (rc) return rc;
+                k += lv;
+                continue;
+            }
+            T *cur = (T *)H->u_now;         // U^k; u_old holds U^{k-1}
             rc = launch_step<T>(H, nullptr, slot);
             if (rc) return rc;
             if (H->ns > 0 && H->n < H->nt_src) {
@@ -1336,6 +1366,7 @@ int adjoint_impl(dpml *H, const void *resid, double *grad, void *grad_w)
             H->u_now = slot;
             H->cur = 1 - H->cur;
             H->n += 1;
+            ++k;
         }
         // reverse sweep over the segment
         for (int64_t n = t1 - 1; n >= t0; --n) {
@@ -1346,11 +1377,15 @@ int adjoint_impl(dpml *H, const void *resid, double *grad, void *grad_w)
                 hipLaunchKernelGGL((dpmlk::k_inject<T>), g2, b2, 0, H->stream, lam, H->d_rec_sorted,
                                    H->d_rec_order, (const T *)resid, H->nr, H->nt_rec, n, (T)1);
             }
-            if (H->ns > 0 && n < H->nt_src && grad_w) {
-                dim3 g2((unsigned)((H->ns + 255) / 256)), b2(256);
-                hipLaunchKernelGGL((dpmlk::k_gather_scaled<T>), g2, b2, 0, H->stream, (const T *)lam,
-                                   H->d_src_cells, H->d_src_order, (T *)grad_w, H->ns, H->nt_src, n, wamp);
-            }
+            // dJ/dw from a^{n+1} (nothing writes a^{n+1} during this level: the 2D
+            // path gathers it on the side stream beside the core)
+            auto gather = [&](hipStream_t st) {
+                if (H->ns > 0 && n < H->nt_src && grad_w) {
+                    dim3 g2((unsigned)((H->ns + 255) / 256)), b2(256);
+                    hipLaunchKernelGGL((dpmlk::k_gather_scaled<T>), g2, b2, 0, st, (const T *)lam, H->d_src_cells,
+                                       H->d_src_order, (T *)grad_w, H->ns, H->nt_src, n, wamp);
+                }
+            };
             dpmlk::AdjArgs<T> q{};
             for (int a = 0; a < 3; ++a) {
                 q.ax[a] = make_axis<T>(H, a, false);
@@ -1379,7 +1414,7 @@ int adjoint_impl(dpml *H, const void *resid, double *grad, void *grad_w)
             q.nz = (int32_t)L.N[2];
             q.batch = (int32_t)L.batch;
             q.bstride = L.ncell;
-            if (L.ndim == 2) {
+            if (march2d) {
                 // the frame's cells on the side stream while the core marches on the
                 // handle's stream (disjoint cells; joined before the next level)
                 const bool fork = H->n_adj_frame > 0 && adj_waves > 0;
@@ -1387,12 +1422,13 @@ int adjoint_impl(dpml *H, const void *resid, double *grad, void *grad_w)
                     HIP_TRY(H, hipEventRecord(H->ev_fork, H->stream));
                     HIP_TRY(H, hipStreamWaitEvent(H->side, H->ev_fork, 0));
                 }
+                gather(fork ? H->side : H->stream);
                 if (H->n_adj_frame > 0) {
                     dpmlk::AdjArgs<T> f = q;
                     f.tiles = H->d_adj_frame;
                     f.ntiles = (int32_t)H->n_adj_frame;
                     for (int k = 0; k < 4; ++k) f.skip[k] = core[k];
-                    hipLaunchKernelGGL((dpmlk::k_adjoint_frame2d<T, kAdjFrameGroups>), fgrid, dim3(64 * kAdjFrameGroups),
+                    hipLaunchKernelGGL((dpmlk::k_adjoint_frame2d<T, kAdjFrameGroups, kAdjFrameShots<T>>), fgrid, dim3(64 * kAdjFrameGroups),
                                        0, fork ? H->side : H->stream, f);
                 }
                 if (adj_waves > 0)
@@ -1403,7 +1439,11 @@ int adjoint_impl(dpml *H, const void *resid, double *grad, void *grad_w)
                     HIP_TRY(H, hipStreamWaitEvent(H->stream, H->ev_join, 0));
                 }
             } else {
-                hipLaunchKernelGGL((dpmlk::k_adjoint_cell<T, 3>), agrid, ablock, 0, H->stream, q);
+                gather(H->stream);
+                if (L.ndim == 2)
+                    hipLaunchKernelGGL((dpmlk::k_adjoint_cell<T, 2>), agrid, ablock, 0, H->stream, q);
+                else
+                    hipLaunchKernelGGL((dpmlk::k_adjoint_cell<T, 3>), agrid, ablock, 0, H->stream, q);
             }
             HIP_TRY(H, hipGetLastError());
             lcur = 1 - lcur;

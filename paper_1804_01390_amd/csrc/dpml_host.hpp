@@ -443,5 +443,15 @@ int multistep_levels3d(const dpml *H, int64_t nsteps);
 template <typename T>
 int launch_multistep3d(dpml *H);
 
+// ---- 2D history passes (dpml_hist.hip; explicit instantiations for float and double)
+// The core kernel of a 2D pass of 4 .. kMaxLevels levels that stores every
+// level: U^{n+l} (l < levels-1) at hist + (l-1) * hstride on the core cells
+// at depth >= levels-l, the last two levels to pen and fin as the ordinary
+// pass.  G: rows whose loads a wave issues together (1, 2 or 4).
+template <typename T>
+void launch_coreN_hist(int levels, int G, bool c2, dim3 grid, hipStream_t st, const dpmlk::StepArgs<T> &p, T *hist,
+                       int64_t hstride, T *pen, T *fin, const int r[4], int strips, int n_waves,
+                       const dpmlk::Taps2<T> &tp);
+
 }  // namespace dpmlh
 

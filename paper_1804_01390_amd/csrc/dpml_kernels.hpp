@@ -1042,10 +1042,12 @@ struct Taps2 {
     int64_t n;                 // time index of the pass's first step
 };
 
-template <typename T, int VX, bool C2F, int NL>
+template <typename T, int VX, bool C2F, int NL, bool HS = false>
 struct MarchNCtx : March2Ctx<T, VX, C2F> {
     using R = Row<T, VX>;
     T *open, *ofin;                // U^{n+NL-1}, U^{n+NL}
+    T *hist = nullptr;             // HS: U^{n+l} at hist + (l-1) * hstride for l < NL-1
+    int64_t hstride = 0;
     Taps2<T> tp;                   // sources and receivers (tp.ns == 0 and tp.nr == 0: none)
     uint32_t smask = 0;            // sources this wave may form (bit q: the run starting at sorted q)
     int member = 0;
@@ -1090,6 +1092,24 @@ struct MarchNCtx : March2Ctx<T, VX, C2F> {
         }
     }
 
+    // HS (history passes): level l < NL-1 of this lane's cells of row y at
+    // depth >= NL-l inside the core; the frame's steps write the cells
+    // nearer the core's edge, so every cell of level l has one writer
+    __device__ __forceinline__ void store_level(int l, int y, const R &r) const
+    {
+        const int dd = NL - l;
+        if (!this->out || y < this->cy0 + dd || y >= this->cy1 - dd) return;
+        T *row = hist + (int64_t)(l - 1) * hstride + (int64_t)y * this->nx + this->xs;
+        const int xa = this->cx0 + dd, xb = this->cx1 - dd;
+        if (this->xs >= xa && this->xs + VX <= xb) {
+            store_row<T, VX>(row, r);
+        } else {
+#pragma unroll
+            for (int k = 0; k < VX; ++k)
+                if (this->xs + k >= xa && this->xs + k < xb) row[k] = r.v[k];
+        }
+    }
+
     // rolling state at march index k: w[m] = level m on rows k-m-1, k-m
     // (m < NL); c[i] = c^2 on row k-NL+1+i (i < NL-1)
     struct State {
@@ -1126,6 +1146,7 @@ struct MarchNCtx : March2Ctx<T, VX, C2F> {
             const R &cl = l == 1 ? cn : s.c[l >= 2 ? NL - l : 0];
             cur[l] = this->template lev<DIR>(s.w[l - 1][0], s.w[l - 1][1], cur[l - 1], old, cl);
             if (TAP) tap(cur[l], l, this->wrapy(base + DIR * r), r >= 0 && r < L);
+            if (HS && l < NL - 1 && r >= 0 && r < L) store_level(l, base + DIR * r, cur[l]);
             if (l == NL - 1 && r >= 0 && r < L) this->store_inner(open, base + DIR * r, cur[l]);
             if (l == NL && r >= 0 && r < L) this->store(ofin, base + DIR * r, cur[l]);
         }
@@ -1191,6 +1212,7 @@ struct MarchNCtx : March2Ctx<T, VX, C2F> {
                 const R v = this->template lev<DIR>(w[l - 1][g], w[l - 1][g + 1], w[l - 1][g + 2],
                                                     l == 1 ? pm[g] : w[l >= 2 ? l - 2 : 0][g], cw[NL - l + g]);
                 if (l < NL) w[l][2 + g] = v;
+                if (HS && l < NL - 1) store_level(l, base + DIR * (k - l + 1 + g), v);
                 if (l == NL - 1) this->store_inner(open, base + DIR * (k - l + 1 + g), v);
                 if (l == NL) this->store(ofin, base + DIR * (k - l + 1 + g), v);
             }
@@ -1262,13 +1284,16 @@ struct MarchNCtx : March2Ctx<T, VX, C2F> {
 
 // Set up a march context for strip `strip`, tile row `ty` of the core
 // [cx0, cx1) x [cy0, cy1) and run it.
-template <typename T, int VX, int G, bool C2F, int NL, bool PF>
+template <typename T, int VX, int G, bool C2F, int NL, bool PF, bool HS = false>
 __device__ __forceinline__ void run_marchN(const StepArgs<T> &p, const T *u, const T *uo, T *u_pen, T *u_fin,
                                            int cx0, int cx1, int cy0, int cy1, int strip, int ty, int lane,
-                                           const Taps2<T> &tp = Taps2<T>{})
+                                           const Taps2<T> &tp = Taps2<T>{}, T *hist = nullptr,
+                                           int64_t hstride = 0)
 {
     constexpr int HL = (NL + VX - 1) / VX;                   // halo lanes per side
-    MarchNCtx<T, VX, C2F, NL> c;
+    MarchNCtx<T, VX, C2F, NL, HS> c;
+    c.hist = hist;
+    c.hstride = hstride;
     c.u = u;
     c.up = uo;
     c.c2 = C2F ? p.c2 : nullptr;
@@ -1326,6 +1351,23 @@ __global__ void __launch_bounds__(256) k_stepN_march(StepArgs<T> p, T *__restric
     const int64_t boff = (int64_t)blockIdx.y * p.bstride;
     run_marchN<T, VX, G, C2F, NL, PF>(p, p.u + boff, p.uo + boff, u_pen + boff, u_fin + boff, cx0, cx1, cy0, cy1,
                                       w % strips, w / strips, (int)(threadIdx.x & 63), tp);
+}
+
+// The same pass storing every level (a history of U^{n+1} .. U^{n+NL} for
+// the adjoint's recompute): levels below NL-1 go to hist + (l-1) * hstride
+// on the core cells at depth >= NL-l, the last two to u_pen and u_fin as
+// above.
+template <typename T, int VX, int G, bool C2F, int NL>
+__global__ void __launch_bounds__(256) k_stepN_hist(StepArgs<T> p, T *__restrict__ hist, int64_t hstride,
+                                                    T *__restrict__ u_pen, T *__restrict__ u_fin, int cx0, int cx1,
+                                                    int cy0, int cy1, int strips, int n_waves, Taps2<T> tp)
+{
+    const int w = __builtin_amdgcn_readfirstlane(xcd_tile(blockIdx.x, gridDim.x) * 4 + (int)(threadIdx.x >> 6));
+    if (w >= n_waves) return;                                // whole waves; no barriers below
+    const int64_t boff = (int64_t)blockIdx.y * p.bstride;
+    run_marchN<T, VX, G, C2F, NL, false, true>(p, p.u + boff, p.uo + boff, u_pen + boff, u_fin + boff, cx0, cx1,
+                                               cy0, cy1, w % strips, w / strips, (int)(threadIdx.x & 63), tp,
+                                               hist + boff, hstride);
 }
 
 // Receivers from a list: traces[idx[i]][t] = U[cells[i]] for i < count (the
@@ -2186,101 +2228,172 @@ __device__ __forceinline__ T pq_at(const Axis<T> &A, int j, int64_t cbase, int64
     return A.phi[c] + A.psi[c];
 }
 
-// The transposed step at cell (x, y, z) for the shots bi0, bi0 + bstep, ...
-// (reverse mode of Eqs. (DiscretePML a-c)): writes a^n and the adjoint
-// auxiliaries of those shots and returns their c^2-gradient terms summed in
-// FP64 in shot order.
+// Geometry of one cell for the transposed step: flat index, neighbours,
+// c^2 there (shared by all batch members) and per-axis band slots.
+template <typename T>
+struct AdjGeo {
+    int64_t idx, nb[6];
+    T cc, cn[6];
+    int jc[3], jm[3], jp[3];
+    int64_t cbase[3], cstr[3];
+};
+
 template <typename T, int D>
-__device__ __forceinline__ double adj_cell(const AdjArgs<T> &p, int x, int y, int z, int bi0, int bstep)
+__device__ __forceinline__ AdjGeo<T> adj_geo(const AdjArgs<T> &p, int x, int y, int z)
 {
+    AdjGeo<T> g;
     const int nx = p.nx, ny = p.ny, nz = p.nz;
     const int64_t sy = nx, sz = (int64_t)nx * ny;
-    const int64_t idx = (int64_t)z * sz + (int64_t)y * sy + x;
+    g.idx = (int64_t)z * sz + (int64_t)y * sy + x;
     const int xm = wrap_dec(x, nx), xp = wrap_inc(x, nx);
     const int ym = wrap_dec(y, ny), yp = wrap_inc(y, ny);
     const int zm = D == 3 ? wrap_dec(z, nz) : 0, zp = D == 3 ? wrap_inc(z, nz) : 0;
-    const int64_t nb[6] = {idx - x + xm, idx - x + xp, idx + (int64_t)(ym - y) * sy, idx + (int64_t)(yp - y) * sy,
-                           idx + (int64_t)(zm - z) * sz, idx + (int64_t)(zp - z) * sz};
-    const int nnb = 2 * D;
-    // c^2 at the cell and its neighbours (shared by all batch members)
-    T cc = p.c2 ? p.c2[idx] : p.c2_const;
-    T cn[6];
+    g.nb[0] = g.idx - x + xm;
+    g.nb[1] = g.idx - x + xp;
+    g.nb[2] = g.idx + (int64_t)(ym - y) * sy;
+    g.nb[3] = g.idx + (int64_t)(yp - y) * sy;
+    g.nb[4] = g.idx + (int64_t)(zm - z) * sz;
+    g.nb[5] = g.idx + (int64_t)(zp - z) * sz;
+    g.cc = p.c2 ? p.c2[g.idx] : p.c2_const;
 #pragma unroll
-    for (int k = 0; k < 6; ++k) cn[k] = (k < nnb) ? (p.c2 ? p.c2[nb[k]] : p.c2_const) : T(0);
-    // per-axis band coordinates of the cell and of its two neighbours
-    int jc[3], jm[3], jp[3];
-    int64_t cbase[3], cstr[3];
+    for (int k = 0; k < 6; ++k) g.cn[k] = (k < 2 * D) ? (p.c2 ? p.c2[g.nb[k]] : p.c2_const) : T(0);
     const int coord[3] = {x, y, z};
     const int cm_[3] = {xm, ym, zm};
     const int cp_[3] = {xp, yp, zp};
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         const Axis<T> &A = p.ax[a];
-        jc[a] = jm[a] = jp[a] = 1 << 30;
-        cbase[a] = 0;
-        cstr[a] = 1;
+        g.jc[a] = g.jm[a] = g.jp[a] = 1 << 30;
+        g.cbase[a] = 0;
+        g.cstr[a] = 1;
         if (a < D && A.M > 0) {
-            jc[a] = band_coord(A, coord[a]);
-            jm[a] = band_coord(A, cm_[a]);
-            jp[a] = band_coord(A, cp_[a]);
-            if (a == 0) { cbase[a] = ((int64_t)z * ny + y) * (A.M + 1); cstr[a] = 1; }
-            if (a == 1) { cbase[a] = (int64_t)z * (A.M + 1) * nx + x; cstr[a] = nx; }
-            if (a == 2) { cbase[a] = (int64_t)y * nx + x; cstr[a] = (int64_t)nx * ny; }
+            g.jc[a] = band_coord(A, coord[a]);
+            g.jm[a] = band_coord(A, cm_[a]);
+            g.jp[a] = band_coord(A, cp_[a]);
+            if (a == 0) { g.cbase[a] = ((int64_t)z * ny + y) * (A.M + 1); g.cstr[a] = 1; }
+            if (a == 1) { g.cbase[a] = (int64_t)z * (A.M + 1) * nx + x; g.cstr[a] = nx; }
+            if (a == 2) { g.cbase[a] = (int64_t)y * nx + x; g.cstr[a] = (int64_t)nx * ny; }
         }
     }
+    return g;
+}
+
+// What the transposed step of one shot reads at a cell: a^{n+1} and U^n at
+// the cell and its neighbours, a^{n+2} at the cell, and per axis the
+// adjoint auxiliaries at the neighbours' band slots (p and q apart) and at
+// the cell's own slot and the slot beside it.
+template <typename T>
+struct AdjIn {
+    T lc, uc, lo, ln[6], uu[6];
+    T upp[3], upq[3], dnp[3], dnq[3];
+    T pc[3], pr[3], qc[3], ql[3];
+};
+
+template <typename T, int D>
+__device__ __forceinline__ void adj_load(const AdjArgs<T> &p, const AdjGeo<T> &g, int bi, AdjIn<T> &in)
+{
+    const int64_t bo = (int64_t)bi * p.bstride;
+    const T *lam = p.lam + bo;
+    const T *un = p.un + bo;
+    in.lc = lam[g.idx];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+        in.ln[k] = (k < 2 * D) ? lam[g.nb[k]] : T(0);
+        in.uu[k] = (k < 2 * D) ? un[g.nb[k]] : T(0);
+    }
+    in.uc = un[g.idx];
+    in.lo = p.lam_o[bo + g.idx];
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+        const Axis<T> &A = p.ax[a];
+        in.upp[a] = in.upq[a] = in.dnp[a] = in.dnq[a] = T(0);
+        in.pc[a] = in.pr[a] = in.qc[a] = in.ql[a] = T(0);
+        if (A.M == 0) continue;
+        const int64_t ba = (int64_t)bi * p.bstride_aux[a] + g.cbase[a];
+        if (g.jp[a] <= A.M) {
+            const int64_t c = ba + (int64_t)g.jp[a] * g.cstr[a];
+            in.upp[a] = A.phi[c];
+            in.upq[a] = A.psi[c];
+        }
+        if (g.jm[a] <= A.M) {
+            const int64_t c = ba + (int64_t)g.jm[a] * g.cstr[a];
+            in.dnp[a] = A.phi[c];
+            in.dnq[a] = A.psi[c];
+        }
+        if (g.jc[a] <= A.M) {
+            const int j = g.jc[a];
+            const int64_t c = ba + (int64_t)j * g.cstr[a];
+            if (j < A.M) {
+                in.pc[a] = A.phi[c];
+                in.pr[a] = A.phi[c + g.cstr[a]];
+            }
+            if (j > 0) {
+                in.qc[a] = A.psi[c];
+                in.ql[a] = A.psi[c - g.cstr[a]];
+            }
+        }
+    }
+}
+
+// The transposed step of shot bi at a cell from its loads (reverse mode of
+// Eqs. (DiscretePML a-c)): writes a^n and the adjoint auxiliaries and
+// returns the shot's c^2-gradient term.
+template <typename T, int D>
+__device__ __forceinline__ double adj_finish(const AdjArgs<T> &p, const AdjGeo<T> &g, int bi, const AdjIn<T> &in)
+{
+    const int64_t bo = (int64_t)bi * p.bstride;
+    const T clc = g.cc * in.lc;
+    T lapc = T(0), lapu = T(0);
+#pragma unroll
+    for (int k = 0; k < 6; k += 2) {
+        if (k < 2 * D) {
+            lapc += ((g.cn[k] * in.ln[k] - T(2) * clc) + g.cn[k + 1] * in.ln[k + 1]) * p.inv_h2;
+            lapu += ((in.uu[k] - T(2) * in.uc) + in.uu[k + 1]) * p.inv_h2;
+        }
+    }
+    T v = (T(2) * in.lc - in.lo) + p.dt2 * lapc;
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+        const Axis<T> &A = p.ax[a];
+        if (A.M == 0) continue;
+        const int64_t ba = (int64_t)bi * p.bstride_aux[a] + g.cbase[a];
+        // G_a(p + q) from the neighbours' band slots ((p + q) is 0 off the band)
+        if (g.jm[a] <= A.M || g.jp[a] <= A.M) {
+            const T up_ = g.jp[a] <= A.M ? in.upp[a] + in.upq[a] : T(0);
+            const T dn_ = g.jm[a] <= A.M ? in.dnp[a] + in.dnq[a] : T(0);
+            v += (p.dt * (up_ - dn_)) * p.inv_2h;
+        }
+        if (g.jc[a] <= A.M) {
+            const int j = g.jc[a];
+            const int64_t c = ba + (int64_t)j * g.cstr[a];
+            const T s = A.sig[j];
+            const T sl = j > 0 ? A.sig[j - 1] : T(0);
+            if (j < A.M) {
+                const T pc = in.pc[a], pr = in.pr[a];
+                A.phi_o[c] = (pc - (p.half_dt * s) * (pc + pr)) - (p.k_damp * s) * in.ln[2 * a + 1];
+            }
+            if (j > 0) {
+                const T qc = in.qc[a], ql = in.ql[a];
+                A.psi_o[c] = (qc - (p.half_dt * sl) * (qc + ql)) + (p.k_damp * sl) * in.ln[2 * a];
+            }
+        }
+    }
+    p.lam_o[bo + g.idx] = v;
+    return (double)(p.dt2 * in.lc) * (double)lapu;
+}
+
+// The transposed step at cell (x, y, z) for the shots bi0, bi0 + bstep, ...:
+// their c^2-gradient terms summed in FP64 in shot order.
+template <typename T, int D>
+__device__ __forceinline__ double adj_cell(const AdjArgs<T> &p, int x, int y, int z, int bi0, int bstep)
+{
+    const AdjGeo<T> g = adj_geo<T, D>(p, x, y, z);
     double gsum = 0.0;
 #pragma unroll 1
     for (int bi = bi0; bi < p.batch; bi += bstep) {
-        const int64_t bo = (int64_t)bi * p.bstride;
-        const T *lam = p.lam + bo;
-        const T *un = p.un + bo;
-        const T lc = lam[idx];
-        T ln[6], uu[6];
-#pragma unroll
-        for (int k = 0; k < 6; ++k) {
-            ln[k] = (k < nnb) ? lam[nb[k]] : T(0);
-            uu[k] = (k < nnb) ? un[nb[k]] : T(0);
-        }
-        const T uc = un[idx];
-        const T clc = cc * lc;
-        T lapc = T(0), lapu = T(0);
-#pragma unroll
-        for (int k = 0; k < 6; k += 2) {
-            if (k < nnb) {
-                lapc += ((cn[k] * ln[k] - T(2) * clc) + cn[k + 1] * ln[k + 1]) * p.inv_h2;
-                lapu += ((uu[k] - T(2) * uc) + uu[k + 1]) * p.inv_h2;
-            }
-        }
-        T v = (T(2) * lc - p.lam_o[bo + idx]) + p.dt2 * lapc;
-#pragma unroll
-        for (int a = 0; a < D; ++a) {
-            const Axis<T> &A = p.ax[a];
-            if (A.M == 0) continue;
-            const int64_t ba = (int64_t)bi * p.bstride_aux[a];
-            // G_a(p + q) from the neighbours' band slots
-            if (jm[a] <= A.M || jp[a] <= A.M) {
-                // neighbours' compact bases: same line, slot differs
-                const T up_ = pq_at(A, jp[a], cbase[a], cstr[a], ba);
-                const T dn_ = pq_at(A, jm[a], cbase[a], cstr[a], ba);
-                v += (p.dt * (up_ - dn_)) * p.inv_2h;
-            }
-            if (jc[a] <= A.M) {
-                const int j = jc[a];
-                const int64_t c = ba + cbase[a] + (int64_t)j * cstr[a];
-                const T s = A.sig[j];
-                const T sl = j > 0 ? A.sig[j - 1] : T(0);
-                if (j < A.M) {
-                    const T pc = A.phi[c], pr = A.phi[c + cstr[a]];
-                    A.phi_o[c] = (pc - (p.half_dt * s) * (pc + pr)) - (p.k_damp * s) * ln[2 * a + 1];
-                }
-                if (j > 0) {
-                    const T qc = A.psi[c], ql = A.psi[c - cstr[a]];
-                    A.psi_o[c] = (qc - (p.half_dt * sl) * (qc + ql)) + (p.k_damp * sl) * ln[2 * a];
-                }
-            }
-        }
-        p.lam_o[bo + idx] = v;
-        gsum += (double)(p.dt2 * lc) * (double)lapu;
+        AdjIn<T> in;
+        adj_load<T, D>(p, g, bi, in);
+        gsum += adj_finish<T, D>(p, g, bi, in);
     }
     return gsum;
 }
@@ -2302,36 +2415,6 @@ __global__ void __launch_bounds__(256) k_adjoint_cell(AdjArgs<T> p)
     p.grad[((int64_t)z * p.ny + y) * p.nx + x] += g;
 }
 
-// The 2D frame of the adjoint (cells outside the marching core) over a list
-// of 64 x 4 tiles: a block takes one row of 64 cells of a tile, and its NG
-// waves split the shots (wave w takes shots w, w+NG, ...), so a frame cell's
-// shot loop is NG times shorter.  The NG FP64 partial gradients of a cell
-// are added in LDS in a fixed order (no atomics).
-template <typename T, int NG>
-__global__ void __launch_bounds__(64 * NG) k_adjoint_frame2d(AdjArgs<T> p)
-{
-    __shared__ double part[NG][64];
-    const int b = xcd_tile(blockIdx.x, gridDim.x);
-    const int t = b >> 2, row = b & 3;
-    const int lane = (int)(threadIdx.x & 63), w = (int)(threadIdx.x >> 6);
-    bool ok = t < p.ntiles;
-    int x = 0, y = 0;
-    if (ok) {
-        const TileRef tl = p.tiles[t];
-        x = tl.tx * 64 + lane;
-        y = tl.ty * 4 + row;
-        ok = x < p.nx && y < p.ny && !(x >= p.skip[0] && x < p.skip[1] && y >= p.skip[2] && y < p.skip[3]);
-    }
-    part[w][lane] = ok ? adj_cell<T, 2>(p, x, y, 0, w, NG) : 0.0;
-    __syncthreads();
-    if (ok && w == 0) {
-        double g = part[0][lane];
-#pragma unroll
-        for (int k = 1; k < NG; ++k) g += part[k][lane];
-        p.grad[(int64_t)y * p.nx + x] += g;
-    }
-}
-
 // Load / store through a base pointer plus a 32-bit byte offset: with a
 // wave-uniform base the hardware adds a scalar base to a vector offset, so a
 // run of loads from different rows shares one offset register.
@@ -2345,6 +2428,182 @@ template <typename T>
 __device__ __forceinline__ void st_off(T *base, uint32_t off, T v)
 {
     *reinterpret_cast<T *>(reinterpret_cast<char *>(base) + off) = v;
+}
+
+// A wave-uniform pointer taken through readfirstlane: a shot's array base
+// then sits in a scalar pair and the lanes' offsets are shared by all
+// shots, instead of the loop keeping a 64-bit per-lane address for every
+// access of every shot it has in flight (two vector registers each).
+template <typename T>
+__device__ __forceinline__ T *uniform_ptr(T *p)
+{
+    const uint64_t v = (uint64_t)p;
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)v);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(v >> 32));
+    return (T *)(((uint64_t)hi << 32) | lo);
+}
+
+// The 2D frame of the adjoint (cells outside the marching core) over a list
+// of 64 x 4 tiles: a block takes one row of 64 cells of a tile, and its NG
+// waves split the shots (wave w takes shots w, w+NG, ...), so a frame cell's
+// shot loop is NG times shorter; a wave issues the loads of SB of its shots
+// before the arithmetic of any.  Every access is a shot's array base (one
+// scalar pair per array) plus a 32-bit byte offset within the member that
+// all shots share, so a member's field and each axis's compact auxiliaries
+// must stay below 2^32 bytes (the host checks).  The expressions and their
+// order are those of adj_finish.  The NG FP64 partial gradients of a cell
+// (each summed in shot order) are added in LDS in a fixed order (no atomics).
+template <typename T, int NG, int SB>
+__global__ void __launch_bounds__(64 * NG) k_adjoint_frame2d(AdjArgs<T> p)
+{
+    __shared__ double part[NG][64];
+    const int b = xcd_tile(blockIdx.x, gridDim.x);
+    const int t = b >> 2, row = b & 3;
+    // the wave index is uniform across the wave: with it in a scalar register
+    // every shot's array bases are scalar too
+    const int lane = (int)(threadIdx.x & 63), w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int nx = p.nx, ny = p.ny;
+    bool ok = t < p.ntiles;
+    int x = 0, y = 0;
+    if (ok) {
+        const TileRef tl = p.tiles[t];
+        x = tl.tx * 64 + lane;
+        y = tl.ty * 4 + row;
+        ok = x < nx && y < ny && !(x >= p.skip[0] && x < p.skip[1] && y >= p.skip[2] && y < p.skip[3]);
+    }
+    double gsum = 0.0;
+    if (ok) {
+        constexpr uint32_t E = sizeof(T);
+        const int xm = wrap_dec(x, nx), xp = wrap_inc(x, nx), ym = wrap_dec(y, ny), yp = wrap_inc(y, ny);
+        const uint32_t oc = (uint32_t)(y * nx + x) * E, oxm = (uint32_t)(y * nx + xm) * E;
+        const uint32_t oxp = (uint32_t)(y * nx + xp) * E, oym = (uint32_t)(ym * nx + x) * E;
+        const uint32_t oyp = (uint32_t)(yp * nx + x) * E;
+        // c^2 at the cell and at x-1, x+1, y-1, y+1 (shared by the shots)
+        const T cc = p.c2 ? ld_off(p.c2, oc) : p.c2_const;
+        const T cn0 = p.c2 ? ld_off(p.c2, oxm) : p.c2_const;
+        const T cn1 = p.c2 ? ld_off(p.c2, oxp) : p.c2_const;
+        const T cn2 = p.c2 ? ld_off(p.c2, oym) : p.c2_const;
+        const T cn3 = p.c2 ? ld_off(p.c2, oyp) : p.c2_const;
+        const Axis<T> &AX = p.ax[0], &AY = p.ax[1];
+        const int MX = AX.M, MY = AY.M;
+        int jx = 1 << 30, jxm = 1 << 30, jxp = 1 << 30, jy = 1 << 30, jym = 1 << 30, jyp = 1 << 30;
+        if (MX > 0) {
+            jx = band_coord(AX, x);
+            jxm = band_coord(AX, xm);
+            jxp = band_coord(AX, xp);
+        }
+        if (MY > 0) {
+            jy = band_coord(AY, y);
+            jym = band_coord(AY, ym);
+            jyp = band_coord(AY, yp);
+        }
+        // offsets in the compact layouts: x band [y][MX+1], y band [MY+1][x]
+        const uint32_t xr = (uint32_t)(y * (MX + 1));
+        const uint32_t oxj = (xr + (uint32_t)jx) * E, oxjm = (xr + (uint32_t)jxm) * E, oxjp = (xr + (uint32_t)jxp) * E;
+        const uint32_t oyj = (uint32_t)(jy * nx + x) * E, oyjm = (uint32_t)(jym * nx + x) * E;
+        const uint32_t oyjp = (uint32_t)(jyp * nx + x) * E, orow = (uint32_t)nx * E;
+#pragma unroll 1
+        for (int b0 = w; b0 < p.batch; b0 += NG * SB) {
+            T lc[SB], uc[SB], lo[SB], ln[SB][4], uu[SB][4];
+            T xup[SB], xuq[SB], xdp[SB], xdq[SB], xpc[SB], xpr[SB], xqc[SB], xql[SB];
+            T yup[SB], yuq[SB], ydp[SB], ydq[SB], ypc[SB], ypr[SB], yqc[SB], yql[SB];
+#pragma unroll
+            for (int k = 0; k < SB; ++k) {
+                const int bi = b0 + k * NG;
+                if (bi >= p.batch) break;
+                const int64_t bo = (int64_t)bi * p.bstride;
+                const T *lam = uniform_ptr(p.lam + bo), *un = uniform_ptr(p.un + bo);
+                lc[k] = ld_off(lam, oc);
+                ln[k][0] = ld_off(lam, oxm);
+                ln[k][1] = ld_off(lam, oxp);
+                ln[k][2] = ld_off(lam, oym);
+                ln[k][3] = ld_off(lam, oyp);
+                uc[k] = ld_off(un, oc);
+                uu[k][0] = ld_off(un, oxm);
+                uu[k][1] = ld_off(un, oxp);
+                uu[k][2] = ld_off(un, oym);
+                uu[k][3] = ld_off(un, oyp);
+                lo[k] = ld_off(uniform_ptr((const T *)p.lam_o + bo), oc);
+                xup[k] = xuq[k] = xdp[k] = xdq[k] = xpc[k] = xpr[k] = xqc[k] = xql[k] = T(0);
+                yup[k] = yuq[k] = ydp[k] = ydq[k] = ypc[k] = ypr[k] = yqc[k] = yql[k] = T(0);
+                if (MX > 0) {
+                    const int64_t ba = (int64_t)bi * p.bstride_aux[0];
+                    const T *ph = uniform_ptr(AX.phi + ba), *ps = uniform_ptr(AX.psi + ba);
+                    if (jxp <= MX) { xup[k] = ld_off(ph, oxjp); xuq[k] = ld_off(ps, oxjp); }
+                    if (jxm <= MX) { xdp[k] = ld_off(ph, oxjm); xdq[k] = ld_off(ps, oxjm); }
+                    if (jx < MX) { xpc[k] = ld_off(ph, oxj); xpr[k] = ld_off(ph, oxj + E); }
+                    if (jx > 0 && jx <= MX) { xqc[k] = ld_off(ps, oxj); xql[k] = ld_off(ps, oxj - E); }
+                }
+                if (MY > 0) {
+                    const int64_t ba = (int64_t)bi * p.bstride_aux[1];
+                    const T *ph = uniform_ptr(AY.phi + ba), *ps = uniform_ptr(AY.psi + ba);
+                    if (jyp <= MY) { yup[k] = ld_off(ph, oyjp); yuq[k] = ld_off(ps, oyjp); }
+                    if (jym <= MY) { ydp[k] = ld_off(ph, oyjm); ydq[k] = ld_off(ps, oyjm); }
+                    if (jy < MY) { ypc[k] = ld_off(ph, oyj); ypr[k] = ld_off(ph, oyj + orow); }
+                    if (jy > 0 && jy <= MY) { yqc[k] = ld_off(ps, oyj); yql[k] = ld_off(ps, oyj - orow); }
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < SB; ++k) {
+                const int bi = b0 + k * NG;
+                if (bi >= p.batch) break;
+                const int64_t bo = (int64_t)bi * p.bstride;
+                const T clc = cc * lc[k];
+                T lapc = T(0), lapu = T(0);
+                lapc += ((cn0 * ln[k][0] - T(2) * clc) + cn1 * ln[k][1]) * p.inv_h2;
+                lapu += ((uu[k][0] - T(2) * uc[k]) + uu[k][1]) * p.inv_h2;
+                lapc += ((cn2 * ln[k][2] - T(2) * clc) + cn3 * ln[k][3]) * p.inv_h2;
+                lapu += ((uu[k][2] - T(2) * uc[k]) + uu[k][3]) * p.inv_h2;
+                T v = (T(2) * lc[k] - lo[k]) + p.dt2 * lapc;
+                if (MX > 0) {
+                    const int64_t ba = (int64_t)bi * p.bstride_aux[0];
+                    if (jxm <= MX || jxp <= MX) {
+                        const T up_ = jxp <= MX ? xup[k] + xuq[k] : T(0);
+                        const T dn_ = jxm <= MX ? xdp[k] + xdq[k] : T(0);
+                        v += (p.dt * (up_ - dn_)) * p.inv_2h;
+                    }
+                    if (jx <= MX) {
+                        const T s = AX.sig[jx];
+                        const T sl = jx > 0 ? AX.sig[jx - 1] : T(0);
+                        if (jx < MX)
+                            st_off(uniform_ptr(AX.phi_o + ba), oxj,
+                                   (xpc[k] - (p.half_dt * s) * (xpc[k] + xpr[k])) - (p.k_damp * s) * ln[k][1]);
+                        if (jx > 0)
+                            st_off(uniform_ptr(AX.psi_o + ba), oxj,
+                                   (xqc[k] - (p.half_dt * sl) * (xqc[k] + xql[k])) + (p.k_damp * sl) * ln[k][0]);
+                    }
+                }
+                if (MY > 0) {
+                    const int64_t ba = (int64_t)bi * p.bstride_aux[1];
+                    if (jym <= MY || jyp <= MY) {
+                        const T up_ = jyp <= MY ? yup[k] + yuq[k] : T(0);
+                        const T dn_ = jym <= MY ? ydp[k] + ydq[k] : T(0);
+                        v += (p.dt * (up_ - dn_)) * p.inv_2h;
+                    }
+                    if (jy <= MY) {
+                        const T s = AY.sig[jy];
+                        const T sl = jy > 0 ? AY.sig[jy - 1] : T(0);
+                        if (jy < MY)
+                            st_off(uniform_ptr(AY.phi_o + ba), oyj,
+                                   (ypc[k] - (p.half_dt * s) * (ypc[k] + ypr[k])) - (p.k_damp * s) * ln[k][3]);
+                        if (jy > 0)
+                            st_off(uniform_ptr(AY.psi_o + ba), oyj,
+                                   (yqc[k] - (p.half_dt * sl) * (yqc[k] + yql[k])) + (p.k_damp * sl) * ln[k][2]);
+                    }
+                }
+                st_off(uniform_ptr(p.lam_o + bo), oc, v);
+                gsum += (double)(p.dt2 * lc[k]) * (double)lapu;
+            }
+        }
+    }
+    part[w][lane] = gsum;
+    __syncthreads();
+    if (ok && w == 0) {
+        double g = part[0][lane];
+#pragma unroll
+        for (int k = 1; k < NG; ++k) g += part[k][lane];
+        p.grad[(int64_t)y * p.nx + x] += g;
+    }
 }
 
 // Marching form of the same transposed step on the core of a 2D periodic
