@@ -462,6 +462,18 @@ def bench_adjoint(steps: int, shots: int):
     e1.record()
     torch.cuda.synchronize()
     ms_plain = e0.elapsed_time(e1)
+    # the same forward in single steps (one thread per cell): the step every
+    # multi-step pass is measured against
+    sim.set_variant(dp.VARIANT_CELL, 4)
+    sim.set_state(torch.zeros(sim.shape, dtype=torch.float32, device="cuda"))
+    sim.sync()
+    e0, e1 = _events()
+    e0.record()
+    sim.step(steps)
+    e1.record()
+    torch.cuda.synchronize()
+    ms_single = e0.elapsed_time(e1)
+    sim.set_variant(choice["variant"], choice["tile_rows"])
     sim.set_state(torch.zeros(sim.shape, dtype=torch.float32, device="cuda"))
     sim.sync()
     e0, e1 = _events()
@@ -488,6 +500,8 @@ def bench_adjoint(steps: int, shots: int):
             "forward_ms": round(ms_fwd, 3), "forward_plain_ms": round(ms_plain, 3),
             "backward_ms": round(ms_bwd, 3),
             "adjoint_forward_ratio": round(ms_bwd / ms_fwd, 3),
+            "forward_single_step_ms": round(ms_single, 3),
+            "adjoint_single_step_ratio": round(ms_bwd / ms_single, 3),
             "forward_value": round(B * cells * steps / (ms_fwd * 1e-3) / 1e9, 3), "unit": "Gcell/s",
             "misfit": misfit, "grad_c2_max": gnorm, "grad_finite": finite,
             "launch": {"variant": choice["variant"], "tile_rows": choice["tile_rows"], "autotuned": True}}
