@@ -112,6 +112,9 @@ def time_gpu(w, dtype_name, steps, warmup, variant=0, tile_rows=0):
             "finite": ok, "launch": launch}
 
 
+VALU_PEAK_WPS = 256 * 2.4e9          # wave64 VALU instructions per second over 256 CUs
+
+
 def roofline_from_timing(kernels, timed_steps, workload=None, dtype_name=None):
     """Roofline of the dominant step kernel from the library's per-launch
     timing: its algorithmic bytes per launch over its mean launch duration.
@@ -121,7 +124,8 @@ def roofline_from_timing(kernels, timed_steps, workload=None, dtype_name=None):
     kernel carries the step.  With a committed counter summary for this
     workload, dtype and kernel class (and the current sources), ``traffic`` is
     the HBM bytes per launch it measured and ``hbm_GBps``/``hbm_frac`` that
-    traffic over the same mean duration."""
+    traffic over the same mean duration, and ``valu_frac`` its VALU wave
+    instructions per launch over the same duration against the issue peak."""
     name, k = max(((n, v) for n, v in kernels.items() if v["launches"]), key=lambda kv: kv[1]["bytes"])
     ms = k["ms"] / k["launches"]
     bpl = k["bytes"] / k["launches"]
@@ -131,12 +135,35 @@ def roofline_from_timing(kernels, timed_steps, workload=None, dtype_name=None):
            "alg_bytes_per_launch": int(round(bpl)), "kernel_ms_mean": round(ms, 5),
            "launches": k["launches"], "timed_steps": timed_steps}
     if workload:
-        t = traffic_from_profile(workload, dtype_name, name)
-        if t:
+        rec = traffic_from_profile(workload, dtype_name, name)
+        if rec and rec.get("bytes_per_launch"):
+            t = rec["bytes_per_launch"]
             out["traffic"] = int(t)
             out["hbm_GBps"] = round(t / (ms * 1e-3) / 1e9, 1)
             out["hbm_frac"] = round(t / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
+        if rec and rec.get("valu_wave_instr_per_launch"):
+            # VALU issue: one wave64 instruction per cycle per CU (non-packed, no FMA)
+            out["valu_frac"] = round(rec["valu_wave_instr_per_launch"] / (ms * 1e-3) / VALU_PEAK_WPS, 4)
     return out
+
+
+def path_hbm(roof, kernels, timed_steps, ms_per_step, workload, dtype_name):
+    """The whole path's HBM rate: the counter-measured bytes per launch of
+    every kernel class in the timing run, summed over its launches, over the
+    same number of steps at the measured time per step (classes run side by
+    side on two streams, so durations do not add).  Needs a current counter
+    record for every class."""
+    total = 0.0
+    for name, v in kernels.items():
+        if not v["launches"]:
+            continue
+        rec = traffic_from_profile(workload, dtype_name, name)
+        if not rec or not rec.get("bytes_per_launch"):
+            return
+        total += v["launches"] * rec["bytes_per_launch"]
+    gbps = total / (timed_steps * ms_per_step * 1e-3) / 1e9
+    roof["path_hbm_GBps"] = round(gbps, 1)
+    roof["path_hbm_frac"] = round(gbps / HBM_PEAK_GBS, 4)
 
 
 def cpu_baseline(w, sample_steps: int, U0=None):
@@ -171,8 +198,9 @@ def cpu_baseline(w, sample_steps: int, U0=None):
 
 
 def traffic_from_profile(workload: str, dtype_name: str, kernel: str):
-    """HBM bytes per launch of a step-kernel class measured by rocprofv3
-    counters, if a summary for this kernel source is committed under profiles/."""
+    """The counter record of a step-kernel class (HBM bytes and VALU wave
+    instructions per launch, measured by rocprofv3), if one for the current
+    kernel sources is committed under profiles/."""
     path = os.path.join(ROOT, "profiles", "traffic_%s_%s_%s.json" % (workload, dtype_name, kernel))
     if not os.path.exists(path):
         return None
@@ -185,7 +213,7 @@ def traffic_from_profile(workload: str, dtype_name: str, kernel: str):
             h.update(f.read())
     if h.hexdigest() != rec.get("sources_sha256"):
         return None                # the kernel changed since the counters were taken
-    return rec.get("bytes_per_launch")
+    return rec
 
 
 def copy_probe(mib: int = 1024, reps: int = 20):
@@ -270,6 +298,7 @@ def bench_ricker3d(steps: int, warmup: int, dtype_name: str = "f64", variant: in
     sim.set_timing(False)
     roof = roofline_from_timing(kernels, k, "ricker3d_512_m24", dtype_name)
     roof["path_alg_GBps"] = round(ab * steps / (ms * 1e-3) / 1e9, 1)
+    path_hbm(roof, kernels, k, ms / steps, "ricker3d_512_m24", dtype_name)
     sim.close()
     return {"dtype": dtype_name,
             "workload": "3D 512^3 interior + 24-cell layer on all six faces (560^3 cells), %s, c=1, dt=0.4h, "
@@ -517,6 +546,7 @@ def bench_2d(dn: str, steps: int, warmup: int, variant: int = 0, tile_rows: int 
     # the whole path: algorithmic bytes per step over the measured time per step
     # (kernels of a step may overlap on two streams, so this is not their sum)
     roof["path_alg_GBps"] = round(alg_bytes_per_step(w, 4 if dn == "f32" else 8) / (r["ms_per_step"] * 1e-3) / 1e9, 1)
+    path_hbm(roof, r["kernels"], r["timed_steps"], r["ms_per_step"], w.name, dn)
     return {"dtype": dn,
             "workload": "2D 4096^2 interior + 32-cell layer per side (4160^2 cells), 64 seeded Gaussians, "
                         "%s, c=1, dt=h/2, quadratic damping ramp to 2/h; %d of the workload's 2000 steps timed "
