@@ -373,6 +373,49 @@ def bench_walls(steps: int = 500):
             "launch": {"variant": choice["variant"], "tile_rows": choice["tile_rows"], "autotuned": True}}
 
 
+def bench_reflection(dn: str = "f64", checks=(64, 2000)):
+    """The paper's claim on the 2D 4096^2 + 32 workload (its 64 bumps with
+    the two cells next to each interface zeroed): the layered run in its
+    tuned launch against the plain wave equation on a 6144^2 periodic grid
+    with no layer (a margin of 1024 cells per side: no wave reaches its edge
+    in 2000 steps), both on the GPU; max |U - U_free| over the physical
+    domain, relative to the initial peak.  Before any wave can have crossed
+    the 64-cell band (64 steps) the difference is rounding; after the full
+    run it holds the residual the layer lets through."""
+    import torch
+    import paper_1804_01390_amd as dp
+    import synthetic
+    from paper_1804_01390_amd import autotune
+    td = torch.float64 if dn == "f64" else torch.float32
+    w = synthetic.bumps2d(n=4096, m=32, steps=max(checks), seed=0, margin=2)
+    n, m, Nf = w.n[0], w.lo[0], 6144
+    off = (Nf - n) // 2
+    peak = float(np.max(np.abs(w.U0)))
+    sim = dp.Simulation(w.n, w.lo, w.hi, w.h, w.dt, w.sigma, dtype=td)
+    sim.set_state(torch.from_numpy(w.U0))
+    choice = autotune.tune(sim)
+    sim.set_state(torch.from_numpy(w.U0))
+    U0f = np.zeros((Nf, Nf))
+    U0f[off:off + n, off:off + n] = w.U0[m:m + n, m:m + n]
+    free = dp.Simulation([Nf, Nf], [0, 0], [0, 0], w.h, w.dt, [None, None], dtype=td)
+    free.set_state(torch.from_numpy(U0f))
+    out, done = {}, 0
+    for t in checks:
+        sim.step(t - done)
+        free.step(t - done)
+        done = t
+        a = sim.U.double()[m:m + n, m:m + n]
+        b = free.U.double()[off:off + n, off:off + n]
+        out[str(t)] = float((a - b).abs().max().item()) / peak
+    sim.close()
+    free.close()
+    return {"workload": "2D 4096^2 + 32-cell layer (4160^2 cells), 64 seeded bumps zero on the two cells next to "
+                        "each interface, %s, tuned launch, against the plain wave equation on 6144^2 (no layer), "
+                        "both on the GPU" % dn.upper(),
+            "max_abs_diff_over_initial_peak": out,
+            "launch": {"variant": choice["variant"], "tile_rows": choice["tile_rows"], "autotuned": True}}
+
+
 def bench_small(steps: int = 500):
     """The 128^2 + 16-cell (160^2 cells) FP64 parity workload, 500 steps: a
     step is far shorter than a kernel launch, so it measures the step loop:
@@ -577,7 +620,7 @@ def main():
     ap.add_argument("--batch-count", type=int, default=256)
     ap.add_argument("--only", default="",
                     help="run a single section: ricker3d, ricker3d32, bumps2d, bumps2d64, batch, adjoint, "
-                         "small, rk4 or walls")
+                         "small, rk4, walls or reflection")
     args = ap.parse_args()
     if args.copy_probe:
         copy_probe()
@@ -594,7 +637,8 @@ def main():
               "bumps2d64": lambda: bench_2d("f64", args.steps, args.warmup, args.variant, args.tile_rows),
               "batch": lambda: bench_batch(args.batch_steps, args.batch_count),
               "adjoint": lambda: bench_adjoint(args.adjoint_steps, 32),
-              "small": bench_small, "rk4": bench_rk4, "walls": bench_walls}[args.only]
+              "small": bench_small, "rk4": bench_rk4, "walls": bench_walls,
+              "reflection": bench_reflection}[args.only]
         print(json.dumps({args.only: fn()}), flush=True)
         return
     import synthetic
@@ -644,6 +688,9 @@ def main():
         log("walls: 4160^2 FP32")
         out["walls"] = bench_walls()
         log("  %s" % out["walls"])
+        log("reflection: 4160^2 FP64 against 6144^2 free space")
+        out["reflection"] = bench_reflection()
+        log("  %s" % out["reflection"])
         log("adjoint: 32 shots x %d steps" % args.adjoint_steps)
         out["adjoint"] = bench_adjoint(args.adjoint_steps, 32)
         log("  %s" % out["adjoint"])

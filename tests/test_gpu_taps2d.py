@@ -45,10 +45,10 @@ def _setup(batch, c2field):
                 receivers=receivers, src_local=src_local, rec_local=rec_local, batch=batch)
 
 
-def _run(cfg, dtype, variant, tile_rows, timing=False):
+def _run(cfg, dtype, variant, tile_rows, timing=False, walls=()):
     td = torch.float64 if dtype == "f64" else torch.float32
     sim = dp.Simulation(cfg["n"], cfg["lo"], cfg["hi"], 1.0, cfg["dt"], cfg["sig"],
-                        c2=1.0 if cfg["c2"] is None else cfg["c2"], dtype=td, batch=cfg["batch"])
+                        c2=1.0 if cfg["c2"] is None else cfg["c2"], dtype=td, batch=cfg["batch"], walls=walls)
     sim.set_variant(variant, tile_rows)
     sim.set_state(torch.zeros(sim.shape, dtype=td, device="cuda"))
     sim.inject(cfg["sources"], torch.from_numpy(cfg["wav"]).to(td))
@@ -112,3 +112,18 @@ def test_source_outside_the_shrunk_core_takes_single_steps():
     assert np.array_equal(got_tr, ref_tr)
     for a, b in zip(got_f, ref_f):
         assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_passes_with_taps_inside_reflecting_walls(dtype):
+    """The same with both axes walled (each has a layer cell above the
+    interior, so the passes apply): bit for bit against single steps."""
+    cfg = _setup(2, True)
+    print("case taps2d walls %s" % dtype, flush=True)
+    ref_tr, ref_f, _ = _run(cfg, dtype, dp.VARIANT_CELL, 0, walls=(True, True))
+    for variant, tile_rows in ((dp.VARIANT_DEEP, 8 << 20), (dp.VARIANT_DEEP, (5 << 20) | (4 << 12) | 16)):
+        got_tr, got_f, t = _run(cfg, dtype, variant, tile_rows, timing=True, walls=(True, True))
+        assert t["pair"]["launches"] >= 7
+        assert np.array_equal(got_tr, ref_tr)
+        for a, b in zip(got_f, ref_f):
+            assert np.array_equal(a, b)
