@@ -103,9 +103,12 @@ extern "C" {
                                  launch over the layer-free core (waves of 64
                                  columns x 2 rows, tile_rows planes per tile) and
                                  one thread per cell over the layer slabs         */
-#define DPML_VARIANT_TWOSTEP 4 /* 2D runs without sources/receivers/planes (with
+#define DPML_VARIANT_TWOSTEP 4 /* 2D runs without a recorded plane (with
                                   reflecting walls when every walled axis has a
-                                  layer with a cell above the interior):
+                                  layer with a cell above the interior; with
+                                  point sources or receivers single steps:
+                                  FOURSTEP and DEEP take them inside their
+                                  passes):
                                   two steps per pass over the layer-free core
                                   (temporal blocking: each wave marches down a
                                   strip keeping U^n and U^{n+1} rows in registers,
@@ -160,7 +163,16 @@ extern "C" {
                                   and frame form 15 in bits 16-19 (any multi-step
                                   variant) takes all the frame's steps of a pass
                                   in one launch over tiles held in LDS with a
-                                  halo of D cells.  3D: as TWOSTEP                */
+                                  halo of D cells.  With point sources or
+                                  receivers (2D): passes of 4 .. 8 levels when
+                                  at most 32 sources are registered, each at
+                                  least D-1 cells inside the core, no two
+                                  receivers share a cell and the frame is not
+                                  fused; the core adds the sources at every
+                                  level it forms and records the receivers at
+                                  least D-l cells inside it at level l, the
+                                  frame's steps the rest; otherwise shallower
+                                  passes or single steps.  3D: as TWOSTEP        */
 
 typedef struct dpml_grid {
     int32_t ndim;    /* 2 or 3 */
@@ -310,7 +322,10 @@ int dpml_put_state(dpml_t *h, const void *blob, int64_t n);
 
 /* Bytes of caller-owned device memory the checkpointed forward + adjoint of
  * nsteps steps needs (checkpoints, one segment of recomputed levels, the
- * adjoint state).  0 on invalid arguments. */
+ * adjoint state).  0 on invalid arguments.  The adjoint recomputes each
+ * segment with the handle's variant (2D multi-step passes keep every level
+ * they form, writing it straight into the segment's history), so results
+ * do not depend on the variant. */
 size_t dpml_adjoint_workspace_bytes(const dpml_t *h, int64_t nsteps, int64_t ckpt_every);
 
 /* Run nsteps steps from time index 0 (after dpml_set_state) exactly as
