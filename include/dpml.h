@@ -321,8 +321,9 @@ int dpml_put_state(dpml_t *h, const void *blob, int64_t n);
  * checkpoints taken every ckpt_every steps (sqrt(T) checkpointing). */
 
 /* Bytes of caller-owned device memory the checkpointed forward + adjoint of
- * nsteps steps needs (checkpoints, one segment of recomputed levels, the
- * adjoint state).  0 on invalid arguments.  The adjoint recomputes each
+ * nsteps steps needs (checkpoints, two segments of recomputed levels -- the
+ * next segment is recomputed on streams of the library's own while the
+ * current one is swept -- and the adjoint state).  0 on invalid arguments.  The adjoint recomputes each
  * segment with the handle's variant (2D multi-step passes keep every level
  * they form, writing it straight into the segment's history), so results
  * do not depend on the variant. */

@@ -1151,6 +1151,11 @@ void dpml_destroy(dpml_t *H)
     if (H->ev_fork) (void)hipEventDestroy(H->ev_fork);
     if (H->ev_join) (void)hipEventDestroy(H->ev_join);
     if (H->side) (void)hipStreamDestroy(H->side);
+    for (hipEvent_t e : {H->adj_rfork, H->adj_rjoin, H->adj_rec_done[0], H->adj_rec_done[1], H->adj_sweep_done[0],
+                         H->adj_sweep_done[1]})
+        if (e) (void)hipEventDestroy(e);
+    if (H->adj_rside) (void)hipStreamDestroy(H->adj_rside);
+    if (H->adj_rs) (void)hipStreamDestroy(H->adj_rs);
     if (H->d_adj_frame) (void)hipFree(H->d_adj_frame);
     free_taps(H);
     if (H->d_rec_sorted) (void)hipFree(H->d_rec_sorted);
@@ -1186,7 +1191,7 @@ namespace {
 
 struct AdjLayout {
     int64_t nck = 0;
-    size_t state = 0, off_ckpt = 0, level = 0, off_hist = 0;
+    size_t state = 0, off_ckpt = 0, level = 0, off_hist[2] = {0, 0};
     size_t off_lam[2] = {0, 0};
     size_t off_p[3][2] = {{0, 0}, {0, 0}, {0, 0}};
     size_t off_q[3][2] = {{0, 0}, {0, 0}, {0, 0}};
@@ -1202,7 +1207,9 @@ AdjLayout adj_layout(const dpml *H, int64_t nsteps, int64_t every)
     A.level = align_up((size_t)(L.ncell * L.batch) * L.esize);
     size_t off = 0;
     A.off_ckpt = off; off += (size_t)A.nck * A.state;
-    A.off_hist = off; off += (size_t)every * A.level;
+    // two segments' histories: the next segment's recompute fills one while
+    // the reverse sweep reads the other
+    for (int k = 0; k < 2; ++k) { A.off_hist[k] = off; off += (size_t)every * A.level; }
     for (int k = 0; k < 2; ++k) { A.off_lam[k] = off; off += A.level; }
     for (int a = 0; a < L.ndim; ++a) {
         if (L.M[a] == 0) continue;
@@ -1286,6 +1293,12 @@ int adjoint_impl(dpml *H, const void *resid, double *grad, void *grad_w)
     const AdjLayout A = adj_layout(H, nsteps, every);
     char *ws = H->adj_ws;
     const size_t lb = (size_t)(L.ncell * L.batch) * sizeof(T);
+    // the recompute's streams and the events that order it against the sweep
+    if (!H->adj_rs) HIP_TRY(H, hipStreamCreateWithFlags(&H->adj_rs, hipStreamNonBlocking));
+    if (!H->adj_rside) HIP_TRY(H, hipStreamCreateWithFlags(&H->adj_rside, hipStreamNonBlocking));
+    for (hipEvent_t *e : {&H->adj_rfork, &H->adj_rjoin, &H->adj_rec_done[0], &H->adj_rec_done[1],
+                          &H->adj_sweep_done[0], &H->adj_sweep_done[1]})
+        if (!*e) HIP_TRY(H, hipEventCreateWithFlags(e, hipEventDisableTiming));
     for (int k = 0; k < 2; ++k) HIP_TRY(H, hipMemsetAsync(ws + A.off_lam[k], 0, lb, H->stream));
     for (int a = 0; a < L.ndim; ++a) {
         if (L.M[a] == 0) continue;
@@ -1325,9 +1338,19 @@ int adjoint_impl(dpml *H, const void *resid, double *grad, void *grad_w)
     }
     const dim3 mgrid((unsigned)round8((adj_waves + 3) / 4));
     const dim3 fgrid((unsigned)round8(4 * (int)std::max<int64_t>(H->n_adj_frame, 0)));   // a block per tile row
-    for (int64_t seg = A.nck - 1; seg >= 0; --seg) {
+    // The recompute of a segment: restore its checkpoint and recompute U^{t0}
+    // .. U^{t1-1} into the segment's history buffer (seg & 1).  U^{t0} goes to
+    // slot 0; each recomputed level is then written straight into its slot:
+    // the multi-step passes keep every level they form (the levels the
+    // handle's variant takes, 2 or 4 and more), the rest single steps reading
+    // the two previous slots.  It runs on the recompute's own streams, so the
+    // next segment's recompute overlaps the current segment's reverse sweep;
+    // the sweep of a segment waits for its recompute, and a recompute waits
+    // for the sweep that last read its history buffer.
+    const int64_t hstride = (int64_t)(A.level / sizeof(T));
+    auto recompute_body = [&](int64_t seg) -> int {
         const int64_t t0 = seg * every, t1 = std::min(t0 + every, nsteps);
-        // restore the checkpoint and recompute U^{t0} .. U^{t1-1} into the history
+        char *hist = ws + A.off_hist[seg & 1];
         H->state_set = true;
         H->cur = 0;
         H->u_now = H->at(L.off_u[0]);
@@ -1335,15 +1358,10 @@ int adjoint_impl(dpml *H, const void *resid, double *grad, void *grad_w)
         int rc = copy_state(H, ws + A.off_ckpt + (size_t)seg * A.state, false);
         if (rc) return rc;
         H->n = t0;
-        // U^{t0} goes to history slot 0; each recomputed level is then written
-        // straight into its slot: the multi-step passes keep every level they
-        // form (the levels the handle's variant takes, 2 or 4 and more), the
-        // rest single steps reading the two previous slots
-        HIP_TRY(H, hipMemcpyAsync(ws + A.off_hist, H->u_now, lb, hipMemcpyDeviceToDevice, H->stream));
-        H->u_now = ws + A.off_hist;
-        const int64_t hstride = (int64_t)(A.level / sizeof(T));
+        HIP_TRY(H, hipMemcpyAsync(hist, H->u_now, lb, hipMemcpyDeviceToDevice, H->stream));
+        H->u_now = hist;
         for (int64_t k = t0; k + 1 < t1;) {
-            T *slot = (T *)(ws + A.off_hist + (size_t)(k - t0 + 1) * A.level);
+            T *slot = (T *)(hist + (size_t)(k - t0 + 1) * A.level);
             int lv = L.ndim == 2 ? multistep_levels(H, t1 - 1 - k) : 1;
             if (lv == 3) lv = 2;
             if (lv >= 2 && frame_fused(H)) lv = 1;
@@ -1367,6 +1385,41 @@ int adjoint_impl(dpml *H, const void *resid, double *grad, void *grad_w)
             H->cur = 1 - H->cur;
             H->n += 1;
             ++k;
+        }
+        HIP_TRY(H, hipEventRecord(H->adj_rec_done[seg & 1], H->stream));
+        return DPML_OK;
+    };
+    // enqueue a recompute with the recompute's streams and events standing in
+    // for the handle's own (every launch path takes those four)
+    auto recompute = [&](int64_t seg) -> int {
+        std::swap(H->stream, H->adj_rs);
+        std::swap(H->side, H->adj_rside);
+        std::swap(H->ev_fork, H->adj_rfork);
+        std::swap(H->ev_join, H->adj_rjoin);
+        const int rc = recompute_body(seg);
+        std::swap(H->stream, H->adj_rs);
+        std::swap(H->side, H->adj_rside);
+        std::swap(H->ev_fork, H->adj_rfork);
+        std::swap(H->ev_join, H->adj_rjoin);
+        return rc;
+    };
+    {
+        // the recompute stream starts after everything enqueued before this call
+        HIP_TRY(H, hipEventRecord(H->adj_sweep_done[0], H->stream));
+        HIP_TRY(H, hipStreamWaitEvent(H->adj_rs, H->adj_sweep_done[0], 0));
+        const int rc = recompute(A.nck - 1);
+        if (rc) return rc;
+    }
+    for (int64_t seg = A.nck - 1; seg >= 0; --seg) {
+        const int64_t t0 = seg * every, t1 = std::min(t0 + every, nsteps);
+        const char *hist = ws + A.off_hist[seg & 1];
+        HIP_TRY(H, hipStreamWaitEvent(H->stream, H->adj_rec_done[seg & 1], 0));
+        if (seg > 0) {
+            // the previous segment's recompute refills the buffer the sweep of
+            // segment seg + 1 read
+            if (seg + 1 < A.nck) HIP_TRY(H, hipStreamWaitEvent(H->adj_rs, H->adj_sweep_done[(seg + 1) & 1], 0));
+            const int rc = recompute(seg - 1);
+            if (rc) return rc;
         }
         // reverse sweep over the segment
         for (int64_t n = t1 - 1; n >= t0; --n) {
@@ -1399,7 +1452,7 @@ int adjoint_impl(dpml *H, const void *resid, double *grad, void *grad_w)
             }
             q.lam = lam;
             q.lam_o = lam_o;
-            q.un = (const T *)(ws + A.off_hist + (size_t)(n - t0) * A.level);
+            q.un = (const T *)(hist + (size_t)(n - t0) * A.level);
             q.c2 = H->c2_field ? (const T *)H->at(L.off_c2) : nullptr;
             q.grad = grad;
             q.c2_const = (T)H->c2_const;
@@ -1449,17 +1502,18 @@ int adjoint_impl(dpml *H, const void *resid, double *grad, void *grad_w)
             lcur = 1 - lcur;
             acur = 1 - acur;
         }
+        HIP_TRY(H, hipEventRecord(H->adj_sweep_done[seg & 1], H->stream));
     }
-    // start: lam[1 - lcur] holds a^1, the history slot 0 holds U^0
+    // start: lam[1 - lcur] holds a^1, slot 0 of segment 0's history U^0
     const T half_dt2 = (T)(0.5 * H->dt * H->dt);
     const T inv_h2 = (T)(1.0 / (H->h * H->h));
     if (L.ndim == 2)
         hipLaunchKernelGGL((dpmlk::k_adjoint_start<T, 2>), grid, block, 0, H->stream,
-                           (const T *)(ws + A.off_lam[1 - lcur]), (const T *)(ws + A.off_hist), grad, half_dt2,
+                           (const T *)(ws + A.off_lam[1 - lcur]), (const T *)(ws + A.off_hist[0]), grad, half_dt2,
                            inv_h2, (int)L.N[0], (int)L.N[1], (int)L.N[2], (int)L.batch, (int64_t)L.ncell);
     else
         hipLaunchKernelGGL((dpmlk::k_adjoint_start<T, 3>), grid, block, 0, H->stream,
-                           (const T *)(ws + A.off_lam[1 - lcur]), (const T *)(ws + A.off_hist), grad, half_dt2,
+                           (const T *)(ws + A.off_lam[1 - lcur]), (const T *)(ws + A.off_hist[0]), grad, half_dt2,
                            inv_h2, (int)L.N[0], (int)L.N[1], (int)L.N[2], (int)L.batch, (int64_t)L.ncell);
     HIP_TRY(H, hipGetLastError());
     H->recording = true;

@@ -167,6 +167,12 @@ struct dpml {
     // the frame's steps run on a second stream beside the core kernel
     hipStream_t side = nullptr;
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+    // the adjoint's recompute beside its reverse sweep: a stream pair and
+    // fork/join events of its own, and per history buffer the events that
+    // order the two (recompute done, sweep done)
+    hipStream_t adj_rs = nullptr, adj_rside = nullptr;
+    hipEvent_t adj_rfork = nullptr, adj_rjoin = nullptr;
+    hipEvent_t adj_rec_done[2] = {nullptr, nullptr}, adj_sweep_done[2] = {nullptr, nullptr};
     dpmlk::TileRef *d_adj_frame = nullptr;  // 2D adjoint: tiles outside the marching core
     int64_t n_adj_frame = -1;               // -1: not built yet
     // sources
