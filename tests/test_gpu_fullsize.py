@@ -151,6 +151,47 @@ def test_ricker3d_full_size_sampled_steps():
     sim.close()
 
 
+def test_ricker3d_full_size_fp64_headline_launch():
+    """The benchmark's headline workload as the benchmark runs it: 560^3
+    cells, FP64, the Ricker source at the centre, the z plane through it
+    recorded, the tuned launch (two-step passes with the source added inside
+    the core).  After 25 steps from rest (twelve passes and one single step)
+    every cell of U, U^{n-1}, Phi and Psi is compared with the oracle's run of
+    the same 25 steps, and the recorded plane after steps 8, 16 and 24 with
+    the oracle's field on that plane."""
+    from paper_1804_01390_amd import autotune
+    w = synthetic.ricker3d(n=512, m=24, steps=1000)
+    zeros = lambda: torch.zeros(tuple(reversed(w.N)), dtype=torch.float64, device="cuda")
+    sim = dp.Simulation(w.n, w.lo, w.hi, w.h, w.dt, w.sigma, dtype=torch.float64)
+    sim.set_state(zeros())
+    sim.inject(w.sources, torch.from_numpy(w.wavelets))
+    axis, index = w.plane
+    planes = sim.record_plane(axis, index, w.steps)
+    choice = autotune.tune(sim, steps=10)
+    _log("launch variant=%d tile_rows=0x%x" % (choice["variant"], choice["tile_rows"]))
+    sim.set_state(zeros())
+    sim.step(25)
+    gs = gpu_state(sim)
+    pl = sim._keep["planes"].cpu().numpy()
+    sim.close()
+    g = oracle.Grid(w.N, w.h, w.dt, w.sigma)
+    s = oracle.start(g, np.zeros(tuple(reversed(w.N))))
+    nt = w.wavelets.shape[1]
+    done = 0
+    for t in (8, 16, 24, 25):
+        s, _ = oracle.run(g, s, t - done, sources=w.sources, wavelets=w.wavelets, nt=nt)
+        done = t
+        _log("oracle at step %d" % t)
+        if t < 25:
+            err = rel_err(pl[t - 1], s.U[index])
+            _log("plane after step %d: error / peak %.2e" % (t, err))
+            assert err <= 1e-12
+    errs = compare_states(gs, s, w.n, w.lo, w.hi)
+    _log("errors: %s" % {k: "%.2e" % v for k, v in errs.items()})
+    for k, v in errs.items():
+        assert v <= 1e-12, (k, v)
+
+
 def test_batch_full_size_sampled_problems():
     """The 256-problem batch in the benchmark's launch (tuned scheme and shape,
     graph launch): the three smallest problems run all 1500 steps against the
