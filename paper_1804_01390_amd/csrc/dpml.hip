@@ -302,7 +302,9 @@ int ensure_multistep(dpml *H, int levels)
 // how deep they lie in the core (min distance to its edges; negative
 // outside), with the frame's share at level l = those less than levels-l
 // deep (the core records the rest).
-int ensure_taps(dpml *H, int levels, const int r[4])
+// Per (member, row) index into a pool of per-row column maps of the
+// registered receivers (receiver index or -1).
+int ensure_rmap(dpml *H)
 {
     const Layout &L = H->L;
     const int NX = (int)L.N[0], NY = (int)L.N[1];
@@ -323,6 +325,15 @@ int ensure_taps(dpml *H, int levels, const int r[4])
         if (!pool.empty())
             HIP_TRY(H, hipMemcpy(H->d_rpool, pool.data(), pool.size() * sizeof(int32_t), hipMemcpyHostToDevice));
     }
+    return DPML_OK;
+}
+
+int ensure_taps(dpml *H, int levels, const int r[4])
+{
+    const Layout &L = H->L;
+    const int NX = (int)L.N[0];
+    int rc = ensure_rmap(H);
+    if (rc) return rc;
     const int q = levels - 2;
     if (!H->d_frec_cells[q]) {
         const int64_t nr = (int64_t)H->rec_host.size();
@@ -360,6 +371,11 @@ void free_taps(dpml *H)
     if (H->d_rmap) (void)hipFree(H->d_rmap);
     if (H->d_rpool) (void)hipFree(H->d_rpool);
     H->d_rmap = H->d_rpool = nullptr;
+    if (H->d_adj_frec_cells) (void)hipFree(H->d_adj_frec_cells);
+    if (H->d_adj_frec_order) (void)hipFree(H->d_adj_frec_order);
+    H->d_adj_frec_cells = nullptr;
+    H->d_adj_frec_order = nullptr;
+    H->n_adj_frec = -1;
     for (int q = 0; q < kMaxLevels - 1; ++q) {
         if (H->d_frec_cells[q]) (void)hipFree(H->d_frec_cells[q]);
         if (H->d_frec_idx[q]) (void)hipFree(H->d_frec_idx[q]);
@@ -1157,6 +1173,8 @@ void dpml_destroy(dpml_t *H)
     if (H->adj_rside) (void)hipStreamDestroy(H->adj_rside);
     if (H->adj_rs) (void)hipStreamDestroy(H->adj_rs);
     if (H->d_adj_frame) (void)hipFree(H->d_adj_frame);
+    for (int k = 0; k < 2; ++k)
+        if (H->d_adj_frame_s[k]) (void)hipFree(H->d_adj_frame_s[k]);
     free_taps(H);
     if (H->d_rec_sorted) (void)hipFree(H->d_rec_sorted);
     if (H->d_rec_order) (void)hipFree(H->d_rec_order);
@@ -1192,7 +1210,7 @@ namespace {
 struct AdjLayout {
     int64_t nck = 0;
     size_t state = 0, off_ckpt = 0, level = 0, off_hist[2] = {0, 0};
-    size_t off_lam[2] = {0, 0};
+    size_t off_lam[4] = {0, 0, 0, 0};
     size_t off_p[3][2] = {{0, 0}, {0, 0}, {0, 0}};
     size_t off_q[3][2] = {{0, 0}, {0, 0}, {0, 0}};
     size_t total = 0;
@@ -1210,7 +1228,7 @@ AdjLayout adj_layout(const dpml *H, int64_t nsteps, int64_t every)
     // two segments' histories: the next segment's recompute fills one while
     // the reverse sweep reads the other
     for (int k = 0; k < 2; ++k) { A.off_hist[k] = off; off += (size_t)every * A.level; }
-    for (int k = 0; k < 2; ++k) { A.off_lam[k] = off; off += A.level; }
+    for (int k = 0; k < 4; ++k) { A.off_lam[k] = off; off += A.level; }
     for (int a = 0; a < L.ndim; ++a) {
         if (L.M[a] == 0) continue;
         const size_t ab = align_up((size_t)(L.aux_elems[a] * L.batch) * L.esize);
@@ -1263,13 +1281,29 @@ void adj_core(const Layout &L, int r[4])
     }
 }
 
-// 64 x 4 tiles holding any cell outside the adjoint core.
-int ensure_adj_frame(dpml *H)
+// The adjoint core shrunk by s cells on every axis with a layer (an axis
+// without one stays whole: it has no frame).
+void adj_core_shrunk(const Layout &L, int s, int r[4])
 {
-    if (H->n_adj_frame >= 0) return DPML_OK;
+    adj_core(L, r);
+    for (int a = 0; a < 2; ++a) {
+        if (L.M[a] == 0) continue;
+        r[2 * a] += s;
+        r[2 * a + 1] = std::max(r[2 * a], r[2 * a + 1] - s);
+    }
+}
+
+// 64 x 4 tiles holding any cell outside the adjoint core shrunk by s (0, 1
+// or 2): the frame of a single step, and of the two steps of a two-level
+// pass.
+int ensure_adj_frame(dpml *H, int s = 0)
+{
+    dpmlk::TileRef **dst = s == 0 ? &H->d_adj_frame : &H->d_adj_frame_s[s - 1];
+    int64_t *cnt = s == 0 ? &H->n_adj_frame : &H->n_adj_frame_s[s - 1];
+    if (*cnt >= 0) return DPML_OK;
     const Layout &L = H->L;
     int r[4];
-    adj_core(L, r);
+    adj_core_shrunk(L, s, r);
     std::vector<dpmlk::TileRef> t;
     const int tx = (int)((L.N[0] + 63) / 64), ty = (int)((L.N[1] + 3) / 4);
     for (int y = 0; y < ty; ++y)
@@ -1278,10 +1312,38 @@ int ensure_adj_frame(dpml *H)
             const int ya = y * 4, yb = std::min<int>(ya + 4, (int)L.N[1]);
             if (!(xa >= r[0] && xb <= r[1] && ya >= r[2] && yb <= r[3])) t.push_back({0, x, y, 0});
         }
-    H->n_adj_frame = (int64_t)t.size();
+    *cnt = (int64_t)t.size();
     if (t.empty()) return DPML_OK;
-    HIP_TRY(H, hipMalloc((void **)&H->d_adj_frame, t.size() * sizeof(dpmlk::TileRef)));
-    HIP_TRY(H, hipMemcpy(H->d_adj_frame, t.data(), t.size() * sizeof(dpmlk::TileRef), hipMemcpyHostToDevice));
+    HIP_TRY(H, hipMalloc((void **)dst, t.size() * sizeof(dpmlk::TileRef)));
+    HIP_TRY(H, hipMemcpy(*dst, t.data(), t.size() * sizeof(dpmlk::TileRef), hipMemcpyHostToDevice));
+    return DPML_OK;
+}
+
+// The receivers outside rectangle S (the cells whose a^n the frame's first
+// step of a two-level pass writes), sorted by cell, with their indices.
+int ensure_adj_frec(dpml *H, const int S[4])
+{
+    if (H->n_adj_frec >= 0) return DPML_OK;
+    const Layout &L = H->L;
+    const int NX = (int)L.N[0];
+    std::vector<std::pair<int64_t, int64_t>> v;
+    for (int64_t i = 0; i < (int64_t)H->rec_host.size(); ++i) {
+        const int64_t c = H->rec_host[i] % L.ncell;
+        const int x = (int)(c % NX), y = (int)(c / NX);
+        if (!(x >= S[0] && x < S[1] && y >= S[2] && y < S[3])) v.push_back({H->rec_host[i], i});
+    }
+    std::sort(v.begin(), v.end());
+    H->n_adj_frec = (int64_t)v.size();
+    if (v.empty()) return DPML_OK;
+    std::vector<int64_t> cells(v.size()), order(v.size());
+    for (size_t k = 0; k < v.size(); ++k) {
+        cells[k] = v[k].first;
+        order[k] = v[k].second;
+    }
+    HIP_TRY(H, hipMalloc((void **)&H->d_adj_frec_cells, v.size() * sizeof(int64_t)));
+    HIP_TRY(H, hipMalloc((void **)&H->d_adj_frec_order, v.size() * sizeof(int64_t)));
+    HIP_TRY(H, hipMemcpy(H->d_adj_frec_cells, cells.data(), v.size() * sizeof(int64_t), hipMemcpyHostToDevice));
+    HIP_TRY(H, hipMemcpy(H->d_adj_frec_order, order.data(), v.size() * sizeof(int64_t), hipMemcpyHostToDevice));
     return DPML_OK;
 }
 
@@ -1299,7 +1361,7 @@ int adjoint_impl(dpml *H, const void *resid, double *grad, void *grad_w)
     for (hipEvent_t *e : {&H->adj_rfork, &H->adj_rjoin, &H->adj_rec_done[0], &H->adj_rec_done[1],
                           &H->adj_sweep_done[0], &H->adj_sweep_done[1]})
         if (!*e) HIP_TRY(H, hipEventCreateWithFlags(e, hipEventDisableTiming));
-    for (int k = 0; k < 2; ++k) HIP_TRY(H, hipMemsetAsync(ws + A.off_lam[k], 0, lb, H->stream));
+    for (int k = 0; k < 4; ++k) HIP_TRY(H, hipMemsetAsync(ws + A.off_lam[k], 0, lb, H->stream));
     for (int a = 0; a < L.ndim; ++a) {
         if (L.M[a] == 0) continue;
         const size_t ab = (size_t)(L.aux_elems[a] * L.batch) * sizeof(T);
@@ -1308,8 +1370,8 @@ int adjoint_impl(dpml *H, const void *resid, double *grad, void *grad_w)
             HIP_TRY(H, hipMemsetAsync(ws + A.off_q[a][k], 0, ab, H->stream));
         }
     }
-    int lcur = 0;     // lam[lcur] = a^{n+1}, lam[1-lcur] = a^{n+2}
-    int acur = 0;     // p/q[acur] = adjoint auxiliaries at level n+1
+    int il = 0, io = 1;   // lam[il] = a^{n+1}, lam[io] = a^{n+2}; the other two take a two-level pass's output
+    int acur = 0;         // p/q[acur] = adjoint auxiliaries at level n+1
     double hd = 1;
     for (int a = 0; a < L.ndim; ++a) hd *= H->h;
     const T wamp = (T)(H->dt * H->dt / hd);
@@ -1336,8 +1398,28 @@ int adjoint_impl(dpml *H, const void *resid, double *grad, void *grad_w)
         adj_tiles_x = (core[1] - core[0] + 63) / 64;
         adj_waves = adj_tiles_x * ((core[3] - core[2] + kAdjRows - 1) / kAdjRows);
     }
+    // two-level passes (2D): a core r = the adjoint core shrunk by one, a^n
+    // stored on r shrunk by one (core2s), the frame's two steps outside those;
+    // receivers on distinct cells (the core adds the residual of the second
+    // step in registers)
+    int core2[4] = {0, 0, 0, 0}, core2s[4] = {0, 0, 0, 0};
+    int tiles2_x = 0, waves2 = 0;
+    bool two_ok = false;
+    if (march2d) {
+        adj_core_shrunk(L, 1, core2);
+        adj_core_shrunk(L, 2, core2s);
+        if (core2[1] > core2[0] && core2[3] > core2[2] && !(H->nr > 0 && H->rec_dups)) {
+            int rc = ensure_adj_frame(H, 1);
+            if (!rc) rc = ensure_adj_frame(H, 2);
+            if (!rc && H->nr > 0) rc = ensure_rmap(H);
+            if (!rc && H->nr > 0) rc = ensure_adj_frec(H, core2s);
+            if (rc) return rc;
+            tiles2_x = (core2[1] - core2[0] + 61) / 62;
+            waves2 = tiles2_x * ((core2[3] - core2[2] + kAdjRows - 1) / kAdjRows);
+            two_ok = true;
+        }
+    }
     const dim3 mgrid((unsigned)round8((adj_waves + 3) / 4));
-    const dim3 fgrid((unsigned)round8(4 * (int)std::max<int64_t>(H->n_adj_frame, 0)));   // a block per tile row
     // The recompute of a segment: restore its checkpoint and recompute U^{t0}
     // .. U^{t1-1} into the segment's history buffer (seg & 1).  U^{t0} goes to
     // slot 0; each recomputed level is then written straight into its slot:
@@ -1422,36 +1504,20 @@ int adjoint_impl(dpml *H, const void *resid, double *grad, void *grad_w)
             if (rc) return rc;
         }
         // reverse sweep over the segment
-        for (int64_t n = t1 - 1; n >= t0; --n) {
-            T *lam = (T *)(ws + A.off_lam[lcur]);
-            T *lam_o = (T *)(ws + A.off_lam[1 - lcur]);
-            if (H->nr > 0 && n < H->nt_rec) {
-                dim3 g2((unsigned)((H->nr + 255) / 256)), b2(256);
-                hipLaunchKernelGGL((dpmlk::k_inject<T>), g2, b2, 0, H->stream, lam, H->d_rec_sorted,
-                                   H->d_rec_order, (const T *)resid, H->nr, H->nt_rec, n, (T)1);
-            }
-            // dJ/dw from a^{n+1} (nothing writes a^{n+1} during this level: the 2D
-            // path gathers it on the side stream beside the core)
-            auto gather = [&](hipStream_t st) {
-                if (H->ns > 0 && n < H->nt_src && grad_w) {
-                    dim3 g2((unsigned)((H->ns + 255) / 256)), b2(256);
-                    hipLaunchKernelGGL((dpmlk::k_gather_scaled<T>), g2, b2, 0, st, (const T *)lam, H->d_src_cells,
-                                       H->d_src_order, (T *)grad_w, H->ns, H->nt_src, n, wamp);
-                }
-            };
+        auto lamb = [&](int k) { return (T *)(ws + A.off_lam[k]); };
+        // arguments of the transposed step n (adjoint auxiliaries at n+1 in p/q[ai])
+        auto base = [&](int64_t n, int ai) {
             dpmlk::AdjArgs<T> q{};
             for (int a = 0; a < 3; ++a) {
                 q.ax[a] = make_axis<T>(H, a, false);
                 if (a < L.ndim && L.M[a] > 0) {
-                    q.ax[a].phi = (const T *)(ws + A.off_p[a][acur]);
-                    q.ax[a].psi = (const T *)(ws + A.off_q[a][acur]);
-                    q.ax[a].phi_o = (T *)(ws + A.off_p[a][1 - acur]);
-                    q.ax[a].psi_o = (T *)(ws + A.off_q[a][1 - acur]);
+                    q.ax[a].phi = (const T *)(ws + A.off_p[a][ai]);
+                    q.ax[a].psi = (const T *)(ws + A.off_q[a][ai]);
+                    q.ax[a].phi_o = (T *)(ws + A.off_p[a][1 - ai]);
+                    q.ax[a].psi_o = (T *)(ws + A.off_q[a][1 - ai]);
                 }
                 q.bstride_aux[a] = L.aux_elems[a];
             }
-            q.lam = lam;
-            q.lam_o = lam_o;
             q.un = (const T *)(hist + (size_t)(n - t0) * A.level);
             q.c2 = H->c2_field ? (const T *)H->at(L.off_c2) : nullptr;
             q.grad = grad;
@@ -1467,6 +1533,107 @@ int adjoint_impl(dpml *H, const void *resid, double *grad, void *grad_w)
             q.nz = (int32_t)L.N[2];
             q.batch = (int32_t)L.batch;
             q.bstride = L.ncell;
+            return q;
+        };
+        // the residual of step n into a^{n+1}
+        auto inject = [&](T *dst, int64_t n, hipStream_t st) {
+            if (H->nr > 0 && n < H->nt_rec) {
+                dim3 g2((unsigned)((H->nr + 255) / 256)), b2(256);
+                hipLaunchKernelGGL((dpmlk::k_inject<T>), g2, b2, 0, st, dst, H->d_rec_sorted, H->d_rec_order,
+                                   (const T *)resid, H->nr, H->nt_rec, n, (T)1);
+            }
+        };
+        // dJ/dw of step n from a^{n+1} (nothing writes a^{n+1} while the step runs)
+        auto gather = [&](const T *src, int64_t n, hipStream_t st) {
+            if (H->ns > 0 && n < H->nt_src && grad_w) {
+                dim3 g2((unsigned)((H->ns + 255) / 256)), b2(256);
+                hipLaunchKernelGGL((dpmlk::k_gather_scaled<T>), g2, b2, 0, st, src, H->d_src_cells,
+                                   H->d_src_order, (T *)grad_w, H->ns, H->nt_src, n, wamp);
+            }
+        };
+        auto frame = [&](dpmlk::AdjArgs<T> f, const dpmlk::TileRef *tiles, int64_t nt, const int skip[4],
+                         const int gskip[4], hipStream_t st) {
+            if (nt <= 0) return;
+            f.tiles = tiles;
+            f.ntiles = (int32_t)nt;
+            for (int k = 0; k < 4; ++k) {
+                f.skip[k] = skip[k];
+                f.gskip[k] = gskip[k];
+            }
+            hipLaunchKernelGGL((dpmlk::k_adjoint_frame2d<T, kAdjFrameGroups, kAdjFrameShots<T>>),
+                               dim3((unsigned)round8(4 * (int)nt)), dim3(64 * kAdjFrameGroups), 0, st, f);
+        };
+        const int none[4] = {0, 0, 0, 0};
+        for (int64_t n = t1 - 1; n >= t0;) {
+            T *lam = lamb(il), *lam_o = lamb(io);
+            inject(lam, n, H->stream);
+            if (two_ok && n - 1 >= t0) {
+                // steps n and n-1 in one pass: the core both in registers, the
+                // frame's two single steps beside it on the side stream
+                int fr[2], nf = 0;
+                for (int k = 0; k < 4; ++k)
+                    if (k != il && k != io) fr[nf++] = k;
+                T *out1 = lamb(fr[0]), *out2 = lamb(fr[1]);
+                HIP_TRY(H, hipEventRecord(H->ev_fork, H->stream));
+                HIP_TRY(H, hipStreamWaitEvent(H->side, H->ev_fork, 0));
+                gather(lam, n, H->side);
+                {
+                    // step n outside core2s (its gradient only outside core2: the core adds the ring's)
+                    dpmlk::AdjArgs<T> f = base(n, acur);
+                    f.lam = lam;
+                    f.lam_o = lam_o;
+                    f.lam_w = out1;
+                    frame(f, H->d_adj_frame_s[1], H->n_adj_frame_s[1], core2s, core2, H->side);
+                }
+                // the residual of step n-1 at the receivers whose a^n the frame wrote
+                if (H->nr > 0 && n - 1 < H->nt_rec && H->n_adj_frec > 0) {
+                    dim3 g2((unsigned)((H->n_adj_frec + 255) / 256)), b2(256);
+                    hipLaunchKernelGGL((dpmlk::k_inject<T>), g2, b2, 0, H->side, out1, H->d_adj_frec_cells,
+                                       H->d_adj_frec_order, (const T *)resid, H->n_adj_frec, H->nt_rec, n - 1, (T)1);
+                }
+                {
+                    // step n-1 outside core2
+                    dpmlk::AdjArgs<T> f = base(n - 1, 1 - acur);
+                    f.lam = out1;
+                    f.lam_o = lam;
+                    f.lam_w = out2;
+                    frame(f, H->d_adj_frame_s[0], H->n_adj_frame_s[0], core2, core2, H->side);
+                }
+                if (waves2 > 0) {
+                    dpmlk::AdjArgs<T> c = base(n, acur);
+                    c.lam = lam;
+                    c.lam_o = lam_o;
+                    c.lam_w = out1;
+                    dpmlk::Adj2<T> q2{};
+                    q2.un2 = (const T *)(hist + (size_t)(n - 1 - t0) * A.level);
+                    q2.out1 = out1;
+                    q2.out2 = out2;
+                    for (int k = 0; k < 4; ++k) q2.s1[k] = core2s[k];
+                    q2.t = -1;
+                    if (H->nr > 0 && n - 1 < H->nt_rec) {
+                        q2.rmap = H->d_rmap;
+                        q2.rpool = H->d_rpool;
+                        q2.resid = (const T *)resid;
+                        q2.nt = H->nt_rec;
+                        q2.t = n - 1;
+                    }
+                    hipLaunchKernelGGL((dpmlk::k_adjoint2_march2d<T, kAdjRows>), dim3((unsigned)round8((waves2 + 3) / 4)),
+                                       ablock, 0, H->stream, c, q2, core2[0], core2[1], core2[2], core2[3], tiles2_x,
+                                       waves2);
+                }
+                HIP_TRY(H, hipEventRecord(H->ev_join, H->side));
+                HIP_TRY(H, hipStreamWaitEvent(H->stream, H->ev_join, 0));
+                gather(out1, n - 1, H->stream);
+                HIP_TRY(H, hipGetLastError());
+                il = fr[1];          // a^{n-1}
+                io = fr[0];          // a^n
+                n -= 2;
+                continue;
+            }
+            dpmlk::AdjArgs<T> q = base(n, acur);
+            q.lam = lam;
+            q.lam_o = lam_o;
+            q.lam_w = lam_o;         // a^n over a^{n+2}
             if (march2d) {
                 // the frame's cells on the side stream while the core marches on the
                 // handle's stream (disjoint cells; joined before the next level)
@@ -1475,15 +1642,8 @@ int adjoint_impl(dpml *H, const void *resid, double *grad, void *grad_w)
                     HIP_TRY(H, hipEventRecord(H->ev_fork, H->stream));
                     HIP_TRY(H, hipStreamWaitEvent(H->side, H->ev_fork, 0));
                 }
-                gather(fork ? H->side : H->stream);
-                if (H->n_adj_frame > 0) {
-                    dpmlk::AdjArgs<T> f = q;
-                    f.tiles = H->d_adj_frame;
-                    f.ntiles = (int32_t)H->n_adj_frame;
-                    for (int k = 0; k < 4; ++k) f.skip[k] = core[k];
-                    hipLaunchKernelGGL((dpmlk::k_adjoint_frame2d<T, kAdjFrameGroups, kAdjFrameShots<T>>), fgrid, dim3(64 * kAdjFrameGroups),
-                                       0, fork ? H->side : H->stream, f);
-                }
+                gather(lam, n, fork ? H->side : H->stream);
+                frame(q, H->d_adj_frame, H->n_adj_frame, core, none, fork ? H->side : H->stream);
                 if (adj_waves > 0)
                     hipLaunchKernelGGL((dpmlk::k_adjoint_march2d<T, kAdjRows>), mgrid, ablock, 0, H->stream, q,
                                        core[0], core[1], core[2], core[3], adj_tiles_x, adj_waves);
@@ -1492,28 +1652,29 @@ int adjoint_impl(dpml *H, const void *resid, double *grad, void *grad_w)
                     HIP_TRY(H, hipStreamWaitEvent(H->stream, H->ev_join, 0));
                 }
             } else {
-                gather(H->stream);
+                gather(lam, n, H->stream);
                 if (L.ndim == 2)
                     hipLaunchKernelGGL((dpmlk::k_adjoint_cell<T, 2>), agrid, ablock, 0, H->stream, q);
                 else
                     hipLaunchKernelGGL((dpmlk::k_adjoint_cell<T, 3>), agrid, ablock, 0, H->stream, q);
             }
             HIP_TRY(H, hipGetLastError());
-            lcur = 1 - lcur;
+            std::swap(il, io);
             acur = 1 - acur;
+            --n;
         }
         HIP_TRY(H, hipEventRecord(H->adj_sweep_done[seg & 1], H->stream));
     }
-    // start: lam[1 - lcur] holds a^1, slot 0 of segment 0's history U^0
+    // start: lam[io] holds a^1, slot 0 of segment 0's history U^0
     const T half_dt2 = (T)(0.5 * H->dt * H->dt);
     const T inv_h2 = (T)(1.0 / (H->h * H->h));
     if (L.ndim == 2)
         hipLaunchKernelGGL((dpmlk::k_adjoint_start<T, 2>), grid, block, 0, H->stream,
-                           (const T *)(ws + A.off_lam[1 - lcur]), (const T *)(ws + A.off_hist[0]), grad, half_dt2,
+                           (const T *)(ws + A.off_lam[io]), (const T *)(ws + A.off_hist[0]), grad, half_dt2,
                            inv_h2, (int)L.N[0], (int)L.N[1], (int)L.N[2], (int)L.batch, (int64_t)L.ncell);
     else
         hipLaunchKernelGGL((dpmlk::k_adjoint_start<T, 3>), grid, block, 0, H->stream,
-                           (const T *)(ws + A.off_lam[1 - lcur]), (const T *)(ws + A.off_hist[0]), grad, half_dt2,
+                           (const T *)(ws + A.off_lam[io]), (const T *)(ws + A.off_hist[0]), grad, half_dt2,
                            inv_h2, (int)L.N[0], (int)L.N[1], (int)L.N[2], (int)L.batch, (int64_t)L.ncell);
     HIP_TRY(H, hipGetLastError());
     H->recording = true;

@@ -175,6 +175,11 @@ struct dpml {
     hipEvent_t adj_rec_done[2] = {nullptr, nullptr}, adj_sweep_done[2] = {nullptr, nullptr};
     dpmlk::TileRef *d_adj_frame = nullptr;  // 2D adjoint: tiles outside the marching core
     int64_t n_adj_frame = -1;               // -1: not built yet
+    dpmlk::TileRef *d_adj_frame_s[2] = {nullptr, nullptr};   // tiles outside the core shrunk by 1, 2
+    int64_t n_adj_frame_s[2] = {-1, -1};
+    int64_t *d_adj_frec_cells = nullptr;    // receivers the two-level pass's frame injects (sorted)
+    int64_t *d_adj_frec_order = nullptr;
+    int64_t n_adj_frec = -1;
     // sources
     int64_t ns = 0, nt_src = 0;
     int64_t *d_src_cells = nullptr, *d_src_order = nullptr;

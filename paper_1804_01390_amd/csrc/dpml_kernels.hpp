@@ -2200,7 +2200,8 @@ template <typename T>
 struct AdjArgs {
     Axis<T> ax[3];    // sig; phi/psi = p, q at n+1; phi_o/psi_o = p, q at n
     const T *lam;     // a^{n+1}
-    T *lam_o;         // a^{n+2} on entry, a^n on exit
+    T *lam_o;         // a^{n+2}
+    T *lam_w;         // where a^n goes: lam_o (in place) or another buffer
     const T *un;      // U^n
     const T *c2;      // per-cell c^2 or nullptr
     double *grad;     // dJ/dc^2, accumulated (+=), one value per cell
@@ -2217,6 +2218,8 @@ struct AdjArgs {
     const TileRef *tiles;  // optional 64 x 4 tile list (2D) instead of the whole grid
     int32_t ntiles;
     int32_t skip[4];       // with a tile list: cells in [skip0, skip1) x [skip2, skip3) are left alone
+    int32_t gskip[4];      // with a tile list: cells in [gskip0, gskip1) x [gskip2, gskip3) add no gradient
+                           // (their gradient term is another kernel's)
 };
 
 // (p + q) of axis A at band slot j (0 outside the band).
@@ -2378,7 +2381,7 @@ __device__ __forceinline__ double adj_finish(const AdjArgs<T> &p, const AdjGeo<T
             }
         }
     }
-    p.lam_o[bo + g.idx] = v;
+    p.lam_w[bo + g.idx] = v;
     return (double)(p.dt2 * in.lc) * (double)lapu;
 }
 
@@ -2591,14 +2594,14 @@ __global__ void __launch_bounds__(64 * NG) k_adjoint_frame2d(AdjArgs<T> p)
                                    (yqc[k] - (p.half_dt * sl) * (yqc[k] + yql[k])) + (p.k_damp * sl) * ln[k][2]);
                     }
                 }
-                st_off(uniform_ptr(p.lam_o + bo), oc, v);
+                st_off(uniform_ptr(p.lam_w + bo), oc, v);
                 gsum += (double)(p.dt2 * lc[k]) * (double)lapu;
             }
         }
     }
     part[w][lane] = gsum;
     __syncthreads();
-    if (ok && w == 0) {
+    if (ok && w == 0 && !(x >= p.gskip[0] && x < p.gskip[1] && y >= p.gskip[2] && y < p.gskip[3])) {
         double g = part[0][lane];
 #pragma unroll
         for (int k = 1; k < NG; ++k) g += part[k][lane];
@@ -2653,7 +2656,8 @@ __global__ void __launch_bounds__(256) k_adjoint_march2d(AdjArgs<T> p, int cx0, 
     for (int bi = 0; bi < p.batch; ++bi) {
         const int64_t bo = (int64_t)bi * p.bstride;
         const T *lam = p.lam + bo, *un = p.un + bo;
-        T *lamo = p.lam_o + bo;
+        const T *lamo = p.lam_o + bo;
+        T *lamw = p.lam_w + bo;
         T L[R + 2], U[R + 2], LO[R], LE[R], UE[R];
 #pragma unroll
         for (int r = 0; r < R + 2; ++r) {
@@ -2662,7 +2666,7 @@ __global__ void __launch_bounds__(256) k_adjoint_march2d(AdjArgs<T> p, int cx0, 
         }
 #pragma unroll
         for (int r = 0; r < R; ++r) {
-            LO[r] = ld_off((const T *)lamo + rowoff(r + 1), oc);
+            LO[r] = ld_off(lamo + rowoff(r + 1), oc);
             LE[r] = UE[r] = T(0);
             if (edge) {
                 LE[r] = ld_off(lam + rowoff(r + 1), oe);
@@ -2686,7 +2690,7 @@ __global__ void __launch_bounds__(256) k_adjoint_march2d(AdjArgs<T> p, int cx0, 
             lapc += ((cl[r] * L[r] - T(2) * clc) + cl[r + 2] * L[r + 2]) * p.inv_h2;
             lapu += ((U[r] - T(2) * uc) + U[r + 2]) * p.inv_h2;
             const T v = (T(2) * lc - LO[r]) + p.dt2 * lapc;
-            if (xout) st_off(lamo + rowoff(r + 1), oc, v);
+            if (xout) st_off(lamw + rowoff(r + 1), oc, v);
             g[r] += (double)(p.dt2 * lc) * (double)lapu;
         }
     }
@@ -2694,6 +2698,142 @@ __global__ void __launch_bounds__(256) k_adjoint_march2d(AdjArgs<T> p, int cx0, 
 #pragma unroll
     for (int r = 0; r < R; ++r)
         if (y0 + r < cy1) p.grad[(int64_t)(y0 + r) * nx + x] += g[r];
+}
+
+// Two transposed steps (n, then n-1) per pass on a 2D core r = [cx0, cx1) x
+// [cy0, cy1) whose cells, and the cells one step around them, carry no layer
+// term.  Each wave owns 62 columns (lanes 1..62; lanes 0 and 63 carry the
+// halo, each loading the column beyond it) x R rows and loops over the
+// shots.  Per shot it loads a^{n+1} on rows -2..R+1, a^{n+2}, U^n and U^{n-1}
+// on rows -1..R, forms a^n on rows -1..R of every lane (adding the residual
+// of step n-1 at receiver cells, as the step's injection would), then
+// a^{n-1} on its own cells from those, in registers.  a^n is stored on r
+// shrunk by one (the frame's first step writes the ring), a^{n-1} on r.  The
+// FP64 c^2 gradient terms of both steps are kept per cell across the shots
+// and added to grad one step after the other, as two single steps add them.
+// The expressions are those of k_adjoint_march2d, in the same order.
+template <typename T>
+struct Adj2 {
+    const T *un2;                  // U^{n-1}
+    T *out1, *out2;                // a^n, a^{n-1}
+    const int32_t *rmap;           // [member * ny + y]: pool slot of row y's column map, or -1 (nullptr: none)
+    const int32_t *rpool;          // pool[slot + x]: receiver index of column x, or -1
+    const T *resid;                // [nr][nt]
+    int64_t nt, t;                 // residual columns; the column injected into a^n (n - 1; -1: none)
+    int32_t s1[4];                 // the rectangle a^n is stored on (the frame writes the rest)
+};
+
+template <typename T, int R>
+__global__ void __launch_bounds__(256) k_adjoint2_march2d(AdjArgs<T> p, Adj2<T> q, int cx0, int cx1, int cy0, int cy1,
+                                                          int tiles_x, int n_waves)
+{
+    const int w = __builtin_amdgcn_readfirstlane(xcd_tile(blockIdx.x, gridDim.x) * 4 + (int)(threadIdx.x >> 6));
+    if (w >= n_waves) return;                                // whole waves; no barriers below
+    const int lane = (int)(threadIdx.x & 63);
+    const int nx = p.nx, ny = p.ny;
+    const int tx = w % tiles_x, ty = w / tiles_x;
+    const int x0 = cx0 + tx * 62 - 1, x = x0 + lane, y0 = cy0 + ty * R;
+    const bool own = lane >= 1 && lane <= 62 && x < cx1;      // a^{n-1} and the gradient of this lane's cells
+    const bool in1 = own && x >= q.s1[0] && x < q.s1[1];       // a^n stored (off r's ring on a layer axis)
+    const int xc = (x + nx) % nx;                            // lanes past either edge read a wrapped column
+    const int xe = lane == 0 ? (x0 - 1 + nx) % nx : (x0 + 64) % nx;   // lanes 0 / 63: outer column
+    const bool edge = lane == 0 || lane == 63;
+    constexpr uint32_t E = sizeof(T);
+    const uint32_t oc = (uint32_t)xc * E, oe = (uint32_t)xe * E;
+    // row y0 - 2 + r (wrapped) as an element offset of the row start
+    auto rowoff = [&](int r) -> int64_t {
+        int y = y0 - 2 + r;
+        y = y < 0 ? y + ny : (y >= ny ? y - ny : y);
+        return (int64_t)y * nx;
+    };
+    // c^2 of the column (rows -2..R+1) and of the outer columns (rows -1..R)
+    T cl[R + 4], ce[R + 2];
+#pragma unroll
+    for (int r = 0; r < R + 4; ++r) cl[r] = p.c2 ? ld_off(p.c2 + rowoff(r), oc) : p.c2_const;
+#pragma unroll
+    for (int r = 0; r < R + 2; ++r) ce[r] = (p.c2 && edge) ? ld_off(p.c2 + rowoff(r + 1), oe) : p.c2_const;
+    double g1[R], g2[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) g1[r] = g2[r] = 0.0;
+    // receiver columns of rows -1..R of this member (set per shot)
+#pragma unroll 1
+    for (int bi = 0; bi < p.batch; ++bi) {
+        const int64_t bo = (int64_t)bi * p.bstride;
+        const T *lam = p.lam + bo, *lamo = p.lam_o + bo, *un = p.un + bo, *un2 = q.un2 + bo;
+        T L[R + 4], LE[R + 2], LO[R + 2], U1[R + 2], U2[R + 2];
+#pragma unroll
+        for (int r = 0; r < R + 4; ++r) L[r] = ld_off(lam + rowoff(r), oc);
+#pragma unroll
+        for (int r = 0; r < R + 2; ++r) {
+            LO[r] = ld_off(lamo + rowoff(r + 1), oc);
+            U1[r] = ld_off(un + rowoff(r + 1), oc);
+            U2[r] = ld_off(un2 + rowoff(r + 1), oc);
+            LE[r] = edge ? ld_off(lam + rowoff(r + 1), oe) : T(0);
+        }
+        // a^n on rows -1..R (index r + 1), every lane
+        T V[R + 2];
+#pragma unroll
+        for (int r = 0; r < R + 2; ++r) {
+            const T lc = L[r + 1];
+            const T clc = cl[r + 1] * lc;
+            T cxm = __shfl_up(clc, 1), cxp = __shfl_down(clc, 1);
+            if (lane == 0) cxm = ce[r] * LE[r];
+            if (lane == 63) cxp = ce[r] * LE[r];
+            T lapc = T(0);
+            lapc += ((cxm - T(2) * clc) + cxp) * p.inv_h2;
+            lapc += ((cl[r] * L[r] - T(2) * clc) + cl[r + 2] * L[r + 2]) * p.inv_h2;
+            T v = (T(2) * lc - LO[r]) + p.dt2 * lapc;
+            if (q.rmap && q.t >= 0) {
+                int y = y0 - 1 + r;
+                y = y < 0 ? y + ny : (y >= ny ? y - ny : y);
+                const int slot = q.rmap[(int64_t)bi * ny + y];    // uniform
+                if (slot >= 0) {
+                    const int ri = q.rpool[slot + xc];
+                    if (ri >= 0) {
+                        const T add = T(0) + q.resid[(int64_t)ri * q.nt + q.t];
+                        v += T(1) * add;
+                    }
+                }
+            }
+            V[r] = v;
+        }
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            if (y0 + r >= cy1) break;                        // uniform
+            // step n on row r: gradient from a^{n+1} and U^n; a^n stored off the ring
+            {
+                const T lc = L[r + 2], uc = U1[r + 1];
+                T uxm = __shfl_up(uc, 1), uxp = __shfl_down(uc, 1);
+                T lapu = T(0);
+                lapu += ((uxm - T(2) * uc) + uxp) * p.inv_h2;
+                lapu += ((U1[r] - T(2) * uc) + U1[r + 2]) * p.inv_h2;
+                g1[r] += (double)(p.dt2 * lc) * (double)lapu;
+                const int y = y0 + r;
+                if (in1 && y >= q.s1[2] && y < q.s1[3]) st_off(q.out1 + bo + rowoff(r + 2), oc, V[r + 1]);
+            }
+            // step n-1 on row r from a^n (registers) and a^{n+1}
+            const T lc = V[r + 1], uc = U2[r + 1];
+            const T clc = cl[r + 2] * lc;
+            T cxm = __shfl_up(clc, 1), cxp = __shfl_down(clc, 1);
+            T uxm = __shfl_up(uc, 1), uxp = __shfl_down(uc, 1);
+            T lapc = T(0), lapu = T(0);
+            lapc += ((cxm - T(2) * clc) + cxp) * p.inv_h2;
+            lapu += ((uxm - T(2) * uc) + uxp) * p.inv_h2;
+            lapc += ((cl[r + 1] * V[r] - T(2) * clc) + cl[r + 3] * V[r + 2]) * p.inv_h2;
+            lapu += ((U2[r] - T(2) * uc) + U2[r + 2]) * p.inv_h2;
+            const T v = (T(2) * lc - L[r + 2]) + p.dt2 * lapc;
+            if (own) st_off(q.out2 + bo + rowoff(r + 2), oc, v);
+            g2[r] += (double)(p.dt2 * lc) * (double)lapu;
+        }
+    }
+    if (!own) return;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        if (y0 + r >= cy1) break;
+        double *gc = p.grad + (int64_t)(y0 + r) * nx + x;
+        *gc += g1[r];
+        *gc += g2[r];
+    }
 }
 
 // Adjoint of the start U^{-1} = U^0 + dt^2/2 c^2 L U^0 with a^{-1} = -a^1:

@@ -15,16 +15,18 @@ pytestmark = pytest.mark.gpu
 TOL = {"f64": 1e-12, "f32": 2e-5}
 
 
-def _shots(ndim=2, batch=3, steps=70, seed=0, wide=False):
+def _shots(ndim=2, batch=3, steps=70, seed=0, wide=False, nolayer_x=False):
     rng = np.random.default_rng(seed)
-    if ndim == 2 and wide:
+    if ndim == 2 and nolayer_x:
+        n, lo, hi = [130, 30], [0, 5], [0, 6]   # x periodic with no layer: the cores span it
+    elif ndim == 2 and wide:
         n, lo, hi = [150, 27], [6, 5], [7, 6]   # several 64-column strips, ragged row groups
     elif ndim == 2:
         n, lo, hi = [40, 34], [6, 5], [7, 6]
     else:
         n, lo, hi = [18, 16, 14], [4, 3, 5], [5, 4, 3]
     N = [lo[a] + n[a] + hi[a] for a in range(ndim)]
-    sig = [synthetic.sigma_random(n[a], lo[a], hi[a], 2.0, rng) for a in range(ndim)]
+    sig = [synthetic.sigma_random(n[a], lo[a], hi[a], 2.0, rng) if lo[a] + hi[a] else None for a in range(ndim)]
     c2 = synthetic.smooth_c2(n, lo, hi, 4, 3.0, 6.0, 0.4, 2, rng)
     dt = 0.4 if ndim == 2 else 0.3
     srcs = []
@@ -61,9 +63,13 @@ def _rel(a, b):
 
 
 @pytest.mark.parametrize("dtype,ndim,every,wide", [("f64", 2, 7, False), ("f32", 2, 9, False), ("f64", 3, 11, False),
-                                                  ("f32", 3, 70, False), ("f64", 2, 8, True), ("f32", 2, 13, True)])
+                                                  ("f32", 3, 70, False), ("f64", 2, 8, True), ("f32", 2, 13, True),
+                                                  ("f64", 2, 9, "nolayer_x"), ("f32", 2, 6, "nolayer_x")])
 def test_adjoint_matches_oracle(dtype, ndim, every, wide):
-    n, lo, hi, N, sig, c2, dt, srcs, rec, wav, obs, steps = _shots(ndim=ndim, wide=wide)
+    """Checkpoint spacings odd and even, so the reverse sweep takes both
+    two-step passes and single steps."""
+    n, lo, hi, N, sig, c2, dt, srcs, rec, wav, obs, steps = _shots(
+        ndim=ndim, wide=wide is True, nolayer_x=wide == "nolayer_x")
     print("case adjoint %dD %s ckpt_every=%d wide=%s" % (ndim, dtype, every, wide), flush=True)
     B = len(srcs)
     tdt = torch.float64 if dtype == "f64" else torch.float32
