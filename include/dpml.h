@@ -132,7 +132,21 @@ extern "C" {
                                   20-27); the core's tiles in launch order bit
                                   28; bit 29: the frame's first step alone
                                   before the core, which then runs beside the
-                                  frame's second step; values below 2^30);
+                                  frame's second step; bit 30 (periodic axes):
+                                  the frame as two levels in one march per box
+                                  beside the core -- the layer auxiliaries of
+                                  the middle level stay in registers, the core
+                                  writes U^{n+1} on all of its cells -- with RY
+                                  of the boxes outside the core along one axis
+                                  in bit 18 (0: 2, 1: 4; the others take 2),
+                                  the boxes outside along two or three axes on
+                                  the core's stream after it with bit 19,
+                                  planes per chunk of those boxes in bit 20
+                                  (0: 8, 1: 4) and of the x and y boxes in bits
+                                  21-25 (in eights; 0 = 32), chunks of the z
+                                  box in bits 26-27 (1, 2, 4 or 8) and with bit
+                                  29 the layer arrays loaded at their own plane
+                                  instead of a plane ahead);
                                   sources are added inside the pass, receivers
                                   and planes recorded after it.
                                   Otherwise single steps as CELL (2D) or MARCH

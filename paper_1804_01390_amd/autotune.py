@@ -43,7 +43,8 @@ CANDIDATES_2D: List[Tuple[int, int]] = ([(VARIANT_DEEP, (pf << 24) | (d << 20) |
 # (0: 1, 1: 2, 2: 4), the core's waves first bit 18, planes per layer chunk
 # in 20-27) and two-step passes (planes per chunk in bits 0-11, rows per wave
 # in 12-17; bit 19 the marching frame with its layer chunk in 20-27; bit 28
-# the core's tiles in launch order)
+# the core's tiles in launch order; bit 30 the frame as two levels per march
+# with its shape in bits 18-29)
 CANDIDATES_3D: List[Tuple[int, int]] = ([(VARIANT_CELL, 4)]
                                         + [(VARIANT_MARCH, (lc << 20) | (cf << 18) | (yl << 16) | (ry << 12) | ch)
                                            for ry, ch, lc, yl, cf in ((2, 16, 8, 0, 0), (4, 16, 8, 0, 0),
@@ -52,7 +53,10 @@ CANDIDATES_3D: List[Tuple[int, int]] = ([(VARIANT_CELL, 4)]
                                                                       (4, 32, 16, 2, 0))]
                                         + [(VARIANT_TWOSTEP, (ry << 12) | ch) for ry in (8, 16) for ch in (32, 64)]
                                         + [(VARIANT_TWOSTEP, (1 << 28) | (1 << 19) | (lc << 20) | (ry << 12) | ch)
-                                           for ry, ch, lc in ((4, 64, 8), (8, 64, 8))])
+                                           for ry, ch, lc in ((4, 64, 8), (8, 64, 8))]
+                                        + [(VARIANT_TWOSTEP, (1 << 30) | (1 << 29) | (3 << 26) | (mc << 20) | (sm << 19)
+                                            | (r4 << 18) | (16 << 12) | 32)
+                                           for mc, sm, r4 in ((1, 1, 1), (0, 1, 1), (1, 1, 0), (0, 0, 1))])
 
 
 def grid_key(sim) -> str:

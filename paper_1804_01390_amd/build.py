@@ -11,7 +11,8 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libdpml.so")
-SOURCES = [os.path.join(HERE, "csrc", n) for n in ("dpml.hip", "dpml3d.hip", "dpml_hist.hip", "probe.hip")]
+SOURCES = [os.path.join(HERE, "csrc", n)
+           for n in ("dpml.hip", "dpml3d.hip", "dpml_hist.hip", "dpml_frame3d.hip", "probe.hip")]
 DEPS = SOURCES + [os.path.join(HERE, "csrc", "dpml_kernels.hpp"), os.path.join(HERE, "csrc", "dpml_host.hpp"),
                   os.path.join(HERE, "csrc", "dpml_kernels3d.hpp"),
                   os.path.join(ROOT, "include", "dpml.h")]

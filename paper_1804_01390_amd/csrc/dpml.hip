@@ -967,8 +967,14 @@ int dpml_record_plane(dpml_t *H, int32_t axis, int64_t index, void *planes, int6
 int dpml_set_variant(dpml_t *H, int32_t variant, int32_t tile_rows)
 {
     if (!H) return DPML_EINVAL;
+    // highest shape bit + 1: 3D multi-step passes read bits up to 30, 3D MARCH
+    // up to 29, DEEP up to 24, the others up to 19
+    const bool d3 = H->L.ndim == 3;
+    const int bits = variant == DPML_VARIANT_DEEP ? 25
+                     : (d3 && variant >= DPML_VARIANT_TWOSTEP) ? 31
+                     : (d3 && variant == DPML_VARIANT_MARCH) ? 30 : 20;
     if (variant < DPML_VARIANT_AUTO || variant > DPML_VARIANT_DEEP || tile_rows < 0 ||
-        tile_rows >= (1 << (variant == DPML_VARIANT_DEEP ? 25 : (H->L.ndim == 3 && variant >= DPML_VARIANT_MARCH && variant != DPML_VARIANT_MARCH1) ? 30 : 20)))
+        (bits < 31 && tile_rows >= (1 << bits)))
         return H->fail(DPML_EINVAL, "bad variant");
     if (variant == DPML_VARIANT_DEEP && (pass_depth(variant, tile_rows) < 2 || pass_depth(variant, tile_rows) > kMaxLevels))
         return H->fail(DPML_EINVAL, "DEEP passes take 2 .. 8 levels");

@@ -26,35 +26,6 @@ static void march_box3d(const Layout &L, int b[4])
     }
 }
 
-// Algorithmic layer axis-cells of a 3D box: per axis, the weight of each band
-// slot in the box's range along it (a half word pair for each of Phi and Psi
-// the slot holds, so a whole band counts M) times the box's other extents.
-static double box_aux(const Layout &L, const dpmlk::Box3 &bx)
-{
-    const int r0[3] = {bx.xs, bx.ys, bx.zs}, r1[3] = {bx.xe, bx.ye, bx.ze};
-    double aux = 0;
-    for (int a = 0; a < 3; ++a) {
-        if (L.M[a] == 0) continue;
-        const int64_t b = L.lo[a] + L.n[a], N = L.N[a];
-        double w = 0;
-        for (int i = r0[a]; i < r1[a]; ++i) {
-            const int64_t ic = i % N;
-            const int64_t j = ic >= b ? ic - b : ic + (N - b);
-            if (j <= L.M[a]) w += 0.5 * ((j < L.M[a]) + (j > 0));
-        }
-        double other = 1;
-        for (int c = 0; c < 3; ++c)
-            if (c != a) other *= (double)(r1[c] - r0[c]);
-        aux += w * other;
-    }
-    return aux;
-}
-
-static double box_cells(const dpmlk::Box3 &bx)
-{
-    return (double)(bx.xe - bx.xs) * (double)(bx.ye - bx.ys) * (double)(bx.ze - bx.zs);
-}
-
 // One thread-per-cell launch over a box with the layer code of the axes in
 // `ax` (x and z, or all).
 template <typename T>
@@ -421,8 +392,12 @@ static int launch_outside3d_boxes(dpml *H, const dpmlk::StepArgs<T> &p, const dp
 // frame takes two ordinary steps on the side stream at the same time, step
 // j over everything outside the core shrunk by 2 - j cells.  The core writes
 // U^{n+1} only on the core shrunk by one, so every cell of every buffer has
-// one writer.  Receivers and the plane record both levels once the side
-// stream has joined.
+// one writer.  With bit 30 of tile_rows (periodic axes) the frame instead
+// takes both levels in one march per box (launch_frame2_3d) over everything
+// outside the core, which then writes U^{n+1} on the whole core; that frame
+// reads the aux buffer of level n and writes level n+2 to the other one, so
+// the pass flips the aux index.  Receivers and the plane record both levels
+// once the side stream has joined.
 template <typename T>
 int launch_multistep3d(dpml *H)
 {
@@ -435,7 +410,8 @@ int launch_multistep3d(dpml *H)
         if (b != H->u_now && b != H->u_old) nxt[k++] = (T *)b;
     }
     if (k < 2) return H->fail(DPML_EINVAL, "not enough field buffers for a multi-step pass");
-    const dpmlk::Box3 c = core_box3d(L, 0), in1 = core_box3d(L, 1);
+    const bool frame2 = ((H->tile_rows >> 30) & 1) && !L.wall[0] && !L.wall[1] && !L.wall[2];
+    const dpmlk::Box3 c = core_box3d(L, 0), in1 = frame2 ? c : core_box3d(L, 1);
     // tile_rows: planes per chunk in the low 12 bits (0: 32), rows per wave
     // in bits 12-17 (4, 8 or 16; 0: 8); the frame's steps by the
     // register-neighbour march when bit 19 is set (planes per layer chunk in
@@ -464,7 +440,7 @@ int launch_multistep3d(dpml *H)
         return frame_plan ? launch_outside3d<T>(H, pj, core_box3d(L, 2 - j), share, st, fsh)
                           : launch_outside3d_boxes<T>(H, pj, core_box3d(L, 2 - j), share, st);
     };
-    if (frame_first) {
+    if (frame_first && !frame2) {
         int rc = frame_step(1, H->stream);
         if (rc) return rc;
     }
@@ -500,10 +476,18 @@ int launch_multistep3d(dpml *H)
 #undef DPML_TWO3D
         timed_end(H, slot);
     }
-    // the frame's (remaining) steps on the side stream beside the core
-    for (int j = frame_first ? 2 : 1; j <= 2; ++j) {
-        int rc = frame_step(j, H->side);
+    if (frame2) {
+        // both levels of the frame in one march per box, beside the core
+        const dpmlk::StepArgs<T> pf = make_args<T>(H);
+        int rc = launch_frame2_3d<T>(H, pf, nxt[0], nxt[1], c, H->tile_rows, H->side, H->stream);
         if (rc) return rc;
+        H->cur = 1 - H->cur;
+    } else {
+        // the frame's (remaining) steps on the side stream beside the core
+        for (int j = frame_first ? 2 : 1; j <= 2; ++j) {
+            int rc = frame_step(j, H->side);
+            if (rc) return rc;
+        }
     }
     HIP_TRY(H, hipEventRecord(H->ev_join, H->side));
     HIP_TRY(H, hipStreamWaitEvent(H->stream, H->ev_join, 0));

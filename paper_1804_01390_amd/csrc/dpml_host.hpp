@@ -439,6 +439,35 @@ inline bool walls_allow_multistep(const Layout &L)
     return true;
 }
 
+// Algorithmic layer axis-cells of a 3D box: per axis, the weight of each band
+// slot in the box's range along it (a half word pair for each of Phi and Psi
+// the slot holds, so a whole band counts M) times the box's other extents.
+inline double box_aux(const Layout &L, const dpmlk::Box3 &bx)
+{
+    const int r0[3] = {bx.xs, bx.ys, bx.zs}, r1[3] = {bx.xe, bx.ye, bx.ze};
+    double aux = 0;
+    for (int a = 0; a < 3; ++a) {
+        if (L.M[a] == 0) continue;
+        const int64_t b = L.lo[a] + L.n[a], N = L.N[a];
+        double w = 0;
+        for (int i = r0[a]; i < r1[a]; ++i) {
+            const int64_t ic = i % N;
+            const int64_t j = ic >= b ? ic - b : ic + (N - b);
+            if (j <= L.M[a]) w += 0.5 * ((j < L.M[a]) + (j > 0));
+        }
+        double other = 1;
+        for (int c = 0; c < 3; ++c)
+            if (c != a) other *= (double)(r1[c] - r0[c]);
+        aux += w * other;
+    }
+    return aux;
+}
+
+inline double box_cells(const dpmlk::Box3 &bx)
+{
+    return (double)(bx.xe - bx.xs) * (double)(bx.ye - bx.ys) * (double)(bx.ze - bx.zs);
+}
+
 // ---- 3D stepping paths (dpml3d.hip; explicit instantiations for float and double)
 // One 3D step by the marching kernels (variants MARCH/MARCH1 and the single
 // steps of the multi-step variants): the step's U^{n+1} goes to p.uout (or
@@ -453,6 +482,17 @@ int multistep_levels3d(const dpml *H, int64_t nsteps);
 // the handle's time index by the pass's levels.
 template <typename T>
 int launch_multistep3d(dpml *H);
+
+// The frame of a 3D two-step pass as two levels in one march per box
+// (dpml_frame3d.hip): everything outside the core box c, as the seven boxes
+// that lie outside c along a nonempty set of axes and inside its range
+// along the others (each with the layer code of that set); U^{n+1} to out1,
+// U^{n+2} to out2, the layer arrays of level n+2 to p's output aux buffers.
+// `shape`: the launch shape bits of the pass's tile_rows; launches on st,
+// the boxes outside c along two or three axes on st2 when shape asks for it.
+template <typename T>
+int launch_frame2_3d(dpml *H, const dpmlk::StepArgs<T> &p, T *out1, T *out2, const dpmlk::Box3 &c, int shape,
+                     hipStream_t st, hipStream_t st2);
 
 // ---- 2D history passes (dpml_hist.hip; explicit instantiations for float and double)
 // The core kernel of a 2D pass of 4 .. kMaxLevels levels that stores every

@@ -61,9 +61,10 @@ def test_tuner_candidates_are_valid_launch_shapes():
     for variant, tr in autotune.CANDIDATES_2D:
         assert dp.VARIANT_AUTO <= variant <= dp.VARIANT_DEEP
         assert 0 <= tr < (1 << (25 if variant == dp.VARIANT_DEEP else 20))
-    for variant, tr in autotune.CANDIDATES_3D:       # 3D shapes take bits up to 28
+    for variant, tr in autotune.CANDIDATES_3D:       # 3D MARCH shapes take bits up to 29, passes up to 30
         assert dp.VARIANT_AUTO <= variant <= dp.VARIANT_DEEP
-        assert 0 <= tr < (1 << (30 if variant >= dp.VARIANT_MARCH and variant != dp.VARIANT_MARCH1 else 20))
+        top = 20 if variant in (dp.VARIANT_CELL, dp.VARIANT_MARCH1) else (30 if variant == dp.VARIANT_MARCH else 31)
+        assert 0 <= tr < (1 << (25 if variant == dp.VARIANT_DEEP else top))
         if variant == dp.VARIANT_DEEP:
             assert ((tr >> 20) & 0xF) in (0, 2, 3, 4, 5, 6, 7, 8)
     for variant, tr in autotune.CANDIDATES_2D:

@@ -35,11 +35,18 @@ def _case(name, rng):
         n, lo, hi = [150, 47, 41], [7, 5, 6], [6, 8, 4]
     elif name == "z_periodic":
         n, lo, hi = [70, 40, 36], [5, 6, 0], [7, 4, 0]
+    elif name == "onesided":
+        n, lo, hi = [70, 21, 19], [0, 5, 4], [6, 0, 3]
+    elif name == "wide_layer":  # the frame's x range spans two strips of a wave
+        n, lo, hi = [20, 16, 14], [40, 9, 6], [33, 8, 7]
     else:   # "x_periodic": the core spans the whole x axis and its strips wrap
         n, lo, hi = [100, 30, 34], [0, 4, 5], [0, 6, 3]
     sig = [synthetic.sigma_random(n[a], lo[a], hi[a], 2.0, rng) if lo[a] + hi[a] > 0 else None for a in range(3)]
     U0 = synthetic.gaussian_sum(n, lo, hi, 6, 2.0, 5.0, rng)
     return n, lo, hi, sig, U0
+
+
+F2 = 1 << 30
 
 
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
@@ -50,7 +57,15 @@ def _case(name, rng):
                                        (1 << 28) | (16 << 12) | 32, (1 << 28) | (1 << 19) | (8 << 20) | (4 << 12) | 16,
                                        (1 << 19) | (3 << 20) | (8 << 12) | 9,
                                        # the frame's first step alone before the core (bit 29)
-                                       (1 << 29) | (16 << 12) | 32, (1 << 29) | (1 << 19) | (4 << 12) | 11])
+                                       (1 << 29) | (16 << 12) | 32, (1 << 29) | (1 << 19) | (4 << 12) | 11,
+                                       # the frame as two levels in one march per box (bit 30)
+                                       # (rows per wave 4, chunk sizes, aux loads at their own plane: bit 29)
+                                       F2 | (16 << 12) | 32, F2 | (1 << 18) | (2 << 21) | (1 << 26) | (8 << 12) | 9,
+                                       F2 | (1 << 28) | (2 << 26) | (1 << 21) | (4 << 12) | 5,
+                                       F2 | (1 << 29) | (1 << 20) | (3 << 26) | (8 << 12) | 16,
+                                       F2 | (1 << 29) | (1 << 18) | (16 << 12) | 32,
+                                       # the boxes outside along two or three axes after the core (bit 19)
+                                       F2 | (1 << 19) | (1 << 29) | (3 << 26) | (1 << 18) | (16 << 12) | 32])
 def test_3d_twostep_bit_identical_and_oracle(dtype, case, tile_rows):
     rng = np.random.default_rng(17)
     n, lo, hi, sig, U0 = _case(case, rng)
@@ -79,6 +94,17 @@ def test_3d_twostep_bit_identical_and_oracle(dtype, case, tile_rows):
 
 
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("case", ["onesided", "wide_layer"])
+@pytest.mark.parametrize("tile_rows", [0, F2 | (16 << 12) | 32, F2 | (1 << 18) | (1 << 21) | (2 << 26) | 7,
+                                       F2 | (1 << 29) | (1 << 20) | (3 << 26) | 7])
+def test_3d_twostep_onesided_and_wide_layers(dtype, case, tile_rows):
+    """Layers of one side only and layers wider than a wave's strip: the
+    two-step pass (frame as single steps, or as two levels in one march per
+    box) equals single steps bit for bit and the oracle within tolerance."""
+    test_3d_twostep_bit_identical_and_oracle(dtype, case, tile_rows)
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
 @pytest.mark.parametrize("where", ["core", "frame"])
 def test_3d_twostep_sources_receivers_plane(dtype, where):
     """Sources inside the core are added by the core kernel at both levels
@@ -95,9 +121,9 @@ def test_3d_twostep_sources_receivers_plane(dtype, where):
     axis, index = w.plane
     print("case 3d two-step sources in %s %s" % (where, dtype), flush=True)
     res = []
-    for variant in (dp.VARIANT_TWOSTEP, dp.VARIANT_MARCH):
+    for variant, shape in ((dp.VARIANT_TWOSTEP, 0), (dp.VARIANT_MARCH, 0), (dp.VARIANT_TWOSTEP, F2 | (8 << 12) | 16)):
         sim = dp.Simulation(w.n, w.lo, w.hi, w.h, w.dt, w.sigma, dtype=_dtype(dtype))
-        sim.set_variant(variant, 0)
+        sim.set_variant(variant, shape)
         sim.set_state(torch.zeros(tuple(reversed(w.N)), dtype=torch.float64))
         sim.inject(w.sources, torch.from_numpy(wav))
         tr = sim.record(rec, w.steps)
@@ -105,14 +131,15 @@ def test_3d_twostep_sources_receivers_plane(dtype, where):
         sim.step(w.steps)
         sim.sync()
         res.append((tr.cpu().numpy().copy(), pl.cpu().numpy().copy(), _fields(sim, w.lo, w.hi)))
-        if variant == dp.VARIANT_TWOSTEP:
+        if variant == dp.VARIANT_TWOSTEP and not shape:
             gs = gpu_state(sim)
         sim.close()
-    (ta, pa, fa), (tb, pb, fb) = res
-    assert np.array_equal(ta, tb)
-    assert np.array_equal(pa, pb)
-    for k, (x, y) in enumerate(zip(fa, fb)):
-        assert np.array_equal(x, y), k
+    (ta, pa, fa) = res[0]
+    for tb, pb, fb in res[1:]:
+        assert np.array_equal(ta, tb)
+        assert np.array_equal(pa, pb)
+        for k, (x, y) in enumerate(zip(fa, fb)):
+            assert np.array_equal(x, y), k
     g = oracle.Grid(w.N, w.h, w.dt, w.sigma)
     ref, rtr = oracle.run(g, oracle.start(g, np.zeros(tuple(reversed(w.N)))), w.steps,
                           sources=w.sources, wavelets=wav, receivers=rec, nt=w.steps)
@@ -134,7 +161,7 @@ def test_3d_twostep_timing_counts_and_bytes():
     N = [lo[a] + n[a] + hi[a] for a in range(3)]
     sim = dp.Simulation(n, lo, hi, 1.0, 0.4, sig, dtype=torch.float32)
     t = {}
-    for form in (0, 1 << 19):
+    for form in (0, 1 << 19, F2):
         sim.set_variant(dp.VARIANT_TWOSTEP, form)
         sim.set_state(torch.from_numpy(U0))
         sim.set_timing(True)
@@ -150,9 +177,16 @@ def test_3d_twostep_timing_counts_and_bytes():
         assert t[form]["pair"]["bytes"] == pytest.approx(4 * 4 * core_cells * 4, rel=1e-12)   # 4 words per pass
         assert t[form]["frame"]["launches"] == 4 * 2 * per_step
         assert t[form]["frame"]["bytes"] == pytest.approx(4 * 2 * (3 * (cells - core_cells) + 4 * aux) * 4, rel=1e-9)
+    # two levels per frame launch: seven boxes per pass, 4 words per frame
+    # cell and 4 per layer axis-cell per pass
+    assert t[F2]["pair"]["launches"] == 4
+    assert t[F2]["pair"]["bytes"] == pytest.approx(4 * 4 * core_cells * 4, rel=1e-12)
+    assert t[F2]["frame"]["launches"] == 4 * 7
+    assert t[F2]["frame"]["bytes"] == pytest.approx(4 * (4 * (cells - core_cells) + 4 * aux) * 4, rel=1e-9)
 
 
-@pytest.mark.parametrize("tile_rows", [0, (1 << 29) | (1 << 19) | (8 << 12) | 16])
+@pytest.mark.parametrize("tile_rows", [0, (1 << 29) | (1 << 19) | (8 << 12) | 16, F2 | (8 << 12) | 16,
+                                       F2 | (1 << 19) | (1 << 29) | (3 << 26) | (16 << 12) | 32])
 def test_3d_twostep_graph_replay_matches_eager(tile_rows):
     """The 3D two-step pass captured into a HIP graph (core on the captured
     stream, frame steps on the side stream joined by events; or the frame's
