@@ -1961,10 +1961,19 @@ __global__ void __launch_bounds__(256) k_step2_zmarch3d(StepArgs<T> p, T *__rest
     const T *u = p.u;
     // a row's base is the same for the whole wave, the lane adds its column
     const uint32_t xo = (uint32_t)xc;
-    auto ld = [&](const T *b, int zc, int row) -> T {
-        const T *rp = b + ((int64_t)zc * sxy + (int64_t)row * nx);
-        return need ? rp[xo] : T(0);
+    // per-lane byte offsets of the relative rows -2 .. RY+1 within a plane
+    // (a plane is below 4 GiB): every access is a plane's base, one scalar
+    // pair per plane and array, plus one of these 32-bit offsets
+    uint32_t ob[RY + 4];
+#pragma unroll
+    for (int r = 0; r < RY + 4; ++r) ob[r] = ((uint32_t)ra[r] * (uint32_t)nx + xo) * (uint32_t)sizeof(T);
+    auto pbase = [&](const T *b, int zc) -> const char * {
+        const uint64_t v = (uint64_t)(b + (int64_t)zc * sxy);
+        const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)v);
+        const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(v >> 32));
+        return (const char *)(((uint64_t)hi << 32) | lo);
     };
+    auto ld = [&](const char *pb, int r) -> T { return need ? *(const T *)(pb + ob[r]) : T(0); };
     // sources whose cell lies in the wave's reach (first level: rows -1..RY,
     // planes z0-1 .. z1): bit q for the run of equal cells starting at q
     uint32_t smask = 0;
@@ -1988,7 +1997,7 @@ __global__ void __launch_bounds__(256) k_step2_zmarch3d(StepArgs<T> p, T *__rest
             for (int64_t r = q; r < src.ns && src.cells[r] == cell; ++r) add += src.wav[src.order[r] * src.nt + tn];
 #pragma unroll
             for (int i = 0; i < NV; ++i)
-                if (ra[r0 + 2 + i] == sy && xc == sx) v[i] = v[i] + src.amp * add;
+                if ((((y0 + r0 + i) % ny) + ny) % ny == sy && xc == sx) v[i] = v[i] + src.amp * add;
         }
     };
     // one step of a cell in cell_update's order (c^2 constant, no damping terms)
@@ -2008,20 +2017,21 @@ __global__ void __launch_bounds__(256) k_step2_zmarch3d(StepArgs<T> p, T *__rest
     };
     auto fetch = [&](int k, Fetch &f) {
         const int zc = zwrap(k), zn = zwrap(k + 1);
+        const char *un = pbase(u, zn), *uc = pbase(u, zc), *uoc = pbase(p.uo, zc);
 #pragma unroll
         for (int i = 0; i < NR; ++i) {
-            f.n2[i] = ld(u, zn, ra[i + 1]);
-            f.old[i] = ld(p.uo, zc, ra[i + 1]);
+            f.n2[i] = ld(un, i + 1);
+            f.old[i] = ld(uoc, i + 1);
         }
-        f.hlo = ld(u, zc, ra[0]);
-        f.hhi = ld(u, zc, ra[RY + 3]);
+        f.hlo = ld(uc, 0);
+        f.hhi = ld(uc, RY + 3);
     };
     {
-        const int zm = zwrap(z0 - 2), zc = zwrap(z0 - 1);
+        const char *um = pbase(u, zwrap(z0 - 2)), *uc = pbase(u, zwrap(z0 - 1));
 #pragma unroll
         for (int i = 0; i < NR; ++i) {
-            n0[i] = ld(u, zm, ra[i + 1]);
-            n1[i] = ld(u, zc, ra[i + 1]);
+            n0[i] = ld(um, i + 1);
+            n1[i] = ld(uc, i + 1);
         }
     }
 #pragma unroll
@@ -2047,11 +2057,11 @@ __global__ void __launch_bounds__(256) k_step2_zmarch3d(StepArgs<T> p, T *__rest
         }
         if (smask) inject(a2, -1, zc, src.n);
         if (k >= z0 && k < z1 && k >= in1.zs && k < in1.ze) {
-            const int64_t plane = (int64_t)zc * sxy;
+            char *ob1 = (char *)pbase(out1, zc);
 #pragma unroll
             for (int r = 0; r < RY; ++r) {
                 const int y = y0 + r;
-                if (xin1 && y < c.ye && y >= in1.ys && y < in1.ye) (out1 + (plane + (int64_t)ra[r + 2] * nx))[xo] = a2[r + 1];
+                if (xin1 && y < c.ye && y >= in1.ys && y < in1.ye) *(T *)(ob1 + ob[r + 2]) = a2[r + 1];
             }
         }
         // level 2: U^{n+2} on plane k-1, rows 0 .. RY-1
@@ -2065,10 +2075,10 @@ __global__ void __launch_bounds__(256) k_step2_zmarch3d(StepArgs<T> p, T *__rest
                 v[r] = upd(uc, uxm, uxp, a1[r], a1[r + 2], a0[r], a2[r + 1], n0[r + 1]);
             }
             if (smask) inject(v, 0, zp, src.n + 1);
-            const int64_t plane = (int64_t)zp * sxy;
+            char *ob2 = (char *)pbase(u_next2, zp);
 #pragma unroll
             for (int r = 0; r < RY; ++r)
-                if (xout && y0 + r < c.ye) (u_next2 + (plane + (int64_t)ra[r + 2] * nx))[xo] = v[r];
+                if (xout && y0 + r < c.ye) *(T *)(ob2 + ob[r + 2]) = v[r];
         }
 #pragma unroll
         for (int r = 0; r < RY; ++r) a0[r] = a1[r + 1];
