@@ -120,9 +120,9 @@ extern "C" {
                                   cell)), the frame holding the layer in single
                                   steps.
                                   3D runs with a constant c^2, one batch member
-                                  (walls as in 2D) and at most 32 sources, all at
-                                  least 3 cells inside the layer-free region: the
-                                  same
+                                  (walls as in 2D), x-y planes below 4 GiB and at
+                                  most 32 sources, all at least 3 cells inside the
+                                  layer-free region: the same
                                   with each wave marching in z over 64 columns x
                                   RY rows (tile_rows: planes per chunk in bits
                                   0-11 (0 = 32), RY in bits 12-17 (4, 8 or 16;

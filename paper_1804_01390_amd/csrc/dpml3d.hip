@@ -308,14 +308,16 @@ static dpmlk::Box3 core_box3d(const Layout &L, int shrink)
 
 // 3D: two levels per pass for the multi-step variants on
 // single-member grids with a constant c^2 (walls as walls_allow_multistep
-// admits), at most 32 sources, all inside the core shrunk by one (the frame's
-// steps then add none); otherwise 1.
+// admits), planes below 4 GiB, at most 32 sources, all inside the core shrunk
+// by one (the frame's steps then add none); otherwise 1.
 int multistep_levels3d(const dpml *H, int64_t nsteps)
 {
     const Layout &L = H->L;
     if (pass_depth(H->variant, H->tile_rows) < 2) return 1;
     if (nsteps < 2 || L.batch != 1 || H->c2_field || !walls_allow_multistep(L)) return 1;
     if (L.N[0] < 8 || L.N[1] < 8 || L.N[2] < 8 || H->ns > 32) return 1;
+    // the core addresses a plane by 32-bit byte offsets
+    if ((double)L.N[0] * (double)L.N[1] * (double)L.esize >= 4294967296.0) return 1;
     const dpmlk::Box3 c = core_box3d(L, 0), in1 = core_box3d(L, 1);
     if (in1.xe <= in1.xs || in1.ye <= in1.ys || in1.ze <= in1.zs) return 1;
     (void)c;
