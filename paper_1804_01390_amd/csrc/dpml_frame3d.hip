@@ -66,7 +66,7 @@ int launch_frame2_3d(dpml *H, const dpmlk::StepArgs<T> &p, T *out1, T *out2, con
     // x and y boxes, in eights (0: 32); bits 26-27: chunks of the z box (0: 1,
     // 1: 2, 2: 4, 3: 8); bit 29: the layer arrays loaded at their own plane
     // instead of a plane ahead; bit 19: the boxes outside along two or three
-    // axes on st2 (else on st)
+    // axes as one launch on st2 (else one launch each on st)
     const int ry1 = ((shape >> 18) & 1) ? 4 : 2;
     const int mchunk = ((shape >> 20) & 1) ? 4 : 8;
     const int lc = (shape >> 21) & 0x1F;
@@ -78,7 +78,12 @@ int launch_frame2_3d(dpml *H, const dpmlk::StepArgs<T> &p, T *out1, T *out2, con
     int out1_[3];
     for (int a = 0; a < 3; ++a)
         out1_[a] = ce[a] - cs[a] < (int)L.N[a] ? cs[a] + (int)L.N[a] : ce[a];   // empty without a layer
-    // the boxes outside c along one axis first (the large ones)
+    // the boxes outside c along one axis first (the large ones); with bit 19
+    // the others as one launch on st2
+    const bool edges = (shape >> 19) & 1;
+    dpmlk::F2Edges eb{};
+    double ebytes = 0.0;
+    int64_t ew = 0;
     static const int order[7] = {1, 2, 4, 3, 5, 6, 7};
     for (int ax : order) {
         int r0[3], r1[3];
@@ -96,10 +101,29 @@ int launch_frame2_3d(dpml *H, const dpmlk::StepArgs<T> &p, T *out1, T *out2, con
         // algorithmic bytes per pass: U^n, U^{n-1} read and two levels
         // written per cell, Phi/Psi read and written once per layer axis-cell
         const double bytes = H->timing ? (4.0 * box_cells(b) + 4.0 * box_aux(L, b)) * (double)L.esize : 0.0;
-        const hipStream_t s = (!single && ((shape >> 19) & 1)) ? st2 : st;
-        const int rc = pa ? f2_launch_ax<T, true>(H, ax, ry, m, s, p, out1, out2, bytes)
-                          : f2_launch_ax<T, false>(H, ax, ry, m, s, p, out1, out2, bytes);
+        if (edges && !single) {
+            const int i = ax == 3 ? 0 : (ax == 5 ? 1 : (ax == 6 ? 2 : 3));
+            eb.b[i] = m;
+            ebytes += bytes;
+            continue;
+        }
+        const int rc = pa ? f2_launch_ax<T, true>(H, ax, ry, m, st, p, out1, out2, bytes)
+                          : f2_launch_ax<T, false>(H, ax, ry, m, st, p, out1, out2, bytes);
         if (rc) return rc;
+    }
+    if (edges) {
+        for (int i = 0; i < 4; ++i) {
+            ew += (int64_t)eb.b[i].strips * eb.b[i].groups * eb.b[i].chunks;   // empty boxes have no waves
+            eb.w[i] = (int32_t)std::min<int64_t>(ew, (int64_t)1 << 30);
+        }
+        if (ew > ((int64_t)1 << 30)) return H->fail(DPML_EINVAL, "3D grid too large for one frame launch");
+        if (ew > 0) {
+            const int slot = timed_begin(H, DPML_KERNEL_FRAME, ebytes, st2);
+            const dim3 g((unsigned)round8((int)((ew + 3) / 4))), b(256);
+            if (pa) hipLaunchKernelGGL((dpmlk::k_frame2_edges3d<T, true>), g, b, 0, st2, p, out1, out2, eb);
+            else hipLaunchKernelGGL((dpmlk::k_frame2_edges3d<T, false>), g, b, 0, st2, p, out1, out2, eb);
+            timed_end(H, slot, st2);
+        }
     }
     return DPML_OK;
 }

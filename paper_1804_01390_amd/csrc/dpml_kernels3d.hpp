@@ -776,4 +776,25 @@ __global__ void __launch_bounds__(256) k_frame2_box3d(StepArgs<T> p, T *__restri
     frame2_box<T, RY, AX, PA>(p, out1, out2, bx, xcd_tile(blockIdx.x, gridDim.x) * 4 + wv);
 }
 
+// The boxes outside the core along two or three axes (its edges and
+// corners: few waves each) in one launch: a wave finds its box from the
+// cumulative wave counts w (boxes with the layer code of x and y, x and z,
+// y and z, all three).
+struct F2Edges {
+    MBox b[4];
+    int32_t w[4];
+};
+
+template <typename T, bool PA>
+__global__ void __launch_bounds__(256) k_frame2_edges3d(StepArgs<T> p, T *__restrict__ out1, T *__restrict__ out2,
+                                                        F2Edges e)
+{
+    const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int wave = xcd_tile(blockIdx.x, gridDim.x) * 4 + wv;
+    if (wave < e.w[0]) frame2_box<T, 2, 3, PA>(p, out1, out2, e.b[0], wave);
+    else if (wave < e.w[1]) frame2_box<T, 2, 5, PA>(p, out1, out2, e.b[1], wave - e.w[0]);
+    else if (wave < e.w[2]) frame2_box<T, 2, 6, PA>(p, out1, out2, e.b[2], wave - e.w[1]);
+    else if (wave < e.w[3]) frame2_box<T, 2, 7, PA>(p, out1, out2, e.b[3], wave - e.w[2]);
+}
+
 }  // namespace dpmlk
