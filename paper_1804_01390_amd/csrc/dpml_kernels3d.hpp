@@ -1,6 +1,7 @@
 // dpml_kernels3d.hpp -- gfx950 z-marching kernels of one 3D step over a box,
 // with the layer terms of Eq. (DiscretePML a-c) taken from register
-// neighbours.
+// neighbours, and (at the end of the file) the frame of a 3D two-step pass
+// taken as two levels per march.
 //
 // A wave owns a strip of 64 consecutive columns (lanes 1..62 produce, lanes
 // 0 and 63 only feed their neighbours) and RY consecutive rows, and marches
