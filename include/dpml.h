@@ -127,12 +127,14 @@ extern "C" {
                                   RY rows (tile_rows: planes per chunk in bits
                                   0-11 (0 = 32), RY in bits 12-17 (4, 8 or 16;
                                   0 = 8); the frame's steps by the box kernels,
-                                  or with bit 19 by the register-neighbour march
-                                  of MARCH (its planes per layer chunk in bits
-                                  20-27); the core's tiles in launch order bit
+                                  or with bit 19 on periodic axes by the
+                                  register-neighbour march of MARCH (its planes
+                                  per layer chunk in bits 20-27); the core's tiles in launch order bit
                                   28; bit 29: the frame's first step alone
                                   before the core, which then runs beside the
-                                  frame's second step; bit 30 (periodic axes):
+                                  frame's second step; bit 30 (periodic axes;
+                                  with walls the frame's single steps by the box
+                                  kernels and bits 18-29 ignored):
                                   the frame as two levels in one march per box
                                   beside the core -- the layer auxiliaries of
                                   the middle level stay in registers, the core

@@ -412,22 +412,26 @@ int launch_multistep3d(dpml *H)
         if (b != H->u_now && b != H->u_old) nxt[k++] = (T *)b;
     }
     if (k < 2) return H->fail(DPML_EINVAL, "not enough field buffers for a multi-step pass");
-    const bool frame2 = ((H->tile_rows >> 30) & 1) && !L.wall[0] && !L.wall[1] && !L.wall[2];
+    // the marching frames (bits 19 and 30) take periodic axes only; bits
+    // 18-29 describe the two-level frame when bit 30 is set
+    const bool periodic = !L.wall[0] && !L.wall[1] && !L.wall[2];
+    const bool f2bit = (H->tile_rows >> 30) & 1;
+    const bool frame2 = f2bit && periodic;
     const dpmlk::Box3 c = core_box3d(L, 0), in1 = frame2 ? c : core_box3d(L, 1);
     // tile_rows: planes per chunk in the low 12 bits (0: 32), rows per wave
     // in bits 12-17 (4, 8 or 16; 0: 8); the frame's steps by the
-    // register-neighbour march when bit 19 is set (planes per layer chunk in
-    // bits 20-27, as in mshape), else by the box kernels; bit 28 the core's
-    // tiles in launch order; bit 29 below
+    // register-neighbour march when bit 19 is set on a periodic grid (planes
+    // per layer chunk in bits 20-27, as in mshape), else by the box kernels;
+    // bit 28 the core's tiles in launch order; bit 29 below
     const int chunk = (H->tile_rows & 0xFFF) > 0 ? (H->tile_rows & 0xFFF) : 32;
     const int ryb = (H->tile_rows >> 12) & 0x3F;
     const int ry = (ryb == 4 || ryb == 16) ? ryb : 8;
     const MShape fsh = mshape(H->tile_rows & ~0xFFFF);
     const int ord = (H->tile_rows >> 28) & 1;
-    const bool frame_plan = (H->tile_rows >> 19) & 1;
+    const bool frame_plan = !f2bit && periodic && ((H->tile_rows >> 19) & 1);
     // bit 29: the frame's first step alone on the handle's stream first, then
     // the core beside the frame's second step (else the core beside both)
-    const bool frame_first = (H->tile_rows >> 29) & 1;
+    const bool frame_first = !f2bit && ((H->tile_rows >> 29) & 1);
     // the frame's step j (1 or 2) on stream st, aux buffers alternating
     auto frame_step = [&](int j, hipStream_t st) -> int {
         if (j == 2) H->cur = 1 - H->cur;
@@ -442,7 +446,7 @@ int launch_multistep3d(dpml *H)
         return frame_plan ? launch_outside3d<T>(H, pj, core_box3d(L, 2 - j), share, st, fsh)
                           : launch_outside3d_boxes<T>(H, pj, core_box3d(L, 2 - j), share, st);
     };
-    if (frame_first && !frame2) {
+    if (frame_first) {
         int rc = frame_step(1, H->stream);
         if (rc) return rc;
     }

@@ -155,13 +155,15 @@ def test_3d_twostep_timing_counts_and_bytes():
     """Per-launch timing of a 3D two-step run: one core launch per pass
     counting both levels of the core's cells, three frame launches per frame
     step (box kernels) or one (the marching frame, bit 19), and the frame's
-    share of the byte model per pass."""
+    share of the byte model per pass; with the two-level frame (bit 30) seven
+    box launches per pass (four with the edges merged) and the frame's bytes
+    of a pass counted once."""
     rng = np.random.default_rng(4)
     n, lo, hi, sig, U0 = _case("ragged", rng)
     N = [lo[a] + n[a] + hi[a] for a in range(3)]
     sim = dp.Simulation(n, lo, hi, 1.0, 0.4, sig, dtype=torch.float32)
     t = {}
-    for form in (0, 1 << 19, F2):
+    for form in (0, 1 << 19, F2, F2 | (1 << 19)):
         sim.set_variant(dp.VARIANT_TWOSTEP, form)
         sim.set_state(torch.from_numpy(U0))
         sim.set_timing(True)
@@ -183,6 +185,9 @@ def test_3d_twostep_timing_counts_and_bytes():
     assert t[F2]["pair"]["bytes"] == pytest.approx(4 * 4 * core_cells * 4, rel=1e-12)
     assert t[F2]["frame"]["launches"] == 4 * 7
     assert t[F2]["frame"]["bytes"] == pytest.approx(4 * (4 * (cells - core_cells) + 4 * aux) * 4, rel=1e-9)
+    # the edges and corners as one launch (bit 19): three boxes and one launch per pass, the same bytes
+    assert t[F2 | (1 << 19)]["frame"]["launches"] == 4 * 4
+    assert t[F2 | (1 << 19)]["frame"]["bytes"] == pytest.approx(t[F2]["frame"]["bytes"], rel=1e-12)
 
 
 @pytest.mark.parametrize("tile_rows", [0, (1 << 29) | (1 << 19) | (8 << 12) | 16, F2 | (8 << 12) | 16,

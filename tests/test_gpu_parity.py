@@ -504,6 +504,12 @@ def test_launch_timing_counts_and_bytes(dtype):
     (2, dp.VARIANT_THREESTEP, (15 << 16) | 8, (True, False), [0, 12], [10, 5]),
     (3, dp.VARIANT_TWOSTEP, 0, (True, False, True), [5, 3, 6], [4, 7, 5]),
     (3, dp.VARIANT_TWOSTEP, 0, (True, True, True), [0, 3, 6], [4, 7, 1]),
+    # the marching frames (bits 19 and 30) are for periodic axes: with walls the frame's single steps
+    # take the box kernels
+    (3, dp.VARIANT_TWOSTEP, (1 << 30) | (1 << 29) | (1 << 19) | (8 << 12) | 16, (True, False, True), [5, 3, 6],
+     [4, 7, 5]),
+    (3, dp.VARIANT_TWOSTEP, (1 << 28) | (1 << 19) | (8 << 20) | (8 << 12) | 16, (False, True, False), [5, 3, 6],
+     [4, 7, 5]),
 ])
 def test_multistep_with_walls_bit_identical_and_oracle(dtype, ndim, variant, tile_rows, walls, lo, hi):
     """Multi-step passes on grids truncated by reflecting walls: the cores read
