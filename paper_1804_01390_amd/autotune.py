@@ -55,7 +55,8 @@ CANDIDATES_3D: List[Tuple[int, int]] = ([(VARIANT_CELL, 4)]
                                         + [(VARIANT_TWOSTEP, (1 << 28) | (1 << 19) | (lc << 20) | (ry << 12) | ch)
                                            for ry, ch, lc in ((4, 64, 8), (8, 64, 8))]
                                         + [(VARIANT_TWOSTEP, (1 << 30) | (1 << 29) | (3 << 26) | (lc << 21) | (mc << 20)
-                                            | (sm << 19) | (r4 << 18) | (16 << 12) | ch)
+                                            | (sm << 19) | (r4 << 18) | (ry << 12) | ch)
+                                           for ry in (8, 16)
                                            for mc, sm, r4, lc, ch in ((1, 1, 1, 0, 32), (0, 1, 1, 0, 32), (1, 1, 0, 0, 32),
                                                                       (0, 0, 1, 0, 32), (1, 1, 1, 2, 64))])
 
