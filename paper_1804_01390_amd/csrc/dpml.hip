@@ -1396,6 +1396,9 @@ int adjoint_impl(dpml *H, const void *resid, double *grad, void *grad_w)
     bool fits32 = (uint64_t)L.ncell * L.esize < (1ull << 32);
     for (int a = 0; a < L.ndim; ++a) fits32 &= (uint64_t)L.aux_elems[a] * L.esize < (1ull << 32);
     const bool march2d = L.ndim == 2 && fits32;
+    // the frame's buffer descriptors span all members of an array
+    bool frame_buf = (uint64_t)L.batch * L.ncell * L.esize < (1ull << 32);
+    for (int a = 0; a < L.ndim; ++a) frame_buf &= (uint64_t)L.batch * L.aux_elems[a] * L.esize < (1ull << 32);
     if (march2d) {
         int rc = ensure_adj_frame(H);
         if (!rc) rc = ensure_side(H);
@@ -1566,8 +1569,12 @@ int adjoint_impl(dpml *H, const void *resid, double *grad, void *grad_w)
                 f.skip[k] = skip[k];
                 f.gskip[k] = gskip[k];
             }
-            hipLaunchKernelGGL((dpmlk::k_adjoint_frame2d<T, kAdjFrameGroups, kAdjFrameShots<T>>),
-                               dim3((unsigned)round8(4 * (int)nt)), dim3(64 * kAdjFrameGroups), 0, st, f);
+            if (frame_buf)
+                hipLaunchKernelGGL((dpmlk::k_adjoint_frame2d<T, kAdjFrameGroups, kAdjFrameShots<T>, true>),
+                                   dim3((unsigned)round8(4 * (int)nt)), dim3(64 * kAdjFrameGroups), 0, st, f);
+            else
+                hipLaunchKernelGGL((dpmlk::k_adjoint_frame2d<T, kAdjFrameGroups, kAdjFrameShots<T>, false>),
+                                   dim3((unsigned)round8(4 * (int)nt)), dim3(64 * kAdjFrameGroups), 0, st, f);
         };
         const int none[4] = {0, 0, 0, 0};
         for (int64_t n = t1 - 1; n >= t0;) {
