@@ -37,8 +37,6 @@ def _run(n, lo, hi, sig, c2, dt, steps, every, shots, recs, wav, resid):
     return out
 
 
-@pytest.mark.skip(reason="a full-suite run that held this test (117 GB of device memory, passed alone) aborted "
-                         "110 tests later in a problem-set test; until the cause is found it stays out of the suite")
 def test_adjoint_frame_past_4gib_equals_two_halves():
     n, lo, hi = [4000, 4000], [16, 16], [16, 16]
     N = [lo[a] + n[a] + hi[a] for a in range(2)]
