@@ -1268,6 +1268,7 @@ int forward_ckpt_impl(dpml *H, int64_t nsteps)
 
 constexpr int kAdjRows = 4;   // rows per wave of the 2D marching adjoint kernel
 constexpr int kAdjFrameGroups = 8;   // waves (shot groups) per block of the 2D adjoint frame
+constexpr int kAdjFrameGroupsBuf = 4;   // ... in its buffer-descriptor form (fewer registers: more blocks per CU)
 template <typename T>
 constexpr int kAdjFrameShots = sizeof(T) == 4 ? 2 : 1;   // shots whose loads a frame wave issues together
 
@@ -1570,8 +1571,8 @@ int adjoint_impl(dpml *H, const void *resid, double *grad, void *grad_w)
                 f.gskip[k] = gskip[k];
             }
             if (frame_buf)
-                hipLaunchKernelGGL((dpmlk::k_adjoint_frame2d<T, kAdjFrameGroups, kAdjFrameShots<T>, true>),
-                                   dim3((unsigned)round8(4 * (int)nt)), dim3(64 * kAdjFrameGroups), 0, st, f);
+                hipLaunchKernelGGL((dpmlk::k_adjoint_frame2d<T, kAdjFrameGroupsBuf, kAdjFrameShots<T>, true>),
+                                   dim3((unsigned)round8(4 * (int)nt)), dim3(64 * kAdjFrameGroupsBuf), 0, st, f);
             else
                 hipLaunchKernelGGL((dpmlk::k_adjoint_frame2d<T, kAdjFrameGroups, kAdjFrameShots<T>, false>),
                                    dim3((unsigned)round8(4 * (int)nt)), dim3(64 * kAdjFrameGroups), 0, st, f);
