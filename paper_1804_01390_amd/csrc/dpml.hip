@@ -2196,7 +2196,13 @@ int multi_step_impl(dpml_multi *H, int64_t nsteps, bool use_graph)
     }
     const int state = state_key(H->now, H->old, H->cur);
     if (!(H->exec && H->graph_steps == nsteps && H->graph_state == state)) {
-        if (H->exec) { (void)hipGraphExecDestroy(H->exec); H->exec = nullptr; }
+        if (H->exec) {
+            // the replaced graph may still run on the stream: wait before its release
+            hipError_t es = hipStreamSynchronize(H->stream);
+            if (es != hipSuccess) return H->fail(DPML_EHIP, hipGetErrorString(es));
+            (void)hipGraphExecDestroy(H->exec);
+            H->exec = nullptr;
+        }
         if (H->graph) { (void)hipGraphDestroy(H->graph); H->graph = nullptr; }
         if (!H->cap) {
             hipError_t e = hipStreamCreateWithFlags(&H->cap, hipStreamNonBlocking);
@@ -2563,7 +2569,12 @@ int step_graph_impl(dpml *H, int64_t nsteps)
                        H->graph_unow == H->u_now && H->graph_uold == H->u_old &&
                        H->graph_variant == H->variant && H->graph_rows == H->tile_rows;
     if (!reuse) {
-        if (H->exec) { (void)hipGraphExecDestroy(H->exec); H->exec = nullptr; }
+        if (H->exec) {
+            // the replaced graph may still run on the stream: wait before its release
+            HIP_TRY(H, hipStreamSynchronize(H->stream));
+            (void)hipGraphExecDestroy(H->exec);
+            H->exec = nullptr;
+        }
         if (H->graph) { (void)hipGraphDestroy(H->graph); H->graph = nullptr; }
         if (!H->cap) HIP_TRY(H, hipStreamCreateWithFlags(&H->cap, hipStreamNonBlocking));
         // capture on a private stream with a throw-away copy of the rotation state
